@@ -1,0 +1,83 @@
+"""Named synthetic workloads and a small on-disk cache.
+
+The three plain-FP64 workloads are structured hex8 meshes of the unit cube
+(E = 1, nu = 0.3, bottom face z = 0 clamped, unit +z traction on the top face):
+
+* ``edge10``   10^3 elements, planar edge crack in x = 0.5 for z < 0.45 across the
+               full width, Heaviside + 4 shifted branch functions within r_e = 0.15,
+               2^3 subdomains.
+* ``penny40``  40^3 elements, penny crack of radius 0.25 centred at (0.5,0.5,0.5)
+               bent into z = 0.5 + 0.3 rho^2, tip enrichment within r_e = 0.05,
+               4^3 subdomains.
+* ``penny80``  80^3 elements, same crack, 8^3 subdomains.
+
+They stand in for the paper's gmsh tetrahedral meshes (notched beam, bracket,
+blade), which are not available; sizes per subdomain (about 3.3k DoFs) sit inside
+the paper's range of DoFs per subdomain.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+
+from .xfem import CurvedPennyCrack, PlanarEdgeCrack, Problem, build_problem
+
+GENERATOR_VERSION = 4
+
+CONFIGS = {
+    "edge10": dict(ne=10, nsd=2, crack=("edge", dict(x0=0.5, zf=0.45)), r_e=0.15),
+    "penny40": dict(ne=40, nsd=4, crack=("penny", dict(center=(0.5, 0.5, 0.5), R=0.25, curv=0.3)), r_e=0.05),
+    "penny80": dict(ne=80, nsd=8, crack=("penny", dict(center=(0.5, 0.5, 0.5), R=0.25, curv=0.3)), r_e=0.05),
+    # small cases for tests: several tiles and ragged tails, fast to generate
+    "edge4": dict(ne=4, nsd=2, crack=("edge", dict(x0=0.5, zf=0.45)), r_e=0.3),
+    "penny12": dict(ne=12, nsd=2, crack=("penny", dict(center=(0.5, 0.5, 0.5), R=0.25, curv=0.3)), r_e=0.1),
+    "plain6": dict(ne=6, nsd=2, crack=None, r_e=0.0),
+}
+
+
+def make_crack(spec):
+    if spec is None:
+        return None
+    kind, kw = spec
+    if kind == "edge":
+        return PlanarEdgeCrack(**kw)
+    if kind == "penny":
+        return CurvedPennyCrack(**kw)
+    raise ValueError(kind)
+
+
+def cache_dir():
+    d = os.environ.get("DPCG_FIXTURE_CACHE")
+    if not d:
+        d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_cache")
+    os.makedirs(d, exist_ok=True)
+    return d
+
+
+def _key(name, cfg):
+    blob = json.dumps({"v": GENERATOR_VERSION, "name": name, "cfg": cfg}, sort_keys=True, default=str)
+    return hashlib.sha1(blob.encode()).hexdigest()[:12]
+
+
+def load(name: str, use_cache: bool = True) -> Problem:
+    cfg = CONFIGS[name]
+    path = os.path.join(cache_dir(), f"{name}-{_key(name, cfg)}.npz")
+    if use_cache and os.path.exists(path):
+        d = np.load(path, allow_pickle=False)
+        meta = json.loads(str(d["meta"]))
+        meta["block_hist"] = {int(b): c for b, c in meta["block_hist"].items()}
+        return Problem(name=name, n=int(d["n"]), k_rowptr=d["k_rowptr"], k_col=d["k_col"],
+                       k_val=d["k_val"], f=d["f"], z_rowptr=d["z_rowptr"], z_col=d["z_col"],
+                       z_val=d["z_val"], k=int(d["k"]), block_ptr=d["block_ptr"], meta=meta)
+    p = build_problem(name, cfg["ne"], cfg["nsd"], crack=make_crack(cfg["crack"]), r_e=cfg["r_e"])
+    p.meta["config_hash"] = _key(name, cfg)
+    if use_cache:
+        tmp = path + ".tmp.npz"
+        np.savez(tmp, n=p.n, k_rowptr=p.k_rowptr, k_col=p.k_col, k_val=p.k_val, f=p.f,
+                 z_rowptr=p.z_rowptr, z_col=p.z_col, z_val=p.z_val, k=p.k, block_ptr=p.block_ptr,
+                 meta=json.dumps(p.meta))
+        os.replace(tmp, path)
+    return p
