@@ -1,0 +1,169 @@
+/*
+ * dpcg.h - C ABI of the MI355X (gfx950) deflated block-Jacobi conjugate gradient
+ * library: CG (Algorithm 1) preconditioned by the adapted-deflation operator
+ * A-DEF2 (Sec. 3.2, Algorithms 2 and 3) combined multiplicatively with a
+ * block-Jacobi preconditioner over small dense blocks (Sec. 3.4), for the SPD
+ * systems K u = f of XFEM/GFEM discretisations of cracked elastic bodies
+ * (Sec. 2.4, eq. linear_system).
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers (HBM of the current HIP device)
+ *     unless stated otherwise; scalars and the option/info structs are host.
+ *   - Floating point is IEEE binary64 throughout.
+ *   - Work is ordered on the HIP stream given to dpcg_setup.  Every call returns
+ *     to the host only once its results are final (a solve must learn on the host
+ *     whether it converged), so outputs may be read right after the call.
+ *   - A handle is not re-entrant: calls on one handle must not overlap.  Distinct
+ *     handles are independent.
+ *   - Return values are status codes (DPCG_OK = 0, positive = finished but not
+ *     converged, negative = error).  On error, outputs are unspecified unless the
+ *     entry point says otherwise, and info->bad_index names the offending item
+ *     when there is one.
+ */
+#ifndef DPCG_H
+#define DPCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DPCG_OK = 0,
+    DPCG_NOT_CONVERGED = 1,   /* max_iter reached; output holds the last iterate   */
+    DPCG_EINVAL = -1,         /* bad sizes, indices, ordering or partition         */
+    DPCG_ENOTSYM = -2,        /* |K - K^T| > 1e-12 max|K| (K must be SPD, Sec. 3.2) */
+    DPCG_EBLOCK_NOT_SPD = -3, /* a diagonal block K_BB is not SPD; bad_index=block */
+    DPCG_ECOARSE_NOT_SPD = -4,/* E = Z^T K Z not SPD: Z not of full column rank     */
+    DPCG_EBREAKDOWN = -5,     /* p^T K p <= 0 or non-finite alpha, beta, residual  */
+    DPCG_EHIP = -6,           /* HIP runtime or device allocation failure           */
+    DPCG_ENONFINITE = -7      /* NaN or Inf in an input vector                      */
+};
+
+typedef struct dpcg_ctx *dpcg_handle;
+
+typedef struct {
+    int32_t max_iter;          /* iteration cap (K p products); default 20000            */
+    int32_t check_every;       /* iterations enqueued between host polls; default 16     */
+    int32_t use_initial_guess; /* 1: u (or lambda) holds u_{-1} of Algorithm 2 on entry */
+    int32_t record_history;    /* 1: keep ||r_i||/||f|| for i = 0..iterations            */
+} dpcg_options;
+
+typedef struct {
+    int32_t status;            /* same value the call returned                          */
+    int32_t iterations;        /* number of K p products of Algorithm 1                 */
+    double rel_res_recursive;  /* ||r_i||_2 / ||f||_2 of the recursively updated r_i    */
+    double rel_res_true;       /* ||f - K u||_2 / ||f||_2 recomputed at exit            */
+    double setup_ms;           /* wall time of dpcg_setup                               */
+    double solve_ms;           /* wall time of the last solve                           */
+    int64_t bad_index;         /* offending block / row / iteration, or -1              */
+} dpcg_info;
+
+typedef struct {
+    int64_t n;                 /* unknowns                                              */
+    int64_t nnz;               /* scalar nonzeros of K                                  */
+    int64_t nnzb;              /* 3x3 blocks of the internal block-CSR copy of K        */
+    int64_t k;                 /* deflation vectors (columns of Z)                      */
+    int64_t nnz_z;             /* nonzeros of Z                                         */
+    int64_t nnz_kz;            /* nonzeros of K Z                                       */
+    int64_t nblocks;           /* block-Jacobi blocks                                   */
+    int64_t bj_values;         /* sum of squared block sizes (stored inverse entries)   */
+    int64_t device_bytes;      /* device memory held by the handle                      */
+} dpcg_stats;
+
+/* Fills *opt with the defaults above. */
+void dpcg_default_options(dpcg_options *opt);
+
+/*
+ * Builds a solver for K (n x n) with deflation matrix Z (n x k) and block
+ * partition block_ptr.
+ *
+ *   K:  CSR, full symmetric storage (both triangles), strictly increasing column
+ *       indices in each row.  k_rowptr[n+1] (int64), k_col[nnz] (int32),
+ *       k_val[nnz].  Unknowns are grouped in consecutive triplets (each nodal DoF
+ *       group of the XFEM approximation, eq. xfem_displ, is a 3-vector), so
+ *       n % 3 == 0; setup packs K into 3x3 blocks.
+ *   Z:  CSR n x k, the deflation basis W of Sec. 3.2 (subdomain rigid-body and
+ *       enriched modes of Sec. 3.3); k >= 0, k = 0 disables deflation (plain
+ *       block-Jacobi PCG).  Z must have full column rank.
+ *   block_ptr[nblocks+1] (int32): the block-Jacobi groups (eq. block_jacobi) as
+ *       contiguous ranges [block_ptr[b], block_ptr[b+1]) tiling [0, n), each of
+ *       1..18 unknowns (one node's standard plus enriched DoFs, eq.
+ *       block_jacobi_enr).
+ *   stream: hipStream_t (may be NULL for the default stream) on which all of the
+ *       handle's work is ordered.
+ *
+ * The library deep-copies what it needs; the caller may free K, Z and block_ptr
+ * on return.  Setup factorises every block and the coarse matrix E = Z^T K Z
+ * (Sec. 3.2; both applied at every iteration) and allocates all device memory
+ * the solves need.  Errors: DPCG_EINVAL, DPCG_ENOTSYM, DPCG_EBLOCK_NOT_SPD,
+ * DPCG_ECOARSE_NOT_SPD, DPCG_EHIP.  On error *h is NULL.  info may be NULL.
+ */
+int dpcg_setup(dpcg_handle *h, int64_t n,
+               const int64_t *k_rowptr, const int32_t *k_col, const double *k_val,
+               int32_t k, const int64_t *z_rowptr, const int32_t *z_col, const double *z_val,
+               int32_t nblocks, const int32_t *block_ptr,
+               void *stream, dpcg_info *info);
+
+/*
+ * Solves K u = f to ||r_i||_2 <= tol ||f||_2 (Sec. 4: relative tolerance) with
+ * Algorithm 1, started from Algorithm 2 and preconditioned by Algorithm 3.
+ * f[n] and u[n] are caller-owned device buffers; u is output, and also input
+ * (u_{-1}) when opt->use_initial_guess.  f = 0 gives u = 0 after 0 iterations.
+ * opt may be NULL (defaults).  Returns DPCG_OK, DPCG_NOT_CONVERGED (u holds the
+ * last iterate), DPCG_EBREAKDOWN (bad_index = iteration), DPCG_ENONFINITE,
+ * DPCG_EINVAL (tol <= 0 or max_iter < 0) or DPCG_EHIP.
+ */
+int dpcg_solve(dpcg_handle h, const double *f, double *u, double tol,
+               const dpcg_options *opt, dpcg_info *info);
+
+/*
+ * Solves K lambda = g with the same operator (K = K^T) and the same method as
+ * dpcg_solve, in a workspace of its own, so it never disturbs a forward solve's
+ * state.  This is the adjoint solve of a loss L(u): g = dL/du.
+ */
+int dpcg_solve_adjoint(dpcg_handle h, const double *g, double *lambda, double tol,
+                       const dpcg_options *opt, dpcg_info *info);
+
+/* Releases every resource of the handle (NULL is a no-op). */
+void dpcg_destroy(dpcg_handle h);
+
+/* Static description of a status code. */
+const char *dpcg_status_string(int status);
+
+/* Sizes of the factorised operator; *out is host memory. */
+int dpcg_get_stats(dpcg_handle h, dpcg_stats *out);
+
+/* Residual history ||r_i||/||f||, i = 0..iterations, of the last forward solve run
+ * with record_history; copies up to cap values into host memory out and returns
+ * how many were written (negative status on error). */
+int64_t dpcg_get_history(dpcg_handle h, double *out, int64_t cap);
+
+/* ---- single steps of the iteration, each the kernel the solve runs ---- */
+
+/* y = K x (Algorithm 1's K p_i) with the block-CSR kernel.  x, y: device, n. */
+int dpcg_spmv(dpcg_handle h, const double *x, double *y);
+
+/* y = M^{-1} r, the block-Jacobi apply inside Algorithm 3 (eq. block_jacobi). */
+int dpcg_bj_apply(dpcg_handle h, const double *r, double *y);
+
+/* g = Z^T a - (K Z)^T b (k-vector), the merged right-hand side of Algorithm 3's
+ * two coarse solves: Z^T r - Z^T K y with a = r, b = y.  b may be NULL (b = 0). */
+int dpcg_restrict(dpcg_handle h, const double *a, const double *b, double *g);
+
+/* delta = E^{-1} g, E = Z^T K Z (k-vectors). */
+int dpcg_coarse_apply(dpcg_handle h, const double *g, double *delta);
+
+/* out = base + Z delta (base may be NULL for 0). */
+int dpcg_prolong(dpcg_handle h, const double *base, const double *delta, double *out);
+
+/* z = A-DEF2 applied to r (Algorithm 3): z = y + Z E^{-1} (Z^T r - Z^T K y),
+ * y = M^{-1} r. */
+int dpcg_precond(dpcg_handle h, const double *r, double *z);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPCG_H */

@@ -37,6 +37,8 @@ def lib():
             getattr(L, name).argtypes = [P, P, P] if name != "oracle_coarse_matrix" else [P, P]
         L.oracle_adef2_apply.argtypes = [P, P, P, P]
         L.oracle_start.argtypes = [P, P, P, P, P]
+        L.oracle_zt_times.argtypes = [P, P, P]
+        L.oracle_x_plus_z_times.argtypes = [P, P, P, P]
         L.oracle_k.argtypes = [P]
         L.oracle_k.restype = C.c_int32
         _lib = L
@@ -117,6 +119,16 @@ class Oracle:
         E = np.zeros((self.k, self.k))
         lib().oracle_coarse_matrix(self._h, _p(E))
         return E
+
+    def zt_times(self, x):
+        return self._vec("oracle_zt_times", x, self.k)
+
+    def x_plus_z_times(self, x, c):
+        c = np.ascontiguousarray(c, np.float64)
+        xx = None if x is None else np.ascontiguousarray(x, np.float64)
+        y = np.zeros(self.n)
+        lib().oracle_x_plus_z_times(self._h, _p(xx), _p(c), _p(y))
+        return y
 
     def adef2_apply(self, r):
         r = np.ascontiguousarray(r, np.float64)

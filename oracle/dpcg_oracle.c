@@ -413,3 +413,17 @@ void oracle_coarse_matrix(const oracle_t *o, double *out) {
 }
 
 int32_t oracle_k(const oracle_t *o) { return o->k; }
+
+/* b = Z^T x (k-vector). */
+void oracle_zt_times(const oracle_t *o, const double *x, double *b) { zt_times(o, x, b); }
+
+/* y = x + Z c (x nullable: 0). */
+void oracle_x_plus_z_times(const oracle_t *o, const double *x, const double *c, double *y) {
+    if (x) {
+        x_plus_z_times(o, x, c, y);
+    } else {
+        double *zero = (double *)calloc((size_t)o->n, sizeof(double));
+        x_plus_z_times(o, zero, c, y);
+        free(zero);
+    }
+}

@@ -1,0 +1,13 @@
+"""MI355X-native deflated block-Jacobi conjugate gradient for XFEM/GFEM crack systems.
+
+CG preconditioned by the adapted-deflation operator A-DEF2 with a block-Jacobi
+smoother over nodal blocks (Agathos, Dodwell, Chatzi, Bordas), implemented as HIP
+kernels for gfx950 behind the C ABI of ``include/dpcg.h``.  This package is the
+binding: ``Solver`` marshals device tensors to the library, which does all of the
+arithmetic.
+"""
+from ._binding import (DpcgError, Info, Options, Solver, Stats, lib,  # noqa: F401
+                       status_string)
+from . import _binding as abi  # noqa: F401
+
+__all__ = ["Solver", "DpcgError", "lib", "status_string", "abi"]

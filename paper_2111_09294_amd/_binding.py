@@ -1,0 +1,280 @@
+"""ctypes binding of libdpcg.so (argument marshalling only).
+
+Every computation runs in the library's HIP kernels; PyTorch supplies device
+memory and the HIP stream.  There is no fallback: if the shared library is not
+built, importing a solver raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpcg.so")
+
+OK, NOT_CONVERGED, EINVAL, ENOTSYM, EBLOCK_NOT_SPD, ECOARSE_NOT_SPD, EBREAKDOWN, EHIP, ENONFINITE = (
+    0, 1, -1, -2, -3, -4, -5, -6, -7)
+
+
+class Options(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("check_every", C.c_int32), ("use_initial_guess", C.c_int32),
+                ("record_history", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("rel_res_recursive", C.c_double),
+                ("rel_res_true", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
+                ("bad_index", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Stats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in ("n", "nnz", "nnzb", "k", "nnz_z", "nnz_kz", "nblocks", "bj_values",
+                                         "device_bytes")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+P = C.c_void_p
+# name -> (restype, argtypes), mirroring include/dpcg.h
+SIGNATURES = {
+    "dpcg_default_options": (None, [C.POINTER(Options)]),
+    "dpcg_setup": (C.c_int, [C.POINTER(P), C.c_int64, P, P, P, C.c_int32, P, P, P, C.c_int32, P, P,
+                             C.POINTER(Info)]),
+    "dpcg_solve": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
+    "dpcg_solve_adjoint": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
+    "dpcg_destroy": (None, [P]),
+    "dpcg_status_string": (C.c_char_p, [C.c_int]),
+    "dpcg_get_stats": (C.c_int, [P, C.POINTER(Stats)]),
+    "dpcg_get_history": (C.c_int64, [P, P, C.c_int64]),
+    "dpcg_spmv": (C.c_int, [P, P, P]),
+    "dpcg_bj_apply": (C.c_int, [P, P, P]),
+    "dpcg_restrict": (C.c_int, [P, P, P, P]),
+    "dpcg_coarse_apply": (C.c_int, [P, P, P]),
+    "dpcg_prolong": (C.c_int, [P, P, P, P]),
+    "dpcg_precond": (C.c_int, [P, P, P]),
+}
+
+
+def lib():
+    """The loaded libdpcg.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback path)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(code: int) -> str:
+    return lib().dpcg_status_string(int(code)).decode()
+
+
+class DpcgError(RuntimeError):
+    def __init__(self, code, where, info=None):
+        self.code = int(code)
+        self.info = info
+        bad = f", bad index {info.bad_index}" if info is not None and info.bad_index >= 0 else ""
+        super().__init__(f"{where}: {status_string(code)} (status {code}{bad})")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_dev(t, dtype, name, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t
+
+
+class Solver:
+    """Handle of the deflated block-Jacobi CG solver for one matrix K.
+
+    All arrays are device tensors: K as CSR (int64 rowptr, int32 col, float64 val),
+    Z as CSR (same types), the block partition as int32.  The library copies what
+    it keeps; the tensors may be released after construction.
+    """
+
+    def __init__(self, n, k_rowptr, k_col, k_val, k, z_rowptr, z_col, z_val, block_ptr, stream=None):
+        import torch
+        self.n, self.k = int(n), int(k)
+        _check_dev(k_rowptr, torch.int64, "k_rowptr", self.n + 1)
+        _check_dev(k_col, torch.int32, "k_col")
+        _check_dev(k_val, torch.float64, "k_val", k_col.numel())
+        _check_dev(block_ptr, torch.int32, "block_ptr")
+        if self.k > 0:
+            _check_dev(z_rowptr, torch.int64, "z_rowptr", self.n + 1)
+            _check_dev(z_col, torch.int32, "z_col")
+            _check_dev(z_val, torch.float64, "z_val", z_col.numel())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = k_val.device
+        h = C.c_void_p()
+        info = Info()
+        st = lib().dpcg_setup(C.byref(h), self.n, _ptr(k_rowptr), _ptr(k_col), _ptr(k_val), self.k,
+                              _ptr(z_rowptr) if self.k else None, _ptr(z_col) if self.k else None,
+                              _ptr(z_val) if self.k else None, block_ptr.numel() - 1, _ptr(block_ptr),
+                              C.c_void_p(self.stream.cuda_stream), C.byref(info))
+        if st != OK:
+            raise DpcgError(st, "dpcg_setup", info)
+        self._h = h
+        self.setup_info = info.as_dict()
+
+    @classmethod
+    def from_problem(cls, p, device="cuda", stream=None):
+        """Uploads a fixtures.Problem (numpy arrays) and builds the solver."""
+        import torch
+        t = lambda a, dt: torch.as_tensor(a).to(device=device, dtype=dt).contiguous()  # noqa: E731
+        zr = t(p.z_rowptr, torch.int64) if p.k else None
+        return cls(p.n, t(p.k_rowptr, torch.int64), t(p.k_col, torch.int32), t(p.k_val, torch.float64), p.k,
+                   zr, t(p.z_col, torch.int32) if p.k else None, t(p.z_val, torch.float64) if p.k else None,
+                   t(p.block_ptr, torch.int32), stream=stream)
+
+    # ------------------------------------------------------------------ lifecycle
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().dpcg_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("solver is closed")
+        return self._h
+
+    # ------------------------------------------------------------------ solves
+    def _opts(self, max_iter, check_every, guess, record):
+        o = Options()
+        lib().dpcg_default_options(C.byref(o))
+        if max_iter is not None:
+            o.max_iter = int(max_iter)
+        if check_every is not None:
+            o.check_every = int(check_every)
+        o.use_initial_guess = int(bool(guess))
+        o.record_history = int(bool(record))
+        return o
+
+    def _run(self, fn, where, f, u, tol, max_iter, check_every, initial_guess, record_history, raise_on_error):
+        import torch
+        _check_dev(f, torch.float64, "rhs", self.n)
+        if u is None:
+            u = torch.empty(self.n, dtype=torch.float64, device=f.device)
+        _check_dev(u, torch.float64, "solution", self.n)
+        if initial_guess is not None:
+            _check_dev(initial_guess, torch.float64, "initial_guess", self.n)
+            if initial_guess.data_ptr() != u.data_ptr():
+                u.copy_(initial_guess)
+        o = self._opts(max_iter, check_every, initial_guess is not None, record_history)
+        info = Info()
+        st = fn(self.handle, _ptr(f), _ptr(u), float(tol), C.byref(o), C.byref(info))
+        if st < 0 and raise_on_error:
+            raise DpcgError(st, where, info)
+        return u, info.as_dict()
+
+    def solve(self, f, u=None, tol=1e-8, max_iter=None, check_every=None, initial_guess=None,
+              record_history=False, raise_on_error=True):
+        """u = K^{-1} f to ||r||/||f|| <= tol.  Returns (u, info dict)."""
+        return self._run(lib().dpcg_solve, "dpcg_solve", f, u, tol, max_iter, check_every, initial_guess,
+                         record_history, raise_on_error)
+
+    def solve_adjoint(self, g, lam=None, tol=1e-8, max_iter=None, check_every=None, initial_guess=None,
+                      raise_on_error=True):
+        """lambda = K^{-1} g in the adjoint workspace.  Returns (lambda, info dict)."""
+        return self._run(lib().dpcg_solve_adjoint, "dpcg_solve_adjoint", g, lam, tol, max_iter, check_every,
+                         initial_guess, False, raise_on_error)
+
+    def history(self):
+        import numpy as np
+        buf = np.zeros(200001)
+        m = lib().dpcg_get_history(self.handle, buf.ctypes.data_as(C.c_void_p), len(buf))
+        if m < 0:
+            raise DpcgError(m, "dpcg_get_history")
+        return buf[:m].copy()
+
+    def stats(self):
+        s = Stats()
+        st = lib().dpcg_get_stats(self.handle, C.byref(s))
+        if st != OK:
+            raise DpcgError(st, "dpcg_get_stats")
+        return s.as_dict()
+
+    # ------------------------------------------------------------------ single steps
+    def _call(self, name, *args):
+        st = getattr(lib(), name)(self.handle, *[_ptr(a) for a in args])
+        if st != OK:
+            raise DpcgError(st, name)
+
+    def spmv(self, x, y=None):
+        import torch
+        _check_dev(x, torch.float64, "x", self.n)
+        y = torch.empty_like(x) if y is None else y
+        self._call("dpcg_spmv", x, y)
+        return y
+
+    def bj_apply(self, r):
+        import torch
+        _check_dev(r, torch.float64, "r", self.n)
+        y = torch.empty_like(r)
+        self._call("dpcg_bj_apply", r, y)
+        return y
+
+    def restrict(self, a, b=None):
+        import torch
+        _check_dev(a, torch.float64, "a", self.n)
+        if b is not None:
+            _check_dev(b, torch.float64, "b", self.n)
+        g = torch.zeros(max(self.k, 1), dtype=torch.float64, device=a.device)
+        self._call("dpcg_restrict", a, b, g)
+        return g[: self.k]
+
+    def coarse_apply(self, g):
+        import torch
+        _check_dev(g, torch.float64, "g", self.k)
+        d = torch.zeros(max(self.k, 1), dtype=torch.float64, device=g.device)
+        self._call("dpcg_coarse_apply", g, d)
+        return d[: self.k]
+
+    def prolong(self, delta, base=None):
+        import torch
+        _check_dev(delta, torch.float64, "delta", self.k)
+        out = torch.empty(self.n, dtype=torch.float64, device=delta.device)
+        self._call("dpcg_prolong", base, delta, out)
+        return out
+
+    def precond(self, r):
+        import torch
+        _check_dev(r, torch.float64, "r", self.n)
+        z = torch.empty_like(r)
+        self._call("dpcg_precond", r, z)
+        return z

@@ -1,0 +1,113 @@
+// Internal data layout of a dpcg handle and the kernel launchers.
+//
+// Device layout (all in HBM, FP64 values, int32 indices):
+//   K   block-CSR over DoF triplets: brow_ptr[nb+1], bcol[nnzb], and the nine
+//       entries of each 3x3 block stored as nine planes, bval[e*nnzb + blk] with
+//       e = 3*i + j, so lanes working on consecutive blocks read consecutive words.
+//   M^-1 explicit inverse of each block-Jacobi block, row-major, concatenated;
+//       per DoF d: bj_rowoff[d] = offset of d's row, bj_meta[d] = size<<8 | (d -
+//       block start).  DoF range of workgroup w of the update kernel:
+//       [bj_wg_start[w], bj_wg_start[w+1]) holds whole blocks only.
+//   Z   CSR by rows (prolongation), Z^T and (KZ)^T as CSR with k rows
+//       (restriction), E^-1 dense k x k row-major (symmetric).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/dpcg.h"
+
+namespace dpcg {
+
+constexpr int kThreads = 256;     // threads per workgroup everywhere
+constexpr int kMaxBlock = 18;     // largest block-Jacobi block
+
+// Solver state shared by the kernels of one solve; lives in device memory.  Every
+// field is written by exactly one thread of one kernel, and read only by kernels
+// that run after that one in stream order.
+struct State {
+    int32_t flag;        // kRunning, kConverged, kMaxIter, kBreakdown
+    int32_t iter;        // index i of the iteration in flight (incremented by the prolongation)
+    int32_t iters_done;  // final iteration count, set together with the flag
+    int32_t bad;         // iteration of a breakdown
+    double thr;          // tol * ||f||_2
+    double rho_new;      // rho_i = r_i^T z_i, written by the SpMV kernel
+    double rho_old;      // rho_{i-1}, written by the update kernel
+    double rr;           // ||r||^2 of the last check
+    double aux;          // scratch scalar for one-off reductions
+    int32_t nonfinite;   // set by the input check
+    int32_t pad;
+};
+
+enum : int32_t { kRunning = 0, kConverged = 1, kMaxIter = 2, kBreakdown = 3 };
+
+struct Workspace {
+    double *r = nullptr, *y = nullptr, *z = nullptr, *q = nullptr, *p[2] = {nullptr, nullptr};
+    double *g = nullptr, *delta = nullptr, *tmp = nullptr;
+    double *part_a = nullptr;   // partial sums (p^T q, r^T r, r^T z); sized max grid
+    double *part_b = nullptr;
+    double *part_c = nullptr;
+    State *st = nullptr;        // device
+    State *snap = nullptr;      // pinned host mirror
+    double *hist = nullptr;     // device, ||r_i|| per iteration
+    int64_t hist_cap = 0;
+    std::vector<double> host_hist;
+    int32_t hist_len = 0;
+};
+
+struct SpmvPlan {
+    int group = 16;          // lanes per block row
+    int nwg = 0;             // workgroups
+    int steps = 0;           // row steps in total (rows per step = 4 * 64 / group)
+};
+
+}  // namespace dpcg
+
+struct dpcg_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int64_t n = 0, nnz = 0, nnzb = 0, nnz_z = 0, nnz_kz = 0, bj_values = 0, device_bytes = 0;
+    int32_t nb = 0, k = 0, nblocks = 0;
+    // K
+    int32_t *brow_ptr = nullptr, *bcol = nullptr;
+    double *bval = nullptr;
+    // block-Jacobi
+    double *minv = nullptr;
+    int32_t *bj_rowoff = nullptr, *bj_meta = nullptr, *bj_wg_start = nullptr;
+    int32_t bj_nwg = 0, bj_ntiles = 0;
+    // deflation
+    int32_t *z_ptr = nullptr, *z_col = nullptr;
+    double *z_val = nullptr;
+    int32_t *zt_ptr = nullptr, *zt_idx = nullptr;
+    double *zt_val = nullptr;
+    int32_t *kzt_ptr = nullptr, *kzt_idx = nullptr;
+    double *kzt_val = nullptr;
+    double *einv = nullptr;
+    // launch shapes
+    dpcg::SpmvPlan spmv;
+    int32_t vec_nwg = 0;       // grid of the elementwise kernels (one DoF per thread)
+    dpcg::Workspace ws[2];     // [0] forward solves, [1] adjoint solves
+    std::vector<void *> allocations;
+    double setup_ms = 0.0;
+};
+
+namespace dpcg {
+
+// ---- launchers (kernels.hip); all enqueue on ctx->stream and return hipError_t ----
+hipError_t launch_check_finite_norm(const dpcg_ctx *c, const double *a, const double *b, Workspace &w);
+hipError_t launch_spmv_plain(const dpcg_ctx *c, const double *x, double *y);
+hipError_t launch_spmv_residual(const dpcg_ctx *c, const double *x, const double *f, double *r,
+                                double *part, Workspace &w, int check);
+hipError_t launch_spmv_p(const dpcg_ctx *c, Workspace &w);
+hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w);
+hipError_t launch_bj(const dpcg_ctx *c, const double *r, double *y, Workspace *w);
+hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, double *g, Workspace *w,
+                           int check, int n_parts, int iter_offset, int max_iter, int record);
+hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Workspace *w);
+hipError_t launch_prolong(const dpcg_ctx *c, const double *base, const double *delta, double *out,
+                          Workspace *w, const double *rdot, int advance);
+hipError_t launch_reduce_aux(const dpcg_ctx *c, Workspace &w, int n_parts);
+
+}  // namespace dpcg

@@ -1,0 +1,512 @@
+// HIP kernels (gfx950, wave64) of one deflated block-Jacobi CG iteration.
+//
+// One iteration of Algorithm 1 preconditioned by Algorithm 3 runs as five kernels:
+//   spmv_p       p_i = z_i + beta p_{i-1} (formed on the fly), q = K p_i, p_i^T q partials
+//   update_bj    alpha = rho_i / p^T q; u += alpha p; r -= alpha q; ||r||^2 partials;
+//                y = M^{-1} r over whole blocks staged in LDS
+//   restrict     convergence test; g = Z^T r - (K Z)^T y  (the two right-hand sides of
+//                Algorithm 3's coarse solves, merged by linearity, with Z^T K y = (KZ)^T y)
+//   coarse       delta = E^{-1} g  (both coarse solves at once: lambda - mu = delta)
+//   prolong      z = y + Z delta; r^T z partials; advance the iteration counter
+// Global reductions are two-stage and fixed-order (per-workgroup partials, then a
+// sequential-per-thread + fixed-tree sum), so results are bitwise reproducible.  No
+// floating-point atomics are used.  Convergence and breakdown are decided on the
+// device; every kernel returns at once when the state flag is set.
+#include "dpcg_internal.h"
+
+namespace dpcg {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// Sum over the workgroup; every thread receives the same value.
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wv] = v;
+    __syncthreads();
+    return (lds[0] + lds[1]) + (lds[2] + lds[3]);
+}
+
+// Fixed-order sum of n partials, valid in every thread.
+__device__ __forceinline__ double reduce_parts(const double *parts, int n, double *lds) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kThreads) s += parts[i];
+    return block_sum(s, lds);
+}
+
+__device__ __forceinline__ bool leader() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// The state flag as seen by the whole workgroup: one thread reads it and the value is
+// broadcast through LDS, so every wave of the workgroup takes the same branch even when
+// another workgroup of the same kernel changes the flag meanwhile.
+__device__ __forceinline__ int32_t wg_flag(const State *st) {
+    __shared__ int32_t f;
+    if (threadIdx.x == 0) f = __atomic_load_n(&st->flag, __ATOMIC_RELAXED);
+    __syncthreads();
+    const int32_t v = f;
+    __syncthreads();
+    return v;
+}
+
+// The hardware spreads consecutive workgroups round-robin over the 8 XCDs; give each
+// XCD a contiguous range of work so neighbouring rows share its L2.
+__device__ __forceinline__ int xcd_remap(int w, int nwg) {
+    if ((nwg & 7) != 0) return w;
+    return (w & 7) * (nwg >> 3) + (w >> 3);
+}
+
+struct XPlain {
+    const double *__restrict__ x;
+    __device__ __forceinline__ double operator()(int64_t i) const { return x[i]; }
+};
+
+// p_i = z_i + beta p_{i-1}, recomputed wherever p_i is gathered (same expression, same bits).
+struct XDirection {
+    const double *__restrict__ z;
+    const double *__restrict__ pprev;
+    double beta;
+    bool first;
+    __device__ __forceinline__ double operator()(int64_t i) const {
+        return first ? z[i] : fma(beta, pprev[i], z[i]);
+    }
+};
+
+// q_R = sum_b K_Rb x_b for block row R, computed by a group of G lanes; the three
+// sums end up in every lane of the group.  Lanes of groups without a row pass
+// row = -1 and take part in the shuffles with zeros.
+template <int G, class XL>
+__device__ __forceinline__ void block_row(int row, int lg, const int32_t *__restrict__ brow_ptr,
+                                          const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+                                          int64_t nnzb, const XL &xl, double &a0, double &a1, double &a2) {
+    a0 = a1 = a2 = 0.0;
+    if (row >= 0) {
+        const int beg = brow_ptr[row], end = brow_ptr[row + 1];
+        for (int b = beg + lg; b < end; b += G) {
+            const double v0 = bval[b], v1 = bval[nnzb + b], v2 = bval[2 * nnzb + b];
+            const double v3 = bval[3 * nnzb + b], v4 = bval[4 * nnzb + b], v5 = bval[5 * nnzb + b];
+            const double v6 = bval[6 * nnzb + b], v7 = bval[7 * nnzb + b], v8 = bval[8 * nnzb + b];
+            const int64_t c = 3 * (int64_t)bcol[b];
+            const double x0 = xl(c), x1 = xl(c + 1), x2 = xl(c + 2);
+            a0 = fma(v0, x0, fma(v1, x1, fma(v2, x2, a0)));
+            a1 = fma(v3, x0, fma(v4, x1, fma(v5, x2, a1)));
+            a2 = fma(v6, x0, fma(v7, x1, fma(v8, x2, a2)));
+        }
+    }
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) {
+        a0 += __shfl_xor(a0, off);
+        a1 += __shfl_xor(a1, off);
+        a2 += __shfl_xor(a2, off);
+    }
+}
+
+struct SpmvShape {
+    int32_t nb;
+    int32_t steps;
+    int32_t nwg;
+};
+
+// Row handled by this lane group at step s, or -1.
+template <int G>
+__device__ __forceinline__ int step_row(int s, int nb) {
+    constexpr int kGroupsPerWave = 64 / G;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = (s * 4 + wv) * kGroupsPerWave + lane / G;
+    return row < nb ? row : -1;
+}
+
+__device__ __forceinline__ double pick3(int lg, double a0, double a1, double a2) {
+    return lg == 0 ? a0 : (lg == 1 ? a1 : a2);
+}
+
+// MODE 0: y = K x.   MODE 1: r = f - K x and ||r||^2 partials.
+template <int G, int MODE>
+__global__ __launch_bounds__(kThreads) void k_spmv(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
+                                                   const int32_t *__restrict__ bcol,
+                                                   const double *__restrict__ bval, int64_t nnzb,
+                                                   const double *__restrict__ x, const double *__restrict__ f,
+                                                   double *__restrict__ y, double *__restrict__ part) {
+    __shared__ double lds[4];
+    const int w = xcd_remap(blockIdx.x, sh.nwg);
+    const int s0 = (int)(((int64_t)w * sh.steps) / sh.nwg), s1 = (int)(((int64_t)(w + 1) * sh.steps) / sh.nwg);
+    const int lg = threadIdx.x % G;
+    XPlain xl{x};
+    double acc = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        const int row = step_row<G>(s, sh.nb);
+        double a0, a1, a2;
+        block_row<G>(row, lg, brow_ptr, bcol, bval, nnzb, xl, a0, a1, a2);
+        if (row >= 0 && lg < 3) {
+            const int64_t i = 3 * (int64_t)row + lg;
+            const double v = pick3(lg, a0, a1, a2);
+            if (MODE == 0) {
+                y[i] = v;
+            } else {
+                const double ri = f[i] - v;
+                y[i] = ri;
+                acc = fma(ri, ri, acc);
+            }
+        }
+    }
+    if (MODE == 1) {
+        const double t = block_sum(acc, lds);
+        if (threadIdx.x == 0) part[blockIdx.x] = t;
+    }
+}
+
+// Search direction and matrix product of Algorithm 1 for iteration i = st->iter:
+// p_i = z_i + beta_{i-1} p_{i-1} (p_0 = z_0), q = K p_i, and partials of p_i^T q.
+template <int G>
+__global__ __launch_bounds__(kThreads) void k_spmv_p(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
+                                                     const int32_t *__restrict__ bcol,
+                                                     const double *__restrict__ bval, int64_t nnzb,
+                                                     const double *__restrict__ z, double *p0, double *p1,
+                                                     double *__restrict__ q, const double *__restrict__ part_rho,
+                                                     int n_rho, double *__restrict__ part_pq, State *st) {
+    __shared__ double lds[4];
+    if (wg_flag(st) != kRunning) return;
+    const int it = st->iter;
+    const double rho = reduce_parts(part_rho, n_rho, lds);
+    if (it > 0 && !isfinite(rho)) {
+        if (leader()) {
+            st->flag = kBreakdown;
+            st->bad = it - 1;
+            st->iters_done = it;
+        }
+        return;
+    }
+    const bool first = (it == 0);
+    const double beta = first ? 0.0 : rho / st->rho_old;
+    if (leader()) st->rho_new = rho;
+    double *pout = (it & 1) ? p1 : p0;
+    const double *pprev = (it & 1) ? p0 : p1;
+    XDirection xl{z, pprev, beta, first};
+    const int w = xcd_remap(blockIdx.x, sh.nwg);
+    const int s0 = (int)(((int64_t)w * sh.steps) / sh.nwg), s1 = (int)(((int64_t)(w + 1) * sh.steps) / sh.nwg);
+    const int lg = threadIdx.x % G;
+    double acc = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        const int row = step_row<G>(s, sh.nb);
+        double a0, a1, a2;
+        block_row<G>(row, lg, brow_ptr, bcol, bval, nnzb, xl, a0, a1, a2);
+        if (row >= 0 && lg < 3) {
+            const int64_t i = 3 * (int64_t)row + lg;
+            const double v = pick3(lg, a0, a1, a2);
+            const double pi = xl(i);
+            q[i] = v;
+            pout[i] = pi;
+            acc = fma(pi, v, acc);
+        }
+    }
+    const double t = block_sum(acc, lds);
+    if (threadIdx.x == 0) part_pq[blockIdx.x] = t;
+}
+
+// y_d = sum_j Minv_B[d - s_B, j] r_{s_B + j} for the DoFs of this tile (whole blocks).
+__device__ __forceinline__ double bj_row(int t, int64_t d, const double *tile, const double *__restrict__ minv,
+                                         const int32_t *__restrict__ bj_rowoff,
+                                         const int32_t *__restrict__ bj_meta) {
+    const int meta = bj_meta[d];
+    const int size = meta >> 8, loc = meta & 255;
+    const double *m = minv + bj_rowoff[d];
+    const double *rt = tile + (t - loc);
+    double s = 0.0;
+    for (int j = 0; j < size; ++j) s = fma(m[j], rt[j], s);
+    return s;
+}
+
+// Step length, solution and residual updates of Algorithm 1 with the residual norm
+// partials, then the block-Jacobi apply y = M^{-1} r that opens Algorithm 3.
+__global__ __launch_bounds__(kThreads) void k_update_bj(
+    int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start, double *__restrict__ u,
+    double *__restrict__ r, double *__restrict__ y, const double *__restrict__ q, const double *p0,
+    const double *p1, const double *__restrict__ minv, const int32_t *__restrict__ bj_rowoff,
+    const int32_t *__restrict__ bj_meta, const double *__restrict__ part_pq, int n_pq,
+    double *__restrict__ part_rr, State *st) {
+    __shared__ double lds[4];
+    __shared__ double tile[kThreads];
+    if (wg_flag(st) != kRunning) return;
+    const double pq = reduce_parts(part_pq, n_pq, lds);
+    const double alpha = st->rho_new / pq;
+    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(alpha)) {
+        if (leader()) {
+            st->flag = kBreakdown;
+            st->bad = st->iter;
+            st->iters_done = st->iter;
+        }
+        return;
+    }
+    if (leader()) st->rho_old = st->rho_new;
+    const double *p = (st->iter & 1) ? p1 : p0;
+    const int t = threadIdx.x;
+    const int w = xcd_remap(blockIdx.x, nwg);
+    const int t0 = (int)(((int64_t)w * ntiles) / nwg), t1 = (int)(((int64_t)(w + 1) * ntiles) / nwg);
+    double acc = 0.0;
+    for (int tt = t0; tt < t1; ++tt) {
+        const int64_t d0 = tile_start[tt], d1 = tile_start[tt + 1];
+        const int64_t d = d0 + t;
+        __syncthreads();
+        if (d < d1) {
+            u[d] = fma(alpha, p[d], u[d]);
+            const double rn = fma(-alpha, q[d], r[d]);
+            r[d] = rn;
+            tile[t] = rn;
+            acc = fma(rn, rn, acc);
+        }
+        __syncthreads();
+        if (d < d1) y[d] = bj_row(t, d, tile, minv, bj_rowoff, bj_meta);
+    }
+    const double s = block_sum(acc, lds);
+    if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+}
+
+// y = M^{-1} r only.
+__global__ __launch_bounds__(kThreads) void k_bj(int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start,
+                                                 const double *__restrict__ r, double *__restrict__ y,
+                                                 const double *__restrict__ minv,
+                                                 const int32_t *__restrict__ bj_rowoff,
+                                                 const int32_t *__restrict__ bj_meta, const State *st) {
+    __shared__ double tile[kThreads];
+    if (st && wg_flag(st) != kRunning) return;
+    const int t = threadIdx.x;
+    const int w = xcd_remap(blockIdx.x, nwg);
+    const int t0 = (int)(((int64_t)w * ntiles) / nwg), t1 = (int)(((int64_t)(w + 1) * ntiles) / nwg);
+    for (int tt = t0; tt < t1; ++tt) {
+        const int64_t d0 = tile_start[tt], d1 = tile_start[tt + 1];
+        const int64_t d = d0 + t;
+        __syncthreads();
+        if (d < d1) tile[t] = r[d];
+        __syncthreads();
+        if (d < d1) y[d] = bj_row(t, d, tile, minv, bj_rowoff, bj_meta);
+    }
+}
+
+// Convergence test (workgroup 0 only) and g_j = Z^T a - (K Z)^T b, one column per workgroup.
+__global__ __launch_bounds__(kThreads) void k_restrict(
+    int32_t k, const int32_t *__restrict__ zt_ptr, const int32_t *__restrict__ zt_idx,
+    const double *__restrict__ zt_val, const int32_t *__restrict__ kzt_ptr, const int32_t *__restrict__ kzt_idx,
+    const double *__restrict__ kzt_val, const double *__restrict__ a, const double *__restrict__ b,
+    double *__restrict__ g, State *st, const double *__restrict__ part_rr, int n_rr, int iter_offset,
+    int max_iter, double *__restrict__ hist) {
+    __shared__ double lds[4];
+    if (st) {
+        if (wg_flag(st) != kRunning) return;
+        if (blockIdx.x == 0 && n_rr > 0) {
+            const double rr = reduce_parts(part_rr, n_rr, lds);
+            if (threadIdx.x == 0) {
+                const int done = st->iter + iter_offset;
+                st->rr = rr;
+                const double rn = sqrt(rr);
+                if (hist) hist[done] = rn;
+                if (!isfinite(rr)) {
+                    st->flag = kBreakdown;
+                    st->bad = st->iter;
+                    st->iters_done = done;
+                } else if (rn <= st->thr) {
+                    st->flag = kConverged;
+                    st->iters_done = done;
+                } else if (done >= max_iter) {
+                    st->flag = kMaxIter;
+                    st->iters_done = done;
+                }
+            }
+        }
+    }
+    for (int j = blockIdx.x; j < k; j += gridDim.x) {
+        double s = 0.0;
+        for (int e = zt_ptr[j] + threadIdx.x; e < zt_ptr[j + 1]; e += kThreads) s = fma(zt_val[e], a[zt_idx[e]], s);
+        if (b)
+            for (int e = kzt_ptr[j] + threadIdx.x; e < kzt_ptr[j + 1]; e += kThreads)
+                s = fma(-kzt_val[e], b[kzt_idx[e]], s);
+        s = block_sum(s, lds);
+        if (threadIdx.x == 0) g[j] = s;
+    }
+}
+
+// delta = E^{-1} g: one wave per row of the dense symmetric inverse.
+__global__ __launch_bounds__(kThreads) void k_coarse(int32_t k, const double *__restrict__ einv,
+                                                     const double *__restrict__ g, double *__restrict__ delta,
+                                                     const State *st) {
+    if (st && wg_flag(st) != kRunning) return;
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= k) return;
+    const double *e = einv + (int64_t)row * k;
+    double s = 0.0;
+    for (int l = lane; l < k; l += 64) s = fma(e[l], g[l], s);
+    s = wave_sum(s);
+    if (lane == 0) delta[row] = s;
+}
+
+// out = base + Z delta; optional partials of rdot^T out; optionally advance the iteration.
+__global__ __launch_bounds__(kThreads) void k_prolong(int64_t n, int32_t nwg, const int32_t *__restrict__ z_ptr,
+                                                      const int32_t *__restrict__ z_col,
+                                                      const double *__restrict__ z_val,
+                                                      const double *__restrict__ delta,
+                                                      const double *base, double *out,
+                                                      const double *__restrict__ rdot, double *__restrict__ part,
+                                                      State *st, int advance) {
+    __shared__ double lds[4];
+    if (st && wg_flag(st) != kRunning) return;
+    const int w = xcd_remap(blockIdx.x, nwg);
+    const int64_t per = (n + nwg - 1) / nwg;
+    const int64_t d0 = (int64_t)w * per, d1 = min(n, d0 + per);
+    double acc = 0.0;
+    for (int64_t d = d0 + threadIdx.x; d < d1; d += kThreads) {
+        double s = base ? base[d] : 0.0;
+        double c = 0.0;
+        for (int e = z_ptr[d]; e < z_ptr[d + 1]; ++e) c = fma(z_val[e], delta[z_col[e]], c);
+        s += c;
+        out[d] = s;
+        if (rdot) acc = fma(rdot[d], s, acc);
+    }
+    if (rdot) {
+        const double t = block_sum(acc, lds);
+        if (threadIdx.x == 0) part[blockIdx.x] = t;
+    }
+    if (advance && leader()) st->iter = st->iter + 1;
+}
+
+// ||a||^2 partials and a count of non-finite entries of a and b (b may be null).
+__global__ __launch_bounds__(kThreads) void k_norm_finite(int64_t n, int32_t nwg, const double *__restrict__ a,
+                                                          const double *__restrict__ b, double *__restrict__ part_sq,
+                                                          double *__restrict__ part_bad) {
+    __shared__ double lds[4];
+    const int64_t per = (n + nwg - 1) / nwg;
+    const int64_t d0 = (int64_t)blockIdx.x * per, d1 = min(n, d0 + per);
+    double acc = 0.0, bad = 0.0;
+    for (int64_t d = d0 + threadIdx.x; d < d1; d += kThreads) {
+        const double v = a[d];
+        if (!isfinite(v)) bad += 1.0;
+        acc = fma(v, v, acc);
+        if (b && !isfinite(b[d])) bad += 1.0;
+    }
+    const double s = block_sum(acc, lds);
+    const double c = block_sum(bad, lds);
+    if (threadIdx.x == 0) {
+        part_sq[blockIdx.x] = s;
+        part_bad[blockIdx.x] = c;
+    }
+}
+
+// st->aux = sum of n partials of part_a; st->nonfinite = (sum of part_b > 0) when part_b given.
+__global__ __launch_bounds__(kThreads) void k_reduce_aux(const double *__restrict__ part_a,
+                                                         const double *__restrict__ part_b, int n, State *st) {
+    __shared__ double lds[4];
+    const double s = reduce_parts(part_a, n, lds);
+    const double c = part_b ? reduce_parts(part_b, n, lds) : 0.0;
+    if (threadIdx.x == 0) {
+        st->aux = s;
+        st->nonfinite = c > 0.0 ? 1 : 0;
+    }
+}
+
+template <int G>
+hipError_t spmv_p_g(const dpcg_ctx *c, Workspace &w) {
+    SpmvShape sh{c->nb, c->spmv.steps, c->spmv.nwg};
+    hipLaunchKernelGGL(k_spmv_p<G>, dim3(c->spmv.nwg), dim3(kThreads), 0, c->stream, sh, c->brow_ptr, c->bcol,
+                       c->bval, c->nnzb, w.z, w.p[0], w.p[1], w.q, w.part_c, c->vec_nwg, w.part_a, w.st);
+    return hipGetLastError();
+}
+
+template <int G, int MODE>
+hipError_t spmv_g(const dpcg_ctx *c, const double *x, const double *f, double *y, double *part) {
+    SpmvShape sh{c->nb, c->spmv.steps, c->spmv.nwg};
+    hipLaunchKernelGGL((k_spmv<G, MODE>), dim3(c->spmv.nwg), dim3(kThreads), 0, c->stream, sh, c->brow_ptr,
+                       c->bcol, c->bval, c->nnzb, x, f, y, part);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_spmv_p(const dpcg_ctx *c, Workspace &w) {
+    switch (c->spmv.group) {
+        case 4: return spmv_p_g<4>(c, w);
+        case 8: return spmv_p_g<8>(c, w);
+        case 32: return spmv_p_g<32>(c, w);
+        default: return spmv_p_g<16>(c, w);
+    }
+}
+
+hipError_t launch_spmv_plain(const dpcg_ctx *c, const double *x, double *y) {
+    switch (c->spmv.group) {
+        case 4: return spmv_g<4, 0>(c, x, nullptr, y, nullptr);
+        case 8: return spmv_g<8, 0>(c, x, nullptr, y, nullptr);
+        case 32: return spmv_g<32, 0>(c, x, nullptr, y, nullptr);
+        default: return spmv_g<16, 0>(c, x, nullptr, y, nullptr);
+    }
+}
+
+hipError_t launch_spmv_residual(const dpcg_ctx *c, const double *x, const double *f, double *r, double *part,
+                                Workspace &w, int check) {
+    (void)w;
+    (void)check;
+    switch (c->spmv.group) {
+        case 4: return spmv_g<4, 1>(c, x, f, r, part);
+        case 8: return spmv_g<8, 1>(c, x, f, r, part);
+        case 32: return spmv_g<32, 1>(c, x, f, r, part);
+        default: return spmv_g<16, 1>(c, x, f, r, part);
+    }
+}
+
+hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w) {
+    hipLaunchKernelGGL(k_update_bj, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles,
+                       c->bj_nwg, c->bj_wg_start, u, w.r, w.y, w.q, w.p[0], w.p[1], c->minv, c->bj_rowoff,
+                       c->bj_meta, w.part_a, c->spmv.nwg, w.part_b, w.st);
+    return hipGetLastError();
+}
+
+hipError_t launch_bj(const dpcg_ctx *c, const double *r, double *y, Workspace *w) {
+    hipLaunchKernelGGL(k_bj, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles, c->bj_nwg,
+                       c->bj_wg_start, r, y, c->minv, c->bj_rowoff, c->bj_meta, w ? w->st : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, double *g, Workspace *w,
+                           int check, int n_parts, int iter_offset, int max_iter, int record) {
+    const int grid = c->k > 0 ? c->k : 1;
+    hipLaunchKernelGGL(k_restrict, dim3(grid), dim3(kThreads), 0, c->stream, c->k, c->zt_ptr, c->zt_idx,
+                       c->zt_val, c->kzt_ptr, c->kzt_idx, c->kzt_val, a, b, g, w ? w->st : nullptr,
+                       w ? w->part_b : nullptr, check ? n_parts : 0, iter_offset, max_iter,
+                       (w && record) ? w->hist : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Workspace *w) {
+    if (c->k == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coarse, dim3((c->k + 3) / 4), dim3(kThreads), 0, c->stream, c->k, c->einv, g, delta,
+                       w ? w->st : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong(const dpcg_ctx *c, const double *base, const double *delta, double *out,
+                          Workspace *w, const double *rdot, int advance) {
+    hipLaunchKernelGGL(k_prolong, dim3(c->vec_nwg), dim3(kThreads), 0, c->stream, c->n, c->vec_nwg, c->z_ptr,
+                       c->z_col, c->z_val, delta, base, out, rdot, w ? w->part_c : nullptr,
+                       w ? w->st : nullptr, advance);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_finite_norm(const dpcg_ctx *c, const double *a, const double *b, Workspace &w) {
+    hipLaunchKernelGGL(k_norm_finite, dim3(c->vec_nwg), dim3(kThreads), 0, c->stream, c->n, c->vec_nwg, a, b,
+                       w.part_a, w.part_b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_reduce_aux, dim3(1), dim3(kThreads), 0, c->stream, w.part_a, w.part_b, c->vec_nwg,
+                       w.st);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_aux(const dpcg_ctx *c, Workspace &w, int n_parts) {
+    hipLaunchKernelGGL(k_reduce_aux, dim3(1), dim3(kThreads), 0, c->stream, w.part_a, nullptr, n_parts, w.st);
+    return hipGetLastError();
+}
+
+}  // namespace dpcg

@@ -1,0 +1,285 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle.
+
+Tolerances:
+* sparse products with the same terms summed in another order: 1e-13 relative to
+  sum_j |K_ij x_j| per entry;
+* block-Jacobi by explicit inverse vs Cholesky solves: 1e-9 relative (nodal blocks
+  have condition numbers up to about 1e6);
+* coarse solve by explicit E^{-1} vs Cholesky solve: 1e-6 relative (kappa(E) up to
+  about 3e8);
+* whole solve at tol 1e-8: solution within 1e-6 relative, iteration counts equal
+  below 50 iterations and within 2% above.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2111_09294_amd as D  # noqa: E402
+from fixtures.xfem import build_problem  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pair(problems):
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            p = problems(name)
+            say(f"[setup] {name} n={p.n} k={p.k}")
+            cache[name] = (p, O.Oracle.from_problem(p), D.Solver.from_problem(p, DEV))
+        return cache[name]
+
+    yield get
+    for _, _, s in cache.values():
+        s.close()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, np.float64), device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def iters_close(a, b):
+    if max(a, b) < 50:
+        return a == b
+    return abs(a - b) <= 0.02 * max(a, b)
+
+
+SMALL = ["plain6", "edge4", "penny12", "edge10"]
+
+
+# ------------------------------------------------------------------ single steps
+@pytest.mark.parametrize("name", SMALL + ["penny40"])
+def test_spmv(pair, name):
+    p, o, s = pair(name)
+    rng = np.random.default_rng(1)
+    for x in (rng.standard_normal(p.n), p.f):
+        y = host(s.spmv(dev(x)))
+        ref = o.spmv(x)
+        K = p.K_scipy()
+        scale = abs(K) @ np.abs(x) + 1e-300
+        assert np.all(np.abs(y - ref) <= 1e-13 * scale)
+
+
+@pytest.mark.parametrize("name", SMALL + ["penny40"])
+def test_block_jacobi(pair, name):
+    p, o, s = pair(name)
+    r = np.random.default_rng(2).standard_normal(p.n)
+    y = host(s.bj_apply(dev(r)))
+    ref = o.bj_apply(r)
+    assert np.linalg.norm(y - ref) <= 1e-9 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("name", SMALL + ["penny40"])
+def test_restrict_coarse_prolong(pair, name):
+    p, o, s = pair(name)
+    rng = np.random.default_rng(3)
+    a, b = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    g = host(s.restrict(dev(a), dev(b)))
+    gref = o.zt_times(a) - o.zt_times(o.spmv(b))
+    scale = np.abs(o.zt_times(a)).max() + np.abs(o.zt_times(o.spmv(b))).max()
+    assert np.abs(g - gref).max() <= 1e-12 * scale
+    g0 = host(s.restrict(dev(a)))
+    assert np.abs(g0 - o.zt_times(a)).max() <= 1e-13 * np.abs(o.zt_times(a)).max()
+    d = host(s.coarse_apply(dev(gref)))
+    dref = o.coarse_solve(gref)
+    assert np.linalg.norm(d - dref) <= 1e-6 * np.linalg.norm(dref)
+    out = host(s.prolong(dev(dref), dev(a)))
+    assert np.allclose(out, o.x_plus_z_times(a, dref), rtol=1e-13, atol=1e-13 * np.abs(out).max())
+    out0 = host(s.prolong(dev(dref)))
+    assert np.allclose(out0, o.x_plus_z_times(None, dref), rtol=1e-13, atol=1e-13 * np.abs(out0).max())
+
+
+@pytest.mark.parametrize("name", SMALL + ["penny40"])
+def test_adef2_preconditioner(pair, name):
+    p, o, s = pair(name)
+    r = np.random.default_rng(4).standard_normal(p.n)
+    z = host(s.precond(dev(r)))
+    zref, _ = o.adef2_apply(r)
+    assert np.linalg.norm(z - zref) <= 1e-6 * np.linalg.norm(zref)
+
+
+# ------------------------------------------------------------------ whole solves
+@pytest.mark.parametrize("name", SMALL + ["penny40"])
+def test_solve_matches_oracle(pair, name):
+    p, o, s = pair(name)
+    say(f"[solve] {name}")
+    ref = o.solve(p.f, tol=1e-8, history=True)
+    u, info = s.solve(dev(p.f), tol=1e-8, record_history=True)
+    u = host(u)
+    say(f"[solve] {name}: gpu {info['iterations']} it, oracle {ref['iterations']} it, "
+        f"setup {info['setup_ms']:.1f} ms solve {info['solve_ms']:.2f} ms")
+    assert ref["status"] == O.OK and info["status"] == D.abi.OK
+    assert iters_close(info["iterations"], ref["iterations"])
+    assert np.linalg.norm(u - ref["u"]) <= 1e-6 * np.linalg.norm(ref["u"])
+    assert info["rel_res_recursive"] <= 1e-8 and info["rel_res_true"] <= 1.5e-8
+    h = s.history()
+    assert len(h) == info["iterations"] + 1
+    m = min(len(h), len(ref["history"]))
+    assert np.allclose(h[:m], ref["history"][:m], rtol=1e-6, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["penny12", "penny40"])
+def test_deterministic_and_adjoint(pair, name):
+    """Two solves are bitwise identical; the adjoint solve runs the same operator."""
+    p, o, s = pair(name)
+    f = dev(p.f)
+    u1, i1 = s.solve(f)
+    u2, i2 = s.solve(f)
+    assert torch.equal(u1, u2) and i1["iterations"] == i2["iterations"]
+    lam, ia = s.solve_adjoint(f)
+    assert torch.equal(lam, u1) and ia["iterations"] == i1["iterations"]
+    # a forward solve is undisturbed by an adjoint solve in between
+    g = dev(np.random.default_rng(9).standard_normal(p.n))
+    s.solve_adjoint(g)
+    u3, _ = s.solve(f)
+    assert torch.equal(u3, u1)
+
+
+def test_random_rhs_and_warm_start(pair):
+    p, o, s = pair("penny12")
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal(p.n)
+    ref = o.solve(f, tol=1e-8)
+    u, info = s.solve(dev(f), tol=1e-8)
+    assert iters_close(info["iterations"], ref["iterations"])
+    assert np.linalg.norm(host(u) - ref["u"]) <= 1e-6 * np.linalg.norm(ref["u"])
+    # warm start from a random u_{-1}
+    u_m1 = rng.standard_normal(p.n)
+    ref = o.solve(f, tol=1e-8, u0=u_m1)
+    u, info = s.solve(dev(f), tol=1e-8, initial_guess=dev(u_m1))
+    assert iters_close(info["iterations"], ref["iterations"])
+    assert np.linalg.norm(host(u) - ref["u"]) <= 1e-6 * np.linalg.norm(ref["u"])
+    # warm start from the solution: 0 iterations
+    tight, _ = s.solve(dev(f), tol=1e-12)
+    u, info = s.solve(dev(f), tol=1e-8, initial_guess=tight)
+    assert info["iterations"] == 0 and info["status"] == D.abi.OK
+
+
+def test_iteration_cap_and_special_rhs(pair):
+    p, o, s = pair("edge10")
+    for cap in (0, 1, 7):
+        ref = o.solve(p.f, tol=1e-8, max_iter=cap)
+        u, info = s.solve(dev(p.f), tol=1e-8, max_iter=cap, check_every=3)
+        assert ref["status"] == O.NOT_CONVERGED and info["status"] == D.abi.NOT_CONVERGED
+        assert info["iterations"] == ref["iterations"] == cap
+        assert np.linalg.norm(host(u) - ref["u"]) <= 1e-9 * np.linalg.norm(ref["u"])
+    u, info = s.solve(torch.zeros(p.n, dtype=torch.float64, device=DEV))
+    assert info["status"] == D.abi.OK and info["iterations"] == 0 and not torch.any(u)
+    f = p.f.copy()
+    f[5] = np.inf
+    with pytest.raises(D.DpcgError) as e:
+        s.solve(dev(f))
+    assert e.value.code == D.abi.ENONFINITE
+    with pytest.raises(D.DpcgError) as e:
+        s.solve(dev(p.f), tol=0.0)
+    assert e.value.code == D.abi.EINVAL
+    # f in K range(Z): the start already solves it
+    c = np.random.default_rng(1).standard_normal(p.k)
+    us = p.Z_scipy() @ c
+    u, info = s.solve(dev(p.K_scipy() @ us))
+    assert info["iterations"] <= 1
+    assert np.linalg.norm(host(u) - us) <= 1e-7 * np.linalg.norm(us)
+
+
+def test_check_every_does_not_change_result(pair):
+    p, o, s = pair("penny12")
+    f = dev(p.f)
+    a, ia = s.solve(f, check_every=1)
+    b, ib = s.solve(f, check_every=64)
+    assert torch.equal(a, b) and ia["iterations"] == ib["iterations"]
+
+
+# ------------------------------------------------------------------ special operators
+def _solver_from_dense(K, Z, bp):
+    import scipy.sparse as sp
+    A = sp.csr_matrix(K)
+    A.sort_indices()
+    n = A.shape[0]
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dt)  # noqa: E731
+    if Z is None:
+        return D.Solver(n, t(A.indptr, torch.int64), t(A.indices, torch.int32), t(A.data, torch.float64), 0,
+                        None, None, None, t(bp, torch.int32))
+    Zs = sp.csr_matrix(Z)
+    Zs.sort_indices()
+    return D.Solver(n, t(A.indptr, torch.int64), t(A.indices, torch.int32), t(A.data, torch.float64),
+                    Zs.shape[1], t(Zs.indptr, torch.int64), t(Zs.indices, torch.int32),
+                    t(Zs.data, torch.float64), t(bp, torch.int32))
+
+
+def test_no_deflation_and_point_jacobi(problems):
+    p = problems("plain6")
+    K = p.K_scipy()
+    for bp in (np.arange(p.n + 1), p.block_ptr):
+        o = O.Oracle(p.n, p.k_rowptr, p.k_col, p.k_val, 0, np.zeros(p.n + 1, np.int64), np.zeros(0, np.int32),
+                     np.zeros(0), bp)
+        ref = o.solve(p.f)
+        with _solver_from_dense(K, None, bp) as s:
+            u, info = s.solve(dev(p.f))
+        assert iters_close(info["iterations"], ref["iterations"])
+        assert np.linalg.norm(host(u) - ref["u"]) <= 1e-6 * np.linalg.norm(ref["u"])
+
+
+def test_one_block_is_direct():
+    p = build_problem("cube1", 1, 1, crack=None)
+    K = p.K_scipy().toarray()
+    with _solver_from_dense(K, p.Z_scipy(), np.array([0, p.n])) as s:
+        u, info = s.solve(dev(p.f), tol=1e-12)
+    assert info["iterations"] == 1
+    assert np.allclose(host(u), np.linalg.solve(K, p.f), rtol=1e-12)
+
+
+def test_single_triplet_system():
+    K = np.array([[4.0, 1.0, 0.5], [1.0, 3.0, 0.2], [0.5, 0.2, 2.0]])
+    f = np.array([1.0, -2.0, 0.5])
+    with _solver_from_dense(K, None, np.array([0, 1, 2, 3])) as s:
+        u, info = s.solve(dev(f), tol=1e-14)
+    assert info["status"] == D.abi.OK
+    assert np.allclose(host(u), np.linalg.solve(K, f), rtol=1e-12)
+
+
+# ------------------------------------------------------------------ setup errors
+def test_setup_errors(problems):
+    p = problems("edge4")
+    K = p.K_scipy().tolil()
+    Z = p.Z_scipy().toarray()
+    bp = p.block_ptr
+    with pytest.raises(D.DpcgError) as e:
+        _solver_from_dense(K.tocsr(), np.concatenate([Z, Z[:, :1]], 1), bp)
+    assert e.value.code == D.abi.ECOARSE_NOT_SPD
+    K2 = K.copy()
+    s0 = bp[3]
+    K2[s0, s0] = -1.0
+    with pytest.raises(D.DpcgError) as e:
+        _solver_from_dense(K2.tocsr(), Z, bp)
+    assert e.value.code == D.abi.EBLOCK_NOT_SPD and e.value.info.bad_index == 3
+    K3 = K.copy()
+    K3[0, 5] = K3[0, 5] + 1.0
+    with pytest.raises(D.DpcgError) as e:
+        _solver_from_dense(K3.tocsr(), Z, bp)
+    assert e.value.code == D.abi.ENOTSYM
+    bad_bp = np.array([0, 19] + list(range(22, p.n + 1, 3)))
+    with pytest.raises(D.DpcgError) as e:
+        _solver_from_dense(K.tocsr(), Z, bad_bp)
+    assert e.value.code == D.abi.EINVAL
+    with pytest.raises(D.DpcgError) as e:
+        _solver_from_dense(K.tocsr()[:-1, :-1], Z[:-1], np.arange(p.n))
+    assert e.value.code == D.abi.EINVAL
