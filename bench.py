@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""Benchmark: DoF-solves per second of the deflated block-Jacobi CG on one MI355X.
+
+A step is one pass of the whole method over one synthetic cracked-body system:
+setup (block-Jacobi inverses, K Z, E = Z^T K Z and E^-1, device layout) followed by
+one solve of K u = f to relative residual 1e-8 and the release of the handle.  The
+inputs (K, Z, blocks, f as device arrays) are resident in HBM before timing starts.
+
+Prints one JSON line with the throughput, the SpMV kernel's HBM roofline fraction
+(algorithmic bytes / average launch duration measured with HIP events on the
+library's stream during the timed steps) and the CPU oracle timed on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "DoF-solves/sec to rel. residual 1e-8 + SpMV HBM GB/s fraction; FP64 vs mixed/batched"
+WORKLOADS = {
+    "penny40": "40^3 hex8 unit cube, curved penny crack (R=0.25, z=0.5+0.3 rho^2), Heaviside + branch "
+               "enrichment within r_e=0.05, 4^3 subdomains, clamped bottom, unit top traction, FP64, tol 1e-8",
+    "edge10": "10^3 hex8 unit cube, planar edge crack x=0.5 z<0.45, Heaviside + branch enrichment within "
+              "r_e=0.15, 2^3 subdomains, clamped bottom, unit top traction, FP64, tol 1e-8",
+    "penny80": "80^3 hex8 unit cube, curved penny crack, r_e=0.05, 8^3 subdomains, FP64, tol 1e-8",
+}
+
+
+def spmv_bytes(nnzb, n):
+    """Algorithmic bytes of one q = K p launch with p = z + beta p_prev formed on the
+    fly: each 3x3 block (72 B values + 4 B column index) once, the block-row pointer,
+    z and p_prev read once, q and p written once."""
+    return nnzb * 76 + 4 * (n // 3 + 1) + 4 * 8 * n
+
+
+def cpu_baseline(p, budget_s=12.0):
+    """The oracle (plain C FP64, OpenMP row loops) on the same workload, full steps."""
+    import oracle
+
+    t0 = time.perf_counter()
+    reps = 0
+    its = None
+    while True:
+        o = oracle.Oracle.from_problem(p)
+        r = o.solve(p.f, tol=1e-8)
+        del o
+        its = r["iterations"]
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s or reps >= 20:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": p.n * reps / dt, "unit": "DoF-solves/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{reps} full steps (setup + solve to 1e-8, {its} iterations) of the same workload, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="penny40", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="also run N plain 512 MiB device copies (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this method is built and measured on a single MI355X "
+              "(run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2111_09294_amd as dpcg
+    from fixtures import load
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    p = load(args.workload)
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    K = (t(p.k_rowptr, torch.int64), t(p.k_col, torch.int32), t(p.k_val, torch.float64))
+    Z = (t(p.z_rowptr, torch.int64), t(p.z_col, torch.int32), t(p.z_val, torch.float64))
+    bp = t(p.block_ptr, torch.int32)
+    f = t(p.f, torch.float64)
+    u = torch.empty_like(f)
+    stream = torch.cuda.current_stream()
+
+    def step(timing):
+        s = dpcg.Solver(p.n, *K, p.k, *Z, bp, stream=stream)
+        if timing:
+            s.set_timing(True)
+        _, info = s.solve(f, u, tol=1e-8)
+        tm = s.timing() if timing else None
+        st = s.stats()
+        s.close()
+        return info, tm, st
+
+    if args.calibrate_copy:
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(args.calibrate_copy):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, spmv_ms, spmv_n = [], 0.0, 0
+    stats = None
+    for _ in range(args.steps):
+        info, tm, stats = step(True)
+        infos.append(info)
+        spmv_ms += tm["spmv_ms"]
+        spmv_n += tm["spmv_launches"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for info in infos:
+        if info["status"] != 0 or info["rel_res_true"] > 1.5e-8:
+            print(f"solve failed: {info}", file=sys.stderr)
+            return 1
+    ms_step = dt * 1e3 / args.steps
+    solve_ms = float(np.mean([i["solve_ms"] for i in infos]))
+    setup_ms = float(np.mean([i["setup_ms"] for i in infos]))
+    per_launch_s = spmv_ms / 1e3 / max(spmv_n, 1)
+    nbytes = spmv_bytes(stats["nnzb"], p.n)
+    achieved = nbytes / per_launch_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": p.n * args.steps / dt,
+        "unit": "DoF-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "n_dofs": p.n,
+                   "n_std": p.meta["n_std"], "n_enr": p.meta["n_enr"], "k": p.k, "nnzb": stats["nnzb"],
+                   "nblocks": p.nblocks, "parallelism": "single GPU"},
+        "iterations": infos[-1]["iterations"],
+        "setup_ms": setup_ms,
+        "solve_ms": solve_ms,
+        "solve_only_dof_solves_per_s": p.n / (solve_ms / 1e3),
+        "rel_res_true": infos[-1]["rel_res_true"],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_spmv_p", "bytes_per_launch": nbytes, "launches": spmv_n,
+                     "avg_launch_us": per_launch_s * 1e6},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -72,6 +72,11 @@ typedef struct {
     int64_t device_bytes;      /* device memory held by the handle                      */
 } dpcg_stats;
 
+typedef struct {
+    int64_t spmv_launches;     /* launches of the iteration's SpMV kernel timed so far  */
+    double spmv_ms;            /* their summed durations (HIP events on the stream)     */
+} dpcg_timing;
+
 /* Fills *opt with the defaults above. */
 void dpcg_default_options(dpcg_options *opt);
 
@@ -139,6 +144,14 @@ int dpcg_get_stats(dpcg_handle h, dpcg_stats *out);
  * with record_history; copies up to cap values into host memory out and returns
  * how many were written (negative status on error). */
 int64_t dpcg_get_history(dpcg_handle h, double *out, int64_t cap);
+
+/* Kernel timing for roofline measurements: with on = 1 every solve brackets each
+ * launch of the iteration's SpMV kernel (K p, the dominant kernel) with a pair of
+ * HIP events on the handle's stream and accumulates the durations; on = 0 stops
+ * timing.  Turning it on resets the counters.  The events add a few microseconds
+ * of stream work per iteration. */
+int dpcg_set_timing(dpcg_handle h, int32_t on);
+int dpcg_get_timing(dpcg_handle h, dpcg_timing *out);
 
 /* ---- single steps of the iteration, each the kernel the solve runs ---- */
 

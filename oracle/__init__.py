@@ -41,8 +41,15 @@ def lib():
         L.oracle_x_plus_z_times.argtypes = [P, P, P, P]
         L.oracle_k.argtypes = [P]
         L.oracle_k.restype = C.c_int32
+        L.oracle_threads.argtypes = []
+        L.oracle_threads.restype = C.c_int32
         _lib = L
     return _lib
+
+
+def threads():
+    """OpenMP threads the oracle's parallel loops run on."""
+    return int(lib().oracle_threads())
 
 
 def _p(a):

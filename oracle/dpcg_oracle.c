@@ -33,6 +33,11 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#else
+static int omp_get_num_threads(void) { return 1; }
+#endif
 
 #define OR_OK 0
 #define OR_NOT_CONVERGED 1
@@ -413,6 +418,17 @@ void oracle_coarse_matrix(const oracle_t *o, double *out) {
 }
 
 int32_t oracle_k(const oracle_t *o) { return o->k; }
+
+/* Threads the OpenMP loops use. */
+int32_t oracle_threads(void) {
+    int32_t t = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        t = (int32_t)omp_get_num_threads();
+    }
+    return t;
+}
 
 /* b = Z^T x (k-vector). */
 void oracle_zt_times(const oracle_t *o, const double *x, double *b) { zt_times(o, x, b); }

@@ -38,6 +38,13 @@ class Stats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Timing(C.Structure):
+    _fields_ = [("spmv_launches", C.c_int64), ("spmv_ms", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 P = C.c_void_p
@@ -52,6 +59,8 @@ SIGNATURES = {
     "dpcg_status_string": (C.c_char_p, [C.c_int]),
     "dpcg_get_stats": (C.c_int, [P, C.POINTER(Stats)]),
     "dpcg_get_history": (C.c_int64, [P, P, C.c_int64]),
+    "dpcg_set_timing": (C.c_int, [P, C.c_int32]),
+    "dpcg_get_timing": (C.c_int, [P, C.POINTER(Timing)]),
     "dpcg_spmv": (C.c_int, [P, P, P]),
     "dpcg_bj_apply": (C.c_int, [P, P, P]),
     "dpcg_restrict": (C.c_int, [P, P, P, P]),
@@ -228,6 +237,18 @@ class Solver:
         if st != OK:
             raise DpcgError(st, "dpcg_get_stats")
         return s.as_dict()
+
+    def set_timing(self, on=True):
+        st = lib().dpcg_set_timing(self.handle, int(bool(on)))
+        if st != OK:
+            raise DpcgError(st, "dpcg_set_timing")
+
+    def timing(self):
+        t = Timing()
+        st = lib().dpcg_get_timing(self.handle, C.byref(t))
+        if st != OK:
+            raise DpcgError(st, "dpcg_get_timing")
+        return t.as_dict()
 
     # ------------------------------------------------------------------ single steps
     def _call(self, name, *args):

@@ -550,6 +550,7 @@ int setup_impl(dpcg_ctx *c, int64_t n, const int64_t *k_rowptr, const int32_t *k
 void release(dpcg_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
     for (void *p : c->allocations) (void)hipFree(p);
     for (auto &w : c->ws) {
         if (w.snap) (void)hipHostFree(w.snap);
@@ -609,8 +610,43 @@ int enqueue_start(dpcg_ctx *c, Workspace &w, const double *f, double *u, bool gu
     return DPCG_OK;
 }
 
+int next_event_pair(dpcg_ctx *c, hipEvent_t *a, hipEvent_t *b) {
+    if ((size_t)c->events_used + 2 > c->events.size()) {
+        for (int i = 0; i < 64; ++i) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            c->events.push_back(e);
+        }
+    }
+    *a = c->events[c->events_used];
+    *b = c->events[c->events_used + 1];
+    c->events_used += 2;
+    return DPCG_OK;
+}
+
+// Adds the durations of the first `real` event pairs of this solve (the SpMV launches of
+// iterations that did work; later ones returned at once) and resets the pool.
+int collect_events(dpcg_ctx *c, int32_t real) {
+    for (int32_t i = 0; i + 1 < c->events_used && i / 2 < real; i += 2) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, c->events[i], c->events[i + 1]));
+        c->spmv_ms += ms;
+        c->spmv_launches += 1;
+    }
+    c->events_used = 0;
+    return DPCG_OK;
+}
+
 int enqueue_iteration(dpcg_ctx *c, Workspace &w, double *u, int max_iter, int record) {
-    LAUNCH(launch_spmv_p(c, w));
+    if (c->timing) {
+        hipEvent_t a, b;
+        TRY(next_event_pair(c, &a, &b));
+        HIP_TRY(hipEventRecord(a, c->stream));
+        LAUNCH(launch_spmv_p(c, w));
+        HIP_TRY(hipEventRecord(b, c->stream));
+    } else {
+        LAUNCH(launch_spmv_p(c, w));
+    }
     LAUNCH(launch_update_bj(c, u, w));
     LAUNCH(launch_restrict(c, w.r, w.y, w.g, &w, 1, c->bj_nwg, 1, max_iter, record));
     LAUNCH(launch_coarse(c, w.g, w.delta, &w));
@@ -630,6 +666,7 @@ int solve_impl(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol
     const int record = opt.record_history != 0;
     if (record) TRY(ensure_history(c, w, (int64_t)opt.max_iter + 1));
     w.hist_len = 0;
+    c->events_used = 0;
     // ||f||^2 and the finiteness of the inputs
     LAUNCH(launch_check_finite_norm(c, f, guess ? u : nullptr, w));
     State s0;
@@ -669,6 +706,7 @@ int solve_impl(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol
         case kBreakdown: status = DPCG_EBREAKDOWN; bad = st.bad; break;
         default: status = DPCG_NOT_CONVERGED; st.iters_done = enq; break;  // max_iter == 0 after a failed check
     }
+    if (c->timing) TRY(collect_events(c, st.iters_done));
     // true residual ||f - K u|| / ||f||
     LAUNCH(launch_spmv_residual(c, u, f, w.tmp, w.part_a, w, 0));
     LAUNCH(launch_reduce_aux(c, w, c->spmv.nwg));
@@ -775,6 +813,24 @@ int64_t dpcg_get_history(dpcg_handle h, double *out, int64_t cap) {
     const int64_t m = std::min<int64_t>(cap, w.hist_len);
     if (m > 0) std::memcpy(out, w.host_hist.data(), sizeof(double) * m);
     return m;
+}
+
+int dpcg_set_timing(dpcg_handle h, int32_t on) {
+    if (!h) return DPCG_EINVAL;
+    h->timing = on != 0;
+    h->events_used = 0;
+    if (h->timing) {
+        h->spmv_launches = 0;
+        h->spmv_ms = 0.0;
+    }
+    return DPCG_OK;
+}
+
+int dpcg_get_timing(dpcg_handle h, dpcg_timing *out) {
+    if (!h || !out) return DPCG_EINVAL;
+    out->spmv_launches = h->spmv_launches;
+    out->spmv_ms = h->spmv_ms;
+    return DPCG_OK;
 }
 
 #define SYNC_RET(expr)                                               \

@@ -91,6 +91,12 @@ struct dpcg_ctx {
     dpcg::Workspace ws[2];     // [0] forward solves, [1] adjoint solves
     std::vector<void *> allocations;
     double setup_ms = 0.0;
+    // optional event timing of the SpMV kernel
+    bool timing = false;
+    std::vector<hipEvent_t> events;   // pairs (start, stop), reused per solve
+    int32_t events_used = 0;
+    int64_t spmv_launches = 0;
+    double spmv_ms = 0.0;
 };
 
 namespace dpcg {
