@@ -1,16 +1,12 @@
-// Host side of the dpcg C ABI: input validation, the one-off factorisations of
-// setup (block-Jacobi inverses, K Z, E = Z^T K Z and E^-1), device upload, and the
-// solve driver that enqueues the iteration kernels and polls the device flag.
+// Host side of the dpcg C ABI: argument checks, handle and workspace management, launch
+// shapes, and the solve driver that enqueues the iteration kernels and polls the device
+// flag.  The setup factorisations run on the GPU (setup.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
-#include <cfloat>
 #include <chrono>
 #include <cmath>
 #include <cstring>
-#include <functional>
-#include <thread>
 #include <vector>
 
 #include "dpcg_internal.h"
@@ -23,290 +19,17 @@ double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// Runs fn(begin, end) over [0, n) split in contiguous chunks across host threads.
-void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)> &fn, int64_t min_chunk = 1024) {
-    int nt = (int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency()));
-    if (n < 2 * min_chunk) nt = 1;
-    nt = (int)std::min<int64_t>(nt, std::max<int64_t>(1, n / min_chunk));
-    if (nt <= 1) {
-        fn(0, n);
-        return;
-    }
-    std::vector<std::thread> th;
-    for (int t = 0; t < nt; ++t) {
-        const int64_t b = n * t / nt, e = n * (t + 1) / nt;
-        th.emplace_back([=, &fn] { fn(b, e); });
-    }
-    for (auto &x : th) x.join();
-}
-
-struct Csr {
-    int64_t rows = 0, cols = 0;
-    std::vector<int64_t> ptr;
-    std::vector<int32_t> idx;
-    std::vector<double> val;
-};
-
 #define HIP_TRY(expr)                                   \
     do {                                                \
         hipError_t e_ = (expr);                         \
         if (e_ != hipSuccess) return DPCG_EHIP;         \
     } while (0)
 
-int download(const void *dev, void *host, size_t bytes, hipStream_t s) {
-    if (bytes == 0) return DPCG_OK;
-    if (!dev) return DPCG_EINVAL;
-    HIP_TRY(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, s));
-    return DPCG_OK;
-}
-
-// Structural checks of a CSR matrix: monotone row pointer, columns in range and
-// strictly increasing per row, finite values.
-bool valid_csr(const Csr &A) {
-    if (A.ptr.size() != (size_t)A.rows + 1 || A.ptr[0] != 0) return false;
-    for (int64_t i = 0; i < A.rows; ++i)
-        if (A.ptr[i + 1] < A.ptr[i]) return false;
-    if ((size_t)A.ptr[A.rows] != A.idx.size()) return false;
-    std::atomic<bool> ok{true};
-    parallel_for(A.rows, [&](int64_t b, int64_t e) {
-        for (int64_t i = b; i < e && ok; ++i) {
-            int64_t prev = -1;
-            for (int64_t p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
-                const int64_t c = A.idx[p];
-                if (c <= prev || c >= A.cols || !std::isfinite(A.val[p])) {
-                    ok = false;
-                    break;
-                }
-                prev = c;
-            }
-        }
-    });
-    return ok;
-}
-
-// |K_ij - K_ji| <= 1e-12 max|K| for every stored entry (a missing mirror counts as 0).
-bool symmetric(const Csr &K) {
-    double mx = 0.0;
-    for (double v : K.val) mx = std::max(mx, std::fabs(v));
-    const double tol = 1e-12 * mx;
-    std::atomic<bool> ok{true};
-    parallel_for(K.rows, [&](int64_t b, int64_t e) {
-        for (int64_t i = b; i < e && ok; ++i)
-            for (int64_t p = K.ptr[i]; p < K.ptr[i + 1]; ++p) {
-                const int64_t j = K.idx[p];
-                const int32_t *lo = K.idx.data() + K.ptr[j], *hi = K.idx.data() + K.ptr[j + 1];
-                const int32_t *f = std::lower_bound(lo, hi, (int32_t)i);
-                const double m = (f != hi && *f == i) ? K.val[f - K.idx.data()] : 0.0;
-                if (std::fabs(K.val[p] - m) > tol) {
-                    ok = false;
-                    break;
-                }
-            }
-    });
-    return ok;
-}
-
-// In-place Cholesky of a dense row-major m x m matrix (lower triangle); the pivot
-// test: a pivot must exceed m * DBL_EPSILON times its own diagonal entry (not SPD to
-// working precision otherwise).
-bool chol_small(double *A, int m) {
-    for (int j = 0; j < m; ++j) {
-        double d = A[j * m + j];
-        const double fl = m * DBL_EPSILON * std::fabs(d);
-        for (int p = 0; p < j; ++p) d -= A[j * m + p] * A[j * m + p];
-        if (!(d > fl) || !std::isfinite(d)) return false;
-        const double l = std::sqrt(d);
-        A[j * m + j] = l;
-        for (int i = j + 1; i < m; ++i) {
-            double s = A[i * m + j];
-            for (int p = 0; p < j; ++p) s -= A[i * m + p] * A[j * m + p];
-            A[i * m + j] = s / l;
-        }
-    }
-    return true;
-}
-
-// inv = (L L^T)^{-1} from the lower factor L (m x m); inv is full and symmetric.
-void inverse_from_chol(const double *L, int m, double *inv) {
-    double Li[kMaxBlock * kMaxBlock];
-    for (int j = 0; j < m; ++j)
-        for (int i = 0; i < m; ++i) {
-            if (i < j) {
-                Li[i * m + j] = 0.0;
-                continue;
-            }
-            double s = (i == j) ? 1.0 : 0.0;
-            for (int p = j; p < i; ++p) s -= L[i * m + p] * Li[p * m + j];
-            Li[i * m + j] = s / L[i * m + i];
-        }
-    for (int i = 0; i < m; ++i)
-        for (int j = i; j < m; ++j) {
-            double s = 0.0;
-            for (int p = j; p < m; ++p) s += Li[p * m + i] * Li[p * m + j];
-            inv[i * m + j] = s;
-            inv[j * m + i] = s;
-        }
-}
-
-// Blocked right-looking Cholesky of the dense k x k matrix A (row-major, lower); the
-// pivot floor is taken against the original diagonal entry.
-bool chol_dense(std::vector<double> &A, int64_t k) {
-    const int64_t nbk = 64;
-    std::vector<double> diag0(k);
-    for (int64_t j = 0; j < k; ++j) diag0[j] = A[j * k + j];
-    for (int64_t j0 = 0; j0 < k; j0 += nbk) {
-        const int64_t j1 = std::min(k, j0 + nbk);
-        for (int64_t j = j0; j < j1; ++j) {
-            double d = A[j * k + j];
-            const double fl = (double)k * DBL_EPSILON * std::fabs(diag0[j]);
-            for (int64_t p = j0; p < j; ++p) d -= A[j * k + p] * A[j * k + p];
-            if (!(d > fl) || !std::isfinite(d)) return false;
-            const double l = std::sqrt(d);
-            A[j * k + j] = l;
-            for (int64_t i = j + 1; i < j1; ++i) {
-                double s = A[i * k + j];
-                for (int64_t p = j0; p < j; ++p) s -= A[i * k + p] * A[j * k + p];
-                A[i * k + j] = s / l;
-            }
-        }
-        // panel below the diagonal tile: L21 = A21 L11^{-T}
-        parallel_for(k - j1, [&](int64_t b, int64_t e) {
-            for (int64_t i = j1 + b; i < j1 + e; ++i)
-                for (int64_t j = j0; j < j1; ++j) {
-                    double s = A[i * k + j];
-                    for (int64_t p = j0; p < j; ++p) s -= A[i * k + p] * A[j * k + p];
-                    A[i * k + j] = s / A[j * k + j];
-                }
-        }, 16);
-        // trailing update of the lower triangle: A22 -= L21 L21^T
-        parallel_for(k - j1, [&](int64_t b, int64_t e) {
-            for (int64_t i = j1 + b; i < j1 + e; ++i) {
-                const double *li = &A[i * k + j0];
-                for (int64_t j = j1; j <= i; ++j) {
-                    const double *lj = &A[j * k + j0];
-                    double s = 0.0;
-                    for (int64_t p = 0; p < j1 - j0; ++p) s += li[p] * lj[p];
-                    A[i * k + j] -= s;
-                }
-            }
-        }, 16);
-    }
-    return true;
-}
-
-// E^{-1} = L^{-T} L^{-1} from the lower factor in A (dense, full symmetric output).
-void inverse_dense(const std::vector<double> &L, int64_t k, std::vector<double> &inv) {
-    // column j of L^{-1} stored as row j of Lt (Lt[j][i] = Linv[i][j], i >= j)
-    std::vector<double> Lt((size_t)k * k, 0.0);
-    parallel_for(k, [&](int64_t b, int64_t e) {
-        for (int64_t j = b; j < e; ++j) {
-            double *x = &Lt[j * k];
-            for (int64_t i = j; i < k; ++i) {
-                double s = (i == j) ? 1.0 : 0.0;
-                const double *li = &L[i * k];
-                for (int64_t p = j; p < i; ++p) s -= li[p] * x[p];
-                x[i] = s / li[i];
-            }
-        }
-    }, 8);
-    inv.assign((size_t)k * k, 0.0);
-    // inv[i][j] = sum_{p >= max(i,j)} Linv[p][i] Linv[p][j] = sum_p Lt[i][p] Lt[j][p]
-    parallel_for(k, [&](int64_t b, int64_t e) {
-        for (int64_t i = b; i < e; ++i)
-            for (int64_t j = i; j < k; ++j) {
-                const double *a = &Lt[i * k], *c = &Lt[j * k];
-                double s = 0.0;
-                for (int64_t p = j; p < k; ++p) s += a[p] * c[p];
-                inv[i * k + j] = s;
-            }
-    }, 8);
-    for (int64_t i = 0; i < k; ++i)
-        for (int64_t j = 0; j < i; ++j) inv[i * k + j] = inv[j * k + i];
-}
-
-Csr transpose(const Csr &A) {
-    Csr T;
-    T.rows = A.cols;
-    T.cols = A.rows;
-    T.ptr.assign(T.rows + 1, 0);
-    for (int32_t c : A.idx) T.ptr[c + 1]++;
-    for (int64_t i = 0; i < T.rows; ++i) T.ptr[i + 1] += T.ptr[i];
-    T.idx.resize(A.idx.size());
-    T.val.resize(A.val.size());
-    std::vector<int64_t> pos(T.ptr.begin(), T.ptr.end() - 1);
-    for (int64_t r = 0; r < A.rows; ++r)
-        for (int64_t p = A.ptr[r]; p < A.ptr[r + 1]; ++p) {
-            const int64_t q = pos[A.idx[p]]++;
-            T.idx[q] = (int32_t)r;
-            T.val[q] = A.val[p];
-        }
-    return T;
-}
-
-// K Z row by row (Gustavson) with a dense accumulator per host thread.
-Csr multiply(const Csr &K, const Csr &Z) {
-    const int64_t n = K.rows, k = Z.cols;
-    std::vector<std::vector<int32_t>> cols(n);
-    std::vector<std::vector<double>> vals(n);
-    parallel_for(n, [&](int64_t b, int64_t e) {
-        std::vector<double> acc(k, 0.0);
-        std::vector<char> mark(k, 0);
-        std::vector<int32_t> touched;
-        for (int64_t r = b; r < e; ++r) {
-            touched.clear();
-            for (int64_t p = K.ptr[r]; p < K.ptr[r + 1]; ++p) {
-                const int64_t c = K.idx[p];
-                const double kv = K.val[p];
-                for (int64_t q = Z.ptr[c]; q < Z.ptr[c + 1]; ++q) {
-                    const int32_t j = Z.idx[q];
-                    if (!mark[j]) {
-                        mark[j] = 1;
-                        touched.push_back(j);
-                    }
-                    acc[j] += kv * Z.val[q];
-                }
-            }
-            std::sort(touched.begin(), touched.end());
-            cols[r] = touched;
-            vals[r].resize(touched.size());
-            for (size_t t = 0; t < touched.size(); ++t) {
-                vals[r][t] = acc[touched[t]];
-                acc[touched[t]] = 0.0;
-                mark[touched[t]] = 0;
-            }
-        }
-    }, 256);
-    Csr P;
-    P.rows = n;
-    P.cols = k;
-    P.ptr.assign(n + 1, 0);
-    for (int64_t r = 0; r < n; ++r) P.ptr[r + 1] = P.ptr[r] + (int64_t)cols[r].size();
-    P.idx.resize(P.ptr[n]);
-    P.val.resize(P.ptr[n]);
-    for (int64_t r = 0; r < n; ++r) {
-        std::copy(cols[r].begin(), cols[r].end(), P.idx.begin() + P.ptr[r]);
-        std::copy(vals[r].begin(), vals[r].end(), P.val.begin() + P.ptr[r]);
-    }
-    return P;
-}
-
-template <class T>
-int upload(dpcg_ctx *c, T **dst, const T *src, size_t count) {
-    const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
-    void *p = nullptr;
-    HIP_TRY(hipMalloc(&p, bytes));
-    c->allocations.push_back(p);
-    c->device_bytes += (int64_t)bytes;
-    if (count) HIP_TRY(hipMemcpyAsync(p, src, count * sizeof(T), hipMemcpyHostToDevice, c->stream));
-    *dst = (T *)p;
-    return DPCG_OK;
-}
-
 template <class T>
 int alloc(dpcg_ctx *c, T **dst, size_t count) {
     const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
     void *p = nullptr;
-    HIP_TRY(hipMalloc(&p, bytes));
+    HIP_TRY(hipMallocAsync(&p, bytes, c->stream));
     HIP_TRY(hipMemsetAsync(p, 0, bytes, c->stream));
     c->allocations.push_back(p);
     c->device_bytes += (int64_t)bytes;
@@ -366,184 +89,15 @@ int setup_impl(dpcg_ctx *c, int64_t n, const int64_t *k_rowptr, const int32_t *k
         return DPCG_EINVAL;
     if (!k_rowptr || !k_col || !k_val || !block_ptr || (k > 0 && (!z_rowptr || !z_col || !z_val)))
         return DPCG_EINVAL;
-    hipStream_t s = c->stream;
     c->n = n;
     c->k = k;
     c->nb = (int32_t)(n / 3);
     c->nblocks = nblocks;
-    // ---- inputs to host ----
-    Csr K;
-    K.rows = K.cols = n;
-    K.ptr.resize(n + 1);
-    TRY(download(k_rowptr, K.ptr.data(), sizeof(int64_t) * (n + 1), s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (K.ptr[0] != 0 || K.ptr[n] < 0 || K.ptr[n] > (int64_t)INT32_MAX) return DPCG_EINVAL;
-    const int64_t nnz = K.ptr[n];
-    K.idx.resize(nnz);
-    K.val.resize(nnz);
-    TRY(download(k_col, K.idx.data(), sizeof(int32_t) * nnz, s));
-    TRY(download(k_val, K.val.data(), sizeof(double) * nnz, s));
-    Csr Z;
-    Z.rows = n;
-    Z.cols = k;
-    Z.ptr.assign(n + 1, 0);
-    if (k > 0) {
-        TRY(download(z_rowptr, Z.ptr.data(), sizeof(int64_t) * (n + 1), s));
-        HIP_TRY(hipStreamSynchronize(s));
-        if (Z.ptr[0] != 0 || Z.ptr[n] < 0 || Z.ptr[n] > (int64_t)INT32_MAX) return DPCG_EINVAL;
-        Z.idx.resize(Z.ptr[n]);
-        Z.val.resize(Z.ptr[n]);
-        TRY(download(z_col, Z.idx.data(), sizeof(int32_t) * Z.ptr[n], s));
-        TRY(download(z_val, Z.val.data(), sizeof(double) * Z.ptr[n], s));
-    }
-    std::vector<int32_t> bp(nblocks + 1);
-    TRY(download(block_ptr, bp.data(), sizeof(int32_t) * (nblocks + 1), s));
-    HIP_TRY(hipStreamSynchronize(s));
-    // ---- validation ----
-    if (!valid_csr(K) || !valid_csr(Z)) return DPCG_EINVAL;
-    if (bp[0] != 0 || bp[nblocks] != n) return DPCG_EINVAL;
-    for (int32_t b = 0; b < nblocks; ++b) {
-        const int32_t m = bp[b + 1] - bp[b];
-        if (m < 1 || m > kMaxBlock) {
-            *bad = b;
-            return DPCG_EINVAL;
-        }
-    }
-    if (!symmetric(K)) return DPCG_ENOTSYM;
-    c->nnz = nnz;
-    c->nnz_z = (int64_t)Z.idx.size();
-    // ---- block-CSR over DoF triplets ----
-    const int32_t nb = c->nb;
-    std::vector<int32_t> bptr(nb + 1, 0);
-    std::vector<std::vector<int32_t>> bcols(nb);
-    parallel_for(nb, [&](int64_t b0, int64_t b1) {
-        for (int64_t R = b0; R < b1; ++R) {
-            auto &v = bcols[R];
-            for (int i = 0; i < 3; ++i)
-                for (int64_t p = K.ptr[3 * R + i]; p < K.ptr[3 * R + i + 1]; ++p) v.push_back(K.idx[p] / 3);
-            std::sort(v.begin(), v.end());
-            v.erase(std::unique(v.begin(), v.end()), v.end());
-        }
-    });
-    for (int32_t R = 0; R < nb; ++R) bptr[R + 1] = bptr[R] + (int32_t)bcols[R].size();
-    const int64_t nnzb = bptr[nb];
-    c->nnzb = nnzb;
-    std::vector<int32_t> bcol(nnzb);
-    std::vector<double> bval(9 * (size_t)nnzb, 0.0);
-    parallel_for(nb, [&](int64_t b0, int64_t b1) {
-        for (int64_t R = b0; R < b1; ++R) {
-            const auto &v = bcols[R];
-            std::copy(v.begin(), v.end(), bcol.begin() + bptr[R]);
-            for (int i = 0; i < 3; ++i)
-                for (int64_t p = K.ptr[3 * R + i]; p < K.ptr[3 * R + i + 1]; ++p) {
-                    const int32_t C = K.idx[p] / 3, j = K.idx[p] % 3;
-                    const int64_t pos = bptr[R] + (std::lower_bound(v.begin(), v.end(), C) - v.begin());
-                    bval[(size_t)(3 * i + j) * nnzb + pos] = K.val[p];
-                }
-        }
-    });
-    bcols.clear();
-    bcols.shrink_to_fit();
-    // ---- block-Jacobi inverses ----
-    std::vector<int64_t> moff(nblocks + 1, 0);
-    for (int32_t b = 0; b < nblocks; ++b) moff[b + 1] = moff[b] + (int64_t)(bp[b + 1] - bp[b]) * (bp[b + 1] - bp[b]);
-    if (moff[nblocks] > (int64_t)INT32_MAX) return DPCG_EINVAL;
-    c->bj_values = moff[nblocks];
-    std::vector<double> minv(moff[nblocks]);
-    std::vector<int32_t> rowoff(n), meta(n);
-    std::atomic<int64_t> first_bad{INT64_MAX};
-    parallel_for(nblocks, [&](int64_t b0, int64_t b1) {
-        double A[kMaxBlock * kMaxBlock];
-        for (int64_t b = b0; b < b1; ++b) {
-            const int32_t s0 = bp[b], m = bp[b + 1] - bp[b];
-            std::fill(A, A + m * m, 0.0);
-            for (int i = 0; i < m; ++i)
-                for (int64_t p = K.ptr[s0 + i]; p < K.ptr[s0 + i + 1]; ++p) {
-                    const int32_t cc = K.idx[p];
-                    if (cc >= s0 && cc < s0 + m) A[i * m + (cc - s0)] = K.val[p];
-                }
-            if (!chol_small(A, m)) {
-                int64_t cur = first_bad.load();
-                while (b < cur && !first_bad.compare_exchange_weak(cur, b)) {
-                }
-                continue;
-            }
-            inverse_from_chol(A, m, &minv[moff[b]]);
-            for (int i = 0; i < m; ++i) {
-                rowoff[s0 + i] = (int32_t)(moff[b] + (int64_t)i * m);
-                meta[s0 + i] = (m << 8) | i;
-            }
-        }
-    }, 64);
-    if (first_bad.load() != INT64_MAX) {
-        *bad = first_bad.load();
-        return DPCG_EBLOCK_NOT_SPD;
-    }
-    // tiles of at most kThreads DoFs made of whole blocks
-    std::vector<int32_t> tiles{0};
-    for (int32_t b = 0; b < nblocks; ++b) {
-        if (bp[b + 1] - tiles.back() > kThreads) tiles.push_back(bp[b]);
-    }
-    tiles.push_back((int32_t)n);
-    c->bj_ntiles = (int32_t)tiles.size() - 1;
-    // ---- coarse operator ----
-    Csr Zt, KZt;
-    std::vector<double> einv;
-    if (k > 0) {
-        Csr KZ = multiply(K, Z);
-        c->nnz_kz = (int64_t)KZ.idx.size();
-        Zt = transpose(Z);
-        std::vector<double> E((size_t)k * k, 0.0);
-        parallel_for(k, [&](int64_t i0, int64_t i1) {
-            for (int64_t i = i0; i < i1; ++i) {
-                double *Ei = &E[i * k];
-                for (int64_t p = Zt.ptr[i]; p < Zt.ptr[i + 1]; ++p) {
-                    const int64_t r = Zt.idx[p];
-                    const double zr = Zt.val[p];
-                    for (int64_t q = KZ.ptr[r]; q < KZ.ptr[r + 1]; ++q) Ei[KZ.idx[q]] += zr * KZ.val[q];
-                }
-            }
-        }, 4);
-        for (int64_t i = 0; i < k; ++i)
-            for (int64_t j = i + 1; j < k; ++j) {
-                const double v = 0.5 * (E[i * k + j] + E[j * k + i]);
-                E[i * k + j] = v;
-                E[j * k + i] = v;
-            }
-        KZt = transpose(KZ);
-        if (!chol_dense(E, k)) return DPCG_ECOARSE_NOT_SPD;
-        inverse_dense(E, k, einv);
-        if (Zt.idx.size() > (size_t)INT32_MAX || KZt.idx.size() > (size_t)INT32_MAX) return DPCG_EINVAL;
-    }
-    // ---- launch shapes and upload ----
+    TRY(gpu_setup(c, n, k_rowptr, k_col, k_val, k, z_rowptr, z_col, z_val, nblocks, block_ptr, bad));
     choose_shapes(c);
-    TRY(upload(c, &c->brow_ptr, bptr.data(), bptr.size()));
-    TRY(upload(c, &c->bcol, bcol.data(), bcol.size()));
-    TRY(upload(c, &c->bval, bval.data(), bval.size()));
-    TRY(upload(c, &c->minv, minv.data(), minv.size()));
-    TRY(upload(c, &c->bj_rowoff, rowoff.data(), rowoff.size()));
-    TRY(upload(c, &c->bj_meta, meta.data(), meta.size()));
-    TRY(upload(c, &c->bj_wg_start, tiles.data(), tiles.size()));
-    std::vector<int32_t> zptr32(n + 1);
-    for (int64_t i = 0; i <= n; ++i) zptr32[i] = (int32_t)Z.ptr[i];
-    TRY(upload(c, &c->z_ptr, zptr32.data(), zptr32.size()));
-    TRY(upload(c, &c->z_col, Z.idx.data(), Z.idx.size()));
-    TRY(upload(c, &c->z_val, Z.val.data(), Z.val.size()));
-    if (k > 0) {
-        std::vector<int32_t> p32(k + 1);
-        for (int64_t i = 0; i <= k; ++i) p32[i] = (int32_t)Zt.ptr[i];
-        TRY(upload(c, &c->zt_ptr, p32.data(), p32.size()));
-        TRY(upload(c, &c->zt_idx, Zt.idx.data(), Zt.idx.size()));
-        TRY(upload(c, &c->zt_val, Zt.val.data(), Zt.val.size()));
-        for (int64_t i = 0; i <= k; ++i) p32[i] = (int32_t)KZt.ptr[i];
-        TRY(upload(c, &c->kzt_ptr, p32.data(), p32.size()));
-        TRY(upload(c, &c->kzt_idx, KZt.idx.data(), KZt.idx.size()));
-        TRY(upload(c, &c->kzt_val, KZt.val.data(), KZt.val.size()));
-        TRY(upload(c, &c->einv, einv.data(), einv.size()));
-    }
     TRY(alloc_workspace(c, c->ws[0]));
     TRY(alloc_workspace(c, c->ws[1]));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipStreamSynchronize(c->stream));
     return DPCG_OK;
 }
 
@@ -551,7 +105,8 @@ void release(dpcg_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
-    for (void *p : c->allocations) (void)hipFree(p);
+    for (void *p : c->allocations) (void)hipFreeAsync(p, c->stream);
+    (void)hipStreamSynchronize(c->stream);
     for (auto &w : c->ws) {
         if (w.snap) (void)hipHostFree(w.snap);
         if (w.hist) (void)hipFree(w.hist);
@@ -748,6 +303,13 @@ int dpcg_setup(dpcg_handle *h, int64_t n, const int64_t *k_rowptr, const int32_t
         delete c;
         fill_info(info, DPCG_EHIP, 0, 0, 0, 0, 0, -1);
         return DPCG_EHIP;
+    }
+    // device memory comes from the stream-ordered pool; keep freed memory cached in it
+    // so that repeated setups on one device do not return to the driver
+    hipMemPool_t mp;
+    if (hipDeviceGetDefaultMemPool(&mp, c->device) == hipSuccess) {
+        uint64_t keep_all = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(mp, hipMemPoolAttrReleaseThreshold, &keep_all);
     }
     int64_t bad = -1;
     int st = setup_impl(c, n, k_rowptr, k_col, k_val, k, z_rowptr, z_col, z_val, nblocks, block_ptr, &bad);

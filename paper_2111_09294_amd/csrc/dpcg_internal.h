@@ -9,7 +9,7 @@
 //       block start).  DoF range of workgroup w of the update kernel:
 //       [bj_wg_start[w], bj_wg_start[w+1]) holds whole blocks only.
 //   Z   CSR by rows (prolongation), Z^T and (KZ)^T as CSR with k rows
-//       (restriction), E^-1 dense k x k row-major (symmetric).
+//       (restriction), E^-1 dense row-major with leading dimension einv_ld.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -85,6 +85,7 @@ struct dpcg_ctx {
     int32_t *kzt_ptr = nullptr, *kzt_idx = nullptr;
     double *kzt_val = nullptr;
     double *einv = nullptr;
+    int64_t einv_ld = 0;       // leading dimension of E^-1 (k rounded up to 32)
     // launch shapes
     dpcg::SpmvPlan spmv;
     int32_t vec_nwg = 0;       // grid of the elementwise kernels (one DoF per thread)
@@ -115,5 +116,10 @@ hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Work
 hipError_t launch_prolong(const dpcg_ctx *c, const double *base, const double *delta, double *out,
                           Workspace *w, const double *rdot, int advance);
 hipError_t launch_reduce_aux(const dpcg_ctx *c, Workspace &w, int n_parts);
+
+// setup.hip: all setup factorisations on the GPU; returns a DPCG_* status.
+int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, const double *kv, int32_t k,
+              const int64_t *zp, const int32_t *zc, const double *zv, int32_t nblocks, const int32_t *bp,
+              int64_t *bad);
 
 }  // namespace dpcg

@@ -331,14 +331,14 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
 }
 
 // delta = E^{-1} g: one wave per row of the dense symmetric inverse.
-__global__ __launch_bounds__(kThreads) void k_coarse(int32_t k, const double *__restrict__ einv,
+__global__ __launch_bounds__(kThreads) void k_coarse(int32_t k, int64_t ld, const double *__restrict__ einv,
                                                      const double *__restrict__ g, double *__restrict__ delta,
                                                      const State *st) {
     if (st && wg_flag(st) != kRunning) return;
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= k) return;
-    const double *e = einv + (int64_t)row * k;
+    const double *e = einv + (int64_t)row * ld;
     double s = 0.0;
     for (int l = lane; l < k; l += 64) s = fma(e[l], g[l], s);
     s = wave_sum(s);
@@ -481,7 +481,7 @@ hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, 
 
 hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Workspace *w) {
     if (c->k == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coarse, dim3((c->k + 3) / 4), dim3(kThreads), 0, c->stream, c->k, c->einv, g, delta,
+    hipLaunchKernelGGL(k_coarse, dim3((c->k + 3) / 4), dim3(kThreads), 0, c->stream, c->k, c->einv_ld, c->einv, g, delta,
                        w ? w->st : nullptr);
     return hipGetLastError();
 }

@@ -154,6 +154,18 @@ def test_deterministic_and_adjoint(pair, name):
     assert torch.equal(u3, u1)
 
 
+@pytest.mark.parametrize("name", ["edge10", "penny40"])
+def test_setup_deterministic(pair, name):
+    """Two independent setups of the same system give bitwise-identical solves."""
+    p, o, s = pair(name)
+    f = dev(p.f)
+    u1, i1 = s.solve(f)
+    with D.Solver.from_problem(p, DEV) as s2:
+        u2, i2 = s2.solve(f)
+        assert s2.stats() == s.stats()
+    assert torch.equal(u1, u2) and i1["iterations"] == i2["iterations"]
+
+
 def test_random_rhs_and_warm_start(pair):
     p, o, s = pair("penny12")
     rng = np.random.default_rng(5)
