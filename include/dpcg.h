@@ -134,6 +134,10 @@ int dpcg_solve_adjoint(dpcg_handle h, const double *g, double *lambda, double to
 /* Releases every resource of the handle (NULL is a no-op). */
 void dpcg_destroy(dpcg_handle h);
 
+/* Device memory of destroyed handles is cached by the library and reused by later
+ * setups on the same device; this returns all cached memory to the driver. */
+void dpcg_release_cached_memory(void);
+
 /* Static description of a status code. */
 const char *dpcg_status_string(int status);
 

@@ -56,6 +56,7 @@ SIGNATURES = {
     "dpcg_solve": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
     "dpcg_solve_adjoint": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
     "dpcg_destroy": (None, [P]),
+    "dpcg_release_cached_memory": (None, []),
     "dpcg_status_string": (C.c_char_p, [C.c_int]),
     "dpcg_get_stats": (C.c_int, [P, C.POINTER(Stats)]),
     "dpcg_get_history": (C.c_int64, [P, P, C.c_int64]),

@@ -1,0 +1,81 @@
+// Process-wide cache of device memory blocks.  Setting up a handle needs a few dozen
+// arrays; a solver that is set up once per system (a crack-growth step) would otherwise
+// pay the driver's allocation and release cost every time.  Blocks are released only
+// after the stream that used them has been synchronised, so a cached block is idle and
+// may be handed to any stream.
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <vector>
+
+#include "dpcg_internal.h"
+
+namespace dpcg {
+
+namespace {
+
+struct Cache {
+    std::mutex m;
+    // (device, rounded size) -> idle blocks
+    std::map<std::pair<int, size_t>, std::vector<void *>> idle;
+    std::unordered_map<void *, std::pair<int, size_t>> owner;
+};
+
+Cache &cache() {
+    static Cache *c = new Cache();  // never destroyed: blocks outlive static destructors
+    return *c;
+}
+
+size_t round_size(size_t bytes) {
+    if (bytes <= (size_t(1) << 20)) return (bytes + 255) & ~size_t(255);
+    const size_t g = size_t(2) << 20;
+    return (bytes + g - 1) / g * g;
+}
+
+}  // namespace
+
+hipError_t dev_alloc(void **p, size_t bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const size_t sz = round_size(bytes ? bytes : 1);
+    Cache &c = cache();
+    {
+        std::lock_guard<std::mutex> lk(c.m);
+        auto it = c.idle.find({dev, sz});
+        if (it != c.idle.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            return hipSuccess;
+        }
+    }
+    e = hipMalloc(p, sz);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(c.m);
+    c.owner[*p] = {dev, sz};
+    return hipSuccess;
+}
+
+void dev_release(void *p) {
+    if (!p) return;
+    Cache &c = cache();
+    std::lock_guard<std::mutex> lk(c.m);
+    auto it = c.owner.find(p);
+    if (it == c.owner.end()) return;
+    c.idle[it->second].push_back(p);
+}
+
+void dev_trim() {
+    Cache &c = cache();
+    std::lock_guard<std::mutex> lk(c.m);
+    for (auto &kv : c.idle)
+        for (void *p : kv.second) {
+            (void)hipFree(p);
+            c.owner.erase(p);
+        }
+    c.idle.clear();
+}
+
+}  // namespace dpcg

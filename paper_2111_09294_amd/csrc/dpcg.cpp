@@ -9,11 +9,57 @@
 #include <cstring>
 #include <vector>
 
+#include <mutex>
+
 #include "dpcg_internal.h"
 
 using namespace dpcg;
 
 namespace {
+
+// Pinned state mirrors and timing events are kept in process-wide free lists: creating
+// and releasing them costs milliseconds, and handles come and go once per system.
+std::mutex g_pool_mutex;
+std::vector<State *> g_pinned_states;
+std::vector<hipEvent_t> g_events;
+
+State *take_pinned_state() {
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mutex);
+        if (!g_pinned_states.empty()) {
+            State *s = g_pinned_states.back();
+            g_pinned_states.pop_back();
+            return s;
+        }
+    }
+    State *s = nullptr;
+    if (hipHostMalloc((void **)&s, sizeof(State), hipHostMallocDefault) != hipSuccess) return nullptr;
+    return s;
+}
+
+void give_pinned_state(State *s) {
+    if (!s) return;
+    std::lock_guard<std::mutex> lk(g_pool_mutex);
+    g_pinned_states.push_back(s);
+}
+
+hipError_t take_event(hipEvent_t *e) {
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mutex);
+        if (!g_events.empty()) {
+            *e = g_events.back();
+            g_events.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipEventCreate(e);
+}
+
+void give_events(std::vector<hipEvent_t> &ev) {
+    std::lock_guard<std::mutex> lk(g_pool_mutex);
+    g_events.insert(g_events.end(), ev.begin(), ev.end());
+    ev.clear();
+}
 
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -29,7 +75,7 @@ template <class T>
 int alloc(dpcg_ctx *c, T **dst, size_t count) {
     const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
     void *p = nullptr;
-    HIP_TRY(hipMallocAsync(&p, bytes, c->stream));
+    HIP_TRY(dev_alloc(&p, bytes));
     HIP_TRY(hipMemsetAsync(p, 0, bytes, c->stream));
     c->allocations.push_back(p);
     c->device_bytes += (int64_t)bytes;
@@ -59,7 +105,8 @@ int alloc_workspace(dpcg_ctx *c, Workspace &w) {
     TRY(alloc(c, &w.part_b, np));
     TRY(alloc(c, &w.part_c, np));
     TRY(alloc(c, &w.st, 1));
-    HIP_TRY(hipHostMalloc((void **)&w.snap, sizeof(State), hipHostMallocDefault));
+    w.snap = take_pinned_state();
+    if (!w.snap) return DPCG_EHIP;
     return DPCG_OK;
 }
 
@@ -104,11 +151,10 @@ int setup_impl(dpcg_ctx *c, int64_t n, const int64_t *k_rowptr, const int32_t *k
 void release(dpcg_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
-    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
-    for (void *p : c->allocations) (void)hipFreeAsync(p, c->stream);
-    (void)hipStreamSynchronize(c->stream);
+    give_events(c->events);
+    for (void *p : c->allocations) dev_release(p);
     for (auto &w : c->ws) {
-        if (w.snap) (void)hipHostFree(w.snap);
+        give_pinned_state(w.snap);
         if (w.hist) (void)hipFree(w.hist);
     }
     delete c;
@@ -169,7 +215,7 @@ int next_event_pair(dpcg_ctx *c, hipEvent_t *a, hipEvent_t *b) {
     if ((size_t)c->events_used + 2 > c->events.size()) {
         for (int i = 0; i < 64; ++i) {
             hipEvent_t e;
-            HIP_TRY(hipEventCreate(&e));
+            HIP_TRY(take_event(&e));
             c->events.push_back(e);
         }
     }
@@ -304,13 +350,6 @@ int dpcg_setup(dpcg_handle *h, int64_t n, const int64_t *k_rowptr, const int32_t
         fill_info(info, DPCG_EHIP, 0, 0, 0, 0, 0, -1);
         return DPCG_EHIP;
     }
-    // device memory comes from the stream-ordered pool; keep freed memory cached in it
-    // so that repeated setups on one device do not return to the driver
-    hipMemPool_t mp;
-    if (hipDeviceGetDefaultMemPool(&mp, c->device) == hipSuccess) {
-        uint64_t keep_all = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(mp, hipMemPoolAttrReleaseThreshold, &keep_all);
-    }
     int64_t bad = -1;
     int st = setup_impl(c, n, k_rowptr, k_col, k_val, k, z_rowptr, z_col, z_val, nblocks, block_ptr, &bad);
     c->setup_ms = now_ms() - t0;
@@ -339,6 +378,8 @@ int dpcg_solve_adjoint(dpcg_handle h, const double *g, double *lambda, double to
 }
 
 void dpcg_destroy(dpcg_handle h) { release(h); }
+
+void dpcg_release_cached_memory(void) { dev_trim(); }
 
 const char *dpcg_status_string(int status) {
     switch (status) {

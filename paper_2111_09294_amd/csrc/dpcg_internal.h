@@ -117,6 +117,11 @@ hipError_t launch_prolong(const dpcg_ctx *c, const double *base, const double *d
                           Workspace *w, const double *rdot, int advance);
 hipError_t launch_reduce_aux(const dpcg_ctx *c, Workspace &w, int n_parts);
 
+// devmem.cpp: cached device allocations (release only after the using stream is idle).
+hipError_t dev_alloc(void **p, size_t bytes);
+void dev_release(void *p);
+void dev_trim();
+
 // setup.hip: all setup factorisations on the GPU; returns a DPCG_* status.
 int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, const double *kv, int32_t k,
               const int64_t *zp, const int32_t *zc, const double *zv, int32_t nblocks, const int32_t *bp,

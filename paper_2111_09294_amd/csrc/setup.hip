@@ -152,25 +152,33 @@ __global__ __launch_bounds__(256) void k_maxabs_part(const double *__restrict__ 
     if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
 }
 
-// |K_ij - K_ji| <= 1e-12 max|K| for every stored entry; the mirror is found by binary search.
-__global__ void k_check_sym(int64_t n, const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                            const double *__restrict__ val, const double *__restrict__ maxpart, int nmax,
-                            int *flag) {
+// |K_ij - K_ji| <= 1e-12 max|K| over the packed 3x3 blocks: block (R, C) against the
+// transpose of block (C, R), found by binary search in block row C (a missing block is 0).
+__global__ void k_check_sym(int32_t nb, const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol,
+                            const double *__restrict__ bval, int64_t nnzb, const double *__restrict__ maxpart,
+                            int nmax, int *flag) {
     double mx = 0.0;
     for (int i = 0; i < nmax; ++i) mx = fmax(mx, maxpart[i]);
     const double tol = 1e-12 * mx;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
-            const int64_t j = idx[e];
-            int64_t lo = ptr[j], hi = ptr[j + 1];
+    for (int R = blockIdx.x * blockDim.x + threadIdx.x; R < nb; R += gridDim.x * blockDim.x) {
+        for (int64_t b = bptr[R]; b < bptr[R + 1]; ++b) {
+            const int32_t C = bcol[b];
+            int64_t lo = bptr[C], hi = bptr[C + 1];
             while (lo < hi) {
                 const int64_t mid = (lo + hi) >> 1;
-                if (idx[mid] < i) lo = mid + 1;
+                if (bcol[mid] < R) lo = mid + 1;
                 else hi = mid;
             }
-            const double m = (lo < ptr[j + 1] && idx[lo] == i) ? val[lo] : 0.0;
-            if (fabs(val[e] - m) > tol) {
-                atomicMin(flag + 3, (int)i);
+            const bool found = lo < bptr[C + 1] && bcol[lo] == R;
+            bool ok = true;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    const double v = bval[(int64_t)(3 * i + j) * nnzb + b];
+                    const double m = found ? bval[(int64_t)(3 * j + i) * nnzb + lo] : 0.0;
+                    ok = ok && fabs(v - m) <= tol;
+                }
+            if (!ok) {
+                atomicMin(flag + 3, 3 * R);
                 break;
             }
         }
@@ -328,23 +336,58 @@ __global__ void k_col_place(int64_t rows, const int64_t *__restrict__ ptr, const
         }
 }
 
-// Orders each segment by its (unique) keys: the rank of an entry is the number of
-// smaller keys in its segment.  Segments are streamed through LDS in chunks.
-__global__ __launch_bounds__(256) void k_seg_rank(const int64_t *__restrict__ tptr, const int32_t *__restrict__ kin,
+// Orders each segment by its (unique) keys.  Segments of up to 4096 entries are sorted
+// in LDS by a bitonic network; longer ones by rank (number of smaller keys), streamed
+// through LDS in chunks.
+__global__ __launch_bounds__(256) void k_seg_sort(const int64_t *__restrict__ tptr, const int32_t *__restrict__ kin,
                                                   const double *__restrict__ vin, int32_t *__restrict__ kout,
                                                   double *__restrict__ vout) {
-    __shared__ int32_t keys[2048];
+    constexpr int kCap = 4096;
+    __shared__ int32_t keys[kCap];
+    __shared__ int32_t pos[kCap];
     const int64_t a = tptr[blockIdx.x], b = tptr[blockIdx.x + 1];
     const int64_t m = b - a;
+    if (m <= kCap) {
+        int L = 1;
+        while (L < m) L <<= 1;
+        for (int t = threadIdx.x; t < L; t += 256) {
+            keys[t] = t < m ? kin[a + t] : INT32_MAX;
+            pos[t] = t;
+        }
+        __syncthreads();
+        for (int size = 2; size <= L; size <<= 1)
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int t = threadIdx.x; t < L; t += 256) {
+                    const int u = t ^ stride;
+                    if (u > t) {
+                        const bool up = (t & size) == 0;
+                        const int32_t kt = keys[t], ku = keys[u];
+                        if ((kt > ku) == up) {
+                            keys[t] = ku;
+                            keys[u] = kt;
+                            const int32_t pt = pos[t];
+                            pos[t] = pos[u];
+                            pos[u] = pt;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        for (int t = threadIdx.x; t < m; t += 256) {
+            kout[a + t] = keys[t];
+            vout[a + t] = vin[a + pos[t]];
+        }
+        return;
+    }
     for (int64_t base = 0; base < m; base += 256) {
         const int64_t mine = base + threadIdx.x;
         const int32_t key = mine < m ? kin[a + mine] : INT32_MAX;
         int64_t rank = 0;
-        for (int64_t c = 0; c < m; c += 2048) {
+        for (int64_t c = 0; c < m; c += kCap) {
             __syncthreads();
-            for (int t = threadIdx.x; t < 2048; t += 256) keys[t] = (c + t < m) ? kin[a + c + t] : INT32_MAX;
+            for (int t = threadIdx.x; t < kCap; t += 256) keys[t] = (c + t < m) ? kin[a + c + t] : INT32_MAX;
             __syncthreads();
-            const int lim = (int)min<int64_t>(2048, m - c);
+            const int lim = (int)min<int64_t>(kCap, m - c);
             for (int t = 0; t < lim; ++t) rank += keys[t] < key;
         }
         if (mine < m) {
@@ -389,98 +432,198 @@ __global__ __launch_bounds__(256) void k_kz_window(int32_t k, const int64_t *__r
     }
 }
 
-// Window of column j: zd = z_j scattered, mk = rows of K z_j's structure (rows adjacent
-// to the rows of z_j; K is structurally symmetric).
-__device__ void kz_window_init(int j, const int64_t *ztp, const int32_t *zti, const double *ztv, const int64_t *kp,
-                               const int32_t *kc, int64_t lo, int64_t w, double *zd, int32_t *mk) {
-    for (int64_t t = threadIdx.x; t < w; t += 256) {
-        zd[t] = 0.0;
-        mk[t] = 0;
+// ---- K Z and E in batches of kBatch consecutive deflation vectors ----
+// A batch owns the union window [lo, lo + w) of its vectors' row windows.  Per window
+// position t (row lo + t) it keeps zd[t][b] = Z[lo+t, j0+b], rb[t] = vectors with a
+// nonzero in that row, mk[t] = vectors whose K z_j has row lo + t in its structure,
+// and kd[t][b] = (K z_{j0+b})_{lo+t}.  Windows are processed in slices of kSlice
+// positions, one workgroup per (slice, batch).
+constexpr int kBatch = 16;
+constexpr int kSlice = 2048;
+
+struct KzBatch {
+    int64_t j0, ncol, lo, w, off, slice0, nslice;
+};
+
+__global__ __launch_bounds__(256) void k_kzb_init(const KzBatch *__restrict__ bt, double *__restrict__ zd,
+                                                  double *__restrict__ kd, uint32_t *__restrict__ mk,
+                                                  uint32_t *__restrict__ rb) {
+    const KzBatch B = bt[blockIdx.y];
+    if (blockIdx.x >= B.nslice) return;
+    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w, t0 + kSlice);
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
+        mk[B.off + t] = 0u;
+        rb[B.off + t] = 0u;
     }
-    __syncthreads();
+    for (int64_t t = t0 * kBatch + threadIdx.x; t < t1 * kBatch; t += 256) {
+        zd[B.off * kBatch + t] = 0.0;
+        kd[B.off * kBatch + t] = 0.0;
+    }
+}
+
+// one workgroup per (vector, batch): scatter z_j and flag its rows
+__global__ __launch_bounds__(256) void k_kzb_scatter(const KzBatch *__restrict__ bt, const int64_t *__restrict__ ztp,
+                                                     const int32_t *__restrict__ zti, const double *__restrict__ ztv,
+                                                     double *__restrict__ zd, uint32_t *rb) {
+    const KzBatch B = bt[blockIdx.y];
+    const int b = blockIdx.x;
+    if (b >= B.ncol) return;
+    const int64_t j = B.j0 + b;
     for (int64_t e = ztp[j] + threadIdx.x; e < ztp[j + 1]; e += 256) {
-        const int64_t r = zti[e];
-        if (r - lo >= 0 && r - lo < w) zd[r - lo] = ztv[e];
+        const int64_t t = (int64_t)zti[e] - B.lo;
+        if (t < 0 || t >= B.w) continue;
+        zd[(B.off + t) * kBatch + b] = ztv[e];
+        atomicOr(&rb[B.off + t], 1u << b);
+    }
+}
+
+// structure of K z_j: every column of K row r for r in the rows of z_j (K is structurally symmetric)
+__global__ __launch_bounds__(256) void k_kzb_mark(const KzBatch *__restrict__ bt, const int64_t *__restrict__ kp,
+                                                  const int32_t *__restrict__ kc, const uint32_t *__restrict__ rb,
+                                                  uint32_t *mk) {
+    const KzBatch B = bt[blockIdx.y];
+    if (blockIdx.x >= B.nslice) return;
+    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w, t0 + kSlice);
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
+        const uint32_t bits = rb[B.off + t];
+        if (!bits) continue;
+        const int64_t r = B.lo + t;
         for (int64_t q = kp[r]; q < kp[r + 1]; ++q) {
-            const int64_t t = (int64_t)kc[q] - lo;
-            if (t >= 0 && t < w) mk[t] = 1;
+            const int64_t c = (int64_t)kc[q] - B.lo;
+            if (c >= 0 && c < B.w) atomicOr(&mk[B.off + c], bits);
         }
     }
+}
+
+// per (slice, vector) counts of structure rows
+__global__ __launch_bounds__(256) void k_kzb_count(const KzBatch *__restrict__ bt, const uint32_t *__restrict__ mk,
+                                                   int32_t *__restrict__ cnt) {
+    __shared__ int32_t c_s[kBatch];
+    const KzBatch B = bt[blockIdx.y];
+    if (blockIdx.x >= B.nslice) return;
+    if (threadIdx.x < kBatch) c_s[threadIdx.x] = 0;
     __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w, t0 + kSlice);
+    int32_t mine[kBatch];
+    for (int b = 0; b < kBatch; ++b) mine[b] = 0;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
+        const uint32_t m = mk[B.off + t];
+        for (int b = 0; b < kBatch; ++b) mine[b] += (m >> b) & 1u;
+    }
+    for (int b = 0; b < kBatch; ++b)
+        if (mine[b]) atomicAdd(&c_s[b], mine[b]);
+    __syncthreads();
+    if (threadIdx.x < kBatch) cnt[(B.slice0 + blockIdx.x) * kBatch + threadIdx.x] = c_s[threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_kz_count(int32_t j0, int32_t j1, const int64_t *__restrict__ ztp,
-                                                  const int32_t *__restrict__ zti, const double *__restrict__ ztv,
-                                                  const int64_t *__restrict__ kp, const int32_t *__restrict__ kc,
-                                                  const int64_t *__restrict__ wlo, const int64_t *__restrict__ wsize,
-                                                  const int64_t *__restrict__ woff, double *zd_all, int32_t *mk_all,
-                                                  int64_t *__restrict__ cnt) {
-    __shared__ int64_t l64[4];
-    const int j = j0 + blockIdx.x;
-    if (j >= j1) return;
-    const int64_t lo = wlo[j], w = wsize[j], off = woff[j] - woff[j0];
-    double *zd = zd_all + off;
-    int32_t *mk = mk_all + off;
-    kz_window_init(j, ztp, zti, ztv, kp, kc, lo, w, zd, mk);
-    int64_t c = 0;
-    for (int64_t t = threadIdx.x; t < w; t += 256) c += mk[t];
-    int64_t tot;
-    block_exclusive_scan(c, l64, tot);
-    if (threadIdx.x == 0) cnt[j] = tot;
+// slice offsets within each vector's structure, and the vector totals
+__global__ void k_kzb_offsets(const KzBatch *__restrict__ bt, int nbat, const int32_t *__restrict__ cnt,
+                              int32_t *__restrict__ soff, int64_t *__restrict__ kzcnt) {
+    const int bi = blockIdx.x;
+    if (bi >= nbat) return;
+    const KzBatch B = bt[bi];
+    const int b = threadIdx.x;
+    if (b >= B.ncol) return;
+    int64_t run = 0;
+    for (int64_t sl = 0; sl < B.nslice; ++sl) {
+        soff[(B.slice0 + sl) * kBatch + b] = (int32_t)run;
+        run += cnt[(B.slice0 + sl) * kBatch + b];
+    }
+    kzcnt[B.j0 + b] = run;
 }
 
-// Column j of K Z (rows ascending) into (KZ)^T row j, then E_raw[j, i] = sum_t KZ[t, j] Z[t, i]
-// for every i whose rows meet the window (ascending t).
-__global__ __launch_bounds__(256) void k_kz_fill(int32_t j0, int32_t j1, int32_t k, const int64_t *__restrict__ ztp,
-                                                 const int32_t *__restrict__ zti, const double *__restrict__ ztv,
-                                                 const int64_t *__restrict__ kp, const int32_t *__restrict__ kc,
-                                                 const double *__restrict__ kv, const int64_t *__restrict__ wlo,
-                                                 const int64_t *__restrict__ wsize, const int64_t *__restrict__ woff,
-                                                 double *zd_all, int32_t *mk_all, const int64_t *__restrict__ kzp,
-                                                 int32_t *__restrict__ kzi, double *__restrict__ kzv,
-                                                 double *__restrict__ eraw, int64_t ld) {
-    __shared__ int64_t l64[4];
-    const int j = j0 + blockIdx.x;
-    if (j >= j1) return;
-    const int64_t lo = wlo[j], w = wsize[j], off = woff[j] - woff[j0];
-    double *zd = zd_all + off;
-    int32_t *mk = mk_all + off;
-    kz_window_init(j, ztp, zti, ztv, kp, kc, lo, w, zd, mk);
-    const int64_t base = kzp[j];
-    int64_t carry = 0;
-    for (int64_t c0 = 0; c0 < w; c0 += 256) {
+// (K z_j)_r for the structure rows of the slice; rows are written ascending into (KZ)^T
+// row j and densely into kd.
+__global__ __launch_bounds__(256) void k_kzb_values(const KzBatch *__restrict__ bt, const int64_t *__restrict__ kp,
+                                                    const int32_t *__restrict__ kc, const double *__restrict__ kv,
+                                                    const double *__restrict__ zd, const uint32_t *__restrict__ mk,
+                                                    const int32_t *__restrict__ soff, const int64_t *__restrict__ kzp,
+                                                    int32_t *__restrict__ kzi, double *__restrict__ kzv,
+                                                    double *__restrict__ kd) {
+    __shared__ int32_t wave_cnt[4][kBatch];
+    __shared__ int32_t carry[kBatch];
+    const KzBatch B = bt[blockIdx.y];
+    if (blockIdx.x >= B.nslice) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x < kBatch) carry[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w, t0 + kSlice);
+    for (int64_t c0 = t0; c0 < t1; c0 += 256) {
         const int64_t t = c0 + threadIdx.x;
-        const int64_t flag = (t < w) ? mk[t] : 0;
-        int64_t tot;
-        const int64_t ex = block_exclusive_scan(flag, l64, tot);
-        if (flag) {
-            const int64_t r = lo + t;
-            double s = 0.0;
+        const uint32_t m = t < t1 ? mk[B.off + t] : 0u;
+        double acc[kBatch];
+        for (int b = 0; b < kBatch; ++b) acc[b] = 0.0;
+        if (m) {
+            const int64_t r = B.lo + t;
             for (int64_t q = kp[r]; q < kp[r + 1]; ++q) {
-                const int64_t cidx = (int64_t)kc[q] - lo;
-                if (cidx >= 0 && cidx < w) s = fma(kv[q], zd[cidx], s);
+                const int64_t c = (int64_t)kc[q] - B.lo;
+                if (c < 0 || c >= B.w) continue;
+                const double v = kv[q];
+                const double *z = zd + (B.off + c) * kBatch;
+                for (int b = 0; b < kBatch; ++b) acc[b] = fma(v, z[b], acc[b]);
             }
-            kzi[base + carry + ex] = (int32_t)r;
-            kzv[base + carry + ex] = s;
+            double *o = kd + (B.off + t) * kBatch;
+            for (int b = 0; b < kBatch; ++b) o[b] = acc[b];
         }
-        carry += tot;
+        // rank of this row among the slice's structure rows of each vector
+        int32_t rank[kBatch];
+        for (int b = 0; b < kBatch; ++b) {
+            const unsigned long long bal = __ballot((m >> b) & 1u);
+            rank[b] = __popcll(bal & ((1ull << lane) - 1ull));
+            if (lane == 0) wave_cnt[wv][b] = __popcll(bal);
+        }
+        __syncthreads();
+        for (int b = 0; b < kBatch; ++b) {
+            if (b >= B.ncol || !((m >> b) & 1u)) continue;
+            int32_t before = carry[b];
+            for (int w2 = 0; w2 < wv; ++w2) before += wave_cnt[w2][b];
+            const int64_t pos = kzp[B.j0 + b] + soff[(B.slice0 + blockIdx.x) * kBatch + b] + before + rank[b];
+            kzi[pos] = (int32_t)(B.lo + t);
+            kzv[pos] = acc[b];
+        }
+        __syncthreads();
+        if (threadIdx.x < kBatch)
+            carry[threadIdx.x] += wave_cnt[0][threadIdx.x] + wave_cnt[1][threadIdx.x] + wave_cnt[2][threadIdx.x] +
+                                  wave_cnt[3][threadIdx.x];
         __syncthreads();
     }
-    // dense K z_j over the window, in place of z_j
-    for (int64_t t = threadIdx.x; t < w; t += 256) zd[t] = 0.0;
-    __syncthreads();
-    for (int64_t e = base + threadIdx.x; e < kzp[j + 1]; e += 256) zd[kzi[e] - lo] = kzv[e];
-    __syncthreads();
-    for (int i = threadIdx.x; i < k; i += 256) {
-        const int64_t a = ztp[i], b = ztp[i + 1];
-        if (a == b || zti[b - 1] < lo || zti[a] >= lo + w) continue;
-        double s = 0.0;
-        for (int64_t e = a; e < b; ++e) {
-            const int64_t t = (int64_t)zti[e] - lo;
-            if (t >= 0 && t < w) s = fma(ztv[e], zd[t], s);
+}
+
+// E_raw[j0+b, i] = sum over the rows t of z_i inside the window of Z[t, i] (K z_{j0+b})_t
+__global__ __launch_bounds__(256) void k_kzb_erows(const KzBatch *__restrict__ bt, int32_t k,
+                                                   const int64_t *__restrict__ ztp, const int32_t *__restrict__ zti,
+                                                   const double *__restrict__ ztv, const double *__restrict__ kd,
+                                                   double *__restrict__ eraw, int64_t ld) {
+    const KzBatch B = bt[blockIdx.y];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= k || B.w == 0) return;
+    int64_t a = ztp[i], e = ztp[i + 1];
+    if (a == e || zti[e - 1] < B.lo || zti[a] >= B.lo + B.w) return;
+    {  // first entry with row >= lo, first with row >= lo + w
+        int64_t l = a, h = e;
+        while (l < h) {
+            const int64_t mid = (l + h) >> 1;
+            if (zti[mid] < B.lo) l = mid + 1;
+            else h = mid;
         }
-        eraw[(int64_t)j * ld + i] = s;
+        a = l;
+        h = e;
+        while (l < h) {
+            const int64_t mid = (l + h) >> 1;
+            if (zti[mid] < B.lo + B.w) l = mid + 1;
+            else h = mid;
+        }
+        e = l;
     }
+    double acc[kBatch];
+    for (int b = 0; b < kBatch; ++b) acc[b] = 0.0;
+    for (int64_t q = a; q < e; ++q) {
+        const double z = ztv[q];
+        const double *kdr = kd + (B.off + (int64_t)zti[q] - B.lo) * kBatch;
+        for (int b = 0; b < kBatch; ++b) acc[b] = fma(z, kdr[b], acc[b]);
+    }
+    for (int b = 0; b < kBatch; ++b)
+        if (b < B.ncol) eraw[(B.j0 + b) * ld + i] = acc[b];
 }
 
 // A = (E + E^T)/2 padded to ld x ld with an identity tail; diag0 = diagonal of A.
@@ -498,8 +641,9 @@ __global__ void k_symmetrise(int32_t k, int64_t ld, const double *__restrict__ e
 }
 
 // ---------------------------------------------------------------- E^-1 by block Gauss-Jordan
-// P = S^-1 for the symmetric 32 x 32 pivot block S (LDS), via Cholesky; the pivots are
-// tested against kdim * DBL_EPSILON times the original diagonal entries.
+// P = S^-1 for the symmetric 32 x 32 pivot block S (LDS) by a right-looking Cholesky
+// S = L L^T, W = L^-1 and P = W^T W; every pivot is tested against kdim * DBL_EPSILON
+// times the original diagonal entry.  S and W are overwritten.
 __device__ void pivot_inverse(double *S, double *W, const double *diag0, int64_t gcol0, int32_t kdim, double *P,
                               int *fail) {
     __shared__ int bad;
@@ -507,41 +651,42 @@ __device__ void pivot_inverse(double *S, double *W, const double *diag0, int64_t
     __syncthreads();
     for (int j = 0; j < kNb; ++j) {
         if (threadIdx.x == 0) {
-            double d = S[j * kNb + j];
-            for (int p = 0; p < j; ++p) d -= S[j * kNb + p] * S[j * kNb + p];
+            const double d = S[j * kNb + j];
             const int64_t g = gcol0 + j;
             const double fl = g < kdim ? (double)kdim * DBL_EPSILON * fabs(diag0[g]) : 0.0;
             if (!(d > fl) || !isfinite(d)) bad = 1;
-            S[j * kNb + j] = sqrt(fmax(d, 0.0));
+            S[j * kNb + j] = d > 0.0 ? sqrt(d) : 1.0;
         }
         __syncthreads();
         const double l = S[j * kNb + j];
-        for (int i = j + 1 + threadIdx.x; i < kNb; i += blockDim.x) {
-            double s = S[i * kNb + j];
-            for (int p = 0; p < j; ++p) s -= S[i * kNb + p] * S[j * kNb + p];
-            S[i * kNb + j] = l > 0.0 ? s / l : 0.0;
+        for (int i = j + 1 + threadIdx.x; i < kNb; i += blockDim.x) S[i * kNb + j] /= l;
+        __syncthreads();
+        const int rem = kNb - j - 1;
+        for (int t = threadIdx.x; t < rem * rem; t += blockDim.x) {
+            const int i = j + 1 + t / rem, c = j + 1 + t % rem;
+            if (c <= i) S[i * kNb + c] -= S[i * kNb + j] * S[c * kNb + j];
         }
         __syncthreads();
     }
-    // W = L^-1 (column j by thread j)
-    if (threadIdx.x < kNb) {
-        const int j = threadIdx.x;
-        for (int i = 0; i < kNb; ++i) {
-            if (i < j) {
-                W[i * kNb + j] = 0.0;
-                continue;
-            }
-            double s = (i == j) ? 1.0 : 0.0;
-            for (int p = j; p < i; ++p) s -= S[i * kNb + p] * W[p * kNb + j];
-            W[i * kNb + j] = S[i * kNb + i] > 0.0 ? s / S[i * kNb + i] : 0.0;
-        }
-    }
+    // W = L^-1, row by row: W[i, :] = (e_i - sum_{p<i} L[i,p] W[p, :]) / L[i,i]
+    for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) W[t] = (t / kNb == t % kNb) ? 1.0 : 0.0;
     __syncthreads();
+    for (int i = 0; i < kNb; ++i) {
+        const double l = S[i * kNb + i];
+        for (int c = threadIdx.x; c <= i; c += blockDim.x) W[i * kNb + c] /= l;
+        __syncthreads();
+        const int rows = kNb - i - 1;
+        for (int t = threadIdx.x; t < rows * (i + 1); t += blockDim.x) {
+            const int r = i + 1 + t / (i + 1), c = t % (i + 1);
+            W[r * kNb + c] -= S[r * kNb + i] * W[i * kNb + c];
+        }
+        __syncthreads();
+    }
     for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
         const int i = t / kNb, j = t % kNb;
-        double s = 0.0;
-        for (int p = max(i, j); p < kNb; ++p) s += W[p * kNb + i] * W[p * kNb + j];
-        P[t] = s;
+        double sacc = 0.0;
+        for (int p = max(i, j); p < kNb; ++p) sacc += W[p * kNb + i] * W[p * kNb + j];
+        P[t] = sacc;
     }
     __syncthreads();
     if (threadIdx.x == 0 && bad) atomicOr(fail, 1);
@@ -620,16 +765,18 @@ __global__ __launch_bounds__(256) void k_gj_sweep(int p, int nt, const double *_
 }
 
 // ---------------------------------------------------------------- host helpers
+// Scratch of one setup call; released (to the cache) once the stream is idle.
 struct Pool {
     dpcg_ctx *c;
     std::vector<void *> scratch;
     ~Pool() {
-        for (void *p : scratch) (void)hipFreeAsync(p, c->stream);
+        (void)hipStreamSynchronize(c->stream);
+        for (void *p : scratch) dev_release(p);
     }
     template <class T>
     hipError_t tmp(T **p, size_t count) {
         void *q = nullptr;
-        hipError_t e = hipMallocAsync(&q, std::max<size_t>(1, count) * sizeof(T), c->stream);
+        hipError_t e = dev_alloc(&q, std::max<size_t>(1, count) * sizeof(T));
         if (e == hipSuccess) scratch.push_back(q);
         *p = (T *)q;
         return e;
@@ -640,7 +787,7 @@ template <class T>
 hipError_t keep(dpcg_ctx *c, T **p, size_t count) {
     void *q = nullptr;
     const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
-    hipError_t e = hipMallocAsync(&q, bytes, c->stream);
+    hipError_t e = dev_alloc(&q, bytes);
     if (e == hipSuccess) {
         c->allocations.push_back(q);
         c->device_bytes += (int64_t)bytes;
@@ -690,6 +837,8 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     c->nnz = nnz;
     c->nnz_z = nnz_z;
     // ---- validation ----
+    const double *maxpart = nullptr;
+    int nmaxpart = 0;
     int *flags = nullptr;
     HT(pool.tmp(&flags, 4));
     const int init_flags[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
@@ -709,8 +858,9 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
         double *mxp = nullptr;
         HT(pool.tmp(&mxp, nmx));
         hipLaunchKernelGGL(k_maxabs_part, dim3(nmx), dim3(256), 0, s, kv, nnz, mxp);
-        hipLaunchKernelGGL(k_check_sym, dim3(grid_for(n)), dim3(256), 0, s, n, kp, kc, kv, mxp, nmx, flags);
         HT(hipGetLastError());
+        maxpart = mxp;
+        nmaxpart = nmx;
     }
     // ---- block-CSR counts, block-Jacobi offsets, Z^T, windows ----
     const int32_t nb = c->nb;
@@ -751,7 +901,7 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
         hipLaunchKernelGGL(k_col_count, dim3(grid_for(nnz_z)), dim3(256), 0, s, nnz_z, zc, ccount);
         HT(scan(s, ccount, k, ztp, part3));
         hipLaunchKernelGGL(k_col_place, dim3(grid_for(n)), dim3(256), 0, s, n, zp, zc, zv, ztp, fill, zti_u, ztv_u);
-        hipLaunchKernelGGL(k_seg_rank, dim3(k), dim3(256), 0, s, ztp, zti_u, ztv_u, zti, ztv);
+        hipLaunchKernelGGL(k_seg_sort, dim3(k), dim3(256), 0, s, ztp, zti_u, ztv_u, zti, ztv);
         HT(pool.tmp(&wlo, k));
         HT(pool.tmp(&wsize, k));
         hipLaunchKernelGGL(k_kz_window, dim3(k), dim3(256), 0, s, k, ztp, zti, kp, kc, wlo, wsize);
@@ -764,7 +914,6 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
     if (k > 0) HT(hipMemcpyAsync(ws.data(), wsize, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
     HT(hipStreamSynchronize(s));
-    if (fl[3] != INT32_MAX) return DPCG_ENOTSYM;
     const int64_t nnzb = tot[0];
     if (nnzb > (int64_t)INT32_MAX || tot[1] > (int64_t)INT32_MAX) return DPCG_EINVAL;
     c->nnzb = nnzb;
@@ -777,6 +926,8 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(hipMemsetAsync(c->bval, 0, sizeof(double) * 9 * (size_t)nnzb, s));
     hipLaunchKernelGGL((k_bsr<true>), dim3(grid_for(nb)), dim3(256), 0, s, nb, kp, kc, kv, nullptr, c->brow_ptr,
                        c->bcol, c->bval, nnzb);
+    hipLaunchKernelGGL(k_check_sym, dim3(grid_for(nb)), dim3(256), 0, s, nb, c->brow_ptr, c->bcol, c->bval, nnzb,
+                       maxpart, nmaxpart, flags);
     HT(keep(c, &c->minv, tot[1]));
     HT(keep(c, &c->bj_rowoff, n));
     HT(keep(c, &c->bj_meta, n));
@@ -800,34 +951,83 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     }
     HT(hipGetLastError());
     if (k > 0) {
-        // ---- K Z and E, windows processed in batches of bounded scratch ----
-        std::vector<int64_t> woff(k + 1, 0);
-        for (int32_t j = 0; j < k; ++j) woff[j + 1] = woff[j] + ws[j];
-        const int64_t budget = std::max<int64_t>(int64_t(48) << 20, *std::max_element(ws.begin(), ws.end()));
-        std::vector<int32_t> cuts{0};
-        for (int32_t j = 0; j < k; ++j)
-            if (woff[j + 1] - woff[cuts.back()] > budget) cuts.push_back(j);
-        cuts.push_back(k);
-        int64_t maxbatch = 0;
-        for (size_t b = 0; b + 1 < cuts.size(); ++b)
-            maxbatch = std::max(maxbatch, woff[cuts[b + 1]] - woff[cuts[b]]);
-        int64_t *woff_d = nullptr, *kzcnt = nullptr, *kzp = nullptr;
-        double *zd = nullptr;
-        int32_t *mk = nullptr;
-        HT(pool.tmp(&woff_d, k + 1));
-        HT(hipMemcpyAsync(woff_d, woff.data(), sizeof(int64_t) * (k + 1), hipMemcpyHostToDevice, s));
-        HT(pool.tmp(&zd, maxbatch));
-        HT(pool.tmp(&mk, maxbatch));
+        // ---- K Z and E, in batches of kBatch vectors; batch groups bound the scratch ----
+        std::vector<int64_t> wl(k);
+        HT(hipMemcpyAsync(wl.data(), wlo, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+        HT(hipStreamSynchronize(s));
+        const int nbat = (k + kBatch - 1) / kBatch;
+        std::vector<KzBatch> bt(nbat);
+        int64_t slices = 0;
+        for (int bi = 0; bi < nbat; ++bi) {
+            KzBatch &B = bt[bi];
+            B.j0 = (int64_t)bi * kBatch;
+            B.ncol = std::min<int64_t>(kBatch, k - B.j0);
+            int64_t lo = INT64_MAX, hi = -1;
+            for (int64_t j = B.j0; j < B.j0 + B.ncol; ++j)
+                if (ws[j] > 0) {
+                    lo = std::min(lo, wl[j]);
+                    hi = std::max(hi, wl[j] + ws[j]);
+                }
+            B.lo = hi > 0 ? lo : 0;
+            B.w = hi > 0 ? hi - lo : 0;
+            B.nslice = std::max<int64_t>(1, (B.w + kSlice - 1) / kSlice);
+            B.slice0 = slices;
+            slices += B.nslice;
+        }
+        // group consecutive batches so that a group's scratch stays under the budget
+        const int64_t per_entry = 2 * kBatch * sizeof(double) + 2 * sizeof(uint32_t);
+        const int64_t budget = std::max<int64_t>(int64_t(1) << 30, 0);
+        std::vector<int> gcut{0};
+        int64_t acc_w = 0, max_group_w = 0;
+        for (int bi = 0; bi < nbat; ++bi) {
+            if (acc_w > 0 && (acc_w + bt[bi].w) * per_entry > budget) {
+                gcut.push_back(bi);
+                acc_w = 0;
+            }
+            bt[bi].off = acc_w;
+            acc_w += bt[bi].w;
+            max_group_w = std::max(max_group_w, acc_w);
+        }
+        gcut.push_back(nbat);
+        KzBatch *bt_d = nullptr;
+        int32_t *scnt = nullptr, *soff = nullptr;
+        int64_t *kzcnt = nullptr, *kzp = nullptr;
+        double *zd = nullptr, *kd = nullptr;
+        uint32_t *mk = nullptr, *rbits = nullptr;
+        HT(pool.tmp(&bt_d, nbat));
+        HT(hipMemcpyAsync(bt_d, bt.data(), sizeof(KzBatch) * nbat, hipMemcpyHostToDevice, s));
+        HT(pool.tmp(&scnt, slices * kBatch));
+        HT(pool.tmp(&soff, slices * kBatch));
         HT(pool.tmp(&kzcnt, k));
         HT(pool.tmp(&kzp, k + 1));
-        for (size_t b = 0; b + 1 < cuts.size(); ++b)
-            hipLaunchKernelGGL(k_kz_count, dim3(cuts[b + 1] - cuts[b]), dim3(256), 0, s, cuts[b], cuts[b + 1], ztp,
-                               zti, ztv, kp, kc, wlo, wsize, woff_d, zd, mk, kzcnt);
+        HT(pool.tmp(&zd, max_group_w * kBatch));
+        HT(pool.tmp(&kd, max_group_w * kBatch));
+        HT(pool.tmp(&mk, max_group_w));
+        HT(pool.tmp(&rbits, max_group_w));
+        auto max_slices = [&](int g0, int g1) {
+            int64_t m = 1;
+            for (int bi = g0; bi < g1; ++bi) m = std::max(m, bt[bi].nslice);
+            return (int)m;
+        };
+        auto prepare = [&](int g0, int g1) {
+            const dim3 gs(max_slices(g0, g1), g1 - g0);
+            hipLaunchKernelGGL(k_kzb_init, gs, dim3(256), 0, s, bt_d + g0, zd, kd, mk, rbits);
+            hipLaunchKernelGGL(k_kzb_scatter, dim3(kBatch, g1 - g0), dim3(256), 0, s, bt_d + g0, ztp, zti, ztv, zd,
+                               rbits);
+            hipLaunchKernelGGL(k_kzb_mark, gs, dim3(256), 0, s, bt_d + g0, kp, kc, rbits, mk);
+        };
+        for (size_t g = 0; g + 1 < gcut.size(); ++g) {
+            prepare(gcut[g], gcut[g + 1]);
+            hipLaunchKernelGGL(k_kzb_count, dim3(max_slices(gcut[g], gcut[g + 1]), gcut[g + 1] - gcut[g]), dim3(256),
+                               0, s, bt_d + gcut[g], mk, scnt);
+        }
+        hipLaunchKernelGGL(k_kzb_offsets, dim3(nbat), dim3(kBatch), 0, s, bt_d, nbat, scnt, soff, kzcnt);
         HT(scan(s, kzcnt, k, kzp, part));
         int64_t nkz = 0;
         HT(hipMemcpyAsync(&nkz, kzp + k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
+        if (fl[3] != INT32_MAX) return DPCG_ENOTSYM;
         if (fl[1] != INT32_MAX) {
             *bad = fl[1];
             return DPCG_EBLOCK_NOT_SPD;
@@ -841,10 +1041,15 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
         double *eraw = nullptr, *ga = nullptr, *diag0 = nullptr, *pv = nullptr;
         HT(pool.tmp(&eraw, ld * ld));
         HT(hipMemsetAsync(eraw, 0, sizeof(double) * ld * ld, s));
-        for (size_t b = 0; b + 1 < cuts.size(); ++b)
-            hipLaunchKernelGGL(k_kz_fill, dim3(cuts[b + 1] - cuts[b]), dim3(256), 0, s, cuts[b], cuts[b + 1], k, ztp,
-                               zti, ztv, kp, kc, kv, wlo, wsize, woff_d, zd, mk, kzp, c->kzt_idx, c->kzt_val, eraw,
-                               ld);
+        for (size_t g = 0; g + 1 < gcut.size(); ++g) {
+            const int g0 = gcut[g], g1 = gcut[g + 1];
+            if (gcut.size() > 2) prepare(g0, g1);  // one group: the count pass left it ready
+            hipLaunchKernelGGL(k_kzb_values, dim3(max_slices(g0, g1), g1 - g0), dim3(256), 0, s, bt_d + g0, kp, kc,
+                               kv, zd, mk, soff, kzp, c->kzt_idx, c->kzt_val, kd);
+            hipLaunchKernelGGL(k_kzb_erows, dim3((k + 255) / 256, g1 - g0), dim3(256), 0, s, bt_d + g0, k, ztp, zti,
+                               ztv, kd, eraw, ld);
+        }
+        HT(hipGetLastError());
         // ---- E^-1 ----
         HT(pool.tmp(&ga, ld * ld));
         HT(keep(c, &c->einv, ld * ld));
@@ -877,6 +1082,7 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     } else {
         HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
+        if (fl[3] != INT32_MAX) return DPCG_ENOTSYM;
         if (fl[1] != INT32_MAX) {
             *bad = fl[1];
             return DPCG_EBLOCK_NOT_SPD;
