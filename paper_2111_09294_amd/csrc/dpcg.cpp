@@ -117,14 +117,19 @@ int round_grid(int want) {
 
 void choose_shapes(dpcg_ctx *c) {
     const double avg = c->nb ? (double)c->nnzb / c->nb : 1.0;
-    int g = 16;
+    // lanes per block row: one pass over a typical row (measured on gfx950: 32 lanes for
+    // rows of ~30 blocks beat 16 lanes with two passes)
+    int g = 32;
     if (avg <= 6) g = 4;
-    else if (avg <= 14) g = 8;
-    else if (avg > 48) g = 32;
+    else if (avg <= 12) g = 8;
+    else if (avg <= 20) g = 16;
     c->spmv.group = g;
-    const int rows_per_step = 4 * 64 / g;
+    const int rows_per_step = 4 * 64 / g;  // 4 waves per SpMV workgroup
     c->spmv.steps = (int)((c->nb + rows_per_step - 1) / rows_per_step);
-    c->spmv.nwg = round_grid(std::min(c->spmv.steps, 2048));
+    // one step per workgroup, rounded up to a multiple of 8 (XCD-aware mapping); the
+    // extra workgroups find an empty step range
+    c->spmv.nwg = std::min(c->spmv.steps, 16384);
+    if (c->spmv.nwg >= 8) c->spmv.nwg = (c->spmv.nwg + 7) & ~7;
     c->vec_nwg = round_grid((int)std::min<int64_t>((c->n + kThreads - 1) / kThreads, 1024));
     c->bj_nwg = round_grid(std::min(c->bj_ntiles, 1024));
 }
@@ -208,6 +213,7 @@ int enqueue_start(dpcg_ctx *c, Workspace &w, const double *f, double *u, bool gu
     LAUNCH(launch_restrict(c, w.r, w.y, w.g, &w, 1, c->spmv.nwg, 0, max_iter, record));
     LAUNCH(launch_coarse(c, w.g, w.delta, &w));
     LAUNCH(launch_prolong(c, w.y, w.delta, w.z, &w, w.r, 0));
+    LAUNCH(launch_beta(c, w));
     return DPCG_OK;
 }
 
@@ -252,6 +258,7 @@ int enqueue_iteration(dpcg_ctx *c, Workspace &w, double *u, int max_iter, int re
     LAUNCH(launch_restrict(c, w.r, w.y, w.g, &w, 1, c->bj_nwg, 1, max_iter, record));
     LAUNCH(launch_coarse(c, w.g, w.delta, &w));
     LAUNCH(launch_prolong(c, w.y, w.delta, w.z, &w, w.r, 1));
+    LAUNCH(launch_beta(c, w));
     return DPCG_OK;
 }
 
@@ -285,7 +292,6 @@ int solve_impl(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol
     State init{};
     init.flag = kRunning;
     init.thr = tol * fnorm;
-    init.rho_old = 1.0;
     *w.snap = init;
     HIP_TRY(hipMemcpyAsync(w.st, w.snap, sizeof(State), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));

@@ -2,8 +2,11 @@
 //
 // Device layout (all in HBM, FP64 values, int32 indices):
 //   K   block-CSR over DoF triplets: brow_ptr[nb+1], bcol[nnzb], and the nine
-//       entries of each 3x3 block stored as nine planes, bval[e*nnzb + blk] with
-//       e = 3*i + j, so lanes working on consecutive blocks read consecutive words.
+//       entries of each 3x3 block stored row by row as nine planes: the values of
+//       block row R (blocks beg..end-1, m = end - beg) occupy bval[9 beg, 9 end) and
+//       entry e = 3*i + j of block b sits at bval[9 beg + e*m + (b - beg)], so the
+//       lanes working on consecutive blocks of a row read consecutive words and a
+//       row's values form one contiguous stretch.
 //   M^-1 explicit inverse of each block-Jacobi block, row-major, concatenated;
 //       per DoF d: bj_rowoff[d] = offset of d's row, bj_meta[d] = size<<8 | (d -
 //       block start).  DoF range of workgroup w of the update kernel:
@@ -33,8 +36,9 @@ struct State {
     int32_t iters_done;  // final iteration count, set together with the flag
     int32_t bad;         // iteration of a breakdown
     double thr;          // tol * ||f||_2
-    double rho_new;      // rho_i = r_i^T z_i, written by the SpMV kernel
-    double rho_old;      // rho_{i-1}, written by the update kernel
+    double rho_cur;      // rho_i = r_i^T z_i of the iteration in flight (k_beta)
+    double alpha;        // alpha_i (k_alpha)
+    double beta;         // beta_{i-1} (k_beta; 0 at i = 0)
     double rr;           // ||r||^2 of the last check
     double aux;          // scratch scalar for one-off reductions
     int32_t nonfinite;   // set by the input check
@@ -109,6 +113,7 @@ hipError_t launch_spmv_residual(const dpcg_ctx *c, const double *x, const double
                                 double *part, Workspace &w, int check);
 hipError_t launch_spmv_p(const dpcg_ctx *c, Workspace &w);
 hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w);
+hipError_t launch_beta(const dpcg_ctx *c, Workspace &w);
 hipError_t launch_bj(const dpcg_ctx *c, const double *r, double *y, Workspace *w);
 hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, double *g, Workspace *w,
                            int check, int n_parts, int iter_offset, int max_iter, int record);

@@ -41,6 +41,27 @@ __device__ __forceinline__ double reduce_parts(const double *parts, int n, doubl
     return block_sum(s, lds);
 }
 
+// Workgroup sum over NW waves (lds >= NW entries); every thread receives the same value.
+template <int NW>
+__device__ __forceinline__ double block_sum_n(double v, double *lds) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; w += 2) s += lds[w] + lds[w + 1];
+    return s;
+}
+
+template <int NW>
+__device__ __forceinline__ double reduce_parts_n(const double *parts, int n, double *lds) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += NW * 64) s += parts[i];
+    return block_sum_n<NW>(s, lds);
+}
+
 __device__ __forceinline__ bool leader() { return blockIdx.x == 0 && threadIdx.x == 0; }
 
 // The state flag as seen by the whole workgroup: one thread reads it and the value is
@@ -88,10 +109,12 @@ __device__ __forceinline__ void block_row(int row, int lg, const int32_t *__rest
     a0 = a1 = a2 = 0.0;
     if (row >= 0) {
         const int beg = brow_ptr[row], end = brow_ptr[row + 1];
+        const int64_t m = end - beg;
+        const double *rv = bval + 9 * (int64_t)beg - beg;  // plane e of block b: rv[e * m + b]
         for (int b = beg + lg; b < end; b += G) {
-            const double v0 = bval[b], v1 = bval[nnzb + b], v2 = bval[2 * nnzb + b];
-            const double v3 = bval[3 * nnzb + b], v4 = bval[4 * nnzb + b], v5 = bval[5 * nnzb + b];
-            const double v6 = bval[6 * nnzb + b], v7 = bval[7 * nnzb + b], v8 = bval[8 * nnzb + b];
+            const double v0 = rv[b], v1 = rv[m + b], v2 = rv[2 * m + b];
+            const double v3 = rv[3 * m + b], v4 = rv[4 * m + b], v5 = rv[5 * m + b];
+            const double v6 = rv[6 * m + b], v7 = rv[7 * m + b], v8 = rv[8 * m + b];
             const int64_t c = 3 * (int64_t)bcol[b];
             const double x0 = xl(c), x1 = xl(c + 1), x2 = xl(c + 2);
             a0 = fma(v0, x0, fma(v1, x1, fma(v2, x2, a0)));
@@ -113,12 +136,18 @@ struct SpmvShape {
     int32_t nwg;
 };
 
+// The SpMV kernels run kSpmvWaves waves per workgroup; every wave handles 64 / G rows
+// per step, and a workgroup normally covers exactly one step, so each wave issues all of
+// its loads at once and many small workgroups in flight hide the index -> gather latency.
+constexpr int kSpmvWaves = 4;
+constexpr int kSpmvThreads = 64 * kSpmvWaves;
+
 // Row handled by this lane group at step s, or -1.
 template <int G>
 __device__ __forceinline__ int step_row(int s, int nb) {
     constexpr int kGroupsPerWave = 64 / G;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row = (s * 4 + wv) * kGroupsPerWave + lane / G;
+    const int row = (s * kSpmvWaves + wv) * kGroupsPerWave + lane / G;
     return row < nb ? row : -1;
 }
 
@@ -128,12 +157,12 @@ __device__ __forceinline__ double pick3(int lg, double a0, double a1, double a2)
 
 // MODE 0: y = K x.   MODE 1: r = f - K x and ||r||^2 partials.
 template <int G, int MODE>
-__global__ __launch_bounds__(kThreads) void k_spmv(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
                                                    const int32_t *__restrict__ bcol,
                                                    const double *__restrict__ bval, int64_t nnzb,
                                                    const double *__restrict__ x, const double *__restrict__ f,
                                                    double *__restrict__ y, double *__restrict__ part) {
-    __shared__ double lds[4];
+    __shared__ double lds[kSpmvWaves];
     const int w = xcd_remap(blockIdx.x, sh.nwg);
     const int s0 = (int)(((int64_t)w * sh.steps) / sh.nwg), s1 = (int)(((int64_t)(w + 1) * sh.steps) / sh.nwg);
     const int lg = threadIdx.x % G;
@@ -156,38 +185,29 @@ __global__ __launch_bounds__(kThreads) void k_spmv(SpmvShape sh, const int32_t *
         }
     }
     if (MODE == 1) {
-        const double t = block_sum(acc, lds);
+        const double t = block_sum_n<kSpmvWaves>(acc, lds);
         if (threadIdx.x == 0) part[blockIdx.x] = t;
     }
 }
 
 // Search direction and matrix product of Algorithm 1 for iteration i = st->iter:
-// p_i = z_i + beta_{i-1} p_{i-1} (p_0 = z_0), q = K p_i, and partials of p_i^T q.
+// p_i = z_i + beta_{i-1} p_{i-1} (p_0 = z_0; beta from the state), q = K p_i, and
+// partials of p_i^T q.  Only the single-workgroup kernels change the flag, so it is
+// stable while this kernel runs.
 template <int G>
-__global__ __launch_bounds__(kThreads) void k_spmv_p(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
-                                                     const int32_t *__restrict__ bcol,
-                                                     const double *__restrict__ bval, int64_t nnzb,
-                                                     const double *__restrict__ z, double *p0, double *p1,
-                                                     double *__restrict__ q, const double *__restrict__ part_rho,
-                                                     int n_rho, double *__restrict__ part_pq, State *st) {
-    __shared__ double lds[4];
-    if (wg_flag(st) != kRunning) return;
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv_p(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
+                                                         const int32_t *__restrict__ bcol,
+                                                         const double *__restrict__ bval, int64_t nnzb,
+                                                         const double *__restrict__ z, double *p0, double *p1,
+                                                         double *__restrict__ q, double *__restrict__ part_pq,
+                                                         const State *st) {
+    __shared__ double lds[kSpmvWaves];
+    if (st->flag != kRunning) return;
     const int it = st->iter;
-    const double rho = reduce_parts(part_rho, n_rho, lds);
-    if (it > 0 && !isfinite(rho)) {
-        if (leader()) {
-            st->flag = kBreakdown;
-            st->bad = it - 1;
-            st->iters_done = it;
-        }
-        return;
-    }
-    const bool first = (it == 0);
-    const double beta = first ? 0.0 : rho / st->rho_old;
-    if (leader()) st->rho_new = rho;
+    const double beta = st->beta;
     double *pout = (it & 1) ? p1 : p0;
     const double *pprev = (it & 1) ? p0 : p1;
-    XDirection xl{z, pprev, beta, first};
+    XDirection xl{z, pprev, beta, it == 0};
     const int w = xcd_remap(blockIdx.x, sh.nwg);
     const int s0 = (int)(((int64_t)w * sh.steps) / sh.nwg), s1 = (int)(((int64_t)(w + 1) * sh.steps) / sh.nwg);
     const int lg = threadIdx.x % G;
@@ -205,8 +225,44 @@ __global__ __launch_bounds__(kThreads) void k_spmv_p(SpmvShape sh, const int32_t
             acc = fma(pi, v, acc);
         }
     }
-    const double t = block_sum(acc, lds);
+    const double t = block_sum_n<kSpmvWaves>(acc, lds);
     if (threadIdx.x == 0) part_pq[blockIdx.x] = t;
+}
+
+// alpha_i = rho_i / p_i^T q_i from the SpMV partials (one workgroup, fixed order).
+__global__ __launch_bounds__(1024) void k_alpha(const double *__restrict__ part_pq, int n, State *st) {
+    __shared__ double lds[16];
+    if (st->flag != kRunning) return;
+    const double pq = reduce_parts_n<16>(part_pq, n, lds);
+    if (threadIdx.x == 0) {
+        const double alpha = st->rho_cur / pq;
+        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(alpha)) {
+            st->flag = kBreakdown;
+            st->bad = st->iter;
+            st->iters_done = st->iter;
+        } else {
+            st->alpha = alpha;
+        }
+    }
+}
+
+// rho_i = r_i^T z_i from the prolongation partials and beta_{i-1} = rho_i / rho_{i-1}
+// (beta unused at i = 0); one workgroup, fixed order.
+__global__ __launch_bounds__(1024) void k_beta(const double *__restrict__ part_rho, int n, State *st) {
+    __shared__ double lds[16];
+    if (st->flag != kRunning) return;
+    const double rho = reduce_parts_n<16>(part_rho, n, lds);
+    if (threadIdx.x == 0) {
+        const int it = st->iter;
+        if (it > 0 && !isfinite(rho)) {
+            st->flag = kBreakdown;
+            st->bad = it - 1;
+            st->iters_done = it;
+        } else {
+            st->beta = it > 0 ? rho / st->rho_cur : 0.0;
+            st->rho_cur = rho;
+        }
+    }
 }
 
 // y_d = sum_j Minv_B[d - s_B, j] r_{s_B + j} for the DoFs of this tile (whole blocks).
@@ -228,22 +284,11 @@ __global__ __launch_bounds__(kThreads) void k_update_bj(
     int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start, double *__restrict__ u,
     double *__restrict__ r, double *__restrict__ y, const double *__restrict__ q, const double *p0,
     const double *p1, const double *__restrict__ minv, const int32_t *__restrict__ bj_rowoff,
-    const int32_t *__restrict__ bj_meta, const double *__restrict__ part_pq, int n_pq,
-    double *__restrict__ part_rr, State *st) {
+    const int32_t *__restrict__ bj_meta, double *__restrict__ part_rr, const State *st) {
     __shared__ double lds[4];
     __shared__ double tile[kThreads];
-    if (wg_flag(st) != kRunning) return;
-    const double pq = reduce_parts(part_pq, n_pq, lds);
-    const double alpha = st->rho_new / pq;
-    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(alpha)) {
-        if (leader()) {
-            st->flag = kBreakdown;
-            st->bad = st->iter;
-            st->iters_done = st->iter;
-        }
-        return;
-    }
-    if (leader()) st->rho_old = st->rho_new;
+    if (st->flag != kRunning) return;
+    const double alpha = st->alpha;
     const double *p = (st->iter & 1) ? p1 : p0;
     const int t = threadIdx.x;
     const int w = xcd_remap(blockIdx.x, nwg);
@@ -274,7 +319,7 @@ __global__ __launch_bounds__(kThreads) void k_bj(int32_t ntiles, int32_t nwg, co
                                                  const int32_t *__restrict__ bj_rowoff,
                                                  const int32_t *__restrict__ bj_meta, const State *st) {
     __shared__ double tile[kThreads];
-    if (st && wg_flag(st) != kRunning) return;
+    if (st && st->flag != kRunning) return;
     const int t = threadIdx.x;
     const int w = xcd_remap(blockIdx.x, nwg);
     const int t0 = (int)(((int64_t)w * ntiles) / nwg), t1 = (int)(((int64_t)(w + 1) * ntiles) / nwg);
@@ -320,12 +365,31 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
         }
     }
     for (int j = blockIdx.x; j < k; j += gridDim.x) {
-        double s = 0.0;
-        for (int e = zt_ptr[j] + threadIdx.x; e < zt_ptr[j + 1]; e += kThreads) s = fma(zt_val[e], a[zt_idx[e]], s);
-        if (b)
-            for (int e = kzt_ptr[j] + threadIdx.x; e < kzt_ptr[j + 1]; e += kThreads)
-                s = fma(-kzt_val[e], b[kzt_idx[e]], s);
-        s = block_sum(s, lds);
+        // four independent chains per thread keep more gathers in flight
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        {
+            const int e1 = zt_ptr[j + 1];
+            int e = zt_ptr[j] + threadIdx.x;
+            for (; e + 3 * kThreads < e1; e += 4 * kThreads) {
+                s0 = fma(zt_val[e], a[zt_idx[e]], s0);
+                s1 = fma(zt_val[e + kThreads], a[zt_idx[e + kThreads]], s1);
+                s2 = fma(zt_val[e + 2 * kThreads], a[zt_idx[e + 2 * kThreads]], s2);
+                s3 = fma(zt_val[e + 3 * kThreads], a[zt_idx[e + 3 * kThreads]], s3);
+            }
+            for (; e < e1; e += kThreads) s0 = fma(zt_val[e], a[zt_idx[e]], s0);
+        }
+        if (b) {
+            const int e1 = kzt_ptr[j + 1];
+            int e = kzt_ptr[j] + threadIdx.x;
+            for (; e + 3 * kThreads < e1; e += 4 * kThreads) {
+                s0 = fma(-kzt_val[e], b[kzt_idx[e]], s0);
+                s1 = fma(-kzt_val[e + kThreads], b[kzt_idx[e + kThreads]], s1);
+                s2 = fma(-kzt_val[e + 2 * kThreads], b[kzt_idx[e + 2 * kThreads]], s2);
+                s3 = fma(-kzt_val[e + 3 * kThreads], b[kzt_idx[e + 3 * kThreads]], s3);
+            }
+            for (; e < e1; e += kThreads) s0 = fma(-kzt_val[e], b[kzt_idx[e]], s0);
+        }
+        const double s = block_sum((s0 + s1) + (s2 + s3), lds);
         if (threadIdx.x == 0) g[j] = s;
     }
 }
@@ -334,14 +398,21 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
 __global__ __launch_bounds__(kThreads) void k_coarse(int32_t k, int64_t ld, const double *__restrict__ einv,
                                                      const double *__restrict__ g, double *__restrict__ delta,
                                                      const State *st) {
-    if (st && wg_flag(st) != kRunning) return;
+    if (st && st->flag != kRunning) return;
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (row >= k) return;
     const double *e = einv + (int64_t)row * ld;
-    double s = 0.0;
-    for (int l = lane; l < k; l += 64) s = fma(e[l], g[l], s);
-    s = wave_sum(s);
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int l = lane;
+    for (; l + 192 < k; l += 256) {
+        s0 = fma(e[l], g[l], s0);
+        s1 = fma(e[l + 64], g[l + 64], s1);
+        s2 = fma(e[l + 128], g[l + 128], s2);
+        s3 = fma(e[l + 192], g[l + 192], s3);
+    }
+    for (; l < k; l += 64) s0 = fma(e[l], g[l], s0);
+    const double s = wave_sum((s0 + s1) + (s2 + s3));
     if (lane == 0) delta[row] = s;
 }
 
@@ -354,7 +425,7 @@ __global__ __launch_bounds__(kThreads) void k_prolong(int64_t n, int32_t nwg, co
                                                       const double *__restrict__ rdot, double *__restrict__ part,
                                                       State *st, int advance) {
     __shared__ double lds[4];
-    if (st && wg_flag(st) != kRunning) return;
+    if (st && st->flag != kRunning) return;
     const int w = xcd_remap(blockIdx.x, nwg);
     const int64_t per = (n + nwg - 1) / nwg;
     const int64_t d0 = (int64_t)w * per, d1 = min(n, d0 + per);
@@ -411,15 +482,15 @@ __global__ __launch_bounds__(kThreads) void k_reduce_aux(const double *__restric
 template <int G>
 hipError_t spmv_p_g(const dpcg_ctx *c, Workspace &w) {
     SpmvShape sh{c->nb, c->spmv.steps, c->spmv.nwg};
-    hipLaunchKernelGGL(k_spmv_p<G>, dim3(c->spmv.nwg), dim3(kThreads), 0, c->stream, sh, c->brow_ptr, c->bcol,
-                       c->bval, c->nnzb, w.z, w.p[0], w.p[1], w.q, w.part_c, c->vec_nwg, w.part_a, w.st);
+    hipLaunchKernelGGL(k_spmv_p<G>, dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, sh, c->brow_ptr, c->bcol,
+                       c->bval, c->nnzb, w.z, w.p[0], w.p[1], w.q, w.part_a, w.st);
     return hipGetLastError();
 }
 
 template <int G, int MODE>
 hipError_t spmv_g(const dpcg_ctx *c, const double *x, const double *f, double *y, double *part) {
     SpmvShape sh{c->nb, c->spmv.steps, c->spmv.nwg};
-    hipLaunchKernelGGL((k_spmv<G, MODE>), dim3(c->spmv.nwg), dim3(kThreads), 0, c->stream, sh, c->brow_ptr,
+    hipLaunchKernelGGL((k_spmv<G, MODE>), dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, sh, c->brow_ptr,
                        c->bcol, c->bval, c->nnzb, x, f, y, part);
     return hipGetLastError();
 }
@@ -457,9 +528,17 @@ hipError_t launch_spmv_residual(const dpcg_ctx *c, const double *x, const double
 }
 
 hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w) {
+    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1024), 0, c->stream, w.part_a, c->spmv.nwg, w.st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_update_bj, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles,
                        c->bj_nwg, c->bj_wg_start, u, w.r, w.y, w.q, w.p[0], w.p[1], c->minv, c->bj_rowoff,
-                       c->bj_meta, w.part_a, c->spmv.nwg, w.part_b, w.st);
+                       c->bj_meta, w.part_b, w.st);
+    return hipGetLastError();
+}
+
+hipError_t launch_beta(const dpcg_ctx *c, Workspace &w) {
+    hipLaunchKernelGGL(k_beta, dim3(1), dim3(1024), 0, c->stream, w.part_c, c->vec_nwg, w.st);
     return hipGetLastError();
 }
 

@@ -110,23 +110,21 @@ __global__ void k_to_i32(const int64_t *__restrict__ a, int64_t n, int32_t *__re
 // ---------------------------------------------------------------- validation
 // flags[0]: first invalid row of K (or INT_MAX), flags[1]: first invalid row of Z,
 // flags[2]: first invalid block, flags[3]: first asymmetric row.
-__global__ void k_check_csr(int64_t rows, int64_t cols, const int64_t *__restrict__ ptr,
-                            const int32_t *__restrict__ idx, const double *__restrict__ val, int64_t nnz,
-                            int *flag) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows; i += (int64_t)gridDim.x * blockDim.x) {
+// One wave per row: row pointer monotone and in range, columns strictly increasing and
+// in range, values finite.
+__global__ __launch_bounds__(256) void k_check_csr(int64_t rows, int64_t cols, const int64_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ idx, const double *__restrict__ val,
+                                                   int64_t nnz, int *flag) {
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * 4;
+    for (int64_t i = blockIdx.x * 4ll + (threadIdx.x >> 6); i < rows; i += waves) {
         const int64_t a = ptr[i], b = ptr[i + 1];
         bool ok = (i != 0 || a == 0) && a >= 0 && a <= b && b <= nnz;
-        if (ok) {
-            int64_t prev = -1;
-            for (int64_t e = a; e < b; ++e) {
+        if (ok)
+            for (int64_t e = a + lane; e < b; e += 64) {
                 const int64_t c = idx[e];
-                if (c <= prev || c >= cols || !isfinite(val[e])) {
-                    ok = false;
-                    break;
-                }
-                prev = c;
+                if (c < 0 || c >= cols || !isfinite(val[e]) || (e + 1 < b && idx[e + 1] <= c)) ok = false;
             }
-        }
         if (!ok) atomicMin(flag, (int)i);
     }
 }
@@ -154,34 +152,37 @@ __global__ __launch_bounds__(256) void k_maxabs_part(const double *__restrict__ 
 
 // |K_ij - K_ji| <= 1e-12 max|K| over the packed 3x3 blocks: block (R, C) against the
 // transpose of block (C, R), found by binary search in block row C (a missing block is 0).
+// One thread per block; its block row R is found by binary search in the row pointer.
 __global__ void k_check_sym(int32_t nb, const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol,
                             const double *__restrict__ bval, int64_t nnzb, const double *__restrict__ maxpart,
                             int nmax, int *flag) {
     double mx = 0.0;
     for (int i = 0; i < nmax; ++i) mx = fmax(mx, maxpart[i]);
     const double tol = 1e-12 * mx;
-    for (int R = blockIdx.x * blockDim.x + threadIdx.x; R < nb; R += gridDim.x * blockDim.x) {
-        for (int64_t b = bptr[R]; b < bptr[R + 1]; ++b) {
-            const int32_t C = bcol[b];
-            int64_t lo = bptr[C], hi = bptr[C + 1];
-            while (lo < hi) {
-                const int64_t mid = (lo + hi) >> 1;
-                if (bcol[mid] < R) lo = mid + 1;
-                else hi = mid;
-            }
-            const bool found = lo < bptr[C + 1] && bcol[lo] == R;
-            bool ok = true;
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) {
-                    const double v = bval[(int64_t)(3 * i + j) * nnzb + b];
-                    const double m = found ? bval[(int64_t)(3 * j + i) * nnzb + lo] : 0.0;
-                    ok = ok && fabs(v - m) <= tol;
-                }
-            if (!ok) {
-                atomicMin(flag + 3, 3 * R);
-                break;
-            }
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nnzb; b += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = nb;  // last R with bptr[R] <= b
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (bptr[mid] <= b) lo = mid;
+            else hi = mid;
         }
+        const int32_t R = lo, C = bcol[b];
+        int64_t l = bptr[C], h = bptr[C + 1];
+        while (l < h) {
+            const int64_t mid = (l + h) >> 1;
+            if (bcol[mid] < R) l = mid + 1;
+            else h = mid;
+        }
+        const bool found = l < bptr[C + 1] && bcol[l] == R;
+        const int64_t bR = bptr[R], mR = bptr[R + 1] - bR, bC = bptr[C], mC = bptr[C + 1] - bC;
+        bool ok = true;
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const double v = bval[9 * bR + (int64_t)(3 * i + j) * mR + (b - bR)];
+                const double m = found ? bval[9 * bC + (int64_t)(3 * j + i) * mC + (l - bC)] : 0.0;
+                ok = ok && fabs(v - m) <= tol;
+            }
+        if (!ok) atomicMin(flag + 3, 3 * R);
     }
 }
 
@@ -198,6 +199,7 @@ __global__ void k_bsr(int32_t nb, const int64_t *__restrict__ ptr, const int32_t
             e[i] = ptr[3 * (int64_t)R + i + 1];
         }
         int64_t pos = FILL ? bptr[R] : 0;
+        const int64_t beg = pos, m = FILL ? (int64_t)bptr[R + 1] - bptr[R] : 0;
         int64_t count = 0;
         while (true) {
             int32_t cur = INT32_MAX;
@@ -207,7 +209,7 @@ __global__ void k_bsr(int32_t nb, const int64_t *__restrict__ ptr, const int32_t
             if (FILL) bcol[pos] = cur;
             for (int i = 0; i < 3; ++i)
                 while (h[i] < e[i] && idx[h[i]] / 3 == cur) {
-                    if (FILL) bval[(int64_t)(3 * i + idx[h[i]] % 3) * nnzb + pos] = val[h[i]];
+                    if (FILL) bval[9 * beg + (int64_t)(3 * i + idx[h[i]] % 3) * m + (pos - beg)] = val[h[i]];
                     ++h[i];
                 }
             ++pos;
@@ -593,7 +595,8 @@ __global__ __launch_bounds__(256) void k_kzb_values(const KzBatch *__restrict__ 
 __global__ __launch_bounds__(256) void k_kzb_erows(const KzBatch *__restrict__ bt, int32_t k,
                                                    const int64_t *__restrict__ ztp, const int32_t *__restrict__ zti,
                                                    const double *__restrict__ ztv, const double *__restrict__ kd,
-                                                   double *__restrict__ eraw, int64_t ld) {
+                                                   const uint32_t *__restrict__ mk, double *__restrict__ eraw,
+                                                   int64_t ld) {
     const KzBatch B = bt[blockIdx.y];
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= k || B.w == 0) return;
@@ -618,8 +621,10 @@ __global__ __launch_bounds__(256) void k_kzb_erows(const KzBatch *__restrict__ b
     double acc[kBatch];
     for (int b = 0; b < kBatch; ++b) acc[b] = 0.0;
     for (int64_t q = a; q < e; ++q) {
+        const int64_t t = B.off + (int64_t)zti[q] - B.lo;
+        if (!mk[t]) continue;  // (K z_j)_t is structurally zero for every vector of the batch
         const double z = ztv[q];
-        const double *kdr = kd + (B.off + (int64_t)zti[q] - B.lo) * kBatch;
+        const double *kdr = kd + t * kBatch;
         for (int b = 0; b < kBatch; ++b) acc[b] = fma(z, kdr[b], acc[b]);
     }
     for (int b = 0; b < kBatch; ++b)
@@ -843,9 +848,9 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(pool.tmp(&flags, 4));
     const int init_flags[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
     HT(hipMemcpyAsync(flags, init_flags, sizeof(init_flags), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n)), dim3(256), 0, s, n, n, kp, kc, kv, nnz, flags);
-    if (k > 0) hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n)), dim3(256), 0, s, n, (int64_t)k, zp, zc, zv, nnz_z,
-                                  flags + 1);
+    hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, 4)), dim3(256), 0, s, n, n, kp, kc, kv, nnz, flags);
+    if (k > 0) hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, 4)), dim3(256), 0, s, n, (int64_t)k, zp, zc, zv,
+                                  nnz_z, flags + 1);
     hipLaunchKernelGGL(k_check_blocks, dim3(grid_for(nblocks)), dim3(256), 0, s, nblocks, bp, n, flags + 2);
     HT(hipGetLastError());
     int fl[4];
@@ -926,8 +931,8 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(hipMemsetAsync(c->bval, 0, sizeof(double) * 9 * (size_t)nnzb, s));
     hipLaunchKernelGGL((k_bsr<true>), dim3(grid_for(nb)), dim3(256), 0, s, nb, kp, kc, kv, nullptr, c->brow_ptr,
                        c->bcol, c->bval, nnzb);
-    hipLaunchKernelGGL(k_check_sym, dim3(grid_for(nb)), dim3(256), 0, s, nb, c->brow_ptr, c->bcol, c->bval, nnzb,
-                       maxpart, nmaxpart, flags);
+    hipLaunchKernelGGL(k_check_sym, dim3(grid_for(nnzb, 256, 16384)), dim3(256), 0, s, nb, c->brow_ptr, c->bcol,
+                       c->bval, nnzb, maxpart, nmaxpart, flags);
     HT(keep(c, &c->minv, tot[1]));
     HT(keep(c, &c->bj_rowoff, n));
     HT(keep(c, &c->bj_meta, n));
@@ -1047,7 +1052,7 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
             hipLaunchKernelGGL(k_kzb_values, dim3(max_slices(g0, g1), g1 - g0), dim3(256), 0, s, bt_d + g0, kp, kc,
                                kv, zd, mk, soff, kzp, c->kzt_idx, c->kzt_val, kd);
             hipLaunchKernelGGL(k_kzb_erows, dim3((k + 255) / 256, g1 - g0), dim3(256), 0, s, bt_d + g0, k, ztp, zti,
-                               ztv, kd, eraw, ld);
+                               ztv, kd, mk, eraw, ld);
         }
         HT(hipGetLastError());
         // ---- E^-1 ----
