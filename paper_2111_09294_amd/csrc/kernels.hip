@@ -333,18 +333,22 @@ __global__ __launch_bounds__(kThreads) void k_bj(int32_t ntiles, int32_t nwg, co
     }
 }
 
-// Convergence test (workgroup 0 only) and g_j = Z^T a - (K Z)^T b, one column per workgroup.
-__global__ __launch_bounds__(kThreads) void k_restrict(
+// Convergence test (workgroup 0 only) and g_j = Z^T a - (K Z)^T b, one column per
+// workgroup of kRestrictThreads threads, four independent chains per thread.
+constexpr int kRestrictWaves = 8;
+constexpr int kRestrictThreads = 64 * kRestrictWaves;
+
+__global__ __launch_bounds__(kRestrictThreads) void k_restrict(
     int32_t k, const int32_t *__restrict__ zt_ptr, const int32_t *__restrict__ zt_idx,
     const double *__restrict__ zt_val, const int32_t *__restrict__ kzt_ptr, const int32_t *__restrict__ kzt_idx,
     const double *__restrict__ kzt_val, const double *__restrict__ a, const double *__restrict__ b,
     double *__restrict__ g, State *st, const double *__restrict__ part_rr, int n_rr, int iter_offset,
     int max_iter, double *__restrict__ hist) {
-    __shared__ double lds[4];
+    __shared__ double lds[kRestrictWaves];
     if (st) {
         if (wg_flag(st) != kRunning) return;
         if (blockIdx.x == 0 && n_rr > 0) {
-            const double rr = reduce_parts(part_rr, n_rr, lds);
+            const double rr = reduce_parts_n<kRestrictWaves>(part_rr, n_rr, lds);
             if (threadIdx.x == 0) {
                 const int done = st->iter + iter_offset;
                 st->rr = rr;
@@ -364,56 +368,54 @@ __global__ __launch_bounds__(kThreads) void k_restrict(
             }
         }
     }
+    constexpr int T = kRestrictThreads;
     for (int j = blockIdx.x; j < k; j += gridDim.x) {
-        // four independent chains per thread keep more gathers in flight
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         {
             const int e1 = zt_ptr[j + 1];
             int e = zt_ptr[j] + threadIdx.x;
-            for (; e + 3 * kThreads < e1; e += 4 * kThreads) {
+            for (; e + 3 * T < e1; e += 4 * T) {
                 s0 = fma(zt_val[e], a[zt_idx[e]], s0);
-                s1 = fma(zt_val[e + kThreads], a[zt_idx[e + kThreads]], s1);
-                s2 = fma(zt_val[e + 2 * kThreads], a[zt_idx[e + 2 * kThreads]], s2);
-                s3 = fma(zt_val[e + 3 * kThreads], a[zt_idx[e + 3 * kThreads]], s3);
+                s1 = fma(zt_val[e + T], a[zt_idx[e + T]], s1);
+                s2 = fma(zt_val[e + 2 * T], a[zt_idx[e + 2 * T]], s2);
+                s3 = fma(zt_val[e + 3 * T], a[zt_idx[e + 3 * T]], s3);
             }
-            for (; e < e1; e += kThreads) s0 = fma(zt_val[e], a[zt_idx[e]], s0);
+            for (; e < e1; e += T) s0 = fma(zt_val[e], a[zt_idx[e]], s0);
         }
         if (b) {
             const int e1 = kzt_ptr[j + 1];
             int e = kzt_ptr[j] + threadIdx.x;
-            for (; e + 3 * kThreads < e1; e += 4 * kThreads) {
+            for (; e + 3 * T < e1; e += 4 * T) {
                 s0 = fma(-kzt_val[e], b[kzt_idx[e]], s0);
-                s1 = fma(-kzt_val[e + kThreads], b[kzt_idx[e + kThreads]], s1);
-                s2 = fma(-kzt_val[e + 2 * kThreads], b[kzt_idx[e + 2 * kThreads]], s2);
-                s3 = fma(-kzt_val[e + 3 * kThreads], b[kzt_idx[e + 3 * kThreads]], s3);
+                s1 = fma(-kzt_val[e + T], b[kzt_idx[e + T]], s1);
+                s2 = fma(-kzt_val[e + 2 * T], b[kzt_idx[e + 2 * T]], s2);
+                s3 = fma(-kzt_val[e + 3 * T], b[kzt_idx[e + 3 * T]], s3);
             }
-            for (; e < e1; e += kThreads) s0 = fma(-kzt_val[e], b[kzt_idx[e]], s0);
+            for (; e < e1; e += T) s0 = fma(-kzt_val[e], b[kzt_idx[e]], s0);
         }
-        const double s = block_sum((s0 + s1) + (s2 + s3), lds);
+        const double s = block_sum_n<kRestrictWaves>((s0 + s1) + (s2 + s3), lds);
         if (threadIdx.x == 0) g[j] = s;
     }
 }
 
-// delta = E^{-1} g: one wave per row of the dense symmetric inverse.
+// delta = E^{-1} g: one workgroup per row of the dense symmetric inverse.
 __global__ __launch_bounds__(kThreads) void k_coarse(int32_t k, int64_t ld, const double *__restrict__ einv,
                                                      const double *__restrict__ g, double *__restrict__ delta,
                                                      const State *st) {
+    __shared__ double lds[4];
     if (st && st->flag != kRunning) return;
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int row = blockIdx.x;
     if (row >= k) return;
     const double *e = einv + (int64_t)row * ld;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int l = lane;
-    for (; l + 192 < k; l += 256) {
+    double s0 = 0.0, s1 = 0.0;
+    int l = threadIdx.x;
+    for (; l + kThreads < k; l += 2 * kThreads) {
         s0 = fma(e[l], g[l], s0);
-        s1 = fma(e[l + 64], g[l + 64], s1);
-        s2 = fma(e[l + 128], g[l + 128], s2);
-        s3 = fma(e[l + 192], g[l + 192], s3);
+        s1 = fma(e[l + kThreads], g[l + kThreads], s1);
     }
-    for (; l < k; l += 64) s0 = fma(e[l], g[l], s0);
-    const double s = wave_sum((s0 + s1) + (s2 + s3));
-    if (lane == 0) delta[row] = s;
+    for (; l < k; l += kThreads) s0 = fma(e[l], g[l], s0);
+    const double s = block_sum(s0 + s1, lds);
+    if (threadIdx.x == 0) delta[row] = s;
 }
 
 // out = base + Z delta; optional partials of rdot^T out; optionally advance the iteration.
@@ -551,7 +553,7 @@ hipError_t launch_bj(const dpcg_ctx *c, const double *r, double *y, Workspace *w
 hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, double *g, Workspace *w,
                            int check, int n_parts, int iter_offset, int max_iter, int record) {
     const int grid = c->k > 0 ? c->k : 1;
-    hipLaunchKernelGGL(k_restrict, dim3(grid), dim3(kThreads), 0, c->stream, c->k, c->zt_ptr, c->zt_idx,
+    hipLaunchKernelGGL(k_restrict, dim3(grid), dim3(kRestrictThreads), 0, c->stream, c->k, c->zt_ptr, c->zt_idx,
                        c->zt_val, c->kzt_ptr, c->kzt_idx, c->kzt_val, a, b, g, w ? w->st : nullptr,
                        w ? w->part_b : nullptr, check ? n_parts : 0, iter_offset, max_iter,
                        (w && record) ? w->hist : nullptr);
@@ -560,7 +562,7 @@ hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, 
 
 hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Workspace *w) {
     if (c->k == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coarse, dim3((c->k + 3) / 4), dim3(kThreads), 0, c->stream, c->k, c->einv_ld, c->einv, g, delta,
+    hipLaunchKernelGGL(k_coarse, dim3(c->k), dim3(kThreads), 0, c->stream, c->k, c->einv_ld, c->einv, g, delta,
                        w ? w->st : nullptr);
     return hipGetLastError();
 }

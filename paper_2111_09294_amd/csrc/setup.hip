@@ -187,35 +187,95 @@ __global__ void k_check_sym(int32_t nb, const int32_t *__restrict__ bptr, const 
 }
 
 // ---------------------------------------------------------------- block-CSR over DoF triplets
-// Block columns of block row R: the union of col/3 over scalar rows 3R..3R+2.
+// Block columns of block row R: the union of col/3 over scalar rows 3R..3R+2.  One
+// wave per block row.  When the three rows have the same set of block columns (a K
+// assembled from 3x3 nodal blocks always does), a block's position is the rank of its
+// block column among the row's distinct block columns, found with ballots; otherwise
+// lane 0 merges the three rows.
+constexpr int kMaxDistinct = 256;
+
+__device__ __forceinline__ void wave_sync() { __builtin_amdgcn_wave_barrier(); }
+
+// distinct block columns of one scalar row, ranks from ballots; returns the count
+__device__ int row_distinct(int64_t a, int64_t e, const int32_t *__restrict__ idx, int32_t *dcol) {
+    const int lane = threadIdx.x & 63;
+    int count = 0;
+    for (int64_t base = a; base < e; base += 64) {
+        const int64_t p = base + lane;
+        const bool in = p < e;
+        const int32_t c = in ? idx[p] / 3 : -1;
+        const bool first = in && (p == a || idx[p - 1] / 3 != c);
+        const unsigned long long bal = __ballot(first);
+        const int rank = count + __popcll(bal & ((1ull << lane) - 1ull));
+        if (first && rank < kMaxDistinct) dcol[rank] = c;
+        count += __popcll(bal);
+    }
+    return count;
+}
+
 template <bool FILL>
-__global__ void k_bsr(int32_t nb, const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                      const double *__restrict__ val, int64_t *__restrict__ cnt, const int32_t *__restrict__ bptr,
-                      int32_t *__restrict__ bcol, double *__restrict__ bval, int64_t nnzb) {
-    for (int R = blockIdx.x * blockDim.x + threadIdx.x; R < nb; R += gridDim.x * blockDim.x) {
-        int64_t h[3], e[3];
+__global__ __launch_bounds__(256) void k_bsr(int32_t nb, const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                             const double *__restrict__ val, int64_t *__restrict__ cnt,
+                                             const int32_t *__restrict__ bptr, int32_t *__restrict__ bcol,
+                                             double *__restrict__ bval) {
+    __shared__ int32_t dcol_s[4][3][kMaxDistinct];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t R = blockIdx.x * 4ll + wv; R < nb; R += (int64_t)gridDim.x * 4) {
+        int64_t a[3], e[3];
+        int dn[3];
         for (int i = 0; i < 3; ++i) {
-            h[i] = ptr[3 * (int64_t)R + i];
-            e[i] = ptr[3 * (int64_t)R + i + 1];
+            a[i] = ptr[3 * R + i];
+            e[i] = ptr[3 * R + i + 1];
+            dn[i] = row_distinct(a[i], e[i], idx, dcol_s[wv][i]);
         }
-        int64_t pos = FILL ? bptr[R] : 0;
-        const int64_t beg = pos, m = FILL ? (int64_t)bptr[R + 1] - bptr[R] : 0;
-        int64_t count = 0;
-        while (true) {
-            int32_t cur = INT32_MAX;
-            for (int i = 0; i < 3; ++i)
-                if (h[i] < e[i]) cur = min(cur, idx[h[i]] / 3);
-            if (cur == INT32_MAX) break;
-            if (FILL) bcol[pos] = cur;
-            for (int i = 0; i < 3; ++i)
-                while (h[i] < e[i] && idx[h[i]] / 3 == cur) {
-                    if (FILL) bval[9 * beg + (int64_t)(3 * i + idx[h[i]] % 3) * m + (pos - beg)] = val[h[i]];
-                    ++h[i];
+        wave_sync();
+        bool same = dn[0] == dn[1] && dn[1] == dn[2] && dn[0] <= kMaxDistinct;
+        if (same)
+            for (int t = lane; t < dn[0]; t += 64)
+                if (dcol_s[wv][0][t] != dcol_s[wv][1][t] || dcol_s[wv][0][t] != dcol_s[wv][2][t]) same = false;
+        same = __ballot(!same) == 0ull;
+        if (same) {
+            if (!FILL) {
+                if (lane == 0) cnt[R] = dn[0];
+            } else {
+                const int64_t beg = bptr[R], m = dn[0];
+                for (int t = lane; t < m; t += 64) bcol[beg + t] = dcol_s[wv][0][t];
+                for (int i = 0; i < 3; ++i) {
+                    int count = 0;
+                    for (int64_t base = a[i]; base < e[i]; base += 64) {
+                        const int64_t p = base + lane;
+                        const bool in = p < e[i];
+                        const int32_t c = in ? idx[p] : 0;
+                        const bool first = in && (p == a[i] || idx[p - 1] / 3 != c / 3);
+                        const unsigned long long bal = __ballot(first);
+                        // rank of p's block column = number of first entries up to and including p, minus 1
+                        const int rank = count + __popcll(bal & ((2ull << lane) - 1ull)) - 1;
+                        if (in) bval[9 * beg + (int64_t)(3 * i + c % 3) * m + rank] = val[p];
+                        count += __popcll(bal);
+                    }
                 }
-            ++pos;
-            ++count;
+            }
+        } else if (lane == 0) {
+            int64_t h[3] = {a[0], a[1], a[2]};
+            const int64_t beg = FILL ? bptr[R] : 0, m = FILL ? (int64_t)bptr[R + 1] - bptr[R] : 0;
+            int64_t pos = beg, count = 0;
+            while (true) {
+                int32_t cur = INT32_MAX;
+                for (int i = 0; i < 3; ++i)
+                    if (h[i] < e[i]) cur = min(cur, idx[h[i]] / 3);
+                if (cur == INT32_MAX) break;
+                if (FILL) bcol[pos] = cur;
+                for (int i = 0; i < 3; ++i)
+                    while (h[i] < e[i] && idx[h[i]] / 3 == cur) {
+                        if (FILL) bval[9 * beg + (int64_t)(3 * i + idx[h[i]] % 3) * m + (pos - beg)] = val[h[i]];
+                        ++h[i];
+                    }
+                ++pos;
+                ++count;
+            }
+            if (!FILL) cnt[R] = count;
         }
-        if (!FILL) cnt[R] = count;
+        wave_sync();
     }
 }
 
@@ -435,35 +495,39 @@ __global__ __launch_bounds__(256) void k_kz_window(int32_t k, const int64_t *__r
 }
 
 // ---- K Z and E in batches of kBatch consecutive deflation vectors ----
-// A batch owns the union window [lo, lo + w) of its vectors' row windows.  Per window
-// position t (row lo + t) it keeps zd[t][b] = Z[lo+t, j0+b], rb[t] = vectors with a
-// nonzero in that row, mk[t] = vectors whose K z_j has row lo + t in its structure,
-// and kd[t][b] = (K z_{j0+b})_{lo+t}.  Windows are processed in slices of kSlice
-// positions, one workgroup per (slice, batch).
+// A batch owns the union window of its vectors' rows in whole DoF triplets
+// [lo3, lo3 + w3).  Per scalar row t of the window (t = row - 3 lo3): zd[t][b] =
+// Z[row, j0+b] and kd[t][b] = (K z_{j0+b})_row.  Per triplet T: rb[T] = vectors with a
+// nonzero in triplet lo3 + T, mk[T] = vectors whose K z_j has that triplet in its block
+// structure (coupled by a 3x3 block of K to a triplet of z_j).  K z_j is evaluated on
+// the packed 3x3 blocks; a structure triplet contributes its three rows.  Windows are
+// processed in slices of kSlice triplets, one workgroup per (slice, batch).
 constexpr int kBatch = 16;
-constexpr int kSlice = 2048;
+constexpr int kSlice = 1024;
 
 struct KzBatch {
-    int64_t j0, ncol, lo, w, off, slice0, nslice;
+    int64_t j0, ncol, lo3, w3, off3, slice0, nslice, bit0;
 };
 
-__global__ __launch_bounds__(256) void k_kzb_init(const KzBatch *__restrict__ bt, double *__restrict__ zd,
+__global__ __launch_bounds__(256) void k_kzb_init(const KzBatch *__restrict__ bt, int words, double *__restrict__ zd,
                                                   double *__restrict__ kd, uint32_t *__restrict__ mk,
-                                                  uint32_t *__restrict__ rb) {
+                                                  uint32_t *__restrict__ rb, uint32_t *__restrict__ touched) {
     const KzBatch B = bt[blockIdx.y];
     if (blockIdx.x >= B.nslice) return;
-    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w, t0 + kSlice);
+    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
     for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
-        mk[B.off + t] = 0u;
-        rb[B.off + t] = 0u;
+        mk[B.off3 + t] = 0u;
+        rb[B.off3 + t] = 0u;
     }
-    for (int64_t t = t0 * kBatch + threadIdx.x; t < t1 * kBatch; t += 256) {
-        zd[B.off * kBatch + t] = 0.0;
-        kd[B.off * kBatch + t] = 0.0;
+    for (int64_t t = 3 * t0 * kBatch + threadIdx.x; t < 3 * t1 * kBatch; t += 256) {
+        zd[3 * B.off3 * kBatch + t] = 0.0;
+        kd[3 * B.off3 * kBatch + t] = 0.0;
     }
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t < words; t += 256) touched[B.bit0 + t] = 0u;
 }
 
-// one workgroup per (vector, batch): scatter z_j and flag its rows
+// one workgroup per (vector, batch): scatter z_j and flag its triplets
 __global__ __launch_bounds__(256) void k_kzb_scatter(const KzBatch *__restrict__ bt, const int64_t *__restrict__ ztp,
                                                      const int32_t *__restrict__ zti, const double *__restrict__ ztv,
                                                      double *__restrict__ zd, uint32_t *rb) {
@@ -472,32 +536,32 @@ __global__ __launch_bounds__(256) void k_kzb_scatter(const KzBatch *__restrict__
     if (b >= B.ncol) return;
     const int64_t j = B.j0 + b;
     for (int64_t e = ztp[j] + threadIdx.x; e < ztp[j + 1]; e += 256) {
-        const int64_t t = (int64_t)zti[e] - B.lo;
-        if (t < 0 || t >= B.w) continue;
-        zd[(B.off + t) * kBatch + b] = ztv[e];
-        atomicOr(&rb[B.off + t], 1u << b);
+        const int64_t t = (int64_t)zti[e] - 3 * B.lo3;
+        if (t < 0 || t >= 3 * B.w3) continue;
+        zd[(3 * B.off3 + t) * kBatch + b] = ztv[e];
+        atomicOr(&rb[B.off3 + t / 3], 1u << b);
     }
 }
 
-// structure of K z_j: every column of K row r for r in the rows of z_j (K is structurally symmetric)
-__global__ __launch_bounds__(256) void k_kzb_mark(const KzBatch *__restrict__ bt, const int64_t *__restrict__ kp,
-                                                  const int32_t *__restrict__ kc, const uint32_t *__restrict__ rb,
+// block structure of K z_j: every block column of the block rows of z_j's triplets
+__global__ __launch_bounds__(256) void k_kzb_mark(const KzBatch *__restrict__ bt, const int32_t *__restrict__ bptr,
+                                                  const int32_t *__restrict__ bcol, const uint32_t *__restrict__ rb,
                                                   uint32_t *mk) {
     const KzBatch B = bt[blockIdx.y];
     if (blockIdx.x >= B.nslice) return;
-    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w, t0 + kSlice);
+    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
     for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
-        const uint32_t bits = rb[B.off + t];
+        const uint32_t bits = rb[B.off3 + t];
         if (!bits) continue;
-        const int64_t r = B.lo + t;
-        for (int64_t q = kp[r]; q < kp[r + 1]; ++q) {
-            const int64_t c = (int64_t)kc[q] - B.lo;
-            if (c >= 0 && c < B.w) atomicOr(&mk[B.off + c], bits);
+        const int64_t R = B.lo3 + t;
+        for (int64_t q = bptr[R]; q < bptr[R + 1]; ++q) {
+            const int64_t c = (int64_t)bcol[q] - B.lo3;
+            if (c >= 0 && c < B.w3) atomicOr(&mk[B.off3 + c], bits);
         }
     }
 }
 
-// per (slice, vector) counts of structure rows
+// per (slice, vector) counts of structure rows (three per structure triplet)
 __global__ __launch_bounds__(256) void k_kzb_count(const KzBatch *__restrict__ bt, const uint32_t *__restrict__ mk,
                                                    int32_t *__restrict__ cnt) {
     __shared__ int32_t c_s[kBatch];
@@ -505,12 +569,12 @@ __global__ __launch_bounds__(256) void k_kzb_count(const KzBatch *__restrict__ b
     if (blockIdx.x >= B.nslice) return;
     if (threadIdx.x < kBatch) c_s[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w, t0 + kSlice);
+    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
     int32_t mine[kBatch];
     for (int b = 0; b < kBatch; ++b) mine[b] = 0;
     for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
-        const uint32_t m = mk[B.off + t];
-        for (int b = 0; b < kBatch; ++b) mine[b] += (m >> b) & 1u;
+        const uint32_t m = mk[B.off3 + t];
+        for (int b = 0; b < kBatch; ++b) mine[b] += 3 * ((m >> b) & 1u);
     }
     for (int b = 0; b < kBatch; ++b)
         if (mine[b]) atomicAdd(&c_s[b], mine[b]);
@@ -534,101 +598,207 @@ __global__ void k_kzb_offsets(const KzBatch *__restrict__ bt, int nbat, const in
     kzcnt[B.j0 + b] = run;
 }
 
-// (K z_j)_r for the structure rows of the slice; rows are written ascending into (KZ)^T
-// row j and densely into kd.
-__global__ __launch_bounds__(256) void k_kzb_values(const KzBatch *__restrict__ bt, const int64_t *__restrict__ kp,
-                                                    const int32_t *__restrict__ kc, const double *__restrict__ kv,
-                                                    const double *__restrict__ zd, const uint32_t *__restrict__ mk,
-                                                    const int32_t *__restrict__ soff, const int64_t *__restrict__ kzp,
-                                                    int32_t *__restrict__ kzi, double *__restrict__ kzv,
-                                                    double *__restrict__ kd) {
-    __shared__ int32_t wave_cnt[4][kBatch];
-    __shared__ int32_t carry[kBatch];
+// Rank pass: every structure triplet of the slice gets a work item (its triplet, its
+// mask of vectors, and for each vector its output position in (KZ)^T), stored densely
+// per batch in slice order.
+struct KzItem {
+    int32_t t, mask;
+    int32_t pos[kBatch];
+};
+
+__global__ __launch_bounds__(256) void k_kzb_rank(const KzBatch *__restrict__ bt, const uint32_t *__restrict__ mk,
+                                                  const int32_t *__restrict__ soff, const int32_t *__restrict__ icnt,
+                                                  const int64_t *__restrict__ kzp, KzItem *__restrict__ items) {
+    __shared__ int32_t wave_cnt[4][kBatch + 1];
+    __shared__ int32_t carry[kBatch + 1];
     const KzBatch B = bt[blockIdx.y];
     if (blockIdx.x >= B.nslice) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (threadIdx.x < kBatch) carry[threadIdx.x] = 0;
+    if (threadIdx.x <= kBatch) carry[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w, t0 + kSlice);
+    // items of this slice start after the items of the batch's earlier slices
+    const int64_t item0 = B.off3 + icnt[B.slice0 + blockIdx.x];
+    const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
     for (int64_t c0 = t0; c0 < t1; c0 += 256) {
         const int64_t t = c0 + threadIdx.x;
-        const uint32_t m = t < t1 ? mk[B.off + t] : 0u;
-        double acc[kBatch];
-        for (int b = 0; b < kBatch; ++b) acc[b] = 0.0;
-        if (m) {
-            const int64_t r = B.lo + t;
-            for (int64_t q = kp[r]; q < kp[r + 1]; ++q) {
-                const int64_t c = (int64_t)kc[q] - B.lo;
-                if (c < 0 || c >= B.w) continue;
-                const double v = kv[q];
-                const double *z = zd + (B.off + c) * kBatch;
-                for (int b = 0; b < kBatch; ++b) acc[b] = fma(v, z[b], acc[b]);
-            }
-            double *o = kd + (B.off + t) * kBatch;
-            for (int b = 0; b < kBatch; ++b) o[b] = acc[b];
-        }
-        // rank of this row among the slice's structure rows of each vector
-        int32_t rank[kBatch];
-        for (int b = 0; b < kBatch; ++b) {
-            const unsigned long long bal = __ballot((m >> b) & 1u);
+        const uint32_t m = t < t1 ? mk[B.off3 + t] : 0u;
+        int32_t rank[kBatch + 1];
+        for (int b = 0; b <= kBatch; ++b) {
+            const bool f = b < kBatch ? ((m >> b) & 1u) : (m != 0u);
+            const unsigned long long bal = __ballot(f);
             rank[b] = __popcll(bal & ((1ull << lane) - 1ull));
             if (lane == 0) wave_cnt[wv][b] = __popcll(bal);
         }
         __syncthreads();
-        for (int b = 0; b < kBatch; ++b) {
-            if (b >= B.ncol || !((m >> b) & 1u)) continue;
-            int32_t before = carry[b];
-            for (int w2 = 0; w2 < wv; ++w2) before += wave_cnt[w2][b];
-            const int64_t pos = kzp[B.j0 + b] + soff[(B.slice0 + blockIdx.x) * kBatch + b] + before + rank[b];
-            kzi[pos] = (int32_t)(B.lo + t);
-            kzv[pos] = acc[b];
+        if (m) {
+            int32_t before[kBatch + 1];
+            for (int b = 0; b <= kBatch; ++b) {
+                before[b] = carry[b];
+                for (int w2 = 0; w2 < wv; ++w2) before[b] += wave_cnt[w2][b];
+            }
+            KzItem it;
+            it.t = (int32_t)t;
+            it.mask = (int32_t)m;
+            for (int b = 0; b < kBatch; ++b)
+                it.pos[b] = (b < B.ncol && ((m >> b) & 1u))
+                                ? (int32_t)(kzp[B.j0 + b] + soff[(B.slice0 + blockIdx.x) * kBatch + b] +
+                                            3 * (before[b] + rank[b]))
+                                : -1;
+            items[item0 + before[kBatch] + rank[kBatch]] = it;
         }
         __syncthreads();
-        if (threadIdx.x < kBatch)
+        if (threadIdx.x <= kBatch)
             carry[threadIdx.x] += wave_cnt[0][threadIdx.x] + wave_cnt[1][threadIdx.x] + wave_cnt[2][threadIdx.x] +
                                   wave_cnt[3][threadIdx.x];
         __syncthreads();
     }
 }
 
-// E_raw[j0+b, i] = sum over the rows t of z_i inside the window of Z[t, i] (K z_{j0+b})_t
+// per slice: number of structure triplets, and their exclusive prefix within the batch
+__global__ void k_kzb_items(const KzBatch *__restrict__ bt, int nbat, const uint32_t *__restrict__ mk,
+                            int32_t *__restrict__ icnt, int64_t *__restrict__ nitems) {
+    const int bi = blockIdx.x;
+    if (bi >= nbat) return;
+    const KzBatch B = bt[bi];
+    __shared__ int32_t c_s;
+    int64_t run = 0;
+    for (int64_t sl = 0; sl < B.nslice; ++sl) {
+        if (threadIdx.x == 0) c_s = 0;
+        __syncthreads();
+        const int64_t t0 = sl * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
+        int32_t mine = 0;
+        for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) mine += mk[B.off3 + t] != 0u;
+        if (mine) atomicAdd(&c_s, mine);
+        __syncthreads();
+        if (threadIdx.x == 0) icnt[B.slice0 + sl] = (int32_t)run;
+        run += c_s;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) nitems[bi] = run;
+}
+
+// Compute pass: (K z_j) on the three rows of each structure triplet from the packed 3x3
+// blocks.  Sixteen lanes per work item: lane bits 0-1 pick four of the batch's vectors,
+// bits 2-3 a quarter of the block row's blocks; the quarters are combined by a fixed
+// shuffle tree.  Writes (KZ)^T at the ranked positions, the dense kd, and flags the
+// deflation vectors with a nonzero in a structure row as touched.
+__global__ __launch_bounds__(256) void k_kzb_values(const KzBatch *__restrict__ bt, const int64_t *__restrict__ nitems,
+                                                    const KzItem *__restrict__ items, const int32_t *__restrict__ bptr,
+                                                    const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+                                                    const double *__restrict__ zd, const int64_t *__restrict__ zp,
+                                                    const int32_t *__restrict__ zc, int32_t *__restrict__ kzi,
+                                                    double *__restrict__ kzv, double *__restrict__ kd,
+                                                    uint32_t *touched) {
+    const KzBatch B = bt[blockIdx.y];
+    const int64_t n_it = nitems[blockIdx.y];
+    const int sub = threadIdx.x & 3, part = (threadIdx.x >> 2) & 3;
+    const int64_t stride = (int64_t)gridDim.x * 16;
+    // the loop bound is uniform over each 16-lane group, so the shuffles stay in step
+    for (int64_t x = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4); x - (threadIdx.x >> 4) < n_it; x += stride) {
+        const bool live = x < n_it;
+        double acc[3][4];
+        for (int i = 0; i < 3; ++i)
+            for (int b = 0; b < 4; ++b) acc[i][b] = 0.0;
+        int64_t t = 0, R = 0;
+        if (live) {
+            t = items[B.off3 + x].t;
+            R = B.lo3 + t;
+            const int64_t beg = bptr[R], mR = bptr[R + 1] - beg;
+            const double *rv = bval + 9 * beg;
+            for (int64_t q = beg + part; q < beg + mR; q += 4) {
+                const int64_t c = (int64_t)bcol[q] - B.lo3;
+                if (c < 0 || c >= B.w3) continue;
+                double v[9];
+                for (int e = 0; e < 9; ++e) v[e] = rv[e * mR + (q - beg)];
+                const double *z = zd + (3 * (B.off3 + c)) * kBatch + 4 * sub;
+                for (int jj = 0; jj < 3; ++jj)
+                    for (int b = 0; b < 4; ++b) {
+                        const double zz = z[jj * kBatch + b];
+                        acc[0][b] = fma(v[jj], zz, acc[0][b]);
+                        acc[1][b] = fma(v[3 + jj], zz, acc[1][b]);
+                        acc[2][b] = fma(v[6 + jj], zz, acc[2][b]);
+                    }
+            }
+        }
+        for (int i = 0; i < 3; ++i)
+            for (int b = 0; b < 4; ++b) {
+                double v = acc[i][b];
+                v += __shfl_xor(v, 4);
+                v += __shfl_xor(v, 8);
+                acc[i][b] = v;
+            }
+        if (!live || part != 0) continue;
+        double *o = kd + (3 * (B.off3 + t)) * kBatch + 4 * sub;
+        for (int i = 0; i < 3; ++i)
+            for (int b = 0; b < 4; ++b) o[i * kBatch + b] = acc[i][b];
+        for (int b = 0; b < 4; ++b) {
+            const int32_t pos = items[B.off3 + x].pos[4 * sub + b];
+            if (pos < 0) continue;
+            for (int i = 0; i < 3; ++i) {
+                kzi[pos + i] = (int32_t)(3 * R + i);
+                kzv[pos + i] = acc[i][b];
+            }
+        }
+        if (sub == 0)
+            for (int i = 0; i < 3; ++i)
+                for (int64_t e = zp[3 * R + i]; e < zp[3 * R + i + 1]; ++e) {
+                    const int32_t col = zc[e];
+                    atomicOr(&touched[B.bit0 + col / 32], 1u << (col % 32));
+                }
+    }
+}
+
+// E_raw[j0+b, i] = sum over the structure rows t of the batch in the rows of z_i of
+// Z[t, i] (K z_{j0+b})_t, for the vectors i flagged as touched.  One wave per (i,
+// batch); lanes stride over the rows of z_i inside the window, then a fixed-order
+// wave reduction.
 __global__ __launch_bounds__(256) void k_kzb_erows(const KzBatch *__restrict__ bt, int32_t k,
                                                    const int64_t *__restrict__ ztp, const int32_t *__restrict__ zti,
                                                    const double *__restrict__ ztv, const double *__restrict__ kd,
-                                                   const uint32_t *__restrict__ mk, double *__restrict__ eraw,
-                                                   int64_t ld) {
+                                                   const uint32_t *__restrict__ mk, const uint32_t *__restrict__ touched,
+                                                   double *__restrict__ eraw, int64_t ld) {
     const KzBatch B = bt[blockIdx.y];
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= k || B.w == 0) return;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= k || B.w3 == 0) return;
+    if (!((touched[B.bit0 + i / 32] >> (i % 32)) & 1u)) return;
+    const int64_t lo = 3 * B.lo3, w = 3 * B.w3;
     int64_t a = ztp[i], e = ztp[i + 1];
-    if (a == e || zti[e - 1] < B.lo || zti[a] >= B.lo + B.w) return;
+    if (a == e || zti[e - 1] < lo || zti[a] >= lo + w) return;
     {  // first entry with row >= lo, first with row >= lo + w
         int64_t l = a, h = e;
         while (l < h) {
             const int64_t mid = (l + h) >> 1;
-            if (zti[mid] < B.lo) l = mid + 1;
+            if (zti[mid] < lo) l = mid + 1;
             else h = mid;
         }
         a = l;
         h = e;
         while (l < h) {
             const int64_t mid = (l + h) >> 1;
-            if (zti[mid] < B.lo + B.w) l = mid + 1;
+            if (zti[mid] < lo + w) l = mid + 1;
             else h = mid;
         }
         e = l;
     }
     double acc[kBatch];
     for (int b = 0; b < kBatch; ++b) acc[b] = 0.0;
-    for (int64_t q = a; q < e; ++q) {
-        const int64_t t = B.off + (int64_t)zti[q] - B.lo;
-        if (!mk[t]) continue;  // (K z_j)_t is structurally zero for every vector of the batch
+    for (int64_t q = a + lane; q < e; q += 64) {
+        const int64_t t = (int64_t)zti[q] - lo;
+        if (!mk[B.off3 + t / 3]) continue;  // (K z_j)_t is structurally zero for every vector of the batch
         const double z = ztv[q];
-        const double *kdr = kd + t * kBatch;
+        const double *kdr = kd + (3 * B.off3 + t) * kBatch;
         for (int b = 0; b < kBatch; ++b) acc[b] = fma(z, kdr[b], acc[b]);
     }
-    for (int b = 0; b < kBatch; ++b)
-        if (b < B.ncol) eraw[(B.j0 + b) * ld + i] = acc[b];
+    for (int b = 0; b < kBatch; ++b) {
+        double v = acc[b];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        acc[b] = v;
+    }
+    if (lane == 0)
+        for (int b = 0; b < kBatch; ++b)
+            if (b < B.ncol) eraw[(B.j0 + b) * ld + i] = acc[b];
 }
 
 // A = (E + E^T)/2 padded to ld x ld with an identity tail; diag0 = diagonal of A.
@@ -647,54 +817,60 @@ __global__ void k_symmetrise(int32_t k, int64_t ld, const double *__restrict__ e
 
 // ---------------------------------------------------------------- E^-1 by block Gauss-Jordan
 // P = S^-1 for the symmetric 32 x 32 pivot block S (LDS) by a right-looking Cholesky
-// S = L L^T, W = L^-1 and P = W^T W; every pivot is tested against kdim * DBL_EPSILON
-// times the original diagonal entry.  S and W are overwritten.
+// S = L L^T, W = L^-1 and P = W^T W, using the whole workgroup with one barrier per
+// column: every thread recomputes the pivot, the scaled column goes to W's strict upper
+// triangle (unused) transposed, and the trailing update reads the unscaled column.
+// Every pivot is tested against kdim * DBL_EPSILON times the original diagonal entry.
+// S and W are overwritten.
 __device__ void pivot_inverse(double *S, double *W, const double *diag0, int64_t gcol0, int32_t kdim, double *P,
                               int *fail) {
-    __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
+    bool bad = false;
     for (int j = 0; j < kNb; ++j) {
-        if (threadIdx.x == 0) {
-            const double d = S[j * kNb + j];
-            const int64_t g = gcol0 + j;
-            const double fl = g < kdim ? (double)kdim * DBL_EPSILON * fabs(diag0[g]) : 0.0;
-            if (!(d > fl) || !isfinite(d)) bad = 1;
-            S[j * kNb + j] = d > 0.0 ? sqrt(d) : 1.0;
-        }
         __syncthreads();
-        const double l = S[j * kNb + j];
-        for (int i = j + 1 + threadIdx.x; i < kNb; i += blockDim.x) S[i * kNb + j] /= l;
-        __syncthreads();
+        const double d = S[j * kNb + j];
+        const int64_t g = gcol0 + j;
+        const double fl = g < kdim ? (double)kdim * DBL_EPSILON * fabs(diag0[g]) : 0.0;
+        if (!(d > fl) || !isfinite(d)) bad = true;
+        const double dd = d > 0.0 ? d : 1.0;
+        const double l = sqrt(dd), il = 1.0 / l, id = 1.0 / dd;
         const int rem = kNb - j - 1;
+        // L[i][j] = S[i][j] / l kept in L's strict lower part of W (row j of the transpose)
+        if ((int)threadIdx.x < rem) W[j * kNb + j + 1 + threadIdx.x] = S[(j + 1 + threadIdx.x) * kNb + j] * il;
+        if (threadIdx.x == 0) W[j * kNb + j] = l;
         for (int t = threadIdx.x; t < rem * rem; t += blockDim.x) {
             const int i = j + 1 + t / rem, c = j + 1 + t % rem;
-            if (c <= i) S[i * kNb + c] -= S[i * kNb + j] * S[c * kNb + j];
+            if (c <= i) S[i * kNb + c] -= S[i * kNb + j] * S[c * kNb + j] * id;
         }
-        __syncthreads();
     }
-    // W = L^-1, row by row: W[i, :] = (e_i - sum_{p<i} L[i,p] W[p, :]) / L[i,i]
-    for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) W[t] = (t / kNb == t % kNb) ? 1.0 : 0.0;
     __syncthreads();
+    // L (lower) from W's transposed storage into S
+    for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
+        const int i = t / kNb, j = t % kNb;
+        S[t] = (j <= i) ? W[j * kNb + i] : 0.0;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) W[t] = (t / kNb == t % kNb) ? 1.0 : 0.0;
+    // W = L^-1 row by row; one barrier per row (scale and eliminate in separate halves)
     for (int i = 0; i < kNb; ++i) {
-        const double l = S[i * kNb + i];
-        for (int c = threadIdx.x; c <= i; c += blockDim.x) W[i * kNb + c] /= l;
         __syncthreads();
+        const double il = 1.0 / S[i * kNb + i];
         const int rows = kNb - i - 1;
+        // rows below: W[r][c] -= L[r][i] * (W[i][c] / L[i][i]) for c <= i, read before row i is scaled
         for (int t = threadIdx.x; t < rows * (i + 1); t += blockDim.x) {
             const int r = i + 1 + t / (i + 1), c = t % (i + 1);
-            W[r * kNb + c] -= S[r * kNb + i] * W[i * kNb + c];
+            W[r * kNb + c] -= S[r * kNb + i] * (W[i * kNb + c] * il);
         }
         __syncthreads();
+        if ((int)threadIdx.x <= i) W[i * kNb + threadIdx.x] *= il;
     }
+    __syncthreads();
     for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
         const int i = t / kNb, j = t % kNb;
         double sacc = 0.0;
         for (int p = max(i, j); p < kNb; ++p) sacc += W[p * kNb + i] * W[p * kNb + j];
         P[t] = sacc;
     }
-    __syncthreads();
-    if (threadIdx.x == 0 && bad) atomicOr(fail, 1);
+    if (bad && threadIdx.x == 0) atomicOr(fail, 1);
 }
 
 __global__ __launch_bounds__(256) void k_gj_first_pivot(const double *__restrict__ A, int64_t ld, int32_t kdim,
@@ -706,6 +882,21 @@ __global__ __launch_bounds__(256) void k_gj_first_pivot(const double *__restrict
     pivot_inverse(S, W, diag0, 0, kdim, P, fail);
 }
 
+// C (32 x 32) = sign * X Y for 32 x 32 tiles in LDS; each thread computes a 2 x 2 block.
+__device__ __forceinline__ void tile_mm(const double *X, const double *Y, double c[2][2]) {
+    const int r0 = 2 * (threadIdx.x / 16), c0 = 2 * (threadIdx.x % 16);
+    c[0][0] = c[0][1] = c[1][0] = c[1][1] = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < kNb; ++q) {
+        const double x0 = X[r0 * kNb + q], x1 = X[(r0 + 1) * kNb + q];
+        const double y0 = Y[q * kNb + c0], y1 = Y[q * kNb + c0 + 1];
+        c[0][0] = fma(x0, y0, c[0][0]);
+        c[0][1] = fma(x0, y1, c[0][1]);
+        c[1][0] = fma(x1, y0, c[1][0]);
+        c[1][1] = fma(x1, y1, c[1][1]);
+    }
+}
+
 // One sweep with pivot block p: B = sweep(A).  Tile (I, J) of 32 x 32:
 //   I = J = p: P;  I = p: P A_pJ;  J = p: -A_Ip P;  else A_IJ - A_Ip (P A_pJ).
 // The workgroup of tile (p+1, p+1) also inverts the next pivot block.
@@ -715,53 +906,40 @@ __global__ __launch_bounds__(256) void k_gj_sweep(int p, int nt, const double *_
                                                   int *fail) {
     __shared__ double Ps[kNb * kNb], X[kNb * kNb], Y[kNb * kNb], T[kNb * kNb];
     const int I = blockIdx.x / nt, J = blockIdx.x % nt;
-    for (int t = threadIdx.x; t < kNb * kNb; t += 256) Ps[t] = Pcur[t];
     const int64_t r0 = (int64_t)I * kNb, c0 = (int64_t)J * kNb, q0 = (int64_t)p * kNb;
-    if (I != p && J != p) {
-        for (int t = threadIdx.x; t < kNb * kNb; t += 256) {
-            const int a = t / kNb, b = t % kNb;
-            X[t] = A[(r0 + a) * ld + q0 + b];   // A_Ip
-            Y[t] = A[(q0 + a) * ld + c0 + b];   // A_pJ
-        }
-    } else if (I == p && J != p) {
-        for (int t = threadIdx.x; t < kNb * kNb; t += 256) Y[t] = A[(q0 + t / kNb) * ld + c0 + t % kNb];
-    } else if (J == p && I != p) {
-        for (int t = threadIdx.x; t < kNb * kNb; t += 256) X[t] = A[(r0 + t / kNb) * ld + q0 + t % kNb];
+    const int tr = 2 * (threadIdx.x / 16), tc = 2 * (threadIdx.x % 16);
+    for (int t = threadIdx.x; t < kNb * kNb; t += 256) {
+        const int a = t / kNb, b = t % kNb;
+        Ps[t] = Pcur[t];
+        if (I != p) X[t] = A[(r0 + a) * ld + q0 + b];   // A_Ip
+        if (J != p) Y[t] = A[(q0 + a) * ld + c0 + b];   // A_pJ
     }
     __syncthreads();
-    if (I != p && J != p) {
-        for (int t = threadIdx.x; t < kNb * kNb; t += 256) {  // T = P A_pJ
-            const int a = t / kNb, b = t % kNb;
-            double s = 0.0;
-            for (int q = 0; q < kNb; ++q) s = fma(Ps[a * kNb + q], Y[q * kNb + b], s);
-            T[t] = s;
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t < kNb * kNb; t += 256) {
-            const int a = t / kNb, b = t % kNb;
-            double s = 0.0;
-            for (int q = 0; q < kNb; ++q) s = fma(X[a * kNb + q], T[q * kNb + b], s);
-            const int64_t g = (r0 + a) * ld + c0 + b;
-            const double v = A[g] - s;
-            B[g] = v;
-            Y[t] = v;   // keep the tile for the next pivot
-        }
-    } else if (I == p && J == p) {
+    double cc[2][2];
+    if (I == p && J == p) {
         for (int t = threadIdx.x; t < kNb * kNb; t += 256) B[(r0 + t / kNb) * ld + c0 + t % kNb] = Ps[t];
     } else if (I == p) {
-        for (int t = threadIdx.x; t < kNb * kNb; t += 256) {
-            const int a = t / kNb, b = t % kNb;
-            double s = 0.0;
-            for (int q = 0; q < kNb; ++q) s = fma(Ps[a * kNb + q], Y[q * kNb + b], s);
-            B[(r0 + a) * ld + c0 + b] = s;
-        }
+        tile_mm(Ps, Y, cc);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) B[(r0 + tr + a) * ld + c0 + tc + b] = cc[a][b];
+    } else if (J == p) {
+        tile_mm(X, Ps, cc);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) B[(r0 + tr + a) * ld + c0 + tc + b] = -cc[a][b];
     } else {
-        for (int t = threadIdx.x; t < kNb * kNb; t += 256) {
-            const int a = t / kNb, b = t % kNb;
-            double s = 0.0;
-            for (int q = 0; q < kNb; ++q) s = fma(X[a * kNb + q], Ps[q * kNb + b], s);
-            B[(r0 + a) * ld + c0 + b] = -s;
-        }
+        tile_mm(Ps, Y, cc);  // T = P A_pJ
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) T[(tr + a) * kNb + tc + b] = cc[a][b];
+        __syncthreads();
+        tile_mm(X, T, cc);
+        __syncthreads();
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                const int64_t g = (r0 + tr + a) * ld + c0 + tc + b;
+                const double v = A[g] - cc[a][b];
+                B[g] = v;
+                Y[(tr + a) * kNb + tc + b] = v;  // kept for the next pivot
+            }
     }
     if (I == p + 1 && J == p + 1) {
         __syncthreads();
@@ -874,8 +1052,8 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(pool.tmp(&cnt, std::max<int64_t>({nb, nblocks, (int64_t)k}) + 1));
     HT(pool.tmp(&bptr64, nb + 1));
     HT(pool.tmp(&part, scan_parts));
-    hipLaunchKernelGGL((k_bsr<false>), dim3(grid_for(nb)), dim3(256), 0, s, nb, kp, kc, kv, cnt, nullptr, nullptr,
-                       nullptr, 0);
+    hipLaunchKernelGGL((k_bsr<false>), dim3(grid_for(nb, 4)), dim3(256), 0, s, nb, kp, kc, kv, cnt, nullptr, nullptr,
+                       nullptr);
     HT(scan(s, cnt, nb, bptr64, part));
     int64_t *moff = nullptr, *sq = nullptr;
     HT(pool.tmp(&moff, nblocks + 1));
@@ -929,8 +1107,8 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(keep(c, &c->bcol, nnzb));
     HT(keep(c, &c->bval, 9 * (size_t)nnzb));
     HT(hipMemsetAsync(c->bval, 0, sizeof(double) * 9 * (size_t)nnzb, s));
-    hipLaunchKernelGGL((k_bsr<true>), dim3(grid_for(nb)), dim3(256), 0, s, nb, kp, kc, kv, nullptr, c->brow_ptr,
-                       c->bcol, c->bval, nnzb);
+    hipLaunchKernelGGL((k_bsr<true>), dim3(grid_for(nb, 4)), dim3(256), 0, s, nb, kp, kc, kv, nullptr, c->brow_ptr,
+                       c->bcol, c->bval);
     hipLaunchKernelGGL(k_check_sym, dim3(grid_for(nnzb, 256, 16384)), dim3(256), 0, s, nb, c->brow_ptr, c->bcol,
                        c->bval, nnzb, maxpart, nmaxpart, flags);
     HT(keep(c, &c->minv, tot[1]));
@@ -961,6 +1139,7 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
         HT(hipMemcpyAsync(wl.data(), wlo, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
         const int nbat = (k + kBatch - 1) / kBatch;
+        const int words = (k + 31) / 32;
         std::vector<KzBatch> bt(nbat);
         int64_t slices = 0;
         for (int bi = 0; bi < nbat; ++bi) {
@@ -973,42 +1152,52 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
                     lo = std::min(lo, wl[j]);
                     hi = std::max(hi, wl[j] + ws[j]);
                 }
-            B.lo = hi > 0 ? lo : 0;
-            B.w = hi > 0 ? hi - lo : 0;
-            B.nslice = std::max<int64_t>(1, (B.w + kSlice - 1) / kSlice);
+            B.lo3 = hi > 0 ? lo / 3 : 0;
+            B.w3 = hi > 0 ? (hi + 2) / 3 - B.lo3 : 0;
+            B.nslice = std::max<int64_t>(1, (B.w3 + kSlice - 1) / kSlice);
             B.slice0 = slices;
             slices += B.nslice;
         }
         // group consecutive batches so that a group's scratch stays under the budget
-        const int64_t per_entry = 2 * kBatch * sizeof(double) + 2 * sizeof(uint32_t);
-        const int64_t budget = std::max<int64_t>(int64_t(1) << 30, 0);
+        const int64_t per_triplet = 2 * 3 * kBatch * sizeof(double) + 2 * sizeof(uint32_t);
+        const int64_t budget = int64_t(1) << 30;
         std::vector<int> gcut{0};
         int64_t acc_w = 0, max_group_w = 0;
+        int max_group_nb = 0;
         for (int bi = 0; bi < nbat; ++bi) {
-            if (acc_w > 0 && (acc_w + bt[bi].w) * per_entry > budget) {
+            if (acc_w > 0 && (acc_w + bt[bi].w3) * per_triplet > budget) {
                 gcut.push_back(bi);
                 acc_w = 0;
             }
-            bt[bi].off = acc_w;
-            acc_w += bt[bi].w;
+            bt[bi].off3 = acc_w;
+            bt[bi].bit0 = (int64_t)(bi - gcut.back()) * words;
+            acc_w += bt[bi].w3;
             max_group_w = std::max(max_group_w, acc_w);
+            max_group_nb = std::max(max_group_nb, bi - gcut.back() + 1);
         }
         gcut.push_back(nbat);
         KzBatch *bt_d = nullptr;
         int32_t *scnt = nullptr, *soff = nullptr;
         int64_t *kzcnt = nullptr, *kzp = nullptr;
         double *zd = nullptr, *kd = nullptr;
-        uint32_t *mk = nullptr, *rbits = nullptr;
+        uint32_t *mk = nullptr, *rbits = nullptr, *touched = nullptr;
         HT(pool.tmp(&bt_d, nbat));
         HT(hipMemcpyAsync(bt_d, bt.data(), sizeof(KzBatch) * nbat, hipMemcpyHostToDevice, s));
         HT(pool.tmp(&scnt, slices * kBatch));
         HT(pool.tmp(&soff, slices * kBatch));
         HT(pool.tmp(&kzcnt, k));
         HT(pool.tmp(&kzp, k + 1));
-        HT(pool.tmp(&zd, max_group_w * kBatch));
-        HT(pool.tmp(&kd, max_group_w * kBatch));
+        HT(pool.tmp(&zd, 3 * max_group_w * kBatch));
+        HT(pool.tmp(&kd, 3 * max_group_w * kBatch));
         HT(pool.tmp(&mk, max_group_w));
         HT(pool.tmp(&rbits, max_group_w));
+        HT(pool.tmp(&touched, (int64_t)max_group_nb * words));
+        int32_t *icnt = nullptr;
+        int64_t *nitems = nullptr;
+        KzItem *items = nullptr;
+        HT(pool.tmp(&icnt, slices));
+        HT(pool.tmp(&nitems, nbat));
+        HT(pool.tmp(&items, max_group_w));
         auto max_slices = [&](int g0, int g1) {
             int64_t m = 1;
             for (int bi = g0; bi < g1; ++bi) m = std::max(m, bt[bi].nslice);
@@ -1016,10 +1205,10 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
         };
         auto prepare = [&](int g0, int g1) {
             const dim3 gs(max_slices(g0, g1), g1 - g0);
-            hipLaunchKernelGGL(k_kzb_init, gs, dim3(256), 0, s, bt_d + g0, zd, kd, mk, rbits);
+            hipLaunchKernelGGL(k_kzb_init, gs, dim3(256), 0, s, bt_d + g0, words, zd, kd, mk, rbits, touched);
             hipLaunchKernelGGL(k_kzb_scatter, dim3(kBatch, g1 - g0), dim3(256), 0, s, bt_d + g0, ztp, zti, ztv, zd,
                                rbits);
-            hipLaunchKernelGGL(k_kzb_mark, gs, dim3(256), 0, s, bt_d + g0, kp, kc, rbits, mk);
+            hipLaunchKernelGGL(k_kzb_mark, gs, dim3(256), 0, s, bt_d + g0, c->brow_ptr, c->bcol, rbits, mk);
         };
         for (size_t g = 0; g + 1 < gcut.size(); ++g) {
             prepare(gcut[g], gcut[g + 1]);
@@ -1049,10 +1238,15 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
         for (size_t g = 0; g + 1 < gcut.size(); ++g) {
             const int g0 = gcut[g], g1 = gcut[g + 1];
             if (gcut.size() > 2) prepare(g0, g1);  // one group: the count pass left it ready
-            hipLaunchKernelGGL(k_kzb_values, dim3(max_slices(g0, g1), g1 - g0), dim3(256), 0, s, bt_d + g0, kp, kc,
-                               kv, zd, mk, soff, kzp, c->kzt_idx, c->kzt_val, kd);
-            hipLaunchKernelGGL(k_kzb_erows, dim3((k + 255) / 256, g1 - g0), dim3(256), 0, s, bt_d + g0, k, ztp, zti,
-                               ztv, kd, mk, eraw, ld);
+            hipLaunchKernelGGL(k_kzb_items, dim3(g1 - g0), dim3(256), 0, s, bt_d + g0, g1 - g0, mk, icnt,
+                               nitems + g0);
+            hipLaunchKernelGGL(k_kzb_rank, dim3(max_slices(g0, g1), g1 - g0), dim3(256), 0, s, bt_d + g0, mk, soff,
+                               icnt, kzp, items);
+            hipLaunchKernelGGL(k_kzb_values, dim3(128, g1 - g0), dim3(256),
+                               0, s, bt_d + g0, nitems + g0, items, c->brow_ptr, c->bcol, c->bval, zd, zp, zc,
+                               c->kzt_idx, c->kzt_val, kd, touched);
+            hipLaunchKernelGGL(k_kzb_erows, dim3((k + 3) / 4, g1 - g0), dim3(256), 0, s, bt_d + g0, k, ztp, zti, ztv,
+                               kd, mk, touched, eraw, ld);
         }
         HT(hipGetLastError());
         // ---- E^-1 ----
