@@ -27,6 +27,13 @@ namespace dpcg {
 constexpr int kThreads = 256;     // threads per workgroup everywhere
 constexpr int kMaxBlock = 18;     // largest block-Jacobi block
 
+// The hardware spreads consecutive workgroups round-robin over the 8 XCDs; give each
+// XCD a contiguous range of work so neighbouring rows share its L2.
+__device__ __forceinline__ int xcd_remap(int w, int nwg) {
+    if ((nwg & 7) != 0) return w;
+    return (w & 7) * (nwg >> 3) + (w >> 3);
+}
+
 // Solver state shared by the kernels of one solve; lives in device memory.  Every
 // field is written by exactly one thread of one kernel, and read only by kernels
 // that run after that one in stream order.

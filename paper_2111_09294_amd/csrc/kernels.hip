@@ -76,13 +76,6 @@ __device__ __forceinline__ int32_t wg_flag(const State *st) {
     return v;
 }
 
-// The hardware spreads consecutive workgroups round-robin over the 8 XCDs; give each
-// XCD a contiguous range of work so neighbouring rows share its L2.
-__device__ __forceinline__ int xcd_remap(int w, int nwg) {
-    if ((nwg & 7) != 0) return w;
-    return (w & 7) * (nwg >> 3) + (w >> 3);
-}
-
 struct XPlain {
     const double *__restrict__ x;
     __device__ __forceinline__ double operator()(int64_t i) const { return x[i]; }

@@ -150,38 +150,119 @@ __global__ __launch_bounds__(256) void k_maxabs_part(const double *__restrict__ 
     if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
 }
 
-// |K_ij - K_ji| <= 1e-12 max|K| over the packed 3x3 blocks: block (R, C) against the
-// transpose of block (C, R), found by binary search in block row C (a missing block is 0).
-// One thread per block; its block row R is found by binary search in the row pointer.
-__global__ void k_check_sym(int32_t nb, const int32_t *__restrict__ bptr, const int32_t *__restrict__ bcol,
-                            const double *__restrict__ bval, int64_t nnzb, const double *__restrict__ maxpart,
-                            int nmax, int *flag) {
+// part[0] = max over part[0..m): one workgroup, fixed order
+__global__ __launch_bounds__(256) void k_max_reduce(double *part, int m) {
+    __shared__ double lds[4];
+    double x = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) x = fmax(x, part[i]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) part[0] = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+}
+
+// |K_ij - K_ji| <= 1e-12 max|K| over the packed 3x3 blocks, one thread per block (R, C)
+// with R = brow[b].  A diagonal block is compared with its own transpose; block (R, C),
+// C > R, with the transpose of block (C, R), found by binary search in block row C (a
+// missing block counts as 0).  Blocks below the diagonal are only counted: when their
+// number equals the number of upper blocks whose mirror was found, every lower block is
+// such a mirror and has been compared; otherwise k_check_sym_lower compares the
+// unpaired ones with 0.  part[2 w], part[2 w + 1]: lower blocks, found mirrors of
+// workgroup w.
+__device__ __forceinline__ int64_t find_block(const int32_t *__restrict__ bcol, int64_t l, int64_t h, int32_t col) {
+    while (l < h) {
+        const int64_t mid = (l + h) >> 1;
+        if (bcol[mid] < col) l = mid + 1;
+        else h = mid;
+    }
+    return l;
+}
+
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t *lds4) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    return (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
+}
+
+__global__ __launch_bounds__(256) void k_check_sym(const int32_t *__restrict__ bptr, const int32_t *__restrict__ brow,
+                                                   const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+                                                   int64_t nnzb, const double *__restrict__ maxpart, int nmax, int *flag,
+                                                   int64_t *__restrict__ part) {
+    __shared__ int64_t lds4[4];
     double mx = 0.0;
     for (int i = 0; i < nmax; ++i) mx = fmax(mx, maxpart[i]);
     const double tol = 1e-12 * mx;
-    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nnzb; b += (int64_t)gridDim.x * blockDim.x) {
-        int lo = 0, hi = nb;  // last R with bptr[R] <= b
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (bptr[mid] <= b) lo = mid;
-            else hi = mid;
+    int64_t lower = 0, found_n = 0;
+    // a contiguous range of blocks per workgroup and per XCD: the mirrors of neighbouring
+    // rows sit side by side in the same block rows, so they share the XCD's L2 lines
+    const int64_t per = ((nnzb + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
+    const int64_t b0 = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * per, b1 = min(nnzb, b0 + per);
+    for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) {
+        const int32_t R = brow[b], C = bcol[b];
+        if (C < R) {
+            ++lower;
+            continue;
         }
-        const int32_t R = lo, C = bcol[b];
-        int64_t l = bptr[C], h = bptr[C + 1];
-        while (l < h) {
-            const int64_t mid = (l + h) >> 1;
-            if (bcol[mid] < R) l = mid + 1;
-            else h = mid;
-        }
-        const bool found = l < bptr[C + 1] && bcol[l] == R;
-        const int64_t bR = bptr[R], mR = bptr[R + 1] - bR, bC = bptr[C], mC = bptr[C + 1] - bC;
+        const int64_t bR = bptr[R], mR = bptr[R + 1] - bR;
+        double v[9];
+        for (int e = 0; e < 9; ++e) v[e] = bval[9 * bR + (int64_t)e * mR + (b - bR)];
         bool ok = true;
-        for (int i = 0; i < 3; ++i)
-            for (int j = 0; j < 3; ++j) {
-                const double v = bval[9 * bR + (int64_t)(3 * i + j) * mR + (b - bR)];
-                const double m = found ? bval[9 * bC + (int64_t)(3 * j + i) * mC + (l - bC)] : 0.0;
-                ok = ok && fabs(v - m) <= tol;
-            }
+        if (C == R) {
+            for (int i = 0; i < 3; ++i)
+                for (int j = i + 1; j < 3; ++j) ok = ok && fabs(v[3 * i + j] - v[3 * j + i]) <= tol;
+        } else {
+            const int64_t bC = bptr[C], mC = bptr[C + 1] - bC;
+            const int64_t l = find_block(bcol, bC, bC + mC, R);
+            const bool found = l < bC + mC && bcol[l] == R;
+            found_n += found;
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    const double m = found ? bval[9 * bC + (int64_t)(3 * j + i) * mC + (l - bC)] : 0.0;
+                    ok = ok && fabs(v[3 * i + j] - m) <= tol;
+                }
+        }
+        if (!ok) atomicMin(flag + 3, 3 * R);
+    }
+    lower = block_sum(lower, lds4);
+    __syncthreads();
+    found_n = block_sum(found_n, lds4);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = lower;
+        part[2 * blockIdx.x + 1] = found_n;
+    }
+}
+
+// need[0] = 1 when some block below the diagonal has no mirror above it
+__global__ __launch_bounds__(256) void k_sym_reduce(const int64_t *__restrict__ part, int nwg, int *need) {
+    __shared__ int64_t lds4[4];
+    int64_t d = 0;
+    for (int w = threadIdx.x; w < nwg; w += 256) d += part[2 * w] - part[2 * w + 1];
+    d = block_sum(d, lds4);
+    if (threadIdx.x == 0) need[0] = d != 0;
+}
+
+__global__ __launch_bounds__(256) void k_check_sym_lower(const int32_t *__restrict__ bptr,
+                                                         const int32_t *__restrict__ brow,
+                                                         const int32_t *__restrict__ bcol,
+                                                         const double *__restrict__ bval, int64_t nnzb,
+                                                         const double *__restrict__ maxpart, int nmax, int *flag,
+                                                         const int *__restrict__ need) {
+    if (!need[0]) return;
+    double mx = 0.0;
+    for (int i = 0; i < nmax; ++i) mx = fmax(mx, maxpart[i]);
+    const double tol = 1e-12 * mx;
+    for (int64_t b = blockIdx.x * 256ll + threadIdx.x; b < nnzb; b += (int64_t)gridDim.x * 256) {
+        const int32_t R = brow[b], C = bcol[b];
+        if (C >= R) continue;
+        const int64_t bC = bptr[C], mC = bptr[C + 1] - bC;
+        const int64_t l = find_block(bcol, bC, bC + mC, R);
+        if (l < bC + mC && bcol[l] == R) continue;
+        const int64_t bR = bptr[R], mR = bptr[R + 1] - bR;
+        bool ok = true;
+        for (int e = 0; e < 9; ++e) ok = ok && fabs(bval[9 * bR + (int64_t)e * mR + (b - bR)]) <= tol;
         if (!ok) atomicMin(flag + 3, 3 * R);
     }
 }
@@ -217,7 +298,7 @@ template <bool FILL>
 __global__ __launch_bounds__(256) void k_bsr(int32_t nb, const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                              const double *__restrict__ val, int64_t *__restrict__ cnt,
                                              const int32_t *__restrict__ bptr, int32_t *__restrict__ bcol,
-                                             double *__restrict__ bval) {
+                                             double *__restrict__ bval, int32_t *__restrict__ brow) {
     __shared__ int32_t dcol_s[4][3][kMaxDistinct];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int64_t R = blockIdx.x * 4ll + wv; R < nb; R += (int64_t)gridDim.x * 4) {
@@ -239,7 +320,10 @@ __global__ __launch_bounds__(256) void k_bsr(int32_t nb, const int64_t *__restri
                 if (lane == 0) cnt[R] = dn[0];
             } else {
                 const int64_t beg = bptr[R], m = dn[0];
-                for (int t = lane; t < m; t += 64) bcol[beg + t] = dcol_s[wv][0][t];
+                for (int t = lane; t < m; t += 64) {
+                    bcol[beg + t] = dcol_s[wv][0][t];
+                    brow[beg + t] = (int32_t)R;
+                }
                 for (int i = 0; i < 3; ++i) {
                     int count = 0;
                     for (int64_t base = a[i]; base < e[i]; base += 64) {
@@ -264,7 +348,10 @@ __global__ __launch_bounds__(256) void k_bsr(int32_t nb, const int64_t *__restri
                 for (int i = 0; i < 3; ++i)
                     if (h[i] < e[i]) cur = min(cur, idx[h[i]] / 3);
                 if (cur == INT32_MAX) break;
-                if (FILL) bcol[pos] = cur;
+                if (FILL) {
+                    bcol[pos] = cur;
+                    brow[pos] = (int32_t)R;
+                }
                 for (int i = 0; i < 3; ++i)
                     while (h[i] < e[i] && idx[h[i]] / 3 == cur) {
                         if (FILL) bval[9 * beg + (int64_t)(3 * i + idx[h[i]] % 3) * m + (pos - beg)] = val[h[i]];
@@ -287,8 +374,101 @@ __global__ void k_block_sq(int32_t nblocks, const int32_t *__restrict__ bp, int6
     }
 }
 
-// One wave per block: Cholesky (pivot test m * DBL_EPSILON * original diagonal) and the
-// explicit inverse L^-T L^-1, same operation order as a sequential column algorithm.
+// Block-Jacobi inverses: Cholesky with the pivot test m * DBL_EPSILON * |original
+// diagonal entry|, then the explicit inverse L^-T L^-1, in the operation order of a
+// sequential column algorithm.  Blocks of up to kSmallBlock DoFs take one thread each
+// (register arrays, every index a compile-time constant); larger blocks one wave each.
+constexpr int kSmallBlock = 6;
+
+__global__ __launch_bounds__(256) void k_bj_small(int32_t nblocks, const int32_t *__restrict__ bp,
+                                                  const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                  const double *__restrict__ val, const int64_t *__restrict__ moff,
+                                                  double *__restrict__ minv, int32_t *__restrict__ rowoff,
+                                                  int32_t *__restrict__ meta, int *bad_block) {
+    constexpr int M = kSmallBlock;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nblocks; b += gridDim.x * blockDim.x) {
+        const int32_t s = bp[b];
+        const int m = bp[b + 1] - s;
+        if (m > M) continue;
+        double A[M][M], Li[M][M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) A[i][j] = 0.0;
+            if (i < m) {
+                // first entry of the row with column >= s (columns are sorted)
+                int64_t lo = ptr[s + i], hi = ptr[s + i + 1];
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (idx[mid] < s) lo = mid + 1;
+                    else hi = mid;
+                }
+                const int64_t end = ptr[s + i + 1];
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    if (j < m && lo < end && idx[lo] == s + j) {
+                        A[i][j] = val[lo];
+                        ++lo;
+                    }
+            }
+        }
+        bool ok = true;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            if (j >= m) continue;
+            double d = A[j][j];
+            const double fl = m * DBL_EPSILON * fabs(d);
+#pragma unroll
+            for (int p = 0; p < j; ++p) d -= A[j][p] * A[j][p];
+            if (!(d > fl) || !isfinite(d)) ok = false;
+            const double l = sqrt(d > 0.0 ? d : 1.0);
+            A[j][j] = l;
+#pragma unroll
+            for (int i = j + 1; i < M; ++i) {
+                if (i >= m) continue;
+                double sacc = A[i][j];
+#pragma unroll
+                for (int p = 0; p < j; ++p) sacc -= A[i][p] * A[j][p];
+                A[i][j] = sacc / l;
+            }
+        }
+        if (!ok) {
+            atomicMin(bad_block, b);
+            continue;
+        }
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                if (i < j || i >= m || j >= m) {
+                    Li[i][j] = 0.0;
+                    continue;
+                }
+                double sacc = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+                for (int p = j; p < i; ++p) sacc -= A[i][p] * Li[p][j];
+                Li[i][j] = sacc / A[i][i];
+            }
+        double *out = minv + moff[b];
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            if (i >= m) continue;
+#pragma unroll
+            for (int j = i; j < M; ++j) {
+                if (j >= m) continue;
+                double sacc = 0.0;
+#pragma unroll
+                for (int p = j; p < M; ++p)
+                    if (p < m) sacc += Li[p][i] * Li[p][j];
+                out[i * m + j] = sacc;
+                out[j * m + i] = sacc;
+            }
+            rowoff[s + i] = (int32_t)(moff[b] + (int64_t)i * m);
+            meta[s + i] = (m << 8) | i;
+        }
+    }
+}
+
 __global__ __launch_bounds__(64) void k_bj_factor(int32_t nblocks, const int32_t *__restrict__ bp,
                                                   const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                   const double *__restrict__ val, const int64_t *__restrict__ moff,
@@ -297,67 +477,82 @@ __global__ __launch_bounds__(64) void k_bj_factor(int32_t nblocks, const int32_t
     __shared__ double A[kMaxBlock * kMaxBlock];
     __shared__ double Li[kMaxBlock * kMaxBlock];
     __shared__ int fail;
-    const int b = blockIdx.x;
-    if (b >= nblocks) return;
     const int lane = threadIdx.x;
-    const int32_t s = bp[b];
-    const int m = bp[b + 1] - s;
-    for (int t = lane; t < m * m; t += 64) A[t] = 0.0;
-    if (lane == 0) fail = 0;
-    __syncthreads();
-    if (lane < m)
-        for (int64_t e = ptr[s + lane]; e < ptr[s + lane + 1]; ++e) {
-            const int32_t c = idx[e];
-            if (c >= s && c < s + m) A[lane * m + (c - s)] = val[e];
-        }
-    __syncthreads();
-    for (int j = 0; j < m; ++j) {
-        if (lane == 0) {
-            double d = A[j * m + j];
-            const double fl = m * DBL_EPSILON * fabs(d);
-            for (int p = 0; p < j; ++p) d -= A[j * m + p] * A[j * m + p];
-            if (!(d > fl) || !isfinite(d)) fail = 1;
-            else A[j * m + j] = sqrt(d);
-        }
+    for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+        const int32_t s = bp[b];
+        const int m = bp[b + 1] - s;
+        if (m <= kSmallBlock) continue;
         __syncthreads();
-        if (fail) break;
-        const double l = A[j * m + j];
-        if (lane > j && lane < m) {
-            double sacc = A[lane * m + j];
-            for (int p = 0; p < j; ++p) sacc -= A[lane * m + p] * A[j * m + p];
-            A[lane * m + j] = sacc / l;
-        }
+        for (int t = lane; t < m * m; t += 64) A[t] = 0.0;
+        if (lane == 0) fail = 0;
         __syncthreads();
-    }
-    if (fail) {
-        if (lane == 0) atomicMin(bad_block, b);
-        return;
-    }
-    // column j of L^-1 (lane j), rows i >= j
-    if (lane < m) {
-        const int j = lane;
-        for (int i = 0; i < m; ++i) {
-            if (i < j) {
-                Li[i * m + j] = 0.0;
-                continue;
+        if (lane < m) {
+            // the row's entries in columns [s, s + m) follow its first column >= s
+            int64_t lo = ptr[s + lane], hi = ptr[s + lane + 1];
+            const int64_t end = hi;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (idx[mid] < s) lo = mid + 1;
+                else hi = mid;
             }
-            double sacc = (i == j) ? 1.0 : 0.0;
-            for (int p = j; p < i; ++p) sacc -= A[i * m + p] * Li[p * m + j];
-            Li[i * m + j] = sacc / A[i * m + i];
+#pragma unroll
+            for (int q = 0; q < kMaxBlock; ++q) {
+                const int64_t e = lo + q;
+                if (q < m && e < end) {
+                    const int32_t c = idx[e];
+                    if (c < s + m) A[lane * m + (c - s)] = val[e];
+                }
+            }
         }
-    }
-    __syncthreads();
-    double *out = minv + moff[b];
-    if (lane < m) {
-        const int i = lane;
-        for (int j = i; j < m; ++j) {
-            double sacc = 0.0;
-            for (int p = j; p < m; ++p) sacc += Li[p * m + i] * Li[p * m + j];
-            out[i * m + j] = sacc;
-            out[j * m + i] = sacc;
+        __syncthreads();
+        for (int j = 0; j < m; ++j) {
+            if (lane == 0) {
+                double d = A[j * m + j];
+                const double fl = m * DBL_EPSILON * fabs(d);
+                for (int p = 0; p < j; ++p) d -= A[j * m + p] * A[j * m + p];
+                if (!(d > fl) || !isfinite(d)) fail = 1;
+                else A[j * m + j] = sqrt(d);
+            }
+            __syncthreads();
+            if (fail) break;
+            const double l = A[j * m + j];
+            if (lane > j && lane < m) {
+                double sacc = A[lane * m + j];
+                for (int p = 0; p < j; ++p) sacc -= A[lane * m + p] * A[j * m + p];
+                A[lane * m + j] = sacc / l;
+            }
+            __syncthreads();
         }
-        rowoff[s + i] = (int32_t)(moff[b] + (int64_t)i * m);
-        meta[s + i] = (m << 8) | i;
+        if (fail) {
+            if (lane == 0) atomicMin(bad_block, b);
+            continue;
+        }
+        // column j of L^-1 (lane j), rows i >= j
+        if (lane < m) {
+            const int j = lane;
+            for (int i = 0; i < m; ++i) {
+                if (i < j) {
+                    Li[i * m + j] = 0.0;
+                    continue;
+                }
+                double sacc = (i == j) ? 1.0 : 0.0;
+                for (int p = j; p < i; ++p) sacc -= A[i * m + p] * Li[p * m + j];
+                Li[i * m + j] = sacc / A[i * m + i];
+            }
+        }
+        __syncthreads();
+        double *out = minv + moff[b];
+        if (lane < m) {
+            const int i = lane;
+            for (int j = i; j < m; ++j) {
+                double sacc = 0.0;
+                for (int p = j; p < m; ++p) sacc += Li[p * m + i] * Li[p * m + j];
+                out[i * m + j] = sacc;
+                out[j * m + i] = sacc;
+            }
+            rowoff[s + i] = (int32_t)(moff[b] + (int64_t)i * m);
+            meta[s + i] = (m << 8) | i;
+        }
     }
 }
 
@@ -381,80 +576,69 @@ __global__ void k_tiles(int32_t ntiles, int32_t nblocks, const int32_t *__restri
 }
 
 // ---------------------------------------------------------------- Z^T
-__global__ void k_col_count(int64_t nnz, const int32_t *__restrict__ idx, int64_t *cnt) {
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd((unsigned long long *)&cnt[idx[e]], 1ull);
-}
+// Z^T by a stable counting sort over chunks of Z's entries in row-major order.  Pass 1
+// counts each chunk's entries per column into cnt[c * nch + w]; an exclusive scan in
+// (column, chunk) order gives every (column, chunk) pair its first slot; pass 2 walks a
+// chunk's entries in order with one wave and places them, so every column of Z^T lists
+// its rows in increasing order without atomics on global memory.  Columns go in ranges
+// of kZtCols (LDS tables), one grid row per range.
+constexpr int kZtCols = 8192;
 
-__global__ void k_col_place(int64_t rows, const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
-                            const double *__restrict__ val, const int64_t *__restrict__ tptr, int64_t *fill,
-                            int32_t *__restrict__ tidx, double *__restrict__ tval) {
+__global__ void k_entry_rows(int64_t rows, const int64_t *__restrict__ ptr, int32_t *__restrict__ erow) {
     for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x)
-        for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) {
-            const int32_t c = idx[e];
-            const int64_t q = tptr[c] + (int64_t)atomicAdd((unsigned long long *)&fill[c], 1ull);
-            tidx[q] = (int32_t)r;
-            tval[q] = val[e];
-        }
+        for (int64_t e = ptr[r]; e < ptr[r + 1]; ++e) erow[e] = (int32_t)r;
 }
 
-// Orders each segment by its (unique) keys.  Segments of up to 4096 entries are sorted
-// in LDS by a bitonic network; longer ones by rank (number of smaller keys), streamed
-// through LDS in chunks.
-__global__ __launch_bounds__(256) void k_seg_sort(const int64_t *__restrict__ tptr, const int32_t *__restrict__ kin,
-                                                  const double *__restrict__ vin, int32_t *__restrict__ kout,
-                                                  double *__restrict__ vout) {
-    constexpr int kCap = 4096;
-    __shared__ int32_t keys[kCap];
-    __shared__ int32_t pos[kCap];
-    const int64_t a = tptr[blockIdx.x], b = tptr[blockIdx.x + 1];
-    const int64_t m = b - a;
-    if (m <= kCap) {
-        int L = 1;
-        while (L < m) L <<= 1;
-        for (int t = threadIdx.x; t < L; t += 256) {
-            keys[t] = t < m ? kin[a + t] : INT32_MAX;
-            pos[t] = t;
-        }
-        __syncthreads();
-        for (int size = 2; size <= L; size <<= 1)
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int t = threadIdx.x; t < L; t += 256) {
-                    const int u = t ^ stride;
-                    if (u > t) {
-                        const bool up = (t & size) == 0;
-                        const int32_t kt = keys[t], ku = keys[u];
-                        if ((kt > ku) == up) {
-                            keys[t] = ku;
-                            keys[u] = kt;
-                            const int32_t pt = pos[t];
-                            pos[t] = pos[u];
-                            pos[u] = pt;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-        for (int t = threadIdx.x; t < m; t += 256) {
-            kout[a + t] = keys[t];
-            vout[a + t] = vin[a + pos[t]];
-        }
-        return;
+__global__ __launch_bounds__(256) void k_zt_count(int64_t nnz, int64_t per, int nch, int32_t k,
+                                                  const int32_t *__restrict__ idx, int64_t *__restrict__ cnt) {
+    extern __shared__ int32_t hist[];
+    const int w = blockIdx.x;
+    const int32_t c0 = blockIdx.y * kZtCols, nc = min(kZtCols, k - c0);
+    for (int t = threadIdx.x; t < nc; t += 256) hist[t] = 0;
+    __syncthreads();
+    const int64_t e0 = (int64_t)w * per, e1 = min(nnz, e0 + per);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
+        const int32_t c = idx[e] - c0;
+        if (c >= 0 && c < nc) atomicAdd(&hist[c], 1);
     }
-    for (int64_t base = 0; base < m; base += 256) {
-        const int64_t mine = base + threadIdx.x;
-        const int32_t key = mine < m ? kin[a + mine] : INT32_MAX;
-        int64_t rank = 0;
-        for (int64_t c = 0; c < m; c += kCap) {
-            __syncthreads();
-            for (int t = threadIdx.x; t < kCap; t += 256) keys[t] = (c + t < m) ? kin[a + c + t] : INT32_MAX;
-            __syncthreads();
-            const int lim = (int)min<int64_t>(kCap, m - c);
-            for (int t = 0; t < lim; ++t) rank += keys[t] < key;
-        }
-        if (mine < m) {
-            kout[a + rank] = key;
-            vout[a + rank] = vin[a + mine];
+    __syncthreads();
+    for (int t = threadIdx.x; t < nc; t += 256) cnt[(int64_t)(c0 + t) * nch + w] = hist[t];
+}
+
+__global__ void k_zt_ptr(int32_t k, int nch, const int64_t *__restrict__ off, int64_t *__restrict__ ztp) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c <= k; c += (int64_t)gridDim.x * blockDim.x)
+        ztp[c] = off[c * nch];
+}
+
+__global__ __launch_bounds__(64) void k_zt_place(int64_t nnz, int64_t per, int nch, int32_t k,
+                                                 const int32_t *__restrict__ idx, const double *__restrict__ val,
+                                                 const int32_t *__restrict__ erow, const int64_t *__restrict__ off,
+                                                 int32_t *__restrict__ zti, double *__restrict__ ztv) {
+    extern __shared__ int64_t run[];
+    const int w = blockIdx.x, lane = threadIdx.x;
+    const int32_t c0 = blockIdx.y * kZtCols, nc = min(kZtCols, k - c0);
+    for (int t = lane; t < nc; t += 64) run[t] = off[(int64_t)(c0 + t) * nch + w];
+    __syncthreads();
+    const int64_t e0 = (int64_t)w * per, e1 = min(nnz, e0 + per);
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    for (int64_t base = e0; base < e1; base += 64) {
+        const int64_t e = base + lane;
+        const int32_t c = e < e1 ? idx[e] - c0 : -1;
+        const bool mine = c >= 0 && c < nc;
+        unsigned long long todo = __ballot(mine);
+        // one distinct column per step: its lanes take consecutive slots in lane order
+        while (todo) {
+            const int leader = __builtin_ctzll(todo);
+            const int32_t cl = __shfl(c, leader);
+            const unsigned long long grp = __ballot(mine && c == cl);
+            const int64_t b = run[cl];
+            if (mine && c == cl) {
+                const int64_t q = b + __popcll(grp & lt);
+                zti[q] = erow[e];
+                ztv[q] = val[e];
+            }
+            if (lane == leader) run[cl] = b + __popcll(grp);
+            todo &= ~grp;
         }
     }
 }
@@ -504,13 +688,13 @@ __global__ __launch_bounds__(256) void k_kz_window(int32_t k, const int64_t *__r
 // processed in slices of kSlice triplets, one workgroup per (slice, batch).
 constexpr int kBatch = 16;
 constexpr int kSlice = 1024;
+constexpr int kTouchLds = 2048;  // LDS words of the touched-vector bitmap (k <= 65536)
 
 struct KzBatch {
     int64_t j0, ncol, lo3, w3, off3, slice0, nslice, bit0;
 };
 
-__global__ __launch_bounds__(256) void k_kzb_init(const KzBatch *__restrict__ bt, int words, double *__restrict__ zd,
-                                                  double *__restrict__ kd, uint32_t *__restrict__ mk,
+__global__ __launch_bounds__(256) void k_kzb_init(const KzBatch *__restrict__ bt, int words, uint32_t *__restrict__ mk,
                                                   uint32_t *__restrict__ rb, uint32_t *__restrict__ touched) {
     const KzBatch B = bt[blockIdx.y];
     if (blockIdx.x >= B.nslice) return;
@@ -519,15 +703,13 @@ __global__ __launch_bounds__(256) void k_kzb_init(const KzBatch *__restrict__ bt
         mk[B.off3 + t] = 0u;
         rb[B.off3 + t] = 0u;
     }
-    for (int64_t t = 3 * t0 * kBatch + threadIdx.x; t < 3 * t1 * kBatch; t += 256) {
-        zd[3 * B.off3 * kBatch + t] = 0.0;
-        kd[3 * B.off3 * kBatch + t] = 0.0;
-    }
     if (blockIdx.x == 0)
         for (int t = threadIdx.x; t < words; t += 256) touched[B.bit0 + t] = 0u;
 }
 
-// one workgroup per (vector, batch): scatter z_j and flag its triplets
+// one workgroup per (vector, batch): scatter z_j and flag its triplets.  The three rows
+// of each flagged triplet are cleared first (column b belongs to this workgroup), so zd
+// holds z_j exactly where rb flags vector b and is never read elsewhere.
 __global__ __launch_bounds__(256) void k_kzb_scatter(const KzBatch *__restrict__ bt, const int64_t *__restrict__ ztp,
                                                      const int32_t *__restrict__ zti, const double *__restrict__ ztv,
                                                      double *__restrict__ zd, uint32_t *rb) {
@@ -535,6 +717,13 @@ __global__ __launch_bounds__(256) void k_kzb_scatter(const KzBatch *__restrict__
     const int b = blockIdx.x;
     if (b >= B.ncol) return;
     const int64_t j = B.j0 + b;
+    for (int64_t e = ztp[j] + threadIdx.x; e < ztp[j + 1]; e += 256) {
+        const int64_t t = (int64_t)zti[e] - 3 * B.lo3;
+        if (t < 0 || t >= 3 * B.w3) continue;
+        const int64_t t3 = 3 * (t / 3);
+        for (int r = 0; r < 3; ++r) zd[(3 * B.off3 + t3 + r) * kBatch + b] = 0.0;
+    }
+    __syncthreads();
     for (int64_t e = ztp[j] + threadIdx.x; e < ztp[j + 1]; e += 256) {
         const int64_t t = (int64_t)zti[e] - 3 * B.lo3;
         if (t < 0 || t >= 3 * B.w3) continue;
@@ -655,7 +844,7 @@ __global__ __launch_bounds__(256) void k_kzb_rank(const KzBatch *__restrict__ bt
 }
 
 // per slice: number of structure triplets, and their exclusive prefix within the batch
-__global__ void k_kzb_items(const KzBatch *__restrict__ bt, int nbat, const uint32_t *__restrict__ mk,
+__global__ __launch_bounds__(256) void k_kzb_items(const KzBatch *__restrict__ bt, int nbat, const uint32_t *__restrict__ mk,
                             int32_t *__restrict__ icnt, int64_t *__restrict__ nitems) {
     const int bi = blockIdx.x;
     if (bi >= nbat) return;
@@ -667,7 +856,7 @@ __global__ void k_kzb_items(const KzBatch *__restrict__ bt, int nbat, const uint
         __syncthreads();
         const int64_t t0 = sl * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
         int32_t mine = 0;
-        for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) mine += mk[B.off3 + t] != 0u;
+        for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) mine += mk[B.off3 + t] != 0u;
         if (mine) atomicAdd(&c_s, mine);
         __syncthreads();
         if (threadIdx.x == 0) icnt[B.slice0 + sl] = (int32_t)run;
@@ -685,17 +874,26 @@ __global__ void k_kzb_items(const KzBatch *__restrict__ bt, int nbat, const uint
 __global__ __launch_bounds__(256) void k_kzb_values(const KzBatch *__restrict__ bt, const int64_t *__restrict__ nitems,
                                                     const KzItem *__restrict__ items, const int32_t *__restrict__ bptr,
                                                     const int32_t *__restrict__ bcol, const double *__restrict__ bval,
-                                                    const double *__restrict__ zd, const int64_t *__restrict__ zp,
+                                                    const double *__restrict__ zd, const uint32_t *__restrict__ rb,
+                                                    const int64_t *__restrict__ zp,
                                                     const int32_t *__restrict__ zc, int32_t *__restrict__ kzi,
                                                     double *__restrict__ kzv, double *__restrict__ kd,
-                                                    uint32_t *touched) {
+                                                    int words, uint32_t *touched) {
+    __shared__ uint32_t tw[kTouchLds];
     const KzBatch B = bt[blockIdx.y];
     const int64_t n_it = nitems[blockIdx.y];
     const int sub = threadIdx.x & 3, part = (threadIdx.x >> 2) & 3;
-    const int64_t stride = (int64_t)gridDim.x * 16;
-    // the loop bound is uniform over each 16-lane group, so the shuffles stay in step
-    for (int64_t x = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4); x - (threadIdx.x >> 4) < n_it; x += stride) {
-        const bool live = x < n_it;
+    const bool lds_bits = words <= kTouchLds;
+    if (lds_bits)
+        for (int t = threadIdx.x; t < words; t += 256) tw[t] = 0u;
+    __syncthreads();
+    uint32_t *tb = lds_bits ? tw : touched + B.bit0;
+    // a contiguous run of items per workgroup (neighbouring triplets, few deflation
+    // vectors); the loop bound is uniform over the workgroup, so the shuffles stay in step
+    const int64_t per = ((n_it + gridDim.x - 1) / gridDim.x + 15) / 16 * 16;
+    const int64_t x0 = (int64_t)blockIdx.x * per, x1 = min(n_it, x0 + per);
+    for (int64_t x = x0 + (threadIdx.x >> 4); x - (threadIdx.x >> 4) < x1; x += 16) {
+        const bool live = x < x1;
         double acc[3][4];
         for (int i = 0; i < 3; ++i)
             for (int b = 0; b < 4; ++b) acc[i][b] = 0.0;
@@ -708,12 +906,14 @@ __global__ __launch_bounds__(256) void k_kzb_values(const KzBatch *__restrict__ 
             for (int64_t q = beg + part; q < beg + mR; q += 4) {
                 const int64_t c = (int64_t)bcol[q] - B.lo3;
                 if (c < 0 || c >= B.w3) continue;
+                const uint32_t zb = rb[B.off3 + c] >> (4 * sub);
+                if (!(zb & 15u)) continue;  // none of this lane's vectors has support on triplet c
                 double v[9];
                 for (int e = 0; e < 9; ++e) v[e] = rv[e * mR + (q - beg)];
                 const double *z = zd + (3 * (B.off3 + c)) * kBatch + 4 * sub;
                 for (int jj = 0; jj < 3; ++jj)
                     for (int b = 0; b < 4; ++b) {
-                        const double zz = z[jj * kBatch + b];
+                        const double zz = ((zb >> b) & 1u) ? z[jj * kBatch + b] : 0.0;
                         acc[0][b] = fma(v[jj], zz, acc[0][b]);
                         acc[1][b] = fma(v[3 + jj], zz, acc[1][b]);
                         acc[2][b] = fma(v[6 + jj], zz, acc[2][b]);
@@ -743,9 +943,13 @@ __global__ __launch_bounds__(256) void k_kzb_values(const KzBatch *__restrict__ 
             for (int i = 0; i < 3; ++i)
                 for (int64_t e = zp[3 * R + i]; e < zp[3 * R + i + 1]; ++e) {
                     const int32_t col = zc[e];
-                    atomicOr(&touched[B.bit0 + col / 32], 1u << (col % 32));
+                    atomicOr(&tb[col / 32], 1u << (col % 32));
                 }
     }
+    if (!lds_bits) return;
+    __syncthreads();
+    for (int t = threadIdx.x; t < words; t += 256)
+        if (tw[t]) atomicOr(&touched[B.bit0 + t], tw[t]);
 }
 
 // E_raw[j0+b, i] = sum over the structure rows t of the batch in the rows of z_i of
@@ -816,61 +1020,53 @@ __global__ void k_symmetrise(int32_t k, int64_t ld, const double *__restrict__ e
 }
 
 // ---------------------------------------------------------------- E^-1 by block Gauss-Jordan
-// P = S^-1 for the symmetric 32 x 32 pivot block S (LDS) by a right-looking Cholesky
-// S = L L^T, W = L^-1 and P = W^T W, using the whole workgroup with one barrier per
-// column: every thread recomputes the pivot, the scaled column goes to W's strict upper
-// triangle (unused) transposed, and the trailing update reads the unscaled column.
+// P = S^-1 for the symmetric positive definite 32 x 32 pivot block S (LDS) by in-place
+// Gauss-Jordan elimination without pivoting (on an SPD matrix its pivots are the Schur
+// complement pivots of the Cholesky factorisation).  Step k, pivot p = a_kk:
+//   a_rc -= a_rk a_kc / p (r, c != k),  a_kc /= p,  a_rk = -a_rk / p,  a_kk = 1 / p.
+// Thread (ty, tx) of the 256 keeps a[ty + 8q][tx], q < 4, in registers; only row k and
+// column k travel through LDS (W, ping-pong by step parity), one barrier per step.
 // Every pivot is tested against kdim * DBL_EPSILON times the original diagonal entry.
-// S and W are overwritten.
-__device__ void pivot_inverse(double *S, double *W, const double *diag0, int64_t gcol0, int32_t kdim, double *P,
+__device__ void pivot_inverse(const double *S, double *W, const double *diag0, int64_t gcol0, int32_t kdim, double *P,
                               int *fail) {
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    double *rowk = W, *colk = W + 2 * kNb;  // [parity][32] each
+    // thread j tests pivot j; its floor is loaded before the first barrier
+    const int64_t gmine = gcol0 + threadIdx.x;
+    const double myfl = ((int)threadIdx.x < kNb && gmine < kdim) ? (double)kdim * DBL_EPSILON * fabs(diag0[gmine]) : 0.0;
+    double a[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = ty + 8 * q;
+        a[q] = S[r * kNb + tx];
+        if (r == 0) rowk[tx] = a[q];
+        if (tx == 0) colk[r] = a[q];
+    }
     bool bad = false;
-    for (int j = 0; j < kNb; ++j) {
-        __syncthreads();
-        const double d = S[j * kNb + j];
-        const int64_t g = gcol0 + j;
-        const double fl = g < kdim ? (double)kdim * DBL_EPSILON * fabs(diag0[g]) : 0.0;
-        if (!(d > fl) || !isfinite(d)) bad = true;
-        const double dd = d > 0.0 ? d : 1.0;
-        const double l = sqrt(dd), il = 1.0 / l, id = 1.0 / dd;
-        const int rem = kNb - j - 1;
-        // L[i][j] = S[i][j] / l kept in L's strict lower part of W (row j of the transpose)
-        if ((int)threadIdx.x < rem) W[j * kNb + j + 1 + threadIdx.x] = S[(j + 1 + threadIdx.x) * kNb + j] * il;
-        if (threadIdx.x == 0) W[j * kNb + j] = l;
-        for (int t = threadIdx.x; t < rem * rem; t += blockDim.x) {
-            const int i = j + 1 + t / rem, c = j + 1 + t % rem;
-            if (c <= i) S[i * kNb + c] -= S[i * kNb + j] * S[c * kNb + j] * id;
-        }
-    }
     __syncthreads();
-    // L (lower) from W's transposed storage into S
-    for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
-        const int i = t / kNb, j = t % kNb;
-        S[t] = (j <= i) ? W[j * kNb + i] : 0.0;
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) W[t] = (t / kNb == t % kNb) ? 1.0 : 0.0;
-    // W = L^-1 row by row; one barrier per row (scale and eliminate in separate halves)
-    for (int i = 0; i < kNb; ++i) {
-        __syncthreads();
-        const double il = 1.0 / S[i * kNb + i];
-        const int rows = kNb - i - 1;
-        // rows below: W[r][c] -= L[r][i] * (W[i][c] / L[i][i]) for c <= i, read before row i is scaled
-        for (int t = threadIdx.x; t < rows * (i + 1); t += blockDim.x) {
-            const int r = i + 1 + t / (i + 1), c = t % (i + 1);
-            W[r * kNb + c] -= S[r * kNb + i] * (W[i * kNb + c] * il);
+    for (int k = 0; k < kNb; ++k) {
+        const int cb = k & 1, nb = cb ^ 1;
+        const double p = rowk[cb * kNb + k];
+        if ((int)threadIdx.x == k && (!(p > myfl) || !isfinite(p))) bad = true;
+        const double ip = 1.0 / p;
+        const double kc = rowk[cb * kNb + tx];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = ty + 8 * q;
+            const double rk = colk[cb * kNb + r];
+            double v;
+            if (r == k) v = (tx == k) ? ip : kc * ip;
+            else if (tx == k) v = -rk * ip;
+            else v = fma(-rk * ip, kc, a[q]);
+            a[q] = v;
+            if (r == k + 1) rowk[nb * kNb + tx] = v;
+            if (tx == k + 1) colk[nb * kNb + r] = v;
         }
         __syncthreads();
-        if ((int)threadIdx.x <= i) W[i * kNb + threadIdx.x] *= il;
     }
-    __syncthreads();
-    for (int t = threadIdx.x; t < kNb * kNb; t += blockDim.x) {
-        const int i = t / kNb, j = t % kNb;
-        double sacc = 0.0;
-        for (int p = max(i, j); p < kNb; ++p) sacc += W[p * kNb + i] * W[p * kNb + j];
-        P[t] = sacc;
-    }
-    if (bad && threadIdx.x == 0) atomicOr(fail, 1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) P[(ty + 8 * q) * kNb + tx] = a[q];
+    if (bad) atomicOr(fail, 1);
 }
 
 __global__ __launch_bounds__(256) void k_gj_first_pivot(const double *__restrict__ A, int64_t ld, int32_t kdim,
@@ -1041,9 +1237,10 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
         double *mxp = nullptr;
         HT(pool.tmp(&mxp, nmx));
         hipLaunchKernelGGL(k_maxabs_part, dim3(nmx), dim3(256), 0, s, kv, nnz, mxp);
+        hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, mxp, nmx);
         HT(hipGetLastError());
         maxpart = mxp;
-        nmaxpart = nmx;
+        nmaxpart = 1;  // the maximum over all partials, in mxp[0]
     }
     // ---- block-CSR counts, block-Jacobi offsets, Z^T, windows ----
     const int32_t nb = c->nb;
@@ -1053,7 +1250,7 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(pool.tmp(&bptr64, nb + 1));
     HT(pool.tmp(&part, scan_parts));
     hipLaunchKernelGGL((k_bsr<false>), dim3(grid_for(nb, 4)), dim3(256), 0, s, nb, kp, kc, kv, cnt, nullptr, nullptr,
-                       nullptr);
+                       nullptr, nullptr);
     HT(scan(s, cnt, nb, bptr64, part));
     int64_t *moff = nullptr, *sq = nullptr;
     HT(pool.tmp(&moff, nblocks + 1));
@@ -1066,25 +1263,31 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     int32_t *zti = nullptr;
     double *ztv = nullptr;
     if (k > 0) {
-        int64_t *ccount = nullptr, *fill = nullptr, *part3 = nullptr;
-        int32_t *zti_u = nullptr;
-        double *ztv_u = nullptr;
-        HT(pool.tmp(&ccount, k));
-        HT(pool.tmp(&fill, k));
-        HT(pool.tmp(&part3, scan_parts));
+        // chunks of Z's entries: at most 1024, and at most 4M (column, chunk) pairs
+        const int64_t nch_cap = std::max<int64_t>(1, std::min<int64_t>(1024, ((int64_t)1 << 22) / k));
+        const int64_t per = std::max<int64_t>(256, (nnz_z + nch_cap - 1) / nch_cap);
+        const int nch = (int)std::max<int64_t>(1, (nnz_z + per - 1) / per);
+        const int nranges = (int)((k + kZtCols - 1) / kZtCols);
+        const int64_t pairs = (int64_t)k * nch;
+        int64_t *cnt = nullptr, *off = nullptr, *part3 = nullptr;
+        int32_t *erow = nullptr;
+        HT(pool.tmp(&cnt, pairs));
+        HT(pool.tmp(&off, pairs + 1));
+        HT(pool.tmp(&part3, pairs / kScanChunk + 2));
+        HT(pool.tmp(&erow, nnz_z));
         HT(pool.tmp(&ztp, k + 1));
-        HT(pool.tmp(&zti_u, nnz_z));
-        HT(pool.tmp(&ztv_u, nnz_z));
         HT(keep(c, &c->zt_idx, nnz_z));
         HT(keep(c, &c->zt_val, nnz_z));
         zti = c->zt_idx;
         ztv = c->zt_val;
-        HT(hipMemsetAsync(ccount, 0, sizeof(int64_t) * k, s));
-        HT(hipMemsetAsync(fill, 0, sizeof(int64_t) * k, s));
-        hipLaunchKernelGGL(k_col_count, dim3(grid_for(nnz_z)), dim3(256), 0, s, nnz_z, zc, ccount);
-        HT(scan(s, ccount, k, ztp, part3));
-        hipLaunchKernelGGL(k_col_place, dim3(grid_for(n)), dim3(256), 0, s, n, zp, zc, zv, ztp, fill, zti_u, ztv_u);
-        hipLaunchKernelGGL(k_seg_sort, dim3(k), dim3(256), 0, s, ztp, zti_u, ztv_u, zti, ztv);
+        const int cols_lds = std::min<int>(k, kZtCols);
+        hipLaunchKernelGGL(k_entry_rows, dim3(grid_for(n)), dim3(256), 0, s, n, zp, erow);
+        hipLaunchKernelGGL(k_zt_count, dim3(nch, nranges), dim3(256), sizeof(int32_t) * cols_lds, s, nnz_z, per, nch,
+                           k, zc, cnt);
+        HT(scan(s, cnt, pairs, off, part3));
+        hipLaunchKernelGGL(k_zt_ptr, dim3(grid_for(k + 1)), dim3(256), 0, s, k, nch, off, ztp);
+        hipLaunchKernelGGL(k_zt_place, dim3(nch, nranges), dim3(64), sizeof(int64_t) * cols_lds, s, nnz_z, per, nch, k,
+                           zc, zv, erow, off, zti, ztv);
         HT(pool.tmp(&wlo, k));
         HT(pool.tmp(&wsize, k));
         hipLaunchKernelGGL(k_kz_window, dim3(k), dim3(256), 0, s, k, ztp, zti, kp, kc, wlo, wsize);
@@ -1107,16 +1310,30 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(keep(c, &c->bcol, nnzb));
     HT(keep(c, &c->bval, 9 * (size_t)nnzb));
     HT(hipMemsetAsync(c->bval, 0, sizeof(double) * 9 * (size_t)nnzb, s));
+    int32_t *brow = nullptr;
+    HT(pool.tmp(&brow, nnzb));
     hipLaunchKernelGGL((k_bsr<true>), dim3(grid_for(nb, 4)), dim3(256), 0, s, nb, kp, kc, kv, nullptr, c->brow_ptr,
-                       c->bcol, c->bval);
-    hipLaunchKernelGGL(k_check_sym, dim3(grid_for(nnzb, 256, 16384)), dim3(256), 0, s, nb, c->brow_ptr, c->bcol,
-                       c->bval, nnzb, maxpart, nmaxpart, flags);
+                       c->bcol, c->bval, brow);
+    {
+        const int gsym = (grid_for(nnzb, 256, 16384) + 7) / 8 * 8;
+        int64_t *sympart = nullptr;
+        int *need = nullptr;
+        HT(pool.tmp(&sympart, 2 * (int64_t)gsym));
+        HT(pool.tmp(&need, 1));
+        hipLaunchKernelGGL(k_check_sym, dim3(gsym), dim3(256), 0, s, c->brow_ptr, brow, c->bcol, c->bval, nnzb,
+                           maxpart, nmaxpart, flags, sympart);
+        hipLaunchKernelGGL(k_sym_reduce, dim3(1), dim3(256), 0, s, sympart, gsym, need);
+        hipLaunchKernelGGL(k_check_sym_lower, dim3(gsym), dim3(256), 0, s, c->brow_ptr, brow, c->bcol, c->bval, nnzb,
+                           maxpart, nmaxpart, flags, need);
+    }
     HT(keep(c, &c->minv, tot[1]));
     HT(keep(c, &c->bj_rowoff, n));
     HT(keep(c, &c->bj_meta, n));
     int *bjbad = flags + 1;  // reuse: Z's flag is known to be clear
-    hipLaunchKernelGGL(k_bj_factor, dim3(nblocks), dim3(64), 0, s, nblocks, bp, kp, kc, kv, moff, c->minv,
+    hipLaunchKernelGGL(k_bj_small, dim3(grid_for(nblocks)), dim3(256), 0, s, nblocks, bp, kp, kc, kv, moff, c->minv,
                        c->bj_rowoff, c->bj_meta, bjbad);
+    hipLaunchKernelGGL(k_bj_factor, dim3(std::min<int32_t>(nblocks, 4096)), dim3(64), 0, s, nblocks, bp, kp, kc, kv,
+                       moff, c->minv, c->bj_rowoff, c->bj_meta, bjbad);
     c->bj_ntiles = (int32_t)((n + kTileDofs - 1) / kTileDofs);
     HT(keep(c, &c->bj_wg_start, c->bj_ntiles + 1));
     hipLaunchKernelGGL(k_tiles, dim3(grid_for(c->bj_ntiles + 1)), dim3(256), 0, s, c->bj_ntiles, nblocks, bp, n,
@@ -1205,7 +1422,7 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
         };
         auto prepare = [&](int g0, int g1) {
             const dim3 gs(max_slices(g0, g1), g1 - g0);
-            hipLaunchKernelGGL(k_kzb_init, gs, dim3(256), 0, s, bt_d + g0, words, zd, kd, mk, rbits, touched);
+            hipLaunchKernelGGL(k_kzb_init, gs, dim3(256), 0, s, bt_d + g0, words, mk, rbits, touched);
             hipLaunchKernelGGL(k_kzb_scatter, dim3(kBatch, g1 - g0), dim3(256), 0, s, bt_d + g0, ztp, zti, ztv, zd,
                                rbits);
             hipLaunchKernelGGL(k_kzb_mark, gs, dim3(256), 0, s, bt_d + g0, c->brow_ptr, c->bcol, rbits, mk);
@@ -1243,8 +1460,8 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
             hipLaunchKernelGGL(k_kzb_rank, dim3(max_slices(g0, g1), g1 - g0), dim3(256), 0, s, bt_d + g0, mk, soff,
                                icnt, kzp, items);
             hipLaunchKernelGGL(k_kzb_values, dim3(128, g1 - g0), dim3(256),
-                               0, s, bt_d + g0, nitems + g0, items, c->brow_ptr, c->bcol, c->bval, zd, zp, zc,
-                               c->kzt_idx, c->kzt_val, kd, touched);
+                               0, s, bt_d + g0, nitems + g0, items, c->brow_ptr, c->bcol, c->bval, zd, rbits, zp, zc,
+                               c->kzt_idx, c->kzt_val, kd, words, touched);
             hipLaunchKernelGGL(k_kzb_erows, dim3((k + 3) / 4, g1 - g0), dim3(256), 0, s, bt_d + g0, k, ztp, zti, ztv,
                                kd, mk, touched, eraw, ld);
         }

@@ -237,6 +237,42 @@ def _solver_from_dense(K, Z, bp):
                     t(Zs.data, torch.float64), t(bp, torch.int32))
 
 
+def _with_entry(K, i, j, v):
+    """CSR copy of K with the structurally absent entry (i, j) stored explicitly as v."""
+    import scipy.sparse as sp
+    A = K.tocoo()
+    B = sp.csr_matrix((np.append(A.data, v), (np.append(A.row, i), np.append(A.col, j))), shape=K.shape)
+    B.sort_indices()
+    assert B.nnz == K.nnz + 1
+    return B
+
+
+def test_setup_structural_asymmetry(problems):
+    """A stored entry whose mirror block is absent: nonzero values are rejected from
+    either side of the diagonal; an explicit zero is symmetric in value and solves as K."""
+    p = problems("edge4")
+    K = p.K_scipy().tocsr()
+    Z = p.Z_scipy().toarray()
+    bp = p.block_ptr
+    i, j = p.n - 3, 0
+    assert K[i, j] == 0 and K[j, i] == 0 and K[i].indices.min() > 2
+    for a, b in ((i, j), (j, i)):
+        with pytest.raises(D.DpcgError) as e:
+            _solver_from_dense(_with_entry(K, a, b, 1.0), Z, bp)
+        assert e.value.code == D.abi.ENOTSYM
+    f = dev(p.f)
+    s0 = _solver_from_dense(K, Z, bp)
+    s1 = _solver_from_dense(_with_entry(K, i, j, 0.0), Z, bp)
+    u0, i0 = s0.solve(f)
+    u1, i1 = s1.solve(f)
+    assert s1.stats()["nnzb"] == s0.stats()["nnzb"] + 1
+    assert i0["iterations"] == i1["iterations"]
+    # only the summation order of the extra zero block differs
+    assert np.abs(host(u1) - host(u0)).max() <= 1e-9 * np.abs(host(u0)).max()
+    s0.close()
+    s1.close()
+
+
 def test_no_deflation_and_point_jacobi(problems):
     p = problems("plain6")
     K = p.K_scipy()
