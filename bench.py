@@ -22,6 +22,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes moved by one k_spmv_p launch on penny40, from two rocprofv3 --pmc passes
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the launches of iterations
+# that did work), each scaled by what the same counter reads for a 512 MiB device copy
+# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources with these
+# digests: after any change to them the figure is reported as null until re-measured.
+SPMV_TRAFFIC = {
+    "workload": "penny40",
+    "sources": {
+        "paper_2111_09294_amd/csrc/kernels.hip": "78012adb34556213860f69074435c4c36917ac6138796cd0a3e9489a3d05606f",
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "e55245df85dd9e6ba0465007797e6bae97f6d233f941bfb11299061a9d3a73aa"
+    },
+    "fetch_bytes": 178212915,
+    "write_bytes": 3764144,
+}
+
+
+def _source_digests():
+    import hashlib
+    out = {}
+    for rel in ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h"):
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            out[rel] = hashlib.sha256(fh.read()).hexdigest()
+    return out
+
+
+def spmv_traffic(workload):
+    """Counter-measured HBM bytes per k_spmv_p launch, or None when the kernel sources
+    changed since the counters were taken (or for another workload)."""
+    t = SPMV_TRAFFIC
+    if workload != t["workload"] or t["fetch_bytes"] is None or _source_digests() != t["sources"]:
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
 METRIC = "DoF-solves/sec to rel. residual 1e-8 + SpMV HBM GB/s fraction; FP64 vs mixed/batched"
 WORKLOADS = {
     "penny40": "40^3 hex8 unit cube, curved penny crack (R=0.25, z=0.5+0.3 rho^2), Heaviside + branch "
@@ -155,7 +188,7 @@ def main():
         "solve_only_dof_solves_per_s": p.n / (solve_ms / 1e3),
         "rel_res_true": infos[-1]["rel_res_true"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": spmv_traffic(args.workload),
                      "kernel": "k_spmv_p", "bytes_per_launch": nbytes, "launches": spmv_n,
                      "avg_launch_us": per_launch_s * 1e6},
     }

@@ -248,11 +248,9 @@ int enqueue_iteration(dpcg_ctx *c, Workspace &w, double *u, int max_iter, int re
     if (c->timing) {
         hipEvent_t a, b;
         TRY(next_event_pair(c, &a, &b));
-        HIP_TRY(hipEventRecord(a, c->stream));
-        LAUNCH(launch_spmv_p(c, w));
-        HIP_TRY(hipEventRecord(b, c->stream));
+        LAUNCH(launch_spmv_p(c, w, a, b));
     } else {
-        LAUNCH(launch_spmv_p(c, w));
+        LAUNCH(launch_spmv_p(c, w, nullptr, nullptr));
     }
     LAUNCH(launch_update_bj(c, u, w));
     LAUNCH(launch_restrict(c, w.r, w.y, w.g, &w, 1, c->bj_nwg, 1, max_iter, record));

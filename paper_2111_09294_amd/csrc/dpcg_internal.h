@@ -118,7 +118,8 @@ hipError_t launch_check_finite_norm(const dpcg_ctx *c, const double *a, const do
 hipError_t launch_spmv_plain(const dpcg_ctx *c, const double *x, double *y);
 hipError_t launch_spmv_residual(const dpcg_ctx *c, const double *x, const double *f, double *r,
                                 double *part, Workspace &w, int check);
-hipError_t launch_spmv_p(const dpcg_ctx *c, Workspace &w);
+// ev0, ev1 (may be null): events that record the kernel's start and end
+hipError_t launch_spmv_p(const dpcg_ctx *c, Workspace &w, hipEvent_t ev0, hipEvent_t ev1);
 hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w);
 hipError_t launch_beta(const dpcg_ctx *c, Workspace &w);
 hipError_t launch_bj(const dpcg_ctx *c, const double *r, double *y, Workspace *w);

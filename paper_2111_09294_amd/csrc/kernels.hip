@@ -12,6 +12,8 @@
 // sequential-per-thread + fixed-tree sum), so results are bitwise reproducible.  No
 // floating-point atomics are used.  Convergence and breakdown are decided on the
 // device; every kernel returns at once when the state flag is set.
+#include <hip/hip_ext.h>
+
 #include "dpcg_internal.h"
 
 namespace dpcg {
@@ -475,10 +477,11 @@ __global__ __launch_bounds__(kThreads) void k_reduce_aux(const double *__restric
 }
 
 template <int G>
-hipError_t spmv_p_g(const dpcg_ctx *c, Workspace &w) {
+hipError_t spmv_p_g(const dpcg_ctx *c, Workspace &w, hipEvent_t ev0, hipEvent_t ev1) {
     SpmvShape sh{c->nb, c->spmv.steps, c->spmv.nwg};
-    hipLaunchKernelGGL(k_spmv_p<G>, dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, sh, c->brow_ptr, c->bcol,
-                       c->bval, c->nnzb, w.z, w.p[0], w.p[1], w.q, w.part_a, w.st);
+    // the events (when given) take the kernel's own start and end timestamps
+    hipExtLaunchKernelGGL(k_spmv_p<G>, dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, ev0, ev1, 0, sh,
+                          c->brow_ptr, c->bcol, c->bval, c->nnzb, w.z, w.p[0], w.p[1], w.q, w.part_a, w.st);
     return hipGetLastError();
 }
 
@@ -492,12 +495,12 @@ hipError_t spmv_g(const dpcg_ctx *c, const double *x, const double *f, double *y
 
 }  // namespace
 
-hipError_t launch_spmv_p(const dpcg_ctx *c, Workspace &w) {
+hipError_t launch_spmv_p(const dpcg_ctx *c, Workspace &w, hipEvent_t ev0, hipEvent_t ev1) {
     switch (c->spmv.group) {
-        case 4: return spmv_p_g<4>(c, w);
-        case 8: return spmv_p_g<8>(c, w);
-        case 32: return spmv_p_g<32>(c, w);
-        default: return spmv_p_g<16>(c, w);
+        case 4: return spmv_p_g<4>(c, w, ev0, ev1);
+        case 8: return spmv_p_g<8>(c, w, ev0, ev1);
+        case 32: return spmv_p_g<32>(c, w, ev0, ev1);
+        default: return spmv_p_g<16>(c, w, ev0, ev1);
     }
 }
 
