@@ -43,11 +43,20 @@ enum {
 
 typedef struct dpcg_ctx *dpcg_handle;
 
+enum {
+    DPCG_PREC_FP64 = 0,        /* every step in binary64                                 */
+    DPCG_PREC_MIXED = 1        /* FP32-stored K and block inverses inside FP64 refinement */
+};
+
 typedef struct {
     int32_t max_iter;          /* iteration cap (K p products); default 20000            */
     int32_t check_every;       /* iterations enqueued between host polls; default 16     */
     int32_t use_initial_guess; /* 1: u (or lambda) holds u_{-1} of Algorithm 2 on entry */
     int32_t record_history;    /* 1: keep ||r_i||/||f|| for i = 0..iterations            */
+    int32_t precision;         /* DPCG_PREC_FP64 (default) or DPCG_PREC_MIXED            */
+    int32_t max_refinements;   /* mixed: cap on refinement cycles; default 50            */
+    double inner_tol;          /* mixed: each inner solve reduces its residual by this
+                                  factor (0 < inner_tol < 1); default 1e-4               */
 } dpcg_options;
 
 typedef struct {
@@ -58,6 +67,8 @@ typedef struct {
     double setup_ms;           /* wall time of dpcg_setup                               */
     double solve_ms;           /* wall time of the last solve                           */
     int64_t bad_index;         /* offending block / row / iteration, or -1              */
+    int32_t refinements;       /* mixed: refinement cycles (inner solves); FP64: 0      */
+    int32_t pad_;
 } dpcg_info;
 
 typedef struct {
@@ -118,7 +129,20 @@ int dpcg_setup(dpcg_handle *h, int64_t n,
  * (u_{-1}) when opt->use_initial_guess.  f = 0 gives u = 0 after 0 iterations.
  * opt may be NULL (defaults).  Returns DPCG_OK, DPCG_NOT_CONVERGED (u holds the
  * last iterate), DPCG_EBREAKDOWN (bad_index = iteration), DPCG_ENONFINITE,
- * DPCG_EINVAL (tol <= 0 or max_iter < 0) or DPCG_EHIP.
+ * DPCG_EINVAL (tol <= 0, max_iter < 0, inner_tol outside (0, 1) or an unknown
+ * precision) or DPCG_EHIP.
+ *
+ * precision = DPCG_PREC_MIXED (an extension beyond the paper's FP64 method):
+ * iterative refinement in FP64 around the same method run on binary32 copies of
+ * K's values and of the block-Jacobi inverses (vectors, E^-1 and all arithmetic
+ * stay binary64).  Each cycle solves K d = r_j for the current FP64 residual
+ * r_j = f - K u_j (FP64 K) to ||r_j - K32 d|| <= inner_tol ||r_j||, then sets
+ * u_{j+1} = u_j + d.  The solve stops when ||f - K u_j||_2 <= tol ||f||_2 (a true
+ * residual, so rel_res_recursive = rel_res_true), or with DPCG_NOT_CONVERGED
+ * after max_iter inner iterations in total or max_refinements cycles.
+ * iterations counts the inner K p products; the history (record_history) holds
+ * ||f - K u_j|| / ||f|| per cycle, j = 0..refinements.  The FP32 copies are made
+ * on the first mixed solve of a handle (9 nnzb + sum b^2 floats).
  */
 int dpcg_solve(dpcg_handle h, const double *f, double *u, double tol,
                const dpcg_options *opt, dpcg_info *info);
@@ -161,6 +185,13 @@ int dpcg_get_timing(dpcg_handle h, dpcg_timing *out);
 
 /* y = K x (Algorithm 1's K p_i) with the block-CSR kernel.  x, y: device, n. */
 int dpcg_spmv(dpcg_handle h, const double *x, double *y);
+
+/* y = K32 x, the product the inner solves of DPCG_PREC_MIXED use: K's values
+ * rounded to binary32, products and sums in binary64. */
+int dpcg_spmv_fp32(dpcg_handle h, const double *x, double *y);
+
+/* y = M32^{-1} r with the block inverses rounded to binary32 (mixed inner solves). */
+int dpcg_bj_apply_fp32(dpcg_handle h, const double *r, double *y);
 
 /* y = M^{-1} r, the block-Jacobi apply inside Algorithm 3 (eq. block_jacobi). */
 int dpcg_bj_apply(dpcg_handle h, const double *r, double *y);

@@ -16,18 +16,23 @@ OK, NOT_CONVERGED, EINVAL, ENOTSYM, EBLOCK_NOT_SPD, ECOARSE_NOT_SPD, EBREAKDOWN,
     0, 1, -1, -2, -3, -4, -5, -6, -7)
 
 
+PREC_FP64, PREC_MIXED = 0, 1
+PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
+
+
 class Options(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("check_every", C.c_int32), ("use_initial_guess", C.c_int32),
-                ("record_history", C.c_int32)]
+                ("record_history", C.c_int32), ("precision", C.c_int32), ("max_refinements", C.c_int32),
+                ("inner_tol", C.c_double)]
 
 
 class Info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("rel_res_recursive", C.c_double),
                 ("rel_res_true", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
-                ("bad_index", C.c_int64)]
+                ("bad_index", C.c_int64), ("refinements", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
 
 
 class Stats(C.Structure):
@@ -63,7 +68,9 @@ SIGNATURES = {
     "dpcg_set_timing": (C.c_int, [P, C.c_int32]),
     "dpcg_get_timing": (C.c_int, [P, C.POINTER(Timing)]),
     "dpcg_spmv": (C.c_int, [P, P, P]),
+    "dpcg_spmv_fp32": (C.c_int, [P, P, P]),
     "dpcg_bj_apply": (C.c_int, [P, P, P]),
+    "dpcg_bj_apply_fp32": (C.c_int, [P, P, P]),
     "dpcg_restrict": (C.c_int, [P, P, P, P]),
     "dpcg_coarse_apply": (C.c_int, [P, P, P]),
     "dpcg_prolong": (C.c_int, [P, P, P, P]),
@@ -184,7 +191,7 @@ class Solver:
         return self._h
 
     # ------------------------------------------------------------------ solves
-    def _opts(self, max_iter, check_every, guess, record):
+    def _opts(self, max_iter, check_every, guess, record, precision="fp64", inner_tol=None, max_refinements=None):
         o = Options()
         lib().dpcg_default_options(C.byref(o))
         if max_iter is not None:
@@ -193,9 +200,17 @@ class Solver:
             o.check_every = int(check_every)
         o.use_initial_guess = int(bool(guess))
         o.record_history = int(bool(record))
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        o.precision = PRECISIONS[precision]
+        if inner_tol is not None:
+            o.inner_tol = float(inner_tol)
+        if max_refinements is not None:
+            o.max_refinements = int(max_refinements)
         return o
 
-    def _run(self, fn, where, f, u, tol, max_iter, check_every, initial_guess, record_history, raise_on_error):
+    def _run(self, fn, where, f, u, tol, max_iter, check_every, initial_guess, record_history, raise_on_error,
+             precision="fp64", inner_tol=None, max_refinements=None):
         import torch
         _check_dev(f, torch.float64, "rhs", self.n)
         if u is None:
@@ -205,7 +220,8 @@ class Solver:
             _check_dev(initial_guess, torch.float64, "initial_guess", self.n)
             if initial_guess.data_ptr() != u.data_ptr():
                 u.copy_(initial_guess)
-        o = self._opts(max_iter, check_every, initial_guess is not None, record_history)
+        o = self._opts(max_iter, check_every, initial_guess is not None, record_history, precision, inner_tol,
+                       max_refinements)
         info = Info()
         st = fn(self.handle, _ptr(f), _ptr(u), float(tol), C.byref(o), C.byref(info))
         if st < 0 and raise_on_error:
@@ -213,16 +229,18 @@ class Solver:
         return u, info.as_dict()
 
     def solve(self, f, u=None, tol=1e-8, max_iter=None, check_every=None, initial_guess=None,
-              record_history=False, raise_on_error=True):
-        """u = K^{-1} f to ||r||/||f|| <= tol.  Returns (u, info dict)."""
+              record_history=False, raise_on_error=True, precision="fp64", inner_tol=None, max_refinements=None):
+        """u = K^{-1} f to ||r||/||f|| <= tol.  precision "mixed" runs FP64 iterative
+        refinement around inner solves on binary32 copies of K and the block inverses.
+        Returns (u, info dict)."""
         return self._run(lib().dpcg_solve, "dpcg_solve", f, u, tol, max_iter, check_every, initial_guess,
-                         record_history, raise_on_error)
+                         record_history, raise_on_error, precision, inner_tol, max_refinements)
 
     def solve_adjoint(self, g, lam=None, tol=1e-8, max_iter=None, check_every=None, initial_guess=None,
-                      raise_on_error=True):
+                      raise_on_error=True, precision="fp64", inner_tol=None, max_refinements=None):
         """lambda = K^{-1} g in the adjoint workspace.  Returns (lambda, info dict)."""
         return self._run(lib().dpcg_solve_adjoint, "dpcg_solve_adjoint", g, lam, tol, max_iter, check_every,
-                         initial_guess, False, raise_on_error)
+                         initial_guess, False, raise_on_error, precision, inner_tol, max_refinements)
 
     def history(self):
         import numpy as np
@@ -269,6 +287,22 @@ class Solver:
         _check_dev(r, torch.float64, "r", self.n)
         y = torch.empty_like(r)
         self._call("dpcg_bj_apply", r, y)
+        return y
+
+    def spmv_fp32(self, x, y=None):
+        """y = K32 x: K's values rounded to binary32, FP64 arithmetic."""
+        import torch
+        _check_dev(x, torch.float64, "x", self.n)
+        y = torch.empty_like(x) if y is None else y
+        self._call("dpcg_spmv_fp32", x, y)
+        return y
+
+    def bj_apply_fp32(self, r):
+        """y = M32^{-1} r with the block inverses rounded to binary32."""
+        import torch
+        _check_dev(r, torch.float64, "r", self.n)
+        y = torch.empty_like(r)
+        self._call("dpcg_bj_apply_fp32", r, y)
         return y
 
     def restrict(self, a, b=None):

@@ -175,6 +175,8 @@ void fill_info(dpcg_info *info, int status, int32_t iters, double rr, double rt,
     info->setup_ms = setup_ms;
     info->solve_ms = solve_ms;
     info->bad_index = bad;
+    info->refinements = 0;
+    info->pad_ = 0;
 }
 
 int ensure_history(dpcg_ctx *c, Workspace &w, int64_t need) {
@@ -260,6 +262,108 @@ int enqueue_iteration(dpcg_ctx *c, Workspace &w, double *u, int max_iter, int re
     return DPCG_OK;
 }
 
+// Algorithm 1 from the start of Algorithm 2 on workspace w until the device flag leaves
+// kRunning (thr: absolute threshold on ||r_i||).  st receives the final state, with
+// iters_done set also when the loop ended by the host-side cap (max_iter == 0).
+int run_cg(dpcg_ctx *c, Workspace &w, const double *f, double *u, double thr, bool guess, int max_iter,
+           int check_every, int record, State &st) {
+    State init{};
+    init.flag = kRunning;
+    init.thr = thr;
+    *w.snap = init;
+    HIP_TRY(hipMemcpyAsync(w.st, w.snap, sizeof(State), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->events_used = 0;
+    TRY(enqueue_start(c, w, f, u, guess, max_iter, record));
+    TRY(read_state(c, w, st));
+    int32_t enq = 0;
+    while (st.flag == kRunning && enq < max_iter) {
+        const int m = std::min(check_every, max_iter - enq);
+        for (int i = 0; i < m; ++i) TRY(enqueue_iteration(c, w, u, max_iter, record));
+        enq += m;
+        TRY(read_state(c, w, st));
+    }
+    if (st.flag == kRunning) st.iters_done = enq;
+    if (c->timing) TRY(collect_events(c, st.iters_done));
+    return DPCG_OK;
+}
+
+// r = f - K u with FP64 K; *rn = ||r||_2.
+int true_residual(dpcg_ctx *c, Workspace &w, const double *f, const double *u, double *r, double *rn) {
+    LAUNCH(launch_spmv_residual(c, u, f, r, w.part_a, w, 0));
+    LAUNCH(launch_reduce_aux(c, w, c->spmv.nwg));
+    State fin;
+    TRY(read_state(c, w, fin));
+    *rn = std::sqrt(fin.aux);
+    return DPCG_OK;
+}
+
+// binary32 copies of K's block values and of the block inverses (same layouts)
+int ensure_fp32(dpcg_ctx *c) {
+    if (c->bval32) return DPCG_OK;
+    float *bv = nullptr, *mi = nullptr;
+    TRY(alloc(c, &bv, 9 * (size_t)c->nnzb));
+    TRY(alloc(c, &mi, (size_t)std::max<int64_t>(1, c->bj_values)));
+    LAUNCH(launch_to_f32(c, c->bval, 9 * c->nnzb, bv));
+    LAUNCH(launch_to_f32(c, c->minv, c->bj_values, mi));
+    c->bval32 = bv;
+    c->minv32 = mi;
+    return DPCG_OK;
+}
+
+// Iterative refinement: FP64 residuals r_j = f - K u_j, inner solves K32 d = r_j by the
+// same method on the binary32 copies, u_{j+1} = u_j + d.
+int solve_mixed(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol, const dpcg_options &opt,
+                double fnorm, double t0, dpcg_info *info) {
+    TRY(ensure_fp32(c));
+    if (!w.rout) {
+        TRY(alloc(c, &w.rout, (size_t)c->n));
+        TRY(alloc(c, &w.dcor, (size_t)c->n));
+    }
+    if (!opt.use_initial_guess) HIP_TRY(hipMemsetAsync(u, 0, sizeof(double) * c->n, c->stream));
+    double rn = 0.0;
+    TRY(true_residual(c, w, f, u, w.rout, &rn));
+    std::vector<double> hist(1, rn / fnorm);
+    int32_t total = 0, cycles = 0;
+    int status = DPCG_NOT_CONVERGED;
+    int64_t bad = -1;
+    while (true) {
+        if (!std::isfinite(rn)) {
+            status = DPCG_EBREAKDOWN;
+            bad = total;
+            break;
+        }
+        if (rn <= tol * fnorm) {
+            status = DPCG_OK;
+            break;
+        }
+        if (total >= opt.max_iter || cycles >= opt.max_refinements) break;
+        State st;
+        c->inner32 = true;
+        const int e = run_cg(c, w, w.rout, w.dcor, opt.inner_tol * rn, false, opt.max_iter - total,
+                             opt.check_every, 0, st);
+        c->inner32 = false;
+        TRY(e);
+        total += st.iters_done;
+        ++cycles;
+        if (st.flag == kBreakdown) {
+            status = DPCG_EBREAKDOWN;
+            bad = total;
+            break;
+        }
+        LAUNCH(launch_add(c, w.dcor, u));
+        TRY(true_residual(c, w, f, u, w.rout, &rn));
+        hist.push_back(rn / fnorm);
+    }
+    if (opt.record_history) {
+        w.host_hist = hist;
+        w.hist_len = (int32_t)hist.size();
+    }
+    fill_info(info, status, total, rn / fnorm, rn / fnorm, c->setup_ms, now_ms() - t0, bad);
+    if (info) info->refinements = cycles;
+    return status;
+}
+
 int solve_impl(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol, const dpcg_options *opt_in,
                dpcg_info *info) {
     const double t0 = now_ms();
@@ -267,12 +371,16 @@ int solve_impl(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol
     dpcg_default_options(&opt);
     if (opt_in) opt = *opt_in;
     if (!c || !f || !u || !(tol > 0.0) || opt.max_iter < 0) return DPCG_EINVAL;
+    const bool mixed = opt.precision == DPCG_PREC_MIXED;
+    if (!mixed && opt.precision != DPCG_PREC_FP64) return DPCG_EINVAL;
+    if (mixed && (!(opt.inner_tol > 0.0 && opt.inner_tol < 1.0) || opt.max_refinements < 0)) return DPCG_EINVAL;
     if (opt.check_every <= 0) opt.check_every = 16;
     const bool guess = opt.use_initial_guess != 0;
     const int record = opt.record_history != 0;
-    if (record) TRY(ensure_history(c, w, (int64_t)opt.max_iter + 1));
+    if (record && !mixed) TRY(ensure_history(c, w, (int64_t)opt.max_iter + 1));
     w.hist_len = 0;
     c->events_used = 0;
+    c->inner32 = false;
     // ||f||^2 and the finiteness of the inputs
     LAUNCH(launch_check_finite_norm(c, f, guess ? u : nullptr, w));
     State s0;
@@ -287,36 +395,19 @@ int solve_impl(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol
         return DPCG_OK;
     }
     const double fnorm = std::sqrt(ff);
-    State init{};
-    init.flag = kRunning;
-    init.thr = tol * fnorm;
-    *w.snap = init;
-    HIP_TRY(hipMemcpyAsync(w.st, w.snap, sizeof(State), hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    TRY(enqueue_start(c, w, f, u, guess, opt.max_iter, record));
+    if (mixed) return solve_mixed(c, w, f, u, tol, opt, fnorm, t0, info);
     State st;
-    TRY(read_state(c, w, st));
-    int32_t enq = 0;
-    while (st.flag == kRunning && enq < opt.max_iter) {
-        const int m = std::min(opt.check_every, opt.max_iter - enq);
-        for (int i = 0; i < m; ++i) TRY(enqueue_iteration(c, w, u, opt.max_iter, record));
-        enq += m;
-        TRY(read_state(c, w, st));
-    }
+    TRY(run_cg(c, w, f, u, tol * fnorm, guess, opt.max_iter, opt.check_every, record, st));
     int status;
     int64_t bad = -1;
     switch (st.flag) {
         case kConverged: status = DPCG_OK; break;
-        case kMaxIter: status = DPCG_NOT_CONVERGED; break;
         case kBreakdown: status = DPCG_EBREAKDOWN; bad = st.bad; break;
-        default: status = DPCG_NOT_CONVERGED; st.iters_done = enq; break;  // max_iter == 0 after a failed check
+        default: status = DPCG_NOT_CONVERGED; break;  // cap reached (on the device or by the host)
     }
-    if (c->timing) TRY(collect_events(c, st.iters_done));
     // true residual ||f - K u|| / ||f||
-    LAUNCH(launch_spmv_residual(c, u, f, w.tmp, w.part_a, w, 0));
-    LAUNCH(launch_reduce_aux(c, w, c->spmv.nwg));
-    State fin;
-    TRY(read_state(c, w, fin));
+    double rt = 0.0;
+    TRY(true_residual(c, w, f, u, w.tmp, &rt));
     if (record) {
         const int64_t len = (int64_t)st.iters_done + 1;
         w.host_hist.resize(len);
@@ -324,8 +415,7 @@ int solve_impl(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol
         for (auto &v : w.host_hist) v /= fnorm;
         w.hist_len = (int32_t)len;
     }
-    fill_info(info, status, st.iters_done, std::sqrt(st.rr) / fnorm, std::sqrt(fin.aux) / fnorm, c->setup_ms,
-              now_ms() - t0, bad);
+    fill_info(info, status, st.iters_done, std::sqrt(st.rr) / fnorm, rt / fnorm, c->setup_ms, now_ms() - t0, bad);
     return status;
 }
 
@@ -339,6 +429,9 @@ void dpcg_default_options(dpcg_options *opt) {
     opt->check_every = 16;
     opt->use_initial_guess = 0;
     opt->record_history = 0;
+    opt->precision = DPCG_PREC_FP64;
+    opt->max_refinements = 50;
+    opt->inner_tol = 1e-4;
 }
 
 int dpcg_setup(dpcg_handle *h, int64_t n, const int64_t *k_rowptr, const int32_t *k_col, const double *k_val,
@@ -450,6 +543,26 @@ int dpcg_get_timing(dpcg_handle h, dpcg_timing *out) {
 int dpcg_spmv(dpcg_handle h, const double *x, double *y) {
     if (!h || !x || !y) return DPCG_EINVAL;
     SYNC_RET(launch_spmv_plain(h, x, y));
+}
+
+int dpcg_spmv_fp32(dpcg_handle h, const double *x, double *y) {
+    if (!h || !x || !y) return DPCG_EINVAL;
+    const int e = ensure_fp32(h);
+    if (e != DPCG_OK) return e;
+    h->inner32 = true;
+    const hipError_t he = launch_spmv_plain(h, x, y);
+    h->inner32 = false;
+    SYNC_RET(he);
+}
+
+int dpcg_bj_apply_fp32(dpcg_handle h, const double *r, double *y) {
+    if (!h || !r || !y) return DPCG_EINVAL;
+    const int e = ensure_fp32(h);
+    if (e != DPCG_OK) return e;
+    h->inner32 = true;
+    const hipError_t he = launch_bj(h, r, y, nullptr);
+    h->inner32 = false;
+    SYNC_RET(he);
 }
 
 int dpcg_bj_apply(dpcg_handle h, const double *r, double *y) {

@@ -60,6 +60,8 @@ struct Workspace {
     double *part_a = nullptr;   // partial sums (p^T q, r^T r, r^T z); sized max grid
     double *part_b = nullptr;
     double *part_c = nullptr;
+    double *rout = nullptr;     // mixed precision: FP64 residual f - K u of the refinement
+    double *dcor = nullptr;     // mixed precision: correction of one inner solve
     State *st = nullptr;        // device
     State *snap = nullptr;      // pinned host mirror
     double *hist = nullptr;     // device, ||r_i|| per iteration
@@ -84,6 +86,10 @@ struct dpcg_ctx {
     // K
     int32_t *brow_ptr = nullptr, *bcol = nullptr;
     double *bval = nullptr;
+    // FP32 copies (same layouts) for the inner solves of mixed precision; made on the
+    // first mixed solve.  inner32 selects them in the launchers while an inner solve runs.
+    float *bval32 = nullptr, *minv32 = nullptr;
+    bool inner32 = false;
     // block-Jacobi
     double *minv = nullptr;
     int32_t *bj_rowoff = nullptr, *bj_meta = nullptr, *bj_wg_start = nullptr;
@@ -129,6 +135,10 @@ hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Work
 hipError_t launch_prolong(const dpcg_ctx *c, const double *base, const double *delta, double *out,
                           Workspace *w, const double *rdot, int advance);
 hipError_t launch_reduce_aux(const dpcg_ctx *c, Workspace &w, int n_parts);
+// dst[i] = (float) src[i]
+hipError_t launch_to_f32(const dpcg_ctx *c, const double *src, int64_t count, float *dst);
+// y += x
+hipError_t launch_add(const dpcg_ctx *c, const double *x, double *y);
 
 // devmem.cpp: cached device allocations (release only after the using stream is idle).
 hipError_t dev_alloc(void **p, size_t bytes);

@@ -14,6 +14,8 @@
 // device; every kernel returns at once when the state flag is set.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "dpcg_internal.h"
 
 namespace dpcg {
@@ -97,15 +99,17 @@ struct XDirection {
 // q_R = sum_b K_Rb x_b for block row R, computed by a group of G lanes; the three
 // sums end up in every lane of the group.  Lanes of groups without a row pass
 // row = -1 and take part in the shuffles with zeros.
-template <int G, class XL>
+// V is the storage type of the block values (double, or float for the inner solves of
+// mixed precision); the arithmetic is FP64 either way.
+template <int G, class XL, class V>
 __device__ __forceinline__ void block_row(int row, int lg, const int32_t *__restrict__ brow_ptr,
-                                          const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+                                          const int32_t *__restrict__ bcol, const V *__restrict__ bval,
                                           int64_t nnzb, const XL &xl, double &a0, double &a1, double &a2) {
     a0 = a1 = a2 = 0.0;
     if (row >= 0) {
         const int beg = brow_ptr[row], end = brow_ptr[row + 1];
         const int64_t m = end - beg;
-        const double *rv = bval + 9 * (int64_t)beg - beg;  // plane e of block b: rv[e * m + b]
+        const V *rv = bval + 9 * (int64_t)beg - beg;  // plane e of block b: rv[e * m + b]
         for (int b = beg + lg; b < end; b += G) {
             const double v0 = rv[b], v1 = rv[m + b], v2 = rv[2 * m + b];
             const double v3 = rv[3 * m + b], v4 = rv[4 * m + b], v5 = rv[5 * m + b];
@@ -151,10 +155,10 @@ __device__ __forceinline__ double pick3(int lg, double a0, double a1, double a2)
 }
 
 // MODE 0: y = K x.   MODE 1: r = f - K x and ||r||^2 partials.
-template <int G, int MODE>
+template <int G, int MODE, class V>
 __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
                                                    const int32_t *__restrict__ bcol,
-                                                   const double *__restrict__ bval, int64_t nnzb,
+                                                   const V *__restrict__ bval, int64_t nnzb,
                                                    const double *__restrict__ x, const double *__restrict__ f,
                                                    double *__restrict__ y, double *__restrict__ part) {
     __shared__ double lds[kSpmvWaves];
@@ -189,10 +193,10 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvShape sh, const int32
 // p_i = z_i + beta_{i-1} p_{i-1} (p_0 = z_0; beta from the state), q = K p_i, and
 // partials of p_i^T q.  Only the single-workgroup kernels change the flag, so it is
 // stable while this kernel runs.
-template <int G>
+template <int G, class V>
 __global__ __launch_bounds__(kSpmvThreads) void k_spmv_p(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
                                                          const int32_t *__restrict__ bcol,
-                                                         const double *__restrict__ bval, int64_t nnzb,
+                                                         const V *__restrict__ bval, int64_t nnzb,
                                                          const double *__restrict__ z, double *p0, double *p1,
                                                          double *__restrict__ q, double *__restrict__ part_pq,
                                                          const State *st) {
@@ -261,12 +265,13 @@ __global__ __launch_bounds__(1024) void k_beta(const double *__restrict__ part_r
 }
 
 // y_d = sum_j Minv_B[d - s_B, j] r_{s_B + j} for the DoFs of this tile (whole blocks).
-__device__ __forceinline__ double bj_row(int t, int64_t d, const double *tile, const double *__restrict__ minv,
+template <class M>
+__device__ __forceinline__ double bj_row(int t, int64_t d, const double *tile, const M *__restrict__ minv,
                                          const int32_t *__restrict__ bj_rowoff,
                                          const int32_t *__restrict__ bj_meta) {
     const int meta = bj_meta[d];
     const int size = meta >> 8, loc = meta & 255;
-    const double *m = minv + bj_rowoff[d];
+    const M *m = minv + bj_rowoff[d];
     const double *rt = tile + (t - loc);
     double s = 0.0;
     for (int j = 0; j < size; ++j) s = fma(m[j], rt[j], s);
@@ -275,10 +280,11 @@ __device__ __forceinline__ double bj_row(int t, int64_t d, const double *tile, c
 
 // Step length, solution and residual updates of Algorithm 1 with the residual norm
 // partials, then the block-Jacobi apply y = M^{-1} r that opens Algorithm 3.
+template <class M>
 __global__ __launch_bounds__(kThreads) void k_update_bj(
     int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start, double *__restrict__ u,
     double *__restrict__ r, double *__restrict__ y, const double *__restrict__ q, const double *p0,
-    const double *p1, const double *__restrict__ minv, const int32_t *__restrict__ bj_rowoff,
+    const double *p1, const M *__restrict__ minv, const int32_t *__restrict__ bj_rowoff,
     const int32_t *__restrict__ bj_meta, double *__restrict__ part_rr, const State *st) {
     __shared__ double lds[4];
     __shared__ double tile[kThreads];
@@ -308,9 +314,10 @@ __global__ __launch_bounds__(kThreads) void k_update_bj(
 }
 
 // y = M^{-1} r only.
+template <class M>
 __global__ __launch_bounds__(kThreads) void k_bj(int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start,
                                                  const double *__restrict__ r, double *__restrict__ y,
-                                                 const double *__restrict__ minv,
+                                                 const M *__restrict__ minv,
                                                  const int32_t *__restrict__ bj_rowoff,
                                                  const int32_t *__restrict__ bj_meta, const State *st) {
     __shared__ double tile[kThreads];
@@ -480,20 +487,51 @@ template <int G>
 hipError_t spmv_p_g(const dpcg_ctx *c, Workspace &w, hipEvent_t ev0, hipEvent_t ev1) {
     SpmvShape sh{c->nb, c->spmv.steps, c->spmv.nwg};
     // the events (when given) take the kernel's own start and end timestamps
-    hipExtLaunchKernelGGL(k_spmv_p<G>, dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, ev0, ev1, 0, sh,
-                          c->brow_ptr, c->bcol, c->bval, c->nnzb, w.z, w.p[0], w.p[1], w.q, w.part_a, w.st);
+    if (c->inner32)
+        hipExtLaunchKernelGGL(k_spmv_p<G, float>, dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, ev0, ev1, 0,
+                              sh, c->brow_ptr, c->bcol, (const float *)c->bval32, c->nnzb, (const double *)w.z,
+                              w.p[0], w.p[1], w.q, w.part_a, (const State *)w.st);
+    else
+        hipExtLaunchKernelGGL(k_spmv_p<G, double>, dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, ev0, ev1,
+                              0, sh, c->brow_ptr, c->bcol, (const double *)c->bval, c->nnzb, (const double *)w.z,
+                              w.p[0], w.p[1], w.q, w.part_a, (const State *)w.st);
     return hipGetLastError();
 }
 
 template <int G, int MODE>
 hipError_t spmv_g(const dpcg_ctx *c, const double *x, const double *f, double *y, double *part) {
     SpmvShape sh{c->nb, c->spmv.steps, c->spmv.nwg};
-    hipLaunchKernelGGL((k_spmv<G, MODE>), dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, sh, c->brow_ptr,
-                       c->bcol, c->bval, c->nnzb, x, f, y, part);
+    if (c->inner32)
+        hipLaunchKernelGGL((k_spmv<G, MODE, float>), dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, sh,
+                           c->brow_ptr, c->bcol, (const float *)c->bval32, c->nnzb, x, f, y, part);
+    else
+        hipLaunchKernelGGL((k_spmv<G, MODE, double>), dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, sh,
+                           c->brow_ptr, c->bcol, (const double *)c->bval, c->nnzb, x, f, y, part);
     return hipGetLastError();
 }
 
+__global__ void k_to_f32(const double *__restrict__ src, int64_t count, float *__restrict__ dst) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
+}
+
+__global__ void k_add(int64_t n, const double *__restrict__ x, double *__restrict__ y) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += x[i];
+}
+
 }  // namespace
+
+hipError_t launch_to_f32(const dpcg_ctx *c, const double *src, int64_t count, float *dst) {
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(8192, (count + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(k_to_f32, dim3(grid), dim3(kThreads), 0, c->stream, src, count, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(const dpcg_ctx *c, const double *x, double *y) {
+    hipLaunchKernelGGL(k_add, dim3(c->vec_nwg), dim3(kThreads), 0, c->stream, c->n, x, y);
+    return hipGetLastError();
+}
 
 hipError_t launch_spmv_p(const dpcg_ctx *c, Workspace &w, hipEvent_t ev0, hipEvent_t ev1) {
     switch (c->spmv.group) {
@@ -529,9 +567,16 @@ hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w) {
     hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1024), 0, c->stream, w.part_a, c->spmv.nwg, w.st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_update_bj, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles,
-                       c->bj_nwg, c->bj_wg_start, u, w.r, w.y, w.q, w.p[0], w.p[1], c->minv, c->bj_rowoff,
-                       c->bj_meta, w.part_b, w.st);
+    if (c->inner32)
+        hipLaunchKernelGGL(k_update_bj<float>, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles,
+                           c->bj_nwg, c->bj_wg_start, u, w.r, w.y, (const double *)w.q, (const double *)w.p[0],
+                           (const double *)w.p[1], (const float *)c->minv32, c->bj_rowoff, c->bj_meta, w.part_b,
+                           (const State *)w.st);
+    else
+        hipLaunchKernelGGL(k_update_bj<double>, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles,
+                           c->bj_nwg, c->bj_wg_start, u, w.r, w.y, (const double *)w.q, (const double *)w.p[0],
+                           (const double *)w.p[1], (const double *)c->minv, c->bj_rowoff, c->bj_meta, w.part_b,
+                           (const State *)w.st);
     return hipGetLastError();
 }
 
@@ -541,8 +586,13 @@ hipError_t launch_beta(const dpcg_ctx *c, Workspace &w) {
 }
 
 hipError_t launch_bj(const dpcg_ctx *c, const double *r, double *y, Workspace *w) {
-    hipLaunchKernelGGL(k_bj, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles, c->bj_nwg,
-                       c->bj_wg_start, r, y, c->minv, c->bj_rowoff, c->bj_meta, w ? w->st : nullptr);
+    const State *st = w ? w->st : nullptr;
+    if (c->inner32)
+        hipLaunchKernelGGL(k_bj<float>, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles, c->bj_nwg,
+                           c->bj_wg_start, r, y, (const float *)c->minv32, c->bj_rowoff, c->bj_meta, st);
+    else
+        hipLaunchKernelGGL(k_bj<double>, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles, c->bj_nwg,
+                           c->bj_wg_start, r, y, (const double *)c->minv, c->bj_rowoff, c->bj_meta, st);
     return hipGetLastError();
 }
 
