@@ -65,11 +65,11 @@ WORKLOADS = {
 }
 
 
-def spmv_bytes(nnzb, n):
+def spmv_bytes(nnzb, n, value_bytes=8):
     """Algorithmic bytes of one q = K p launch with p = z + beta p_prev formed on the
-    fly: each 3x3 block (72 B values + 4 B column index) once, the block-row pointer,
+    fly: each 3x3 block (9 values + a 4 B column index) once, the block-row pointer,
     z and p_prev read once, q and p written once."""
-    return nnzb * 76 + 4 * (n // 3 + 1) + 4 * 8 * n
+    return nnzb * (9 * value_bytes + 4) + 4 * (n // 3 + 1) + 4 * 8 * n
 
 
 def cpu_baseline(p, budget_s=12.0):
@@ -93,6 +93,38 @@ def cpu_baseline(p, budget_s=12.0):
                       f"{dt:.1f} s"}
 
 
+def run_mixed(step, p, args, stats):
+    """The same steps with precision "mixed" (FP64 refinement around inner solves on
+    binary32 copies of K and of the block inverses), to the same true FP64 residual."""
+    import numpy as np
+    import torch
+
+    for _ in range(args.warmup):
+        step(False, "mixed")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, spmv_ms, spmv_n = [], 0.0, 0
+    for _ in range(args.steps):
+        info, tm, _ = step(True, "mixed")
+        infos.append(info)
+        spmv_ms += tm["spmv_ms"]
+        spmv_n += tm["spmv_launches"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    bad = [i for i in infos if i["status"] != 0 or i["rel_res_true"] > 1e-8]
+    per_launch_s = spmv_ms / 1e3 / max(spmv_n, 1)
+    nbytes = spmv_bytes(stats["nnzb"], p.n, value_bytes=4)
+    achieved = nbytes / per_launch_s / 1e9
+    return {"value": p.n * args.steps / dt, "unit": "DoF-solves/s", "ms_per_step": dt * 1e3 / args.steps,
+            "ok": not bad, "iterations": infos[-1]["iterations"], "refinements": infos[-1]["refinements"],
+            "rel_res_true": infos[-1]["rel_res_true"],
+            "setup_ms": float(np.mean([i["setup_ms"] for i in infos])),
+            "solve_ms": float(np.mean([i["solve_ms"] for i in infos])),
+            "spmv_fp32_values": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": nbytes,
+                                 "launches": spmv_n, "avg_launch_us": per_launch_s * 1e6}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +132,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="penny40", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison line")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run N plain 512 MiB device copies (counter calibration)")
     args = ap.parse_args()
@@ -125,11 +158,11 @@ def main():
     u = torch.empty_like(f)
     stream = torch.cuda.current_stream()
 
-    def step(timing):
+    def step(timing, precision="fp64"):
         s = dpcg.Solver(p.n, *K, p.k, *Z, bp, stream=stream)
         if timing:
             s.set_timing(True)
-        _, info = s.solve(f, u, tol=1e-8)
+        _, info = s.solve(f, u, tol=1e-8, precision=precision)
         tm = s.timing() if timing else None
         st = s.stats()
         s.close()
@@ -192,6 +225,8 @@ def main():
                      "kernel": "k_spmv_p", "bytes_per_launch": nbytes, "launches": spmv_n,
                      "avg_launch_us": per_launch_s * 1e6},
     }
+    if not args.no_mixed:
+        out["mixed"] = run_mixed(step, p, args, stats)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)

@@ -43,9 +43,9 @@ struct State {
     int32_t iters_done;  // final iteration count, set together with the flag
     int32_t bad;         // iteration of a breakdown
     double thr;          // tol * ||f||_2
-    double rho_cur;      // rho_i = r_i^T z_i of the iteration in flight (k_beta)
+    double rho[2];       // rho_i = r_i^T z_i in slot i & 1 (k_beta_p), so rho_{i-1} stays readable
     double alpha;        // alpha_i (k_alpha)
-    double beta;         // beta_{i-1} (k_beta; 0 at i = 0)
+    double beta;         // beta_{i-1} (k_beta_p; 0 at i = 0)
     double rr;           // ||r||^2 of the last check
     double aux;          // scratch scalar for one-off reductions
     int32_t nonfinite;   // set by the input check

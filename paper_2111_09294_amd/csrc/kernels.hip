@@ -85,17 +85,6 @@ struct XPlain {
     __device__ __forceinline__ double operator()(int64_t i) const { return x[i]; }
 };
 
-// p_i = z_i + beta p_{i-1}, recomputed wherever p_i is gathered (same expression, same bits).
-struct XDirection {
-    const double *__restrict__ z;
-    const double *__restrict__ pprev;
-    double beta;
-    bool first;
-    __device__ __forceinline__ double operator()(int64_t i) const {
-        return first ? z[i] : fma(beta, pprev[i], z[i]);
-    }
-};
-
 // q_R = sum_b K_Rb x_b for block row R, computed by a group of G lanes; the three
 // sums end up in every lane of the group.  Lanes of groups without a row pass
 // row = -1 and take part in the shuffles with zeros.
@@ -189,24 +178,20 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvShape sh, const int32
     }
 }
 
-// Search direction and matrix product of Algorithm 1 for iteration i = st->iter:
-// p_i = z_i + beta_{i-1} p_{i-1} (p_0 = z_0; beta from the state), q = K p_i, and
-// partials of p_i^T q.  Only the single-workgroup kernels change the flag, so it is
-// stable while this kernel runs.
+// Matrix product of Algorithm 1 for iteration i = st->iter: q = K p_i (p_i in buffer
+// i & 1, formed by k_beta_p) and partials of p_i^T q.  Only the single-workgroup
+// kernels change the flag, so it is stable while this kernel runs.
 template <int G, class V>
 __global__ __launch_bounds__(kSpmvThreads) void k_spmv_p(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
                                                          const int32_t *__restrict__ bcol,
                                                          const V *__restrict__ bval, int64_t nnzb,
-                                                         const double *__restrict__ z, double *p0, double *p1,
+                                                         const double *p0, const double *p1,
                                                          double *__restrict__ q, double *__restrict__ part_pq,
                                                          const State *st) {
     __shared__ double lds[kSpmvWaves];
     if (st->flag != kRunning) return;
-    const int it = st->iter;
-    const double beta = st->beta;
-    double *pout = (it & 1) ? p1 : p0;
-    const double *pprev = (it & 1) ? p0 : p1;
-    XDirection xl{z, pprev, beta, it == 0};
+    const double *__restrict__ p = (st->iter & 1) ? p1 : p0;
+    XPlain xl{p};
     const int w = xcd_remap(blockIdx.x, sh.nwg);
     const int s0 = (int)(((int64_t)w * sh.steps) / sh.nwg), s1 = (int)(((int64_t)(w + 1) * sh.steps) / sh.nwg);
     const int lg = threadIdx.x % G;
@@ -218,10 +203,8 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv_p(SpmvShape sh, const int
         if (row >= 0 && lg < 3) {
             const int64_t i = 3 * (int64_t)row + lg;
             const double v = pick3(lg, a0, a1, a2);
-            const double pi = xl(i);
             q[i] = v;
-            pout[i] = pi;
-            acc = fma(pi, v, acc);
+            acc = fma(p[i], v, acc);
         }
     }
     const double t = block_sum_n<kSpmvWaves>(acc, lds);
@@ -234,7 +217,7 @@ __global__ __launch_bounds__(1024) void k_alpha(const double *__restrict__ part_
     if (st->flag != kRunning) return;
     const double pq = reduce_parts_n<16>(part_pq, n, lds);
     if (threadIdx.x == 0) {
-        const double alpha = st->rho_cur / pq;
+        const double alpha = st->rho[st->iter & 1] / pq;
         if (!(pq > 0.0) || !isfinite(pq) || !isfinite(alpha)) {
             st->flag = kBreakdown;
             st->bad = st->iter;
@@ -245,23 +228,37 @@ __global__ __launch_bounds__(1024) void k_alpha(const double *__restrict__ part_
     }
 }
 
-// rho_i = r_i^T z_i from the prolongation partials and beta_{i-1} = rho_i / rho_{i-1}
-// (beta unused at i = 0); one workgroup, fixed order.
-__global__ __launch_bounds__(1024) void k_beta(const double *__restrict__ part_rho, int n, State *st) {
-    __shared__ double lds[16];
-    if (st->flag != kRunning) return;
-    const double rho = reduce_parts_n<16>(part_rho, n, lds);
-    if (threadIdx.x == 0) {
-        const int it = st->iter;
-        if (it > 0 && !isfinite(rho)) {
+// rho_i = r_i^T z_i from the prolongation partials (every workgroup reduces them in
+// the same fixed order, so all hold the same bits), beta_{i-1} = rho_i / rho_{i-1} and
+// the search direction p_i = z_i + beta_{i-1} p_{i-1} (p_0 = z_0) into buffer i & 1 over
+// the workgroup's DoF range.  Workgroup 0 stores rho_i in slot i & 1 (rho_{i-1} in the
+// other slot stays valid for the others) and tests it for breakdown.
+__global__ __launch_bounds__(kThreads) void k_beta_p(const double *__restrict__ part_rho, int nparts, int64_t n,
+                                                     int32_t nwg, const double *__restrict__ z, double *p0,
+                                                     double *p1, State *st) {
+    __shared__ double lds[4];
+    if (wg_flag(st) != kRunning) return;
+    const int it = st->iter;
+    const double rho = reduce_parts_n<4>(part_rho, nparts, lds);
+    const bool bad = it > 0 && !isfinite(rho);
+    const double beta = it > 0 ? rho / st->rho[(it + 1) & 1] : 0.0;
+    if (leader()) {
+        if (bad) {
             st->flag = kBreakdown;
             st->bad = it - 1;
             st->iters_done = it;
         } else {
-            st->beta = it > 0 ? rho / st->rho_cur : 0.0;
-            st->rho_cur = rho;
+            st->beta = beta;
+            st->rho[it & 1] = rho;
         }
     }
+    if (bad) return;
+    double *__restrict__ pc = (it & 1) ? p1 : p0;
+    const double *__restrict__ pp = (it & 1) ? p0 : p1;
+    const int w = xcd_remap(blockIdx.x, nwg);
+    const int64_t per = (n + nwg - 1) / nwg;
+    const int64_t d1 = min(n, (int64_t)(w + 1) * per);
+    for (int64_t d = (int64_t)w * per + threadIdx.x; d < d1; d += kThreads) pc[d] = it == 0 ? z[d] : fma(beta, pp[d], z[d]);
 }
 
 // y_d = sum_j Minv_B[d - s_B, j] r_{s_B + j} for the DoFs of this tile (whole blocks).
@@ -489,12 +486,12 @@ hipError_t spmv_p_g(const dpcg_ctx *c, Workspace &w, hipEvent_t ev0, hipEvent_t 
     // the events (when given) take the kernel's own start and end timestamps
     if (c->inner32)
         hipExtLaunchKernelGGL(k_spmv_p<G, float>, dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, ev0, ev1, 0,
-                              sh, c->brow_ptr, c->bcol, (const float *)c->bval32, c->nnzb, (const double *)w.z,
-                              w.p[0], w.p[1], w.q, w.part_a, (const State *)w.st);
+                              sh, c->brow_ptr, c->bcol, (const float *)c->bval32, c->nnzb,
+                              (const double *)w.p[0], (const double *)w.p[1], w.q, w.part_a, (const State *)w.st);
     else
         hipExtLaunchKernelGGL(k_spmv_p<G, double>, dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, ev0, ev1,
-                              0, sh, c->brow_ptr, c->bcol, (const double *)c->bval, c->nnzb, (const double *)w.z,
-                              w.p[0], w.p[1], w.q, w.part_a, (const State *)w.st);
+                              0, sh, c->brow_ptr, c->bcol, (const double *)c->bval, c->nnzb,
+                              (const double *)w.p[0], (const double *)w.p[1], w.q, w.part_a, (const State *)w.st);
     return hipGetLastError();
 }
 
@@ -581,7 +578,8 @@ hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w) {
 }
 
 hipError_t launch_beta(const dpcg_ctx *c, Workspace &w) {
-    hipLaunchKernelGGL(k_beta, dim3(1), dim3(1024), 0, c->stream, w.part_c, c->vec_nwg, w.st);
+    hipLaunchKernelGGL(k_beta_p, dim3(c->vec_nwg), dim3(kThreads), 0, c->stream, w.part_c, c->vec_nwg, c->n,
+                       c->vec_nwg, w.z, w.p[0], w.p[1], w.st);
     return hipGetLastError();
 }
 
