@@ -66,10 +66,9 @@ WORKLOADS = {
 
 
 def spmv_bytes(nnzb, n, value_bytes=8):
-    """Algorithmic bytes of one q = K p launch with p = z + beta p_prev formed on the
-    fly: each 3x3 block (9 values + a 4 B column index) once, the block-row pointer,
-    z and p_prev read once, q and p written once."""
-    return nnzb * (9 * value_bytes + 4) + 4 * (n // 3 + 1) + 4 * 8 * n
+    """Algorithmic bytes of one q = K p launch: each 3x3 block (9 values + a 4 B column
+    index) once, the block-row pointers, p read once and q written once."""
+    return nnzb * (9 * value_bytes + 4) + 4 * (n // 3 + 1) + 2 * 8 * n
 
 
 def cpu_baseline(p, budget_s=12.0):
