@@ -23,7 +23,7 @@ import os
 
 import numpy as np
 
-from .xfem import CurvedPennyCrack, PlanarEdgeCrack, Problem, build_problem
+from .xfem import CurvedPennyCrack, PlanarEdgeCrack, Problem, XfemBox, build_problem
 
 GENERATOR_VERSION = 4
 
@@ -81,3 +81,31 @@ def load(name: str, use_cache: bool = True) -> Problem:
                  meta=json.dumps(p.meta))
         os.replace(tmp, path)
     return p
+
+
+def box(name: str, elem_E=None) -> XfemBox:
+    """The mesh object of a named workload (optionally with per-element moduli)."""
+    cfg = CONFIGS[name]
+    return XfemBox(cfg["ne"], crack=make_crack(cfg["crack"]), r_e=cfg["r_e"], elem_E=elem_E)
+
+
+def load_elements(name: str, use_cache: bool = True):
+    """Unit-modulus element matrices of a named workload (XfemBox.element_matrices)."""
+    cfg = CONFIGS[name]
+    path = os.path.join(cache_dir(), f"{name}-{_key(name, cfg)}-elements.npz")
+    if use_cache and os.path.exists(path):
+        d = np.load(path, allow_pickle=False)
+        return d["elem_ptr"], d["elem_dof"], d["kmat_off"], d["kmat"]
+    ep, ed, ko, km = box(name).element_matrices()
+    if use_cache:
+        tmp = path + ".tmp.npz"
+        np.savez(tmp, elem_ptr=ep, elem_dof=ed, kmat_off=ko, kmat=km)
+        os.replace(tmp, path)
+    return ep, ed, ko, km
+
+
+def problem_with_moduli(name: str, elem_E) -> Problem:
+    """The named workload re-assembled with per-element Young's moduli elem_E."""
+    cfg = CONFIGS[name]
+    return build_problem(name, cfg["ne"], cfg["nsd"], crack=make_crack(cfg["crack"]), r_e=cfg["r_e"],
+                         elem_E=np.asarray(elem_E, float))

@@ -474,6 +474,62 @@ class XfemBox:
             return np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros((0, 3, 3))
         return np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
 
+    def element_matrices(self):
+        """Unit-modulus element stiffness matrices in scalar DoF space.
+
+        K = sum_e elem_E[e] K_e, with K_e the element's matrix for E = 1 over its DoFs
+        elem_dof[elem_ptr[e]:elem_ptr[e+1]] (-1 for a DoF of a clamped node).  Each
+        function of the element (standard N_a, then N_a (H - H_a) and the four shifted
+        branch functions of enriched nodes, node by node) contributes the DoF triplet
+        3t, 3t+1, 3t+2 of its triplet t.  Standard elements share one 24 x 24 matrix,
+        stored first (kmat_off = 0); an enriched element has its own (8^3 Gauss, with the
+        standard-standard pairs from the exact 2^3 matrix, as assembled).
+        Returns (elem_ptr int64, elem_dof int32, kmat_off int64, kmat float64).
+        """
+        nel = self.ne ** 3
+        Ke0 = hex8_standard_stiffness(self.h, 1.0, self.nu)        # (8,3,8,3)
+        mats = [Ke0.reshape(24, 24)]
+        off = 576
+        kmat_off = np.zeros(nel, np.int64)
+        dofs = [None] * nel
+        std_trip = np.where(self.free[self.conn], self.trip_start[self.conn], -1)    # (nel, 8)
+        std_dofs = np.where(std_trip[:, :, None] >= 0, 3 * std_trip[:, :, None] + np.arange(3), -1).reshape(nel, 24)
+        enr = np.zeros(nel, bool)
+        enr_ids = self.enriched_elements()
+        enr[enr_ids] = True
+        if len(enr_ids):
+            xi, wq = gauss_rule_3d(self.ng)
+            lam1, mu1 = lame(1.0, self.nu)
+        for e in enr_ids:
+            G, tr, w = self.element_functions(e, xi, wq)
+            Ke = stiffness_from_gradients(G, w, lam1, mu1)             # (m,3,m,3)
+            std_pos = []
+            pos = 0
+            for a in range(8):
+                I = self.conn[e, a]
+                std_pos.append(pos)
+                pos += 1 + int(self.H_node[I]) + 4 * int(self.T_node[I])
+            sp_ = np.array(std_pos)
+            Ke[np.ix_(sp_, np.arange(3), sp_, np.arange(3))] = Ke0
+            m = len(tr)
+            mats.append(Ke.reshape(3 * m, 3 * m))
+            kmat_off[e] = off
+            off += 9 * m * m
+            dofs[e] = np.where(tr[:, None] >= 0, 3 * tr[:, None] + np.arange(3), -1).reshape(-1)
+        sizes = np.where(enr, 0, 24)
+        for e in enr_ids:
+            sizes[e] = len(dofs[e])
+        elem_ptr = np.zeros(nel + 1, np.int64)
+        np.cumsum(sizes, out=elem_ptr[1:])
+        elem_dof = np.empty(elem_ptr[-1], np.int32)
+        std_ids = np.nonzero(~enr)[0]
+        base = elem_ptr[std_ids][:, None] + np.arange(24)
+        elem_dof[base.reshape(-1)] = std_dofs[std_ids].reshape(-1)
+        for e in enr_ids:
+            elem_dof[elem_ptr[e]:elem_ptr[e + 1]] = dofs[e]
+        kmat = np.concatenate([M.reshape(-1) for M in mats])
+        return elem_ptr, elem_dof, kmat_off, kmat
+
     def assemble_bsr(self):
         r1, c1, v1 = self._standard_blocks()
         r2, c2, v2 = self._enriched_blocks()

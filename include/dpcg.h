@@ -181,6 +181,27 @@ int64_t dpcg_get_history(dpcg_handle h, double *out, int64_t cap);
 int dpcg_set_timing(dpcg_handle h, int32_t on);
 int dpcg_get_timing(dpcg_handle h, dpcg_timing *out);
 
+/*
+ * Element sensitivities for the adjoint of a solve (an extension beyond the paper's
+ * solver: the assembled stiffness of Sec. 2.4, eq. linear_system, is linear in each
+ * element's modulus).  For K = sum_e s_e K_e with K_e element e's matrix at s_e = 1,
+ * u = K^{-1} f and a loss L(u) whose adjoint lambda = K^{-1} dL/du comes from
+ * dpcg_solve_adjoint, writes g[e] = dL/ds_e = -lambda_e^T K_e u_e, e < nel.
+ *   elem_ptr[nel+1] (int64): element e's DoFs are elem_dof[elem_ptr[e]..elem_ptr[e+1])
+ *       (int32; -1 marks a DoF removed by a Dirichlet condition, which is skipped);
+ *       at most 256 DoFs per element.
+ *   kmat_off[nel] (int64): K_e (m_e x m_e, row-major, in the element's DoF order)
+ *       starts at kmat[kmat_off[e]]; elements may share one matrix.  kmat_len is the
+ *       number of doubles in kmat.
+ *   u, lambda: n; g: nel.  All device arrays, caller-owned.
+ * The element data are checked on the device first (sizes, DoF and matrix ranges):
+ * DPCG_EINVAL if they are inconsistent, nothing written.  K_e must be the matrices K
+ * was assembled from for g to be the gradient; the call does not check that.
+ */
+int dpcg_element_gradient(dpcg_handle h, int64_t nel, const int64_t *elem_ptr, const int32_t *elem_dof,
+                          const int64_t *kmat_off, int64_t kmat_len, const double *kmat, const double *u,
+                          const double *lambda, double *g);
+
 /* ---- single steps of the iteration, each the kernel the solve runs ---- */
 
 /* y = K x (Algorithm 1's K p_i) with the block-CSR kernel.  x, y: device, n. */

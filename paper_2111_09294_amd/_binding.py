@@ -72,6 +72,7 @@ SIGNATURES = {
     "dpcg_bj_apply": (C.c_int, [P, P, P]),
     "dpcg_bj_apply_fp32": (C.c_int, [P, P, P]),
     "dpcg_restrict": (C.c_int, [P, P, P, P]),
+    "dpcg_element_gradient": (C.c_int, [P, C.c_int64, P, P, P, C.c_int64, P, P, P, P]),
     "dpcg_coarse_apply": (C.c_int, [P, P, P]),
     "dpcg_prolong": (C.c_int, [P, P, P, P]),
     "dpcg_precond": (C.c_int, [P, P, P]),
@@ -289,6 +290,19 @@ class Solver:
         self._call("dpcg_bj_apply", r, y)
         return y
 
+    def element_gradient(self, elements, u, lam):
+        """g[e] = -lam_e^T K_e u_e for the element data `elements` (an Elements)."""
+        import torch
+        _check_dev(u, torch.float64, "u", self.n)
+        _check_dev(lam, torch.float64, "lambda", self.n)
+        g = torch.empty(elements.nel, dtype=torch.float64, device=u.device)
+        st = lib().dpcg_element_gradient(self.handle, elements.nel, _ptr(elements.elem_ptr),
+                                         _ptr(elements.elem_dof), _ptr(elements.kmat_off), elements.kmat.numel(),
+                                         _ptr(elements.kmat), _ptr(u), _ptr(lam), _ptr(g))
+        if st != OK:
+            raise DpcgError(st, "dpcg_element_gradient")
+        return g
+
     def spmv_fp32(self, x, y=None):
         """y = K32 x: K's values rounded to binary32, FP64 arithmetic."""
         import torch
@@ -334,3 +348,20 @@ class Solver:
         z = torch.empty_like(r)
         self._call("dpcg_precond", r, z)
         return z
+
+
+class Elements:
+    """Element matrices K_e (for a unit scaling) and their DoF lists, as device tensors,
+    for dpcg_element_gradient: elem_ptr int64 (nel+1), elem_dof int32 (-1 = removed
+    DoF), kmat_off int64 (nel), kmat float64 (row-major m_e x m_e blocks)."""
+
+    def __init__(self, elem_ptr, elem_dof, kmat_off, kmat, device="cuda"):
+        import torch
+        t = lambda a, dt: torch.as_tensor(a).to(device=device, dtype=dt).contiguous()  # noqa: E731
+        self.elem_ptr = t(elem_ptr, torch.int64)
+        self.elem_dof = t(elem_dof, torch.int32)
+        self.kmat_off = t(kmat_off, torch.int64)
+        self.kmat = t(kmat, torch.float64)
+        self.nel = self.kmat_off.numel()
+        if self.elem_ptr.numel() != self.nel + 1:
+            raise ValueError("elem_ptr must have nel + 1 entries")

@@ -565,6 +565,14 @@ int dpcg_bj_apply_fp32(dpcg_handle h, const double *r, double *y) {
     SYNC_RET(he);
 }
 
+int dpcg_element_gradient(dpcg_handle h, int64_t nel, const int64_t *elem_ptr, const int32_t *elem_dof,
+                          const int64_t *kmat_off, int64_t kmat_len, const double *kmat, const double *u,
+                          const double *lambda, double *g) {
+    if (!h || nel < 0 || kmat_len < 0) return DPCG_EINVAL;
+    if (nel > 0 && (!elem_ptr || !elem_dof || !kmat_off || !kmat || !u || !lambda || !g)) return DPCG_EINVAL;
+    return element_gradient(h, nel, elem_ptr, elem_dof, kmat_off, kmat_len, kmat, u, lambda, g);
+}
+
 int dpcg_bj_apply(dpcg_handle h, const double *r, double *y) {
     if (!h || !r || !y) return DPCG_EINVAL;
     SYNC_RET(launch_bj(h, r, y, nullptr));

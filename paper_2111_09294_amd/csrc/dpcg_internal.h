@@ -26,6 +26,7 @@ namespace dpcg {
 
 constexpr int kThreads = 256;     // threads per workgroup everywhere
 constexpr int kMaxBlock = 18;     // largest block-Jacobi block
+constexpr int kMaxElemDofs = 256; // largest element (DoFs) of dpcg_element_gradient
 
 // The hardware spreads consecutive workgroups round-robin over the 8 XCDs; give each
 // XCD a contiguous range of work so neighbouring rows share its L2.
@@ -139,6 +140,11 @@ hipError_t launch_reduce_aux(const dpcg_ctx *c, Workspace &w, int n_parts);
 hipError_t launch_to_f32(const dpcg_ctx *c, const double *src, int64_t count, float *dst);
 // y += x
 hipError_t launch_add(const dpcg_ctx *c, const double *x, double *y);
+
+// adjoint.hip: g[e] = -lam_e^T K_e u_e after a device-side check of the element data;
+// returns a DPCG_* status.
+int element_gradient(dpcg_ctx *c, int64_t nel, const int64_t *ep, const int32_t *ed, const int64_t *ko,
+                     int64_t kmat_len, const double *km, const double *u, const double *lam, double *g);
 
 // devmem.cpp: cached device allocations (release only after the using stream is idle).
 hipError_t dev_alloc(void **p, size_t bytes);

@@ -1,0 +1,136 @@
+"""GPU parity of the adjoint path: the element-sensitivity kernel against the oracle,
+and the autograd wrapper (forward solve, adjoint solve, element kernel) against
+direct CPU solves and finite differences.
+
+Tolerances:
+* element kernel with the same u, lambda: 1e-12 relative to |lambda_e|^T |K_e| |u_e|
+  (summation order only);
+* gradients from solves at tol 1e-10 against direct solves: 1e-6 relative to the
+  largest entry;
+* central finite differences (h = 3e-3 on one element modulus, truncation error about
+  h^2 relative; GPU solves at tol 1e-12 on freshly assembled systems): 1e-4 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import scipy.sparse.linalg as spla  # noqa: E402
+
+import paper_2111_09294_amd as D  # noqa: E402
+from fixtures import load_elements, problem_with_moduli  # noqa: E402
+from oracle.adjoint import element_gradient  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, np.float64), device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["edge4", "penny12", "edge10", "penny40"])
+def test_element_gradient_kernel(problems, name):
+    p = problems(name)
+    ep, ed, ko, km = load_elements(name)
+    el = D.Elements(ep, ed, ko, km, DEV)
+    rng = np.random.default_rng(31)
+    u, lam = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    with D.Solver.from_problem(p, DEV) as s:
+        g = host(s.element_gradient(el, dev(u), dev(lam)))
+    ref = element_gradient(ep, ed, ko, km, u, lam)
+    scale = element_gradient(ep, ed, ko, km, u, lam, absolute=True)
+    assert np.all(np.abs(g - ref) <= 1e-12 * scale + 1e-300)
+
+
+def test_element_gradient_rejects_bad_element_data(problems):
+    p = problems("edge4")
+    ep, ed, ko, km = load_elements("edge4")
+    u = dev(np.ones(p.n))
+    with D.Solver.from_problem(p, DEV) as s:
+        bad = []
+        ed2 = ed.copy()
+        ed2[5] = p.n                      # DoF out of range
+        bad.append((ep, ed2, ko, km))
+        ko2 = ko.copy()
+        ko2[-1] = len(km) - 10            # matrix beyond the end of kmat
+        bad.append((ep, ed, ko2, km))
+        ep2 = ep.copy()
+        ep2[1:] += 300                    # an element of 300 DoFs (> 256)
+        bad.append((ep2, np.concatenate([np.full(300, -1, np.int32), ed]), ko, km))
+        for args in bad:
+            with pytest.raises(D.DpcgError) as e:
+                s.element_gradient(D.Elements(*args, device=DEV), u, u)
+            assert e.value.code == D.abi.EINVAL
+        g = s.element_gradient(D.Elements(ep, ed, ko, km, DEV), u, u)   # still usable
+        assert torch.isfinite(g).all()
+
+
+def test_autograd_matches_direct_solves(problems):
+    name = "edge10"
+    p = problems(name)
+    ep, ed, ko, km = load_elements(name)
+    nel = len(ep) - 1
+    el = D.Elements(ep, ed, ko, km, DEV)
+    c = np.random.default_rng(32).standard_normal(p.n)
+    K = p.K_scipy().tocsc()
+    u_ref = spla.spsolve(K, p.f)
+    with D.Solver.from_problem(p, DEV) as s:
+        for precision in ("fp64", "mixed"):
+            f = dev(p.f).requires_grad_(True)
+            scale = torch.ones(nel, dtype=torch.float64, device=DEV, requires_grad=True)
+            u = D.solve(f, s, scale=scale, elements=el, tol=1e-10, precision=precision)
+            # compliance f^T u plus a linear functional c^T u
+            L = (f * u).sum() + (dev(c) * u).sum()
+            L.backward()
+            # dL/du = f + c, lambda = K^{-1}(f + c); dL/df = u + lambda (explicit term + adjoint)
+            lam_ref = spla.spsolve(K, p.f + c)
+            gf_ref = u_ref + lam_ref
+            gs_ref = element_gradient(ep, ed, ko, km, u_ref, lam_ref)
+            gf, gs = host(f.grad), host(scale.grad)
+            say(f"[adjoint] {precision}: |dL/df err| {np.abs(gf - gf_ref).max():.2e}, "
+                f"|dL/ds err| {np.abs(gs - gs_ref).max():.2e} (max {np.abs(gs_ref).max():.2e})")
+            assert np.abs(gf - gf_ref).max() <= 1e-6 * np.abs(gf_ref).max()
+            assert np.abs(gs - gs_ref).max() <= 1e-6 * np.abs(gs_ref).max()
+
+
+def test_autograd_matches_finite_differences(problems):
+    name = "edge10"
+    p = problems(name)
+    ep, ed, ko, km = load_elements(name)
+    nel = len(ep) - 1
+    m = np.diff(ep)
+    el = D.Elements(ep, ed, ko, km, DEV)
+    c = dev(np.random.default_rng(33).standard_normal(p.n))
+    with D.Solver.from_problem(p, DEV) as s:
+        scale = torch.ones(nel, dtype=torch.float64, device=DEV, requires_grad=True)
+        u = D.solve(dev(p.f), s, scale=scale, elements=el, tol=1e-12)
+        (c * u).sum().backward()
+        gs = host(scale.grad)
+    h = 3e-3
+    for j in [int(np.nonzero(m == 24)[0][7]), int(np.argmax(np.abs(gs) * (m > 24)))]:
+        Ls = []
+        for sgn in (1.0, -1.0):
+            E = np.ones(nel)
+            E[j] += sgn * h
+            pj = problem_with_moduli(name, E)
+            with D.Solver.from_problem(pj, DEV) as sj:
+                uj, info = sj.solve(dev(pj.f), tol=1e-12)
+                assert info["status"] == D.abi.OK
+            Ls.append(float((c * uj).sum()))
+        fd = (Ls[0] - Ls[1]) / (2 * h)
+        say(f"[adjoint] element {j} (m={m[j]}): autograd {gs[j]:.10e}, central FD {fd:.10e}")
+        assert abs(fd - gs[j]) <= 1e-4 * abs(gs[j])
