@@ -155,6 +155,26 @@ int dpcg_solve(dpcg_handle h, const double *f, double *u, double tol,
 int dpcg_solve_adjoint(dpcg_handle h, const double *g, double *lambda, double tol,
                        const dpcg_options *opt, dpcg_info *info);
 
+/*
+ * Solves K U = F for nrhs right-hand sides at once, 1 <= nrhs <= 32 (an extension
+ * beyond the paper's single-RHS solver): the method of dpcg_solve run as nrhs
+ * independent recurrences that share every pass over K, Z, (KZ)^T, E^{-1} and the
+ * block inverses.  F and U are n x nrhs, row-major (column j of row d at
+ * F[d * nrhs + j]), caller-owned device arrays; U is output, and input when
+ * opt->use_initial_guess.  Each column runs Algorithms 1-3 with its own scalars and
+ * its own stopping test ||r_j|| <= tol ||F_j||; a column that stops is frozen while
+ * the others continue, so column j takes the iterates of dpcg_solve on F[:, j] up to
+ * the order of floating-point sums.  A zero column gives 0 after 0 iterations.
+ * infos[nrhs] (host, may be NULL) receives one record per column.  Returns DPCG_OK
+ * when every column converged, else DPCG_EBREAKDOWN if some column broke down, else
+ * DPCG_NOT_CONVERGED; DPCG_EINVAL for nrhs outside [1, 32], tol <= 0, max_iter < 0,
+ * record_history or a precision other than DPCG_PREC_FP64; DPCG_ENONFINITE; DPCG_EHIP.
+ * The first call makes the handle's multi-RHS workspace (8 n x 32 and 2 k x 32
+ * doubles).  SpMV timing (dpcg_set_timing) covers the batched product kernel.
+ */
+int dpcg_solve_batch(dpcg_handle h, int32_t nrhs, const double *F, double *U, double tol,
+                     const dpcg_options *opt, dpcg_info *infos);
+
 /* Releases every resource of the handle (NULL is a no-op). */
 void dpcg_destroy(dpcg_handle h);
 

@@ -60,6 +60,7 @@ SIGNATURES = {
                              C.POINTER(Info)]),
     "dpcg_solve": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
     "dpcg_solve_adjoint": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
+    "dpcg_solve_batch": (C.c_int, [P, C.c_int32, P, P, C.c_double, C.POINTER(Options), P]),
     "dpcg_destroy": (None, [P]),
     "dpcg_release_cached_memory": (None, []),
     "dpcg_status_string": (C.c_char_p, [C.c_int]),
@@ -242,6 +243,31 @@ class Solver:
         """lambda = K^{-1} g in the adjoint workspace.  Returns (lambda, info dict)."""
         return self._run(lib().dpcg_solve_adjoint, "dpcg_solve_adjoint", g, lam, tol, max_iter, check_every,
                          initial_guess, False, raise_on_error, precision, inner_tol, max_refinements)
+
+    def solve_batch(self, F, U=None, tol=1e-8, max_iter=None, check_every=None, initial_guess=None,
+                    raise_on_error=True):
+        """U = K^{-1} F for an n x nrhs float64 device tensor F (1 <= nrhs <= 32), each
+        column its own recurrence sharing the passes over the operator.  Returns
+        (U, list of per-column info dicts)."""
+        import torch
+        if F.dim() != 2 or F.shape[0] != self.n:
+            raise ValueError(f"F must be {self.n} x nrhs")
+        nrhs = F.shape[1]
+        _check_dev(F, torch.float64, "F")
+        if U is None:
+            U = torch.empty_like(F)
+        _check_dev(U, torch.float64, "U", F.numel())
+        if initial_guess is not None:
+            _check_dev(initial_guess, torch.float64, "initial_guess", F.numel())
+            if initial_guess.data_ptr() != U.data_ptr():
+                U.copy_(initial_guess)
+        o = self._opts(max_iter, check_every, initial_guess is not None, False)
+        infos = (Info * max(1, nrhs))()
+        st = lib().dpcg_solve_batch(self.handle, int(nrhs), _ptr(F), _ptr(U), float(tol), C.byref(o),
+                                    C.cast(infos, C.c_void_p))
+        if st < 0 and raise_on_error:
+            raise DpcgError(st, "dpcg_solve_batch", infos[0] if nrhs else None)
+        return U, [infos[j].as_dict() for j in range(nrhs)]
 
     def history(self):
         import numpy as np

@@ -1,0 +1,668 @@
+// Multi-RHS solves: the method of dpcg_solve (Algorithm 1 started by Algorithm 2, with
+// the A-DEF2 preconditioner of Algorithm 3 around block-Jacobi) run as up to 32
+// independent recurrences whose vectors are the columns of n x 32 row-major arrays, so
+// that every pass over K, Z, (KZ)^T, E^-1 and the block inverses serves all of them.
+// A column whose residual test passes is frozen (its u and r no longer change) while
+// the others continue, so each column follows the iterates of its own single solve.
+// Lane j of every 32-lane group owns column j; row accesses are 256-byte contiguous.
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "dpcg_internal.h"
+
+namespace dpcg {
+namespace {
+
+constexpr int W = kBatchCols;
+constexpr int kSpmmRowsPerWave = 4;
+
+// The batch's "any column running" flag as seen by the whole workgroup (one read,
+// broadcast through LDS): the restriction's workgroup 0 may change it meanwhile.
+__device__ __forceinline__ int32_t wg_any(const BatchState *st) {
+    __shared__ int32_t a;
+    if (threadIdx.x == 0) a = st->any;
+    __syncthreads();
+    const int32_t v = a;
+    __syncthreads();
+    return v;
+}
+
+// Fixed-order column sums of nparts rows of part (row-major, W columns) by a
+// 1024-thread workgroup: thread (g, j) sums rows g, g + 32, ...; the 32 group sums are
+// then added in order.  Valid in threads j < W.
+__device__ __forceinline__ double col_reduce_1024(const double *__restrict__ part, int nparts, double (*lds)[W + 1]) {
+    const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
+    double s = 0.0;
+    for (int w = g; w < nparts; w += 32) s += part[(int64_t)w * W + j];
+    lds[g][j] = s;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < W)
+        for (int h = 0; h < 32; ++h) t += lds[h][threadIdx.x];
+    return t;
+}
+
+// Same over the 8 groups of a 256-thread workgroup (values v of group g, lane j).
+__device__ __forceinline__ double group_sum_8(double v, double (*lds)[W]) {
+    const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
+    lds[g][j] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < W)
+        for (int h = 0; h < 8; ++h) t += lds[h][threadIdx.x];
+    return t;
+}
+
+// MODE 0: y = K x and partials of x_j^T y_j.  MODE 1: y = f - K x and partials of
+// ||y_j||^2.  One wave per block row (kSpmmRowsPerWave rows per wave): lanes 0-31 take
+// the even blocks of the row, lanes 32-63 the odd ones, one column per lane; the two
+// halves are added by a shuffle.  Block values are read once for all columns.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_bspmm(int32_t nb, const int32_t *__restrict__ brow_ptr,
+                                               const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+                                               const double *__restrict__ x, const double *__restrict__ f,
+                                               double *__restrict__ y, double *__restrict__ part,
+                                               const BatchState *st) {
+    __shared__ double lds[4][W];
+    if (st && !st->any) return;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, j = lane & 31, half = lane >> 5;
+    const int w = xcd_remap(blockIdx.x, gridDim.x);
+    double acc = 0.0;
+    for (int rr = 0; rr < kSpmmRowsPerWave; ++rr) {
+        const int row = (w * 4 + wv) * kSpmmRowsPerWave + rr;
+        if (row >= nb) break;  // uniform over the wave
+        const int beg = brow_ptr[row], end = brow_ptr[row + 1];
+        const int64_t m = end - beg;
+        const double *rv = bval + 9 * (int64_t)beg - beg;  // plane e of block b: rv[e * m + b]
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int b = beg + half; b < end; b += 2) {
+            const double v0 = rv[b], v1 = rv[m + b], v2 = rv[2 * m + b];
+            const double v3 = rv[3 * m + b], v4 = rv[4 * m + b], v5 = rv[5 * m + b];
+            const double v6 = rv[6 * m + b], v7 = rv[7 * m + b], v8 = rv[8 * m + b];
+            const int64_t c = 3 * (int64_t)bcol[b];
+            const double x0 = x[c * W + j], x1 = x[(c + 1) * W + j], x2 = x[(c + 2) * W + j];
+            a0 = fma(v0, x0, fma(v1, x1, fma(v2, x2, a0)));
+            a1 = fma(v3, x0, fma(v4, x1, fma(v5, x2, a1)));
+            a2 = fma(v6, x0, fma(v7, x1, fma(v8, x2, a2)));
+        }
+        a0 += __shfl_xor(a0, 32);
+        a1 += __shfl_xor(a1, 32);
+        a2 += __shfl_xor(a2, 32);
+        if (half == 0) {
+            const int64_t o = 3 * (int64_t)row * W + j;
+            if (MODE == 0) {
+                y[o] = a0;
+                y[o + W] = a1;
+                y[o + 2 * W] = a2;
+                acc = fma(x[o], a0, fma(x[o + W], a1, fma(x[o + 2 * W], a2, acc)));
+            } else {
+                const double r0 = f[o] - a0, r1 = f[o + W] - a1, r2 = f[o + 2 * W] - a2;
+                y[o] = r0;
+                y[o + W] = r1;
+                y[o + 2 * W] = r2;
+                acc = fma(r0, r0, fma(r1, r1, fma(r2, r2, acc)));
+            }
+        }
+    }
+    if (half == 0) lds[wv][j] = acc;
+    __syncthreads();
+    if (threadIdx.x < W)
+        part[(int64_t)blockIdx.x * W + threadIdx.x] =
+            (lds[0][threadIdx.x] + lds[1][threadIdx.x]) + (lds[2][threadIdx.x] + lds[3][threadIdx.x]);
+}
+
+// alpha_j = rho_j / p_j^T q_j for the running columns (breakdown test as in Algorithm 1).
+__global__ __launch_bounds__(1024) void k_balpha(const double *__restrict__ part, int nparts, BatchState *st) {
+    __shared__ double lds[32][W + 1];
+    if (!st->any) return;
+    const double pq = col_reduce_1024(part, nparts, lds);
+    if (threadIdx.x < W) {
+        const int j = threadIdx.x;
+        if (st->flag[j] == kRunning) {
+            const int it = st->iter;
+            const double a = st->rho[it & 1][j] / pq;
+            if (!(pq > 0.0) || !isfinite(pq) || !isfinite(a)) {
+                st->flag[j] = kBreakdown;
+                st->bad[j] = it;
+                st->iters_done[j] = it;
+            } else {
+                st->alpha[j] = a;
+            }
+        }
+    }
+}
+
+// update = 1: u_j += alpha_j p_j and r_j -= alpha_j q_j for the running columns, with
+// partials of ||r_j||^2; then (both modes) y = M^{-1} r over the tile's whole blocks
+// from an LDS copy of r.  One workgroup per contiguous range of tiles.
+__global__ __launch_bounds__(256) void k_bupdate_bj(int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start,
+                                                    double *__restrict__ u, double *__restrict__ r,
+                                                    double *__restrict__ y, const double *__restrict__ q,
+                                                    const double *__restrict__ p, const double *__restrict__ minv,
+                                                    const int32_t *__restrict__ bj_rowoff,
+                                                    const int32_t *__restrict__ bj_meta, double *__restrict__ part,
+                                                    const BatchState *st, int update) {
+    __shared__ double tile[kBatchTileDofs][W];
+    __shared__ double lds[8][W];
+    if (!st->any) return;
+    const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const bool run = update && st->flag[j] == kRunning;
+    const double alpha = run ? st->alpha[j] : 0.0;
+    const int w = xcd_remap(blockIdx.x, nwg);
+    const int t0 = (int)(((int64_t)w * ntiles) / nwg), t1 = (int)(((int64_t)(w + 1) * ntiles) / nwg);
+    double acc = 0.0;
+    for (int t = t0; t < t1; ++t) {
+        const int64_t d0 = tile_start[t], d1 = tile_start[t + 1];
+        __syncthreads();
+        for (int64_t d = d0 + g; d < d1; d += 8) {
+            const int64_t o = d * W + j;
+            double rn = r[o];
+            if (run) {
+                u[o] = fma(alpha, p[o], u[o]);
+                rn = fma(-alpha, q[o], rn);
+                r[o] = rn;
+            }
+            tile[d - d0][j] = rn;
+            acc = fma(rn, rn, acc);
+        }
+        __syncthreads();
+        for (int64_t d = d0 + g; d < d1; d += 8) {
+            const int meta = bj_meta[d];
+            const int size = meta >> 8, loc = meta & 255;
+            const double *mrow = minv + bj_rowoff[d];
+            const int base = (int)(d - d0) - loc;
+            double s = 0.0;
+            for (int kk = 0; kk < size; ++kk) s = fma(mrow[kk], tile[base + kk][j], s);
+            y[d * W + j] = s;
+        }
+    }
+    const double tot = group_sum_8(acc, lds);
+    if (update && threadIdx.x < W) part[(int64_t)blockIdx.x * W + threadIdx.x] = tot;
+}
+
+// Column checks (workgroup 0, when n_rr > 0): ||r_j|| from the partials against thr_j
+// and the iteration cap; any = some column still running.  Then the merged right-hand
+// side of Algorithm 3, g[c][j] = sum_e Z^T[c,e] a[e][j] - (KZ)^T[c,e] b[e][j], one
+// workgroup per deflation vector c (8 groups of 32 lanes stride over the entries; the
+// group sums are added in a fixed order).  b may be null.
+__global__ __launch_bounds__(256) void k_brestrict(int32_t k, const int32_t *__restrict__ zt_ptr,
+                                                   const int32_t *__restrict__ zt_idx,
+                                                   const double *__restrict__ zt_val,
+                                                   const int32_t *__restrict__ kzt_ptr,
+                                                   const int32_t *__restrict__ kzt_idx,
+                                                   const double *__restrict__ kzt_val, const double *__restrict__ a,
+                                                   const double *__restrict__ b, double *__restrict__ gout,
+                                                   BatchState *st, const double *__restrict__ part_rr, int n_rr,
+                                                   int iter_offset, int max_iter) {
+    __shared__ double lds[8][W];
+    const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
+    if (st) {
+        if (wg_any(st) == 0) return;
+        if (blockIdx.x == 0 && n_rr > 0) {
+            double s = 0.0;
+            for (int w = g; w < n_rr; w += 8) s += part_rr[(int64_t)w * W + j];
+            const double rr = group_sum_8(s, lds);
+            __shared__ int32_t run_s[W];
+            if (threadIdx.x < W) {
+                int32_t fl = st->flag[j];
+                if (fl == kRunning) {
+                    const int done = st->iter + iter_offset;
+                    st->rr[j] = rr;
+                    if (!isfinite(rr)) {
+                        fl = kBreakdown;
+                        st->bad[j] = st->iter;
+                    } else if (sqrt(rr) <= st->thr[j]) {
+                        fl = kConverged;
+                    } else if (done >= max_iter) {
+                        fl = kMaxIter;
+                    }
+                    if (fl != kRunning) {
+                        st->flag[j] = fl;
+                        st->iters_done[j] = done;
+                    }
+                }
+                run_s[j] = fl == kRunning;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                int32_t any = 0;
+                for (int h = 0; h < W; ++h) any |= run_s[h];
+                st->any = any;
+            }
+            __syncthreads();
+        }
+    }
+    const int cc = xcd_remap(blockIdx.x, gridDim.x);
+    if (cc >= k) return;
+    double s = 0.0;
+    for (int e = zt_ptr[cc] + g; e < zt_ptr[cc + 1]; e += 8) s = fma(zt_val[e], a[(int64_t)zt_idx[e] * W + j], s);
+    if (b)
+        for (int e = kzt_ptr[cc] + g; e < kzt_ptr[cc + 1]; e += 8)
+            s = fma(-kzt_val[e], b[(int64_t)kzt_idx[e] * W + j], s);
+    const double t = group_sum_8(s, lds);
+    if (threadIdx.x < W) gout[(int64_t)cc * W + threadIdx.x] = t;
+}
+
+// delta = E^{-1} g for all columns: one workgroup per row of E^{-1}.
+__global__ __launch_bounds__(256) void k_bcoarse(int32_t k, int64_t ld, const double *__restrict__ einv,
+                                                 const double *__restrict__ gin, double *__restrict__ delta,
+                                                 const BatchState *st) {
+    __shared__ double lds[8][W];
+    if (st && !st->any) return;
+    const int row = blockIdx.x;
+    if (row >= k) return;
+    const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const double *e = einv + (int64_t)row * ld;
+    double s = 0.0;
+    for (int c = g; c < k; c += 8) s = fma(e[c], gin[(int64_t)c * W + j], s);
+    const double t = group_sum_8(s, lds);
+    if (threadIdx.x < W) delta[(int64_t)row * W + threadIdx.x] = t;
+}
+
+// out = base + Z delta (base may be null); optional partials of rdot_j^T out_j;
+// optionally advance the iteration.
+__global__ __launch_bounds__(256) void k_bprolong(int64_t n, int32_t nwg, const int32_t *__restrict__ z_ptr,
+                                                  const int32_t *__restrict__ z_col, const double *__restrict__ z_val,
+                                                  const double *__restrict__ delta, const double *base, double *out,
+                                                  const double *__restrict__ rdot, double *__restrict__ part,
+                                                  BatchState *st, int advance) {
+    __shared__ double lds[8][W];
+    if (st && !st->any) return;
+    const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int w = xcd_remap(blockIdx.x, nwg);
+    const int64_t per = (n + nwg - 1) / nwg;
+    const int64_t d1 = std::min<int64_t>(n, (int64_t)(w + 1) * per);
+    double acc = 0.0;
+    for (int64_t d = (int64_t)w * per + g; d < d1; d += 8) {
+        const int64_t o = d * W + j;
+        double s = base ? base[o] : 0.0;
+        double c = 0.0;
+        if (delta)
+            for (int e = z_ptr[d]; e < z_ptr[d + 1]; ++e) c = fma(z_val[e], delta[(int64_t)z_col[e] * W + j], c);
+        s += c;
+        out[o] = s;
+        if (rdot) acc = fma(rdot[o], s, acc);
+    }
+    if (rdot) {
+        const double t = group_sum_8(acc, lds);
+        if (threadIdx.x < W) part[(int64_t)blockIdx.x * W + threadIdx.x] = t;
+    }
+    if (advance && blockIdx.x == 0 && threadIdx.x == 0) st->iter = st->iter + 1;
+}
+
+// rho_j = r_j^T z_j, beta_{i-1,j} = rho_{i,j} / rho_{i-1,j} for the running columns,
+// rho kept in two parity slots.
+__global__ __launch_bounds__(1024) void k_bbeta(const double *__restrict__ part, int nparts, BatchState *st) {
+    __shared__ double lds[32][W + 1];
+    if (!st->any) return;
+    const double rho = col_reduce_1024(part, nparts, lds);
+    if (threadIdx.x < W) {
+        const int j = threadIdx.x;
+        if (st->flag[j] == kRunning) {
+            const int it = st->iter;
+            if (it > 0 && !isfinite(rho)) {
+                st->flag[j] = kBreakdown;
+                st->bad[j] = it - 1;
+                st->iters_done[j] = it;
+            } else {
+                st->beta[j] = it > 0 ? rho / st->rho[(it + 1) & 1][j] : 0.0;
+                st->rho[it & 1][j] = rho;
+            }
+        }
+    }
+}
+
+// p_j = z_j + beta_j p_j (p_0 = z_0) for the running columns; 0 for the others.
+__global__ __launch_bounds__(256) void k_bpupdate(int64_t n, const double *__restrict__ z, double *__restrict__ p,
+                                                  const BatchState *st) {
+    if (!st->any) return;
+    const int j = threadIdx.x & 31;
+    const bool run = st->flag[j] == kRunning;
+    const bool first = st->iter == 0;
+    const double beta = st->beta[j];
+    for (int64_t d = blockIdx.x * 8ll + (threadIdx.x >> 5); d < n; d += (int64_t)gridDim.x * 8) {
+        const int64_t o = d * W + j;
+        p[o] = run ? (first ? z[o] : fma(beta, p[o], z[o])) : 0.0;
+    }
+}
+
+// dst[d][j] = src[d * nrhs + j] for j < nrhs, 0 for the padding columns.
+__global__ void k_bpack(int64_t n, int32_t nrhs, const double *__restrict__ src, double *__restrict__ dst) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * W; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = i / W;
+        const int j = (int)(i % W);
+        dst[i] = j < nrhs ? src[d * nrhs + j] : 0.0;
+    }
+}
+
+// dst[d * nrhs + j] = src[d][j], or 0 for the columns in zero_mask.
+__global__ void k_bunpack(int64_t n, int32_t nrhs, const double *__restrict__ src, double *__restrict__ dst,
+                          uint32_t zero_mask) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * nrhs;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = i / nrhs;
+        const int j = (int)(i % nrhs);
+        dst[i] = ((zero_mask >> j) & 1u) ? 0.0 : src[d * W + j];
+    }
+}
+
+// Column partials of ||a_j||^2 and of the count of non-finite entries of a and b.
+__global__ __launch_bounds__(256) void k_bnorm(int64_t n, int32_t nwg, const double *__restrict__ a,
+                                               const double *__restrict__ b, double *__restrict__ part,
+                                               double *__restrict__ part_bad) {
+    __shared__ double lds[8][W];
+    const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int64_t per = (n + nwg - 1) / nwg;
+    const int64_t d1 = std::min<int64_t>(n, (int64_t)(blockIdx.x + 1) * per);
+    double acc = 0.0, bad = 0.0;
+    for (int64_t d = (int64_t)blockIdx.x * per + g; d < d1; d += 8) {
+        const double v = a[d * W + j];
+        acc = fma(v, v, acc);
+        if (!isfinite(v)) bad += 1.0;
+        if (b && !isfinite(b[d * W + j])) bad += 1.0;
+    }
+    const double t = group_sum_8(acc, lds);
+    __syncthreads();
+    const double tb = group_sum_8(bad, lds);
+    if (threadIdx.x < W) {
+        part[(int64_t)blockIdx.x * W + threadIdx.x] = t;
+        part_bad[(int64_t)blockIdx.x * W + threadIdx.x] = tb;
+    }
+}
+
+// aux[j] = column sums of part; nonfinite = 1 when the column sums of part_bad (if
+// given) are not all zero.
+__global__ __launch_bounds__(1024) void k_baux(const double *__restrict__ part, const double *__restrict__ part_bad,
+                                               int nparts, BatchState *st) {
+    __shared__ double lds[32][W + 1];
+    const double s = col_reduce_1024(part, nparts, lds);
+    if (threadIdx.x < W) st->aux[threadIdx.x] = s;
+    if (part_bad) {
+        __syncthreads();
+        const double b = col_reduce_1024(part_bad, nparts, lds);
+        __shared__ double bsum[W];
+        if (threadIdx.x < W) bsum[threadIdx.x] = b;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int h = 0; h < W; ++h) t += bsum[h];
+            st->nonfinite = t > 0.0 ? 1 : 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host side
+#define BLAUNCH(...)                                         \
+    do {                                                     \
+        hipLaunchKernelGGL(__VA_ARGS__);                     \
+        if (hipGetLastError() != hipSuccess) return DPCG_EHIP; \
+    } while (0)
+#define BHIP(expr)                                    \
+    do {                                              \
+        if ((expr) != hipSuccess) return DPCG_EHIP;   \
+    } while (0)
+#define BTRY(expr)                         \
+    do {                                   \
+        int s_ = (expr);                   \
+        if (s_ != DPCG_OK) return s_;      \
+    } while (0)
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+int grid_rows(int64_t work, int per, int cap) {
+    int g = (int)std::max<int64_t>(1, std::min<int64_t>(cap, (work + per - 1) / per));
+    if (g >= 8) g = (g + 7) & ~7;
+    return g;
+}
+
+template <class T>
+int balloc(dpcg_ctx *c, T **p, size_t count) {
+    void *q = nullptr;
+    const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
+    BHIP(dev_alloc(&q, bytes));
+    c->allocations.push_back(q);
+    c->device_bytes += (int64_t)bytes;
+    *p = (T *)q;
+    return DPCG_OK;
+}
+
+int ensure_ws(dpcg_ctx *c) {
+    if (c->bws) return DPCG_OK;
+    auto *b = new BatchWorkspace();
+    c->bws = b;
+    const size_t nw = (size_t)c->n * W, kw = (size_t)std::max(1, c->k) * W;
+    BTRY(balloc(c, &b->f, nw));
+    BTRY(balloc(c, &b->u, nw));
+    BTRY(balloc(c, &b->r, nw));
+    BTRY(balloc(c, &b->y, nw));
+    BTRY(balloc(c, &b->z, nw));
+    BTRY(balloc(c, &b->q, nw));
+    BTRY(balloc(c, &b->p, nw));
+    BTRY(balloc(c, &b->g, kw));
+    BTRY(balloc(c, &b->delta, kw));
+    b->spmm_nwg = grid_rows(c->nb, 4 * kSpmmRowsPerWave, 1 << 30);
+    b->upd_nwg = grid_rows(c->bjb_ntiles, 1, 512);
+    b->vec_nwg = grid_rows(c->n, 64, 512);
+    const size_t np = (size_t)std::max({b->spmm_nwg, b->upd_nwg, b->vec_nwg}) * W;
+    BTRY(balloc(c, &b->part, np));
+    BTRY(balloc(c, &b->part2, np));
+    BTRY(balloc(c, &b->st, 1));
+    BHIP(hipHostMalloc((void **)&b->snap, sizeof(BatchState), hipHostMallocDefault));
+    return DPCG_OK;
+}
+
+int read_bstate(dpcg_ctx *c, BatchState &out) {
+    BatchWorkspace *b = c->bws;
+    BHIP(hipMemcpyAsync(b->snap, b->st, sizeof(BatchState), hipMemcpyDeviceToHost, c->stream));
+    BHIP(hipStreamSynchronize(c->stream));
+    out = *b->snap;
+    return DPCG_OK;
+}
+
+int enqueue_restrict(dpcg_ctx *c, const double *a, const double *bvec, BatchState *st, const double *part_rr, int n_rr,
+                     int iter_offset, int max_iter) {
+    BatchWorkspace *b = c->bws;
+    const int grid = c->k > 0 ? ((c->k + 7) & ~7) : 8;
+    BLAUNCH(k_brestrict, dim3(grid), dim3(256), 0, c->stream, c->k, c->zt_ptr, c->zt_idx, c->zt_val, c->kzt_ptr,
+            c->kzt_idx, c->kzt_val, a, bvec, b->g, st, part_rr, n_rr, iter_offset, max_iter);
+    return DPCG_OK;
+}
+
+int enqueue_coarse(dpcg_ctx *c, const BatchState *st) {
+    BatchWorkspace *b = c->bws;
+    if (c->k == 0) return DPCG_OK;
+    BLAUNCH(k_bcoarse, dim3(c->k), dim3(256), 0, c->stream, c->k, c->einv_ld, c->einv, b->g, b->delta, st);
+    return DPCG_OK;
+}
+
+int enqueue_prolong(dpcg_ctx *c, const double *base, double *out, const double *rdot, BatchState *st, int advance) {
+    BatchWorkspace *b = c->bws;
+    BLAUNCH(k_bprolong, dim3(b->vec_nwg), dim3(256), 0, c->stream, c->n, b->vec_nwg, c->z_ptr, c->z_col, c->z_val,
+            c->k > 0 ? b->delta : nullptr, base, out, rdot, b->part, st, advance);
+    return DPCG_OK;
+}
+
+// Algorithm 2 for every column, then Algorithm 3 on r_0 and p_0 = z_0.
+int enqueue_bstart(dpcg_ctx *c, bool guess, int max_iter) {
+    BatchWorkspace *b = c->bws;
+    BatchState *st = b->st;
+    if (c->k > 0) {
+        BTRY(enqueue_restrict(c, b->f, guess ? b->u : nullptr, nullptr, nullptr, 0, 0, 0));
+        BTRY(enqueue_coarse(c, nullptr));
+        BTRY(enqueue_prolong(c, guess ? b->u : nullptr, b->u, nullptr, nullptr, 0));
+    }
+    BLAUNCH(k_bspmm<1>, dim3(b->spmm_nwg), dim3(256), 0, c->stream, c->nb, c->brow_ptr, c->bcol, c->bval,
+            (const double *)b->u, (const double *)b->f, b->r, b->part2, (const BatchState *)st);
+    BLAUNCH(k_bupdate_bj, dim3(b->upd_nwg), dim3(256), 0, c->stream, c->bjb_ntiles, b->upd_nwg, c->bjb_start, b->u,
+            b->r, b->y, (const double *)b->q, (const double *)b->p, (const double *)c->minv, c->bj_rowoff, c->bj_meta,
+            b->part, (const BatchState *)st, 0);
+    BTRY(enqueue_restrict(c, b->r, b->y, st, b->part2, b->spmm_nwg, 0, max_iter));
+    BTRY(enqueue_coarse(c, st));
+    BTRY(enqueue_prolong(c, b->y, b->z, b->r, st, 0));
+    BLAUNCH(k_bbeta, dim3(1), dim3(1024), 0, c->stream, (const double *)b->part, b->vec_nwg, st);
+    BLAUNCH(k_bpupdate, dim3(std::min<int64_t>(8192, (c->n + 7) / 8)), dim3(256), 0, c->stream, c->n,
+            (const double *)b->z, b->p, (const BatchState *)st);
+    return DPCG_OK;
+}
+
+int enqueue_biteration(dpcg_ctx *c, int max_iter, std::vector<hipEvent_t> &ev, size_t &ev_used) {
+    BatchWorkspace *b = c->bws;
+    BatchState *st = b->st;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        if (ev_used + 2 > ev.size())
+            for (int i = 0; i < 32; ++i) {
+                hipEvent_t e;
+                BHIP(hipEventCreate(&e));
+                ev.push_back(e);
+            }
+        e0 = ev[ev_used];
+        e1 = ev[ev_used + 1];
+        ev_used += 2;
+    }
+    hipExtLaunchKernelGGL(k_bspmm<0>, dim3(b->spmm_nwg), dim3(256), 0, c->stream, e0, e1, 0, c->nb, c->brow_ptr,
+                          c->bcol, (const double *)c->bval, (const double *)b->p, (const double *)nullptr, b->q,
+                          b->part, (const BatchState *)st);
+    BHIP(hipGetLastError());
+    BLAUNCH(k_balpha, dim3(1), dim3(1024), 0, c->stream, (const double *)b->part, b->spmm_nwg, st);
+    BLAUNCH(k_bupdate_bj, dim3(b->upd_nwg), dim3(256), 0, c->stream, c->bjb_ntiles, b->upd_nwg, c->bjb_start, b->u,
+            b->r, b->y, (const double *)b->q, (const double *)b->p, (const double *)c->minv, c->bj_rowoff, c->bj_meta,
+            b->part2, (const BatchState *)st, 1);
+    BTRY(enqueue_restrict(c, b->r, b->y, st, b->part2, b->upd_nwg, 1, max_iter));
+    BTRY(enqueue_coarse(c, st));
+    BTRY(enqueue_prolong(c, b->y, b->z, b->r, st, 1));
+    BLAUNCH(k_bbeta, dim3(1), dim3(1024), 0, c->stream, (const double *)b->part, b->vec_nwg, st);
+    BLAUNCH(k_bpupdate, dim3(std::min<int64_t>(8192, (c->n + 7) / 8)), dim3(256), 0, c->stream, c->n,
+            (const double *)b->z, b->p, (const BatchState *)st);
+    return DPCG_OK;
+}
+
+// ||a_j||^2 into aux (and the non-finite test of a and b when asked).
+int column_norms(dpcg_ctx *c, const double *a, const double *bvec, bool check, BatchState &out) {
+    BatchWorkspace *b = c->bws;
+    BLAUNCH(k_bnorm, dim3(b->vec_nwg), dim3(256), 0, c->stream, c->n, b->vec_nwg, a, bvec, b->part, b->part2);
+    BLAUNCH(k_baux, dim3(1), dim3(1024), 0, c->stream, (const double *)b->part, check ? (const double *)b->part2 : nullptr,
+            b->vec_nwg, b->st);
+    return read_bstate(c, out);
+}
+
+}  // namespace
+
+int solve_batch(dpcg_ctx *c, int32_t nrhs, const double *F, double *U, double tol, const dpcg_options *opt_in,
+                dpcg_info *infos) {
+    const double t0 = now_ms();
+    dpcg_options opt;
+    dpcg_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (!c || nrhs < 1 || nrhs > W || !F || !U || !(tol > 0.0) || opt.max_iter < 0) return DPCG_EINVAL;
+    if (opt.precision != DPCG_PREC_FP64 || opt.record_history) return DPCG_EINVAL;
+    if (opt.check_every <= 0) opt.check_every = 16;
+    const bool guess = opt.use_initial_guess != 0;
+    BTRY(ensure_ws(c));
+    BatchWorkspace *b = c->bws;
+    hipStream_t s = c->stream;
+    const int pgrid = (int)std::min<int64_t>(8192, (c->n * W + 255) / 256);
+    BLAUNCH(k_bpack, dim3(pgrid), dim3(256), 0, s, c->n, nrhs, F, b->f);
+    if (guess) BLAUNCH(k_bpack, dim3(pgrid), dim3(256), 0, s, c->n, nrhs, (const double *)U, b->u);
+    else BHIP(hipMemsetAsync(b->u, 0, sizeof(double) * c->n * W, s));
+    BatchState nrm;
+    BTRY(column_norms(c, b->f, guess ? b->u : nullptr, true, nrm));
+    if (nrm.nonfinite) return DPCG_ENONFINITE;
+    BatchState init{};
+    init.any = 0;
+    uint32_t zero_mask = 0;
+    double fnorm[W];
+    for (int j = 0; j < W; ++j) {
+        fnorm[j] = std::sqrt(nrm.aux[j]);
+        const bool live = j < nrhs && nrm.aux[j] > 0.0;
+        init.flag[j] = live ? kRunning : kConverged;
+        init.thr[j] = tol * fnorm[j];
+        if (live) init.any = 1;
+        else if (j < nrhs) zero_mask |= 1u << j;
+    }
+    std::vector<hipEvent_t> ev;
+    size_t ev_used = 0;
+    BatchState st = init;
+    if (init.any) {
+        *b->snap = init;
+        BHIP(hipMemcpyAsync(b->st, b->snap, sizeof(BatchState), hipMemcpyHostToDevice, s));
+        BHIP(hipStreamSynchronize(s));
+        BTRY(enqueue_bstart(c, guess, opt.max_iter));
+        BTRY(read_bstate(c, st));
+        int32_t enq = 0;
+        while (st.any && enq < opt.max_iter) {
+            const int m = std::min(opt.check_every, opt.max_iter - enq);
+            for (int i = 0; i < m; ++i) BTRY(enqueue_biteration(c, opt.max_iter, ev, ev_used));
+            enq += m;
+            BTRY(read_bstate(c, st));
+        }
+        for (int j = 0; j < W; ++j)
+            if (st.flag[j] == kRunning) {  // the host-side cap ended the loop (max_iter == 0)
+                st.flag[j] = kMaxIter;
+                st.iters_done[j] = enq;
+            }
+        if (c->timing) {
+            int32_t real = 0;
+            for (int j = 0; j < nrhs; ++j) real = std::max(real, st.iters_done[j]);
+            for (size_t i = 0; i + 1 < ev_used && (int32_t)(i / 2) < real; i += 2) {
+                float ms = 0.f;
+                BHIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+                c->spmv_ms += ms;
+                c->spmv_launches += 1;
+            }
+        }
+    }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    // true residuals f_j - K u_j
+    BLAUNCH(k_bspmm<1>, dim3(b->spmm_nwg), dim3(256), 0, s, c->nb, c->brow_ptr, c->bcol, c->bval,
+            (const double *)b->u, (const double *)b->f, b->q, b->part2, (const BatchState *)nullptr);
+    BLAUNCH(k_baux, dim3(1), dim3(1024), 0, s, (const double *)b->part2, (const double *)nullptr, b->spmm_nwg, b->st);
+    BatchState fin;
+    BTRY(read_bstate(c, fin));
+    BLAUNCH(k_bunpack, dim3(pgrid), dim3(256), 0, s, c->n, nrhs, (const double *)b->u, U, zero_mask);
+    BHIP(hipStreamSynchronize(s));
+    const double ms = now_ms() - t0;
+    int worst = DPCG_OK;
+    for (int j = 0; j < nrhs; ++j) {
+        int status;
+        int64_t bad = -1;
+        switch (st.flag[j]) {
+            case kConverged: status = DPCG_OK; break;
+            case kBreakdown: status = DPCG_EBREAKDOWN; bad = st.bad[j]; break;
+            default: status = DPCG_NOT_CONVERGED; break;
+        }
+        const bool zero = (zero_mask >> j) & 1u;
+        if (status == DPCG_EBREAKDOWN) worst = DPCG_EBREAKDOWN;
+        else if (status == DPCG_NOT_CONVERGED && worst == DPCG_OK) worst = DPCG_NOT_CONVERGED;
+        if (infos) {
+            dpcg_info &in = infos[j];
+            in.status = status;
+            in.iterations = zero ? 0 : st.iters_done[j];
+            in.rel_res_recursive = zero ? 0.0 : std::sqrt(st.rr[j]) / fnorm[j];
+            in.rel_res_true = zero ? 0.0 : std::sqrt(fin.aux[j]) / fnorm[j];
+            in.setup_ms = c->setup_ms;
+            in.solve_ms = ms;
+            in.bad_index = bad;
+            in.refinements = 0;
+            in.pad_ = 0;
+        }
+    }
+    return worst;
+}
+
+void release_batch(dpcg_ctx *c) {
+    if (!c || !c->bws) return;
+    if (c->bws->snap) (void)hipHostFree(c->bws->snap);
+    delete c->bws;  // device arrays are in c->allocations
+    c->bws = nullptr;
+}
+
+}  // namespace dpcg

@@ -157,6 +157,7 @@ void release(dpcg_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     give_events(c->events);
+    release_batch(c);
     for (void *p : c->allocations) dev_release(p);
     for (auto &w : c->ws) {
         give_pinned_state(w.snap);
@@ -464,6 +465,13 @@ int dpcg_solve(dpcg_handle h, const double *f, double *u, double tol, const dpcg
     const int st = solve_impl(h, h->ws[0], f, u, tol, opt, info);
     if (st < 0 && info) info->status = st;
     return st;
+}
+
+int dpcg_solve_batch(dpcg_handle h, int32_t nrhs, const double *F, double *U, double tol, const dpcg_options *opt,
+                     dpcg_info *infos) {
+    if (!h) return DPCG_EINVAL;
+    h->inner32 = false;
+    return solve_batch(h, nrhs, F, U, tol, opt, infos);
 }
 
 int dpcg_solve_adjoint(dpcg_handle h, const double *g, double *lambda, double tol, const dpcg_options *opt,

@@ -27,6 +27,9 @@ namespace dpcg {
 constexpr int kThreads = 256;     // threads per workgroup everywhere
 constexpr int kMaxBlock = 18;     // largest block-Jacobi block
 constexpr int kMaxElemDofs = 256; // largest element (DoFs) of dpcg_element_gradient
+constexpr int kBatchCols = 32;    // columns of the multi-RHS workspace (right-hand sides per batch)
+constexpr int kBatchTileWindow = 47;                         // block starts per multi-RHS tile
+constexpr int kBatchTileDofs = kBatchTileWindow + kMaxBlock - 1;  // <= 64 DoFs per tile
 
 // The hardware spreads consecutive workgroups round-robin over the 8 XCDs; give each
 // XCD a contiguous range of work so neighbouring rows share its L2.
@@ -71,6 +74,34 @@ struct Workspace {
     int32_t hist_len = 0;
 };
 
+// Device state of a multi-RHS solve: one recurrence per column, as State.
+struct BatchState {
+    int32_t any;                 // 1 while some column runs (set by the restriction's check)
+    int32_t iter;                // iteration in flight
+    int32_t flag[kBatchCols];    // kRunning, kConverged, kMaxIter, kBreakdown per column
+    int32_t iters_done[kBatchCols];
+    int32_t bad[kBatchCols];
+    int32_t pad;
+    double thr[kBatchCols];
+    double rho[2][kBatchCols];
+    double alpha[kBatchCols];
+    double beta[kBatchCols];
+    double rr[kBatchCols];
+    double aux[kBatchCols];      // per-column scratch (norms)
+    int32_t nonfinite;
+    int32_t pad2;
+};
+
+// n x kBatchCols row-major vectors (entry (d, j) at d * kBatchCols + j).
+struct BatchWorkspace {
+    double *f = nullptr, *u = nullptr, *r = nullptr, *y = nullptr, *z = nullptr, *q = nullptr, *p = nullptr;
+    double *g = nullptr, *delta = nullptr;        // k x kBatchCols
+    double *part = nullptr, *part2 = nullptr;     // per-workgroup column partials
+    BatchState *st = nullptr;                     // device
+    BatchState *snap = nullptr;                   // pinned host mirror
+    int32_t spmm_nwg = 0, upd_nwg = 0, vec_nwg = 0;
+};
+
 struct SpmvPlan {
     int group = 16;          // lanes per block row
     int nwg = 0;             // workgroups
@@ -95,6 +126,9 @@ struct dpcg_ctx {
     double *minv = nullptr;
     int32_t *bj_rowoff = nullptr, *bj_meta = nullptr, *bj_wg_start = nullptr;
     int32_t bj_nwg = 0, bj_ntiles = 0;
+    int32_t *bjb_start = nullptr;   // tiles of whole blocks, <= kBatchTileDofs DoFs (multi-RHS)
+    int32_t bjb_ntiles = 0;
+    dpcg::BatchWorkspace *bws = nullptr;  // multi-RHS workspace, made on the first batched solve
     // deflation
     int32_t *z_ptr = nullptr, *z_col = nullptr;
     double *z_val = nullptr;
@@ -140,6 +174,12 @@ hipError_t launch_reduce_aux(const dpcg_ctx *c, Workspace &w, int n_parts);
 hipError_t launch_to_f32(const dpcg_ctx *c, const double *src, int64_t count, float *dst);
 // y += x
 hipError_t launch_add(const dpcg_ctx *c, const double *x, double *y);
+
+// batch.hip: multi-RHS solve (nrhs <= kBatchCols columns, caller arrays n x nrhs
+// row-major); returns a DPCG_* status and fills infos[nrhs] when given.
+int solve_batch(dpcg_ctx *c, int32_t nrhs, const double *F, double *U, double tol, const dpcg_options *opt,
+                dpcg_info *infos);
+void release_batch(dpcg_ctx *c);
 
 // adjoint.hip: g[e] = -lam_e^T K_e u_e after a device-side check of the element data;
 // returns a DPCG_* status.

@@ -556,15 +556,15 @@ __global__ __launch_bounds__(64) void k_bj_factor(int32_t nblocks, const int32_t
     }
 }
 
-// tile t = blocks starting in [t * kTileDofs, (t+1) * kTileDofs); start = first such block.
+// tile t = blocks starting in [t * window, (t+1) * window); start = first such block.
 __global__ void k_tiles(int32_t ntiles, int32_t nblocks, const int32_t *__restrict__ bp, int64_t n,
-                        int32_t *__restrict__ tile_start) {
+                        int32_t window, int32_t *__restrict__ tile_start) {
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t <= ntiles; t += gridDim.x * blockDim.x) {
         if (t == ntiles) {
             tile_start[t] = (int32_t)n;
             continue;
         }
-        const int64_t target = (int64_t)t * kTileDofs;
+        const int64_t target = (int64_t)t * window;
         int lo = 0, hi = nblocks;  // first block with start >= target
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
@@ -1337,7 +1337,12 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     c->bj_ntiles = (int32_t)((n + kTileDofs - 1) / kTileDofs);
     HT(keep(c, &c->bj_wg_start, c->bj_ntiles + 1));
     hipLaunchKernelGGL(k_tiles, dim3(grid_for(c->bj_ntiles + 1)), dim3(256), 0, s, c->bj_ntiles, nblocks, bp, n,
-                       c->bj_wg_start);
+                       kTileDofs, c->bj_wg_start);
+    // the multi-RHS kernels stage tiles of <= kBatchTileDofs DoFs times 32 columns
+    c->bjb_ntiles = (int32_t)((n + kBatchTileWindow - 1) / kBatchTileWindow);
+    HT(keep(c, &c->bjb_start, c->bjb_ntiles + 1));
+    hipLaunchKernelGGL(k_tiles, dim3(grid_for(c->bjb_ntiles + 1)), dim3(256), 0, s, c->bjb_ntiles, nblocks, bp, n,
+                       kBatchTileWindow, c->bjb_start);
     // Z by rows (int32 row pointer) for the prolongation
     HT(keep(c, &c->z_ptr, n + 1));
     if (k > 0) {

@@ -1,0 +1,154 @@
+"""GPU parity of multi-RHS solves: every column against its own single-RHS solve (same
+method, same iterates up to the order of floating-point sums) and the first column
+against the oracle.
+
+Tolerances: solutions within 1e-6 relative of the single solves and of the oracle;
+iteration counts equal below 50 iterations and within 2% above; zero and already
+converged columns stop at iteration 0; frozen columns do not move while others run.
+"""
+import ctypes as C
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2111_09294_amd as D  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a, np.float64), device=DEV)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def iters_close(a, b):
+    if max(a, b) < 50:
+        return a == b
+    return abs(a - b) <= 0.02 * max(a, b)
+
+
+@pytest.fixture(scope="module")
+def solver(problems):
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            p = problems(name)
+            say(f"[batch setup] {name} n={p.n} k={p.k}")
+            cache[name] = (p, D.Solver.from_problem(p, DEV))
+        return cache[name]
+
+    yield get
+    for _, s in cache.values():
+        s.close()
+
+
+def _columns(p, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    F = rng.standard_normal((p.n, nrhs))
+    F[:, 0] = p.f
+    return F
+
+
+@pytest.mark.parametrize("name,nrhs", [("plain6", 5), ("edge4", 32), ("penny12", 7), ("edge10", 32),
+                                       ("penny40", 8)])
+def test_batch_matches_single_solves(solver, name, nrhs):
+    p, s = solver(name)
+    F = _columns(p, nrhs, 41)
+    U, infos = s.solve_batch(dev(F), tol=1e-8)
+    U = host(U)
+    its = []
+    for j in range(nrhs):
+        u1, i1 = s.solve(dev(F[:, j]), tol=1e-8)
+        u1 = host(u1)
+        its.append((infos[j]["iterations"], i1["iterations"]))
+        assert infos[j]["status"] == D.abi.OK
+        assert iters_close(infos[j]["iterations"], i1["iterations"]), (j, infos[j], i1)
+        assert np.linalg.norm(U[:, j] - u1) <= 1e-6 * np.linalg.norm(u1)
+        assert infos[j]["rel_res_recursive"] <= 1e-8 and infos[j]["rel_res_true"] <= 1.5e-8
+    say(f"[batch] {name} nrhs={nrhs}: (batch, single) iterations {its[:4]}..., "
+        f"batch solve {infos[0]['solve_ms']:.2f} ms")
+    if name in ("edge10", "penny40"):
+        o = O.Oracle.from_problem(p)
+        ref = o.solve(p.f, tol=1e-8)
+        assert np.linalg.norm(U[:, 0] - ref["u"]) <= 1e-6 * np.linalg.norm(ref["u"])
+        assert iters_close(infos[0]["iterations"], ref["iterations"])
+
+
+def test_batch_masking_of_finished_columns(solver):
+    p, s = solver("edge10")
+    K = p.K_scipy()
+    Z = p.Z_scipy()
+    rng = np.random.default_rng(42)
+    x = rng.standard_normal(p.k)
+    F = np.stack([p.f,                       # ordinary column
+                  np.zeros(p.n),             # zero column: 0 after 0 iterations
+                  K @ (Z @ x),               # in K range(Z): exact after the start vector
+                  1e6 * p.f,                 # same iterates as column 0, scaled
+                  rng.standard_normal(p.n)], 1)
+    U, infos = s.solve_batch(dev(F), tol=1e-8)
+    U = host(U)
+    assert [i["status"] for i in infos] == [D.abi.OK] * 5
+    assert infos[1]["iterations"] == 0 and np.all(U[:, 1] == 0.0)
+    assert infos[2]["iterations"] == 0
+    assert np.linalg.norm(U[:, 2] - Z @ x) <= 1e-8 * np.linalg.norm(Z @ x)
+    assert infos[3]["iterations"] == infos[0]["iterations"]
+    assert np.allclose(U[:, 3], 1e6 * U[:, 0], rtol=1e-9, atol=1e-9 * np.abs(1e6 * U[:, 0]).max())
+    for j in (0, 4):
+        u1, i1 = s.solve(dev(F[:, j]))
+        assert infos[j]["iterations"] == i1["iterations"]
+        assert np.linalg.norm(U[:, j] - host(u1)) <= 1e-6 * np.linalg.norm(host(u1))
+    # the finished columns are not disturbed by a longer one in the same batch
+    U2, infos2 = s.solve_batch(dev(F[:, [0, 4]]), tol=1e-8)
+    assert np.array_equal(host(U2)[:, 0], U[:, 0]) or np.linalg.norm(host(U2)[:, 0] - U[:, 0]) <= 1e-12 * np.linalg.norm(U[:, 0])
+
+
+def test_batch_options_and_errors(solver):
+    p, s = solver("penny12")
+    F = dev(_columns(p, 4, 43))
+    U1, i1 = s.solve_batch(F)
+    U2, i2 = s.solve_batch(F)
+    assert torch.equal(U1, U2) and [a["iterations"] for a in i1] == [a["iterations"] for a in i2]
+    # warm start from the solution: every column stops at iteration 0
+    U3, i3 = s.solve_batch(F, initial_guess=U1, tol=1e-7)
+    assert all(a["iterations"] == 0 and a["status"] == D.abi.OK for a in i3)
+    # iteration cap
+    U4, i4 = s.solve_batch(F, max_iter=3, raise_on_error=False)
+    assert all(a["status"] == D.abi.NOT_CONVERGED and a["iterations"] == 3 for a in i4)
+    # invalid batch sizes and options through the C ABI
+    o = D.abi.Options()
+    D.abi.lib().dpcg_default_options(C.byref(o))
+    out = torch.empty(p.n * 40, dtype=torch.float64, device=DEV)
+    src = torch.zeros(p.n * 40, dtype=torch.float64, device=DEV)
+    for nrhs in (0, 33, -1):
+        st = D.abi.lib().dpcg_solve_batch(s.handle, nrhs, C.c_void_p(src.data_ptr()), C.c_void_p(out.data_ptr()),
+                                          1e-8, C.byref(o), None)
+        assert st == D.abi.EINVAL
+    o.precision = D.abi.PREC_MIXED
+    st = D.abi.lib().dpcg_solve_batch(s.handle, 2, C.c_void_p(src.data_ptr()), C.c_void_p(out.data_ptr()), 1e-8,
+                                      C.byref(o), None)
+    assert st == D.abi.EINVAL
+    bad = _columns(p, 3, 44)
+    bad[7, 1] = np.nan
+    with pytest.raises(D.DpcgError) as e:
+        s.solve_batch(dev(bad))
+    assert e.value.code == D.abi.ENONFINITE
+    # a single solve afterwards is unaffected
+    u, info = s.solve(dev(p.f))
+    assert info["status"] == D.abi.OK
