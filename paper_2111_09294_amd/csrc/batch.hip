@@ -20,7 +20,6 @@ namespace dpcg {
 namespace {
 
 constexpr int W = kBatchCols;
-constexpr int kSpmmRowsPerWave = 4;
 
 // The batch's "any column running" flag as seen by the whole workgroup (one read,
 // broadcast through LDS): the restriction's workgroup 0 may change it meanwhile.
@@ -59,10 +58,12 @@ __device__ __forceinline__ double group_sum_8(double v, double (*lds)[W]) {
     return t;
 }
 
-// MODE 0: y = K x and partials of x_j^T y_j.  MODE 1: y = f - K x and partials of
-// ||y_j||^2.  One wave per block row (kSpmmRowsPerWave rows per wave): lanes 0-31 take
-// the even blocks of the row, lanes 32-63 the odd ones, one column per lane; the two
-// halves are added by a shuffle.  Block values are read once for all columns.
+// MODE 0: y = K x and partials of x_j^T y_j (column-major: part[j * gridDim.x + wg]).
+// MODE 1: y = f - K x and partials of ||y_j||^2 (row-major: part[wg * W + j]).
+// One wave per block row: lane (bg, cq) = (lane >> 3, lane & 7) takes every eighth
+// block of the row starting at bg (two blocks per step) and the four columns
+// 4 cq .. 4 cq + 3, so a block's nine values are read once for all columns and each x
+// row is read as 16-byte pairs; the eight block groups are added by a fixed shuffle tree.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_bspmm(int32_t nb, const int32_t *__restrict__ brow_ptr,
                                                const int32_t *__restrict__ bcol, const double *__restrict__ bval,
@@ -71,69 +72,117 @@ __global__ __launch_bounds__(256) void k_bspmm(int32_t nb, const int32_t *__rest
                                                const BatchState *st) {
     __shared__ double lds[4][W];
     if (st && !st->any) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, j = lane & 31, half = lane >> 5;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, bg = lane >> 3, cq = lane & 7;
     const int w = xcd_remap(blockIdx.x, gridDim.x);
-    double acc = 0.0;
-    for (int rr = 0; rr < kSpmmRowsPerWave; ++rr) {
-        const int row = (w * 4 + wv) * kSpmmRowsPerWave + rr;
-        if (row >= nb) break;  // uniform over the wave
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const int row = w * 4 + wv;
+    if (row < nb) {
         const int beg = brow_ptr[row], end = brow_ptr[row + 1];
         const int64_t m = end - beg;
         const double *rv = bval + 9 * (int64_t)beg - beg;  // plane e of block b: rv[e * m + b]
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        for (int b = beg + half; b < end; b += 2) {
-            const double v0 = rv[b], v1 = rv[m + b], v2 = rv[2 * m + b];
-            const double v3 = rv[3 * m + b], v4 = rv[4 * m + b], v5 = rv[5 * m + b];
-            const double v6 = rv[6 * m + b], v7 = rv[7 * m + b], v8 = rv[8 * m + b];
-            const int64_t c = 3 * (int64_t)bcol[b];
-            const double x0 = x[c * W + j], x1 = x[(c + 1) * W + j], x2 = x[(c + 2) * W + j];
-            a0 = fma(v0, x0, fma(v1, x1, fma(v2, x2, a0)));
-            a1 = fma(v3, x0, fma(v4, x1, fma(v5, x2, a1)));
-            a2 = fma(v6, x0, fma(v7, x1, fma(v8, x2, a2)));
+        double a[3][4];
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a[i][t] = 0.0;
+        for (int b0 = beg + bg; b0 < end; b0 += 16) {
+            double v[2][9], xv[2][3][4];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int b = b0 + 8 * h;
+                const bool ok = b < end;
+                const int bb = ok ? b : b0;
+#pragma unroll
+                for (int e = 0; e < 9; ++e) v[h][e] = ok ? rv[e * m + bb] : 0.0;
+                const int64_t c = 3 * (int64_t)bcol[bb];
+#pragma unroll
+                for (int jj = 0; jj < 3; ++jj) {
+                    const double2 *xr = (const double2 *)(x + (c + jj) * W + 4 * cq);
+                    const double2 x01 = xr[0], x23 = xr[1];
+                    xv[h][jj][0] = x01.x;
+                    xv[h][jj][1] = x01.y;
+                    xv[h][jj][2] = x23.x;
+                    xv[h][jj][3] = x23.y;
+                }
+            }
+            const bool ok1 = b0 + 8 < end;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (h == 0 || ok1)
+#pragma unroll
+                    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+                        for (int i = 0; i < 3; ++i)
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) a[i][t] = fma(v[h][3 * i + jj], xv[h][jj][t], a[i][t]);
         }
-        a0 += __shfl_xor(a0, 32);
-        a1 += __shfl_xor(a1, 32);
-        a2 += __shfl_xor(a2, 32);
-        if (half == 0) {
-            const int64_t o = 3 * (int64_t)row * W + j;
-            if (MODE == 0) {
-                y[o] = a0;
-                y[o + W] = a1;
-                y[o + 2 * W] = a2;
-                acc = fma(x[o], a0, fma(x[o + W], a1, fma(x[o + 2 * W], a2, acc)));
-            } else {
-                const double r0 = f[o] - a0, r1 = f[o + W] - a1, r2 = f[o + 2 * W] - a2;
-                y[o] = r0;
-                y[o + W] = r1;
-                y[o + 2 * W] = r2;
-                acc = fma(r0, r0, fma(r1, r1, fma(r2, r2, acc)));
+#pragma unroll
+        for (int off = 8; off < 64; off <<= 1)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) a[i][t] += __shfl_xor(a[i][t], off);
+        if (bg == 0) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int64_t o = (3 * (int64_t)row + i) * W + 4 * cq;
+                double out[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    if (MODE == 0) {
+                        out[t] = a[i][t];
+                        acc[t] = fma(x[o + t], out[t], acc[t]);
+                    } else {
+                        out[t] = f[o + t] - a[i][t];
+                        acc[t] = fma(out[t], out[t], acc[t]);
+                    }
+                }
+                double2 *yo = (double2 *)(y + o);
+                yo[0] = make_double2(out[0], out[1]);
+                yo[1] = make_double2(out[2], out[3]);
             }
         }
     }
-    if (half == 0) lds[wv][j] = acc;
+    if (bg == 0)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) lds[wv][4 * cq + t] = acc[t];
     __syncthreads();
-    if (threadIdx.x < W)
-        part[(int64_t)blockIdx.x * W + threadIdx.x] =
-            (lds[0][threadIdx.x] + lds[1][threadIdx.x]) + (lds[2][threadIdx.x] + lds[3][threadIdx.x]);
+    if (threadIdx.x < W) {
+        const double v = (lds[0][threadIdx.x] + lds[1][threadIdx.x]) + (lds[2][threadIdx.x] + lds[3][threadIdx.x]);
+        if (MODE == 0) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = v;
+        else part[(int64_t)blockIdx.x * W + threadIdx.x] = v;
+    }
 }
 
-// alpha_j = rho_j / p_j^T q_j for the running columns (breakdown test as in Algorithm 1).
-__global__ __launch_bounds__(1024) void k_balpha(const double *__restrict__ part, int nparts, BatchState *st) {
-    __shared__ double lds[32][W + 1];
+// Fixed-order sum of column j of column-major partials (nparts per column) by one
+// 256-thread workgroup; valid in thread 0.
+__device__ __forceinline__ double col_sum_cm(const double *__restrict__ part, int nparts, int j, double *lds4) {
+    const double *pc = part + (int64_t)j * nparts;
+    double s = 0.0;
+    for (int w = threadIdx.x; w < nparts; w += 256) s += pc[w];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = s;
+    __syncthreads();
+    return (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
+}
+
+// alpha_j = rho_j / p_j^T q_j for the running columns (breakdown test as in Algorithm 1);
+// workgroup j reduces column j of the SpMM partials.
+__global__ __launch_bounds__(256) void k_balpha(const double *__restrict__ part, int nparts, BatchState *st) {
+    __shared__ double lds[4];
     if (!st->any) return;
-    const double pq = col_reduce_1024(part, nparts, lds);
-    if (threadIdx.x < W) {
-        const int j = threadIdx.x;
-        if (st->flag[j] == kRunning) {
-            const int it = st->iter;
-            const double a = st->rho[it & 1][j] / pq;
-            if (!(pq > 0.0) || !isfinite(pq) || !isfinite(a)) {
-                st->flag[j] = kBreakdown;
-                st->bad[j] = it;
-                st->iters_done[j] = it;
-            } else {
-                st->alpha[j] = a;
-            }
+    const int j = blockIdx.x;
+    const double pq = col_sum_cm(part, nparts, j, lds);
+    if (threadIdx.x == 0 && st->flag[j] == kRunning) {
+        const int it = st->iter;
+        const double a = st->rho[it & 1][j] / pq;
+        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(a)) {
+            st->flag[j] = kBreakdown;
+            st->bad[j] = it;
+            st->iters_done[j] = it;
+        } else {
+            st->alpha[j] = a;
         }
     }
 }
@@ -186,28 +235,26 @@ __global__ __launch_bounds__(256) void k_bupdate_bj(int32_t ntiles, int32_t nwg,
     if (update && threadIdx.x < W) part[(int64_t)blockIdx.x * W + threadIdx.x] = tot;
 }
 
-// Column checks (workgroup 0, when n_rr > 0): ||r_j|| from the partials against thr_j
-// and the iteration cap; any = some column still running.  Then the merged right-hand
-// side of Algorithm 3, g[c][j] = sum_e Z^T[c,e] a[e][j] - (KZ)^T[c,e] b[e][j], one
-// workgroup per deflation vector c (8 groups of 32 lanes stride over the entries; the
-// group sums are added in a fixed order).  b may be null.
-__global__ __launch_bounds__(256) void k_brestrict(int32_t k, const int32_t *__restrict__ zt_ptr,
+// Column checks (workgroup 0, when n_rr > 0): ||r_j|| from the row-major partials
+// against thr_j and the iteration cap; any = some column still running.  Then the
+// merged right-hand side of Algorithm 3 in segments: segment s of deflation vector c
+// sums Z^T[c, e] a[e][j] over its entries (list 0) or -(KZ)^T[c, e] b[e][j] (list 1; 0
+// when b is null) into seg_part[s][j]; 32 groups of 32 lanes stride over the entries,
+// the group sums are added in a fixed order.
+__global__ __launch_bounds__(1024) void k_brestrict(const int32_t *__restrict__ seg, int32_t nseg,
                                                    const int32_t *__restrict__ zt_idx,
                                                    const double *__restrict__ zt_val,
-                                                   const int32_t *__restrict__ kzt_ptr,
                                                    const int32_t *__restrict__ kzt_idx,
                                                    const double *__restrict__ kzt_val, const double *__restrict__ a,
-                                                   const double *__restrict__ b, double *__restrict__ gout,
+                                                   const double *__restrict__ b, double *__restrict__ seg_part,
                                                    BatchState *st, const double *__restrict__ part_rr, int n_rr,
                                                    int iter_offset, int max_iter) {
-    __shared__ double lds[8][W];
+    __shared__ double lds[32][W + 1];
     const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
     if (st) {
         if (wg_any(st) == 0) return;
         if (blockIdx.x == 0 && n_rr > 0) {
-            double s = 0.0;
-            for (int w = g; w < n_rr; w += 8) s += part_rr[(int64_t)w * W + j];
-            const double rr = group_sum_8(s, lds);
+            const double rr = col_reduce_1024(part_rr, n_rr, lds);
             __shared__ int32_t run_s[W];
             if (threadIdx.x < W) {
                 int32_t fl = st->flag[j];
@@ -238,31 +285,72 @@ __global__ __launch_bounds__(256) void k_brestrict(int32_t k, const int32_t *__r
             __syncthreads();
         }
     }
-    const int cc = xcd_remap(blockIdx.x, gridDim.x);
-    if (cc >= k) return;
-    double s = 0.0;
-    for (int e = zt_ptr[cc] + g; e < zt_ptr[cc + 1]; e += 8) s = fma(zt_val[e], a[(int64_t)zt_idx[e] * W + j], s);
-    if (b)
-        for (int e = kzt_ptr[cc] + g; e < kzt_ptr[cc + 1]; e += 8)
-            s = fma(-kzt_val[e], b[(int64_t)kzt_idx[e] * W + j], s);
-    const double t = group_sum_8(s, lds);
-    if (threadIdx.x < W) gout[(int64_t)cc * W + threadIdx.x] = t;
+    const int sg = xcd_remap(blockIdx.x, gridDim.x);
+    if (sg >= nseg) return;
+    const int list = seg[4 * sg + 1], e0 = seg[4 * sg + 2], e1 = seg[4 * sg + 3];
+    const int32_t *idx = list ? kzt_idx : zt_idx;
+    const double *val = list ? kzt_val : zt_val;
+    const double *vec = list ? b : a;
+    double s = 0.0, s1 = 0.0;
+    if (vec) {
+        int e = e0 + g;
+        for (; e + 32 < e1; e += 64) {
+            s = fma(val[e], vec[(int64_t)idx[e] * W + j], s);
+            s1 = fma(val[e + 32], vec[(int64_t)idx[e + 32] * W + j], s1);
+        }
+        for (; e < e1; e += 32) s = fma(val[e], vec[(int64_t)idx[e] * W + j], s);
+    }
+    __syncthreads();  // lds may still be read by the check above
+    lds[g][j] = s + s1;
+    __syncthreads();
+    if (threadIdx.x < W) {
+        double t = 0.0;
+        for (int h = 0; h < 32; ++h) t += lds[h][threadIdx.x];
+        seg_part[(int64_t)sg * W + threadIdx.x] = list ? -t : t;
+    }
 }
 
-// delta = E^{-1} g for all columns: one workgroup per row of E^{-1}.
-__global__ __launch_bounds__(256) void k_bcoarse(int32_t k, int64_t ld, const double *__restrict__ einv,
-                                                 const double *__restrict__ gin, double *__restrict__ delta,
+// g[c][j] = sum of column c's segment partials, in segment order (8 columns per
+// workgroup).
+__global__ __launch_bounds__(256) void k_bsegsum(int32_t k, const int32_t *__restrict__ seg_ptr,
+                                                 const double *__restrict__ seg_part, double *__restrict__ gout,
                                                  const BatchState *st) {
-    __shared__ double lds[8][W];
     if (st && !st->any) return;
-    const int row = blockIdx.x;
-    if (row >= k) return;
+    const int c = blockIdx.x * 8 + (threadIdx.x >> 5), j = threadIdx.x & 31;
+    if (c >= k) return;
+    double t = 0.0;
+    for (int sg = seg_ptr[c]; sg < seg_ptr[c + 1]; ++sg) t += seg_part[(int64_t)sg * W + j];
+    gout[(int64_t)c * W + j] = t;
+}
+
+// delta = E^{-1} g for all columns: each workgroup takes four rows of E^{-1}, so every
+// row of g it reads serves four output rows; group h of 32 lanes sums c = h, h + 32, ...
+constexpr int kCoarseRows = 4;
+__global__ __launch_bounds__(1024) void k_bcoarse(int32_t k, int64_t ld, const double *__restrict__ einv,
+                                                  const double *__restrict__ gin, double *__restrict__ delta,
+                                                  const BatchState *st) {
+    __shared__ double lds[32][kCoarseRows][W + 1];
+    if (st && !st->any) return;
+    const int r0 = blockIdx.x * kCoarseRows;
     const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
-    const double *e = einv + (int64_t)row * ld;
-    double s = 0.0;
-    for (int c = g; c < k; c += 8) s = fma(e[c], gin[(int64_t)c * W + j], s);
-    const double t = group_sum_8(s, lds);
-    if (threadIdx.x < W) delta[(int64_t)row * W + threadIdx.x] = t;
+    double s[kCoarseRows];
+#pragma unroll
+    for (int q = 0; q < kCoarseRows; ++q) s[q] = 0.0;
+    for (int c = g; c < k; c += 32) {
+        const double gv = gin[(int64_t)c * W + j];
+#pragma unroll
+        for (int q = 0; q < kCoarseRows; ++q)
+            if (r0 + q < k) s[q] = fma(einv[(int64_t)(r0 + q) * ld + c], gv, s[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < kCoarseRows; ++q) lds[g][q][j] = s[q];
+    __syncthreads();
+    if (threadIdx.x < kCoarseRows * W) {
+        const int q = threadIdx.x / W, jj = threadIdx.x % W;
+        double t = 0.0;
+        for (int h = 0; h < 32; ++h) t += lds[h][q][jj];
+        if (r0 + q < k) delta[(int64_t)(r0 + q) * W + jj] = t;
+    }
 }
 
 // out = base + Z delta (base may be null); optional partials of rdot_j^T out_j;
@@ -291,29 +379,28 @@ __global__ __launch_bounds__(256) void k_bprolong(int64_t n, int32_t nwg, const 
     }
     if (rdot) {
         const double t = group_sum_8(acc, lds);
-        if (threadIdx.x < W) part[(int64_t)blockIdx.x * W + threadIdx.x] = t;
+        if (threadIdx.x < W) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;  // column-major
     }
     if (advance && blockIdx.x == 0 && threadIdx.x == 0) st->iter = st->iter + 1;
 }
 
 // rho_j = r_j^T z_j, beta_{i-1,j} = rho_{i,j} / rho_{i-1,j} for the running columns,
-// rho kept in two parity slots.
-__global__ __launch_bounds__(1024) void k_bbeta(const double *__restrict__ part, int nparts, BatchState *st) {
-    __shared__ double lds[32][W + 1];
+// rho kept in two parity slots; workgroup j reduces column j of the prolongation
+// partials.
+__global__ __launch_bounds__(256) void k_bbeta(const double *__restrict__ part, int nparts, BatchState *st) {
+    __shared__ double lds[4];
     if (!st->any) return;
-    const double rho = col_reduce_1024(part, nparts, lds);
-    if (threadIdx.x < W) {
-        const int j = threadIdx.x;
-        if (st->flag[j] == kRunning) {
-            const int it = st->iter;
-            if (it > 0 && !isfinite(rho)) {
-                st->flag[j] = kBreakdown;
-                st->bad[j] = it - 1;
-                st->iters_done[j] = it;
-            } else {
-                st->beta[j] = it > 0 ? rho / st->rho[(it + 1) & 1][j] : 0.0;
-                st->rho[it & 1][j] = rho;
-            }
+    const int j = blockIdx.x;
+    const double rho = col_sum_cm(part, nparts, j, lds);
+    if (threadIdx.x == 0 && st->flag[j] == kRunning) {
+        const int it = st->iter;
+        if (it > 0 && !isfinite(rho)) {
+            st->flag[j] = kBreakdown;
+            st->bad[j] = it - 1;
+            st->iters_done[j] = it;
+        } else {
+            st->beta[j] = it > 0 ? rho / st->rho[(it + 1) & 1][j] : 0.0;
+            st->rho[it & 1][j] = rho;
         }
     }
 }
@@ -448,14 +535,41 @@ int ensure_ws(dpcg_ctx *c) {
     BTRY(balloc(c, &b->p, nw));
     BTRY(balloc(c, &b->g, kw));
     BTRY(balloc(c, &b->delta, kw));
-    b->spmm_nwg = grid_rows(c->nb, 4 * kSpmmRowsPerWave, 1 << 30);
-    b->upd_nwg = grid_rows(c->bjb_ntiles, 1, 512);
-    b->vec_nwg = grid_rows(c->n, 64, 512);
+    b->spmm_nwg = grid_rows(c->nb, 4, 1 << 30);
+    b->upd_nwg = grid_rows(c->bjb_ntiles, 1, 2048);
+    b->vec_nwg = grid_rows(c->n, 32, 4096);
     const size_t np = (size_t)std::max({b->spmm_nwg, b->upd_nwg, b->vec_nwg}) * W;
     BTRY(balloc(c, &b->part, np));
     BTRY(balloc(c, &b->part2, np));
     BTRY(balloc(c, &b->st, 1));
     BHIP(hipHostMalloc((void **)&b->snap, sizeof(BatchState), hipHostMallocDefault));
+    // restriction segments from the column pointers of Z^T and (KZ)^T
+    std::vector<int32_t> zp(c->k + 1, 0), kp(c->k + 1, 0), seg, sptr(c->k + 1, 0);
+    if (c->k > 0) {
+        BHIP(hipMemcpyAsync(zp.data(), c->zt_ptr, sizeof(int32_t) * (c->k + 1), hipMemcpyDeviceToHost, c->stream));
+        BHIP(hipMemcpyAsync(kp.data(), c->kzt_ptr, sizeof(int32_t) * (c->k + 1), hipMemcpyDeviceToHost, c->stream));
+        BHIP(hipStreamSynchronize(c->stream));
+    }
+    for (int cc = 0; cc < c->k; ++cc) {
+        sptr[cc] = (int32_t)(seg.size() / 4);
+        for (int list = 0; list < 2; ++list) {
+            const int32_t e0 = list ? kp[cc] : zp[cc], e1 = list ? kp[cc + 1] : zp[cc + 1];
+            for (int32_t e = e0; e == e0 || e < e1; e += kBatchSegEntries) {
+                seg.push_back(cc);
+                seg.push_back(list);
+                seg.push_back(e);
+                seg.push_back(std::min(e1, e + kBatchSegEntries));
+            }
+        }
+    }
+    b->nseg = (int32_t)(seg.size() / 4);
+    sptr[c->k] = b->nseg;
+    BTRY(balloc(c, &b->seg, std::max<size_t>(4, seg.size())));
+    BTRY(balloc(c, &b->seg_ptr, (size_t)c->k + 1));
+    BTRY(balloc(c, &b->seg_part, (size_t)std::max(1, b->nseg) * W));
+    if (!seg.empty()) BHIP(hipMemcpyAsync(b->seg, seg.data(), sizeof(int32_t) * seg.size(), hipMemcpyHostToDevice, c->stream));
+    BHIP(hipMemcpyAsync(b->seg_ptr, sptr.data(), sizeof(int32_t) * sptr.size(), hipMemcpyHostToDevice, c->stream));
+    BHIP(hipStreamSynchronize(c->stream));
     return DPCG_OK;
 }
 
@@ -470,16 +584,21 @@ int read_bstate(dpcg_ctx *c, BatchState &out) {
 int enqueue_restrict(dpcg_ctx *c, const double *a, const double *bvec, BatchState *st, const double *part_rr, int n_rr,
                      int iter_offset, int max_iter) {
     BatchWorkspace *b = c->bws;
-    const int grid = c->k > 0 ? ((c->k + 7) & ~7) : 8;
-    BLAUNCH(k_brestrict, dim3(grid), dim3(256), 0, c->stream, c->k, c->zt_ptr, c->zt_idx, c->zt_val, c->kzt_ptr,
-            c->kzt_idx, c->kzt_val, a, bvec, b->g, st, part_rr, n_rr, iter_offset, max_iter);
+    const int grid = std::max(8, (b->nseg + 7) & ~7);
+    BLAUNCH(k_brestrict, dim3(grid), dim3(1024), 0, c->stream, (const int32_t *)b->seg, b->nseg, c->zt_idx,
+            (const double *)c->zt_val, c->kzt_idx, (const double *)c->kzt_val, a, bvec, b->seg_part, st, part_rr, n_rr,
+            iter_offset, max_iter);
+    if (c->k > 0)
+        BLAUNCH(k_bsegsum, dim3((c->k + 7) / 8), dim3(256), 0, c->stream, c->k, (const int32_t *)b->seg_ptr,
+                (const double *)b->seg_part, b->g, (const BatchState *)st);
     return DPCG_OK;
 }
 
 int enqueue_coarse(dpcg_ctx *c, const BatchState *st) {
     BatchWorkspace *b = c->bws;
     if (c->k == 0) return DPCG_OK;
-    BLAUNCH(k_bcoarse, dim3(c->k), dim3(256), 0, c->stream, c->k, c->einv_ld, c->einv, b->g, b->delta, st);
+    BLAUNCH(k_bcoarse, dim3((c->k + kCoarseRows - 1) / kCoarseRows), dim3(1024), 0, c->stream, c->k, c->einv_ld,
+            c->einv, b->g, b->delta, st);
     return DPCG_OK;
 }
 
@@ -507,7 +626,7 @@ int enqueue_bstart(dpcg_ctx *c, bool guess, int max_iter) {
     BTRY(enqueue_restrict(c, b->r, b->y, st, b->part2, b->spmm_nwg, 0, max_iter));
     BTRY(enqueue_coarse(c, st));
     BTRY(enqueue_prolong(c, b->y, b->z, b->r, st, 0));
-    BLAUNCH(k_bbeta, dim3(1), dim3(1024), 0, c->stream, (const double *)b->part, b->vec_nwg, st);
+    BLAUNCH(k_bbeta, dim3(W), dim3(256), 0, c->stream, (const double *)b->part, b->vec_nwg, st);
     BLAUNCH(k_bpupdate, dim3(std::min<int64_t>(8192, (c->n + 7) / 8)), dim3(256), 0, c->stream, c->n,
             (const double *)b->z, b->p, (const BatchState *)st);
     return DPCG_OK;
@@ -532,14 +651,14 @@ int enqueue_biteration(dpcg_ctx *c, int max_iter, std::vector<hipEvent_t> &ev, s
                           c->bcol, (const double *)c->bval, (const double *)b->p, (const double *)nullptr, b->q,
                           b->part, (const BatchState *)st);
     BHIP(hipGetLastError());
-    BLAUNCH(k_balpha, dim3(1), dim3(1024), 0, c->stream, (const double *)b->part, b->spmm_nwg, st);
+    BLAUNCH(k_balpha, dim3(W), dim3(256), 0, c->stream, (const double *)b->part, b->spmm_nwg, st);
     BLAUNCH(k_bupdate_bj, dim3(b->upd_nwg), dim3(256), 0, c->stream, c->bjb_ntiles, b->upd_nwg, c->bjb_start, b->u,
             b->r, b->y, (const double *)b->q, (const double *)b->p, (const double *)c->minv, c->bj_rowoff, c->bj_meta,
             b->part2, (const BatchState *)st, 1);
     BTRY(enqueue_restrict(c, b->r, b->y, st, b->part2, b->upd_nwg, 1, max_iter));
     BTRY(enqueue_coarse(c, st));
     BTRY(enqueue_prolong(c, b->y, b->z, b->r, st, 1));
-    BLAUNCH(k_bbeta, dim3(1), dim3(1024), 0, c->stream, (const double *)b->part, b->vec_nwg, st);
+    BLAUNCH(k_bbeta, dim3(W), dim3(256), 0, c->stream, (const double *)b->part, b->vec_nwg, st);
     BLAUNCH(k_bpupdate, dim3(std::min<int64_t>(8192, (c->n + 7) / 8)), dim3(256), 0, c->stream, c->n,
             (const double *)b->z, b->p, (const BatchState *)st);
     return DPCG_OK;

@@ -28,6 +28,7 @@ constexpr int kThreads = 256;     // threads per workgroup everywhere
 constexpr int kMaxBlock = 18;     // largest block-Jacobi block
 constexpr int kMaxElemDofs = 256; // largest element (DoFs) of dpcg_element_gradient
 constexpr int kBatchCols = 32;    // columns of the multi-RHS workspace (right-hand sides per batch)
+constexpr int kBatchSegEntries = 2048;  // entries per multi-RHS restriction segment
 constexpr int kBatchTileWindow = 47;                         // block starts per multi-RHS tile
 constexpr int kBatchTileDofs = kBatchTileWindow + kMaxBlock - 1;  // <= 64 DoFs per tile
 
@@ -100,6 +101,12 @@ struct BatchWorkspace {
     BatchState *st = nullptr;                     // device
     BatchState *snap = nullptr;                   // pinned host mirror
     int32_t spmm_nwg = 0, upd_nwg = 0, vec_nwg = 0;
+    // restriction segments: seg[4 s .. 4 s + 3] = (column, list 0 = Z^T / 1 = (KZ)^T, begin,
+    // end), at most kBatchSegEntries entries each; column c owns segments
+    // seg_ptr[c] .. seg_ptr[c + 1] - 1, whose partial sums are added in that order
+    int32_t *seg = nullptr, *seg_ptr = nullptr;
+    double *seg_part = nullptr;
+    int32_t nseg = 0;
 };
 
 struct SpmvPlan {
