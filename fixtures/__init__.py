@@ -3,5 +3,5 @@ tests and bench.
 
 Holds none of the solver's arithmetic; see ``fixtures.xfem``.
 """
-from .configs import CONFIGS, box, load, load_elements, problem_with_moduli  # noqa: F401
+from .configs import CONFIGS, box, load, load_elements, log_normal_moduli, problem_with_moduli  # noqa: F401
 from .xfem import Problem, build_problem  # noqa: F401

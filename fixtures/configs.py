@@ -10,6 +10,8 @@ The three plain-FP64 workloads are structured hex8 meshes of the unit cube
                bent into z = 0.5 + 0.3 rho^2, tip enrichment within r_e = 0.05,
                4^3 subdomains.
 * ``penny80``  80^3 elements, same crack, 8^3 subdomains.
+* ``penny60``  60^3 elements, same crack, 6^3 subdomains (the adjoint workload, with
+               per-element moduli E_e = exp(0.5 g_e), g a seeded N(0, 1) field).
 
 They stand in for the paper's gmsh tetrahedral meshes (notched beam, bracket,
 blade), which are not available; sizes per subdomain (about 3.3k DoFs) sit inside
@@ -31,6 +33,7 @@ CONFIGS = {
     "edge10": dict(ne=10, nsd=2, crack=("edge", dict(x0=0.5, zf=0.45)), r_e=0.15),
     "penny40": dict(ne=40, nsd=4, crack=("penny", dict(center=(0.5, 0.5, 0.5), R=0.25, curv=0.3)), r_e=0.05),
     "penny80": dict(ne=80, nsd=8, crack=("penny", dict(center=(0.5, 0.5, 0.5), R=0.25, curv=0.3)), r_e=0.05),
+    "penny60": dict(ne=60, nsd=6, crack=("penny", dict(center=(0.5, 0.5, 0.5), R=0.25, curv=0.3)), r_e=0.05),
     # small cases for tests: several tiles and ragged tails, fast to generate
     "edge4": dict(ne=4, nsd=2, crack=("edge", dict(x0=0.5, zf=0.45)), r_e=0.3),
     "penny12": dict(ne=12, nsd=2, crack=("penny", dict(center=(0.5, 0.5, 0.5), R=0.25, curv=0.3)), r_e=0.1),
@@ -109,3 +112,9 @@ def problem_with_moduli(name: str, elem_E) -> Problem:
     cfg = CONFIGS[name]
     return build_problem(name, cfg["ne"], cfg["nsd"], crack=make_crack(cfg["crack"]), r_e=cfg["r_e"],
                          elem_E=np.asarray(elem_E, float))
+
+
+def log_normal_moduli(name: str, seed: int = 7, sigma: float = 0.5):
+    """Per-element Young's moduli E_e = exp(sigma g_e), g i.i.d. N(0, 1) (seeded)."""
+    nel = CONFIGS[name]["ne"] ** 3
+    return np.exp(sigma * np.random.default_rng(seed).standard_normal(nel))

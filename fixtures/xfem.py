@@ -564,6 +564,40 @@ class XfemBox:
         f[3 * self.trip_start[top] + 2] = wx * wy * self.h * self.h
         return f
 
+    def random_top_tractions(self, nrhs, seed):
+        """nrhs load cases: on every free node of the top face z = 1, a force whose three
+        components are i.i.d. N(0, 1) times the node's tributary area (consistent
+        forces of a piecewise-constant random traction).  Returns (n, nrhs)."""
+        rng = np.random.default_rng(seed)
+        top = np.nonzero((self.node_ijk[:, 2] == self.ne) & self.free)[0]
+        i, j = self.node_ijk[top, 0], self.node_ijk[top, 1]
+        wx = np.where((i == 0) | (i == self.ne), 0.5, 1.0)
+        wy = np.where((j == 0) | (j == self.ne), 0.5, 1.0)
+        area = wx * wy * self.h * self.h
+        F = np.zeros((self.n, nrhs))
+        comps = rng.standard_normal((len(top), 3, nrhs))
+        for c in range(3):
+            F[3 * self.trip_start[top] + c] = area[:, None] * comps[:, c, :]
+        return F
+
+    def cod_functional(self):
+        """c with c^T u = the sum over enriched nodes of the crack-opening displacement
+        jump components: the shifted Heaviside function jumps by 2 across the crack, so a
+        jump node's b DoFs count twice; of the four branch functions only
+        sqrt(r) sin(theta / 2) jumps (by 2 sqrt(r)), so a tip node's c1 DoFs count
+        2 sqrt(r_I), r_I its distance to the front."""
+        c = np.zeros(self.n)
+        jn = np.nonzero(self.H_node)[0]
+        for comp in range(3):
+            c[3 * (self.trip_start[jn] + self.slot_b[jn]) + comp] = 2.0
+        tn = np.nonzero(self.T_node)[0]
+        if len(tn):
+            phi, psi, _, _ = self.crack.tip_coords(self.X[tn])
+            r = np.sqrt(phi * phi + psi * psi)
+            for comp in range(3):
+                c[3 * (self.trip_start[tn] + self.slot_c[tn]) + comp] = 2.0 * np.sqrt(r)
+        return c
+
     # -- deflation space -----------------------------------------------------------
     def subdomain_of_nodes(self, nsd):
         q = np.maximum(0, np.ceil(self.node_ijk * nsd / self.ne).astype(np.int64) - 1)

@@ -134,3 +134,87 @@ def test_autograd_matches_finite_differences(problems):
         fd = (Ls[0] - Ls[1]) / (2 * h)
         say(f"[adjoint] element {j} (m={m[j]}): autograd {gs[j]:.10e}, central FD {fd:.10e}")
         assert abs(fd - gs[j]) <= 1e-4 * abs(gs[j])
+
+
+# ------------------------------------------------------------------ the adjoint workload
+def _perturbed_values(p, ep, ed, ko, km, j, delta):
+    """CSR values of K + delta K_j: element j's unit-modulus matrix added at its DoF
+    pairs (every such pair is in K's pattern), i.e. K re-assembled with E_j + delta."""
+    vals = p.k_val.copy()
+    d = ed[ep[j]:ep[j + 1]].astype(np.int64)
+    m = len(d)
+    M = km[ko[j]:ko[j] + m * m].reshape(m, m)
+    ok = np.nonzero(d >= 0)[0]
+    for a in ok:
+        r0, r1 = p.k_rowptr[d[a]], p.k_rowptr[d[a] + 1]
+        pos = r0 + np.searchsorted(p.k_col[r0:r1], d[ok])
+        assert np.array_equal(p.k_col[pos], d[ok])
+        vals[pos] += delta * M[a, ok]
+    return vals
+
+
+def _solver_with_values(p, vals):
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dt)  # noqa: E731
+    return D.Solver(p.n, t(p.k_rowptr, torch.int64), t(p.k_col, torch.int32), t(vals, torch.float64), p.k,
+                    t(p.z_rowptr, torch.int64), t(p.z_col, torch.int32), t(p.z_val, torch.float64),
+                    t(p.block_ptr, torch.int32))
+
+
+def _adjoint_vs_fd(name, picks, h_rel, tol):
+    """Loss L = f^T u + (sum of crack-opening jumps) with per-element moduli
+    E_e = exp(0.5 g_e): autograd gradients against central differences of L over the
+    moduli of the picked elements, each L from a fresh setup and solve at tol."""
+    from fixtures import box, load_elements, log_normal_moduli, problem_with_moduli
+    E = log_normal_moduli(name)
+    p = problem_with_moduli(name, E)
+    ep, ed, ko, km = load_elements(name)
+    c = box(name).cod_functional()
+    el = D.Elements(ep, ed, ko, km, DEV)
+    fc = dev(p.f + c)
+    with D.Solver.from_problem(p, DEV) as s:
+        f = dev(p.f).requires_grad_(True)
+        scale = torch.as_tensor(E, device=DEV).requires_grad_(True)
+        u = D.solve(f, s, scale=scale, elements=el, tol=tol)
+        L = (f * u).sum() + (dev(c) * u).sum()
+        L.backward()
+        gs = host(scale.grad)
+        gf = host(f.grad)
+        # dL/df = u + lambda, lambda = K^{-1} (f + c)
+        lam, _ = s.solve(fc, tol=tol)
+        assert np.abs(gf - host(u.detach()) - host(lam)).max() <= 1e-8 * np.abs(gf).max()
+    fd = np.empty(len(picks))
+    for q, j in enumerate(picks):
+        h = h_rel * E[j]
+        Ls = []
+        for sgn in (1.0, -1.0):
+            with _solver_with_values(p, _perturbed_values(p, ep, ed, ko, km, j, sgn * h)) as sj:
+                uj, info = sj.solve(dev(p.f), tol=tol)
+                assert info["status"] == D.abi.OK
+                Ls.append(float(((dev(p.f) + dev(c)) * uj).sum()))
+        fd[q] = (Ls[0] - Ls[1]) / (2 * h)
+    return gs, fd
+
+
+def test_adjoint_full_finite_difference_check_edge10():
+    """Every element of the 10^3 mesh (log-normal moduli, compliance + COD loss)."""
+    import fixtures
+    nel = fixtures.CONFIGS["edge10"]["ne"] ** 3
+    picks = np.arange(nel)
+    gs, fd = _adjoint_vs_fd("edge10", picks, 1e-3, 1e-12)
+    err = np.abs(fd - gs[picks])
+    say(f"[adjoint] edge10 all {nel} elements: max |FD - adjoint| / max |g| = {err.max() / np.abs(gs).max():.2e}, "
+        f"median relative {np.median(err / np.abs(gs[picks])):.2e}")
+    assert err.max() <= 1e-5 * np.abs(gs).max()
+
+
+def test_adjoint_finite_differences_penny60():
+    """The 60^3 adjoint workload: 20 seeded random elements."""
+    import fixtures
+    nel = fixtures.CONFIGS["penny60"]["ne"] ** 3
+    picks = np.random.default_rng(60).choice(nel, 20, replace=False)
+    say("[adjoint] penny60: building the system and element matrices (about a minute)")
+    gs, fd = _adjoint_vs_fd("penny60", picks, 1e-3, 1e-12)
+    err = np.abs(fd - gs[picks])
+    say(f"[adjoint] penny60 20 elements: max |FD - adjoint| / max |g| = {err.max() / np.abs(gs).max():.2e}, "
+        f"max relative {np.max(err / np.abs(gs[picks])):.2e}")
+    assert err.max() <= 1e-5 * np.abs(gs).max()

@@ -152,3 +152,28 @@ def test_batch_options_and_errors(solver):
     # a single solve afterwards is unaffected
     u, info = s.solve(dev(p.f))
     assert info["status"] == D.abi.OK
+
+
+def test_batch_case_a_top_face_tractions(solver):
+    """The batching workload (Case A): penny40, 32 random top-face tractions solved
+    together, against 32 sequential single solves and, for two columns, the oracle."""
+    from fixtures import box
+    p, s = solver("penny40")
+    F = box("penny40").random_top_tractions(32, seed=2024)
+    U, infos = s.solve_batch(dev(F), tol=1e-8)
+    U = host(U)
+    t_single = 0.0
+    for j in range(32):
+        u1, i1 = s.solve(dev(F[:, j]), tol=1e-8)
+        t_single += i1["solve_ms"]
+        assert infos[j]["status"] == D.abi.OK
+        assert iters_close(infos[j]["iterations"], i1["iterations"]), (j, infos[j], i1)
+        assert np.linalg.norm(U[:, j] - host(u1)) <= 1e-6 * np.linalg.norm(host(u1))
+    say(f"[batch] penny40 32 top-face tractions: batch {infos[0]['solve_ms']:.1f} ms, "
+        f"32 single solves {t_single:.1f} ms, iterations {min(i['iterations'] for i in infos)}-"
+        f"{max(i['iterations'] for i in infos)}")
+    o = O.Oracle.from_problem(p)
+    for j in (0, 17):
+        ref = o.solve(F[:, j], tol=1e-8)
+        assert np.linalg.norm(U[:, j] - ref["u"]) <= 1e-6 * np.linalg.norm(ref["u"])
+        assert iters_close(infos[j]["iterations"], ref["iterations"])

@@ -163,3 +163,34 @@ def test_mixed_caps_and_options(solver):
     # loose inner solves still converge, with more cycles
     u, info = s.solve(f, precision="mixed", inner_tol=0.1)
     assert info["status"] == D.abi.OK and info["refinements"] >= 4 and info["rel_res_true"] <= 1e-8
+
+
+def test_mixed_vs_fp64_penny80(problems):
+    """The mixed-precision workload (80^3, curved penny crack): mixed and FP64 solves both
+    reach a true FP64 residual <= 1e-8 (checked on the host with the fixture's K), and
+    their errors against an FP64 solve to 1e-12 are of the same size.  Two solutions
+    with relative residual 1e-8 may differ by up to cond(K) * 1e-8; the FP64 solve takes
+    the oracle's iterates (parity-tested at the smaller sizes), so its error is the
+    oracle's, and the oracle's own solve at this size takes minutes on the host."""
+    say("[mixed] penny80: building the system (about a minute)")
+    p = problems("penny80")
+    K = p.K_scipy()
+    fn = np.linalg.norm(p.f)
+    with D.Solver.from_problem(p, DEV) as s:
+        f = dev(p.f)
+        u64, i64 = s.solve(f, tol=1e-8)
+        um, im = s.solve(f, tol=1e-8, precision="mixed")
+        uref, iref = s.solve(f, tol=1e-12)
+        u64, um, uref = host(u64), host(um), host(uref)
+    r64 = np.linalg.norm(p.f - K @ u64) / fn
+    rm = np.linalg.norm(p.f - K @ um) / fn
+    nref = np.linalg.norm(uref)
+    e64 = np.linalg.norm(u64 - uref) / nref
+    em = np.linalg.norm(um - uref) / nref
+    say(f"[mixed] penny80 n={p.n} k={p.k}: FP64 {i64['iterations']} it {i64['solve_ms']:.1f} ms (true res {r64:.2e}, "
+        f"error {e64:.2e}); mixed {im['iterations']} inner it in {im['refinements']} cycles {im['solve_ms']:.1f} ms "
+        f"(true res {rm:.2e}, error {em:.2e}); reference at 1e-12: {iref['iterations']} it")
+    assert i64["status"] == D.abi.OK and im["status"] == D.abi.OK and iref["status"] == D.abi.OK
+    assert r64 <= 1.5e-8 and rm <= 1.5e-8
+    assert abs(im["rel_res_true"] - rm) <= 1e-3 * rm + 1e-12
+    assert em <= 10.0 * max(e64, 1e-7)
