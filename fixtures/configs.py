@@ -118,3 +118,18 @@ def log_normal_moduli(name: str, seed: int = 7, sigma: float = 0.5):
     """Per-element Young's moduli E_e = exp(sigma g_e), g i.i.d. N(0, 1) (seeded)."""
     nel = CONFIGS[name]["ne"] ** 3
     return np.exp(sigma * np.random.default_rng(seed).standard_normal(nel))
+
+
+def uneven_systems(count: int = 16, seed: int = 16, ne_range=(20, 48), r_e: float = 0.05):
+    """Independent systems of the multi-system workload: meshes of ne^3 elements with ne
+    uniform in ne_range, each with a curved penny crack (radius 0.25, curvature 0.3)
+    whose centre is uniform in [0.3, 0.7]^3, 1 + ne // 12 subdomains per axis.
+    Returns a list of Problems (not cached)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        ne = int(rng.integers(ne_range[0], ne_range[1] + 1))
+        centre = tuple(float(v) for v in rng.uniform(0.3, 0.7, 3))
+        crack = CurvedPennyCrack(center=centre, R=0.25, curv=0.3)
+        out.append(build_problem(f"uneven{i}", ne, 1 + ne // 12, crack=crack, r_e=r_e))
+    return out

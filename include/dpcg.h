@@ -175,6 +175,28 @@ int dpcg_solve_adjoint(dpcg_handle h, const double *g, double *lambda, double to
 int dpcg_solve_batch(dpcg_handle h, int32_t nrhs, const double *F, double *U, double tol,
                      const dpcg_options *opt, dpcg_info *infos);
 
+/*
+ * Solves count independent systems at once (1 <= count <= 64; an extension beyond the
+ * paper): handles[i] (distinct handles, each from its own dpcg_setup, any sizes, same
+ * device) solves K_i U[i] = F[i] (device arrays of its n_i) with the method of
+ * dpcg_solve and its own stopping test.  Each phase of an iteration runs as one kernel
+ * launch over the workgroups of every system still iterating, so small systems share
+ * the launches instead of queueing 7 of them per iteration each.  Handles that were
+ * never tuned get their SpMV lane-group size from dpcg_autotune first.  All work of the
+ * call runs on handles[0]'s stream (the others are synchronised first).
+ * infos[count] (host, may be NULL).  Returns DPCG_OK when every system converged, else
+ * DPCG_EBREAKDOWN if one broke down, else DPCG_NOT_CONVERGED; DPCG_EINVAL (count, a
+ * repeated handle, tol, max_iter, record_history or a precision other than FP64),
+ * DPCG_ENONFINITE, DPCG_EHIP.
+ */
+int dpcg_solve_many(dpcg_handle *handles, int32_t count, const double *const *F, double *const *U,
+                    double tol, const dpcg_options *opt, dpcg_info *infos);
+
+/* Times the SpMV kernel for each lane-group size (4, 8, 16, 32 lanes per block row;
+ * reps launches each, HIP events) and keeps the fastest for every later solve of the
+ * handle.  Returns the chosen size, or a negative status. */
+int dpcg_autotune(dpcg_handle h, int32_t reps);
+
 /* Releases every resource of the handle (NULL is a no-op). */
 void dpcg_destroy(dpcg_handle h);
 

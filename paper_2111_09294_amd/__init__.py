@@ -7,10 +7,10 @@ binding: ``Solver`` marshals device tensors to the library, which does all of th
 arithmetic.
 """
 from ._binding import (DpcgError, Elements, Info, Options, Solver, Stats, lib,  # noqa: F401
-                       status_string)
+                       solve_many, status_string)
 from . import _binding as abi  # noqa: F401
 
-__all__ = ["Solver", "Elements", "DpcgError", "lib", "status_string", "abi", "solve"]
+__all__ = ["Solver", "Elements", "DpcgError", "lib", "status_string", "abi", "solve", "solve_many"]
 
 
 def solve(f, solver, scale=None, elements=None, tol=1e-8, **opts):

@@ -61,6 +61,8 @@ SIGNATURES = {
     "dpcg_solve": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
     "dpcg_solve_adjoint": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
     "dpcg_solve_batch": (C.c_int, [P, C.c_int32, P, P, C.c_double, C.POINTER(Options), P]),
+    "dpcg_solve_many": (C.c_int, [P, C.c_int32, P, P, C.c_double, C.POINTER(Options), P]),
+    "dpcg_autotune": (C.c_int, [P, C.c_int32]),
     "dpcg_destroy": (None, [P]),
     "dpcg_release_cached_memory": (None, []),
     "dpcg_status_string": (C.c_char_p, [C.c_int]),
@@ -329,6 +331,13 @@ class Solver:
             raise DpcgError(st, "dpcg_element_gradient")
         return g
 
+    def autotune(self, reps=5):
+        """Measures the SpMV lane-group sizes and keeps the fastest; returns it."""
+        g = lib().dpcg_autotune(self.handle, int(reps))
+        if g < 0:
+            raise DpcgError(g, "dpcg_autotune")
+        return g
+
     def spmv_fp32(self, x, y=None):
         """y = K32 x: K's values rounded to binary32, FP64 arithmetic."""
         import torch
@@ -374,6 +383,35 @@ class Solver:
         z = torch.empty_like(r)
         self._call("dpcg_precond", r, z)
         return z
+
+
+def solve_many(solvers, fs, us=None, tol=1e-8, max_iter=None, check_every=None, initial_guesses=None,
+               raise_on_error=True):
+    """Independent systems solved together (one launch per iteration phase for all):
+    solvers[i] solves K_i u_i = fs[i].  Returns (list of u, list of info dicts)."""
+    import torch
+    m = len(solvers)
+    if m != len(fs) or m == 0:
+        raise ValueError("one right-hand side per solver")
+    if us is None:
+        us = [torch.empty_like(f) for f in fs]
+    for s, f, u in zip(solvers, fs, us):
+        _check_dev(f, torch.float64, "rhs", s.n)
+        _check_dev(u, torch.float64, "solution", s.n)
+    if initial_guesses is not None:
+        for u, g in zip(us, initial_guesses):
+            if g.data_ptr() != u.data_ptr():
+                u.copy_(g)
+    o = solvers[0]._opts(max_iter, check_every, initial_guesses is not None, False)
+    hs = (C.c_void_p * m)(*[s.handle.value for s in solvers])
+    fp = (C.c_void_p * m)(*[f.data_ptr() for f in fs])
+    up = (C.c_void_p * m)(*[u.data_ptr() for u in us])
+    infos = (Info * m)()
+    st = lib().dpcg_solve_many(C.cast(hs, C.c_void_p), m, C.cast(fp, C.c_void_p), C.cast(up, C.c_void_p),
+                               float(tol), C.byref(o), C.cast(infos, C.c_void_p))
+    if st < 0 and raise_on_error:
+        raise DpcgError(st, "dpcg_solve_many", infos[0])
+    return us, [infos[i].as_dict() for i in range(m)]
 
 
 class Elements:

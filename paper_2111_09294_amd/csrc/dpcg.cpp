@@ -100,7 +100,10 @@ int alloc_workspace(dpcg_ctx *c, Workspace &w) {
     TRY(alloc(c, &w.tmp, n));
     TRY(alloc(c, &w.g, (size_t)std::max(1, c->k)));
     TRY(alloc(c, &w.delta, (size_t)std::max(1, c->k)));
-    const size_t np = (size_t)std::max({c->spmv.nwg, c->bj_nwg, c->vec_nwg, 1});
+    // partial sums for the largest SpMV grid any lane-group size can choose (autotuner)
+    const int spmv_max = std::min<int>(16384, (int)((c->nb + 7) / 8) + 8);
+    const size_t np = (size_t)std::max({spmv_max, c->spmv.nwg, c->bj_nwg, c->vec_nwg, 1});
+    c->part_cap = (int32_t)np;
     TRY(alloc(c, &w.part_a, np));
     TRY(alloc(c, &w.part_b, np));
     TRY(alloc(c, &w.part_c, np));
@@ -115,10 +118,18 @@ int round_grid(int want) {
     return std::max(1, want);
 }
 
+void set_spmv_group(dpcg_ctx *c, int g) {
+    c->spmv.group = g;
+    const int rows_per_step = 4 * 64 / g;  // 4 waves per SpMV workgroup
+    c->spmv.steps = (int)((c->nb + rows_per_step - 1) / rows_per_step);
+    c->spmv.nwg = std::min(c->spmv.steps, 16384);
+    if (c->spmv.nwg >= 8) c->spmv.nwg = (c->spmv.nwg + 7) & ~7;
+}
+
 void choose_shapes(dpcg_ctx *c) {
     const double avg = c->nb ? (double)c->nnzb / c->nb : 1.0;
     // lanes per block row: one pass over a typical row (measured on gfx950: 32 lanes for
-    // rows of ~30 blocks beat 16 lanes with two passes)
+    // rows of ~30 blocks beat 16 lanes with two passes); dpcg_autotune measures instead
     int g = 32;
     if (avg <= 6) g = 4;
     else if (avg <= 12) g = 8;
@@ -420,6 +431,248 @@ int solve_impl(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol
     return status;
 }
 
+// ---------------------------------------------------------------- several systems
+// Measures the SpMV for each lane-group size whose grid fits the workspace and keeps the
+// fastest; returns the chosen size.
+int autotune_spmv(dpcg_ctx *c, int reps) {
+    Workspace &w = c->ws[0];
+    const int cand[4] = {4, 8, 16, 32};
+    hipEvent_t e0, e1;
+    HIP_TRY(take_event(&e0));
+    HIP_TRY(take_event(&e1));
+    std::vector<hipEvent_t> evs{e0, e1};
+    const SpmvPlan keep = c->spmv;
+    int best = keep.group;
+    float best_ms = 1e30f;
+    c->inner32 = false;
+    HIP_TRY(hipMemsetAsync(w.p[0], 0, sizeof(double) * c->n, c->stream));
+    for (int g : cand) {
+        set_spmv_group(c, g);
+        if (c->spmv.nwg > c->part_cap) continue;
+        LAUNCH(launch_spmv_plain(c, w.p[0], w.q));  // warm-up
+        HIP_TRY(hipEventRecord(e0, c->stream));
+        for (int i = 0; i < reps; ++i) LAUNCH(launch_spmv_plain(c, w.p[0], w.q));
+        HIP_TRY(hipEventRecord(e1, c->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = g;
+        }
+    }
+    give_events(evs);
+    set_spmv_group(c, best);
+    if (c->spmv.nwg > c->part_cap) c->spmv = keep;
+    c->tuned = true;
+    return c->spmv.group;
+}
+
+int round8(int v) { return v >= 8 ? (v + 7) & ~7 : v; }
+
+int solve_many_impl(dpcg_handle *hs, int32_t count, const double *const *F, double *const *U, double tol,
+                    const dpcg_options *opt_in, dpcg_info *infos) {
+    const double t0 = now_ms();
+    dpcg_options opt;
+    dpcg_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (!hs || count < 1 || count > kMaxSystems || !F || !U || !(tol > 0.0) || opt.max_iter < 0) return DPCG_EINVAL;
+    if (opt.precision != DPCG_PREC_FP64 || opt.record_history) return DPCG_EINVAL;
+    if (opt.check_every <= 0) opt.check_every = 16;
+    const bool guess = opt.use_initial_guess != 0;
+    for (int i = 0; i < count; ++i) {
+        if (!hs[i] || !F[i] || !U[i] || hs[i]->device != hs[0]->device) return DPCG_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return DPCG_EINVAL;  // one workspace per system
+    }
+    // all work of the call goes to the first handle's stream
+    hipStream_t S = hs[0]->stream;
+    std::vector<hipStream_t> own(count);
+    for (int i = 0; i < count; ++i) {
+        HIP_TRY(hipStreamSynchronize(hs[i]->stream));
+        own[i] = hs[i]->stream;
+        hs[i]->stream = S;
+        hs[i]->inner32 = false;
+    }
+    struct Restore {
+        dpcg_handle *hs;
+        std::vector<hipStream_t> &own;
+        ~Restore() {
+            for (size_t i = 0; i < own.size(); ++i) hs[i]->stream = own[i];
+        }
+    } restore{hs, own};
+    for (int i = 0; i < count; ++i)
+        if (!hs[i]->tuned) autotune_spmv(hs[i], 5);
+    // norms and finiteness of every right-hand side (and guess)
+    std::vector<double> fnorm(count);
+    for (int i = 0; i < count; ++i) {
+        LAUNCH(launch_check_finite_norm(hs[i], F[i], guess ? U[i] : nullptr, hs[i]->ws[0]));
+    }
+    HIP_TRY(hipStreamSynchronize(S));
+    std::vector<State> st(count);
+    for (int i = 0; i < count; ++i) {
+        HIP_TRY(hipMemcpyAsync(hs[i]->ws[0].snap, hs[i]->ws[0].st, sizeof(State), hipMemcpyDeviceToHost, S));
+    }
+    HIP_TRY(hipStreamSynchronize(S));
+    for (int i = 0; i < count; ++i) {
+        const State &s0 = *hs[i]->ws[0].snap;
+        if (s0.nonfinite) return DPCG_ENONFINITE;
+        fnorm[i] = std::sqrt(s0.aux);
+    }
+    // states: zero right-hand sides are done (u = 0) before the first iteration
+    for (int i = 0; i < count; ++i) {
+        State init{};
+        init.flag = fnorm[i] > 0.0 ? kRunning : kConverged;
+        init.thr = tol * fnorm[i];
+        *hs[i]->ws[0].snap = init;
+        HIP_TRY(hipMemcpyAsync(hs[i]->ws[0].st, hs[i]->ws[0].snap, sizeof(State), hipMemcpyHostToDevice, S));
+        if (fnorm[i] == 0.0) HIP_TRY(hipMemsetAsync(U[i], 0, sizeof(double) * hs[i]->n, S));
+    }
+    HIP_TRY(hipStreamSynchronize(S));
+    // descriptors and phase offsets
+    std::vector<MsSys> sys(count);
+    MsTable tab{};
+    tab.nsys = count;
+    int tot[kMsPhases] = {0, 0, 0, 0, 0, 0};
+    for (int i = 0; i < count; ++i) {
+        dpcg_ctx *c = hs[i];
+        Workspace &w = c->ws[0];
+        MsSys &d = sys[i];
+        d.nb = c->nb;
+        d.steps = c->spmv.steps;
+        d.spmv_nwg = c->spmv.nwg;
+        d.group = c->spmv.group;
+        d.k = c->k;
+        d.bj_ntiles = c->bj_ntiles;
+        d.bj_nwg = c->bj_nwg;
+        d.vec_nwg = c->vec_nwg;
+        d.guess = guess ? 1 : 0;
+        d.pad = 0;
+        d.n = c->n;
+        d.nnzb = c->nnzb;
+        d.einv_ld = c->einv_ld;
+        d.brow_ptr = c->brow_ptr;
+        d.bcol = c->bcol;
+        d.bval = c->bval;
+        d.minv = c->minv;
+        d.bj_rowoff = c->bj_rowoff;
+        d.bj_meta = c->bj_meta;
+        d.bj_wg_start = c->bj_wg_start;
+        d.zt_ptr = c->zt_ptr;
+        d.zt_idx = c->zt_idx;
+        d.zt_val = c->zt_val;
+        d.kzt_ptr = c->kzt_ptr;
+        d.kzt_idx = c->kzt_idx;
+        d.kzt_val = c->kzt_val;
+        d.einv = c->einv;
+        d.z_ptr = c->z_ptr;
+        d.z_col = c->z_col;
+        d.z_val = c->z_val;
+        d.f = F[i];
+        d.u = U[i];
+        d.r = w.r;
+        d.y = w.y;
+        d.z = w.z;
+        d.q = w.q;
+        d.p0 = w.p[0];
+        d.p1 = w.p[1];
+        d.g = w.g;
+        d.delta = w.delta;
+        d.part_a = w.part_a;
+        d.part_b = w.part_b;
+        d.part_c = w.part_c;
+        d.st = w.st;
+        const int n_ph[kMsPhases] = {round8(c->spmv.nwg), 1, round8(c->bj_nwg), std::max(1, c->k), c->k,
+                                     round8(c->vec_nwg)};
+        for (int ph = 0; ph < kMsPhases; ++ph) {
+            tab.off[ph][i] = tot[ph];
+            tot[ph] += n_ph[ph];
+        }
+    }
+    for (int ph = 0; ph < kMsPhases; ++ph) tab.off[ph][count] = tot[ph];
+    void *dtab = nullptr, *dsys = nullptr;
+    HIP_TRY(dev_alloc(&dtab, sizeof(MsTable)));
+    if (dev_alloc(&dsys, sizeof(MsSys) * count) != hipSuccess) {
+        dev_release(dtab);
+        return DPCG_EHIP;
+    }
+    struct Release {
+        void *a, *b;
+        hipStream_t s;
+        ~Release() {
+            (void)hipStreamSynchronize(s);
+            dev_release(a);
+            dev_release(b);
+        }
+    } rel{dtab, dsys, S};
+    HIP_TRY(hipMemcpyAsync(dtab, &tab, sizeof(MsTable), hipMemcpyHostToDevice, S));
+    HIP_TRY(hipMemcpyAsync(dsys, sys.data(), sizeof(MsSys) * count, hipMemcpyHostToDevice, S));
+    const MsTable *T = (const MsTable *)dtab;
+    const MsSys *Y = (const MsSys *)dsys;
+    const int max_iter = opt.max_iter;
+    // Algorithm 2 and the first preconditioned residual, every system at once
+    LAUNCH(launch_ms_restrict(S, T, Y, tot[kMsRestrict], 0, 0, 0, 0));
+    LAUNCH(launch_ms_coarse(S, T, Y, tot[kMsCoarse], 0));
+    LAUNCH(launch_ms_prolong(S, T, Y, tot[kMsVec], 0, 0));
+    LAUNCH(launch_ms_spmv_res(S, T, Y, tot[kMsSpmv]));
+    LAUNCH(launch_ms_bj(S, T, Y, tot[kMsBj]));
+    LAUNCH(launch_ms_restrict(S, T, Y, tot[kMsRestrict], 1, 1, 0, max_iter));
+    LAUNCH(launch_ms_coarse(S, T, Y, tot[kMsCoarse], 1));
+    LAUNCH(launch_ms_prolong(S, T, Y, tot[kMsVec], 1, 0));
+    LAUNCH(launch_ms_beta(S, T, Y, tot[kMsVec]));
+    auto read_all = [&]() -> int {
+        for (int i = 0; i < count; ++i)
+            HIP_TRY(hipMemcpyAsync(hs[i]->ws[0].snap, hs[i]->ws[0].st, sizeof(State), hipMemcpyDeviceToHost, S));
+        HIP_TRY(hipStreamSynchronize(S));
+        for (int i = 0; i < count; ++i) st[i] = *hs[i]->ws[0].snap;
+        return DPCG_OK;
+    };
+    TRY(read_all());
+    int32_t enq = 0;
+    auto any_running = [&]() {
+        for (int i = 0; i < count; ++i)
+            if (st[i].flag == kRunning) return true;
+        return false;
+    };
+    while (any_running() && enq < max_iter) {
+        const int m = std::min(opt.check_every, max_iter - enq);
+        for (int it = 0; it < m; ++it) {
+            LAUNCH(launch_ms_spmv_p(S, T, Y, tot[kMsSpmv]));
+            LAUNCH(launch_ms_alpha(S, Y, count));
+            LAUNCH(launch_ms_update_bj(S, T, Y, tot[kMsBj]));
+            LAUNCH(launch_ms_restrict(S, T, Y, tot[kMsRestrict], 1, 1, 1, max_iter));
+            LAUNCH(launch_ms_coarse(S, T, Y, tot[kMsCoarse], 1));
+            LAUNCH(launch_ms_prolong(S, T, Y, tot[kMsVec], 1, 1));
+            LAUNCH(launch_ms_beta(S, T, Y, tot[kMsVec]));
+        }
+        enq += m;
+        TRY(read_all());
+    }
+    int worst = DPCG_OK;
+    const double ms = now_ms() - t0;
+    for (int i = 0; i < count; ++i) {
+        dpcg_ctx *c = hs[i];
+        int status;
+        int64_t bad = -1;
+        switch (st[i].flag) {
+            case kConverged: status = DPCG_OK; break;
+            case kBreakdown: status = DPCG_EBREAKDOWN; bad = st[i].bad; break;
+            default: status = DPCG_NOT_CONVERGED; break;
+        }
+        if (st[i].flag == kRunning) st[i].iters_done = enq;
+        if (status == DPCG_EBREAKDOWN) worst = DPCG_EBREAKDOWN;
+        else if (status == DPCG_NOT_CONVERGED && worst == DPCG_OK) worst = DPCG_NOT_CONVERGED;
+        double rt = 0.0;
+        if (fnorm[i] > 0.0) TRY(true_residual(c, c->ws[0], F[i], U[i], c->ws[0].tmp, &rt));
+        if (infos) {
+            fill_info(&infos[i], status, fnorm[i] > 0.0 ? st[i].iters_done : 0,
+                      fnorm[i] > 0.0 ? std::sqrt(st[i].rr) / fnorm[i] : 0.0, fnorm[i] > 0.0 ? rt / fnorm[i] : 0.0,
+                      c->setup_ms, ms, bad);
+        }
+    }
+    return worst;
+}
+
 }  // namespace
 
 extern "C" {
@@ -465,6 +718,17 @@ int dpcg_solve(dpcg_handle h, const double *f, double *u, double tol, const dpcg
     const int st = solve_impl(h, h->ws[0], f, u, tol, opt, info);
     if (st < 0 && info) info->status = st;
     return st;
+}
+
+int dpcg_solve_many(dpcg_handle *handles, int32_t count, const double *const *F, double *const *U, double tol,
+                    const dpcg_options *opt, dpcg_info *infos) {
+    return solve_many_impl(handles, count, F, U, tol, opt, infos);
+}
+
+int dpcg_autotune(dpcg_handle h, int32_t reps) {
+    if (!h || reps < 1) return DPCG_EINVAL;
+    const int g = autotune_spmv(h, reps);
+    return g > 0 ? g : DPCG_EHIP;
 }
 
 int dpcg_solve_batch(dpcg_handle h, int32_t nrhs, const double *F, double *U, double tol, const dpcg_options *opt,

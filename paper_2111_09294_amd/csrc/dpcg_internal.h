@@ -109,6 +109,38 @@ struct BatchWorkspace {
     int32_t nseg = 0;
 };
 
+// Several systems per launch: one descriptor per system (its operator, its forward
+// workspace and its state) and, per phase, the prefix offsets of the systems'
+// workgroups in the launch grid.
+constexpr int kMaxSystems = 64;
+enum MsPhase { kMsSpmv = 0, kMsAlpha, kMsBj, kMsRestrict, kMsCoarse, kMsVec, kMsPhases };
+
+struct MsSys {
+    int32_t nb, steps, spmv_nwg, group;
+    int32_t k, bj_ntiles, bj_nwg, vec_nwg;
+    int32_t guess, pad;
+    int64_t n, nnzb, einv_ld;
+    const int32_t *brow_ptr, *bcol;
+    const double *bval;
+    const double *minv;
+    const int32_t *bj_rowoff, *bj_meta, *bj_wg_start;
+    const int32_t *zt_ptr, *zt_idx;
+    const double *zt_val;
+    const int32_t *kzt_ptr, *kzt_idx;
+    const double *kzt_val;
+    const double *einv;
+    const int32_t *z_ptr, *z_col;
+    const double *z_val;
+    const double *f;
+    double *u, *r, *y, *z, *q, *p0, *p1, *g, *delta, *part_a, *part_b, *part_c;
+    State *st;
+};
+
+struct MsTable {
+    int32_t nsys;
+    int32_t off[kMsPhases][kMaxSystems + 1];  // off[phase][s]: first workgroup of system s
+};
+
 struct SpmvPlan {
     int group = 16;          // lanes per block row
     int nwg = 0;             // workgroups
@@ -149,6 +181,8 @@ struct dpcg_ctx {
     dpcg::SpmvPlan spmv;
     int32_t vec_nwg = 0;       // grid of the elementwise kernels (one DoF per thread)
     dpcg::Workspace ws[2];     // [0] forward solves, [1] adjoint solves
+    int32_t part_cap = 0;      // entries of each workspace partial-sum array
+    bool tuned = false;        // SpMV lane-group size chosen by measurement (dpcg_autotune)
     std::vector<void *> allocations;
     double setup_ms = 0.0;
     // optional event timing of the SpMV kernel
@@ -177,6 +211,18 @@ hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Work
 hipError_t launch_prolong(const dpcg_ctx *c, const double *base, const double *delta, double *out,
                           Workspace *w, const double *rdot, int advance);
 hipError_t launch_reduce_aux(const dpcg_ctx *c, Workspace &w, int n_parts);
+// several systems per launch (tab, sys: device copies); mode 0: start of Algorithm 2
+// (restriction of f and of the guess), 1: the merged right-hand side of Algorithm 3
+hipError_t launch_ms_spmv_p(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid);
+hipError_t launch_ms_spmv_res(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid);
+hipError_t launch_ms_alpha(hipStream_t s, const MsSys *sys, int nsys);
+hipError_t launch_ms_update_bj(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid);
+hipError_t launch_ms_bj(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid);
+hipError_t launch_ms_restrict(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int mode, int check,
+                              int iter_offset, int max_iter);
+hipError_t launch_ms_coarse(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int with_state);
+hipError_t launch_ms_prolong(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int mode, int advance);
+hipError_t launch_ms_beta(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid);
 // dst[i] = (float) src[i]
 hipError_t launch_to_f32(const dpcg_ctx *c, const double *src, int64_t count, float *dst);
 // y += x

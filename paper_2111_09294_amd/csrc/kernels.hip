@@ -145,13 +145,13 @@ __device__ __forceinline__ double pick3(int lg, double a0, double a1, double a2)
 
 // MODE 0: y = K x.   MODE 1: r = f - K x and ||r||^2 partials.
 template <int G, int MODE, class V>
-__global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
+__device__ __forceinline__ void k_spmv_body(int vb, SpmvShape sh, const int32_t *__restrict__ brow_ptr,
                                                    const int32_t *__restrict__ bcol,
                                                    const V *__restrict__ bval, int64_t nnzb,
                                                    const double *__restrict__ x, const double *__restrict__ f,
                                                    double *__restrict__ y, double *__restrict__ part) {
     __shared__ double lds[kSpmvWaves];
-    const int w = xcd_remap(blockIdx.x, sh.nwg);
+    const int w = xcd_remap(vb, sh.nwg);
     const int s0 = (int)(((int64_t)w * sh.steps) / sh.nwg), s1 = (int)(((int64_t)(w + 1) * sh.steps) / sh.nwg);
     const int lg = threadIdx.x % G;
     XPlain xl{x};
@@ -174,15 +174,25 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvShape sh, const int32
     }
     if (MODE == 1) {
         const double t = block_sum_n<kSpmvWaves>(acc, lds);
-        if (threadIdx.x == 0) part[blockIdx.x] = t;
+        if (threadIdx.x == 0) part[vb] = t;
     }
 }
+
+template <int G, int MODE, class V>
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
+                                                   const int32_t *__restrict__ bcol,
+                                                   const V *__restrict__ bval, int64_t nnzb,
+                                                   const double *__restrict__ x, const double *__restrict__ f,
+                                                   double *__restrict__ y, double *__restrict__ part) {
+    k_spmv_body<G, MODE, V>(blockIdx.x, sh, brow_ptr, bcol, bval, nnzb, x, f, y, part);
+}
+
 
 // Matrix product of Algorithm 1 for iteration i = st->iter: q = K p_i (p_i in buffer
 // i & 1, formed by k_beta_p) and partials of p_i^T q.  Only the single-workgroup
 // kernels change the flag, so it is stable while this kernel runs.
 template <int G, class V>
-__global__ __launch_bounds__(kSpmvThreads) void k_spmv_p(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
+__device__ __forceinline__ void k_spmv_p_body(int vb, SpmvShape sh, const int32_t *__restrict__ brow_ptr,
                                                          const int32_t *__restrict__ bcol,
                                                          const V *__restrict__ bval, int64_t nnzb,
                                                          const double *p0, const double *p1,
@@ -192,7 +202,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv_p(SpmvShape sh, const int
     if (st->flag != kRunning) return;
     const double *__restrict__ p = (st->iter & 1) ? p1 : p0;
     XPlain xl{p};
-    const int w = xcd_remap(blockIdx.x, sh.nwg);
+    const int w = xcd_remap(vb, sh.nwg);
     const int s0 = (int)(((int64_t)w * sh.steps) / sh.nwg), s1 = (int)(((int64_t)(w + 1) * sh.steps) / sh.nwg);
     const int lg = threadIdx.x % G;
     double acc = 0.0;
@@ -208,8 +218,19 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv_p(SpmvShape sh, const int
         }
     }
     const double t = block_sum_n<kSpmvWaves>(acc, lds);
-    if (threadIdx.x == 0) part_pq[blockIdx.x] = t;
+    if (threadIdx.x == 0) part_pq[vb] = t;
 }
+
+template <int G, class V>
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv_p(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
+                                                         const int32_t *__restrict__ bcol,
+                                                         const V *__restrict__ bval, int64_t nnzb,
+                                                         const double *p0, const double *p1,
+                                                         double *__restrict__ q, double *__restrict__ part_pq,
+                                                         const State *st) {
+    k_spmv_p_body<G, V>(blockIdx.x, sh, brow_ptr, bcol, bval, nnzb, p0, p1, q, part_pq, st);
+}
+
 
 // alpha_i = rho_i / p_i^T q_i from the SpMV partials (one workgroup, fixed order).
 __global__ __launch_bounds__(1024) void k_alpha(const double *__restrict__ part_pq, int n, State *st) {
@@ -233,7 +254,7 @@ __global__ __launch_bounds__(1024) void k_alpha(const double *__restrict__ part_
 // the search direction p_i = z_i + beta_{i-1} p_{i-1} (p_0 = z_0) into buffer i & 1 over
 // the workgroup's DoF range.  Workgroup 0 stores rho_i in slot i & 1 (rho_{i-1} in the
 // other slot stays valid for the others) and tests it for breakdown.
-__global__ __launch_bounds__(kThreads) void k_beta_p(const double *__restrict__ part_rho, int nparts, int64_t n,
+__device__ __forceinline__ void k_beta_p_body(int vb, const double *__restrict__ part_rho, int nparts, int64_t n,
                                                      int32_t nwg, const double *__restrict__ z, double *p0,
                                                      double *p1, State *st) {
     __shared__ double lds[4];
@@ -242,7 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_beta_p(const double *__restrict__ 
     const double rho = reduce_parts_n<4>(part_rho, nparts, lds);
     const bool bad = it > 0 && !isfinite(rho);
     const double beta = it > 0 ? rho / st->rho[(it + 1) & 1] : 0.0;
-    if (leader()) {
+    if ((vb == 0 && threadIdx.x == 0)) {
         if (bad) {
             st->flag = kBreakdown;
             st->bad = it - 1;
@@ -255,11 +276,18 @@ __global__ __launch_bounds__(kThreads) void k_beta_p(const double *__restrict__ 
     if (bad) return;
     double *__restrict__ pc = (it & 1) ? p1 : p0;
     const double *__restrict__ pp = (it & 1) ? p0 : p1;
-    const int w = xcd_remap(blockIdx.x, nwg);
+    const int w = xcd_remap(vb, nwg);
     const int64_t per = (n + nwg - 1) / nwg;
     const int64_t d1 = min(n, (int64_t)(w + 1) * per);
     for (int64_t d = (int64_t)w * per + threadIdx.x; d < d1; d += kThreads) pc[d] = it == 0 ? z[d] : fma(beta, pp[d], z[d]);
 }
+
+__global__ __launch_bounds__(kThreads) void k_beta_p(const double *__restrict__ part_rho, int nparts, int64_t n,
+                                                     int32_t nwg, const double *__restrict__ z, double *p0,
+                                                     double *p1, State *st) {
+    k_beta_p_body(blockIdx.x, part_rho, nparts, n, nwg, z, p0, p1, st);
+}
+
 
 // y_d = sum_j Minv_B[d - s_B, j] r_{s_B + j} for the DoFs of this tile (whole blocks).
 template <class M>
@@ -278,7 +306,7 @@ __device__ __forceinline__ double bj_row(int t, int64_t d, const double *tile, c
 // Step length, solution and residual updates of Algorithm 1 with the residual norm
 // partials, then the block-Jacobi apply y = M^{-1} r that opens Algorithm 3.
 template <class M>
-__global__ __launch_bounds__(kThreads) void k_update_bj(
+__device__ __forceinline__ void k_update_bj_body(int vb, 
     int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start, double *__restrict__ u,
     double *__restrict__ r, double *__restrict__ y, const double *__restrict__ q, const double *p0,
     const double *p1, const M *__restrict__ minv, const int32_t *__restrict__ bj_rowoff,
@@ -289,7 +317,7 @@ __global__ __launch_bounds__(kThreads) void k_update_bj(
     const double alpha = st->alpha;
     const double *p = (st->iter & 1) ? p1 : p0;
     const int t = threadIdx.x;
-    const int w = xcd_remap(blockIdx.x, nwg);
+    const int w = xcd_remap(vb, nwg);
     const int t0 = (int)(((int64_t)w * ntiles) / nwg), t1 = (int)(((int64_t)(w + 1) * ntiles) / nwg);
     double acc = 0.0;
     for (int tt = t0; tt < t1; ++tt) {
@@ -307,12 +335,23 @@ __global__ __launch_bounds__(kThreads) void k_update_bj(
         if (d < d1) y[d] = bj_row(t, d, tile, minv, bj_rowoff, bj_meta);
     }
     const double s = block_sum(acc, lds);
-    if (threadIdx.x == 0) part_rr[blockIdx.x] = s;
+    if (threadIdx.x == 0) part_rr[vb] = s;
 }
+
+template <class M>
+__global__ __launch_bounds__(kThreads) void k_update_bj(
+    int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start, double *__restrict__ u,
+    double *__restrict__ r, double *__restrict__ y, const double *__restrict__ q, const double *p0,
+    const double *p1, const M *__restrict__ minv, const int32_t *__restrict__ bj_rowoff,
+    const int32_t *__restrict__ bj_meta, double *__restrict__ part_rr, const State *st) {
+    k_update_bj_body<M>(blockIdx.x, ntiles, nwg, tile_start, u, r, y, q, p0, p1, minv, bj_rowoff, bj_meta, part_rr,
+                        st);
+}
+
 
 // y = M^{-1} r only.
 template <class M>
-__global__ __launch_bounds__(kThreads) void k_bj(int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start,
+__device__ __forceinline__ void k_bj_body(int vb, int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start,
                                                  const double *__restrict__ r, double *__restrict__ y,
                                                  const M *__restrict__ minv,
                                                  const int32_t *__restrict__ bj_rowoff,
@@ -320,7 +359,7 @@ __global__ __launch_bounds__(kThreads) void k_bj(int32_t ntiles, int32_t nwg, co
     __shared__ double tile[kThreads];
     if (st && st->flag != kRunning) return;
     const int t = threadIdx.x;
-    const int w = xcd_remap(blockIdx.x, nwg);
+    const int w = xcd_remap(vb, nwg);
     const int t0 = (int)(((int64_t)w * ntiles) / nwg), t1 = (int)(((int64_t)(w + 1) * ntiles) / nwg);
     for (int tt = t0; tt < t1; ++tt) {
         const int64_t d0 = tile_start[tt], d1 = tile_start[tt + 1];
@@ -332,12 +371,22 @@ __global__ __launch_bounds__(kThreads) void k_bj(int32_t ntiles, int32_t nwg, co
     }
 }
 
+template <class M>
+__global__ __launch_bounds__(kThreads) void k_bj(int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start,
+                                                 const double *__restrict__ r, double *__restrict__ y,
+                                                 const M *__restrict__ minv,
+                                                 const int32_t *__restrict__ bj_rowoff,
+                                                 const int32_t *__restrict__ bj_meta, const State *st) {
+    k_bj_body<M>(blockIdx.x, ntiles, nwg, tile_start, r, y, minv, bj_rowoff, bj_meta, st);
+}
+
+
 // Convergence test (workgroup 0 only) and g_j = Z^T a - (K Z)^T b, one column per
 // workgroup of kRestrictThreads threads, four independent chains per thread.
 constexpr int kRestrictWaves = 8;
 constexpr int kRestrictThreads = 64 * kRestrictWaves;
 
-__global__ __launch_bounds__(kRestrictThreads) void k_restrict(
+__device__ __forceinline__ void k_restrict_body(int vb, int vg, 
     int32_t k, const int32_t *__restrict__ zt_ptr, const int32_t *__restrict__ zt_idx,
     const double *__restrict__ zt_val, const int32_t *__restrict__ kzt_ptr, const int32_t *__restrict__ kzt_idx,
     const double *__restrict__ kzt_val, const double *__restrict__ a, const double *__restrict__ b,
@@ -346,7 +395,7 @@ __global__ __launch_bounds__(kRestrictThreads) void k_restrict(
     __shared__ double lds[kRestrictWaves];
     if (st) {
         if (wg_flag(st) != kRunning) return;
-        if (blockIdx.x == 0 && n_rr > 0) {
+        if (vb == 0 && n_rr > 0) {
             const double rr = reduce_parts_n<kRestrictWaves>(part_rr, n_rr, lds);
             if (threadIdx.x == 0) {
                 const int done = st->iter + iter_offset;
@@ -368,7 +417,7 @@ __global__ __launch_bounds__(kRestrictThreads) void k_restrict(
         }
     }
     constexpr int T = kRestrictThreads;
-    for (int j = blockIdx.x; j < k; j += gridDim.x) {
+    for (int j = vb; j < k; j += vg) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         {
             const int e1 = zt_ptr[j + 1];
@@ -397,13 +446,24 @@ __global__ __launch_bounds__(kRestrictThreads) void k_restrict(
     }
 }
 
+__global__ __launch_bounds__(kRestrictThreads) void k_restrict(
+    int32_t k, const int32_t *__restrict__ zt_ptr, const int32_t *__restrict__ zt_idx,
+    const double *__restrict__ zt_val, const int32_t *__restrict__ kzt_ptr, const int32_t *__restrict__ kzt_idx,
+    const double *__restrict__ kzt_val, const double *__restrict__ a, const double *__restrict__ b,
+    double *__restrict__ g, State *st, const double *__restrict__ part_rr, int n_rr, int iter_offset,
+    int max_iter, double *__restrict__ hist) {
+    k_restrict_body(blockIdx.x, gridDim.x, k, zt_ptr, zt_idx, zt_val, kzt_ptr, kzt_idx, kzt_val, a, b, g, st, part_rr,
+                    n_rr, iter_offset, max_iter, hist);
+}
+
+
 // delta = E^{-1} g: one workgroup per row of the dense symmetric inverse.
-__global__ __launch_bounds__(kThreads) void k_coarse(int32_t k, int64_t ld, const double *__restrict__ einv,
+__device__ __forceinline__ void k_coarse_body(int vb, int32_t k, int64_t ld, const double *__restrict__ einv,
                                                      const double *__restrict__ g, double *__restrict__ delta,
                                                      const State *st) {
     __shared__ double lds[4];
     if (st && st->flag != kRunning) return;
-    const int row = blockIdx.x;
+    const int row = vb;
     if (row >= k) return;
     const double *e = einv + (int64_t)row * ld;
     double s0 = 0.0, s1 = 0.0;
@@ -417,8 +477,15 @@ __global__ __launch_bounds__(kThreads) void k_coarse(int32_t k, int64_t ld, cons
     if (threadIdx.x == 0) delta[row] = s;
 }
 
+__global__ __launch_bounds__(kThreads) void k_coarse(int32_t k, int64_t ld, const double *__restrict__ einv,
+                                                     const double *__restrict__ g, double *__restrict__ delta,
+                                                     const State *st) {
+    k_coarse_body(blockIdx.x, k, ld, einv, g, delta, st);
+}
+
+
 // out = base + Z delta; optional partials of rdot^T out; optionally advance the iteration.
-__global__ __launch_bounds__(kThreads) void k_prolong(int64_t n, int32_t nwg, const int32_t *__restrict__ z_ptr,
+__device__ __forceinline__ void k_prolong_body(int vb, int64_t n, int32_t nwg, const int32_t *__restrict__ z_ptr,
                                                       const int32_t *__restrict__ z_col,
                                                       const double *__restrict__ z_val,
                                                       const double *__restrict__ delta,
@@ -427,7 +494,7 @@ __global__ __launch_bounds__(kThreads) void k_prolong(int64_t n, int32_t nwg, co
                                                       State *st, int advance) {
     __shared__ double lds[4];
     if (st && st->flag != kRunning) return;
-    const int w = xcd_remap(blockIdx.x, nwg);
+    const int w = xcd_remap(vb, nwg);
     const int64_t per = (n + nwg - 1) / nwg;
     const int64_t d0 = (int64_t)w * per, d1 = min(n, d0 + per);
     double acc = 0.0;
@@ -441,10 +508,21 @@ __global__ __launch_bounds__(kThreads) void k_prolong(int64_t n, int32_t nwg, co
     }
     if (rdot) {
         const double t = block_sum(acc, lds);
-        if (threadIdx.x == 0) part[blockIdx.x] = t;
+        if (threadIdx.x == 0) part[vb] = t;
     }
-    if (advance && leader()) st->iter = st->iter + 1;
+    if (advance && (vb == 0 && threadIdx.x == 0)) st->iter = st->iter + 1;
 }
+
+__global__ __launch_bounds__(kThreads) void k_prolong(int64_t n, int32_t nwg, const int32_t *__restrict__ z_ptr,
+                                                      const int32_t *__restrict__ z_col,
+                                                      const double *__restrict__ z_val,
+                                                      const double *__restrict__ delta,
+                                                      const double *base, double *out,
+                                                      const double *__restrict__ rdot, double *__restrict__ part,
+                                                      State *st, int advance) {
+    k_prolong_body(blockIdx.x, n, nwg, z_ptr, z_col, z_val, delta, base, out, rdot, part, st, advance);
+}
+
 
 // ||a||^2 partials and a count of non-finite entries of a and b (b may be null).
 __global__ __launch_bounds__(kThreads) void k_norm_finite(int64_t n, int32_t nwg, const double *__restrict__ a,
@@ -515,6 +593,136 @@ __global__ void k_to_f32(const double *__restrict__ src, int64_t count, float *_
 __global__ void k_add(int64_t n, const double *__restrict__ x, double *__restrict__ y) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] += x[i];
+}
+
+// ---------------------------------------------------------------- several systems per launch
+// Each phase of an iteration of several independent systems runs as one launch whose
+// workgroups are the systems' own, concatenated: a workgroup finds its system and its
+// index within that system in the phase's offset table (each system's count is a
+// multiple of 8 where the kernel maps workgroups XCD-major, so the mapping holds), and
+// then runs the single-system body on that system's operator, vectors and state.
+__device__ __forceinline__ int ms_find(const MsTable *__restrict__ tab, int phase, int bid) {
+    int lo = 0, hi = tab->nsys;  // last s with off[phase][s] <= bid
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tab->off[phase][mid] <= bid) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kSpmvThreads) void k_ms_spmv(const MsTable *__restrict__ tab,
+                                                          const MsSys *__restrict__ sys) {
+    const int s = ms_find(tab, kMsSpmv, blockIdx.x);
+    const MsSys &S = sys[s];
+    const int vb = blockIdx.x - tab->off[kMsSpmv][s];
+    const SpmvShape sh{S.nb, S.steps, S.spmv_nwg};
+    if (MODE == 0) {
+        switch (S.group) {
+            case 4: k_spmv_p_body<4, double>(vb, sh, S.brow_ptr, S.bcol, S.bval, S.nnzb, S.p0, S.p1, S.q, S.part_a, S.st); break;
+            case 8: k_spmv_p_body<8, double>(vb, sh, S.brow_ptr, S.bcol, S.bval, S.nnzb, S.p0, S.p1, S.q, S.part_a, S.st); break;
+            case 16: k_spmv_p_body<16, double>(vb, sh, S.brow_ptr, S.bcol, S.bval, S.nnzb, S.p0, S.p1, S.q, S.part_a, S.st); break;
+            default: k_spmv_p_body<32, double>(vb, sh, S.brow_ptr, S.bcol, S.bval, S.nnzb, S.p0, S.p1, S.q, S.part_a, S.st); break;
+        }
+    } else {
+        if (S.st->flag != kRunning) return;
+        switch (S.group) {
+            case 4: k_spmv_body<4, 1, double>(vb, sh, S.brow_ptr, S.bcol, S.bval, S.nnzb, S.u, S.f, S.r, S.part_b); break;
+            case 8: k_spmv_body<8, 1, double>(vb, sh, S.brow_ptr, S.bcol, S.bval, S.nnzb, S.u, S.f, S.r, S.part_b); break;
+            case 16: k_spmv_body<16, 1, double>(vb, sh, S.brow_ptr, S.bcol, S.bval, S.nnzb, S.u, S.f, S.r, S.part_b); break;
+            default: k_spmv_body<32, 1, double>(vb, sh, S.brow_ptr, S.bcol, S.bval, S.nnzb, S.u, S.f, S.r, S.part_b); break;
+        }
+    }
+}
+
+// alpha for system blockIdx.x (as k_alpha)
+__global__ __launch_bounds__(1024) void k_ms_alpha(const MsSys *__restrict__ sys) {
+    __shared__ double lds[16];
+    const MsSys &S = sys[blockIdx.x];
+    State *st = S.st;
+    if (st->flag != kRunning) return;
+    const double pq = reduce_parts_n<16>(S.part_a, S.spmv_nwg, lds);
+    if (threadIdx.x == 0) {
+        const double alpha = st->rho[st->iter & 1] / pq;
+        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(alpha)) {
+            st->flag = kBreakdown;
+            st->bad = st->iter;
+            st->iters_done = st->iter;
+        } else {
+            st->alpha = alpha;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_ms_update_bj(const MsTable *__restrict__ tab,
+                                                           const MsSys *__restrict__ sys) {
+    const int s = ms_find(tab, kMsBj, blockIdx.x);
+    const MsSys &S = sys[s];
+    k_update_bj_body<double>(blockIdx.x - tab->off[kMsBj][s], S.bj_ntiles, S.bj_nwg, S.bj_wg_start, S.u, S.r, S.y,
+                             S.q, S.p0, S.p1, S.minv, S.bj_rowoff, S.bj_meta, S.part_b, S.st);
+}
+
+__global__ __launch_bounds__(kThreads) void k_ms_bj(const MsTable *__restrict__ tab, const MsSys *__restrict__ sys) {
+    const int s = ms_find(tab, kMsBj, blockIdx.x);
+    const MsSys &S = sys[s];
+    k_bj_body<double>(blockIdx.x - tab->off[kMsBj][s], S.bj_ntiles, S.bj_nwg, S.bj_wg_start, S.r, S.y, S.minv,
+                      S.bj_rowoff, S.bj_meta, S.st);
+}
+
+// mode 0: g = Z^T f - (KZ)^T u_{-1} (no state); mode 1: g = Z^T r - (KZ)^T y with the
+// convergence test when check.
+__global__ __launch_bounds__(kRestrictThreads) void k_ms_restrict(const MsTable *__restrict__ tab,
+                                                                  const MsSys *__restrict__ sys, int mode, int check,
+                                                                  int iter_offset, int max_iter) {
+    const int s = ms_find(tab, kMsRestrict, blockIdx.x);
+    const MsSys &S = sys[s];
+    const int vb = blockIdx.x - tab->off[kMsRestrict][s];
+    const int vg = tab->off[kMsRestrict][s + 1] - tab->off[kMsRestrict][s];
+    if (mode == 0) {
+        if (S.st->flag != kRunning) return;
+        k_restrict_body(vb, vg, S.k, S.zt_ptr, S.zt_idx, S.zt_val, S.kzt_ptr, S.kzt_idx, S.kzt_val, S.f,
+                        S.guess ? S.u : nullptr, S.g, nullptr, nullptr, 0, 0, 0, nullptr);
+    } else {
+        k_restrict_body(vb, vg, S.k, S.zt_ptr, S.zt_idx, S.zt_val, S.kzt_ptr, S.kzt_idx, S.kzt_val, S.r, S.y, S.g, S.st,
+                        S.part_b, check ? (iter_offset ? S.bj_nwg : S.spmv_nwg) : 0, iter_offset, max_iter, nullptr);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_ms_coarse(const MsTable *__restrict__ tab, const MsSys *__restrict__ sys,
+                                                        int with_state) {
+    const int s = ms_find(tab, kMsCoarse, blockIdx.x);
+    const MsSys &S = sys[s];
+    if (!with_state && S.st->flag != kRunning) return;
+    k_coarse_body(blockIdx.x - tab->off[kMsCoarse][s], S.k, S.einv_ld, S.einv, S.g, S.delta,
+                  with_state ? S.st : nullptr);
+}
+
+// mode 0: u = u_{-1} + Z delta (no state); mode 1: z = y + Z delta with r^T z partials
+__global__ __launch_bounds__(kThreads) void k_ms_prolong(const MsTable *__restrict__ tab,
+                                                         const MsSys *__restrict__ sys, int mode, int advance) {
+    const int s = ms_find(tab, kMsVec, blockIdx.x);
+    const MsSys &S = sys[s];
+    const int vb = blockIdx.x - tab->off[kMsVec][s];
+    if (mode == 0) {
+        if (S.st->flag != kRunning) return;
+        if (S.k > 0)
+            k_prolong_body(vb, S.n, S.vec_nwg, S.z_ptr, S.z_col, S.z_val, S.delta, S.guess ? S.u : nullptr, S.u,
+                           nullptr, nullptr, nullptr, 0);
+        else if (!S.guess)
+            k_prolong_body(vb, S.n, S.vec_nwg, S.z_ptr, S.z_col, S.z_val, S.delta, nullptr, S.u, nullptr, nullptr,
+                           nullptr, 0);
+    } else {
+        k_prolong_body(vb, S.n, S.vec_nwg, S.z_ptr, S.z_col, S.z_val, S.delta, S.y, S.z, S.r, S.part_c, S.st,
+                       advance);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_ms_beta_p(const MsTable *__restrict__ tab,
+                                                        const MsSys *__restrict__ sys) {
+    const int s = ms_find(tab, kMsVec, blockIdx.x);
+    const MsSys &S = sys[s];
+    k_beta_p_body(blockIdx.x - tab->off[kMsVec][s], S.part_c, S.vec_nwg, S.n, S.vec_nwg, S.z, S.p0, S.p1, S.st);
 }
 
 }  // namespace
@@ -626,6 +834,61 @@ hipError_t launch_check_finite_norm(const dpcg_ctx *c, const double *a, const do
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reduce_aux, dim3(1), dim3(kThreads), 0, c->stream, w.part_a, w.part_b, c->vec_nwg,
                        w.st);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_spmv_p(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid) {
+    if (ngrid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ms_spmv<0>, dim3(ngrid), dim3(kSpmvThreads), 0, s, tab, sys);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_spmv_res(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid) {
+    if (ngrid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ms_spmv<1>, dim3(ngrid), dim3(kSpmvThreads), 0, s, tab, sys);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_alpha(hipStream_t s, const MsSys *sys, int nsys) {
+    hipLaunchKernelGGL(k_ms_alpha, dim3(nsys), dim3(1024), 0, s, sys);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_update_bj(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid) {
+    if (ngrid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ms_update_bj, dim3(ngrid), dim3(kThreads), 0, s, tab, sys);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_bj(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid) {
+    if (ngrid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ms_bj, dim3(ngrid), dim3(kThreads), 0, s, tab, sys);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_restrict(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int mode, int check,
+                              int iter_offset, int max_iter) {
+    if (ngrid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ms_restrict, dim3(ngrid), dim3(kRestrictThreads), 0, s, tab, sys, mode, check, iter_offset,
+                       max_iter);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_coarse(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int with_state) {
+    if (ngrid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ms_coarse, dim3(ngrid), dim3(kThreads), 0, s, tab, sys, with_state);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_prolong(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int mode, int advance) {
+    if (ngrid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ms_prolong, dim3(ngrid), dim3(kThreads), 0, s, tab, sys, mode, advance);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_beta(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid) {
+    if (ngrid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ms_beta_p, dim3(ngrid), dim3(kThreads), 0, s, tab, sys);
     return hipGetLastError();
 }
 

@@ -177,3 +177,56 @@ def test_batch_case_a_top_face_tractions(solver):
         ref = o.solve(F[:, j], tol=1e-8)
         assert np.linalg.norm(U[:, j] - ref["u"]) <= 1e-6 * np.linalg.norm(ref["u"])
         assert iters_close(infos[j]["iterations"], ref["iterations"])
+
+
+# ------------------------------------------------------------------ several systems per launch
+def test_solve_many_matches_single_solves():
+    """Uneven independent systems (6 meshes of 4^3 to 12^3 elements, penny cracks at
+    random centres) solved together: every system equals its own single solve bitwise
+    (same kernels, same workgroup counts, same tuned lane groups) and the oracle."""
+    from fixtures import uneven_systems
+    ps = uneven_systems(6, seed=3, ne_range=(4, 12), r_e=0.1)
+    solvers = [D.Solver.from_problem(p, DEV) for p in ps]
+    try:
+        fs = [dev(p.f) for p in ps]
+        fs[3] = torch.zeros_like(fs[3])          # a zero right-hand side: 0 after 0 iterations
+        us, infos = D.solve_many(solvers, fs, tol=1e-8)
+        for i, (p, s) in enumerate(zip(ps, solvers)):
+            u1, i1 = s.solve(fs[i], tol=1e-8)
+            assert infos[i]["status"] == D.abi.OK
+            assert infos[i]["iterations"] == i1["iterations"], (i, infos[i], i1)
+            assert torch.equal(us[i], u1), i
+            assert infos[i]["rel_res_true"] <= 1.5e-8
+        assert infos[3]["iterations"] == 0 and not torch.any(us[3])
+        o = O.Oracle.from_problem(ps[0])
+        ref = o.solve(ps[0].f, tol=1e-8)
+        assert np.linalg.norm(host(us[0]) - ref["u"]) <= 1e-6 * np.linalg.norm(ref["u"])
+        assert iters_close(infos[0]["iterations"], ref["iterations"])
+        # warm start from the solutions: every system stops at iteration 0
+        us2, infos2 = D.solve_many(solvers, fs, tol=1e-7, initial_guesses=us)
+        assert all(i["iterations"] == 0 for i in infos2)
+        # a repeated handle and an empty set are rejected
+        o_ = D.abi.Options()
+        D.abi.lib().dpcg_default_options(C.byref(o_))
+        hs = (C.c_void_p * 2)(solvers[0].handle.value, solvers[0].handle.value)
+        fp = (C.c_void_p * 2)(fs[0].data_ptr(), fs[0].data_ptr())
+        up = (C.c_void_p * 2)(us[0].data_ptr(), us[0].data_ptr())
+        assert D.abi.lib().dpcg_solve_many(C.cast(hs, C.c_void_p), 2, C.cast(fp, C.c_void_p),
+                                           C.cast(up, C.c_void_p), 1e-8, C.byref(o_), None) == D.abi.EINVAL
+        assert D.abi.lib().dpcg_solve_many(C.cast(hs, C.c_void_p), 0, C.cast(fp, C.c_void_p),
+                                           C.cast(up, C.c_void_p), 1e-8, C.byref(o_), None) == D.abi.EINVAL
+        say(f"[many] 6 systems n={[p.n for p in ps]}: iterations {[i['iterations'] for i in infos]}, "
+            f"together {infos[0]['solve_ms']:.1f} ms")
+    finally:
+        for s in solvers:
+            s.close()
+
+
+def test_autotune_keeps_results_valid(solver):
+    p, s = solver("edge10")
+    u0, i0 = s.solve(dev(p.f))
+    g = s.autotune(3)
+    assert g in (4, 8, 16, 32)
+    u1, i1 = s.solve(dev(p.f))
+    assert iters_close(i0["iterations"], i1["iterations"])
+    assert torch.linalg.norm(u1 - u0) <= 1e-8 * torch.linalg.norm(u0)
