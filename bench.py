@@ -125,16 +125,16 @@ def run_mixed(step, p, args, stats):
 
 
 def run_batched(p, args, K, Z, bp, f, stream, nrhs=32):
-    """The same steps with nrhs right-hand sides solved together (column 0 = the
-    workload's load, the others seeded Gaussian vectors), every column to 1e-8."""
+    """The same steps with nrhs right-hand sides solved together (Case A of the batching
+    workload: seeded random top-face tractions, N(0, 1) components per face node),
+    every column to 1e-8."""
     import numpy as np
     import torch
 
     import paper_2111_09294_amd as dpcg
 
-    rng = np.random.default_rng(2024)
-    F = rng.standard_normal((p.n, nrhs))
-    F[:, 0] = p.f
+    from fixtures import box
+    F = box(args.workload).random_top_tractions(nrhs, seed=2024)
     Fd = torch.as_tensor(F, device=f.device)
     U = torch.empty_like(Fd)
 
@@ -175,6 +175,54 @@ def run_batched(p, args, K, Z, bp, f, stream, nrhs=32):
             "spmm": {"kernel": "k_bspmm<0>", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "launches": spmm_n,
                      "avg_launch_us": per_launch_s * 1e6}}
+
+
+def run_many(args, count=16):
+    """Case B of the batching workload: count independent systems (ne^3 meshes, ne uniform
+    in [20, 48], penny cracks at random centres in [0.3, 0.7]^3), solved together by
+    dpcg_solve_many (one launch per iteration phase for all) against the same systems
+    solved one after another.  Solve time only: the systems are set up (and the SpMV
+    lane groups tuned) once before timing."""
+    import numpy as np
+    import torch
+
+    import paper_2111_09294_amd as dpcg
+    from fixtures import uneven_systems
+
+    t_gen = time.perf_counter()
+    ps = uneven_systems(count, seed=16, ne_range=(20, 48))
+    t_gen = time.perf_counter() - t_gen
+    solvers = [dpcg.Solver.from_problem(p, "cuda:0") for p in ps]
+    fs = [torch.as_tensor(p.f, device="cuda:0") for p in ps]
+    us = [torch.empty_like(f) for f in fs]
+    for s in solvers:
+        s.autotune(5)
+    for _ in range(max(1, args.warmup)):
+        dpcg.solve_many(solvers, fs, us)
+        for s, f, u in zip(solvers, fs, us):
+            s.solve(f, u)
+    torch.cuda.synchronize()
+    reps = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, infos = dpcg.solve_many(solvers, fs, us)
+    torch.cuda.synchronize()
+    t_many = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        singles = [s.solve(f, u)[1] for s, f, u in zip(solvers, fs, us)]
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / reps
+    for s in solvers:
+        s.close()
+    n_tot = sum(p.n for p in ps)
+    same_its = all(a["iterations"] == b["iterations"] for a, b in zip(infos, singles))
+    return {"value": n_tot / t_many, "unit": "DoF-solves/s", "systems": count, "dofs_total": n_tot,
+            "dofs_min": min(p.n for p in ps), "dofs_max": max(p.n for p in ps),
+            "ms_together": t_many * 1e3, "ms_sequential": t_seq * 1e3,
+            "sequential_dof_solves_per_s": n_tot / t_seq, "speedup": t_seq / t_many,
+            "ok": all(i["status"] == 0 for i in infos), "same_iterations_as_single": same_its,
+            "iterations_max": max(i["iterations"] for i in infos), "generation_s": t_gen}
 
 
 def main():
@@ -282,6 +330,7 @@ def main():
         out["mixed"] = run_mixed(step, p, args, stats)
     if not args.no_batched:
         out["batched"] = run_batched(p, args, K, Z, bp, f, stream)
+        out["many_systems"] = run_many(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
