@@ -192,6 +192,22 @@ int dpcg_solve_batch(dpcg_handle h, int32_t nrhs, const double *F, double *U, do
 int dpcg_solve_many(dpcg_handle *handles, int32_t count, const double *const *F, double *const *U,
                     double tol, const dpcg_options *opt, dpcg_info *infos);
 
+/*
+ * New values of K on the sparsity pattern of the setup (Sec. 4: as the crack grows,
+ * only the blocks of nodes whose enrichment changes need new factors).  k_rowptr,
+ * k_col, k_val as in dpcg_setup; the pattern (rows, columns, block structure) must be
+ * the one the handle was set up with.  The block values, the symmetry test, K Z, E and
+ * E^{-1} are rebuilt; the block-Jacobi inverses only of the nchanged blocks listed in
+ * changed_blocks (host array of block indices), or of every block when changed_blocks
+ * is NULL.  A block whose values changed but is not listed keeps its old inverse: the
+ * solves stay correct (an SPD preconditioner), they may take more iterations.
+ * info->setup_ms reports the update's wall time.  Errors: DPCG_EINVAL (another
+ * pattern, an invalid array or block index), DPCG_ENOTSYM, DPCG_EBLOCK_NOT_SPD,
+ * DPCG_ECOARSE_NOT_SPD, DPCG_EHIP; after an error the handle must be destroyed.
+ */
+int dpcg_update_values(dpcg_handle h, const int64_t *k_rowptr, const int32_t *k_col, const double *k_val,
+                       int32_t nchanged, const int32_t *changed_blocks, dpcg_info *info);
+
 /* Times the SpMV kernel for each lane-group size (4, 8, 16, 32 lanes per block row;
  * reps launches each, HIP events) and keeps the fastest for every later solve of the
  * handle.  Returns the chosen size, or a negative status. */

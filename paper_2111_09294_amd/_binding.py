@@ -63,6 +63,7 @@ SIGNATURES = {
     "dpcg_solve_batch": (C.c_int, [P, C.c_int32, P, P, C.c_double, C.POINTER(Options), P]),
     "dpcg_solve_many": (C.c_int, [P, C.c_int32, P, P, C.c_double, C.POINTER(Options), P]),
     "dpcg_autotune": (C.c_int, [P, C.c_int32]),
+    "dpcg_update_values": (C.c_int, [P, P, P, P, C.c_int32, P, C.POINTER(Info)]),
     "dpcg_destroy": (None, [P]),
     "dpcg_release_cached_memory": (None, []),
     "dpcg_status_string": (C.c_char_p, [C.c_int]),
@@ -330,6 +331,26 @@ class Solver:
         if st != OK:
             raise DpcgError(st, "dpcg_element_gradient")
         return g
+
+    def update_values(self, k_rowptr, k_col, k_val, changed_blocks=None):
+        """New values of K on the setup's pattern; only the listed block-Jacobi blocks
+        (all when None) are refactorised.  Returns the info dict (setup_ms = update time)."""
+        import numpy as np
+        import torch
+        _check_dev(k_rowptr, torch.int64, "k_rowptr", self.n + 1)
+        _check_dev(k_col, torch.int32, "k_col")
+        _check_dev(k_val, torch.float64, "k_val", k_col.numel())
+        info = Info()
+        if changed_blocks is None:
+            st = lib().dpcg_update_values(self.handle, _ptr(k_rowptr), _ptr(k_col), _ptr(k_val), -1, None,
+                                          C.byref(info))
+        else:
+            blk = np.ascontiguousarray(changed_blocks, dtype=np.int32)
+            st = lib().dpcg_update_values(self.handle, _ptr(k_rowptr), _ptr(k_col), _ptr(k_val), len(blk),
+                                          blk.ctypes.data_as(C.c_void_p), C.byref(info))
+        if st != OK:
+            raise DpcgError(st, "dpcg_update_values", info)
+        return info.as_dict()
 
     def autotune(self, reps=5):
         """Measures the SpMV lane-group sizes and keeps the fastest; returns it."""

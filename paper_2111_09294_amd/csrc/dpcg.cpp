@@ -725,6 +725,18 @@ int dpcg_solve_many(dpcg_handle *handles, int32_t count, const double *const *F,
     return solve_many_impl(handles, count, F, U, tol, opt, infos);
 }
 
+int dpcg_update_values(dpcg_handle h, const int64_t *k_rowptr, const int32_t *k_col, const double *k_val,
+                       int32_t nchanged, const int32_t *changed_blocks, dpcg_info *info) {
+    const double t0 = now_ms();
+    if (!h || !k_rowptr || !k_col || !k_val || (changed_blocks && nchanged < 0)) return DPCG_EINVAL;
+    int64_t bad = -1;
+    h->inner32 = false;
+    const int st = gpu_update_values(h, k_rowptr, k_col, k_val, changed_blocks ? nchanged : 0, changed_blocks, &bad);
+    h->setup_ms = now_ms() - t0;
+    fill_info(info, st, 0, 0.0, 0.0, h->setup_ms, 0.0, bad);
+    return st;
+}
+
 int dpcg_autotune(dpcg_handle h, int32_t reps) {
     if (!h || reps < 1) return DPCG_EINVAL;
     const int g = autotune_spmv(h, reps);

@@ -166,6 +166,8 @@ struct dpcg_ctx {
     int32_t *bj_rowoff = nullptr, *bj_meta = nullptr, *bj_wg_start = nullptr;
     int32_t bj_nwg = 0, bj_ntiles = 0;
     int32_t *bjb_start = nullptr;   // tiles of whole blocks, <= kBatchTileDofs DoFs (multi-RHS)
+    int32_t *block_ptr = nullptr;   // the block partition (nblocks + 1), kept for value updates
+    int64_t *bj_moff = nullptr;     // offset of each block's inverse in minv (nblocks + 1)
     int32_t bjb_ntiles = 0;
     dpcg::BatchWorkspace *bws = nullptr;  // multi-RHS workspace, made on the first batched solve
     // deflation
@@ -227,6 +229,10 @@ hipError_t launch_ms_beta(hipStream_t s, const MsTable *tab, const MsSys *sys, i
 hipError_t launch_to_f32(const dpcg_ctx *c, const double *src, int64_t count, float *dst);
 // y += x
 hipError_t launch_add(const dpcg_ctx *c, const double *x, double *y);
+
+// setup.hip: new values of K on the same pattern (see dpcg_update_values)
+int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const double *kv, int32_t nlist,
+                      const int32_t *list_host, int64_t *bad);
 
 // batch.hip: multi-RHS solve (nrhs <= kBatchCols columns, caller arrays n x nrhs
 // row-major); returns a DPCG_* status and fills infos[nrhs] when given.

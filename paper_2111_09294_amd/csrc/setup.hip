@@ -380,13 +380,17 @@ __global__ void k_block_sq(int32_t nblocks, const int32_t *__restrict__ bp, int6
 // (register arrays, every index a compile-time constant); larger blocks one wave each.
 constexpr int kSmallBlock = 6;
 
+// list (may be null): factorise only the nlist blocks list[0..nlist) instead of all.
 __global__ __launch_bounds__(256) void k_bj_small(int32_t nblocks, const int32_t *__restrict__ bp,
                                                   const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                   const double *__restrict__ val, const int64_t *__restrict__ moff,
                                                   double *__restrict__ minv, int32_t *__restrict__ rowoff,
-                                                  int32_t *__restrict__ meta, int *bad_block) {
+                                                  int32_t *__restrict__ meta, int *bad_block,
+                                                  const int32_t *__restrict__ list, int32_t nlist) {
     constexpr int M = kSmallBlock;
-    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nblocks; b += gridDim.x * blockDim.x) {
+    const int count = list ? nlist : nblocks;
+    for (int ib = blockIdx.x * blockDim.x + threadIdx.x; ib < count; ib += gridDim.x * blockDim.x) {
+        const int b = list ? list[ib] : ib;
         const int32_t s = bp[b];
         const int m = bp[b + 1] - s;
         if (m > M) continue;
@@ -473,12 +477,15 @@ __global__ __launch_bounds__(64) void k_bj_factor(int32_t nblocks, const int32_t
                                                   const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                                   const double *__restrict__ val, const int64_t *__restrict__ moff,
                                                   double *__restrict__ minv, int32_t *__restrict__ rowoff,
-                                                  int32_t *__restrict__ meta, int *bad_block) {
+                                                  int32_t *__restrict__ meta, int *bad_block,
+                                                  const int32_t *__restrict__ list, int32_t nlist) {
     __shared__ double A[kMaxBlock * kMaxBlock];
     __shared__ double Li[kMaxBlock * kMaxBlock];
     __shared__ int fail;
     const int lane = threadIdx.x;
-    for (int b = blockIdx.x; b < nblocks; b += gridDim.x) {
+    const int count = list ? nlist : nblocks;
+    for (int ib = blockIdx.x; ib < count; ib += gridDim.x) {
+        const int b = list ? list[ib] : ib;
         const int32_t s = bp[b];
         const int m = bp[b + 1] - s;
         if (m <= kSmallBlock) continue;
@@ -1143,6 +1150,30 @@ __global__ __launch_bounds__(256) void k_gj_sweep(int p, int nt, const double *_
     }
 }
 
+// ---------------------------------------------------------------- value updates
+__global__ void k_to_i64(const int32_t *__restrict__ a, int64_t n, int64_t *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = a[i];
+}
+
+__global__ void k_to_f32_s(const double *__restrict__ a, int64_t n, float *__restrict__ out) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)a[i];
+}
+
+// flag = first block row whose block count differs from the stored row pointer
+__global__ void k_cmp_counts(int32_t nb, const int64_t *__restrict__ cnt, const int32_t *__restrict__ bptr,
+                             int *flag) {
+    for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < nb; r += (int64_t)gridDim.x * blockDim.x)
+        if (cnt[r] != (int64_t)(bptr[r + 1] - bptr[r])) atomicMin(flag, (int)r);
+}
+
+// flag = 0 when a[i] != b[i] for some i
+__global__ void k_cmp_i32(int64_t n, const int32_t *__restrict__ a, const int32_t *__restrict__ b, int *flag) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        if (a[i] != b[i]) atomicMin(flag, 0);
+}
+
 // ---------------------------------------------------------------- host helpers
 // Scratch of one setup call; released (to the cache) once the stream is idle.
 struct Pool {
@@ -1192,6 +1223,166 @@ hipError_t scan(hipStream_t s, const int64_t *a, int64_t n, int64_t *out, int64_
     do {                                               \
         if ((expr) != hipSuccess) return DPCG_EHIP;    \
     } while (0)
+
+// K Z (as (KZ)^T) and E = Z^T K Z in batches of kBatch deflation vectors, then E^-1 by
+// blocked Gauss-Jordan sweeps.  Inputs: Z (int64 row pointer), Z^T (int64 pointer), the
+// row windows of K z_j (wlo on the device, ws on the host).  reuse: the arrays of a
+// previous build are overwritten (same structure) instead of allocated.
+int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const int32_t *zc, const int64_t *ztp,
+                    const int32_t *zti, const double *ztv, const int64_t *wlo, const std::vector<int64_t> &ws,
+                    int64_t *part, int *flags, int64_t *bad, bool reuse) {
+    hipStream_t s = c->stream;
+    int fl[4];
+    {
+        // ---- K Z and E, in batches of kBatch vectors; batch groups bound the scratch ----
+        std::vector<int64_t> wl(k);
+        HT(hipMemcpyAsync(wl.data(), wlo, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+        HT(hipStreamSynchronize(s));
+        const int nbat = (k + kBatch - 1) / kBatch;
+        const int words = (k + 31) / 32;
+        std::vector<KzBatch> bt(nbat);
+        int64_t slices = 0;
+        for (int bi = 0; bi < nbat; ++bi) {
+            KzBatch &B = bt[bi];
+            B.j0 = (int64_t)bi * kBatch;
+            B.ncol = std::min<int64_t>(kBatch, k - B.j0);
+            int64_t lo = INT64_MAX, hi = -1;
+            for (int64_t j = B.j0; j < B.j0 + B.ncol; ++j)
+                if (ws[j] > 0) {
+                    lo = std::min(lo, wl[j]);
+                    hi = std::max(hi, wl[j] + ws[j]);
+                }
+            B.lo3 = hi > 0 ? lo / 3 : 0;
+            B.w3 = hi > 0 ? (hi + 2) / 3 - B.lo3 : 0;
+            B.nslice = std::max<int64_t>(1, (B.w3 + kSlice - 1) / kSlice);
+            B.slice0 = slices;
+            slices += B.nslice;
+        }
+        // group consecutive batches so that a group's scratch stays under the budget
+        const int64_t per_triplet = 2 * 3 * kBatch * sizeof(double) + 2 * sizeof(uint32_t);
+        const int64_t budget = int64_t(1) << 30;
+        std::vector<int> gcut{0};
+        int64_t acc_w = 0, max_group_w = 0;
+        int max_group_nb = 0;
+        for (int bi = 0; bi < nbat; ++bi) {
+            if (acc_w > 0 && (acc_w + bt[bi].w3) * per_triplet > budget) {
+                gcut.push_back(bi);
+                acc_w = 0;
+            }
+            bt[bi].off3 = acc_w;
+            bt[bi].bit0 = (int64_t)(bi - gcut.back()) * words;
+            acc_w += bt[bi].w3;
+            max_group_w = std::max(max_group_w, acc_w);
+            max_group_nb = std::max(max_group_nb, bi - gcut.back() + 1);
+        }
+        gcut.push_back(nbat);
+        KzBatch *bt_d = nullptr;
+        int32_t *scnt = nullptr, *soff = nullptr;
+        int64_t *kzcnt = nullptr, *kzp = nullptr;
+        double *zd = nullptr, *kd = nullptr;
+        uint32_t *mk = nullptr, *rbits = nullptr, *touched = nullptr;
+        HT(pool.tmp(&bt_d, nbat));
+        HT(hipMemcpyAsync(bt_d, bt.data(), sizeof(KzBatch) * nbat, hipMemcpyHostToDevice, s));
+        HT(pool.tmp(&scnt, slices * kBatch));
+        HT(pool.tmp(&soff, slices * kBatch));
+        HT(pool.tmp(&kzcnt, k));
+        HT(pool.tmp(&kzp, k + 1));
+        HT(pool.tmp(&zd, 3 * max_group_w * kBatch));
+        HT(pool.tmp(&kd, 3 * max_group_w * kBatch));
+        HT(pool.tmp(&mk, max_group_w));
+        HT(pool.tmp(&rbits, max_group_w));
+        HT(pool.tmp(&touched, (int64_t)max_group_nb * words));
+        int32_t *icnt = nullptr;
+        int64_t *nitems = nullptr;
+        KzItem *items = nullptr;
+        HT(pool.tmp(&icnt, slices));
+        HT(pool.tmp(&nitems, nbat));
+        HT(pool.tmp(&items, max_group_w));
+        auto max_slices = [&](int g0, int g1) {
+            int64_t m = 1;
+            for (int bi = g0; bi < g1; ++bi) m = std::max(m, bt[bi].nslice);
+            return (int)m;
+        };
+        auto prepare = [&](int g0, int g1) {
+            const dim3 gs(max_slices(g0, g1), g1 - g0);
+            hipLaunchKernelGGL(k_kzb_init, gs, dim3(256), 0, s, bt_d + g0, words, mk, rbits, touched);
+            hipLaunchKernelGGL(k_kzb_scatter, dim3(kBatch, g1 - g0), dim3(256), 0, s, bt_d + g0, ztp, zti, ztv, zd,
+                               rbits);
+            hipLaunchKernelGGL(k_kzb_mark, gs, dim3(256), 0, s, bt_d + g0, c->brow_ptr, c->bcol, rbits, mk);
+        };
+        for (size_t g = 0; g + 1 < gcut.size(); ++g) {
+            prepare(gcut[g], gcut[g + 1]);
+            hipLaunchKernelGGL(k_kzb_count, dim3(max_slices(gcut[g], gcut[g + 1]), gcut[g + 1] - gcut[g]), dim3(256),
+                               0, s, bt_d + gcut[g], mk, scnt);
+        }
+        hipLaunchKernelGGL(k_kzb_offsets, dim3(nbat), dim3(kBatch), 0, s, bt_d, nbat, scnt, soff, kzcnt);
+        HT(scan(s, kzcnt, k, kzp, part));
+        int64_t nkz = 0;
+        HT(hipMemcpyAsync(&nkz, kzp + k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+        HT(hipStreamSynchronize(s));
+        if (fl[3] != INT32_MAX) return DPCG_ENOTSYM;
+        if (fl[1] != INT32_MAX) {
+            *bad = fl[1];
+            return DPCG_EBLOCK_NOT_SPD;
+        }
+        if (nkz > (int64_t)INT32_MAX) return DPCG_EINVAL;
+        if (reuse && nkz != c->nnz_kz) return DPCG_EINVAL;  // the structure of K Z must not change
+        c->nnz_kz = nkz;
+        if (!reuse) {
+            HT(keep(c, &c->kzt_idx, nkz));
+            HT(keep(c, &c->kzt_val, nkz));
+        }
+        const int64_t ld = ((int64_t)k + kNb - 1) / kNb * kNb;
+        c->einv_ld = ld;
+        double *eraw = nullptr, *ga = nullptr, *diag0 = nullptr, *pv = nullptr;
+        HT(pool.tmp(&eraw, ld * ld));
+        HT(hipMemsetAsync(eraw, 0, sizeof(double) * ld * ld, s));
+        for (size_t g = 0; g + 1 < gcut.size(); ++g) {
+            const int g0 = gcut[g], g1 = gcut[g + 1];
+            if (gcut.size() > 2) prepare(g0, g1);  // one group: the count pass left it ready
+            hipLaunchKernelGGL(k_kzb_items, dim3(g1 - g0), dim3(256), 0, s, bt_d + g0, g1 - g0, mk, icnt,
+                               nitems + g0);
+            hipLaunchKernelGGL(k_kzb_rank, dim3(max_slices(g0, g1), g1 - g0), dim3(256), 0, s, bt_d + g0, mk, soff,
+                               icnt, kzp, items);
+            hipLaunchKernelGGL(k_kzb_values, dim3(128, g1 - g0), dim3(256),
+                               0, s, bt_d + g0, nitems + g0, items, c->brow_ptr, c->bcol, c->bval, zd, rbits, zp, zc,
+                               c->kzt_idx, c->kzt_val, kd, words, touched);
+            hipLaunchKernelGGL(k_kzb_erows, dim3((k + 3) / 4, g1 - g0), dim3(256), 0, s, bt_d + g0, k, ztp, zti, ztv,
+                               kd, mk, touched, eraw, ld);
+        }
+        HT(hipGetLastError());
+        // ---- E^-1 ----
+        HT(pool.tmp(&ga, ld * ld));
+        if (!reuse) HT(keep(c, &c->einv, ld * ld));
+        HT(pool.tmp(&diag0, ld));
+        HT(pool.tmp(&pv, 2 * kNb * kNb));
+        hipLaunchKernelGGL(k_symmetrise, dim3(grid_for(ld * ld)), dim3(256), 0, s, k, ld, eraw, ga, diag0);
+        int *cfail = flags + 2;
+        HT(hipMemsetAsync(cfail, 0, sizeof(int), s));
+        hipLaunchKernelGGL(k_gj_first_pivot, dim3(1), dim3(256), 0, s, ga, ld, k, diag0, pv, cfail);
+        const int nt = (int)(ld / kNb);
+        double *src = ga, *dst = c->einv;
+        if (nt % 2 == 0) std::swap(src, dst);  // the last sweep must land in c->einv
+        if (nt % 2 == 0)
+            HT(hipMemcpyAsync(src, ga, sizeof(double) * ld * ld, hipMemcpyDeviceToDevice, s));
+        for (int p = 0; p < nt; ++p) {
+            hipLaunchKernelGGL(k_gj_sweep, dim3(nt * nt), dim3(256), 0, s, p, nt, src, dst, ld, k,
+                               pv + (p & 1) * kNb * kNb, pv + ((p + 1) & 1) * kNb * kNb, diag0, cfail);
+            std::swap(src, dst);
+        }
+        HT(hipGetLastError());
+        if (!reuse) {
+            HT(keep(c, &c->kzt_ptr, k + 1));
+            hipLaunchKernelGGL(k_to_i32, dim3(grid_for(k + 1)), dim3(256), 0, s, kzp, (int64_t)k + 1, c->kzt_ptr);
+        }
+        int cf = 0;
+        HT(hipMemcpyAsync(&cf, cfail, sizeof(int), hipMemcpyDeviceToHost, s));
+        HT(hipStreamSynchronize(s));
+        if (cf) return DPCG_ECOARSE_NOT_SPD;
+        return DPCG_OK;
+    }
+}
 
 }  // namespace
 
@@ -1331,9 +1522,14 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(keep(c, &c->bj_meta, n));
     int *bjbad = flags + 1;  // reuse: Z's flag is known to be clear
     hipLaunchKernelGGL(k_bj_small, dim3(grid_for(nblocks)), dim3(256), 0, s, nblocks, bp, kp, kc, kv, moff, c->minv,
-                       c->bj_rowoff, c->bj_meta, bjbad);
+                       c->bj_rowoff, c->bj_meta, bjbad, (const int32_t *)nullptr, 0);
     hipLaunchKernelGGL(k_bj_factor, dim3(std::min<int32_t>(nblocks, 4096)), dim3(64), 0, s, nblocks, bp, kp, kc, kv,
-                       moff, c->minv, c->bj_rowoff, c->bj_meta, bjbad);
+                       moff, c->minv, c->bj_rowoff, c->bj_meta, bjbad, (const int32_t *)nullptr, 0);
+    // kept for value updates: the partition and each block's offset in minv
+    HT(keep(c, &c->block_ptr, nblocks + 1));
+    HT(keep(c, &c->bj_moff, nblocks + 1));
+    HT(hipMemcpyAsync(c->block_ptr, bp, sizeof(int32_t) * (nblocks + 1), hipMemcpyDeviceToDevice, s));
+    HT(hipMemcpyAsync(c->bj_moff, moff, sizeof(int64_t) * (nblocks + 1), hipMemcpyDeviceToDevice, s));
     c->bj_ntiles = (int32_t)((n + kTileDofs - 1) / kTileDofs);
     HT(keep(c, &c->bj_wg_start, c->bj_ntiles + 1));
     hipLaunchKernelGGL(k_tiles, dim3(grid_for(c->bj_ntiles + 1)), dim3(256), 0, s, c->bj_ntiles, nblocks, bp, n,
@@ -1356,150 +1552,12 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     }
     HT(hipGetLastError());
     if (k > 0) {
-        // ---- K Z and E, in batches of kBatch vectors; batch groups bound the scratch ----
-        std::vector<int64_t> wl(k);
-        HT(hipMemcpyAsync(wl.data(), wlo, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
-        HT(hipStreamSynchronize(s));
-        const int nbat = (k + kBatch - 1) / kBatch;
-        const int words = (k + 31) / 32;
-        std::vector<KzBatch> bt(nbat);
-        int64_t slices = 0;
-        for (int bi = 0; bi < nbat; ++bi) {
-            KzBatch &B = bt[bi];
-            B.j0 = (int64_t)bi * kBatch;
-            B.ncol = std::min<int64_t>(kBatch, k - B.j0);
-            int64_t lo = INT64_MAX, hi = -1;
-            for (int64_t j = B.j0; j < B.j0 + B.ncol; ++j)
-                if (ws[j] > 0) {
-                    lo = std::min(lo, wl[j]);
-                    hi = std::max(hi, wl[j] + ws[j]);
-                }
-            B.lo3 = hi > 0 ? lo / 3 : 0;
-            B.w3 = hi > 0 ? (hi + 2) / 3 - B.lo3 : 0;
-            B.nslice = std::max<int64_t>(1, (B.w3 + kSlice - 1) / kSlice);
-            B.slice0 = slices;
-            slices += B.nslice;
-        }
-        // group consecutive batches so that a group's scratch stays under the budget
-        const int64_t per_triplet = 2 * 3 * kBatch * sizeof(double) + 2 * sizeof(uint32_t);
-        const int64_t budget = int64_t(1) << 30;
-        std::vector<int> gcut{0};
-        int64_t acc_w = 0, max_group_w = 0;
-        int max_group_nb = 0;
-        for (int bi = 0; bi < nbat; ++bi) {
-            if (acc_w > 0 && (acc_w + bt[bi].w3) * per_triplet > budget) {
-                gcut.push_back(bi);
-                acc_w = 0;
-            }
-            bt[bi].off3 = acc_w;
-            bt[bi].bit0 = (int64_t)(bi - gcut.back()) * words;
-            acc_w += bt[bi].w3;
-            max_group_w = std::max(max_group_w, acc_w);
-            max_group_nb = std::max(max_group_nb, bi - gcut.back() + 1);
-        }
-        gcut.push_back(nbat);
-        KzBatch *bt_d = nullptr;
-        int32_t *scnt = nullptr, *soff = nullptr;
-        int64_t *kzcnt = nullptr, *kzp = nullptr;
-        double *zd = nullptr, *kd = nullptr;
-        uint32_t *mk = nullptr, *rbits = nullptr, *touched = nullptr;
-        HT(pool.tmp(&bt_d, nbat));
-        HT(hipMemcpyAsync(bt_d, bt.data(), sizeof(KzBatch) * nbat, hipMemcpyHostToDevice, s));
-        HT(pool.tmp(&scnt, slices * kBatch));
-        HT(pool.tmp(&soff, slices * kBatch));
-        HT(pool.tmp(&kzcnt, k));
-        HT(pool.tmp(&kzp, k + 1));
-        HT(pool.tmp(&zd, 3 * max_group_w * kBatch));
-        HT(pool.tmp(&kd, 3 * max_group_w * kBatch));
-        HT(pool.tmp(&mk, max_group_w));
-        HT(pool.tmp(&rbits, max_group_w));
-        HT(pool.tmp(&touched, (int64_t)max_group_nb * words));
-        int32_t *icnt = nullptr;
-        int64_t *nitems = nullptr;
-        KzItem *items = nullptr;
-        HT(pool.tmp(&icnt, slices));
-        HT(pool.tmp(&nitems, nbat));
-        HT(pool.tmp(&items, max_group_w));
-        auto max_slices = [&](int g0, int g1) {
-            int64_t m = 1;
-            for (int bi = g0; bi < g1; ++bi) m = std::max(m, bt[bi].nslice);
-            return (int)m;
-        };
-        auto prepare = [&](int g0, int g1) {
-            const dim3 gs(max_slices(g0, g1), g1 - g0);
-            hipLaunchKernelGGL(k_kzb_init, gs, dim3(256), 0, s, bt_d + g0, words, mk, rbits, touched);
-            hipLaunchKernelGGL(k_kzb_scatter, dim3(kBatch, g1 - g0), dim3(256), 0, s, bt_d + g0, ztp, zti, ztv, zd,
-                               rbits);
-            hipLaunchKernelGGL(k_kzb_mark, gs, dim3(256), 0, s, bt_d + g0, c->brow_ptr, c->bcol, rbits, mk);
-        };
-        for (size_t g = 0; g + 1 < gcut.size(); ++g) {
-            prepare(gcut[g], gcut[g + 1]);
-            hipLaunchKernelGGL(k_kzb_count, dim3(max_slices(gcut[g], gcut[g + 1]), gcut[g + 1] - gcut[g]), dim3(256),
-                               0, s, bt_d + gcut[g], mk, scnt);
-        }
-        hipLaunchKernelGGL(k_kzb_offsets, dim3(nbat), dim3(kBatch), 0, s, bt_d, nbat, scnt, soff, kzcnt);
-        HT(scan(s, kzcnt, k, kzp, part));
-        int64_t nkz = 0;
-        HT(hipMemcpyAsync(&nkz, kzp + k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
-        HT(hipStreamSynchronize(s));
-        if (fl[3] != INT32_MAX) return DPCG_ENOTSYM;
-        if (fl[1] != INT32_MAX) {
-            *bad = fl[1];
-            return DPCG_EBLOCK_NOT_SPD;
-        }
-        if (nkz > (int64_t)INT32_MAX) return DPCG_EINVAL;
-        c->nnz_kz = nkz;
-        HT(keep(c, &c->kzt_idx, nkz));
-        HT(keep(c, &c->kzt_val, nkz));
-        const int64_t ld = ((int64_t)k + kNb - 1) / kNb * kNb;
-        c->einv_ld = ld;
-        double *eraw = nullptr, *ga = nullptr, *diag0 = nullptr, *pv = nullptr;
-        HT(pool.tmp(&eraw, ld * ld));
-        HT(hipMemsetAsync(eraw, 0, sizeof(double) * ld * ld, s));
-        for (size_t g = 0; g + 1 < gcut.size(); ++g) {
-            const int g0 = gcut[g], g1 = gcut[g + 1];
-            if (gcut.size() > 2) prepare(g0, g1);  // one group: the count pass left it ready
-            hipLaunchKernelGGL(k_kzb_items, dim3(g1 - g0), dim3(256), 0, s, bt_d + g0, g1 - g0, mk, icnt,
-                               nitems + g0);
-            hipLaunchKernelGGL(k_kzb_rank, dim3(max_slices(g0, g1), g1 - g0), dim3(256), 0, s, bt_d + g0, mk, soff,
-                               icnt, kzp, items);
-            hipLaunchKernelGGL(k_kzb_values, dim3(128, g1 - g0), dim3(256),
-                               0, s, bt_d + g0, nitems + g0, items, c->brow_ptr, c->bcol, c->bval, zd, rbits, zp, zc,
-                               c->kzt_idx, c->kzt_val, kd, words, touched);
-            hipLaunchKernelGGL(k_kzb_erows, dim3((k + 3) / 4, g1 - g0), dim3(256), 0, s, bt_d + g0, k, ztp, zti, ztv,
-                               kd, mk, touched, eraw, ld);
-        }
-        HT(hipGetLastError());
-        // ---- E^-1 ----
-        HT(pool.tmp(&ga, ld * ld));
-        HT(keep(c, &c->einv, ld * ld));
-        HT(pool.tmp(&diag0, ld));
-        HT(pool.tmp(&pv, 2 * kNb * kNb));
-        hipLaunchKernelGGL(k_symmetrise, dim3(grid_for(ld * ld)), dim3(256), 0, s, k, ld, eraw, ga, diag0);
-        int *cfail = flags + 2;
-        HT(hipMemsetAsync(cfail, 0, sizeof(int), s));
-        hipLaunchKernelGGL(k_gj_first_pivot, dim3(1), dim3(256), 0, s, ga, ld, k, diag0, pv, cfail);
-        const int nt = (int)(ld / kNb);
-        double *src = ga, *dst = c->einv;
-        if (nt % 2 == 0) std::swap(src, dst);  // the last sweep must land in c->einv
-        if (nt % 2 == 0)
-            HT(hipMemcpyAsync(src, ga, sizeof(double) * ld * ld, hipMemcpyDeviceToDevice, s));
-        for (int p = 0; p < nt; ++p) {
-            hipLaunchKernelGGL(k_gj_sweep, dim3(nt * nt), dim3(256), 0, s, p, nt, src, dst, ld, k,
-                               pv + (p & 1) * kNb * kNb, pv + ((p + 1) & 1) * kNb * kNb, diag0, cfail);
-            std::swap(src, dst);
-        }
-        HT(hipGetLastError());
+        const int st = coarse_operator(c, pool, k, zp, zc, ztp, zti, ztv, wlo, ws, part, flags, bad, false);
+        if (st != DPCG_OK) return st;
         // transposed pointers as int32
         HT(keep(c, &c->zt_ptr, k + 1));
-        HT(keep(c, &c->kzt_ptr, k + 1));
         hipLaunchKernelGGL(k_to_i32, dim3(grid_for(k + 1)), dim3(256), 0, s, ztp, (int64_t)k + 1, c->zt_ptr);
-        hipLaunchKernelGGL(k_to_i32, dim3(grid_for(k + 1)), dim3(256), 0, s, kzp, (int64_t)k + 1, c->kzt_ptr);
-        int cf = 0;
-        HT(hipMemcpyAsync(&cf, cfail, sizeof(int), hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
-        if (cf) return DPCG_ECOARSE_NOT_SPD;
     } else {
         HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
@@ -1509,6 +1567,119 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
             return DPCG_EBLOCK_NOT_SPD;
         }
     }
+    return DPCG_OK;
+}
+
+// New values of K on the same sparsity pattern: block values, the symmetry test, the
+// inverses of the listed blocks (all when list is null), K Z, E and E^-1 again.
+int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const double *kv, int32_t nlist,
+                      const int32_t *list_host, int64_t *bad) {
+    hipStream_t s = c->stream;
+    Pool pool{c, {}};
+    const int64_t n = c->n;
+    const int32_t nb = c->nb, k = c->k, nblocks = c->nblocks;
+    if (list_host)
+        for (int32_t i = 0; i < nlist; ++i)
+            if (list_host[i] < 0 || list_host[i] >= nblocks) return DPCG_EINVAL;
+    int64_t ends[2] = {0, 0};
+    HT(hipMemcpyAsync(&ends[0], kp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HT(hipMemcpyAsync(&ends[1], kp + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HT(hipStreamSynchronize(s));
+    if (ends[0] != 0 || ends[1] != c->nnz) return DPCG_EINVAL;
+    const int64_t nnz = c->nnz, nnzb = c->nnzb;
+    int *flags = nullptr;
+    HT(pool.tmp(&flags, 4));
+    const int init_flags[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+    HT(hipMemcpyAsync(flags, init_flags, sizeof(init_flags), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, 4)), dim3(256), 0, s, n, n, kp, kc, kv, nnz, flags);
+    int fl[4];
+    HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    HT(hipStreamSynchronize(s));
+    if (fl[0] != INT32_MAX) return DPCG_EINVAL;
+    // the CSR arrays are valid: the block structure must be the stored one
+    int64_t *cnt = nullptr;
+    HT(pool.tmp(&cnt, nb));
+    hipLaunchKernelGGL((k_bsr<false>), dim3(grid_for(nb, 4)), dim3(256), 0, s, nb, kp, kc, kv, cnt, nullptr, nullptr,
+                       nullptr, nullptr);
+    hipLaunchKernelGGL(k_cmp_counts, dim3(grid_for(nb)), dim3(256), 0, s, nb, cnt, c->brow_ptr, flags + 2);
+    HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    HT(hipStreamSynchronize(s));
+    if (fl[2] != INT32_MAX) return DPCG_EINVAL;
+    // max |K| for the symmetry tolerance
+    const int nmx = grid_for(nnz, 256, 1024);
+    double *mxp = nullptr;
+    HT(pool.tmp(&mxp, nmx));
+    hipLaunchKernelGGL(k_maxabs_part, dim3(nmx), dim3(256), 0, s, kv, nnz, mxp);
+    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, mxp, nmx);
+    // block values; the block columns must be the stored ones
+    int32_t *bcol2 = nullptr, *brow = nullptr;
+    HT(pool.tmp(&bcol2, nnzb));
+    HT(pool.tmp(&brow, nnzb));
+    HT(hipMemsetAsync(c->bval, 0, sizeof(double) * 9 * (size_t)nnzb, s));
+    hipLaunchKernelGGL((k_bsr<true>), dim3(grid_for(nb, 4)), dim3(256), 0, s, nb, kp, kc, kv, nullptr, c->brow_ptr,
+                       bcol2, c->bval, brow);
+    hipLaunchKernelGGL(k_cmp_i32, dim3(grid_for(nnzb)), dim3(256), 0, s, nnzb, bcol2, c->bcol, flags + 2);
+    {
+        const int gsym = (grid_for(nnzb, 256, 16384) + 7) / 8 * 8;
+        int64_t *sympart = nullptr;
+        int *need = nullptr;
+        HT(pool.tmp(&sympart, 2 * (int64_t)gsym));
+        HT(pool.tmp(&need, 1));
+        hipLaunchKernelGGL(k_check_sym, dim3(gsym), dim3(256), 0, s, c->brow_ptr, brow, c->bcol, c->bval, nnzb, mxp,
+                           1, flags, sympart);
+        hipLaunchKernelGGL(k_sym_reduce, dim3(1), dim3(256), 0, s, sympart, gsym, need);
+        hipLaunchKernelGGL(k_check_sym_lower, dim3(gsym), dim3(256), 0, s, c->brow_ptr, brow, c->bcol, c->bval, nnzb,
+                           mxp, 1, flags, need);
+    }
+    // block-Jacobi inverses of the listed blocks
+    int32_t *list_d = nullptr;
+    if (list_host && nlist > 0) {
+        HT(pool.tmp(&list_d, nlist));
+        HT(hipMemcpyAsync(list_d, list_host, sizeof(int32_t) * nlist, hipMemcpyHostToDevice, s));
+    }
+    if (!list_host || nlist > 0) {
+        const int32_t count = list_host ? nlist : nblocks;
+        hipLaunchKernelGGL(k_bj_small, dim3(grid_for(count)), dim3(256), 0, s, nblocks, c->block_ptr, kp, kc, kv,
+                           c->bj_moff, c->minv, c->bj_rowoff, c->bj_meta, flags + 1, (const int32_t *)list_d, nlist);
+        hipLaunchKernelGGL(k_bj_factor, dim3(std::min<int32_t>(std::max(count, 1), 4096)), dim3(64), 0, s, nblocks,
+                           c->block_ptr, kp, kc, kv, c->bj_moff, c->minv, c->bj_rowoff, c->bj_meta, flags + 1,
+                           (const int32_t *)list_d, nlist);
+    }
+    HT(hipGetLastError());
+    HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    HT(hipStreamSynchronize(s));
+    if (fl[2] != INT32_MAX) return DPCG_EINVAL;
+    if (k > 0) {
+        int64_t *ztp = nullptr, *zp = nullptr, *wlo = nullptr, *wsize = nullptr, *part = nullptr;
+        HT(pool.tmp(&ztp, k + 1));
+        HT(pool.tmp(&zp, n + 1));
+        HT(pool.tmp(&wlo, k));
+        HT(pool.tmp(&wsize, k));
+        HT(pool.tmp(&part, (int64_t)k / kScanChunk + 2));
+        hipLaunchKernelGGL(k_to_i64, dim3(grid_for(k + 1)), dim3(256), 0, s, c->zt_ptr, (int64_t)k + 1, ztp);
+        hipLaunchKernelGGL(k_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, c->z_ptr, n + 1, zp);
+        hipLaunchKernelGGL(k_kz_window, dim3(k), dim3(256), 0, s, k, ztp, c->zt_idx, kp, kc, wlo, wsize);
+        std::vector<int64_t> ws(k);
+        HT(hipMemcpyAsync(ws.data(), wsize, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+        HT(hipStreamSynchronize(s));
+        const int st = coarse_operator(c, pool, k, zp, c->z_col, ztp, c->zt_idx, c->zt_val, wlo, ws, part, flags, bad,
+                                       true);
+        if (st != DPCG_OK) return st;
+    } else {
+        if (fl[3] != INT32_MAX) return DPCG_ENOTSYM;
+        if (fl[1] != INT32_MAX) {
+            *bad = fl[1];
+            return DPCG_EBLOCK_NOT_SPD;
+        }
+    }
+    // binary32 copies of a handle that has run mixed solves
+    if (c->bval32) {
+        hipLaunchKernelGGL(k_to_f32_s, dim3(grid_for(9 * nnzb, 256, 8192)), dim3(256), 0, s, c->bval, 9 * nnzb, c->bval32);
+        hipLaunchKernelGGL(k_to_f32_s, dim3(grid_for(c->bj_values, 256, 8192)), dim3(256), 0, s, c->minv,
+                           c->bj_values, c->minv32);
+    }
+    HT(hipGetLastError());
+    HT(hipStreamSynchronize(s));
     return DPCG_OK;
 }
 
