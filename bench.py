@@ -31,11 +31,11 @@ HBM_PEAK_GBS = 8000.0
 SPMV_TRAFFIC = {
     "workload": "penny40",
     "sources": {
-        "paper_2111_09294_amd/csrc/kernels.hip": "97f84f3dcc1f3e56df07e878b14038696db95425a7a7f3d15de1e055b1b7bbbd",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "73ecba349c5ac160fba2ea8f79bf70f3ab11dd2f8107845f592b4364ab16d1e9"
+        "paper_2111_09294_amd/csrc/kernels.hip": "7b786c6f6cf8f44abdaf114b32ab4815a0357efb1e45502e6e263c0dea7c4bb1",
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "33065377bea269dc4e76ccbeec9b62af5ac2ade8f14c450337a14f7594445b05"
     },
-    "fetch_bytes": 171117023,
-    "write_bytes": 2029880,
+    "fetch_bytes": 171097547,
+    "write_bytes": 2028798,
 }
 
 
