@@ -133,3 +133,48 @@ def uneven_systems(count: int = 16, seed: int = 16, ne_range=(20, 48), r_e: floa
         crack = CurvedPennyCrack(center=centre, R=0.25, curv=0.3)
         out.append(build_problem(f"uneven{i}", ne, 1 + ne // 12, crack=crack, r_e=r_e))
     return out
+
+
+def subdomain_order(bx: XfemBox, nsd: int):
+    """DoF permutation that numbers the unknowns subdomain by subdomain (nsd^3 boxes of
+    nodes, XfemBox.subdomain_of_nodes; a node's DoFs stay together and in order) and the
+    block partition with one block per non-empty subdomain: the subdomain-sized
+    block-Jacobi blocks of Sec. 3.4.  Returns (perm int64, block_ptr int32) with new
+    unknown i = old unknown perm[i]."""
+    sd = bx.subdomain_of_nodes(nsd)
+    nodes = np.nonzero(bx.ngroups > 0)[0]
+    order = nodes[np.argsort(sd[nodes], kind="stable")]
+    starts = 3 * bx.trip_start[order]
+    lens = 3 * bx.ngroups[order]
+    offs = np.zeros(len(order) + 1, np.int64)
+    np.cumsum(lens, out=offs[1:])
+    perm = np.repeat(starts - offs[:-1], lens) + np.arange(offs[-1])
+    sizes = np.bincount(sd[order], weights=lens, minlength=nsd ** 3).astype(np.int64)
+    sizes = sizes[sizes > 0]
+    bp = np.zeros(len(sizes) + 1, np.int64)
+    np.cumsum(sizes, out=bp[1:])
+    return perm.astype(np.int64), bp.astype(np.int32)
+
+
+def permuted(p: Problem, perm, block_ptr, name=None) -> Problem:
+    """P K P^T, P f, P Z for the permutation perm (new i = old perm[i]) with a new block
+    partition; columns sorted in every row."""
+    K = p.K_scipy()[perm][:, perm].tocsr()
+    K.sort_indices()
+    Z = p.Z_scipy()[perm].tocsr()
+    Z.sort_indices()
+    meta = dict(p.meta)
+    meta["perm"] = "subdomain"
+    return Problem(name=name or p.name, n=p.n, k_rowptr=K.indptr.astype(np.int64), k_col=K.indices.astype(np.int32),
+                   k_val=K.data.astype(np.float64), f=np.ascontiguousarray(p.f[perm]),
+                   z_rowptr=Z.indptr.astype(np.int64), z_col=Z.indices.astype(np.int32),
+                   z_val=Z.data.astype(np.float64), k=p.k, block_ptr=np.asarray(block_ptr, np.int32), meta=meta)
+
+
+def with_subdomain_blocks(name: str, nsd: int, p: Problem | None = None):
+    """The named workload (or p, a problem on the same mesh) renumbered subdomain by
+    subdomain with one block-Jacobi block per subdomain of an nsd^3 box partition.
+    Returns (problem, perm)."""
+    p = load(name) if p is None else p
+    perm, bp = subdomain_order(box(name), nsd)
+    return permuted(p, perm, bp, name=f"{name}-sd{nsd}"), perm

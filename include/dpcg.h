@@ -79,8 +79,10 @@ typedef struct {
     int64_t nnz_z;             /* nonzeros of Z                                         */
     int64_t nnz_kz;            /* nonzeros of K Z                                       */
     int64_t nblocks;           /* block-Jacobi blocks                                   */
-    int64_t bj_values;         /* sum of squared block sizes (stored inverse entries)   */
+    int64_t bj_values;         /* sum of squared sizes of the blocks of <= 18 unknowns  */
     int64_t device_bytes;      /* device memory held by the handle                      */
+    int64_t dense_blocks;      /* blocks of more than 18 unknowns                       */
+    int64_t dense_values;      /* entries of their stored inverses (sum of ld^2)        */
 } dpcg_stats;
 
 typedef struct {
@@ -105,8 +107,14 @@ void dpcg_default_options(dpcg_options *opt);
  *       block-Jacobi PCG).  Z must have full column rank.
  *   block_ptr[nblocks+1] (int32): the block-Jacobi groups (eq. block_jacobi) as
  *       contiguous ranges [block_ptr[b], block_ptr[b+1]) tiling [0, n), each of
- *       1..18 unknowns (one node's standard plus enriched DoFs, eq.
- *       block_jacobi_enr).
+ *       1..8192 unknowns.  Blocks of up to 18 unknowns (one node's standard plus
+ *       enriched DoFs, eq. block_jacobi_enr) share the fused small-block kernels.
+ *       Larger blocks (the subdomain-sized blocks of Sec. 3.4: all unknowns of
+ *       one subdomain, numbered consecutively) keep an explicit FP64 inverse of
+ *       ld x ld entries, ld = 32 * ceil(size / 32), made by Gauss-Jordan sweeps
+ *       at setup and applied by a dense matrix-vector kernel each iteration;
+ *       dpcg_solve_batch and dpcg_solve_many refuse handles with such blocks
+ *       (DPCG_EINVAL).
  *   stream: hipStream_t (may be NULL for the default stream) on which all of the
  *       handle's work is ordered.
  *

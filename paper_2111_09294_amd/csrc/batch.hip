@@ -682,7 +682,7 @@ int solve_batch(dpcg_ctx *c, int32_t nrhs, const double *F, double *U, double to
     dpcg_default_options(&opt);
     if (opt_in) opt = *opt_in;
     if (!c || nrhs < 1 || nrhs > W || !F || !U || !(tol > 0.0) || opt.max_iter < 0) return DPCG_EINVAL;
-    if (opt.precision != DPCG_PREC_FP64 || opt.record_history) return DPCG_EINVAL;
+    if (opt.precision != DPCG_PREC_FP64 || opt.record_history || c->ndense > 0) return DPCG_EINVAL;
     if (opt.check_every <= 0) opt.check_every = 16;
     const bool guess = opt.use_initial_guess != 0;
     BTRY(ensure_ws(c));

@@ -313,13 +313,18 @@ int true_residual(dpcg_ctx *c, Workspace &w, const double *f, const double *u, d
 // binary32 copies of K's block values and of the block inverses (same layouts)
 int ensure_fp32(dpcg_ctx *c) {
     if (c->bval32) return DPCG_OK;
-    float *bv = nullptr, *mi = nullptr;
+    float *bv = nullptr, *mi = nullptr, *di = nullptr;
     TRY(alloc(c, &bv, 9 * (size_t)c->nnzb));
     TRY(alloc(c, &mi, (size_t)std::max<int64_t>(1, c->bj_values)));
+    if (c->ndense > 0) {
+        TRY(alloc(c, &di, (size_t)c->dinv_len));
+        LAUNCH(launch_to_f32(c, c->dinv, c->dinv_len, di));
+    }
     LAUNCH(launch_to_f32(c, c->bval, 9 * c->nnzb, bv));
     LAUNCH(launch_to_f32(c, c->minv, c->bj_values, mi));
     c->bval32 = bv;
     c->minv32 = mi;
+    c->dinv32 = di;
     return DPCG_OK;
 }
 
@@ -481,7 +486,7 @@ int solve_many_impl(dpcg_handle *hs, int32_t count, const double *const *F, doub
     if (opt.check_every <= 0) opt.check_every = 16;
     const bool guess = opt.use_initial_guess != 0;
     for (int i = 0; i < count; ++i) {
-        if (!hs[i] || !F[i] || !U[i] || hs[i]->device != hs[0]->device) return DPCG_EINVAL;
+        if (!hs[i] || !F[i] || !U[i] || hs[i]->device != hs[0]->device || hs[i]->ndense > 0) return DPCG_EINVAL;
         for (int j = 0; j < i; ++j)
             if (hs[j] == hs[i]) return DPCG_EINVAL;  // one workspace per system
     }
@@ -788,6 +793,8 @@ int dpcg_get_stats(dpcg_handle h, dpcg_stats *out) {
     out->nblocks = h->nblocks;
     out->bj_values = h->bj_values;
     out->device_bytes = h->device_bytes;
+    out->dense_blocks = h->ndense;
+    out->dense_values = h->dinv_len;
     return DPCG_OK;
 }
 

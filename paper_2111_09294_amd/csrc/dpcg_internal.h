@@ -7,10 +7,13 @@
 //       entry e = 3*i + j of block b sits at bval[9 beg + e*m + (b - beg)], so the
 //       lanes working on consecutive blocks of a row read consecutive words and a
 //       row's values form one contiguous stretch.
-//   M^-1 explicit inverse of each block-Jacobi block, row-major, concatenated;
-//       per DoF d: bj_rowoff[d] = offset of d's row, bj_meta[d] = size<<8 | (d -
-//       block start).  DoF range of workgroup w of the update kernel:
-//       [bj_wg_start[w], bj_wg_start[w+1]) holds whole blocks only.
+//   M^-1 explicit inverse of each block-Jacobi block of up to kMaxBlock DoFs,
+//       row-major, concatenated; per DoF d: bj_rowoff[d] = offset of d's row,
+//       bj_meta[d] = size<<8 | (d - block start), 0 for the DoFs of larger blocks.
+//       Tile w of the update kernel, [bj_wg_start[w], bj_wg_start[w+1]), holds whole
+//       small blocks (a tile may cut a large block).  Blocks of kMaxBlock+1 ..
+//       kMaxDense DoFs ("dense blocks", subdomain-sized) keep their inverse in dinv:
+//       ld x ld row-major, ld = 32 * ceil(size / 32), zero beyond size.
 //   Z   CSR by rows (prolongation), Z^T and (KZ)^T as CSR with k rows
 //       (restriction), E^-1 dense row-major with leading dimension einv_ld.
 #pragma once
@@ -25,7 +28,9 @@
 namespace dpcg {
 
 constexpr int kThreads = 256;     // threads per workgroup everywhere
-constexpr int kMaxBlock = 18;     // largest block-Jacobi block
+constexpr int kMaxBlock = 18;     // largest block-Jacobi block of the fused (nodal) path
+constexpr int kMaxDense = 8192;   // largest block-Jacobi block (dense path above kMaxBlock)
+constexpr int kDenseRows = 32;    // rows of a dense block per workgroup of its apply
 constexpr int kMaxElemDofs = 256; // largest element (DoFs) of dpcg_element_gradient
 constexpr int kBatchCols = 32;    // columns of the multi-RHS workspace (right-hand sides per batch)
 constexpr int kBatchSegEntries = 2048;  // entries per multi-RHS restriction segment
@@ -109,6 +114,15 @@ struct BatchWorkspace {
     int32_t nseg = 0;
 };
 
+// A block-Jacobi block of more than kMaxBlock DoFs and a workgroup of its apply.
+struct DenseBlk {
+    int64_t off;                    // first entry of its inverse in dinv
+    int32_t start, size, ld, block; // first DoF, DoFs, leading dimension, block index
+};
+struct DenseChunk {
+    int32_t dense, row0;            // index in the dense table, first row
+};
+
 // Several systems per launch: one descriptor per system (its operator, its forward
 // workspace and its state) and, per phase, the prefix offsets of the systems'
 // workgroups in the launch grid.
@@ -169,6 +183,14 @@ struct dpcg_ctx {
     int32_t *block_ptr = nullptr;   // the block partition (nblocks + 1), kept for value updates
     int64_t *bj_moff = nullptr;     // offset of each block's inverse in minv (nblocks + 1)
     int32_t bjb_ntiles = 0;
+    // dense (subdomain-sized) blocks, in increasing block order
+    int32_t ndense = 0, ndchunks = 0, dense_maxld = 0;
+    std::vector<dpcg::DenseBlk> dense_h;
+    dpcg::DenseBlk *dense = nullptr;
+    dpcg::DenseChunk *dchunk = nullptr;
+    double *dinv = nullptr;
+    float *dinv32 = nullptr;
+    int64_t dinv_len = 0;
     dpcg::BatchWorkspace *bws = nullptr;  // multi-RHS workspace, made on the first batched solve
     // deflation
     int32_t *z_ptr = nullptr, *z_col = nullptr;
@@ -207,6 +229,7 @@ hipError_t launch_spmv_p(const dpcg_ctx *c, Workspace &w, hipEvent_t ev0, hipEve
 hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w);
 hipError_t launch_beta(const dpcg_ctx *c, Workspace &w);
 hipError_t launch_bj(const dpcg_ctx *c, const double *r, double *y, Workspace *w);
+hipError_t launch_bj_dense(const dpcg_ctx *c, const double *r, double *y, const State *st);
 hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, double *g, Workspace *w,
                            int check, int n_parts, int iter_offset, int max_iter, int record);
 hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Workspace *w);

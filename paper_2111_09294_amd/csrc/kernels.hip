@@ -381,6 +381,63 @@ __global__ __launch_bounds__(kThreads) void k_bj(int32_t ntiles, int32_t nwg, co
 }
 
 
+// y_B = M_B^-1 r_B for the blocks of more than kMaxBlock DoFs (Algorithm 3's block
+// solve with the explicit inverse of a subdomain-sized block).  A workgroup owns
+// kDenseRows consecutive rows of one block: r_B is staged in LDS (zero from the
+// block's size up to ld), each wave takes 8 rows and every lane reads 16-byte pieces of
+// all 8 rows per step, so a wave keeps 8 row streams in flight.  The row sums are
+// reduced across the wave in a fixed order.
+template <class M> struct DensePiece;
+template <> struct DensePiece<double> { static constexpr int W = 2; using T = double2; };
+template <> struct DensePiece<float> { static constexpr int W = 4; using T = float4; };
+
+__device__ __forceinline__ double piece_dot(const double2 &a, const double *x) {
+    return fma(a.y, x[1], a.x * x[0]);
+}
+__device__ __forceinline__ double piece_dot(const float4 &a, const double *x) {
+    return fma((double)a.w, x[3], fma((double)a.z, x[2], fma((double)a.y, x[1], (double)a.x * x[0])));
+}
+
+template <class M>
+__global__ __launch_bounds__(kThreads) void k_bj_dense(const DenseBlk *__restrict__ blk,
+                                                       const DenseChunk *__restrict__ chunk,
+                                                       const double *__restrict__ r, double *__restrict__ y,
+                                                       const M *__restrict__ dinv, const State *st) {
+    constexpr int W = DensePiece<M>::W;
+    constexpr int R = kDenseRows / 4;  // rows per wave
+    using T = typename DensePiece<M>::T;
+    extern __shared__ double rb[];  // ld of the largest dense block
+    if (st && st->flag != kRunning) return;
+    const DenseChunk ch = chunk[xcd_remap(blockIdx.x, gridDim.x)];
+    const DenseBlk B = blk[ch.dense];
+    for (int j = threadIdx.x; j < B.ld; j += kThreads) rb[j] = j < B.size ? r[B.start + j] : 0.0;
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i0 = ch.row0 + wave * R;
+    const int nr = min(R, B.size - i0);
+    if (nr <= 0) return;
+    const M *base = dinv + B.off + (int64_t)i0 * B.ld;
+    double acc[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q] = 0.0;
+    for (int j = W * lane; j < B.ld; j += 64 * W) {
+        T v[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (q < nr) v[q] = *reinterpret_cast<const T *>(base + (int64_t)q * B.ld + j);
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (q < nr) acc[q] += piece_dot(v[q], rb + j);
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        double a = acc[q];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        if (lane == 0 && q < nr) y[B.start + i0 + q] = a;
+    }
+}
+
 // Convergence test (workgroup 0 only) and g_j = Z^T a - (K Z)^T b, one column per
 // workgroup of kRestrictThreads threads, four independent chains per thread.
 constexpr int kRestrictWaves = 8;
@@ -782,7 +839,9 @@ hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w) {
                            c->bj_nwg, c->bj_wg_start, u, w.r, w.y, (const double *)w.q, (const double *)w.p[0],
                            (const double *)w.p[1], (const double *)c->minv, c->bj_rowoff, c->bj_meta, w.part_b,
                            (const State *)w.st);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_bj_dense(c, w.r, w.y, w.st);
 }
 
 hipError_t launch_beta(const dpcg_ctx *c, Workspace &w) {
@@ -799,6 +858,21 @@ hipError_t launch_bj(const dpcg_ctx *c, const double *r, double *y, Workspace *w
     else
         hipLaunchKernelGGL(k_bj<double>, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles, c->bj_nwg,
                            c->bj_wg_start, r, y, (const double *)c->minv, c->bj_rowoff, c->bj_meta, st);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_bj_dense(c, r, y, st);
+}
+
+// the dense blocks' part of y = M^-1 r, after the small blocks' kernel on the same stream
+hipError_t launch_bj_dense(const dpcg_ctx *c, const double *r, double *y, const State *st) {
+    if (c->ndense == 0) return hipSuccess;
+    const size_t lds = sizeof(double) * (size_t)c->dense_maxld;
+    if (c->inner32)
+        hipLaunchKernelGGL(k_bj_dense<float>, dim3(c->ndchunks), dim3(kThreads), lds, c->stream, c->dense, c->dchunk,
+                           r, y, (const float *)c->dinv32, st);
+    else
+        hipLaunchKernelGGL(k_bj_dense<double>, dim3(c->ndchunks), dim3(kThreads), lds, c->stream, c->dense, c->dchunk,
+                           r, y, (const double *)c->dinv, st);
     return hipGetLastError();
 }
 

@@ -129,12 +129,18 @@ __global__ __launch_bounds__(256) void k_check_csr(int64_t rows, int64_t cols, c
     }
 }
 
-__global__ void k_check_blocks(int32_t nblocks, const int32_t *__restrict__ bp, int64_t n, int *flag) {
+// flag = first invalid block; maxsize = size of the largest block
+__global__ void k_check_blocks(int32_t nblocks, const int32_t *__restrict__ bp, int64_t n, int *flag, int *maxsize) {
+    int big = 0;
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nblocks; b += gridDim.x * blockDim.x) {
         const int64_t s = bp[b], e = bp[b + 1];
-        bool ok = (b != 0 || s == 0) && (b != nblocks - 1 || e == n) && e - s >= 1 && e - s <= kMaxBlock;
+        bool ok = (b != 0 || s == 0) && (b != nblocks - 1 || e == n) && e - s >= 1 && e - s <= kMaxDense;
         if (!ok) atomicMin(flag, b);
+        else big = max(big, (int)(e - s));
     }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) big = max(big, __shfl_xor(big, off));
+    if ((threadIdx.x & 63) == 0 && big > kMaxBlock) atomicMax(maxsize, big);
 }
 
 __global__ __launch_bounds__(256) void k_maxabs_part(const double *__restrict__ v, int64_t m,
@@ -370,7 +376,7 @@ __global__ __launch_bounds__(256) void k_bsr(int32_t nb, const int64_t *__restri
 __global__ void k_block_sq(int32_t nblocks, const int32_t *__restrict__ bp, int64_t *__restrict__ sq) {
     for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nblocks; b += gridDim.x * blockDim.x) {
         const int64_t m = bp[b + 1] - bp[b];
-        sq[b] = m * m;
+        sq[b] = m <= kMaxBlock ? m * m : 0;  // larger blocks keep dense inverses of their own
     }
 }
 
@@ -488,7 +494,7 @@ __global__ __launch_bounds__(64) void k_bj_factor(int32_t nblocks, const int32_t
         const int b = list ? list[ib] : ib;
         const int32_t s = bp[b];
         const int m = bp[b + 1] - s;
-        if (m <= kSmallBlock) continue;
+        if (m <= kSmallBlock || m > kMaxBlock) continue;
         __syncthreads();
         for (int t = lane; t < m * m; t += 64) A[t] = 0.0;
         if (lane == 0) fail = 0;
@@ -563,7 +569,9 @@ __global__ __launch_bounds__(64) void k_bj_factor(int32_t nblocks, const int32_t
     }
 }
 
-// tile t = blocks starting in [t * window, (t+1) * window); start = first such block.
+// tile t = blocks starting in [t * window, (t+1) * window); start = first such block,
+// or t * window itself when that DoF lies inside a block of more than kMaxBlock DoFs
+// (their rows need no neighbours in the tile), so a tile holds < window + kMaxBlock DoFs.
 __global__ void k_tiles(int32_t ntiles, int32_t nblocks, const int32_t *__restrict__ bp, int64_t n,
                         int32_t window, int32_t *__restrict__ tile_start) {
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t <= ntiles; t += gridDim.x * blockDim.x) {
@@ -578,7 +586,8 @@ __global__ void k_tiles(int32_t ntiles, int32_t nblocks, const int32_t *__restri
             if (bp[mid] < target) lo = mid + 1;
             else hi = mid;
         }
-        tile_start[t] = lo < nblocks ? bp[lo] : (int32_t)n;
+        if (lo > 0 && bp[lo - 1] < target && bp[lo] - bp[lo - 1] > kMaxBlock) tile_start[t] = (int32_t)target;
+        else tile_start[t] = lo < nblocks ? bp[lo] : (int32_t)n;
     }
 }
 
@@ -1033,9 +1042,10 @@ __global__ void k_symmetrise(int32_t k, int64_t ld, const double *__restrict__ e
 //   a_rc -= a_rk a_kc / p (r, c != k),  a_kc /= p,  a_rk = -a_rk / p,  a_kk = 1 / p.
 // Thread (ty, tx) of the 256 keeps a[ty + 8q][tx], q < 4, in registers; only row k and
 // column k travel through LDS (W, ping-pong by step parity), one barrier per step.
-// Every pivot is tested against kdim * DBL_EPSILON times the original diagonal entry.
+// Every pivot is tested against kdim * DBL_EPSILON times the original diagonal entry;
+// a failure sets *fail to 1 (failval < 0) or lowers it to failval.
 __device__ void pivot_inverse(const double *S, double *W, const double *diag0, int64_t gcol0, int32_t kdim, double *P,
-                              int *fail) {
+                              int *fail, int failval) {
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     double *rowk = W, *colk = W + 2 * kNb;  // [parity][32] each
     // thread j tests pivot j; its floor is loaded before the first barrier
@@ -1073,7 +1083,10 @@ __device__ void pivot_inverse(const double *S, double *W, const double *diag0, i
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) P[(ty + 8 * q) * kNb + tx] = a[q];
-    if (bad) atomicOr(fail, 1);
+    if (bad) {
+        if (failval < 0) atomicOr(fail, 1);
+        else atomicMin(fail, failval);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_gj_first_pivot(const double *__restrict__ A, int64_t ld, int32_t kdim,
@@ -1082,7 +1095,7 @@ __global__ __launch_bounds__(256) void k_gj_first_pivot(const double *__restrict
     __shared__ double S[kNb * kNb], W[kNb * kNb];
     for (int t = threadIdx.x; t < kNb * kNb; t += 256) S[t] = A[(t / kNb) * ld + (t % kNb)];
     __syncthreads();
-    pivot_inverse(S, W, diag0, 0, kdim, P, fail);
+    pivot_inverse(S, W, diag0, 0, kdim, P, fail, -1);
 }
 
 // C (32 x 32) = sign * X Y for 32 x 32 tiles in LDS; each thread computes a 2 x 2 block.
@@ -1103,12 +1116,11 @@ __device__ __forceinline__ void tile_mm(const double *X, const double *Y, double
 // One sweep with pivot block p: B = sweep(A).  Tile (I, J) of 32 x 32:
 //   I = J = p: P;  I = p: P A_pJ;  J = p: -A_Ip P;  else A_IJ - A_Ip (P A_pJ).
 // The workgroup of tile (p+1, p+1) also inverts the next pivot block.
-__global__ __launch_bounds__(256) void k_gj_sweep(int p, int nt, const double *__restrict__ A, double *__restrict__ B,
-                                                  int64_t ld, int32_t kdim, const double *__restrict__ Pcur,
-                                                  double *__restrict__ Pnext, const double *__restrict__ diag0,
-                                                  int *fail) {
+__device__ __forceinline__ void gj_sweep_tile(int p, int nt, int I, int J, const double *__restrict__ A,
+                                              double *__restrict__ B, int64_t ld, int32_t kdim,
+                                              const double *__restrict__ Pcur, double *__restrict__ Pnext,
+                                              const double *__restrict__ diag0, int *fail, int failval) {
     __shared__ double Ps[kNb * kNb], X[kNb * kNb], Y[kNb * kNb], T[kNb * kNb];
-    const int I = blockIdx.x / nt, J = blockIdx.x % nt;
     const int64_t r0 = (int64_t)I * kNb, c0 = (int64_t)J * kNb, q0 = (int64_t)p * kNb;
     const int tr = 2 * (threadIdx.x / 16), tc = 2 * (threadIdx.x % 16);
     for (int t = threadIdx.x; t < kNb * kNb; t += 256) {
@@ -1146,7 +1158,118 @@ __global__ __launch_bounds__(256) void k_gj_sweep(int p, int nt, const double *_
     }
     if (I == p + 1 && J == p + 1) {
         __syncthreads();
-        pivot_inverse(Y, X, diag0, (int64_t)(p + 1) * kNb, kdim, Pnext, fail);
+        pivot_inverse(Y, X, diag0, (int64_t)(p + 1) * kNb, kdim, Pnext, fail, failval);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gj_sweep(int p, int nt, const double *__restrict__ A, double *__restrict__ B,
+                                                  int64_t ld, int32_t kdim, const double *__restrict__ Pcur,
+                                                  double *__restrict__ Pnext, const double *__restrict__ diag0,
+                                                  int *fail) {
+    gj_sweep_tile(p, nt, blockIdx.x / nt, blockIdx.x % nt, A, B, ld, kdim, Pcur, Pnext, diag0, fail, -1);
+}
+
+// ---------------------------------------------------------------- dense blocks
+// Block-Jacobi blocks of more than kMaxBlock DoFs (subdomain-sized blocks).  K_BB is
+// gathered from the block's lower triangle (mirrored), padded to ld = 32 * ceil(m / 32)
+// with the identity, and inverted by the Gauss-Jordan sweeps above, batched over the
+// blocks: the table is sorted by ld, largest first, so the blocks that still have a
+// pivot tile p form a prefix, and sweep p runs the tiles of that prefix in one launch.
+// A failed pivot lowers the flag to the block's index.
+struct GjMat {
+    int64_t off;    // first entry of its ld x ld matrix in the work buffers (= in dinv)
+    int64_t tile0;  // first workgroup of its tiles in a sweep (prefix of nt^2)
+    int64_t dg;     // first entry of its original diagonal in diag0 (prefix of ld)
+    int32_t ld, size, start, block;
+};
+
+__device__ __forceinline__ int gj_find(const GjMat *__restrict__ m, int count, int64_t wg) {
+    int lo = 0, hi = count - 1;  // last matrix with tile0 <= wg
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (m[mid].tile0 <= wg) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// rows of matrix blockIdx.y (grid-stride): the lower-triangle entries of K_BB to both
+// (i, c) and (c, i), the original diagonal to diag0, the identity beyond the block's
+// size.  A and diag0 are zero on entry.
+__global__ __launch_bounds__(256) void k_dense_gather(const GjMat *__restrict__ mats, int count,
+                                                      const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
+                                                      const double *__restrict__ val, double *__restrict__ A,
+                                                      double *__restrict__ diag0) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int mi = blockIdx.y; mi < count; mi += gridDim.y) {
+        const GjMat G = mats[mi];
+        double *a = A + G.off;
+        for (int i = blockIdx.x * 4 + wave; i < G.ld; i += gridDim.x * 4) {
+            if (i >= G.size) {
+                if (lane == 0) {
+                    a[(int64_t)i * G.ld + i] = 1.0;
+                    diag0[G.dg + i] = 1.0;
+                }
+                continue;
+            }
+            const int64_t g = (int64_t)G.start + i;
+            for (int64_t e = ptr[g] + lane; e < ptr[g + 1]; e += 64) {
+                const int64_t c = (int64_t)idx[e] - G.start;
+                if (c < 0 || c > i) continue;
+                const double v = val[e];
+                a[(int64_t)i * G.ld + c] = v;
+                a[c * G.ld + i] = v;
+                if (c == i) diag0[G.dg + i] = v;
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gjb_first_pivot(const GjMat *__restrict__ mats, int count,
+                                                         const double *__restrict__ A,
+                                                         const double *__restrict__ diag0, double *__restrict__ P,
+                                                         int *fail) {
+    __shared__ double S[kNb * kNb], W[kNb * kNb];
+    for (int mi = blockIdx.x; mi < count; mi += gridDim.x) {
+        const GjMat G = mats[mi];
+        __syncthreads();
+        for (int t = threadIdx.x; t < kNb * kNb; t += 256) S[t] = A[G.off + (t / kNb) * (int64_t)G.ld + (t % kNb)];
+        __syncthreads();
+        pivot_inverse(S, W, diag0 + G.dg, 0, G.size, P + (int64_t)mi * 2 * kNb * kNb, fail, G.block);
+    }
+}
+
+// sweep p over the first count matrices (those with more than p pivot tiles)
+__global__ __launch_bounds__(256) void k_gjb_sweep(int p, const GjMat *__restrict__ mats, int count,
+                                                   const double *__restrict__ A, double *__restrict__ B,
+                                                   double *__restrict__ P, const double *__restrict__ diag0,
+                                                   int *fail) {
+    const int mi = gj_find(mats, count, blockIdx.x);
+    const GjMat G = mats[mi];
+    const int nt = G.ld / kNb;
+    const int64_t t = blockIdx.x - G.tile0;
+    double *pv = P + (int64_t)mi * 2 * kNb * kNb;
+    gj_sweep_tile(p, nt, (int)(t / nt), (int)(t % nt), A + G.off, B + G.off, G.ld, G.size, pv + (p & 1) * kNb * kNb,
+                  pv + ((p + 1) & 1) * kNb * kNb, diag0 + G.dg, fail, G.block);
+}
+
+__global__ __launch_bounds__(256) void k_gjb_zero(const GjMat *__restrict__ mats, int count, double *__restrict__ A) {
+    for (int mi = blockIdx.y; mi < count; mi += gridDim.y) {
+        const GjMat G = mats[mi];
+        const int64_t len = (int64_t)G.ld * G.ld;
+        for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256) A[G.off + t] = 0.0;
+    }
+}
+
+// matrices with an even number of pivot tiles end their sweeps in the work buffer
+__global__ __launch_bounds__(256) void k_gjb_copy_even(const GjMat *__restrict__ mats, int count,
+                                                       const double *__restrict__ src, double *__restrict__ dst) {
+    for (int mi = blockIdx.y; mi < count; mi += gridDim.y) {
+        const GjMat G = mats[mi];
+        if ((G.ld / kNb) % 2 != 0) continue;
+        const int64_t len = (int64_t)G.ld * G.ld;
+        for (int64_t t = blockIdx.x * 256ll + threadIdx.x; t < len; t += (int64_t)gridDim.x * 256)
+            dst[G.off + t] = src[G.off + t];
     }
 }
 
@@ -1384,6 +1507,84 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
     }
 }
 
+// Inverses of the dense blocks which[] (indices into c->dense_h), written to c->dinv.
+// A block that is not SPD to working precision lowers *bad_flag to its block index.
+int dense_inverses(dpcg_ctx *c, Pool &pool, const int64_t *kp, const int32_t *kc, const double *kv,
+                   const std::vector<int32_t> &which, int *bad_flag) {
+    hipStream_t s = c->stream;
+    const int count = (int)which.size();
+    if (count == 0) return DPCG_OK;
+    std::vector<GjMat> m(count);
+    for (int i = 0; i < count; ++i) {
+        const DenseBlk &D = c->dense_h[which[i]];
+        m[i] = GjMat{D.off, 0, 0, D.ld, D.size, D.start, D.block};
+    }
+    std::stable_sort(m.begin(), m.end(), [](const GjMat &a, const GjMat &b) { return a.ld > b.ld; });
+    std::vector<int64_t> tiles(count + 1, 0);
+    int64_t dg = 0;
+    for (int i = 0; i < count; ++i) {
+        const int64_t nt = m[i].ld / kNb;
+        m[i].tile0 = tiles[i];
+        tiles[i + 1] = tiles[i] + nt * nt;
+        m[i].dg = dg;
+        dg += m[i].ld;
+    }
+    GjMat *md = nullptr;
+    double *X0 = nullptr, *diag0 = nullptr, *pv = nullptr;
+    HT(pool.tmp(&md, count));
+    HT(pool.tmp(&X0, c->dinv_len));
+    HT(pool.tmp(&diag0, dg));
+    HT(pool.tmp(&pv, (int64_t)count * 2 * kNb * kNb));
+    HT(hipMemcpyAsync(md, m.data(), sizeof(GjMat) * count, hipMemcpyHostToDevice, s));
+    HT(hipMemsetAsync(diag0, 0, sizeof(double) * dg, s));
+    const int gy = std::min(count, 65535);
+    const int ldmax = m[0].ld;
+    hipLaunchKernelGGL(k_gjb_zero, dim3(64, gy), dim3(256), 0, s, md, count, X0);
+    hipLaunchKernelGGL(k_dense_gather, dim3(std::min(1024, (ldmax + 3) / 4), gy), dim3(256), 0, s, md, count, kp, kc,
+                       kv, X0, diag0);
+    hipLaunchKernelGGL(k_gjb_first_pivot, dim3(gy), dim3(256), 0, s, md, count, X0, diag0, pv, bad_flag);
+    int active = count;
+    for (int p = 0; p < ldmax / kNb; ++p) {
+        while (active > 0 && m[active - 1].ld / kNb <= p) --active;
+        const double *src = (p & 1) ? c->dinv : X0;
+        double *dst = (p & 1) ? X0 : c->dinv;
+        hipLaunchKernelGGL(k_gjb_sweep, dim3((unsigned)tiles[active]), dim3(256), 0, s, p, md, active, src, dst, pv,
+                           diag0, bad_flag);
+    }
+    hipLaunchKernelGGL(k_gjb_copy_even, dim3(64, gy), dim3(256), 0, s, md, count, X0, c->dinv);
+    HT(hipGetLastError());
+    return DPCG_OK;
+}
+
+// The dense-block tables from the host copy of the partition: extents, offsets in dinv,
+// and the apply's workgroups (kDenseRows rows of one block each).
+int dense_tables(dpcg_ctx *c, const std::vector<int32_t> &bph) {
+    hipStream_t s = c->stream;
+    c->dense_h.clear();
+    int64_t off = 0;
+    for (size_t b = 0; b + 1 < bph.size(); ++b) {
+        const int32_t m = bph[b + 1] - bph[b];
+        if (m <= kMaxBlock) continue;
+        const int32_t ld = (m + kNb - 1) / kNb * kNb;
+        c->dense_h.push_back(DenseBlk{off, bph[b], m, ld, (int32_t)b});
+        c->dense_maxld = std::max(c->dense_maxld, ld);
+        off += (int64_t)ld * ld;
+    }
+    std::vector<DenseChunk> ch;
+    for (size_t i = 0; i < c->dense_h.size(); ++i)
+        for (int32_t r = 0; r < c->dense_h[i].size; r += kDenseRows) ch.push_back(DenseChunk{(int32_t)i, r});
+    c->ndense = (int32_t)c->dense_h.size();
+    c->ndchunks = (int32_t)ch.size();
+    c->dinv_len = off;
+    HT(keep(c, &c->dense, c->ndense));
+    HT(keep(c, &c->dchunk, c->ndchunks));
+    HT(keep(c, &c->dinv, off));
+    HT(hipMemcpyAsync(c->dense, c->dense_h.data(), sizeof(DenseBlk) * c->ndense, hipMemcpyHostToDevice, s));
+    HT(hipMemcpyAsync(c->dchunk, ch.data(), sizeof(DenseChunk) * c->ndchunks, hipMemcpyHostToDevice, s));
+    HT(hipStreamSynchronize(s));  // ch is a host temporary
+    return DPCG_OK;
+}
+
 }  // namespace
 
 int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, const double *kv, int32_t k,
@@ -1410,19 +1611,27 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     const double *maxpart = nullptr;
     int nmaxpart = 0;
     int *flags = nullptr;
-    HT(pool.tmp(&flags, 4));
-    const int init_flags[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
+    HT(pool.tmp(&flags, 5));
+    const int init_flags[5] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX, 0};  // [4]: largest block above kMaxBlock
     HT(hipMemcpyAsync(flags, init_flags, sizeof(init_flags), hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, 4)), dim3(256), 0, s, n, n, kp, kc, kv, nnz, flags);
     if (k > 0) hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, 4)), dim3(256), 0, s, n, (int64_t)k, zp, zc, zv,
                                   nnz_z, flags + 1);
-    hipLaunchKernelGGL(k_check_blocks, dim3(grid_for(nblocks)), dim3(256), 0, s, nblocks, bp, n, flags + 2);
+    hipLaunchKernelGGL(k_check_blocks, dim3(grid_for(nblocks)), dim3(256), 0, s, nblocks, bp, n, flags + 2,
+                       flags + 4);
     HT(hipGetLastError());
-    int fl[4];
+    int fl[5];
     HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
     HT(hipStreamSynchronize(s));
     if (fl[2] != INT32_MAX) *bad = fl[2];
     if (fl[0] != INT32_MAX || fl[1] != INT32_MAX || fl[2] != INT32_MAX) return DPCG_EINVAL;
+    if (fl[4] > kMaxBlock) {
+        std::vector<int32_t> bph(nblocks + 1);
+        HT(hipMemcpyAsync(bph.data(), bp, sizeof(int32_t) * (nblocks + 1), hipMemcpyDeviceToHost, s));
+        HT(hipStreamSynchronize(s));
+        const int st = dense_tables(c, bph);
+        if (st != DPCG_OK) return st;
+    }
     {
         const int nmx = grid_for(nnz, 256, 1024);
         double *mxp = nullptr;
@@ -1521,10 +1730,20 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(keep(c, &c->bj_rowoff, n));
     HT(keep(c, &c->bj_meta, n));
     int *bjbad = flags + 1;  // reuse: Z's flag is known to be clear
+    if (c->ndense > 0) {  // the DoFs of dense blocks take no part in the small-block kernels
+        HT(hipMemsetAsync(c->bj_meta, 0, sizeof(int32_t) * n, s));
+        HT(hipMemsetAsync(c->bj_rowoff, 0, sizeof(int32_t) * n, s));
+    }
     hipLaunchKernelGGL(k_bj_small, dim3(grid_for(nblocks)), dim3(256), 0, s, nblocks, bp, kp, kc, kv, moff, c->minv,
                        c->bj_rowoff, c->bj_meta, bjbad, (const int32_t *)nullptr, 0);
     hipLaunchKernelGGL(k_bj_factor, dim3(std::min<int32_t>(nblocks, 4096)), dim3(64), 0, s, nblocks, bp, kp, kc, kv,
                        moff, c->minv, c->bj_rowoff, c->bj_meta, bjbad, (const int32_t *)nullptr, 0);
+    if (c->ndense > 0) {
+        std::vector<int32_t> all(c->ndense);
+        for (int32_t i = 0; i < c->ndense; ++i) all[i] = i;
+        const int st = dense_inverses(c, pool, kp, kc, kv, all, bjbad);
+        if (st != DPCG_OK) return st;
+    }
     // kept for value updates: the partition and each block's offset in minv
     HT(keep(c, &c->block_ptr, nblocks + 1));
     HT(keep(c, &c->bj_moff, nblocks + 1));
@@ -1645,6 +1864,24 @@ int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const d
                            c->block_ptr, kp, kc, kv, c->bj_moff, c->minv, c->bj_rowoff, c->bj_meta, flags + 1,
                            (const int32_t *)list_d, nlist);
     }
+    if (c->ndense > 0) {  // the listed dense blocks (all without a list)
+        std::vector<int32_t> which;
+        if (!list_host) {
+            for (int32_t i = 0; i < c->ndense; ++i) which.push_back(i);
+        } else {
+            std::vector<char> seen(c->ndense, 0);
+            for (int32_t i = 0; i < nlist; ++i) {
+                auto it = std::lower_bound(c->dense_h.begin(), c->dense_h.end(), list_host[i],
+                                           [](const DenseBlk &d, int32_t b) { return d.block < b; });
+                if (it != c->dense_h.end() && it->block == list_host[i] && !seen[it - c->dense_h.begin()]) {
+                    seen[it - c->dense_h.begin()] = 1;
+                    which.push_back((int32_t)(it - c->dense_h.begin()));
+                }
+            }
+        }
+        const int st = dense_inverses(c, pool, kp, kc, kv, which, flags + 1);
+        if (st != DPCG_OK) return st;
+    }
     HT(hipGetLastError());
     HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
     HT(hipStreamSynchronize(s));
@@ -1677,6 +1914,9 @@ int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const d
         hipLaunchKernelGGL(k_to_f32_s, dim3(grid_for(9 * nnzb, 256, 8192)), dim3(256), 0, s, c->bval, 9 * nnzb, c->bval32);
         hipLaunchKernelGGL(k_to_f32_s, dim3(grid_for(c->bj_values, 256, 8192)), dim3(256), 0, s, c->minv,
                            c->bj_values, c->minv32);
+        if (c->ndense > 0)
+            hipLaunchKernelGGL(k_to_f32_s, dim3(grid_for(c->dinv_len, 256, 8192)), dim3(256), 0, s, c->dinv,
+                               c->dinv_len, c->dinv32);
     }
     HT(hipGetLastError());
     HT(hipStreamSynchronize(s));

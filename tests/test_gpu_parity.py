@@ -324,7 +324,7 @@ def test_setup_errors(problems):
     with pytest.raises(D.DpcgError) as e:
         _solver_from_dense(K3.tocsr(), Z, bp)
     assert e.value.code == D.abi.ENOTSYM
-    bad_bp = np.array([0, 19] + list(range(22, p.n + 1, 3)))
+    bad_bp = np.array([0, 3, 3] + list(range(6, p.n + 1, 3)))   # an empty block
     with pytest.raises(D.DpcgError) as e:
         _solver_from_dense(K.tocsr(), Z, bad_bp)
     assert e.value.code == D.abi.EINVAL
