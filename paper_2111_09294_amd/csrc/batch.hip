@@ -239,8 +239,10 @@ __global__ __launch_bounds__(256) void k_bupdate_bj(int32_t ntiles, int32_t nwg,
 // against thr_j and the iteration cap; any = some column still running.  Then the
 // merged right-hand side of Algorithm 3 in segments: segment s of deflation vector c
 // sums Z^T[c, e] a[e][j] over its entries (list 0) or -(KZ)^T[c, e] b[e][j] (list 1; 0
-// when b is null) into seg_part[s][j]; 32 groups of 32 lanes stride over the entries,
-// the group sums are added in a fixed order.
+// when b is null) into seg_part[s][j].  Group g of 32 lanes takes the chunks of 32
+// entries g, g + 32, ...: lane j loads entry j of the chunk (one coalesced load of
+// indices and values), the chunk's row indices are passed round by shuffles and eight
+// row gathers are in flight at a time; the group sums are added in a fixed order.
 __global__ __launch_bounds__(1024) void k_brestrict(const int32_t *__restrict__ seg, int32_t nseg,
                                                    const int32_t *__restrict__ zt_idx,
                                                    const double *__restrict__ zt_val,
@@ -291,17 +293,36 @@ __global__ __launch_bounds__(1024) void k_brestrict(const int32_t *__restrict__ 
     const int32_t *idx = list ? kzt_idx : zt_idx;
     const double *val = list ? kzt_val : zt_val;
     const double *vec = list ? b : a;
-    double s = 0.0, s1 = 0.0;
+    constexpr int kInFlight = 8;
+    double s = 0.0;
     if (vec) {
-        int e = e0 + g;
-        for (; e + 32 < e1; e += 64) {
-            s = fma(val[e], vec[(int64_t)idx[e] * W + j], s);
-            s1 = fma(val[e + 32], vec[(int64_t)idx[e + 32] * W + j], s1);
+        for (int c0 = e0 + 32 * g; c0 < e1; c0 += 32 * 32) {
+            const int e = c0 + j;
+            int col = 0;
+            double v = 0.0;
+            if (e < e1) {
+                col = idx[e];
+                v = val[e];
+            }
+            const int cnt = min(32, e1 - c0);  // the same for the whole group
+#pragma unroll
+            for (int q0 = 0; q0 < 32; q0 += kInFlight) {
+                double x[kInFlight];
+#pragma unroll
+                for (int q = 0; q < kInFlight; ++q) {
+                    const int cq = __shfl(col, q0 + q, 32);
+                    x[q] = q0 + q < cnt ? vec[(int64_t)cq * W + j] : 0.0;
+                }
+#pragma unroll
+                for (int q = 0; q < kInFlight; ++q) {
+                    const double vq = __shfl(v, q0 + q, 32);
+                    if (q0 + q < cnt) s = fma(vq, x[q], s);
+                }
+            }
         }
-        for (; e < e1; e += 32) s = fma(val[e], vec[(int64_t)idx[e] * W + j], s);
     }
     __syncthreads();  // lds may still be read by the check above
-    lds[g][j] = s + s1;
+    lds[g][j] = s;
     __syncthreads();
     if (threadIdx.x < W) {
         double t = 0.0;
@@ -323,33 +344,47 @@ __global__ __launch_bounds__(256) void k_bsegsum(int32_t k, const int32_t *__res
     gout[(int64_t)c * W + j] = t;
 }
 
-// delta = E^{-1} g for all columns: each workgroup takes four rows of E^{-1}, so every
-// row of g it reads serves four output rows; group h of 32 lanes sums c = h, h + 32, ...
-constexpr int kCoarseRows = 4;
-__global__ __launch_bounds__(1024) void k_bcoarse(int32_t k, int64_t ld, const double *__restrict__ einv,
-                                                  const double *__restrict__ gin, double *__restrict__ delta,
-                                                  const BatchState *st) {
-    __shared__ double lds[32][kCoarseRows][W + 1];
+// delta = E^{-1} g for all 32 columns on the matrix cores: workgroup = 16 rows of
+// E^{-1}; wave w of 8 takes the w-th eighth of the contraction index c in steps of 4
+// (v_mfma_f64_16x16x4f64: a = E^{-1}[row l % 16][c + l / 16], b = g[c + l / 16][col],
+// two 16-column halves), then the eight partial tiles are added in wave order in LDS.
+// Result item v of lane l is row l / 16 + 4 v, column l % 16 of a half.
+constexpr int kCoarseWaves = 8;
+typedef double bdbl4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(64 * kCoarseWaves) void k_bcoarse(int32_t k, int64_t ld,
+                                                               const double *__restrict__ einv,
+                                                               const double *__restrict__ gin,
+                                                               double *__restrict__ delta, const BatchState *st) {
+    __shared__ double part[kCoarseWaves][16][W + 1];
     if (st && !st->any) return;
-    const int r0 = blockIdx.x * kCoarseRows;
-    const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
-    double s[kCoarseRows];
-#pragma unroll
-    for (int q = 0; q < kCoarseRows; ++q) s[q] = 0.0;
-    for (int c = g; c < k; c += 32) {
-        const double gv = gin[(int64_t)c * W + j];
-#pragma unroll
-        for (int q = 0; q < kCoarseRows; ++q)
-            if (r0 + q < k) s[q] = fma(einv[(int64_t)(r0 + q) * ld + c], gv, s[q]);
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r0 = blockIdx.x * 16;
+    const int row = r0 + (l & 15), kq = l >> 4;
+    const int steps = (k + 3) / 4;
+    const int s0 = (int)(((int64_t)wv * steps) / kCoarseWaves), s1 = (int)(((int64_t)(wv + 1) * steps) / kCoarseWaves);
+    const double *erow = einv + (int64_t)min(row, k - 1) * ld;
+    bdbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int st4 = s0; st4 < s1; ++st4) {
+        const int c = 4 * st4 + kq;
+        const bool ok = c < k && row < k;
+        const double a = ok ? erow[c] : 0.0;
+        const double *gr = gin + (int64_t)min(c, k - 1) * W;
+        const double b0 = c < k ? gr[l & 15] : 0.0, b1 = c < k ? gr[16 + (l & 15)] : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
     }
 #pragma unroll
-    for (int q = 0; q < kCoarseRows; ++q) lds[g][q][j] = s[q];
+    for (int v = 0; v < 4; ++v) {
+        part[wv][kq + 4 * v][l & 15] = acc0[v];
+        part[wv][kq + 4 * v][16 + (l & 15)] = acc1[v];
+    }
     __syncthreads();
-    if (threadIdx.x < kCoarseRows * W) {
-        const int q = threadIdx.x / W, jj = threadIdx.x % W;
-        double t = 0.0;
-        for (int h = 0; h < 32; ++h) t += lds[h][q][jj];
-        if (r0 + q < k) delta[(int64_t)(r0 + q) * W + jj] = t;
+    for (int t = threadIdx.x; t < 16 * W; t += 64 * kCoarseWaves) {
+        const int rr = t / W, j = t % W;
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < kCoarseWaves; ++w) sum += part[w][rr][j];
+        if (r0 + rr < k) delta[(int64_t)(r0 + rr) * W + j] = sum;
     }
 }
 
@@ -597,8 +632,8 @@ int enqueue_restrict(dpcg_ctx *c, const double *a, const double *bvec, BatchStat
 int enqueue_coarse(dpcg_ctx *c, const BatchState *st) {
     BatchWorkspace *b = c->bws;
     if (c->k == 0) return DPCG_OK;
-    BLAUNCH(k_bcoarse, dim3((c->k + kCoarseRows - 1) / kCoarseRows), dim3(1024), 0, c->stream, c->k, c->einv_ld,
-            c->einv, b->g, b->delta, st);
+    BLAUNCH(k_bcoarse, dim3((c->k + 15) / 16), dim3(64 * kCoarseWaves), 0, c->stream, c->k, c->einv_ld, c->einv,
+            b->g, b->delta, st);
     return DPCG_OK;
 }
 

@@ -1044,8 +1044,8 @@ __global__ void k_symmetrise(int32_t k, int64_t ld, const double *__restrict__ e
 // column k travel through LDS (W, ping-pong by step parity), one barrier per step.
 // Every pivot is tested against kdim * DBL_EPSILON times the original diagonal entry;
 // a failure sets *fail to 1 (failval < 0) or lowers it to failval.
-__device__ void pivot_inverse(const double *S, double *W, const double *diag0, int64_t gcol0, int32_t kdim, double *P,
-                              int *fail, int failval) {
+__device__ void pivot_inverse(const double *S, int lds, double *W, const double *diag0, int64_t gcol0, int32_t kdim,
+                              double *P, int *fail, int failval) {
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     double *rowk = W, *colk = W + 2 * kNb;  // [parity][32] each
     // thread j tests pivot j; its floor is loaded before the first barrier
@@ -1055,7 +1055,7 @@ __device__ void pivot_inverse(const double *S, double *W, const double *diag0, i
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int r = ty + 8 * q;
-        a[q] = S[r * kNb + tx];
+        a[q] = S[r * lds + tx];
         if (r == 0) rowk[tx] = a[q];
         if (tx == 0) colk[r] = a[q];
     }
@@ -1095,23 +1095,33 @@ __global__ __launch_bounds__(256) void k_gj_first_pivot(const double *__restrict
     __shared__ double S[kNb * kNb], W[kNb * kNb];
     for (int t = threadIdx.x; t < kNb * kNb; t += 256) S[t] = A[(t / kNb) * ld + (t % kNb)];
     __syncthreads();
-    pivot_inverse(S, W, diag0, 0, kdim, P, fail, -1);
+    pivot_inverse(S, kNb, W, diag0, 0, kdim, P, fail, -1);
 }
 
-// C (32 x 32) = sign * X Y for 32 x 32 tiles in LDS; each thread computes a 2 x 2 block.
-__device__ __forceinline__ void tile_mm(const double *X, const double *Y, double c[2][2]) {
-    const int r0 = 2 * (threadIdx.x / 16), c0 = 2 * (threadIdx.x % 16);
-    c[0][0] = c[0][1] = c[1][0] = c[1][1] = 0.0;
-#pragma unroll 8
-    for (int q = 0; q < kNb; ++q) {
-        const double x0 = X[r0 * kNb + q], x1 = X[(r0 + 1) * kNb + q];
-        const double y0 = Y[q * kNb + c0], y1 = Y[q * kNb + c0 + 1];
-        c[0][0] = fma(x0, y0, c[0][0]);
-        c[0][1] = fma(x0, y1, c[0][1]);
-        c[1][0] = fma(x1, y0, c[1][0]);
-        c[1][1] = fma(x1, y1, c[1][1]);
-    }
+// The 32 x 32 tile products of the sweeps on the matrix cores: wave w of the 256 threads
+// computes the 16 x 16 quarter (w / 2, w % 2) of X Y (X, Y in LDS, row stride kLd) as
+// eight v_mfma_f64_16x16x4f64 steps.  Operand lanes: a = X[row l % 16][k-step col l / 16],
+// b = Y[k-step row l / 16][col l % 16]; result item v of lane l is element
+// (l / 16 + 4 v, l % 16) of the quarter.  The stride 33 spreads a column's 16 rows over
+// distinct LDS banks.
+constexpr int kLd = kNb + 1;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ dbl4 tile_mfma(const double *X, const double *Y) {
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int r = (wv >> 1) * 16 + (l & 15), c = (wv & 1) * 16 + (l & 15), kq = l >> 4;
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < kNb; s4 += 4)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[r * kLd + s4 + kq], Y[(s4 + kq) * kLd + c], acc, 0, 0, 0);
+    return acc;
 }
+
+// row and column (within the 32 x 32 tile) of result item v of this thread
+__device__ __forceinline__ int tile_row(int v) {
+    return ((threadIdx.x >> 6) >> 1) * 16 + ((threadIdx.x & 63) >> 4) + 4 * v;
+}
+__device__ __forceinline__ int tile_col() { return ((threadIdx.x >> 6) & 1) * 16 + (threadIdx.x & 15); }
 
 // One sweep with pivot block p: B = sweep(A).  Tile (I, J) of 32 x 32:
 //   I = J = p: P;  I = p: P A_pJ;  J = p: -A_Ip P;  else A_IJ - A_Ip (P A_pJ).
@@ -1120,45 +1130,45 @@ __device__ __forceinline__ void gj_sweep_tile(int p, int nt, int I, int J, const
                                               double *__restrict__ B, int64_t ld, int32_t kdim,
                                               const double *__restrict__ Pcur, double *__restrict__ Pnext,
                                               const double *__restrict__ diag0, int *fail, int failval) {
-    __shared__ double Ps[kNb * kNb], X[kNb * kNb], Y[kNb * kNb], T[kNb * kNb];
+    __shared__ double Ps[kNb * kLd], X[kNb * kLd], Y[kNb * kLd], T[kNb * kLd];
     const int64_t r0 = (int64_t)I * kNb, c0 = (int64_t)J * kNb, q0 = (int64_t)p * kNb;
-    const int tr = 2 * (threadIdx.x / 16), tc = 2 * (threadIdx.x % 16);
     for (int t = threadIdx.x; t < kNb * kNb; t += 256) {
         const int a = t / kNb, b = t % kNb;
-        Ps[t] = Pcur[t];
-        if (I != p) X[t] = A[(r0 + a) * ld + q0 + b];   // A_Ip
-        if (J != p) Y[t] = A[(q0 + a) * ld + c0 + b];   // A_pJ
+        Ps[a * kLd + b] = Pcur[t];
+        if (I != p) X[a * kLd + b] = A[(r0 + a) * ld + q0 + b];   // A_Ip
+        if (J != p) Y[a * kLd + b] = A[(q0 + a) * ld + c0 + b];   // A_pJ
     }
     __syncthreads();
-    double cc[2][2];
+    const int cc = tile_col();
     if (I == p && J == p) {
-        for (int t = threadIdx.x; t < kNb * kNb; t += 256) B[(r0 + t / kNb) * ld + c0 + t % kNb] = Ps[t];
+        for (int t = threadIdx.x; t < kNb * kNb; t += 256) B[(r0 + t / kNb) * ld + c0 + t % kNb] = Pcur[t];
     } else if (I == p) {
-        tile_mm(Ps, Y, cc);
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) B[(r0 + tr + a) * ld + c0 + tc + b] = cc[a][b];
+        const dbl4 d = tile_mfma(Ps, Y);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) B[(r0 + tile_row(v)) * ld + c0 + cc] = d[v];
     } else if (J == p) {
-        tile_mm(X, Ps, cc);
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) B[(r0 + tr + a) * ld + c0 + tc + b] = -cc[a][b];
+        const dbl4 d = tile_mfma(X, Ps);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) B[(r0 + tile_row(v)) * ld + c0 + cc] = -d[v];
     } else {
-        tile_mm(Ps, Y, cc);  // T = P A_pJ
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) T[(tr + a) * kNb + tc + b] = cc[a][b];
+        const dbl4 t4 = tile_mfma(Ps, Y);  // T = P A_pJ
+#pragma unroll
+        for (int v = 0; v < 4; ++v) T[tile_row(v) * kLd + cc] = t4[v];
         __syncthreads();
-        tile_mm(X, T, cc);
+        const dbl4 d = tile_mfma(X, T);
         __syncthreads();
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b) {
-                const int64_t g = (r0 + tr + a) * ld + c0 + tc + b;
-                const double v = A[g] - cc[a][b];
-                B[g] = v;
-                Y[(tr + a) * kNb + tc + b] = v;  // kept for the next pivot
-            }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = tile_row(v);
+            const int64_t g = (r0 + rr) * ld + c0 + cc;
+            const double nv = A[g] - d[v];
+            B[g] = nv;
+            Y[rr * kLd + cc] = nv;  // kept for the next pivot
+        }
     }
     if (I == p + 1 && J == p + 1) {
         __syncthreads();
-        pivot_inverse(Y, X, diag0, (int64_t)(p + 1) * kNb, kdim, Pnext, fail, failval);
+        pivot_inverse(Y, kLd, X, diag0, (int64_t)(p + 1) * kNb, kdim, Pnext, fail, failval);
     }
 }
 
@@ -1235,7 +1245,7 @@ __global__ __launch_bounds__(256) void k_gjb_first_pivot(const GjMat *__restrict
         __syncthreads();
         for (int t = threadIdx.x; t < kNb * kNb; t += 256) S[t] = A[G.off + (t / kNb) * (int64_t)G.ld + (t % kNb)];
         __syncthreads();
-        pivot_inverse(S, W, diag0 + G.dg, 0, G.size, P + (int64_t)mi * 2 * kNb * kNb, fail, G.block);
+        pivot_inverse(S, kNb, W, diag0 + G.dg, 0, G.size, P + (int64_t)mi * 2 * kNb * kNb, fail, G.block);
     }
 }
 
