@@ -1062,22 +1062,33 @@ __device__ void pivot_inverse(const double *S, int lds, double *W, const double 
     bool bad = false;
     __syncthreads();
     for (int k = 0; k < kNb; ++k) {
+        // all LDS reads of the step first (one wait), then selects instead of branches
         const int cb = k & 1, nb = cb ^ 1;
         const double p = rowk[cb * kNb + k];
-        if ((int)threadIdx.x == k && (!(p > myfl) || !isfinite(p))) bad = true;
-        const double ip = 1.0 / p;
         const double kc = rowk[cb * kNb + tx];
+        double rk[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rk[q] = colk[cb * kNb + ty + 8 * q];
+        if ((int)threadIdx.x == k && (!(p > myfl) || !isfinite(p))) bad = true;
+        // 1/p: hardware reciprocal refined by two Newton steps
+        double ip = __builtin_amdgcn_rcp(p);
+        ip = fma(ip, fma(-p, ip, 1.0), ip);
+        ip = fma(ip, fma(-p, ip, 1.0), ip);
+        const double kcip = kc * ip;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = ty + 8 * q;
-            const double rk = colk[cb * kNb + r];
-            double v;
-            if (r == k) v = (tx == k) ? ip : kc * ip;
-            else if (tx == k) v = -rk * ip;
-            else v = fma(-rk * ip, kc, a[q]);
+            const double m = -rk[q] * ip;
+            double v = fma(m, kc, a[q]);
+            v = (tx == k) ? m : v;
+            v = (r == k) ? ((tx == k) ? ip : kcip) : v;
             a[q] = v;
-            if (r == k + 1) rowk[nb * kNb + tx] = v;
-            if (tx == k + 1) colk[nb * kNb + r] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = ty + 8 * q;
+            if (r == k + 1) rowk[nb * kNb + tx] = a[q];
+            if (tx == k + 1) colk[nb * kNb + r] = a[q];
         }
         __syncthreads();
     }
