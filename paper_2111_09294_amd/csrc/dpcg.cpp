@@ -158,8 +158,7 @@ int setup_impl(dpcg_ctx *c, int64_t n, const int64_t *k_rowptr, const int32_t *k
     c->nblocks = nblocks;
     TRY(gpu_setup(c, n, k_rowptr, k_col, k_val, k, z_rowptr, z_col, z_val, nblocks, block_ptr, bad));
     choose_shapes(c);
-    TRY(alloc_workspace(c, c->ws[0]));
-    TRY(alloc_workspace(c, c->ws[1]));
+    TRY(alloc_workspace(c, c->ws[0]));  // the adjoint workspace is made on the first adjoint solve
     HIP_TRY(hipStreamSynchronize(c->stream));
     return DPCG_OK;
 }
@@ -758,6 +757,13 @@ int dpcg_solve_batch(dpcg_handle h, int32_t nrhs, const double *F, double *U, do
 int dpcg_solve_adjoint(dpcg_handle h, const double *g, double *lambda, double tol, const dpcg_options *opt,
                        dpcg_info *info) {
     if (!h) return DPCG_EINVAL;
+    if (!h->ws[1].st) {
+        const int e = alloc_workspace(h, h->ws[1]);
+        if (e != DPCG_OK) {
+            if (info) info->status = e;
+            return e;
+        }
+    }
     const int st = solve_impl(h, h->ws[1], g, lambda, tol, opt, info);
     if (st < 0 && info) info->status = st;
     return st;
