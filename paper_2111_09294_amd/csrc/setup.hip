@@ -110,23 +110,53 @@ __global__ void k_to_i32(const int64_t *__restrict__ a, int64_t n, int32_t *__re
 // ---------------------------------------------------------------- validation
 // flags[0]: first invalid row of K (or INT_MAX), flags[1]: first invalid row of Z,
 // flags[2]: first invalid block, flags[3]: first asymmetric row.
-// One wave per row: row pointer monotone and in range, columns strictly increasing and
-// in range, values finite.
-__global__ __launch_bounds__(256) void k_check_csr(int64_t rows, int64_t cols, const int64_t *__restrict__ ptr,
-                                                   const int32_t *__restrict__ idx, const double *__restrict__ val,
-                                                   int64_t nnz, int *flag) {
-    const int lane = threadIdx.x & 63;
-    const int64_t waves = (int64_t)gridDim.x * 4;
-    for (int64_t i = blockIdx.x * 4ll + (threadIdx.x >> 6); i < rows; i += waves) {
+// Checks of a CSR matrix: row pointer monotone and in range, columns strictly increasing
+// and in range, values finite.  Pass 1 (one thread per
+// row): the row pointer, and a bit at each nonempty row's first entry.  Pass 2 (one
+// thread per entry): column in range, value finite, and, unless the next entry opens a
+// row, a larger column in the next entry; the failing row is found by bisection of the
+// row pointer.  Optionally the per-workgroup maxima of |value| (for the symmetry
+// tolerance) go to mxpart.
+__global__ __launch_bounds__(256) void k_csr_rows(int64_t rows, const int64_t *__restrict__ ptr, int64_t nnz,
+                                                  uint32_t *bits, int *flag) {
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < rows; i += (int64_t)gridDim.x * 256) {
         const int64_t a = ptr[i], b = ptr[i + 1];
-        bool ok = (i != 0 || a == 0) && a >= 0 && a <= b && b <= nnz;
-        if (ok)
-            for (int64_t e = a + lane; e < b; e += 64) {
-                const int64_t c = idx[e];
-                if (c < 0 || c >= cols || !isfinite(val[e]) || (e + 1 < b && idx[e + 1] <= c)) ok = false;
-            }
+        const bool ok = (i != 0 || a == 0) && a >= 0 && a <= b && b <= nnz;
         if (!ok) atomicMin(flag, (int)i);
+        else if (a < b) atomicOr(&bits[a >> 5], 1u << (a & 31));
     }
+}
+
+__global__ __launch_bounds__(256) void k_csr_entries(int64_t rows, int64_t cols, const int64_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ idx,
+                                                     const double *__restrict__ val, int64_t nnz,
+                                                     const uint32_t *__restrict__ bits, int *flag,
+                                                     double *__restrict__ mxpart) {
+    __shared__ double lds[4];
+    double mx = 0.0;
+    for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * 256) {
+        const int64_t c = idx[e];
+        const double v = val[e];
+        bool bad = c < 0 || c >= cols || !isfinite(v);
+        const int64_t n1 = e + 1;
+        if (n1 < nnz && !((bits[n1 >> 5] >> (n1 & 31)) & 1u) && idx[n1] <= c) bad = true;
+        mx = fmax(mx, fabs(v));
+        if (bad) {
+            int64_t lo = 0, hi = rows;  // last row with ptr <= e
+            while (hi - lo > 1) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (ptr[mid] <= e) lo = mid;
+                else hi = mid;
+            }
+            atomicMin(flag, (int)lo);
+        }
+    }
+    if (!mxpart) return;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) mxpart[blockIdx.x] = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
 }
 
 // flag = first invalid block; maxsize = size of the largest block
@@ -141,19 +171,6 @@ __global__ void k_check_blocks(int32_t nblocks, const int32_t *__restrict__ bp, 
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) big = max(big, __shfl_xor(big, off));
     if ((threadIdx.x & 63) == 0 && big > kMaxBlock) atomicMax(maxsize, big);
-}
-
-__global__ __launch_bounds__(256) void k_maxabs_part(const double *__restrict__ v, int64_t m,
-                                                     double *__restrict__ part) {
-    __shared__ double lds[4];
-    double x = 0.0;
-    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256)
-        x = fmax(x, fabs(v[i]));
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
 }
 
 // part[0] = max over part[0..m): one workgroup, fixed order
@@ -1354,6 +1371,29 @@ int grid_for(int64_t work, int per = 256, int cap = 8192) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(cap, (work + per - 1) / per));
 }
 
+// Checks a CSR matrix (rows x cols, nnz entries) into *flag; with mx, also max |value|
+// into (*mx)[0] (scratch from the pool).
+hipError_t check_csr(hipStream_t s, Pool &pool, int64_t rows, int64_t cols, const int64_t *ptr, const int32_t *idx,
+                     const double *val, int64_t nnz, int *flag, double **mx) {
+    uint32_t *bits = nullptr;
+    hipError_t e = pool.tmp(&bits, nnz / 32 + 1);
+    if (e != hipSuccess) return e;
+    e = hipMemsetAsync(bits, 0, sizeof(uint32_t) * (size_t)(nnz / 32 + 1), s);
+    if (e != hipSuccess) return e;
+    const int ge = grid_for(nnz, 256, 4096);
+    double *part = nullptr;
+    if (mx) {
+        e = pool.tmp(&part, ge);
+        if (e != hipSuccess) return e;
+        *mx = part;
+    }
+    hipLaunchKernelGGL(k_csr_rows, dim3(grid_for(rows, 256, 4096)), dim3(256), 0, s, rows, ptr, nnz, bits, flag);
+    hipLaunchKernelGGL(k_csr_entries, dim3(ge), dim3(256), 0, s, rows, cols, ptr, idx, val, nnz,
+                       (const uint32_t *)bits, flag, part);
+    if (mx) hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, part, ge);
+    return hipGetLastError();
+}
+
 // out[0..n] = exclusive scan of a[0..n); tmp holds the chunk partials.
 hipError_t scan(hipStream_t s, const int64_t *a, int64_t n, int64_t *out, int64_t *part) {
     const int chunks = (int)std::max<int64_t>(1, (n + kScanChunk - 1) / kScanChunk);
@@ -1635,9 +1675,9 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(pool.tmp(&flags, 5));
     const int init_flags[5] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX, 0};  // [4]: largest block above kMaxBlock
     HT(hipMemcpyAsync(flags, init_flags, sizeof(init_flags), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, 4)), dim3(256), 0, s, n, n, kp, kc, kv, nnz, flags);
-    if (k > 0) hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, 4)), dim3(256), 0, s, n, (int64_t)k, zp, zc, zv,
-                                  nnz_z, flags + 1);
+    double *mxk = nullptr;
+    HT(check_csr(s, pool, n, n, kp, kc, kv, nnz, flags, &mxk));
+    if (k > 0) HT(check_csr(s, pool, n, (int64_t)k, zp, zc, zv, nnz_z, flags + 1, nullptr));
     hipLaunchKernelGGL(k_check_blocks, dim3(grid_for(nblocks)), dim3(256), 0, s, nblocks, bp, n, flags + 2,
                        flags + 4);
     HT(hipGetLastError());
@@ -1653,16 +1693,8 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
         const int st = dense_tables(c, bph);
         if (st != DPCG_OK) return st;
     }
-    {
-        const int nmx = grid_for(nnz, 256, 1024);
-        double *mxp = nullptr;
-        HT(pool.tmp(&mxp, nmx));
-        hipLaunchKernelGGL(k_maxabs_part, dim3(nmx), dim3(256), 0, s, kv, nnz, mxp);
-        hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, mxp, nmx);
-        HT(hipGetLastError());
-        maxpart = mxp;
-        nmaxpart = 1;  // the maximum over all partials, in mxp[0]
-    }
+    maxpart = mxk;
+    nmaxpart = 1;  // the maximum of |K| over all entries, in mxk[0]
     // ---- block-CSR counts, block-Jacobi offsets, Z^T, windows ----
     const int32_t nb = c->nb;
     int64_t *cnt = nullptr, *bptr64 = nullptr, *part = nullptr;
@@ -1831,7 +1863,8 @@ int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const d
     HT(pool.tmp(&flags, 4));
     const int init_flags[4] = {INT32_MAX, INT32_MAX, INT32_MAX, INT32_MAX};
     HT(hipMemcpyAsync(flags, init_flags, sizeof(init_flags), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_check_csr, dim3(grid_for(n, 4)), dim3(256), 0, s, n, n, kp, kc, kv, nnz, flags);
+    double *mxp = nullptr;
+    HT(check_csr(s, pool, n, n, kp, kc, kv, nnz, flags, &mxp));
     int fl[4];
     HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
     HT(hipStreamSynchronize(s));
@@ -1845,12 +1878,7 @@ int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const d
     HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
     HT(hipStreamSynchronize(s));
     if (fl[2] != INT32_MAX) return DPCG_EINVAL;
-    // max |K| for the symmetry tolerance
-    const int nmx = grid_for(nnz, 256, 1024);
-    double *mxp = nullptr;
-    HT(pool.tmp(&mxp, nmx));
-    hipLaunchKernelGGL(k_maxabs_part, dim3(nmx), dim3(256), 0, s, kv, nnz, mxp);
-    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, mxp, nmx);
+    // max |K| for the symmetry tolerance: mxp[0], from the checks above
     // block values; the block columns must be the stored ones
     int32_t *bcol2 = nullptr, *brow = nullptr;
     HT(pool.tmp(&bcol2, nnzb));

@@ -336,3 +336,48 @@ def test_setup_errors(problems):
     with pytest.raises(D.DpcgError) as e:
         _solver_from_dense(K.tocsr()[:-1, :-1], Z[:-1], np.arange(p.n))
     assert e.value.code == D.abi.EINVAL
+
+
+def test_setup_rejects_malformed_csr(problems):
+    """Malformed K or Z arrays (with a truthful entry count) are refused before use."""
+    p = problems("edge4")
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dt)  # noqa: E731
+
+    def setup(kp, kc, kv, zc=p.z_col):
+        return D.Solver(p.n, t(kp, torch.int64), t(kc, torch.int32), t(kv, torch.float64), p.k,
+                        t(p.z_rowptr, torch.int64), t(zc, torch.int32), t(p.z_val, torch.float64),
+                        t(p.block_ptr, torch.int32))
+
+    r = 7
+    a, b = int(p.k_rowptr[r]), int(p.k_rowptr[r + 1])
+    cases = {}
+    kc = p.k_col.copy()
+    kc[a], kc[a + 1] = kc[a + 1], kc[a]
+    cases["unsorted columns"] = (p.k_rowptr, kc, p.k_val)
+    kc = p.k_col.copy()
+    kc[a + 1] = kc[a]
+    cases["repeated column"] = (p.k_rowptr, kc, p.k_val)
+    kc = p.k_col.copy()
+    kc[b - 1] = p.n
+    cases["column out of range"] = (p.k_rowptr, kc, p.k_val)
+    kv = p.k_val.copy()
+    kv[a + 2] = np.nan
+    cases["NaN value"] = (p.k_rowptr, p.k_col, kv)
+    kp = p.k_rowptr.copy()
+    kp[r + 1] = kp[r + 2] + 1
+    cases["row pointer decreasing"] = (kp, p.k_col, p.k_val)
+    kp = p.k_rowptr.copy()
+    kp[r + 1] = kp[-1] + 50
+    cases["row pointer past the end"] = (kp, p.k_col, p.k_val)
+    for what, (kp, kc, kv) in cases.items():
+        with pytest.raises(D.DpcgError) as e:
+            setup(kp, kc, kv)
+        assert e.value.code == D.abi.EINVAL, what
+    zc = p.z_col.copy()
+    zc[3] = p.k
+    with pytest.raises(D.DpcgError) as e:
+        setup(p.k_rowptr, p.k_col, p.k_val, zc)
+    assert e.value.code == D.abi.EINVAL
+    with setup(p.k_rowptr, p.k_col, p.k_val) as s:   # the well-formed arrays still work
+        u, info = s.solve(dev(p.f))
+        assert info["status"] == D.abi.OK
