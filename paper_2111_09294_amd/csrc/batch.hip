@@ -169,11 +169,23 @@ __device__ __forceinline__ double col_sum_cm(const double *__restrict__ part, in
 
 // alpha_j = rho_j / p_j^T q_j for the running columns (breakdown test as in Algorithm 1);
 // workgroup j reduces column j of the SpMM partials.
-__global__ __launch_bounds__(256) void k_balpha(const double *__restrict__ part, int nparts, BatchState *st) {
-    __shared__ double lds[4];
+__global__ __launch_bounds__(1024) void k_balpha(const double *__restrict__ part, int nparts, BatchState *st) {
+    __shared__ double lds[16];
     if (!st->any) return;
     const int j = blockIdx.x;
-    const double pq = col_sum_cm(part, nparts, j, lds);
+    double pq;
+    {  // fixed-order sum of column j over 1024 threads
+        const double *pc = part + (int64_t)j * nparts;
+        double s = 0.0;
+        for (int w = threadIdx.x; w < nparts; w += 1024) s += pc[w];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+        __syncthreads();
+        pq = 0.0;
+#pragma unroll
+        for (int h = 0; h < 16; h += 2) pq += lds[h] + lds[h + 1];
+    }
     if (threadIdx.x == 0 && st->flag[j] == kRunning) {
         const int it = st->iter;
         const double a = st->rho[it & 1][j] / pq;
@@ -209,26 +221,56 @@ __global__ __launch_bounds__(256) void k_bupdate_bj(int32_t ntiles, int32_t nwg,
     for (int t = t0; t < t1; ++t) {
         const int64_t d0 = tile_start[t], d1 = tile_start[t + 1];
         __syncthreads();
-        for (int64_t d = d0 + g; d < d1; d += 8) {
-            const int64_t o = d * W + j;
-            double rn = r[o];
-            if (run) {
-                u[o] = fma(alpha, p[o], u[o]);
-                rn = fma(-alpha, q[o], rn);
-                r[o] = rn;
+        // four DoFs of the group at a time: all loads first, then the updates
+        for (int64_t db = d0 + g; db < d1; db += 32) {
+            double rv[4], pv[4], qv[4], uv[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int64_t d = db + 8 * h, o = d * W + j;
+                rv[h] = pv[h] = qv[h] = uv[h] = 0.0;
+                if (d < d1) {
+                    rv[h] = r[o];
+                    if (run) {
+                        pv[h] = p[o];
+                        qv[h] = q[o];
+                        uv[h] = u[o];
+                    }
+                }
             }
-            tile[d - d0][j] = rn;
-            acc = fma(rn, rn, acc);
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int64_t d = db + 8 * h, o = d * W + j;
+                if (d >= d1) continue;
+                double rn = rv[h];
+                if (run) {
+                    u[o] = fma(alpha, pv[h], uv[h]);
+                    rn = fma(-alpha, qv[h], rn);
+                    r[o] = rn;
+                }
+                tile[d - d0][j] = rn;
+                acc = fma(rn, rn, acc);
+            }
         }
         __syncthreads();
-        for (int64_t d = d0 + g; d < d1; d += 8) {
-            const int meta = bj_meta[d];
-            const int size = meta >> 8, loc = meta & 255;
-            const double *mrow = minv + bj_rowoff[d];
-            const int base = (int)(d - d0) - loc;
-            double s = 0.0;
-            for (int kk = 0; kk < size; ++kk) s = fma(mrow[kk], tile[base + kk][j], s);
-            y[d * W + j] = s;
+        for (int64_t db = d0 + g; db < d1; db += 32) {
+            int meta[4], ro[4];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int64_t d = db + 8 * h;
+                meta[h] = d < d1 ? bj_meta[d] : 0;
+                ro[h] = d < d1 ? bj_rowoff[d] : 0;
+            }
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const int64_t d = db + 8 * h;
+                if (d >= d1) continue;
+                const int size = meta[h] >> 8, loc = meta[h] & 255;
+                const double *mrow = minv + ro[h];
+                const int base = (int)(d - d0) - loc;
+                double s = 0.0;
+                for (int kk = 0; kk < size; ++kk) s = fma(mrow[kk], tile[base + kk][j], s);
+                y[d * W + j] = s;
+            }
         }
     }
     const double tot = group_sum_8(acc, lds);
@@ -364,14 +406,22 @@ __global__ __launch_bounds__(64 * kCoarseWaves) void k_bcoarse(int32_t k, int64_
     const int s0 = (int)(((int64_t)wv * steps) / kCoarseWaves), s1 = (int)(((int64_t)(wv + 1) * steps) / kCoarseWaves);
     const double *erow = einv + (int64_t)min(row, k - 1) * ld;
     bdbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int st4 = s0; st4 < s1; ++st4) {
-        const int c = 4 * st4 + kq;
-        const bool ok = c < k && row < k;
-        const double a = ok ? erow[c] : 0.0;
-        const double *gr = gin + (int64_t)min(c, k - 1) * W;
-        const double b0 = c < k ? gr[l & 15] : 0.0, b1 = c < k ? gr[16 + (l & 15)] : 0.0;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc1, 0, 0, 0);
+    for (int sb = s0; sb < s1; sb += 4) {  // four steps' loads in flight, then their products
+        double a[4], b0[4], b1[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = 4 * (sb + u) + kq;
+            const bool ok = sb + u < s1 && c < k;
+            const double *gr = gin + (int64_t)min(c, k - 1) * W;
+            a[u] = ok && row < k ? erow[min(c, k - 1)] : 0.0;
+            b0[u] = ok ? gr[l & 15] : 0.0;
+            b1[u] = ok ? gr[16 + (l & 15)] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b0[u], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b1[u], acc1, 0, 0, 0);
+        }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -406,8 +456,32 @@ __global__ __launch_bounds__(256) void k_bprolong(int64_t n, int32_t nwg, const 
         const int64_t o = d * W + j;
         double s = base ? base[o] : 0.0;
         double c = 0.0;
-        if (delta)
-            for (int e = z_ptr[d]; e < z_ptr[d + 1]; ++e) c = fma(z_val[e], delta[(int64_t)z_col[e] * W + j], c);
+        if (delta) {
+            // lane j loads entry j of the row (one coalesced load); the column indices are
+            // passed round by shuffles and up to eight delta rows are gathered at a time
+            const int e0 = z_ptr[d], cnt = z_ptr[d + 1] - e0;
+            for (int b0 = 0; b0 < cnt; b0 += 32) {
+                int col = 0;
+                double v = 0.0;
+                if (b0 + j < cnt) {
+                    col = z_col[e0 + b0 + j];
+                    v = z_val[e0 + b0 + j];
+                }
+                const int m = min(32, cnt - b0);  // the same for the whole group
+                for (int q0 = 0; q0 < m; q0 += 8) {
+                    double x[8], vq[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) {
+                        const int cq = __shfl(col, q0 + q, 32);
+                        vq[q] = __shfl(v, q0 + q, 32);
+                        x[q] = q0 + q < m ? delta[(int64_t)cq * W + j] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (q0 + q < m) c = fma(vq[q], x[q], c);
+                }
+            }
+        }
         s += c;
         out[o] = s;
         if (rdot) acc = fma(rdot[o], s, acc);
@@ -686,7 +760,7 @@ int enqueue_biteration(dpcg_ctx *c, int max_iter, std::vector<hipEvent_t> &ev, s
                           c->bcol, (const double *)c->bval, (const double *)b->p, (const double *)nullptr, b->q,
                           b->part, (const BatchState *)st);
     BHIP(hipGetLastError());
-    BLAUNCH(k_balpha, dim3(W), dim3(256), 0, c->stream, (const double *)b->part, b->spmm_nwg, st);
+    BLAUNCH(k_balpha, dim3(W), dim3(1024), 0, c->stream, (const double *)b->part, b->spmm_nwg, st);
     BLAUNCH(k_bupdate_bj, dim3(b->upd_nwg), dim3(256), 0, c->stream, c->bjb_ntiles, b->upd_nwg, c->bjb_start, b->u,
             b->r, b->y, (const double *)b->q, (const double *)b->p, (const double *)c->minv, c->bj_rowoff, c->bj_meta,
             b->part2, (const BatchState *)st, 1);
