@@ -201,8 +201,8 @@ int dpcg_solve_many(dpcg_handle *handles, int32_t count, const double *const *F,
                     double tol, const dpcg_options *opt, dpcg_info *infos);
 
 /*
- * New values of K on the sparsity pattern of the setup (Sec. 4: as the crack grows,
- * only the blocks of nodes whose enrichment changes need new factors).  k_rowptr,
+ * New values of K on the sparsity pattern of the setup (Sec. 3.4: as the crack grows,
+ * only the blocks that hold enriched DoFs need new factors).  k_rowptr,
  * k_col, k_val as in dpcg_setup; the pattern (rows, columns, block structure) must be
  * the one the handle was set up with.  The block values, the symmetry test, K Z, E and
  * E^{-1} are rebuilt; the block-Jacobi inverses only of the nchanged blocks listed in
