@@ -225,7 +225,7 @@ int dpcg_autotune(dpcg_handle h, int32_t reps);
 void dpcg_destroy(dpcg_handle h);
 
 /* Device memory of destroyed handles is cached by the library and reused by later
- * setups on the same device; this returns all cached memory to the driver. */
+ * setups on the same device; this returns all cached memory to the HIP runtime. */
 void dpcg_release_cached_memory(void);
 
 /* Static description of a status code. */

@@ -1,6 +1,6 @@
 // Process-wide cache of device memory blocks.  Setting up a handle needs a few dozen
 // arrays; a solver that is set up once per system (a crack-growth step) would otherwise
-// pay the driver's allocation and release cost every time.  Blocks are released only
+// pay the HIP runtime's allocation and release cost every time.  Blocks are released only
 // after the stream that used them has been synchronised, so a cached block is idle and
 // may be handed to any stream.
 #include <hip/hip_runtime.h>
