@@ -31,11 +31,11 @@ HBM_PEAK_GBS = 8000.0
 SPMV_TRAFFIC = {
     "workload": "penny40",
     "sources": {
-        "paper_2111_09294_amd/csrc/kernels.hip": "7b786c6f6cf8f44abdaf114b32ab4815a0357efb1e45502e6e263c0dea7c4bb1",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "33065377bea269dc4e76ccbeec9b62af5ac2ade8f14c450337a14f7594445b05"
+        "paper_2111_09294_amd/csrc/kernels.hip": "70bd4dbe31e4aa337690e3d5d3858d099bc90b3772a153a796fda438a4f4a463",
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "5b54d913be5132b6108a63a74b6dec1f72e731c33c7de3acca7ec6dfe0ef3549"
     },
-    "fetch_bytes": 171097547,
-    "write_bytes": 2028798,
+    "fetch_bytes": 171041948,
+    "write_bytes": 2023189,
 }
 
 
