@@ -67,12 +67,37 @@ void dev_release(void *p) {
     c.idle[it->second].push_back(p);
 }
 
+// Pinned host blocks for the setup's read-backs of sizes and flags: a device-to-host
+// copy into pinned memory stays asynchronous, so several of them share one stream
+// synchronisation.  Cached like the device blocks (device -1 in the key).
+hipError_t host_alloc(void **p, size_t bytes) {
+    const size_t sz = round_size(bytes ? bytes : 1);
+    Cache &c = cache();
+    {
+        std::lock_guard<std::mutex> lk(c.m);
+        auto it = c.idle.find({-1, sz});
+        if (it != c.idle.end() && !it->second.empty()) {
+            *p = it->second.back();
+            it->second.pop_back();
+            return hipSuccess;
+        }
+    }
+    hipError_t e = hipHostMalloc(p, sz, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(c.m);
+    c.owner[*p] = {-1, sz};
+    return hipSuccess;
+}
+
+void host_release(void *p) { dev_release(p); }
+
 void dev_trim() {
     Cache &c = cache();
     std::lock_guard<std::mutex> lk(c.m);
     for (auto &kv : c.idle)
         for (void *p : kv.second) {
-            (void)hipFree(p);
+            if (kv.first.first < 0) (void)hipHostFree(p);
+            else (void)hipFree(p);
             c.owner.erase(p);
         }
     c.idle.clear();

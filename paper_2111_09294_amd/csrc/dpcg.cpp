@@ -90,24 +90,24 @@ int alloc(dpcg_ctx *c, T **dst, size_t count) {
     } while (0)
 
 int alloc_workspace(dpcg_ctx *c, Workspace &w) {
-    const size_t n = (size_t)c->n;
-    TRY(alloc(c, &w.r, n));
-    TRY(alloc(c, &w.y, n));
-    TRY(alloc(c, &w.z, n));
-    TRY(alloc(c, &w.q, n));
-    TRY(alloc(c, &w.p[0], n));
-    TRY(alloc(c, &w.p[1], n));
-    TRY(alloc(c, &w.tmp, n));
-    TRY(alloc(c, &w.g, (size_t)std::max(1, c->k)));
-    TRY(alloc(c, &w.delta, (size_t)std::max(1, c->k)));
+    const size_t n = (size_t)c->n, kk = (size_t)std::max(1, c->k);
     // partial sums for the largest SpMV grid any lane-group size can choose (autotuner)
     const int spmv_max = std::min<int>(16384, (int)((c->nb + 7) / 8) + 8);
     const size_t np = (size_t)std::max({spmv_max, c->spmv.nwg, c->bj_nwg, c->vec_nwg, 1});
     c->part_cap = (int32_t)np;
-    TRY(alloc(c, &w.part_a, np));
-    TRY(alloc(c, &w.part_b, np));
-    TRY(alloc(c, &w.part_c, np));
-    TRY(alloc(c, &w.st, 1));
+    // one allocation (one zero fill) carved into 256-byte aligned arrays
+    double **vec[] = {&w.r, &w.y, &w.z, &w.q, &w.p[0], &w.p[1], &w.tmp};
+    double **kv[] = {&w.g, &w.delta};
+    double **pv[] = {&w.part_a, &w.part_b, &w.part_c};
+    auto up = [](size_t bytes) { return (bytes + 255) & ~size_t(255); };
+    const size_t total = 7 * up(8 * n) + 2 * up(8 * kk) + 3 * up(8 * np) + up(sizeof(State));
+    char *base = nullptr;
+    TRY(alloc(c, &base, total));
+    size_t off = 0;
+    for (double **d : vec) { *d = (double *)(base + off); off += up(8 * n); }
+    for (double **d : kv) { *d = (double *)(base + off); off += up(8 * kk); }
+    for (double **d : pv) { *d = (double *)(base + off); off += up(8 * np); }
+    w.st = (State *)(base + off);
     w.snap = take_pinned_state();
     if (!w.snap) return DPCG_EHIP;
     return DPCG_OK;

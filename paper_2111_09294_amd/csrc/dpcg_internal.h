@@ -271,6 +271,8 @@ int element_gradient(dpcg_ctx *c, int64_t nel, const int64_t *ep, const int32_t 
 // devmem.cpp: cached device allocations (release only after the using stream is idle).
 hipError_t dev_alloc(void **p, size_t bytes);
 void dev_release(void *p);
+hipError_t host_alloc(void **p, size_t bytes);  // pinned host memory, same cache
+void host_release(void *p);
 void dev_trim();
 
 // setup.hip: all setup factorisations on the GPU; returns a DPCG_* status.

@@ -1340,9 +1340,19 @@ __global__ void k_cmp_i32(int64_t n, const int32_t *__restrict__ a, const int32_
 struct Pool {
     dpcg_ctx *c;
     std::vector<void *> scratch;
+    std::vector<void *> pinned;  // host read-back buffers (pinned, so the copies stay asynchronous)
     ~Pool() {
         (void)hipStreamSynchronize(c->stream);
         for (void *p : scratch) dev_release(p);
+        for (void *p : pinned) host_release(p);
+    }
+    template <class T>
+    hipError_t host(T **p, size_t count) {
+        void *q = nullptr;
+        hipError_t e = host_alloc(&q, std::max<size_t>(1, count) * sizeof(T));
+        if (e == hipSuccess) pinned.push_back(q);
+        *p = (T *)q;
+        return e;
     }
     template <class T>
     hipError_t tmp(T **p, size_t count) {
@@ -1413,15 +1423,16 @@ hipError_t scan(hipStream_t s, const int64_t *a, int64_t n, int64_t *out, int64_
 // row windows of K z_j (wlo on the device, ws on the host).  reuse: the arrays of a
 // previous build are overwritten (same structure) instead of allocated.
 int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const int32_t *zc, const int64_t *ztp,
-                    const int32_t *zti, const double *ztv, const int64_t *wlo, const std::vector<int64_t> &ws,
-                    int64_t *part, int *flags, int64_t *bad, bool reuse) {
+                    const int32_t *zti, const double *ztv, const int64_t *wl, const int64_t *ws, int64_t *part,
+                    int *flags, int64_t *bad, bool reuse) {
     hipStream_t s = c->stream;
-    int fl[4];
+    int *fl = nullptr;  // pinned read-backs: fl[0..4), nkz, cf
+    int64_t *nkzp = nullptr;
+    HT(pool.host(&fl, 5));
+    HT(pool.host(&nkzp, 1));
     {
         // ---- K Z and E, in batches of kBatch vectors; batch groups bound the scratch ----
-        std::vector<int64_t> wl(k);
-        HT(hipMemcpyAsync(wl.data(), wlo, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
-        HT(hipStreamSynchronize(s));
+        // (wl, ws: host copies of the row windows of K z_j)
         const int nbat = (k + kBatch - 1) / kBatch;
         const int words = (k + 31) / 32;
         std::vector<KzBatch> bt(nbat);
@@ -1501,10 +1512,10 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         }
         hipLaunchKernelGGL(k_kzb_offsets, dim3(nbat), dim3(kBatch), 0, s, bt_d, nbat, scnt, soff, kzcnt);
         HT(scan(s, kzcnt, k, kzp, part));
-        int64_t nkz = 0;
-        HT(hipMemcpyAsync(&nkz, kzp + k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+        HT(hipMemcpyAsync(nkzp, kzp + k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HT(hipMemcpyAsync(fl, flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
+        const int64_t nkz = *nkzp;
         if (fl[3] != INT32_MAX) return DPCG_ENOTSYM;
         if (fl[1] != INT32_MAX) {
             *bad = fl[1];
@@ -1560,10 +1571,9 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
             HT(keep(c, &c->kzt_ptr, k + 1));
             hipLaunchKernelGGL(k_to_i32, dim3(grid_for(k + 1)), dim3(256), 0, s, kzp, (int64_t)k + 1, c->kzt_ptr);
         }
-        int cf = 0;
-        HT(hipMemcpyAsync(&cf, cfail, sizeof(int), hipMemcpyDeviceToHost, s));
+        HT(hipMemcpyAsync(fl + 4, cfail, sizeof(int), hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
-        if (cf) return DPCG_ECOARSE_NOT_SPD;
+        if (fl[4]) return DPCG_ECOARSE_NOT_SPD;
         return DPCG_OK;
     }
 }
@@ -1619,11 +1629,11 @@ int dense_inverses(dpcg_ctx *c, Pool &pool, const int64_t *kp, const int32_t *kc
 
 // The dense-block tables from the host copy of the partition: extents, offsets in dinv,
 // and the apply's workgroups (kDenseRows rows of one block each).
-int dense_tables(dpcg_ctx *c, const std::vector<int32_t> &bph) {
+int dense_tables(dpcg_ctx *c, const int32_t *bph, int32_t nblocks) {
     hipStream_t s = c->stream;
     c->dense_h.clear();
     int64_t off = 0;
-    for (size_t b = 0; b + 1 < bph.size(); ++b) {
+    for (int32_t b = 0; b < nblocks; ++b) {
         const int32_t m = bph[b + 1] - bph[b];
         if (m <= kMaxBlock) continue;
         const int32_t ld = (m + kNb - 1) / kNb * kNb;
@@ -1654,7 +1664,13 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     hipStream_t s = c->stream;
     Pool pool{c, {}};
     // ---- sizes ----
-    int64_t ends[4] = {0, 0, 0, 0};
+    int64_t *ends = nullptr;  // pinned read-backs of the setup
+    int *fl = nullptr;
+    int64_t *tot = nullptr;
+    HT(pool.host(&ends, 4));
+    HT(pool.host(&fl, 5));
+    HT(pool.host(&tot, 2));
+    ends[2] = ends[3] = 0;
     HT(hipMemcpyAsync(&ends[0], kp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HT(hipMemcpyAsync(&ends[1], kp + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     if (k > 0) {
@@ -1681,16 +1697,16 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     hipLaunchKernelGGL(k_check_blocks, dim3(grid_for(nblocks)), dim3(256), 0, s, nblocks, bp, n, flags + 2,
                        flags + 4);
     HT(hipGetLastError());
-    int fl[5];
-    HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    HT(hipMemcpyAsync(fl, flags, sizeof(int) * 5, hipMemcpyDeviceToHost, s));
     HT(hipStreamSynchronize(s));
     if (fl[2] != INT32_MAX) *bad = fl[2];
     if (fl[0] != INT32_MAX || fl[1] != INT32_MAX || fl[2] != INT32_MAX) return DPCG_EINVAL;
     if (fl[4] > kMaxBlock) {
-        std::vector<int32_t> bph(nblocks + 1);
-        HT(hipMemcpyAsync(bph.data(), bp, sizeof(int32_t) * (nblocks + 1), hipMemcpyDeviceToHost, s));
+        int32_t *bph = nullptr;
+        HT(pool.host(&bph, nblocks + 1));
+        HT(hipMemcpyAsync(bph, bp, sizeof(int32_t) * (nblocks + 1), hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
-        const int st = dense_tables(c, bph);
+        const int st = dense_tables(c, bph, nblocks);
         if (st != DPCG_OK) return st;
     }
     maxpart = mxk;
@@ -1746,12 +1762,16 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
         hipLaunchKernelGGL(k_kz_window, dim3(k), dim3(256), 0, s, k, ztp, zti, kp, kc, wlo, wsize);
         HT(hipGetLastError());
     }
-    int64_t tot[2];
-    std::vector<int64_t> ws(k > 0 ? k : 0);
+    int64_t *ws = nullptr, *wl = nullptr;
+    HT(pool.host(&ws, k));
+    HT(pool.host(&wl, k));
     HT(hipMemcpyAsync(&tot[0], bptr64 + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HT(hipMemcpyAsync(&tot[1], moff + nblocks, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
-    if (k > 0) HT(hipMemcpyAsync(ws.data(), wsize, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+    HT(hipMemcpyAsync(fl, flags, sizeof(int) * 5, hipMemcpyDeviceToHost, s));
+    if (k > 0) {
+        HT(hipMemcpyAsync(ws, wsize, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+        HT(hipMemcpyAsync(wl, wlo, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+    }
     HT(hipStreamSynchronize(s));
     const int64_t nnzb = tot[0];
     if (nnzb > (int64_t)INT32_MAX || tot[1] > (int64_t)INT32_MAX) return DPCG_EINVAL;
@@ -1824,14 +1844,14 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     }
     HT(hipGetLastError());
     if (k > 0) {
-        const int st = coarse_operator(c, pool, k, zp, zc, ztp, zti, ztv, wlo, ws, part, flags, bad, false);
+        const int st = coarse_operator(c, pool, k, zp, zc, ztp, zti, ztv, wl, ws, part, flags, bad, false);
         if (st != DPCG_OK) return st;
         // transposed pointers as int32
         HT(keep(c, &c->zt_ptr, k + 1));
         hipLaunchKernelGGL(k_to_i32, dim3(grid_for(k + 1)), dim3(256), 0, s, ztp, (int64_t)k + 1, c->zt_ptr);
         HT(hipStreamSynchronize(s));
     } else {
-        HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+        HT(hipMemcpyAsync(fl, flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
         if (fl[3] != INT32_MAX) return DPCG_ENOTSYM;
         if (fl[1] != INT32_MAX) {
@@ -1853,7 +1873,10 @@ int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const d
     if (list_host)
         for (int32_t i = 0; i < nlist; ++i)
             if (list_host[i] < 0 || list_host[i] >= nblocks) return DPCG_EINVAL;
-    int64_t ends[2] = {0, 0};
+    int64_t *ends = nullptr;  // pinned read-backs
+    int *fl = nullptr;
+    HT(pool.host(&ends, 2));
+    HT(pool.host(&fl, 4));
     HT(hipMemcpyAsync(&ends[0], kp, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HT(hipMemcpyAsync(&ends[1], kp + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HT(hipStreamSynchronize(s));
@@ -1865,8 +1888,7 @@ int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const d
     HT(hipMemcpyAsync(flags, init_flags, sizeof(init_flags), hipMemcpyHostToDevice, s));
     double *mxp = nullptr;
     HT(check_csr(s, pool, n, n, kp, kc, kv, nnz, flags, &mxp));
-    int fl[4];
-    HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    HT(hipMemcpyAsync(fl, flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
     HT(hipStreamSynchronize(s));
     if (fl[0] != INT32_MAX) return DPCG_EINVAL;
     // the CSR arrays are valid: the block structure must be the stored one
@@ -1875,7 +1897,7 @@ int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const d
     hipLaunchKernelGGL((k_bsr<false>), dim3(grid_for(nb, 4)), dim3(256), 0, s, nb, kp, kc, kv, cnt, nullptr, nullptr,
                        nullptr, nullptr);
     hipLaunchKernelGGL(k_cmp_counts, dim3(grid_for(nb)), dim3(256), 0, s, nb, cnt, c->brow_ptr, flags + 2);
-    HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    HT(hipMemcpyAsync(fl, flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
     HT(hipStreamSynchronize(s));
     if (fl[2] != INT32_MAX) return DPCG_EINVAL;
     // max |K| for the symmetry tolerance: mxp[0], from the checks above
@@ -1932,7 +1954,7 @@ int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const d
         if (st != DPCG_OK) return st;
     }
     HT(hipGetLastError());
-    HT(hipMemcpyAsync(fl, flags, sizeof(fl), hipMemcpyDeviceToHost, s));
+    HT(hipMemcpyAsync(fl, flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
     HT(hipStreamSynchronize(s));
     if (fl[2] != INT32_MAX) return DPCG_EINVAL;
     if (k > 0) {
@@ -1945,10 +1967,13 @@ int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const d
         hipLaunchKernelGGL(k_to_i64, dim3(grid_for(k + 1)), dim3(256), 0, s, c->zt_ptr, (int64_t)k + 1, ztp);
         hipLaunchKernelGGL(k_to_i64, dim3(grid_for(n + 1)), dim3(256), 0, s, c->z_ptr, n + 1, zp);
         hipLaunchKernelGGL(k_kz_window, dim3(k), dim3(256), 0, s, k, ztp, c->zt_idx, kp, kc, wlo, wsize);
-        std::vector<int64_t> ws(k);
-        HT(hipMemcpyAsync(ws.data(), wsize, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+        int64_t *ws = nullptr, *wl = nullptr;
+        HT(pool.host(&ws, k));
+        HT(pool.host(&wl, k));
+        HT(hipMemcpyAsync(ws, wsize, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
+        HT(hipMemcpyAsync(wl, wlo, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
-        const int st = coarse_operator(c, pool, k, zp, c->z_col, ztp, c->zt_idx, c->zt_val, wlo, ws, part, flags, bad,
+        const int st = coarse_operator(c, pool, k, zp, c->z_col, ztp, c->zt_idx, c->zt_val, wl, ws, part, flags, bad,
                                        true);
         if (st != DPCG_OK) return st;
     } else {
