@@ -65,6 +65,12 @@ WORKLOADS = {
 }
 
 
+# The roofline's kernel duration comes from start/stop events recorded by every
+# TIMING_EVERY-th SpMV launch of the timed steps: events on each launch add about 8 us to
+# every iteration (0.8 ms per solve), sampling keeps the timed run close to an untimed one.
+TIMING_EVERY = 8
+
+
 def spmv_bytes(nnzb, n, value_bytes=8):
     """Algorithmic bytes of one q = K p launch: each 3x3 block (9 values + a 4 B column
     index) once, the block-row pointers, p read once and q written once."""
@@ -141,7 +147,7 @@ def run_batched(p, args, K, Z, bp, f, stream, nrhs=32):
     def step(timing):
         s = dpcg.Solver(p.n, *K, p.k, *Z, bp, stream=stream)
         if timing:
-            s.set_timing(True)
+            s.set_timing(True, every=TIMING_EVERY)
         _, infos = s.solve_batch(Fd, U, tol=1e-8)
         tm = s.timing() if timing else None
         s.close()
@@ -319,7 +325,7 @@ def main():
     def step(timing, precision="fp64"):
         s = dpcg.Solver(p.n, *K, p.k, *Z, bp, stream=stream)
         if timing:
-            s.set_timing(True)
+            s.set_timing(True, every=TIMING_EVERY)
         _, info = s.solve(f, u, tol=1e-8, precision=precision)
         tm = s.timing() if timing else None
         st = s.stats()

@@ -239,11 +239,13 @@ int dpcg_get_stats(dpcg_handle h, dpcg_stats *out);
  * how many were written (negative status on error). */
 int64_t dpcg_get_history(dpcg_handle h, double *out, int64_t cap);
 
-/* Kernel timing for roofline measurements: with on = 1 every solve brackets each
- * launch of the iteration's SpMV kernel (K p, the dominant kernel) with a pair of
- * HIP events on the handle's stream and accumulates the durations; on = 0 stops
- * timing.  Turning it on resets the counters.  The events add a few microseconds
- * of stream work per iteration. */
+/* Kernel timing for roofline measurements: with on = m >= 1 every solve brackets
+ * every m-th launch of the iteration's SpMV kernel (K p, the dominant kernel; m = 1:
+ * each launch) with a pair of HIP events recorded by the launch on the handle's
+ * stream, and accumulates the durations of the launches that did work; on = 0 stops
+ * timing, on < 0 is DPCG_EINVAL.  Turning it on resets the counters.  A timed launch
+ * adds about 8 us to its iteration (measured: 0.8 ms per 105-iteration solve with
+ * m = 1), so sampling every 8th launch keeps the measured run close to an untimed one. */
 int dpcg_set_timing(dpcg_handle h, int32_t on);
 int dpcg_get_timing(dpcg_handle h, dpcg_timing *out);
 

@@ -287,8 +287,9 @@ class Solver:
             raise DpcgError(st, "dpcg_get_stats")
         return s.as_dict()
 
-    def set_timing(self, on=True):
-        st = lib().dpcg_set_timing(self.handle, int(bool(on)))
+    def set_timing(self, on=True, every=1):
+        """Event timing of every `every`-th SpMV launch of the solves (off with on=False)."""
+        st = lib().dpcg_set_timing(self.handle, int(every) if on else 0)
         if st != OK:
             raise DpcgError(st, "dpcg_set_timing")
 

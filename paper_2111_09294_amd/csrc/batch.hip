@@ -741,11 +741,11 @@ int enqueue_bstart(dpcg_ctx *c, bool guess, int max_iter) {
     return DPCG_OK;
 }
 
-int enqueue_biteration(dpcg_ctx *c, int max_iter, std::vector<hipEvent_t> &ev, size_t &ev_used) {
+int enqueue_biteration(dpcg_ctx *c, int max_iter, std::vector<hipEvent_t> &ev, size_t &ev_used, int32_t index) {
     BatchWorkspace *b = c->bws;
     BatchState *st = b->st;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing) {
+    if (c->timing > 0 && index % c->timing == 0) {
         if (ev_used + 2 > ev.size())
             for (int i = 0; i < 32; ++i) {
                 hipEvent_t e;
@@ -828,7 +828,7 @@ int solve_batch(dpcg_ctx *c, int32_t nrhs, const double *F, double *U, double to
         int32_t enq = 0;
         while (st.any && enq < opt.max_iter) {
             const int m = std::min(opt.check_every, opt.max_iter - enq);
-            for (int i = 0; i < m; ++i) BTRY(enqueue_biteration(c, opt.max_iter, ev, ev_used));
+            for (int i = 0; i < m; ++i) BTRY(enqueue_biteration(c, opt.max_iter, ev, ev_used, enq + i));
             enq += m;
             BTRY(read_bstate(c, st));
         }
@@ -840,6 +840,7 @@ int solve_batch(dpcg_ctx *c, int32_t nrhs, const double *F, double *U, double to
         if (c->timing) {
             int32_t real = 0;
             for (int j = 0; j < nrhs; ++j) real = std::max(real, st.iters_done[j]);
+            real = (real + c->timing - 1) / c->timing;  // timed launches of working iterations
             for (size_t i = 0; i + 1 < ev_used && (int32_t)(i / 2) < real; i += 2) {
                 float ms = 0.f;
                 BHIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));

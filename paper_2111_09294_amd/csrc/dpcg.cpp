@@ -257,8 +257,9 @@ int collect_events(dpcg_ctx *c, int32_t real) {
     return DPCG_OK;
 }
 
-int enqueue_iteration(dpcg_ctx *c, Workspace &w, double *u, int max_iter, int record) {
-    if (c->timing) {
+// index: the iteration's position in this run (timing samples every c->timing-th one)
+int enqueue_iteration(dpcg_ctx *c, Workspace &w, double *u, int max_iter, int record, int32_t index) {
+    if (c->timing > 0 && index % c->timing == 0) {
         hipEvent_t a, b;
         TRY(next_event_pair(c, &a, &b));
         LAUNCH(launch_spmv_p(c, w, a, b));
@@ -290,12 +291,12 @@ int run_cg(dpcg_ctx *c, Workspace &w, const double *f, double *u, double thr, bo
     int32_t enq = 0;
     while (st.flag == kRunning && enq < max_iter) {
         const int m = std::min(check_every, max_iter - enq);
-        for (int i = 0; i < m; ++i) TRY(enqueue_iteration(c, w, u, max_iter, record));
+        for (int i = 0; i < m; ++i) TRY(enqueue_iteration(c, w, u, max_iter, record, enq + i));
         enq += m;
         TRY(read_state(c, w, st));
     }
     if (st.flag == kRunning) st.iters_done = enq;
-    if (c->timing) TRY(collect_events(c, st.iters_done));
+    if (c->timing > 0) TRY(collect_events(c, (st.iters_done + c->timing - 1) / c->timing));
     return DPCG_OK;
 }
 
@@ -813,8 +814,8 @@ int64_t dpcg_get_history(dpcg_handle h, double *out, int64_t cap) {
 }
 
 int dpcg_set_timing(dpcg_handle h, int32_t on) {
-    if (!h) return DPCG_EINVAL;
-    h->timing = on != 0;
+    if (!h || on < 0) return DPCG_EINVAL;
+    h->timing = on;
     h->events_used = 0;
     if (h->timing) {
         h->spmv_launches = 0;

@@ -210,7 +210,7 @@ struct dpcg_ctx {
     std::vector<void *> allocations;
     double setup_ms = 0.0;
     // optional event timing of the SpMV kernel
-    bool timing = false;
+    int32_t timing = 0;               // time every timing-th SpMV launch (0: off)
     std::vector<hipEvent_t> events;   // pairs (start, stop), reused per solve
     int32_t events_used = 0;
     int64_t spmv_launches = 0;

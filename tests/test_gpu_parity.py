@@ -381,3 +381,23 @@ def test_setup_rejects_malformed_csr(problems):
     with setup(p.k_rowptr, p.k_col, p.k_val) as s:   # the well-formed arrays still work
         u, info = s.solve(dev(p.f))
         assert info["status"] == D.abi.OK
+
+
+def test_spmv_timing_samples(pair):
+    """dpcg_set_timing(m): the SpMV launches of working iterations 0, m, 2m, ... are
+    timed; m = 0 turns timing off, m < 0 is refused."""
+    p, o, s = pair("edge10")
+    f = dev(p.f)
+    for every in (1, 8):
+        s.set_timing(True, every=every)
+        _, info = s.solve(f)
+        t = s.timing()
+        it = info["iterations"]
+        assert t["spmv_launches"] == (it + every - 1) // every
+        assert t["spmv_ms"] > 0.0
+    s.set_timing(False)
+    _, info = s.solve(f)
+    assert s.timing()["spmv_launches"] == (info["iterations"] + 7) // 8   # counters kept while off
+    with pytest.raises(D.DpcgError) as e:
+        s.set_timing(True, every=-1)
+    assert e.value.code == D.abi.EINVAL
