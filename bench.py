@@ -32,10 +32,10 @@ SPMV_TRAFFIC = {
     "workload": "penny40",
     "sources": {
         "paper_2111_09294_amd/csrc/kernels.hip": "70bd4dbe31e4aa337690e3d5d3858d099bc90b3772a153a796fda438a4f4a463",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "5b54d913be5132b6108a63a74b6dec1f72e731c33c7de3acca7ec6dfe0ef3549"
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "eca3b66702767347e3c8f685c18ec800347f4d46f2ed3be7fe278639c649bda8"
     },
-    "fetch_bytes": 171041948,
-    "write_bytes": 2023189,
+    "fetch_bytes": 171012982,
+    "write_bytes": 2025719,
 }
 
 
@@ -231,6 +231,66 @@ def run_many(args, count=16):
             "iterations_max": max(i["iterations"] for i in infos), "generation_s": t_gen}
 
 
+def run_large(name="penny80", steps=2):
+    """The FP64 path on the 80^3 configuration (1.66M DoFs): its matrix (1.38 GB of block
+    values) is far larger than the 256 MB last-level cache, so the SpMV figure there is
+    an HBM figure; at 40^3 an iteration's data (about 250 MB) can partly stay in that
+    cache.  Full steps (setup + solve to 1e-8), SpMV events on every 8th launch."""
+    import numpy as np
+    import torch
+
+    import paper_2111_09294_amd as dpcg
+    from fixtures import load
+
+    t_gen = time.perf_counter()
+    q = load(name)
+    t_gen = time.perf_counter() - t_gen
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    K = (t(q.k_rowptr, torch.int64), t(q.k_col, torch.int32), t(q.k_val, torch.float64))
+    Z = (t(q.z_rowptr, torch.int64), t(q.z_col, torch.int32), t(q.z_val, torch.float64))
+    bp = t(q.block_ptr, torch.int32)
+    f = t(q.f, torch.float64)
+    u = torch.empty_like(f)
+
+    def step(timing):
+        s = dpcg.Solver(q.n, *K, q.k, *Z, bp)
+        if timing:
+            s.set_timing(True, every=TIMING_EVERY)
+        _, info = s.solve(f, u, tol=1e-8)
+        tm = s.timing() if timing else None
+        st = s.stats()
+        s.close()
+        return info, tm, st
+
+    step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, spmv_ms, spmv_n = [], 0.0, 0
+    for _ in range(steps):
+        info, tm, st = step(True)
+        infos.append(info)
+        spmv_ms += tm["spmv_ms"]
+        spmv_n += tm["spmv_launches"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    per_launch_s = spmv_ms / 1e3 / max(spmv_n, 1)
+    nbytes = spmv_bytes(st["nnzb"], q.n)
+    achieved = nbytes / per_launch_s / 1e9
+    out = {"value": q.n * steps / dt, "unit": "DoF-solves/s", "workload": name, "n_dofs": q.n, "k": q.k,
+           "nnzb": st["nnzb"], "steps": steps, "ms_per_step": dt * 1e3 / steps,
+           "ok": all(i["status"] == 0 and i["rel_res_true"] <= 1.5e-8 for i in infos),
+           "iterations": infos[-1]["iterations"],
+           "setup_ms": float(np.mean([i["setup_ms"] for i in infos])),
+           "solve_ms": float(np.mean([i["solve_ms"] for i in infos])),
+           "spmv": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "bytes_per_launch": nbytes, "launches": spmv_n, "avg_launch_us": per_launch_s * 1e6},
+           "generation_s": t_gen}
+    del K, Z, bp, f, u, q
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_subdomain(args, p, nsds=(8, 4)):
     """The paper's subdomain-sized block-Jacobi blocks (Sec. 3.4): the same system
     renumbered subdomain by subdomain with one block per subdomain of an nsd^3 box
@@ -297,6 +357,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison line")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-right-hand-side comparison line")
     ap.add_argument("--no-subdomain", action="store_true", help="skip the subdomain-block comparison lines")
+    ap.add_argument("--no-large", action="store_true", help="skip the 80^3 FP64 line")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run N plain 512 MiB device copies (counter calibration)")
     args = ap.parse_args()
@@ -396,6 +457,8 @@ def main():
         out["many_systems"] = run_many(args)
     if not args.no_subdomain:
         out["subdomain_blocks"] = run_subdomain(args, p)
+    if not args.no_large:
+        out["large_80"] = run_large()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
