@@ -92,7 +92,7 @@ int alloc(dpcg_ctx *c, T **dst, size_t count) {
 int alloc_workspace(dpcg_ctx *c, Workspace &w) {
     const size_t n = (size_t)c->n, kk = (size_t)std::max(1, c->k);
     // partial sums for the largest SpMV grid any lane-group size can choose (autotuner)
-    const int spmv_max = std::min<int>(16384, (int)((c->nb + 7) / 8) + 8);
+    const int spmv_max = (int)((c->nb + 7) / 8) + 8;
     const size_t np = (size_t)std::max({spmv_max, c->spmv.nwg, c->bj_nwg, c->vec_nwg, 1});
     c->part_cap = (int32_t)np;
     // one allocation (one zero fill) carved into 256-byte aligned arrays
@@ -122,7 +122,7 @@ void set_spmv_group(dpcg_ctx *c, int g) {
     c->spmv.group = g;
     const int rows_per_step = 4 * 64 / g;  // 4 waves per SpMV workgroup
     c->spmv.steps = (int)((c->nb + rows_per_step - 1) / rows_per_step);
-    c->spmv.nwg = std::min(c->spmv.steps, 16384);
+    c->spmv.nwg = c->spmv.steps;  // one row step per workgroup (more per workgroup measured slower)
     if (c->spmv.nwg >= 8) c->spmv.nwg = (c->spmv.nwg + 7) & ~7;
 }
 
@@ -139,10 +139,10 @@ void choose_shapes(dpcg_ctx *c) {
     c->spmv.steps = (int)((c->nb + rows_per_step - 1) / rows_per_step);
     // one step per workgroup, rounded up to a multiple of 8 (XCD-aware mapping); the
     // extra workgroups find an empty step range
-    c->spmv.nwg = std::min(c->spmv.steps, 16384);
+    c->spmv.nwg = c->spmv.steps;  // one row step per workgroup (more per workgroup measured slower)
     if (c->spmv.nwg >= 8) c->spmv.nwg = (c->spmv.nwg + 7) & ~7;
     c->vec_nwg = round_grid((int)std::min<int64_t>((c->n + kThreads - 1) / kThreads, 1024));
-    c->bj_nwg = round_grid(std::min(c->bj_ntiles, 1024));
+    c->bj_nwg = round_grid(std::min(c->bj_ntiles, 65536));  // one tile each (partials reduced by one workgroup)
 }
 
 int setup_impl(dpcg_ctx *c, int64_t n, const int64_t *k_rowptr, const int32_t *k_col, const double *k_val,
