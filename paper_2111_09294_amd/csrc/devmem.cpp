@@ -91,6 +91,64 @@ hipError_t host_alloc(void **p, size_t bytes) {
 
 void host_release(void *p) { dev_release(p); }
 
+// A second stream per device for setup work that runs beside the main chain (default
+// priority, created once, kept until the process ends), and a pool of synchronisation
+// events (no timing) per device for the fork and join points.  Every setup takes its own
+// events, so setups of different handles on the same device may share the stream.
+namespace {
+struct SideCache {
+    std::mutex m;
+    std::unordered_map<int, hipStream_t> stream;
+    std::map<int, std::vector<hipEvent_t>> events;
+};
+SideCache &side_cache() {
+    static SideCache *c = new SideCache();
+    return *c;
+}
+}  // namespace
+
+hipError_t side_stream(hipStream_t *s) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    SideCache &c = side_cache();
+    std::lock_guard<std::mutex> lk(c.m);
+    auto it = c.stream.find(dev);
+    if (it != c.stream.end()) {
+        *s = it->second;
+        return hipSuccess;
+    }
+    e = hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+    if (e == hipSuccess) c.stream[dev] = *s;
+    return e;
+}
+
+hipError_t sync_event_take(hipEvent_t *ev) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    SideCache &c = side_cache();
+    {
+        std::lock_guard<std::mutex> lk(c.m);
+        auto &v = c.events[dev];
+        if (!v.empty()) {
+            *ev = v.back();
+            v.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipEventCreateWithFlags(ev, hipEventDisableTiming);
+}
+
+void sync_event_give(hipEvent_t ev) {
+    if (!ev) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    SideCache &c = side_cache();
+    std::lock_guard<std::mutex> lk(c.m);
+    c.events[dev].push_back(ev);
+}
+
 void dev_trim() {
     Cache &c = cache();
     std::lock_guard<std::mutex> lk(c.m);

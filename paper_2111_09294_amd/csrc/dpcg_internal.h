@@ -274,6 +274,11 @@ void dev_release(void *p);
 hipError_t host_alloc(void **p, size_t bytes);  // pinned host memory, same cache
 void host_release(void *p);
 void dev_trim();
+// a second stream of the current device for setup work beside the main chain, and
+// pooled synchronisation events (without timing) of the current device
+hipError_t side_stream(hipStream_t *s);
+hipError_t sync_event_take(hipEvent_t *ev);
+void sync_event_give(hipEvent_t ev);
 
 // setup.hip: all setup factorisations on the GPU; returns a DPCG_* status.
 int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, const double *kv, int32_t k,

@@ -1341,10 +1341,36 @@ struct Pool {
     dpcg_ctx *c;
     std::vector<void *> scratch;
     std::vector<void *> pinned;  // host read-back buffers (pinned, so the copies stay asynchronous)
+    // work enqueued on the side stream after fork() runs beside the main stream from that
+    // point on; join() makes the main stream wait for all of it
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool pending = false;
     ~Pool() {
+        if (pending) (void)hipStreamSynchronize(side);
         (void)hipStreamSynchronize(c->stream);
         for (void *p : scratch) dev_release(p);
         for (void *p : pinned) host_release(p);
+        sync_event_give(ev_fork);
+        sync_event_give(ev_join);
+    }
+    hipError_t fork(hipStream_t *sb) {
+        hipError_t e = side_stream(&side);
+        if (e == hipSuccess && !ev_fork) e = sync_event_take(&ev_fork);
+        if (e == hipSuccess && !ev_join) e = sync_event_take(&ev_join);
+        if (e == hipSuccess) e = hipEventRecord(ev_fork, c->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side, ev_fork, 0);
+        if (e != hipSuccess) return e;
+        pending = true;
+        *sb = side;
+        return hipSuccess;
+    }
+    hipError_t join() {
+        if (!pending) return hipSuccess;
+        hipError_t e = hipEventRecord(ev_join, side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, ev_join, 0);
+        if (e == hipSuccess) pending = false;
+        return e;
     }
     template <class T>
     hipError_t host(T **p, size_t count) {
@@ -1513,6 +1539,7 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         hipLaunchKernelGGL(k_kzb_offsets, dim3(nbat), dim3(kBatch), 0, s, bt_d, nbat, scnt, soff, kzcnt);
         HT(scan(s, kzcnt, k, kzp, part));
         HT(hipMemcpyAsync(nkzp, kzp + k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HT(pool.join());  // the symmetry and block flags are read here
         HT(hipMemcpyAsync(fl, flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
         const int64_t nkz = *nkzp;
@@ -1787,30 +1814,35 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(pool.tmp(&brow, nnzb));
     hipLaunchKernelGGL((k_bsr<true>), dim3(grid_for(nb, 4)), dim3(256), 0, s, nb, kp, kc, kv, nullptr, c->brow_ptr,
                        c->bcol, c->bval, brow);
-    {
-        const int gsym = (grid_for(nnzb, 256, 16384) + 7) / 8 * 8;
-        int64_t *sympart = nullptr;
-        int *need = nullptr;
-        HT(pool.tmp(&sympart, 2 * (int64_t)gsym));
-        HT(pool.tmp(&need, 1));
-        hipLaunchKernelGGL(k_check_sym, dim3(gsym), dim3(256), 0, s, c->brow_ptr, brow, c->bcol, c->bval, nnzb,
-                           maxpart, nmaxpart, flags, sympart);
-        hipLaunchKernelGGL(k_sym_reduce, dim3(1), dim3(256), 0, s, sympart, gsym, need);
-        hipLaunchKernelGGL(k_check_sym_lower, dim3(gsym), dim3(256), 0, s, c->brow_ptr, brow, c->bcol, c->bval, nnzb,
-                           maxpart, nmaxpart, flags, need);
-    }
+    // The symmetry test and the small block-Jacobi inverses do not feed K Z, E or E^-1:
+    // they run on the side stream beside that chain (whose kernels are latency bound and
+    // leave most of the chip idle), joined before their flags are read.  Dense blocks
+    // keep one stream.
+    hipStream_t sb = s;
+    if (c->ndense == 0) HT(pool.fork(&sb));
+    const int gsym = (grid_for(nnzb, 256, 16384) + 7) / 8 * 8;
+    int64_t *sympart = nullptr;
+    int *need = nullptr;
+    HT(pool.tmp(&sympart, 2 * (int64_t)gsym));
+    HT(pool.tmp(&need, 1));
     HT(keep(c, &c->minv, tot[1]));
     HT(keep(c, &c->bj_rowoff, n));
     HT(keep(c, &c->bj_meta, n));
+    hipLaunchKernelGGL(k_check_sym, dim3(gsym), dim3(256), 0, sb, c->brow_ptr, brow, c->bcol, c->bval, nnzb, maxpart,
+                       nmaxpart, flags, sympart);
+    hipLaunchKernelGGL(k_sym_reduce, dim3(1), dim3(256), 0, sb, sympart, gsym, need);
+    hipLaunchKernelGGL(k_check_sym_lower, dim3(gsym), dim3(256), 0, sb, c->brow_ptr, brow, c->bcol, c->bval, nnzb,
+                       maxpart, nmaxpart, flags, need);
     int *bjbad = flags + 1;  // reuse: Z's flag is known to be clear
     if (c->ndense > 0) {  // the DoFs of dense blocks take no part in the small-block kernels
         HT(hipMemsetAsync(c->bj_meta, 0, sizeof(int32_t) * n, s));
         HT(hipMemsetAsync(c->bj_rowoff, 0, sizeof(int32_t) * n, s));
     }
-    hipLaunchKernelGGL(k_bj_small, dim3(grid_for(nblocks)), dim3(256), 0, s, nblocks, bp, kp, kc, kv, moff, c->minv,
+    hipLaunchKernelGGL(k_bj_small, dim3(grid_for(nblocks)), dim3(256), 0, sb, nblocks, bp, kp, kc, kv, moff, c->minv,
                        c->bj_rowoff, c->bj_meta, bjbad, (const int32_t *)nullptr, 0);
-    hipLaunchKernelGGL(k_bj_factor, dim3(std::min<int32_t>(nblocks, 4096)), dim3(64), 0, s, nblocks, bp, kp, kc, kv,
+    hipLaunchKernelGGL(k_bj_factor, dim3(std::min<int32_t>(nblocks, 4096)), dim3(64), 0, sb, nblocks, bp, kp, kc, kv,
                        moff, c->minv, c->bj_rowoff, c->bj_meta, bjbad, (const int32_t *)nullptr, 0);
+    HT(hipGetLastError());
     if (c->ndense > 0) {
         std::vector<int32_t> all(c->ndense);
         for (int32_t i = 0; i < c->ndense; ++i) all[i] = i;
@@ -1851,6 +1883,7 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
         hipLaunchKernelGGL(k_to_i32, dim3(grid_for(k + 1)), dim3(256), 0, s, ztp, (int64_t)k + 1, c->zt_ptr);
         HT(hipStreamSynchronize(s));
     } else {
+        HT(pool.join());
         HT(hipMemcpyAsync(fl, flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
         if (fl[3] != INT32_MAX) return DPCG_ENOTSYM;
