@@ -1078,6 +1078,9 @@ __device__ void pivot_inverse(const double *S, int lds, double *W, const double 
     }
     bool bad = false;
     __syncthreads();
+    // unrolled by 8 only: fully unrolled it needs ~150 VGPRs, which would cap the occupancy
+    // of every sweep workgroup at 3 waves per SIMD (this routine is inlined into the sweeps)
+#pragma unroll 8
     for (int k = 0; k < kNb; ++k) {
         // all LDS reads of the step first (one wait), then selects instead of branches
         const int cb = k & 1, nb = cb ^ 1;
@@ -1153,48 +1156,66 @@ __device__ __forceinline__ int tile_col() { return ((threadIdx.x >> 6) & 1) * 16
 
 // One sweep with pivot block p: B = sweep(A).  Tile (I, J) of 32 x 32:
 //   I = J = p: P;  I = p: P A_pJ;  J = p: -A_Ip P;  else A_IJ - A_Ip (P A_pJ).
-// The workgroup of tile (p+1, p+1) also inverts the next pivot block.
+// Every tile is computed from its own formula: mirroring the tiles above the diagonal
+// from those below (the symmetric sweep operator, half the tiles) leaves the inverse as
+// close to E^-1 but makes E X - I about a thousand times larger on an ill-conditioned E,
+// and the deflated iteration then stalls at tight tolerances.  All global loads of a
+// tile are issued before the first LDS store, and P A_pJ reuses the LDS of A_pJ.  The
+// workgroup of tile (p+1, p+1) also inverts the next pivot block.
 __device__ __forceinline__ void gj_sweep_tile(int p, int nt, int I, int J, const double *__restrict__ A,
                                               double *__restrict__ B, int64_t ld, int32_t kdim,
                                               const double *__restrict__ Pcur, double *__restrict__ Pnext,
                                               const double *__restrict__ diag0, int *fail, int failval) {
-    __shared__ double Ps[kNb * kLd], X[kNb * kLd], Y[kNb * kLd], T[kNb * kLd];
+    __shared__ double Ps[kNb * kLd], X[kNb * kLd], Y[kNb * kLd];
     const int64_t r0 = (int64_t)I * kNb, c0 = (int64_t)J * kNb, q0 = (int64_t)p * kNb;
-    for (int t = threadIdx.x; t < kNb * kNb; t += 256) {
-        const int a = t / kNb, b = t % kNb;
-        Ps[a * kLd + b] = Pcur[t];
-        if (I != p) X[a * kLd + b] = A[(r0 + a) * ld + q0 + b];   // A_Ip
-        if (J != p) Y[a * kLd + b] = A[(q0 + a) * ld + c0 + b];   // A_pJ
+    const bool piv = I == p && J == p, rowp = !piv && I == p, colp = !piv && J == p;
+    const bool gen = !piv && !rowp && !colp;
+    const bool use_x = colp || gen, use_y = rowp || gen;  // X = A_Ip, Y = A_pJ
+    const int cc = tile_col();
+    double pr[4], xr[4], yr[4], sr[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int t = threadIdx.x + 256 * q, a = t / kNb, b = t % kNb;
+        pr[q] = Pcur[t];
+        xr[q] = use_x ? A[(r0 + a) * ld + q0 + b] : 0.0;
+        yr[q] = use_y ? A[(q0 + a) * ld + c0 + b] : 0.0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sr[v] = gen ? A[(r0 + tile_row(v)) * ld + c0 + cc] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int t = threadIdx.x + 256 * q, a = t / kNb, b = t % kNb;
+        Ps[a * kLd + b] = pr[q];
+        if (use_x) X[a * kLd + b] = xr[q];
+        if (use_y) Y[a * kLd + b] = yr[q];
     }
     __syncthreads();
-    const int cc = tile_col();
-    if (I == p && J == p) {
-        for (int t = threadIdx.x; t < kNb * kNb; t += 256) B[(r0 + t / kNb) * ld + c0 + t % kNb] = Pcur[t];
-    } else if (I == p) {
-        const dbl4 d = tile_mfma(Ps, Y);
+    dbl4 d;
+    if (piv) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) B[(r0 + tile_row(v)) * ld + c0 + cc] = d[v];
-    } else if (J == p) {
-        const dbl4 d = tile_mfma(X, Ps);
+        for (int v = 0; v < 4; ++v) d[v] = Ps[tile_row(v) * kLd + cc];
+    } else if (rowp) {
+        d = tile_mfma(Ps, Y);
+    } else if (colp) {
+        const dbl4 x4 = tile_mfma(X, Ps);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) B[(r0 + tile_row(v)) * ld + c0 + cc] = -d[v];
+        for (int v = 0; v < 4; ++v) d[v] = -x4[v];
     } else {
-        const dbl4 t4 = tile_mfma(Ps, Y);  // T = P A_pJ
-#pragma unroll
-        for (int v = 0; v < 4; ++v) T[tile_row(v) * kLd + cc] = t4[v];
-        __syncthreads();
-        const dbl4 d = tile_mfma(X, T);
+        const dbl4 t4 = tile_mfma(Ps, Y);  // P A_pJ, into Y once every wave has read Y
         __syncthreads();
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int rr = tile_row(v);
-            const int64_t g = (r0 + rr) * ld + c0 + cc;
-            const double nv = A[g] - d[v];
-            B[g] = nv;
-            Y[rr * kLd + cc] = nv;  // kept for the next pivot
-        }
+        for (int v = 0; v < 4; ++v) Y[tile_row(v) * kLd + cc] = t4[v];
+        __syncthreads();
+        const dbl4 x4 = tile_mfma(X, Y);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) d[v] = sr[v] - x4[v];
     }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) B[(r0 + tile_row(v)) * ld + c0 + cc] = d[v];
     if (I == p + 1 && J == p + 1) {
+        __syncthreads();  // every wave is done with Y
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Y[tile_row(v) * kLd + cc] = d[v];
         __syncthreads();
         pivot_inverse(Y, kLd, X, diag0, (int64_t)(p + 1) * kNb, kdim, Pnext, fail, failval);
     }
