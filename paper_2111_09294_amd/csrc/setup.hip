@@ -765,54 +765,91 @@ __global__ __launch_bounds__(256) void k_kzb_scatter(const KzBatch *__restrict__
     }
 }
 
-// block structure of K z_j: every block column of the block rows of z_j's triplets
+// block structure of K z_j: every block column of the block rows of z_j's triplets.  A
+// workgroup ORs the bits of its slice's block rows into an LDS window of the columns
+// around the slice (kMarkHalo triplets on either side) and then ORs each nonzero window
+// word into mk once; a column outside the window goes to mk directly.  Slices without a
+// flagged triplet return at once.
+constexpr int kMarkHalo = 7680;
+constexpr int kMarkWindow = kSlice + 2 * kMarkHalo;  // 16384 words, 64 KB of LDS
+
 __global__ __launch_bounds__(256) void k_kzb_mark(const KzBatch *__restrict__ bt, const int32_t *__restrict__ bptr,
                                                   const int32_t *__restrict__ bcol, const uint32_t *__restrict__ rb,
                                                   uint32_t *mk) {
+    __shared__ uint32_t win[kMarkWindow];
     const KzBatch B = bt[blockIdx.y];
     if (blockIdx.x >= B.nslice) return;
     const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
+    bool any = false;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) any = any || rb[B.off3 + t] != 0u;
+    if (!__syncthreads_or(any)) return;
+    for (int i = threadIdx.x; i < kMarkWindow; i += 256) win[i] = 0u;
+    __syncthreads();
+    const int64_t w0 = t0 - kMarkHalo;  // window column of win[0] (may be negative)
     for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
         const uint32_t bits = rb[B.off3 + t];
         if (!bits) continue;
         const int64_t R = B.lo3 + t;
         for (int64_t q = bptr[R]; q < bptr[R + 1]; ++q) {
             const int64_t c = (int64_t)bcol[q] - B.lo3;
-            if (c >= 0 && c < B.w3) atomicOr(&mk[B.off3 + c], bits);
+            if (c < 0 || c >= B.w3) continue;
+            const int64_t l = c - w0;
+            if (l >= 0 && l < kMarkWindow) atomicOr(&win[l], bits);
+            else atomicOr(&mk[B.off3 + c], bits);
         }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kMarkWindow; i += 256) {
+        const uint32_t v = win[i];
+        const int64_t c = w0 + i;
+        if (v && c >= 0 && c < B.w3) atomicOr(&mk[B.off3 + c], v);
     }
 }
 
-// per (slice, vector) counts of structure rows (three per structure triplet)
+// per (slice, vector) counts of structure rows (three per structure triplet), and per
+// slice the number of structure triplets (work items)
 __global__ __launch_bounds__(256) void k_kzb_count(const KzBatch *__restrict__ bt, const uint32_t *__restrict__ mk,
-                                                   int32_t *__restrict__ cnt) {
-    __shared__ int32_t c_s[kBatch];
+                                                   int32_t *__restrict__ cnt, int32_t *__restrict__ tcnt) {
+    __shared__ int32_t c_s[kBatch + 1];
     const KzBatch B = bt[blockIdx.y];
     if (blockIdx.x >= B.nslice) return;
-    if (threadIdx.x < kBatch) c_s[threadIdx.x] = 0;
+    if (threadIdx.x <= kBatch) c_s[threadIdx.x] = 0;
     __syncthreads();
     const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
-    int32_t mine[kBatch];
-    for (int b = 0; b < kBatch; ++b) mine[b] = 0;
+    int32_t mine[kBatch + 1];
+    for (int b = 0; b <= kBatch; ++b) mine[b] = 0;
     for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
         const uint32_t m = mk[B.off3 + t];
         for (int b = 0; b < kBatch; ++b) mine[b] += 3 * ((m >> b) & 1u);
+        mine[kBatch] += m != 0u;
     }
-    for (int b = 0; b < kBatch; ++b)
+    for (int b = 0; b <= kBatch; ++b)
         if (mine[b]) atomicAdd(&c_s[b], mine[b]);
     __syncthreads();
     if (threadIdx.x < kBatch) cnt[(B.slice0 + blockIdx.x) * kBatch + threadIdx.x] = c_s[threadIdx.x];
+    if (threadIdx.x == kBatch) tcnt[B.slice0 + blockIdx.x] = c_s[kBatch];
 }
 
-// slice offsets within each vector's structure, and the vector totals
+// Per batch (kBatch + 1 threads): thread b < ncol forms the slice offsets within vector
+// b's structure and the vector's total; thread kBatch forms each slice's first work item
+// (exclusive prefix of the triplet counts) and the batch's number of items.
 __global__ void k_kzb_offsets(const KzBatch *__restrict__ bt, int nbat, const int32_t *__restrict__ cnt,
-                              int32_t *__restrict__ soff, int64_t *__restrict__ kzcnt) {
+                              const int32_t *__restrict__ tcnt, int32_t *__restrict__ soff,
+                              int64_t *__restrict__ kzcnt, int32_t *__restrict__ icnt, int64_t *__restrict__ nitems) {
     const int bi = blockIdx.x;
     if (bi >= nbat) return;
     const KzBatch B = bt[bi];
     const int b = threadIdx.x;
-    if (b >= B.ncol) return;
     int64_t run = 0;
+    if (b == kBatch) {
+        for (int64_t sl = 0; sl < B.nslice; ++sl) {
+            icnt[B.slice0 + sl] = (int32_t)run;
+            run += tcnt[B.slice0 + sl];
+        }
+        nitems[bi] = run;
+        return;
+    }
+    if (b >= B.ncol) return;
     for (int64_t sl = 0; sl < B.nslice; ++sl) {
         soff[(B.slice0 + sl) * kBatch + b] = (int32_t)run;
         run += cnt[(B.slice0 + sl) * kBatch + b];
@@ -874,29 +911,6 @@ __global__ __launch_bounds__(256) void k_kzb_rank(const KzBatch *__restrict__ bt
                                   wave_cnt[3][threadIdx.x];
         __syncthreads();
     }
-}
-
-// per slice: number of structure triplets, and their exclusive prefix within the batch
-__global__ __launch_bounds__(256) void k_kzb_items(const KzBatch *__restrict__ bt, int nbat, const uint32_t *__restrict__ mk,
-                            int32_t *__restrict__ icnt, int64_t *__restrict__ nitems) {
-    const int bi = blockIdx.x;
-    if (bi >= nbat) return;
-    const KzBatch B = bt[bi];
-    __shared__ int32_t c_s;
-    int64_t run = 0;
-    for (int64_t sl = 0; sl < B.nslice; ++sl) {
-        if (threadIdx.x == 0) c_s = 0;
-        __syncthreads();
-        const int64_t t0 = sl * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
-        int32_t mine = 0;
-        for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) mine += mk[B.off3 + t] != 0u;
-        if (mine) atomicAdd(&c_s, mine);
-        __syncthreads();
-        if (threadIdx.x == 0) icnt[B.slice0 + sl] = (int32_t)run;
-        run += c_s;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) nitems[bi] = run;
 }
 
 // Compute pass: (K z_j) on the three rows of each structure triplet from the packed 3x3
@@ -1519,13 +1533,14 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         }
         gcut.push_back(nbat);
         KzBatch *bt_d = nullptr;
-        int32_t *scnt = nullptr, *soff = nullptr;
+        int32_t *scnt = nullptr, *soff = nullptr, *tcnt = nullptr;
         int64_t *kzcnt = nullptr, *kzp = nullptr;
         double *zd = nullptr, *kd = nullptr;
         uint32_t *mk = nullptr, *rbits = nullptr, *touched = nullptr;
         HT(pool.tmp(&bt_d, nbat));
         HT(hipMemcpyAsync(bt_d, bt.data(), sizeof(KzBatch) * nbat, hipMemcpyHostToDevice, s));
         HT(pool.tmp(&scnt, slices * kBatch));
+        HT(pool.tmp(&tcnt, slices));
         HT(pool.tmp(&soff, slices * kBatch));
         HT(pool.tmp(&kzcnt, k));
         HT(pool.tmp(&kzp, k + 1));
@@ -1555,9 +1570,10 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         for (size_t g = 0; g + 1 < gcut.size(); ++g) {
             prepare(gcut[g], gcut[g + 1]);
             hipLaunchKernelGGL(k_kzb_count, dim3(max_slices(gcut[g], gcut[g + 1]), gcut[g + 1] - gcut[g]), dim3(256),
-                               0, s, bt_d + gcut[g], mk, scnt);
+                               0, s, bt_d + gcut[g], mk, scnt, tcnt);
         }
-        hipLaunchKernelGGL(k_kzb_offsets, dim3(nbat), dim3(kBatch), 0, s, bt_d, nbat, scnt, soff, kzcnt);
+        hipLaunchKernelGGL(k_kzb_offsets, dim3(nbat), dim3(kBatch + 1), 0, s, bt_d, nbat, scnt, tcnt, soff, kzcnt,
+                           icnt, nitems);
         HT(scan(s, kzcnt, k, kzp, part));
         HT(hipMemcpyAsync(nkzp, kzp + k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         HT(pool.join());  // the symmetry and block flags are read here
@@ -1584,8 +1600,6 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         for (size_t g = 0; g + 1 < gcut.size(); ++g) {
             const int g0 = gcut[g], g1 = gcut[g + 1];
             if (gcut.size() > 2) prepare(g0, g1);  // one group: the count pass left it ready
-            hipLaunchKernelGGL(k_kzb_items, dim3(g1 - g0), dim3(256), 0, s, bt_d + g0, g1 - g0, mk, icnt,
-                               nitems + g0);
             hipLaunchKernelGGL(k_kzb_rank, dim3(max_slices(g0, g1), g1 - g0), dim3(256), 0, s, bt_d + g0, mk, soff,
                                icnt, kzp, items);
             hipLaunchKernelGGL(k_kzb_values, dim3(128, g1 - g0), dim3(256),
