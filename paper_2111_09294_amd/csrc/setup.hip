@@ -1003,6 +1003,29 @@ __global__ __launch_bounds__(256) void k_kzb_values(const KzBatch *__restrict__ 
 // Z[t, i] (K z_{j0+b})_t, for the vectors i flagged as touched.  One wave per (i,
 // batch); lanes stride over the rows of z_i inside the window, then a fixed-order
 // wave reduction.
+// First index in [a, e) whose entry is >= key (e if none), for an increasing array, by
+// the whole wave: each round tests 64 evenly spaced entries and keeps the one gap that
+// holds the answer, so a range of L entries takes about log_64 L rounds of one load.
+__device__ __forceinline__ int64_t wave_lower_bound(const int32_t *__restrict__ v, int64_t a, int64_t e,
+                                                    int64_t key) {
+    const int lane = threadIdx.x & 63;
+    int64_t lo = a, hi = e;  // the answer lies in [lo, hi]
+    while (lo < hi) {
+        const int64_t step = (hi - lo + 63) / 64;
+        const int64_t idx = lo + lane * step;
+        const bool below = idx < hi && (int64_t)v[idx] < key;
+        const int nless = __popcll(__ballot(below));  // the samples below key form a prefix
+        if (nless == 0) {
+            hi = lo;
+        } else {
+            const int64_t nlo = lo + (int64_t)(nless - 1) * step + 1;
+            hi = min(hi, lo + (int64_t)nless * step);
+            lo = nlo;
+        }
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(256) void k_kzb_erows(const KzBatch *__restrict__ bt, int32_t k,
                                                    const int64_t *__restrict__ ztp, const int32_t *__restrict__ zti,
                                                    const double *__restrict__ ztv, const double *__restrict__ kd,
@@ -1016,22 +1039,9 @@ __global__ __launch_bounds__(256) void k_kzb_erows(const KzBatch *__restrict__ b
     const int64_t lo = 3 * B.lo3, w = 3 * B.w3;
     int64_t a = ztp[i], e = ztp[i + 1];
     if (a == e || zti[e - 1] < lo || zti[a] >= lo + w) return;
-    {  // first entry with row >= lo, first with row >= lo + w
-        int64_t l = a, h = e;
-        while (l < h) {
-            const int64_t mid = (l + h) >> 1;
-            if (zti[mid] < lo) l = mid + 1;
-            else h = mid;
-        }
-        a = l;
-        h = e;
-        while (l < h) {
-            const int64_t mid = (l + h) >> 1;
-            if (zti[mid] < lo + w) l = mid + 1;
-            else h = mid;
-        }
-        e = l;
-    }
+    // the entries of z_i with rows in the window: [first row >= lo, first row >= lo + w)
+    e = wave_lower_bound(zti, a, e, lo + w);
+    a = wave_lower_bound(zti, a, e, lo);
     double acc[kBatch];
     for (int b = 0; b < kBatch; ++b) acc[b] = 0.0;
     for (int64_t q = a + lane; q < e; q += 64) {
