@@ -317,6 +317,12 @@ __device__ int row_distinct(int64_t a, int64_t e, const int32_t *__restrict__ id
     return count;
 }
 
+// Block-CSR of K, one wave per block row R (its scalar rows 3R, 3R+1, 3R+2).  FILL false:
+// the number of distinct block columns; FILL true: block columns, block rows and the nine
+// value planes.  Rows of at most 128 entries each (nearly all) are read once, all three
+// rows' loads in one round, and ranked from registers with ballots; longer rows are ranked
+// chunk by chunk from memory.  Rows whose three scalar rows do not share one block-column
+// set take the serial merge of lane 0.
 template <bool FILL>
 __global__ __launch_bounds__(256) void k_bsr(int32_t nb, const int64_t *__restrict__ ptr, const int32_t *__restrict__ idx,
                                              const double *__restrict__ val, int64_t *__restrict__ cnt,
@@ -324,13 +330,49 @@ __global__ __launch_bounds__(256) void k_bsr(int32_t nb, const int64_t *__restri
                                              double *__restrict__ bval, int32_t *__restrict__ brow) {
     __shared__ int32_t dcol_s[4][3][kMaxDistinct];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
     for (int64_t R = blockIdx.x * 4ll + wv; R < nb; R += (int64_t)gridDim.x * 4) {
         int64_t a[3], e[3];
-        int dn[3];
         for (int i = 0; i < 3; ++i) {
             a[i] = ptr[3 * R + i];
             e[i] = ptr[3 * R + i + 1];
-            dn[i] = row_distinct(a[i], e[i], idx, dcol_s[wv][i]);
+        }
+        const bool small = e[0] - a[0] <= 128 && e[1] - a[1] <= 128 && e[2] - a[2] <= 128;
+        int dn[3];
+        unsigned long long bal[3][2] = {{0ull, 0ull}, {0ull, 0ull}, {0ull, 0ull}};
+        double cv[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+        int32_t ci[3][2];
+        if (small) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int64_t p = a[i] + 64 * c + lane;
+                    const bool in = p < e[i];
+                    ci[i][c] = in ? idx[p] : -3;
+                    if (FILL) cv[i][c] = in ? val[p] : 0.0;
+                }
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                int count = 0;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int32_t cur = ci[i][c];
+                    // the previous entry of the row: lane - 1 of this chunk, or lane 63 of the last
+                    int32_t prev = __shfl_up(cur, 1);
+                    const int32_t last = __shfl(ci[i][0], 63);
+                    if (lane == 0) prev = c == 0 ? -3 : last;
+                    const bool in = a[i] + 64 * c + lane < e[i];
+                    const bool first = in && (prev < 0 || prev / 3 != cur / 3);
+                    bal[i][c] = __ballot(first);
+                    const int rank = count + __popcll(bal[i][c] & below);
+                    if (first && rank < kMaxDistinct) dcol_s[wv][i][rank] = cur / 3;
+                    count += __popcll(bal[i][c]);
+                }
+                dn[i] = count;
+            }
+        } else {
+            for (int i = 0; i < 3; ++i) dn[i] = row_distinct(a[i], e[i], idx, dcol_s[wv][i]);
         }
         wave_sync();
         bool same = dn[0] == dn[1] && dn[1] == dn[2] && dn[0] <= kMaxDistinct;
@@ -347,18 +389,32 @@ __global__ __launch_bounds__(256) void k_bsr(int32_t nb, const int64_t *__restri
                     bcol[beg + t] = dcol_s[wv][0][t];
                     brow[beg + t] = (int32_t)R;
                 }
-                for (int i = 0; i < 3; ++i) {
-                    int count = 0;
-                    for (int64_t base = a[i]; base < e[i]; base += 64) {
-                        const int64_t p = base + lane;
-                        const bool in = p < e[i];
-                        const int32_t c = in ? idx[p] : 0;
-                        const bool first = in && (p == a[i] || idx[p - 1] / 3 != c / 3);
-                        const unsigned long long bal = __ballot(first);
-                        // rank of p's block column = number of first entries up to and including p, minus 1
-                        const int rank = count + __popcll(bal & ((2ull << lane) - 1ull)) - 1;
-                        if (in) bval[9 * beg + (int64_t)(3 * i + c % 3) * m + rank] = val[p];
-                        count += __popcll(bal);
+                if (small) {
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) {
+                        int count = 0;
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            // rank of the entry's block column: first entries up to and including it, minus 1
+                            const int rank = count + __popcll(bal[i][c] & (below | (1ull << lane))) - 1;
+                            if (a[i] + 64 * c + lane < e[i])
+                                bval[9 * beg + (int64_t)(3 * i + ci[i][c] % 3) * m + rank] = cv[i][c];
+                            count += __popcll(bal[i][c]);
+                        }
+                    }
+                } else {
+                    for (int i = 0; i < 3; ++i) {
+                        int count = 0;
+                        for (int64_t base = a[i]; base < e[i]; base += 64) {
+                            const int64_t p = base + lane;
+                            const bool in = p < e[i];
+                            const int32_t c = in ? idx[p] : 0;
+                            const bool first = in && (p == a[i] || idx[p - 1] / 3 != c / 3);
+                            const unsigned long long bl = __ballot(first);
+                            const int rank = count + __popcll(bl & ((2ull << lane) - 1ull)) - 1;
+                            if (in) bval[9 * beg + (int64_t)(3 * i + c % 3) * m + rank] = val[p];
+                            count += __popcll(bl);
+                        }
                     }
                 }
             }
@@ -1249,7 +1305,11 @@ __global__ __launch_bounds__(256) void k_gj_sweep(int p, int nt, const double *_
                                                   int64_t ld, int32_t kdim, const double *__restrict__ Pcur,
                                                   double *__restrict__ Pnext, const double *__restrict__ diag0,
                                                   int *fail) {
-    gj_sweep_tile(p, nt, blockIdx.x / nt, blockIdx.x % nt, A, B, ld, kdim, Pcur, Pnext, diag0, fail, -1);
+    // tiles rotated so that the next pivot tile (p+1, p+1), whose workgroup also runs the
+    // pivot inversion (the critical path of the sweep), is dispatched first
+    const int ntt = nt * nt;
+    const int t = (int)((blockIdx.x + (int64_t)(p + 1) * (nt + 1)) % ntt);
+    gj_sweep_tile(p, nt, t / nt, t % nt, A, B, ld, kdim, Pcur, Pnext, diag0, fail, -1);
 }
 
 // ---------------------------------------------------------------- dense blocks
