@@ -645,22 +645,18 @@ __global__ __launch_bounds__(64) void k_bj_factor(int32_t nblocks, const int32_t
 // tile t = blocks starting in [t * window, (t+1) * window); start = first such block,
 // or t * window itself when that DoF lies inside a block of more than kMaxBlock DoFs
 // (their rows need no neighbours in the tile), so a tile holds < window + kMaxBlock DoFs.
+// One thread per block b <= nblocks (bp[nblocks] = n): the targets t * window in
+// (bp[b-1], bp[b]] have b as their first block starting at or after the target, so b
+// writes those tiles (usually none or one) and no thread searches.
 __global__ void k_tiles(int32_t ntiles, int32_t nblocks, const int32_t *__restrict__ bp, int64_t n,
                         int32_t window, int32_t *__restrict__ tile_start) {
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t <= ntiles; t += gridDim.x * blockDim.x) {
-        if (t == ntiles) {
-            tile_start[t] = (int32_t)n;
-            continue;
-        }
-        const int64_t target = (int64_t)t * window;
-        int lo = 0, hi = nblocks;  // first block with start >= target
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (bp[mid] < target) lo = mid + 1;
-            else hi = mid;
-        }
-        if (lo > 0 && bp[lo - 1] < target && bp[lo] - bp[lo - 1] > kMaxBlock) tile_start[t] = (int32_t)target;
-        else tile_start[t] = lo < nblocks ? bp[lo] : (int32_t)n;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b <= nblocks; b += gridDim.x * blockDim.x) {
+        const int64_t hi = bp[b];
+        const int64_t t0 = b == 0 ? 0 : (int64_t)bp[b - 1] / window + 1;
+        const int64_t t1 = min<int64_t>(ntiles - 1, hi / window);
+        const bool split = b > 0 && hi - bp[b - 1] > kMaxBlock;  // the target lies inside block b - 1
+        for (int64_t t = t0; t <= t1; ++t) tile_start[t] = split ? (int32_t)(t * window) : (int32_t)hi;
+        if (b == nblocks) tile_start[ntiles] = (int32_t)n;
     }
 }
 
@@ -1961,12 +1957,12 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(hipMemcpyAsync(c->bj_moff, moff, sizeof(int64_t) * (nblocks + 1), hipMemcpyDeviceToDevice, s));
     c->bj_ntiles = (int32_t)((n + kTileDofs - 1) / kTileDofs);
     HT(keep(c, &c->bj_wg_start, c->bj_ntiles + 1));
-    hipLaunchKernelGGL(k_tiles, dim3(grid_for(c->bj_ntiles + 1)), dim3(256), 0, s, c->bj_ntiles, nblocks, bp, n,
+    hipLaunchKernelGGL(k_tiles, dim3(grid_for((int64_t)nblocks + 1)), dim3(256), 0, s, c->bj_ntiles, nblocks, bp, n,
                        kTileDofs, c->bj_wg_start);
     // the multi-RHS kernels stage tiles of <= kBatchTileDofs DoFs times 32 columns
     c->bjb_ntiles = (int32_t)((n + kBatchTileWindow - 1) / kBatchTileWindow);
     HT(keep(c, &c->bjb_start, c->bjb_ntiles + 1));
-    hipLaunchKernelGGL(k_tiles, dim3(grid_for(c->bjb_ntiles + 1)), dim3(256), 0, s, c->bjb_ntiles, nblocks, bp, n,
+    hipLaunchKernelGGL(k_tiles, dim3(grid_for((int64_t)nblocks + 1)), dim3(256), 0, s, c->bjb_ntiles, nblocks, bp, n,
                        kBatchTileWindow, c->bjb_start);
     // Z by rows (int32 row pointer) for the prolongation
     HT(keep(c, &c->z_ptr, n + 1));
