@@ -32,10 +32,10 @@ SPMV_TRAFFIC = {
     "workload": "penny40",
     "sources": {
         "paper_2111_09294_amd/csrc/kernels.hip": "70bd4dbe31e4aa337690e3d5d3858d099bc90b3772a153a796fda438a4f4a463",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "eca3b66702767347e3c8f685c18ec800347f4d46f2ed3be7fe278639c649bda8"
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "5b40e7e70f09d3111cf29ee700c351d070c313171f337e0093fac1ec0ef25372"
     },
-    "fetch_bytes": 171012982,
-    "write_bytes": 2025719,
+    "fetch_bytes": 171118563,
+    "write_bytes": 2027321,
 }
 
 
