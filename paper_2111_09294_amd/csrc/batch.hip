@@ -32,19 +32,27 @@ __device__ __forceinline__ int32_t wg_any(const BatchState *st) {
     return v;
 }
 
-// Fixed-order column sums of nparts rows of part (row-major, W columns) by a
-// 1024-thread workgroup: thread (g, j) sums rows g, g + 32, ...; the 32 group sums are
-// then added in order.  Valid in threads j < W.
-__device__ __forceinline__ double col_reduce_1024(const double *__restrict__ part, int nparts, double (*lds)[W + 1]) {
+// Fixed-order column sums of nparts rows of part (row-major, W columns): partial sum h
+// (h < 32) adds rows h, h + 32, ..., and the 32 partial sums are then added in order.  A
+// workgroup of 32 NG threads computes partial sums h = g, g + NG, ... in lane group g,
+// so the result does not depend on NG.  Valid in threads j < W.
+template <int NG>
+__device__ __forceinline__ double col_reduce(const double *__restrict__ part, int nparts, double (*lds)[W + 1]) {
     const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
-    double s = 0.0;
-    for (int w = g; w < nparts; w += 32) s += part[(int64_t)w * W + j];
-    lds[g][j] = s;
+    for (int h = g; h < 32; h += NG) {
+        double s = 0.0;
+        for (int w = h; w < nparts; w += 32) s += part[(int64_t)w * W + j];
+        lds[h][j] = s;
+    }
     __syncthreads();
     double t = 0.0;
     if (threadIdx.x < W)
         for (int h = 0; h < 32; ++h) t += lds[h][threadIdx.x];
     return t;
+}
+
+__device__ __forceinline__ double col_reduce_1024(const double *__restrict__ part, int nparts, double (*lds)[W + 1]) {
+    return col_reduce<32>(part, nparts, lds);
 }
 
 // Same over the 8 groups of a 256-thread workgroup (values v of group g, lane j).
@@ -277,9 +285,46 @@ __global__ __launch_bounds__(256) void k_bupdate_bj(int32_t ntiles, int32_t nwg,
     if (update && threadIdx.x < W) part[(int64_t)blockIdx.x * W + threadIdx.x] = tot;
 }
 
-// Column checks (workgroup 0, when n_rr > 0): ||r_j|| from the row-major partials
-// against thr_j and the iteration cap; any = some column still running.  Then the
-// merged right-hand side of Algorithm 3 in segments: segment s of deflation vector c
+// Column checks by workgroup 0 of a restriction launch (32 NG threads): ||r_j|| from the
+// row-major partials against thr_j and the iteration cap, then any = some column still
+// running.
+template <int NG>
+__device__ void column_check(BatchState *st, const double *__restrict__ part_rr, int n_rr, int iter_offset,
+                             int max_iter, double (*lds)[W + 1]) {
+    const int j = threadIdx.x & 31;
+    const double rr = col_reduce<NG>(part_rr, n_rr, lds);
+    __shared__ int32_t run_s[W];
+    if (threadIdx.x < W) {
+        int32_t fl = st->flag[j];
+        if (fl == kRunning) {
+            const int done = st->iter + iter_offset;
+            st->rr[j] = rr;
+            if (!isfinite(rr)) {
+                fl = kBreakdown;
+                st->bad[j] = st->iter;
+            } else if (sqrt(rr) <= st->thr[j]) {
+                fl = kConverged;
+            } else if (done >= max_iter) {
+                fl = kMaxIter;
+            }
+            if (fl != kRunning) {
+                st->flag[j] = fl;
+                st->iters_done[j] = done;
+            }
+        }
+        run_s[j] = fl == kRunning;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t any = 0;
+        for (int h = 0; h < W; ++h) any |= run_s[h];
+        st->any = any;
+    }
+    __syncthreads();
+}
+
+// Workgroup 0 runs the column checks when n_rr > 0.  Then the merged right-hand side
+// of Algorithm 3 in segments: segment s of deflation vector c
 // sums Z^T[c, e] a[e][j] over its entries (list 0) or -(KZ)^T[c, e] b[e][j] (list 1; 0
 // when b is null) into seg_part[s][j].  Group g of 32 lanes takes the chunks of 32
 // entries g, g + 32, ...: lane j loads entry j of the chunk (one coalesced load of
@@ -297,37 +342,7 @@ __global__ __launch_bounds__(1024) void k_brestrict(const int32_t *__restrict__ 
     const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
     if (st) {
         if (wg_any(st) == 0) return;
-        if (blockIdx.x == 0 && n_rr > 0) {
-            const double rr = col_reduce_1024(part_rr, n_rr, lds);
-            __shared__ int32_t run_s[W];
-            if (threadIdx.x < W) {
-                int32_t fl = st->flag[j];
-                if (fl == kRunning) {
-                    const int done = st->iter + iter_offset;
-                    st->rr[j] = rr;
-                    if (!isfinite(rr)) {
-                        fl = kBreakdown;
-                        st->bad[j] = st->iter;
-                    } else if (sqrt(rr) <= st->thr[j]) {
-                        fl = kConverged;
-                    } else if (done >= max_iter) {
-                        fl = kMaxIter;
-                    }
-                    if (fl != kRunning) {
-                        st->flag[j] = fl;
-                        st->iters_done[j] = done;
-                    }
-                }
-                run_s[j] = fl == kRunning;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                int32_t any = 0;
-                for (int h = 0; h < W; ++h) any |= run_s[h];
-                st->any = any;
-            }
-            __syncthreads();
-        }
+        if (blockIdx.x == 0 && n_rr > 0) column_check<32>(st, part_rr, n_rr, iter_offset, max_iter, lds);
     }
     const int sg = xcd_remap(blockIdx.x, gridDim.x);
     if (sg >= nseg) return;
@@ -386,13 +401,139 @@ __global__ __launch_bounds__(256) void k_bsegsum(int32_t k, const int32_t *__res
     gout[(int64_t)c * W + j] = t;
 }
 
+// ---- grouped restriction on the matrix cores ----
+// Runs of consecutive deflation vectors whose Z columns cover the same DoF triplets (the
+// rigid-body modes of one subdomain, or those restricted to one enrichment function's
+// DoFs) and whose (KZ)^T rows coincide form groups of up to kGroupCols vectors.  Z is
+// kept per group as a dense kg x L block over the group's triplet rows (zeros where a
+// mode has no component; column c's L values follow column c - 1's), as (KZ)^T already
+// is, so
+//   G[group] = Z_g^T a[rows_g] - (KZ)_g^T b[rows'_g]
+// is a dense (kg x L) by (L x 32) product: every gathered row of a or b serves all kg
+// vectors at once, where the per-entry kernel gathers it once per vector.
+typedef double bdbl4 __attribute__((ext_vector_type(4)));
+constexpr int kGroupCols = 16;    // vectors of a group (one MFMA row tile)
+constexpr int kGroupRows = 128;   // rows of a group's list per segment (one wave)
+constexpr int kGroupUnroll = 8;   // 4-row MFMA steps whose loads are issued together
+constexpr int kGroupSeg = 7;      // ints per segment record
+
+// flag[j] = 1 when column j of (ptr, idx) lists the same rows as column j - 1 (flag[0] =
+// 0); one wave per column.
+__global__ __launch_bounds__(256) void k_same_rows(int32_t k, const int32_t *__restrict__ ptr,
+                                                   const int32_t *__restrict__ idx, uint8_t *__restrict__ flag) {
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (j >= k) return;
+    bool same = false;
+    if (j > 0) {
+        const int a0 = ptr[j - 1], a1 = ptr[j], len = a1 - a0;
+        same = len == ptr[j + 1] - a1;
+        if (same) {
+            bool mine = true;
+            for (int e = lane; e < len; e += 64) mine = mine && idx[a0 + e] == idx[a1 + e];
+            same = __ballot(!mine) == 0ull;
+        }
+    }
+    if (lane == 0) flag[j] = same ? 1 : 0;
+}
+
+// One wave per segment gseg[7 s ..] = (first vector j0, vectors kg, list 0 = the dense
+// group blocks of Z (rows zr, values zv) / 1 = (KZ)^T, first row-list entry of the
+// segment, its first value for vector j0, rows, row-list length L): 4 rows per
+// v_mfma_f64_16x16x4f64 step, a = value of vector m = l % 16 at row l / 16 of the step
+// (0 for m >= kg), b = row l / 16 of the vector at columns l % 16 and 16 + l % 16 (two
+// 16-column halves).  The row indices and values of kGroupUnroll steps are loaded
+// before their row gathers.  Rows m < kg of the result go to seg_part[s][m][.],
+// negated for list 1 (0 when b is null).  Workgroup 0 runs the column checks.
+constexpr int kGroupWaves = 16;  // segments (waves) per workgroup of the grouped restriction
+
+__global__ __launch_bounds__(64 * kGroupWaves) void k_brestrict_mfma(const int32_t *__restrict__ gseg, int32_t ngseg,
+                                                        const int32_t *__restrict__ zr,
+                                                        const double *__restrict__ zv,
+                                                        const int32_t *__restrict__ kzt_idx,
+                                                        const double *__restrict__ kzt_val,
+                                                        const double *__restrict__ a, const double *__restrict__ b,
+                                                        double *__restrict__ seg_part, BatchState *st,
+                                                        const double *__restrict__ part_rr, int n_rr, int iter_offset,
+                                                        int max_iter) {
+    __shared__ double lds[32][W + 1];
+    if (st) {
+        if (wg_any(st) == 0) return;
+        if (blockIdx.x == 0 && n_rr > 0) column_check<2 * kGroupWaves>(st, part_rr, n_rr, iter_offset, max_iter, lds);
+    }
+    const int sg = xcd_remap(blockIdx.x, gridDim.x) * kGroupWaves + (threadIdx.x >> 6), l = threadIdx.x & 63;
+    if (sg >= ngseg) return;
+    const int32_t *G = gseg + kGroupSeg * sg;
+    const int kg = G[1], list = G[2], ibeg = G[3], vbeg = G[4], nrows = G[5], L = G[6];
+    const int32_t *idx = list ? kzt_idx : zr;
+    const double *val = list ? kzt_val : zv;
+    const double *vec = list ? b : a;
+    const int m = l & 15, kk = l >> 4, mm = min(m, kg - 1);
+    bdbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    if (vec) {
+        const int nsteps = (nrows + 3) / 4;
+        for (int s0 = 0; s0 < nsteps; s0 += kGroupUnroll) {
+            int32_t ri[kGroupUnroll];
+            double av[kGroupUnroll];
+#pragma unroll
+            for (int u = 0; u < kGroupUnroll; ++u) {
+                const int r = 4 * (s0 + u) + kk, rc = min(r, nrows - 1);  // past the end: the last row, masked
+                ri[u] = idx[ibeg + rc];
+                const double v = val[vbeg + (int64_t)mm * L + rc];
+                av[u] = (r < nrows && m < kg) ? v : 0.0;
+            }
+            double b0[kGroupUnroll], b1[kGroupUnroll];
+#pragma unroll
+            for (int u = 0; u < kGroupUnroll; ++u) {
+                const double *row = vec + (int64_t)ri[u] * W;
+                b0[u] = row[m];
+                b1[u] = row[16 + m];
+            }
+#pragma unroll
+            for (int u = 0; u < kGroupUnroll; ++u) {
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b0[u], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], b1[u], acc1, 0, 0, 0);
+            }
+        }
+    }
+    const double sgn = list ? -1.0 : 1.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int mo = kk + 4 * v;  // result item v of lane l: row l / 16 + 4 v, column l % 16
+        if (mo < kg) {
+            double *o = seg_part + ((int64_t)sg * kGroupCols + mo) * W;
+            o[m] = sgn * acc0[v];
+            o[16 + m] = sgn * acc1[v];
+        }
+    }
+}
+
+// g[c][j] = sum over the segments gcol[3c] .. gcol[3c+1]-1 of c's group of their partial
+// row gcol[3c+2], in segment order (8 vectors per workgroup).
+__global__ __launch_bounds__(256) void k_bgroupsum(int32_t k, const int32_t *__restrict__ gcol,
+                                                   const double *__restrict__ seg_part, double *__restrict__ gout,
+                                                   const BatchState *st) {
+    if (st && !st->any) return;
+    const int c = blockIdx.x * 8 + (threadIdx.x >> 5), j = threadIdx.x & 31;
+    if (c >= k) return;
+    const int s0 = gcol[3 * c], s1 = gcol[3 * c + 1], mo = gcol[3 * c + 2];
+    double t = 0.0;
+    for (int sg = s0; sg < s1; sg += 8) {  // eight loads in flight, added in segment order
+        double x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = sg + q < s1 ? seg_part[((int64_t)(sg + q) * kGroupCols + mo) * W + j] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (sg + q < s1) t += x[q];
+    }
+    gout[(int64_t)c * W + j] = t;
+}
+
 // delta = E^{-1} g for all 32 columns on the matrix cores: workgroup = 16 rows of
 // E^{-1}; wave w of 8 takes the w-th eighth of the contraction index c in steps of 4
 // (v_mfma_f64_16x16x4f64: a = E^{-1}[row l % 16][c + l / 16], b = g[c + l / 16][col],
 // two 16-column halves), then the eight partial tiles are added in wave order in LDS.
 // Result item v of lane l is row l / 16 + 4 v, column l % 16 of a half.
 constexpr int kCoarseWaves = 8;
-typedef double bdbl4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(64 * kCoarseWaves) void k_bcoarse(int32_t k, int64_t ld,
                                                                const double *__restrict__ einv,
                                                                const double *__restrict__ gin,
@@ -675,7 +816,94 @@ int ensure_ws(dpcg_ctx *c) {
     sptr[c->k] = b->nseg;
     BTRY(balloc(c, &b->seg, std::max<size_t>(4, seg.size())));
     BTRY(balloc(c, &b->seg_ptr, (size_t)c->k + 1));
-    BTRY(balloc(c, &b->seg_part, (size_t)std::max(1, b->nseg) * W));
+    // groups of consecutive vectors whose Z columns cover the same triplets and whose
+    // (KZ)^T rows coincide; the grouped kernel is used when they hold two vectors or more
+    // on average
+    std::vector<int32_t> gseg, gcol(3 * (size_t)std::max(1, c->k), 0), zr;
+    std::vector<double> zv;
+    if (c->k > 0) {
+        const int64_t nz = zp[c->k];
+        std::vector<int32_t> zi(std::max<int64_t>(1, nz));
+        std::vector<double> zval(std::max<int64_t>(1, nz));
+        std::vector<uint8_t> fk(c->k);
+        void *fl_d = nullptr;
+        BHIP(dev_alloc(&fl_d, (size_t)c->k));
+        hipLaunchKernelGGL(k_same_rows, dim3((c->k + 3) / 4), dim3(256), 0, c->stream, c->k, c->kzt_ptr, c->kzt_idx,
+                           (uint8_t *)fl_d);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(fk.data(), fl_d, fk.size(), hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && nz > 0)
+            e = hipMemcpyAsync(zi.data(), c->zt_idx, sizeof(int32_t) * nz, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && nz > 0)
+            e = hipMemcpyAsync(zval.data(), c->zt_val, sizeof(double) * nz, hipMemcpyDeviceToHost, c->stream);
+        const hipError_t es = hipStreamSynchronize(c->stream);
+        dev_release(fl_d);
+        if (e != hipSuccess || es != hipSuccess) return DPCG_EHIP;
+        // the triplets of column j (its rows are increasing, so equal triplets are adjacent)
+        auto triplets = [&](int j, std::vector<int32_t> &t) {
+            t.clear();
+            for (int32_t q = zp[j]; q < zp[j + 1]; ++q)
+                if (t.empty() || t.back() != zi[q] / 3) t.push_back(zi[q] / 3);
+        };
+        std::vector<int32_t> tprev, tcur, pos;
+        int ngroups = 0;
+        for (int j0 = 0; j0 < c->k;) {
+            triplets(j0, tprev);
+            int j1 = j0 + 1;
+            while (j1 < c->k && j1 - j0 < kGroupCols && fk[j1]) {
+                triplets(j1, tcur);
+                if (tcur != tprev) break;
+                ++j1;
+            }
+            const int kg = j1 - j0, s0 = (int)(gseg.size() / kGroupSeg);
+            // dense Z block of the group: rows 3t, 3t + 1, 3t + 2 of its triplets t
+            const int32_t L = 3 * (int32_t)tprev.size(), r_off = (int32_t)zr.size(), v_off = (int32_t)zv.size();
+            for (int32_t t : tprev)
+                for (int i = 0; i < 3; ++i) zr.push_back(3 * t + i);
+            zv.resize(zv.size() + (size_t)kg * L, 0.0);
+            for (int m = 0; m < kg; ++m) {
+                size_t ti = 0;
+                for (int32_t q = zp[j0 + m]; q < zp[j0 + m + 1]; ++q) {
+                    while (tprev[ti] != zi[q] / 3) ++ti;  // both increasing; every triplet is present
+                    zv[v_off + (size_t)m * L + 3 * ti + zi[q] % 3] = zval[q];
+                }
+            }
+            for (int32_t r0 = 0; r0 < L; r0 += kGroupRows) {
+                const int32_t rec[kGroupSeg] = {j0, kg, 0, r_off + r0, v_off + r0, std::min(kGroupRows, L - r0), L};
+                gseg.insert(gseg.end(), rec, rec + kGroupSeg);
+            }
+            const int32_t e0 = kp[j0], len = kp[j0 + 1] - e0;
+            for (int32_t r0 = 0; r0 < len; r0 += kGroupRows) {
+                const int32_t rec[kGroupSeg] = {j0, kg, 1, e0 + r0, e0 + r0, std::min(kGroupRows, len - r0), len};
+                gseg.insert(gseg.end(), rec, rec + kGroupSeg);
+            }
+            const int s1 = (int)(gseg.size() / kGroupSeg);
+            for (int cc = j0; cc < j1; ++cc) {
+                gcol[3 * cc] = s0;
+                gcol[3 * cc + 1] = s1;
+                gcol[3 * cc + 2] = cc - j0;
+            }
+            ++ngroups;
+            j0 = j1;
+        }
+        b->grouped = c->k >= 2 * ngroups && zv.size() <= (size_t)INT32_MAX;
+    }
+    b->ngseg = b->grouped ? (int32_t)(gseg.size() / kGroupSeg) : 0;
+    if (b->grouped) {
+        BTRY(balloc(c, &b->gseg, std::max<size_t>(kGroupSeg, gseg.size())));
+        BTRY(balloc(c, &b->gcol, gcol.size()));
+        BTRY(balloc(c, &b->zr, std::max<size_t>(1, zr.size())));
+        BTRY(balloc(c, &b->zv, std::max<size_t>(1, zv.size())));
+        if (!gseg.empty())
+            BHIP(hipMemcpyAsync(b->gseg, gseg.data(), sizeof(int32_t) * gseg.size(), hipMemcpyHostToDevice, c->stream));
+        BHIP(hipMemcpyAsync(b->gcol, gcol.data(), sizeof(int32_t) * gcol.size(), hipMemcpyHostToDevice, c->stream));
+        if (!zr.empty())
+            BHIP(hipMemcpyAsync(b->zr, zr.data(), sizeof(int32_t) * zr.size(), hipMemcpyHostToDevice, c->stream));
+        if (!zv.empty())
+            BHIP(hipMemcpyAsync(b->zv, zv.data(), sizeof(double) * zv.size(), hipMemcpyHostToDevice, c->stream));
+    }
+    BTRY(balloc(c, &b->seg_part,
+                std::max<size_t>((size_t)std::max(1, b->nseg) * W, (size_t)b->ngseg * kGroupCols * W)));
     if (!seg.empty()) BHIP(hipMemcpyAsync(b->seg, seg.data(), sizeof(int32_t) * seg.size(), hipMemcpyHostToDevice, c->stream));
     BHIP(hipMemcpyAsync(b->seg_ptr, sptr.data(), sizeof(int32_t) * sptr.size(), hipMemcpyHostToDevice, c->stream));
     BHIP(hipStreamSynchronize(c->stream));
@@ -693,6 +921,15 @@ int read_bstate(dpcg_ctx *c, BatchState &out) {
 int enqueue_restrict(dpcg_ctx *c, const double *a, const double *bvec, BatchState *st, const double *part_rr, int n_rr,
                      int iter_offset, int max_iter) {
     BatchWorkspace *b = c->bws;
+    if (b->grouped) {
+        const int grid = ((b->ngseg + kGroupWaves - 1) / kGroupWaves + 7) & ~7;  // a multiple of 8: XCD-major
+        BLAUNCH(k_brestrict_mfma, dim3(grid), dim3(64 * kGroupWaves), 0, c->stream, (const int32_t *)b->gseg, b->ngseg,
+                (const int32_t *)b->zr, (const double *)b->zv, c->kzt_idx, (const double *)c->kzt_val, a, bvec,
+                b->seg_part, st, part_rr, n_rr, iter_offset, max_iter);
+        BLAUNCH(k_bgroupsum, dim3((c->k + 7) / 8), dim3(256), 0, c->stream, c->k, (const int32_t *)b->gcol,
+                (const double *)b->seg_part, b->g, (const BatchState *)st);
+        return DPCG_OK;
+    }
     const int grid = std::max(8, (b->nseg + 7) & ~7);
     BLAUNCH(k_brestrict, dim3(grid), dim3(1024), 0, c->stream, (const int32_t *)b->seg, b->nseg, c->zt_idx,
             (const double *)c->zt_val, c->kzt_idx, (const double *)c->kzt_val, a, bvec, b->seg_part, st, part_rr, n_rr,

@@ -112,6 +112,14 @@ struct BatchWorkspace {
     int32_t *seg = nullptr, *seg_ptr = nullptr;
     double *seg_part = nullptr;
     int32_t nseg = 0;
+    // grouped restriction on the matrix cores, used when runs of vectors share their
+    // triplets: gseg[7 s ..] = (first vector, vectors, list, first row entry, first value,
+    // rows, row-list length); vector c adds partial row gcol[3c+2] of segments gcol[3c] ..
+    // gcol[3c+1]-1; zr, zv: the groups' rows and dense blocks of Z
+    int32_t *gseg = nullptr, *gcol = nullptr, *zr = nullptr;
+    double *zv = nullptr;
+    int32_t ngseg = 0;
+    bool grouped = false;
 };
 
 // A block-Jacobi block of more than kMaxBlock DoFs and a workgroup of its apply.

@@ -91,6 +91,43 @@ def test_batch_matches_single_solves(solver, name, nrhs):
         assert iters_close(infos[0]["iterations"], ref["iterations"])
 
 
+@pytest.mark.parametrize("order", ["mod7", "tail10"])
+def test_batch_restriction_column_orders(problems, order):
+    """The batched restriction takes runs of deflation vectors that cover the same
+    triplets (the modes of one subdomain) together on the matrix cores, and keeps the
+    per-entry kernel when such runs are rare.  Z's columns reordered (the same deflation
+    space): "mod7" leaves no two neighbours of one subdomain (per-entry kernel), "tail10"
+    moves every tenth column to the end (grouped, with single-vector groups).  Batched
+    columns match single solves, and the solutions match the original order's."""
+    import scipy.sparse as sp
+    p = problems("edge10")
+    k = p.k
+    if order == "mod7":
+        perm = np.argsort(np.arange(k) % 7, kind="stable")
+    else:
+        perm = np.r_[[j for j in range(k) if j % 10], [j for j in range(k) if j % 10 == 0]]
+    Zs = sp.csr_matrix(p.Z_scipy().tocsc()[:, perm])
+    Zs.sort_indices()
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(DEV, dt)  # noqa: E731
+    F = _columns(p, 6, 43)
+    with D.Solver.from_problem(p, DEV) as s0, \
+            D.Solver(p.n, t(p.k_rowptr, torch.int64), t(p.k_col, torch.int32), t(p.k_val, torch.float64), k,
+                     t(Zs.indptr.astype(np.int64), torch.int64), t(Zs.indices, torch.int32),
+                     t(Zs.data, torch.float64), t(p.block_ptr, torch.int32)) as s:
+        U, infos = s.solve_batch(dev(F), tol=1e-8)
+        U = host(U)
+        for j in range(F.shape[1]):
+            u1, i1 = s.solve(dev(F[:, j]), tol=1e-8)
+            u0, i0 = s0.solve(dev(F[:, j]), tol=1e-8)
+            u1, u0 = host(u1), host(u0)
+            assert infos[j]["status"] == D.abi.OK
+            assert iters_close(infos[j]["iterations"], i1["iterations"]), (j, infos[j], i1)
+            assert iters_close(i1["iterations"], i0["iterations"]), (j, i1, i0)
+            assert np.linalg.norm(U[:, j] - u1) <= 1e-6 * np.linalg.norm(u1)
+            assert np.linalg.norm(u1 - u0) <= 1e-6 * np.linalg.norm(u0)
+    say(f"[batch] edge10 Z order {order}: iterations {[i['iterations'] for i in infos]}")
+
+
 def test_batch_masking_of_finished_columns(solver):
     p, s = solver("edge10")
     K = p.K_scipy()
