@@ -32,10 +32,10 @@ SPMV_TRAFFIC = {
     "workload": "penny40",
     "sources": {
         "paper_2111_09294_amd/csrc/kernels.hip": "70bd4dbe31e4aa337690e3d5d3858d099bc90b3772a153a796fda438a4f4a463",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "5b40e7e70f09d3111cf29ee700c351d070c313171f337e0093fac1ec0ef25372"
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "9ad4cabc29b19e9ef5e79642b31c90cba093a5764f752205bf97200ebb7e57d7"
     },
-    "fetch_bytes": 171118563,
-    "write_bytes": 2027321,
+    "fetch_bytes": 171137285,
+    "write_bytes": 2026886,
 }
 
 
