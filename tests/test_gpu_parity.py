@@ -117,6 +117,34 @@ def test_adef2_preconditioner(pair, name):
     assert np.linalg.norm(z - zref) <= 1e-6 * np.linalg.norm(zref)
 
 
+def test_operators_at_full_size_80(pair):
+    """Every operator of the iteration at the 80^3 configuration (1.66M DoFs, k = 4,528),
+    whole output vectors against the oracle with the tolerances of the smaller cases: the
+    SpMV, block-Jacobi, the merged restriction, the coarse solve, the prolongation and
+    the A-DEF2 preconditioner (the launch shapes of the bench's 80^3 line)."""
+    p, o, s = pair("penny80")
+    rng = np.random.default_rng(80)
+    a, b = rng.standard_normal(p.n), rng.standard_normal(p.n)
+    y = host(s.spmv(dev(a)))
+    ref = o.spmv(a)
+    assert np.linalg.norm(y - ref) <= 1e-13 * np.linalg.norm(ref)
+    z = host(s.bj_apply(dev(a)))
+    ref = o.bj_apply(a)
+    assert np.linalg.norm(z - ref) <= 1e-9 * np.linalg.norm(ref)
+    g = host(s.restrict(dev(a), dev(b)))
+    za, zkb = o.zt_times(a), o.zt_times(o.spmv(b))
+    assert np.abs(g - (za - zkb)).max() <= 1e-12 * (np.abs(za).max() + np.abs(zkb).max())
+    d = host(s.coarse_apply(dev(za - zkb)))
+    dref = o.coarse_solve(za - zkb)
+    assert np.linalg.norm(d - dref) <= 1e-6 * np.linalg.norm(dref)
+    out = host(s.prolong(dev(dref), dev(a)))
+    assert np.allclose(out, o.x_plus_z_times(a, dref), rtol=1e-13, atol=1e-13 * np.abs(out).max())
+    zz = host(s.precond(dev(a)))
+    zref, _ = o.adef2_apply(a)
+    assert np.linalg.norm(zz - zref) <= 1e-6 * np.linalg.norm(zref)
+    say(f"[full size] penny80 n={p.n} k={p.k}: operators match the oracle")
+
+
 # ------------------------------------------------------------------ whole solves
 @pytest.mark.parametrize("name", SMALL + ["penny40"])
 def test_solve_matches_oracle(pair, name):
