@@ -1668,7 +1668,7 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
             if (gcut.size() > 2) prepare(g0, g1);  // one group: the count pass left it ready
             hipLaunchKernelGGL(k_kzb_rank, dim3(max_slices(g0, g1), g1 - g0), dim3(256), 0, s, bt_d + g0, mk, soff,
                                icnt, kzp, items);
-            hipLaunchKernelGGL(k_kzb_values, dim3(128, g1 - g0), dim3(256),
+            hipLaunchKernelGGL(k_kzb_values, dim3(512, g1 - g0), dim3(256),
                                0, s, bt_d + g0, nitems + g0, items, c->brow_ptr, c->bcol, c->bval, zd, rbits, zp, zc,
                                c->kzt_idx, c->kzt_val, kd, words, touched);
             hipLaunchKernelGGL(k_kzb_erows, dim3((k + 3) / 4, g1 - g0), dim3(256), 0, s, bt_d + g0, k, ztp, zti, ztv,
