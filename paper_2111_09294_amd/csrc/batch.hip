@@ -845,7 +845,7 @@ int ensure_ws(dpcg_ctx *c) {
             for (int32_t q = zp[j]; q < zp[j + 1]; ++q)
                 if (t.empty() || t.back() != zi[q] / 3) t.push_back(zi[q] / 3);
         };
-        std::vector<int32_t> tprev, tcur, pos;
+        std::vector<int32_t> tprev, tcur;
         int ngroups = 0;
         for (int j0 = 0; j0 < c->k;) {
             triplets(j0, tprev);
