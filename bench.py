@@ -34,8 +34,8 @@ SPMV_TRAFFIC = {
         "paper_2111_09294_amd/csrc/kernels.hip": "70bd4dbe31e4aa337690e3d5d3858d099bc90b3772a153a796fda438a4f4a463",
         "paper_2111_09294_amd/csrc/dpcg_internal.h": "9ad4cabc29b19e9ef5e79642b31c90cba093a5764f752205bf97200ebb7e57d7"
     },
-    "fetch_bytes": 171137285,
-    "write_bytes": 2026886,
+    "fetch_bytes": 171105229,
+    "write_bytes": 2026508,
 }
 
 
