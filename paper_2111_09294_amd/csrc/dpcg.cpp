@@ -97,10 +97,10 @@ int alloc_workspace(dpcg_ctx *c, Workspace &w) {
     c->part_cap = (int32_t)np;
     // one allocation (one zero fill) carved into 256-byte aligned arrays
     double **vec[] = {&w.r, &w.y, &w.z, &w.q, &w.p[0], &w.p[1], &w.tmp};
-    double **kv[] = {&w.g, &w.delta};
+    double **kv[] = {&w.g, &w.delta, &w.h, &w.hd};
     double **pv[] = {&w.part_a, &w.part_b, &w.part_c};
     auto up = [](size_t bytes) { return (bytes + 255) & ~size_t(255); };
-    const size_t total = 7 * up(8 * n) + 2 * up(8 * kk) + 3 * up(8 * np) + up(sizeof(State));
+    const size_t total = 7 * up(8 * n) + 4 * up(8 * kk) + 3 * up(8 * np) + up(sizeof(State));
     char *base = nullptr;
     TRY(alloc(c, &base, total));
     size_t off = 0;
@@ -265,6 +265,15 @@ int enqueue_iteration(dpcg_ctx *c, Workspace &w, double *u, int max_iter, int re
         LAUNCH(launch_spmv_p(c, w, a, b));
     } else {
         LAUNCH(launch_spmv_p(c, w, nullptr, nullptr));
+    }
+    if (c->ndense == 0) {
+        // y comes whole from the update kernel, so its r^T y partials and h = Z^T r give
+        // rho = r^T z without z: the prolongation forms beta and p itself
+        LAUNCH(launch_update_bj(c, u, w, true));
+        LAUNCH(launch_restrict(c, w.r, w.y, w.g, &w, 1, c->bj_nwg, 1, max_iter, record, true));
+        LAUNCH(launch_coarse(c, w.g, w.delta, &w, true));
+        LAUNCH(launch_prolong_p(c, w));
+        return DPCG_OK;
     }
     LAUNCH(launch_update_bj(c, u, w));
     LAUNCH(launch_restrict(c, w.r, w.y, w.g, &w, 1, c->bj_nwg, 1, max_iter, record));
@@ -586,6 +595,8 @@ int solve_many_impl(dpcg_handle *hs, int32_t count, const double *const *F, doub
         d.part_a = w.part_a;
         d.part_b = w.part_b;
         d.part_c = w.part_c;
+        d.h = w.h;
+        d.hd = w.hd;
         d.st = w.st;
         const int n_ph[kMsPhases] = {round8(c->spmv.nwg), 1, round8(c->bj_nwg), std::max(1, c->k), c->k,
                                      round8(c->vec_nwg)};
@@ -646,9 +657,8 @@ int solve_many_impl(dpcg_handle *hs, int32_t count, const double *const *F, doub
             LAUNCH(launch_ms_alpha(S, Y, count));
             LAUNCH(launch_ms_update_bj(S, T, Y, tot[kMsBj]));
             LAUNCH(launch_ms_restrict(S, T, Y, tot[kMsRestrict], 1, 1, 1, max_iter));
-            LAUNCH(launch_ms_coarse(S, T, Y, tot[kMsCoarse], 1));
-            LAUNCH(launch_ms_prolong(S, T, Y, tot[kMsVec], 1, 1));
-            LAUNCH(launch_ms_beta(S, T, Y, tot[kMsVec]));
+            LAUNCH(launch_ms_coarse(S, T, Y, tot[kMsCoarse], 2));
+            LAUNCH(launch_ms_prolong(S, T, Y, tot[kMsVec], 2, 0));
         }
         enq += m;
         TRY(read_all());

@@ -49,15 +49,18 @@ __device__ __forceinline__ int xcd_remap(int w, int nwg) {
 // that run after that one in stream order.
 struct State {
     int32_t flag;        // kRunning, kConverged, kMaxIter, kBreakdown
-    int32_t iter;        // index i of the iteration in flight (incremented by the prolongation)
+    int32_t iter;        // index i of the iteration in flight (advanced by the restriction when
+                         // the prolongation is fused with beta, else by the prolongation)
     int32_t iters_done;  // final iteration count, set together with the flag
     int32_t bad;         // iteration of a breakdown
     double thr;          // tol * ||f||_2
-    double rho[2];       // rho_i = r_i^T z_i in slot i & 1 (k_beta_p), so rho_{i-1} stays readable
+    double rho[2];       // rho_i = r_i^T z_i in slot i & 1 (beta kernel or fused prolongation),
+                         // so rho_{i-1} stays readable
     double alpha;        // alpha_i (k_alpha)
-    double beta;         // beta_{i-1} (k_beta_p; 0 at i = 0)
+    double beta;         // beta_{i-1} (as rho; 0 at i = 0)
     double rr;           // ||r||^2 of the last check
     double aux;          // scratch scalar for one-off reductions
+    double ry;           // r_i^T y_i (the fused restriction, from the update's partials)
     int32_t nonfinite;   // set by the input check
     int32_t pad;
 };
@@ -67,6 +70,7 @@ enum : int32_t { kRunning = 0, kConverged = 1, kMaxIter = 2, kBreakdown = 3 };
 struct Workspace {
     double *r = nullptr, *y = nullptr, *z = nullptr, *q = nullptr, *p[2] = {nullptr, nullptr};
     double *g = nullptr, *delta = nullptr, *tmp = nullptr;
+    double *h = nullptr, *hd = nullptr;  // Z^T r and h_j delta_j for the fused prolongation
     double *part_a = nullptr;   // partial sums (p^T q, r^T r, r^T z); sized max grid
     double *part_b = nullptr;
     double *part_c = nullptr;
@@ -154,7 +158,7 @@ struct MsSys {
     const int32_t *z_ptr, *z_col;
     const double *z_val;
     const double *f;
-    double *u, *r, *y, *z, *q, *p0, *p1, *g, *delta, *part_a, *part_b, *part_c;
+    double *u, *r, *y, *z, *q, *p0, *p1, *g, *delta, *part_a, *part_b, *part_c, *h, *hd;
     State *st;
 };
 
@@ -234,13 +238,17 @@ hipError_t launch_spmv_residual(const dpcg_ctx *c, const double *x, const double
                                 double *part, Workspace &w, int check);
 // ev0, ev1 (may be null): events that record the kernel's start and end
 hipError_t launch_spmv_p(const dpcg_ctx *c, Workspace &w, hipEvent_t ev0, hipEvent_t ev1);
-hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w);
+// fused: also the r^T y partials (part_c) for the fused prolongation (no dense blocks)
+hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w, bool fused = false);
 hipError_t launch_beta(const dpcg_ctx *c, Workspace &w);
 hipError_t launch_bj(const dpcg_ctx *c, const double *r, double *y, Workspace *w);
 hipError_t launch_bj_dense(const dpcg_ctx *c, const double *r, double *y, const State *st);
 hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, double *g, Workspace *w,
-                           int check, int n_parts, int iter_offset, int max_iter, int record);
-hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Workspace *w);
+                           int check, int n_parts, int iter_offset, int max_iter, int record, bool fused = false);
+hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Workspace *w, bool fused = false);
+// z = y + Z delta, rho = r^T y + h^T delta, beta and p in one kernel (after the fused
+// update, restriction and coarse product)
+hipError_t launch_prolong_p(const dpcg_ctx *c, Workspace &w);
 hipError_t launch_prolong(const dpcg_ctx *c, const double *base, const double *delta, double *out,
                           Workspace *w, const double *rdot, int advance);
 hipError_t launch_reduce_aux(const dpcg_ctx *c, Workspace &w, int n_parts);

@@ -80,6 +80,29 @@ __device__ __forceinline__ int32_t wg_flag(const State *st) {
     return v;
 }
 
+// Two workgroup sums over NW waves at once (lds >= 2 NW entries); every thread
+// receives both.
+template <int NW>
+__device__ __forceinline__ void block_sum2_n(double &a, double &b, double *lds) {
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+        lds[wv] = a;
+        lds[NW + wv] = b;
+    }
+    __syncthreads();
+    double x = 0.0, y = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; w += 2) {
+        x += lds[w] + lds[w + 1];
+        y += lds[NW + w] + lds[NW + w + 1];
+    }
+    a = x;
+    b = y;
+}
+
 struct XPlain {
     const double *__restrict__ x;
     __device__ __forceinline__ double operator()(int64_t i) const { return x[i]; }
@@ -310,7 +333,8 @@ __device__ __forceinline__ void k_update_bj_body(int vb,
     int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start, double *__restrict__ u,
     double *__restrict__ r, double *__restrict__ y, const double *__restrict__ q, const double *p0,
     const double *p1, const M *__restrict__ minv, const int32_t *__restrict__ bj_rowoff,
-    const int32_t *__restrict__ bj_meta, double *__restrict__ part_rr, const State *st) {
+    const int32_t *__restrict__ bj_meta, double *__restrict__ part_rr, double *__restrict__ part_ry,
+    const State *st) {
     __shared__ double lds[4];
     __shared__ double tile[kThreads];
     if (st->flag != kRunning) return;
@@ -319,23 +343,32 @@ __device__ __forceinline__ void k_update_bj_body(int vb,
     const int t = threadIdx.x;
     const int w = xcd_remap(vb, nwg);
     const int t0 = (int)(((int64_t)w * ntiles) / nwg), t1 = (int)(((int64_t)(w + 1) * ntiles) / nwg);
-    double acc = 0.0;
+    double acc = 0.0, accy = 0.0;
     for (int tt = t0; tt < t1; ++tt) {
         const int64_t d0 = tile_start[tt], d1 = tile_start[tt + 1];
         const int64_t d = d0 + t;
+        double rn = 0.0;
         __syncthreads();
         if (d < d1) {
             u[d] = fma(alpha, p[d], u[d]);
-            const double rn = fma(-alpha, q[d], r[d]);
+            rn = fma(-alpha, q[d], r[d]);
             r[d] = rn;
             tile[t] = rn;
             acc = fma(rn, rn, acc);
         }
         __syncthreads();
-        if (d < d1) y[d] = bj_row(t, d, tile, minv, bj_rowoff, bj_meta);
+        if (d < d1) {
+            const double yd = bj_row(t, d, tile, minv, bj_rowoff, bj_meta);
+            y[d] = yd;
+            accy = fma(rn, yd, accy);
+        }
     }
     const double s = block_sum(acc, lds);
     if (threadIdx.x == 0) part_rr[vb] = s;
+    if (part_ry) {  // r^T y partials: rho = r^T z is formed from them in the prolongation
+        const double sy = block_sum(accy, lds);
+        if (threadIdx.x == 0) part_ry[vb] = sy;
+    }
 }
 
 template <class M>
@@ -343,9 +376,10 @@ __global__ __launch_bounds__(kThreads) void k_update_bj(
     int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start, double *__restrict__ u,
     double *__restrict__ r, double *__restrict__ y, const double *__restrict__ q, const double *p0,
     const double *p1, const M *__restrict__ minv, const int32_t *__restrict__ bj_rowoff,
-    const int32_t *__restrict__ bj_meta, double *__restrict__ part_rr, const State *st) {
+    const int32_t *__restrict__ bj_meta, double *__restrict__ part_rr, double *__restrict__ part_ry,
+    const State *st) {
     k_update_bj_body<M>(blockIdx.x, ntiles, nwg, tile_start, u, r, y, q, p0, p1, minv, bj_rowoff, bj_meta, part_rr,
-                        st);
+                        part_ry, st);
 }
 
 
@@ -439,7 +473,10 @@ __global__ __launch_bounds__(kThreads) void k_bj_dense(const DenseBlk *__restric
 }
 
 // Convergence test (workgroup 0 only) and g_j = Z^T a - (K Z)^T b, one column per
-// workgroup of kRestrictThreads threads, four independent chains per thread.
+// workgroup of kRestrictThreads threads, four independent chains per thread for each of
+// the two products.  h (when given) receives Z^T a and workgroup 0 also sums the r^T y
+// partials into st->ry; advance (iteration launches whose iterate continues) moves the
+// state to the next iteration after the test.
 constexpr int kRestrictWaves = 8;
 constexpr int kRestrictThreads = 64 * kRestrictWaves;
 
@@ -447,16 +484,23 @@ __device__ __forceinline__ void k_restrict_body(int vb, int vg,
     int32_t k, const int32_t *__restrict__ zt_ptr, const int32_t *__restrict__ zt_idx,
     const double *__restrict__ zt_val, const int32_t *__restrict__ kzt_ptr, const int32_t *__restrict__ kzt_idx,
     const double *__restrict__ kzt_val, const double *__restrict__ a, const double *__restrict__ b,
-    double *__restrict__ g, State *st, const double *__restrict__ part_rr, int n_rr, int iter_offset,
-    int max_iter, double *__restrict__ hist) {
-    __shared__ double lds[kRestrictWaves];
+    double *__restrict__ g, double *__restrict__ h, State *st, const double *__restrict__ part_rr,
+    const double *__restrict__ part_ry, int n_rr, int iter_offset, int max_iter, double *__restrict__ hist,
+    int advance) {
+    __shared__ double lds[2 * kRestrictWaves];
     if (st) {
         if (wg_flag(st) != kRunning) return;
         if (vb == 0 && n_rr > 0) {
-            const double rr = reduce_parts_n<kRestrictWaves>(part_rr, n_rr, lds);
+            double rr = 0.0, ry = 0.0;
+            for (int i = threadIdx.x; i < n_rr; i += kRestrictThreads) {
+                rr += part_rr[i];
+                if (part_ry) ry += part_ry[i];
+            }
+            block_sum2_n<kRestrictWaves>(rr, ry, lds);
             if (threadIdx.x == 0) {
                 const int done = st->iter + iter_offset;
                 st->rr = rr;
+                st->ry = ry;
                 const double rn = sqrt(rr);
                 if (hist) hist[done] = rn;
                 if (!isfinite(rr)) {
@@ -469,13 +513,16 @@ __device__ __forceinline__ void k_restrict_body(int vb, int vg,
                 } else if (done >= max_iter) {
                     st->flag = kMaxIter;
                     st->iters_done = done;
+                } else if (advance) {
+                    st->iter = st->iter + 1;
                 }
             }
         }
     }
     constexpr int T = kRestrictThreads;
     for (int j = vb; j < k; j += vg) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;  // Z^T a
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;  // -(K Z)^T b
         {
             const int e1 = zt_ptr[j + 1];
             int e = zt_ptr[j] + threadIdx.x;
@@ -491,15 +538,19 @@ __device__ __forceinline__ void k_restrict_body(int vb, int vg,
             const int e1 = kzt_ptr[j + 1];
             int e = kzt_ptr[j] + threadIdx.x;
             for (; e + 3 * T < e1; e += 4 * T) {
-                s0 = fma(-kzt_val[e], b[kzt_idx[e]], s0);
-                s1 = fma(-kzt_val[e + T], b[kzt_idx[e + T]], s1);
-                s2 = fma(-kzt_val[e + 2 * T], b[kzt_idx[e + 2 * T]], s2);
-                s3 = fma(-kzt_val[e + 3 * T], b[kzt_idx[e + 3 * T]], s3);
+                t0 = fma(-kzt_val[e], b[kzt_idx[e]], t0);
+                t1 = fma(-kzt_val[e + T], b[kzt_idx[e + T]], t1);
+                t2 = fma(-kzt_val[e + 2 * T], b[kzt_idx[e + 2 * T]], t2);
+                t3 = fma(-kzt_val[e + 3 * T], b[kzt_idx[e + 3 * T]], t3);
             }
-            for (; e < e1; e += T) s0 = fma(-kzt_val[e], b[kzt_idx[e]], s0);
+            for (; e < e1; e += T) t0 = fma(-kzt_val[e], b[kzt_idx[e]], t0);
         }
-        const double s = block_sum_n<kRestrictWaves>((s0 + s1) + (s2 + s3), lds);
-        if (threadIdx.x == 0) g[j] = s;
+        double za = (s0 + s1) + (s2 + s3), kb = (t0 + t1) + (t2 + t3);
+        block_sum2_n<kRestrictWaves>(za, kb, lds);
+        if (threadIdx.x == 0) {
+            g[j] = za + kb;
+            if (h) h[j] = za;
+        }
     }
 }
 
@@ -508,16 +559,19 @@ __global__ __launch_bounds__(kRestrictThreads) void k_restrict(
     const double *__restrict__ zt_val, const int32_t *__restrict__ kzt_ptr, const int32_t *__restrict__ kzt_idx,
     const double *__restrict__ kzt_val, const double *__restrict__ a, const double *__restrict__ b,
     double *__restrict__ g, State *st, const double *__restrict__ part_rr, int n_rr, int iter_offset,
-    int max_iter, double *__restrict__ hist) {
-    k_restrict_body(blockIdx.x, gridDim.x, k, zt_ptr, zt_idx, zt_val, kzt_ptr, kzt_idx, kzt_val, a, b, g, st, part_rr,
-                    n_rr, iter_offset, max_iter, hist);
+    int max_iter, double *__restrict__ hist, double *__restrict__ h, const double *__restrict__ part_ry,
+    int advance) {
+    k_restrict_body(blockIdx.x, gridDim.x, k, zt_ptr, zt_idx, zt_val, kzt_ptr, kzt_idx, kzt_val, a, b, g, h, st,
+                    part_rr, part_ry, n_rr, iter_offset, max_iter, hist, advance);
 }
 
 
-// delta = E^{-1} g: one workgroup per row of the dense symmetric inverse.
+// delta = E^{-1} g: one workgroup per row of the dense symmetric inverse; with h given,
+// also the products hd_j = h_j delta_j.
 __device__ __forceinline__ void k_coarse_body(int vb, int32_t k, int64_t ld, const double *__restrict__ einv,
                                                      const double *__restrict__ g, double *__restrict__ delta,
-                                                     const State *st) {
+                                                     const State *st, const double *__restrict__ h,
+                                                     double *__restrict__ hd) {
     __shared__ double lds[4];
     if (st && st->flag != kRunning) return;
     const int row = vb;
@@ -531,13 +585,17 @@ __device__ __forceinline__ void k_coarse_body(int vb, int32_t k, int64_t ld, con
     }
     for (; l < k; l += kThreads) s0 = fma(e[l], g[l], s0);
     const double s = block_sum(s0 + s1, lds);
-    if (threadIdx.x == 0) delta[row] = s;
+    if (threadIdx.x == 0) {
+        delta[row] = s;
+        if (hd) hd[row] = h[row] * s;
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_coarse(int32_t k, int64_t ld, const double *__restrict__ einv,
                                                      const double *__restrict__ g, double *__restrict__ delta,
-                                                     const State *st) {
-    k_coarse_body(blockIdx.x, k, ld, einv, g, delta, st);
+                                                     const State *st, const double *__restrict__ h,
+                                                     double *__restrict__ hd) {
+    k_coarse_body(blockIdx.x, k, ld, einv, g, delta, st, h, hd);
 }
 
 
@@ -580,6 +638,69 @@ __global__ __launch_bounds__(kThreads) void k_prolong(int64_t n, int32_t nwg, co
     k_prolong_body(blockIdx.x, n, nwg, z_ptr, z_col, z_val, delta, base, out, rdot, part, st, advance);
 }
 
+
+// The prolongation of Algorithm 3 fused with beta and the new search direction of
+// Algorithm 1.  With h = Z^T r from the restriction, r^T z = r^T y + h^T delta exactly, so
+// rho_i is r^T y (summed by the restriction) plus the fixed-order sum of the products
+// hd_j = h_j delta_j of the coarse kernel: every workgroup forms the same bits of rho_i
+// and of beta_{i-1} = rho_i / rho_{i-1} and writes p_i = y + Z delta + beta_{i-1} p_{i-1}
+// into buffer i & 1 directly (z itself is never stored).  The restriction has already
+// advanced the iteration.  Workgroup 0 stores rho_i in slot i & 1 and tests it.
+__device__ __forceinline__ void k_prolong_p_body(int vb, int64_t n, int32_t nwg, const int32_t *__restrict__ z_ptr,
+                                                 const int32_t *__restrict__ z_col, const double *__restrict__ z_val,
+                                                 const double *__restrict__ delta, const double *__restrict__ y,
+                                                 const double *__restrict__ hd, int32_t k, double *p0, double *p1,
+                                                 State *st) {
+    __shared__ double lds[4];
+    if (wg_flag(st) != kRunning) return;
+    const int it = st->iter;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    {
+        constexpr int T = kThreads;
+        int j = threadIdx.x;
+        for (; j + 3 * T < k; j += 4 * T) {
+            s0 += hd[j];
+            s1 += hd[j + T];
+            s2 += hd[j + 2 * T];
+            s3 += hd[j + 3 * T];
+        }
+        for (; j < k; j += T) s0 += hd[j];
+    }
+    const double rho = st->ry + block_sum((s0 + s1) + (s2 + s3), lds);
+    const bool bad = !isfinite(rho);
+    const double beta = rho / st->rho[(it + 1) & 1];
+    if (vb == 0 && threadIdx.x == 0) {
+        if (bad) {
+            st->flag = kBreakdown;
+            st->bad = it - 1;
+            st->iters_done = it;
+        } else {
+            st->beta = beta;
+            st->rho[it & 1] = rho;
+        }
+    }
+    if (bad) return;
+    double *__restrict__ pc = (it & 1) ? p1 : p0;
+    const double *__restrict__ pp = (it & 1) ? p0 : p1;
+    const int w = xcd_remap(vb, nwg);
+    const int64_t per = (n + nwg - 1) / nwg;
+    const int64_t d1 = min(n, (int64_t)(w + 1) * per);
+    for (int64_t d = (int64_t)w * per + threadIdx.x; d < d1; d += kThreads) {
+        double c = 0.0;
+        for (int e = z_ptr[d]; e < z_ptr[d + 1]; ++e) c = fma(z_val[e], delta[z_col[e]], c);
+        pc[d] = fma(beta, pp[d], y[d] + c);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_prolong_p(int64_t n, int32_t nwg, const int32_t *__restrict__ z_ptr,
+                                                        const int32_t *__restrict__ z_col,
+                                                        const double *__restrict__ z_val,
+                                                        const double *__restrict__ delta,
+                                                        const double *__restrict__ y,
+                                                        const double *__restrict__ hd, int32_t k, double *p0,
+                                                        double *p1, State *st) {
+    k_prolong_p_body(blockIdx.x, n, nwg, z_ptr, z_col, z_val, delta, y, hd, k, p0, p1, st);
+}
 
 // ||a||^2 partials and a count of non-finite entries of a and b (b may be null).
 __global__ __launch_bounds__(kThreads) void k_norm_finite(int64_t n, int32_t nwg, const double *__restrict__ a,
@@ -717,7 +838,7 @@ __global__ __launch_bounds__(kThreads) void k_ms_update_bj(const MsTable *__rest
     const int s = ms_find(tab, kMsBj, blockIdx.x);
     const MsSys &S = sys[s];
     k_update_bj_body<double>(blockIdx.x - tab->off[kMsBj][s], S.bj_ntiles, S.bj_nwg, S.bj_wg_start, S.u, S.r, S.y,
-                             S.q, S.p0, S.p1, S.minv, S.bj_rowoff, S.bj_meta, S.part_b, S.st);
+                             S.q, S.p0, S.p1, S.minv, S.bj_rowoff, S.bj_meta, S.part_b, S.part_c, S.st);
 }
 
 __global__ __launch_bounds__(kThreads) void k_ms_bj(const MsTable *__restrict__ tab, const MsSys *__restrict__ sys) {
@@ -739,10 +860,13 @@ __global__ __launch_bounds__(kRestrictThreads) void k_ms_restrict(const MsTable 
     if (mode == 0) {
         if (S.st->flag != kRunning) return;
         k_restrict_body(vb, vg, S.k, S.zt_ptr, S.zt_idx, S.zt_val, S.kzt_ptr, S.kzt_idx, S.kzt_val, S.f,
-                        S.guess ? S.u : nullptr, S.g, nullptr, nullptr, 0, 0, 0, nullptr);
+                        S.guess ? S.u : nullptr, S.g, nullptr, nullptr, nullptr, nullptr, 0, 0, 0, nullptr, 0);
     } else {
-        k_restrict_body(vb, vg, S.k, S.zt_ptr, S.zt_idx, S.zt_val, S.kzt_ptr, S.kzt_idx, S.kzt_val, S.r, S.y, S.g, S.st,
-                        S.part_b, check ? (iter_offset ? S.bj_nwg : S.spmv_nwg) : 0, iter_offset, max_iter, nullptr);
+        // iterations (iter_offset 1) take the fused prolongation: h = Z^T r and the advance
+        k_restrict_body(vb, vg, S.k, S.zt_ptr, S.zt_idx, S.zt_val, S.kzt_ptr, S.kzt_idx, S.kzt_val, S.r, S.y, S.g,
+                        iter_offset ? S.h : nullptr, S.st, S.part_b, iter_offset ? S.part_c : nullptr,
+                        check ? (iter_offset ? S.bj_nwg : S.spmv_nwg) : 0, iter_offset, max_iter, nullptr,
+                        iter_offset);
     }
 }
 
@@ -752,10 +876,11 @@ __global__ __launch_bounds__(kThreads) void k_ms_coarse(const MsTable *__restric
     const MsSys &S = sys[s];
     if (!with_state && S.st->flag != kRunning) return;
     k_coarse_body(blockIdx.x - tab->off[kMsCoarse][s], S.k, S.einv_ld, S.einv, S.g, S.delta,
-                  with_state ? S.st : nullptr);
+                  with_state ? S.st : nullptr, S.h, with_state == 2 ? S.hd : nullptr);
 }
 
-// mode 0: u = u_{-1} + Z delta (no state); mode 1: z = y + Z delta with r^T z partials
+// mode 0: u = u_{-1} + Z delta (no state); mode 1: z = y + Z delta with r^T z partials;
+// mode 2: the fused prolongation, beta and search direction of an iteration
 __global__ __launch_bounds__(kThreads) void k_ms_prolong(const MsTable *__restrict__ tab,
                                                          const MsSys *__restrict__ sys, int mode, int advance) {
     const int s = ms_find(tab, kMsVec, blockIdx.x);
@@ -769,9 +894,12 @@ __global__ __launch_bounds__(kThreads) void k_ms_prolong(const MsTable *__restri
         else if (!S.guess)
             k_prolong_body(vb, S.n, S.vec_nwg, S.z_ptr, S.z_col, S.z_val, S.delta, nullptr, S.u, nullptr, nullptr,
                            nullptr, 0);
-    } else {
+    } else if (mode == 1) {
         k_prolong_body(vb, S.n, S.vec_nwg, S.z_ptr, S.z_col, S.z_val, S.delta, S.y, S.z, S.r, S.part_c, S.st,
                        advance);
+    } else {
+        k_prolong_p_body(vb, S.n, S.vec_nwg, S.z_ptr, S.z_col, S.z_val, S.delta, S.y, S.hd, S.k, S.p0, S.p1,
+                         S.st);
     }
 }
 
@@ -825,7 +953,7 @@ hipError_t launch_spmv_residual(const dpcg_ctx *c, const double *x, const double
     }
 }
 
-hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w) {
+hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w, bool fused) {
     hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1024), 0, c->stream, w.part_a, c->spmv.nwg, w.st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -833,12 +961,12 @@ hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w) {
         hipLaunchKernelGGL(k_update_bj<float>, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles,
                            c->bj_nwg, c->bj_wg_start, u, w.r, w.y, (const double *)w.q, (const double *)w.p[0],
                            (const double *)w.p[1], (const float *)c->minv32, c->bj_rowoff, c->bj_meta, w.part_b,
-                           (const State *)w.st);
+                           fused ? w.part_c : nullptr, (const State *)w.st);
     else
         hipLaunchKernelGGL(k_update_bj<double>, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles,
                            c->bj_nwg, c->bj_wg_start, u, w.r, w.y, (const double *)w.q, (const double *)w.p[0],
                            (const double *)w.p[1], (const double *)c->minv, c->bj_rowoff, c->bj_meta, w.part_b,
-                           (const State *)w.st);
+                           fused ? w.part_c : nullptr, (const State *)w.st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_bj_dense(c, w.r, w.y, w.st);
@@ -877,19 +1005,20 @@ hipError_t launch_bj_dense(const dpcg_ctx *c, const double *r, double *y, const 
 }
 
 hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, double *g, Workspace *w,
-                           int check, int n_parts, int iter_offset, int max_iter, int record) {
+                           int check, int n_parts, int iter_offset, int max_iter, int record, bool fused) {
     const int grid = c->k > 0 ? c->k : 1;
     hipLaunchKernelGGL(k_restrict, dim3(grid), dim3(kRestrictThreads), 0, c->stream, c->k, c->zt_ptr, c->zt_idx,
                        c->zt_val, c->kzt_ptr, c->kzt_idx, c->kzt_val, a, b, g, w ? w->st : nullptr,
                        w ? w->part_b : nullptr, check ? n_parts : 0, iter_offset, max_iter,
-                       (w && record) ? w->hist : nullptr);
+                       (w && record) ? w->hist : nullptr, fused ? w->h : nullptr, fused ? w->part_c : nullptr,
+                       fused ? 1 : 0);
     return hipGetLastError();
 }
 
-hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Workspace *w) {
+hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Workspace *w, bool fused) {
     if (c->k == 0) return hipSuccess;
     hipLaunchKernelGGL(k_coarse, dim3(c->k), dim3(kThreads), 0, c->stream, c->k, c->einv_ld, c->einv, g, delta,
-                       w ? w->st : nullptr);
+                       w ? w->st : nullptr, fused ? w->h : nullptr, fused ? w->hd : nullptr);
     return hipGetLastError();
 }
 
@@ -898,6 +1027,12 @@ hipError_t launch_prolong(const dpcg_ctx *c, const double *base, const double *d
     hipLaunchKernelGGL(k_prolong, dim3(c->vec_nwg), dim3(kThreads), 0, c->stream, c->n, c->vec_nwg, c->z_ptr,
                        c->z_col, c->z_val, delta, base, out, rdot, w ? w->part_c : nullptr,
                        w ? w->st : nullptr, advance);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_p(const dpcg_ctx *c, Workspace &w) {
+    hipLaunchKernelGGL(k_prolong_p, dim3(c->vec_nwg), dim3(kThreads), 0, c->stream, c->n, c->vec_nwg, c->z_ptr,
+                       c->z_col, c->z_val, w.delta, w.y, w.hd, c->k, w.p[0], w.p[1], w.st);
     return hipGetLastError();
 }
 
