@@ -31,11 +31,11 @@ HBM_PEAK_GBS = 8000.0
 SPMV_TRAFFIC = {
     "workload": "penny40",
     "sources": {
-        "paper_2111_09294_amd/csrc/kernels.hip": "70bd4dbe31e4aa337690e3d5d3858d099bc90b3772a153a796fda438a4f4a463",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "9ad4cabc29b19e9ef5e79642b31c90cba093a5764f752205bf97200ebb7e57d7"
+        "paper_2111_09294_amd/csrc/kernels.hip": "324bf5537b02bbec61d49c66c37738a99d2c4b243080830e5dac97ed095f90fa",
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "c0ba109d4262e5c5c843b0b0f6bd48ea92e9f470dca8de0f2b5f3d72bdf9d8c6"
     },
-    "fetch_bytes": 171105229,
-    "write_bytes": 2026508,
+    "fetch_bytes": 171107177,
+    "write_bytes": 2027401,
 }
 
 
