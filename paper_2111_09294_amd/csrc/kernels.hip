@@ -114,12 +114,11 @@ struct XPlain {
 // V is the storage type of the block values (double, or float for the inner solves of
 // mixed precision); the arithmetic is FP64 either way.
 template <int G, class XL, class V>
-__device__ __forceinline__ void block_row(int row, int lg, const int32_t *__restrict__ brow_ptr,
-                                          const int32_t *__restrict__ bcol, const V *__restrict__ bval,
-                                          int64_t nnzb, const XL &xl, double &a0, double &a1, double &a2) {
+__device__ __forceinline__ void block_row_span(int row, int beg, int end, int lg, const int32_t *__restrict__ bcol,
+                                               const V *__restrict__ bval, const XL &xl, double &a0, double &a1,
+                                               double &a2) {
     a0 = a1 = a2 = 0.0;
     if (row >= 0) {
-        const int beg = brow_ptr[row], end = brow_ptr[row + 1];
         const int64_t m = end - beg;
         const V *rv = bval + 9 * (int64_t)beg - beg;  // plane e of block b: rv[e * m + b]
         for (int b = beg + lg; b < end; b += G) {
@@ -141,6 +140,18 @@ __device__ __forceinline__ void block_row(int row, int lg, const int32_t *__rest
     }
 }
 
+template <int G, class XL, class V>
+__device__ __forceinline__ void block_row(int row, int lg, const int32_t *__restrict__ brow_ptr,
+                                          const int32_t *__restrict__ bcol, const V *__restrict__ bval,
+                                          int64_t nnzb, const XL &xl, double &a0, double &a1, double &a2) {
+    int beg = 0, end = 0;
+    if (row >= 0) {
+        beg = brow_ptr[row];
+        end = brow_ptr[row + 1];
+    }
+    block_row_span<G>(row, beg, end, lg, bcol, bval, xl, a0, a1, a2);
+}
+
 struct SpmvShape {
     int32_t nb;
     int32_t steps;
@@ -152,6 +163,18 @@ struct SpmvShape {
 // its loads at once and many small workgroups in flight hide the index -> gather latency.
 constexpr int kSpmvWaves = 4;
 constexpr int kSpmvThreads = 64 * kSpmvWaves;
+
+// Row steps [s0, s1) of workgroup w: one step each when the grid has a workgroup per
+// step (the usual launch; workgroups past the last step get none), else an even split.
+__device__ __forceinline__ void step_range(int w, const SpmvShape &sh, int &s0, int &s1) {
+    if (sh.nwg >= sh.steps) {
+        s0 = w;
+        s1 = w < sh.steps ? w + 1 : w;
+    } else {
+        s0 = (int)(((int64_t)w * sh.steps) / sh.nwg);
+        s1 = (int)(((int64_t)(w + 1) * sh.steps) / sh.nwg);
+    }
+}
 
 // Row handled by this lane group at step s, or -1.
 template <int G>
@@ -175,7 +198,8 @@ __device__ __forceinline__ void k_spmv_body(int vb, SpmvShape sh, const int32_t 
                                                    double *__restrict__ y, double *__restrict__ part) {
     __shared__ double lds[kSpmvWaves];
     const int w = xcd_remap(vb, sh.nwg);
-    const int s0 = (int)(((int64_t)w * sh.steps) / sh.nwg), s1 = (int)(((int64_t)(w + 1) * sh.steps) / sh.nwg);
+    int s0, s1;
+    step_range(w, sh, s0, s1);
     const int lg = threadIdx.x % G;
     XPlain xl{x};
     double acc = 0.0;
@@ -212,8 +236,10 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvShape sh, const int32
 
 
 // Matrix product of Algorithm 1 for iteration i = st->iter: q = K p_i (p_i in buffer
-// i & 1, formed by k_beta_p) and partials of p_i^T q.  Only the single-workgroup
-// kernels change the flag, so it is stable while this kernel runs.
+// i & 1, formed by the prolongation or the beta kernel) and partials of p_i^T q.  Only
+// single-workgroup kernels and workgroup 0 of later kernels change the flag, so it is
+// stable while this kernel runs.  The first step's row pointers are loaded before the
+// state, so that the two round trips overlap.
 template <int G, class V>
 __device__ __forceinline__ void k_spmv_p_body(int vb, SpmvShape sh, const int32_t *__restrict__ brow_ptr,
                                                          const int32_t *__restrict__ bcol,
@@ -222,17 +248,30 @@ __device__ __forceinline__ void k_spmv_p_body(int vb, SpmvShape sh, const int32_
                                                          double *__restrict__ q, double *__restrict__ part_pq,
                                                          const State *st) {
     __shared__ double lds[kSpmvWaves];
+    const int w = xcd_remap(vb, sh.nwg);
+    int s0, s1;
+    step_range(w, sh, s0, s1);
+    const int lg = threadIdx.x % G;
+    int row = s0 < s1 ? step_row<G>(s0, sh.nb) : -1;
+    int beg = 0, end = 0;
+    if (row >= 0) {
+        beg = brow_ptr[row];
+        end = brow_ptr[row + 1];
+    }
     if (st->flag != kRunning) return;
     const double *__restrict__ p = (st->iter & 1) ? p1 : p0;
     XPlain xl{p};
-    const int w = xcd_remap(vb, sh.nwg);
-    const int s0 = (int)(((int64_t)w * sh.steps) / sh.nwg), s1 = (int)(((int64_t)(w + 1) * sh.steps) / sh.nwg);
-    const int lg = threadIdx.x % G;
     double acc = 0.0;
     for (int s = s0; s < s1; ++s) {
-        const int row = step_row<G>(s, sh.nb);
+        if (s > s0) {
+            row = step_row<G>(s, sh.nb);
+            if (row >= 0) {
+                beg = brow_ptr[row];
+                end = brow_ptr[row + 1];
+            }
+        }
         double a0, a1, a2;
-        block_row<G>(row, lg, brow_ptr, bcol, bval, nnzb, xl, a0, a1, a2);
+        block_row_span<G>(row, beg, end, lg, bcol, bval, xl, a0, a1, a2);
         if (row >= 0 && lg < 3) {
             const int64_t i = 3 * (int64_t)row + lg;
             const double v = pick3(lg, a0, a1, a2);
@@ -312,18 +351,22 @@ __global__ __launch_bounds__(kThreads) void k_beta_p(const double *__restrict__ 
 }
 
 
-// y_d = sum_j Minv_B[d - s_B, j] r_{s_B + j} for the DoFs of this tile (whole blocks).
+// y_d = sum_j Minv_B[d - s_B, j] r_{s_B + j} for the DoFs of this tile (whole blocks),
+// given row d's inverse row m and its packed size and position in the block.
 template <class M>
-__device__ __forceinline__ double bj_row(int t, int64_t d, const double *tile, const M *__restrict__ minv,
-                                         const int32_t *__restrict__ bj_rowoff,
-                                         const int32_t *__restrict__ bj_meta) {
-    const int meta = bj_meta[d];
+__device__ __forceinline__ double bj_row_at(int t, const double *tile, const M *__restrict__ m, int meta) {
     const int size = meta >> 8, loc = meta & 255;
-    const M *m = minv + bj_rowoff[d];
     const double *rt = tile + (t - loc);
     double s = 0.0;
     for (int j = 0; j < size; ++j) s = fma(m[j], rt[j], s);
     return s;
+}
+
+template <class M>
+__device__ __forceinline__ double bj_row(int t, int64_t d, const double *tile, const M *__restrict__ minv,
+                                         const int32_t *__restrict__ bj_rowoff,
+                                         const int32_t *__restrict__ bj_meta) {
+    return bj_row_at(t, tile, minv + bj_rowoff[d], bj_meta[d]);
 }
 
 // Step length, solution and residual updates of Algorithm 1 with the residual norm
@@ -337,19 +380,39 @@ __device__ __forceinline__ void k_update_bj_body(int vb,
     const State *st) {
     __shared__ double lds[4];
     __shared__ double tile[kThreads];
+    const int t = threadIdx.x;
+    const int w = xcd_remap(vb, nwg);
+    int t0, t1;
+    if ((uint64_t)ntiles * (uint64_t)nwg < (1ull << 32)) {  // 32-bit quotients when they fit
+        t0 = (int)(((uint32_t)w * (uint32_t)ntiles) / (uint32_t)nwg);
+        t1 = (int)(((uint32_t)(w + 1) * (uint32_t)ntiles) / (uint32_t)nwg);
+    } else {
+        t0 = (int)(((int64_t)w * ntiles) / nwg);
+        t1 = (int)(((int64_t)(w + 1) * ntiles) / nwg);
+    }
+    // the first tile's bounds are loaded before the state, so the two round trips overlap
+    int64_t b0 = 0, b1 = 0;
+    if (t0 < t1) {
+        b0 = tile_start[t0];
+        b1 = tile_start[t0 + 1];
+    }
     if (st->flag != kRunning) return;
     const double alpha = st->alpha;
     const double *p = (st->iter & 1) ? p1 : p0;
-    const int t = threadIdx.x;
-    const int w = xcd_remap(vb, nwg);
-    const int t0 = (int)(((int64_t)w * ntiles) / nwg), t1 = (int)(((int64_t)(w + 1) * ntiles) / nwg);
     double acc = 0.0, accy = 0.0;
     for (int tt = t0; tt < t1; ++tt) {
-        const int64_t d0 = tile_start[tt], d1 = tile_start[tt + 1];
+        if (tt > t0) {
+            b0 = tile_start[tt];
+            b1 = tile_start[tt + 1];
+        }
+        const int64_t d0 = b0, d1 = b1;
         const int64_t d = d0 + t;
         double rn = 0.0;
+        int meta = 0, roff = 0;  // loaded with the vectors, ahead of the barrier
         __syncthreads();
         if (d < d1) {
+            meta = bj_meta[d];
+            roff = bj_rowoff[d];
             u[d] = fma(alpha, p[d], u[d]);
             rn = fma(-alpha, q[d], r[d]);
             r[d] = rn;
@@ -358,7 +421,7 @@ __device__ __forceinline__ void k_update_bj_body(int vb,
         }
         __syncthreads();
         if (d < d1) {
-            const double yd = bj_row(t, d, tile, minv, bj_rowoff, bj_meta);
+            const double yd = bj_row_at(t, tile, minv + roff, meta);
             y[d] = yd;
             accy = fma(rn, yd, accy);
         }
@@ -654,6 +717,21 @@ __device__ __forceinline__ void k_prolong_p_body(int vb, int64_t n, int32_t nwg,
     __shared__ double lds[4];
     if (wg_flag(st) != kRunning) return;
     const int it = st->iter;
+    double *__restrict__ pc = (it & 1) ? p1 : p0;
+    const double *__restrict__ pp = (it & 1) ? p0 : p1;
+    const int w = xcd_remap(vb, nwg);
+    const int64_t per = (n + nwg - 1) / nwg;
+    const int64_t d1 = min(n, (int64_t)(w + 1) * per);
+    // the thread's first row, y + Z delta and the old p, before beta is known: these
+    // loads overlap the reduction below
+    int64_t d = (int64_t)w * per + threadIdx.x;
+    double v = 0.0, pold = 0.0;
+    if (d < d1) {
+        double c = 0.0;
+        for (int e = z_ptr[d]; e < z_ptr[d + 1]; ++e) c = fma(z_val[e], delta[z_col[e]], c);
+        v = y[d] + c;
+        pold = pp[d];
+    }
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     {
         constexpr int T = kThreads;
@@ -680,12 +758,8 @@ __device__ __forceinline__ void k_prolong_p_body(int vb, int64_t n, int32_t nwg,
         }
     }
     if (bad) return;
-    double *__restrict__ pc = (it & 1) ? p1 : p0;
-    const double *__restrict__ pp = (it & 1) ? p0 : p1;
-    const int w = xcd_remap(vb, nwg);
-    const int64_t per = (n + nwg - 1) / nwg;
-    const int64_t d1 = min(n, (int64_t)(w + 1) * per);
-    for (int64_t d = (int64_t)w * per + threadIdx.x; d < d1; d += kThreads) {
+    if (d < d1) pc[d] = fma(beta, pold, v);
+    for (d += kThreads; d < d1; d += kThreads) {
         double c = 0.0;
         for (int e = z_ptr[d]; e < z_ptr[d + 1]; ++e) c = fma(z_val[e], delta[z_col[e]], c);
         pc[d] = fma(beta, pp[d], y[d] + c);
