@@ -337,6 +337,28 @@ def test_single_triplet_system():
     assert np.allclose(host(u), np.linalg.solve(K, f), rtol=1e-12)
 
 
+def test_indefinite_system_breaks_down_like_the_oracle():
+    """Symmetric K with SPD nodal blocks but indefinite, f chosen so that p_0^T K p_0 < 0
+    (the system of the oracle's own breakdown test): the single solve and the
+    several-systems path both stop at iteration 0 with the breakdown status."""
+    from test_oracle import indefinite_breakdown_system
+    K, f, bp = indefinite_breakdown_system()
+    import scipy.sparse as sp
+    Ks = sp.csr_matrix(K)
+    Ks.sort_indices()
+    ref = O.Oracle(6, Ks.indptr.astype(np.int64), Ks.indices.astype(np.int32), Ks.data, 0,
+                   np.zeros(7, np.int64), np.zeros(0, np.int32), np.zeros(0), bp).solve(f)
+    with _solver_from_dense(K, None, bp) as s:
+        u, info = s.solve(dev(f), raise_on_error=False)
+        assert info["status"] == D.abi.EBREAKDOWN == ref["status"]
+        assert info["bad_index"] == ref["bad"] and info["iterations"] == ref["iterations"]
+        with pytest.raises(D.DpcgError) as e:
+            s.solve(dev(f))
+        assert e.value.code == D.abi.EBREAKDOWN
+        _, infos = D.solve_many([s], [dev(f)], raise_on_error=False)
+        assert infos[0]["status"] == D.abi.EBREAKDOWN and infos[0]["bad_index"] == ref["bad"]
+
+
 # ------------------------------------------------------------------ setup errors
 def test_setup_errors(problems):
     p = problems("edge4")

@@ -268,6 +268,31 @@ def test_status_codes(problems):
     assert e.value.status == O.EBLOCK_NOT_SPD and e.value.bad == b
 
 
+def indefinite_breakdown_system():
+    """K = [[A, 2A], [2A, A]] with A SPD: symmetric with SPD nodal blocks, but indefinite
+    (eigenvalues of A times 3 and -1).  With f = (A x, -A x) and no deflation, the first
+    search direction of Algorithm 1 is p_0 = M^-1 f = (x, -x), and p_0^T K p_0 =
+    2 x^T A x - 4 x^T A x = -2 x^T A x < 0: the step length has no valid value."""
+    A = np.array([[4.0, 1.0, 0.5], [1.0, 3.0, 0.2], [0.5, 0.2, 2.0]])
+    K = np.block([[A, 2 * A], [2 * A, A]])
+    x = np.array([1.0, -0.5, 0.25])
+    f = np.concatenate([A @ x, -(A @ x)])
+    return K, f, np.array([0, 3, 6])
+
+
+def test_indefinite_system_breaks_down_at_the_first_step():
+    K, f, bp = indefinite_breakdown_system()
+    assert np.linalg.eigvalsh(K).min() < 0
+    p0 = np.linalg.solve(np.kron(np.eye(2), K[:3, :3]), f)  # block-Jacobi, no deflation
+    assert p0 @ K @ p0 < 0
+    Ks = sp.csr_matrix(K)
+    Ks.sort_indices()
+    o = O.Oracle(6, Ks.indptr.astype(np.int64), Ks.indices.astype(np.int32), Ks.data, 0,
+                 np.zeros(7, np.int64), np.zeros(0, np.int32), np.zeros(0), bp)
+    r = o.solve(f)
+    assert r["status"] == O.EBREAKDOWN and r["bad"] == 0 and r["iterations"] == 0
+
+
 def test_deterministic(problems):
     p = problems("penny12")
     o = O.Oracle.from_problem(p)
