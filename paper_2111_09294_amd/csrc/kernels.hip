@@ -362,6 +362,24 @@ __device__ __forceinline__ double bj_row_at(int t, const double *tile, const M *
     return s;
 }
 
+// sum_e z_val[e] delta[z_col[e]] over e in [e0, e1) in index order, four entries per step
+// with their column, value and delta loads issued together (clamped as above).
+__device__ __forceinline__ double z_row_dot(int e0, int e1, const int32_t *__restrict__ z_col,
+                                            const double *__restrict__ z_val, const double *__restrict__ delta) {
+    double c = 0.0;
+    for (int e = e0; e < e1; e += 4) {
+        const int i1 = min(e + 1, e1 - 1), i2 = min(e + 2, e1 - 1), i3 = min(e + 3, e1 - 1);
+        const int32_t c0 = z_col[e], c1 = z_col[i1], c2 = z_col[i2], c3 = z_col[i3];
+        const double v0 = z_val[e], v1 = z_val[i1], v2 = z_val[i2], v3 = z_val[i3];
+        const double d0 = delta[c0], d1 = delta[c1], d2 = delta[c2], d3 = delta[c3];
+        c = fma(v0, d0, c);
+        if (e + 1 < e1) c = fma(v1, d1, c);
+        if (e + 2 < e1) c = fma(v2, d2, c);
+        if (e + 3 < e1) c = fma(v3, d3, c);
+    }
+    return c;
+}
+
 template <class M>
 __device__ __forceinline__ double bj_row(int t, int64_t d, const double *tile, const M *__restrict__ minv,
                                          const int32_t *__restrict__ bj_rowoff,
@@ -678,8 +696,7 @@ __device__ __forceinline__ void k_prolong_body(int vb, int64_t n, int32_t nwg, c
     double acc = 0.0;
     for (int64_t d = d0 + threadIdx.x; d < d1; d += kThreads) {
         double s = base ? base[d] : 0.0;
-        double c = 0.0;
-        for (int e = z_ptr[d]; e < z_ptr[d + 1]; ++e) c = fma(z_val[e], delta[z_col[e]], c);
+        const double c = z_row_dot(z_ptr[d], z_ptr[d + 1], z_col, z_val, delta);
         s += c;
         out[d] = s;
         if (rdot) acc = fma(rdot[d], s, acc);
@@ -727,8 +744,7 @@ __device__ __forceinline__ void k_prolong_p_body(int vb, int64_t n, int32_t nwg,
     int64_t d = (int64_t)w * per + threadIdx.x;
     double v = 0.0, pold = 0.0;
     if (d < d1) {
-        double c = 0.0;
-        for (int e = z_ptr[d]; e < z_ptr[d + 1]; ++e) c = fma(z_val[e], delta[z_col[e]], c);
+        const double c = z_row_dot(z_ptr[d], z_ptr[d + 1], z_col, z_val, delta);
         v = y[d] + c;
         pold = pp[d];
     }
@@ -760,8 +776,7 @@ __device__ __forceinline__ void k_prolong_p_body(int vb, int64_t n, int32_t nwg,
     if (bad) return;
     if (d < d1) pc[d] = fma(beta, pold, v);
     for (d += kThreads; d < d1; d += kThreads) {
-        double c = 0.0;
-        for (int e = z_ptr[d]; e < z_ptr[d + 1]; ++e) c = fma(z_val[e], delta[z_col[e]], c);
+        const double c = z_row_dot(z_ptr[d], z_ptr[d + 1], z_col, z_val, delta);
         pc[d] = fma(beta, pp[d], y[d] + c);
     }
 }
