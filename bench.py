@@ -31,11 +31,11 @@ HBM_PEAK_GBS = 8000.0
 SPMV_TRAFFIC = {
     "workload": "penny40",
     "sources": {
-        "paper_2111_09294_amd/csrc/kernels.hip": "46993671b3be451665f165994d8d3f1f1548c11ba50b89ce0b9ec472bde0dce8",
+        "paper_2111_09294_amd/csrc/kernels.hip": "60fe0a48b57125dca7338279e4cbb335fc9bc8626137cc3e6124bb84713b9bc3",
         "paper_2111_09294_amd/csrc/dpcg_internal.h": "c0ba109d4262e5c5c843b0b0f6bd48ea92e9f470dca8de0f2b5f3d72bdf9d8c6"
     },
-    "fetch_bytes": 171339671,
-    "write_bytes": 2028955,
+    "fetch_bytes": 171350110,
+    "write_bytes": 2029550,
 }
 
 
