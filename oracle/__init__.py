@@ -30,13 +30,16 @@ def lib():
                                    C.c_int32, P, C.POINTER(C.c_int64)]
         L.oracle_setup.restype = C.c_int
         L.oracle_destroy.argtypes = [P]
-        L.oracle_solve.argtypes = [P, P, P, C.c_double, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
+        L.oracle_solve.argtypes = [P, P, P, C.c_double, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int32),
                                    C.POINTER(C.c_double), C.POINTER(C.c_double), P, C.POINTER(C.c_int64)]
         L.oracle_solve.restype = C.c_int
         for name in ("oracle_spmv", "oracle_bj_apply", "oracle_coarse_solve", "oracle_coarse_matrix"):
             getattr(L, name).argtypes = [P, P, P] if name != "oracle_coarse_matrix" else [P, P]
-        L.oracle_adef2_apply.argtypes = [P, P, P, P]
-        L.oracle_start.argtypes = [P, P, P, P, P]
+        L.oracle_adef2_apply.argtypes = [P, P, P, P, C.c_int32]
+        L.oracle_start.argtypes = [P, P, P, P, P, C.c_int32]
+        L.oracle_prepare_fast.argtypes = [P]
+        L.oracle_prepare_fast.restype = C.c_int
+        L.oracle_coarse_inverse.argtypes = [P, P]
         L.oracle_zt_times.argtypes = [P, P, P]
         L.oracle_x_plus_z_times.argtypes = [P, P, P, P]
         L.oracle_k.argtypes = [P]
@@ -90,8 +93,10 @@ class Oracle:
             lib().oracle_destroy(h)
             self._h = None
 
-    def solve(self, f, tol=1e-8, max_iter=20000, u0=None, history=False):
-        """Returns dict(u, status, iterations, rel_res, rel_res_true, history, bad)."""
+    def solve(self, f, tol=1e-8, max_iter=20000, u0=None, history=False, fast=False):
+        """Returns dict(u, status, iterations, rel_res, rel_res_true, history, bad).
+        fast=True runs the fast mode (same iterates up to rounding, exact rewrites:
+        precomputed K Z, one merged coarse solve by the explicit E^-1)."""
         f = np.ascontiguousarray(f, np.float64)
         u = np.zeros(self.n) if u0 is None else np.array(u0, np.float64, copy=True)
         hist = np.zeros(max_iter + 1) if history else None
@@ -99,7 +104,7 @@ class Oracle:
         rr = C.c_double()
         rt = C.c_double()
         bad = C.c_int64()
-        st = lib().oracle_solve(self._h, _p(f), _p(u), float(tol), int(max_iter), int(u0 is not None),
+        st = lib().oracle_solve(self._h, _p(f), _p(u), float(tol), int(max_iter), int(u0 is not None), int(fast),
                                 C.byref(it), C.byref(rr), C.byref(rt), _p(hist), C.byref(bad))
         out = dict(u=u, status=st, iterations=it.value, rel_res=rr.value, rel_res_true=rt.value,
                    bad=bad.value)
@@ -137,17 +142,27 @@ class Oracle:
         lib().oracle_x_plus_z_times(self._h, _p(xx), _p(c), _p(y))
         return y
 
-    def adef2_apply(self, r):
+    def adef2_apply(self, r, fast=False):
         r = np.ascontiguousarray(r, np.float64)
         z = np.zeros(self.n)
         y = np.zeros(self.n)
-        lib().oracle_adef2_apply(self._h, _p(r), _p(z), _p(y))
+        lib().oracle_adef2_apply(self._h, _p(r), _p(z), _p(y), int(fast))
         return z, y
 
-    def start(self, f, u_m1=None):
+    def start(self, f, u_m1=None, fast=False):
         f = np.ascontiguousarray(f, np.float64)
         um = None if u_m1 is None else np.ascontiguousarray(u_m1, np.float64)
         u0 = np.zeros(self.n)
         r0 = np.zeros(self.n)
-        lib().oracle_start(self._h, _p(f), _p(um), _p(u0), _p(r0))
+        lib().oracle_start(self._h, _p(f), _p(um), _p(u0), _p(r0), int(fast))
         return u0, r0
+
+    def prepare_fast(self):
+        """Builds the fast mode's Z^T, (K Z)^T and explicit E^-1 (done on first use)."""
+        lib().oracle_prepare_fast(self._h)
+
+    def coarse_inverse(self):
+        """The fast mode's explicit E^-1 = L^-T L^-1 (k x k)."""
+        Ei = np.zeros((self.k, self.k))
+        lib().oracle_coarse_inverse(self._h, _p(Ei))
+        return Ei

@@ -12,13 +12,25 @@
  *     block_jacobi_enr); M^{-1} r is applied by a dense Cholesky solve per block;
  *   - coarse matrix E = Z^T K Z (Sec. 3.2, definition of Q), formed as Z^T (K Z)
  *     and symmetrised as (E + E^T)/2, factorised by dense Cholesky;
- *   - the A-DEF2 initial solution (Algorithm 2: two coarse solves),
- *   - the A-DEF2 preconditioner (Algorithm 3: y = M^{-1} r, two coarse solves
- *     with right-hand sides Z^T K y and Z^T r, z = y + Z(lambda - mu)), with an
- *     explicit product K y,
+ *   - the coarse-space correction Q = Z E^{-1} Z^T and the deflation projection
+ *     P = I - K Q (Sec. 3.2),
+ *   - the A-DEF2 initial solution u_0 = Q f + P^T u_{-1} (Sec. 3.2, Algorithm 2),
+ *   - the A-DEF2 preconditioner M_A-DEF2 = P^T M^{-1} + Q (Sec. 3.2, Algorithm 3):
+ *     z = P^T y + Q r with y = M^{-1} r, i.e. y - Q(K y) + Q r, each Q applied by
+ *     its own coarse Cholesky solve and the product K y formed explicitly,
  *   - preconditioned CG (Algorithm 1, Fletcher-Reeves beta), stopped when
  *     ||r_i||_2 <= tol ||f||_2 for the recursively updated residual (Sec. 4:
  *     relative tolerance 1e-8), tested after each residual update and once on r_0.
+ *
+ * A second, "fast" mode computes the same iterates (up to rounding) with the exact
+ * rewrites the GPU library uses, so that the CPU baseline is not slowed by
+ * redundant work: K Z is formed once at setup and Z^T K y is taken as (K Z)^T y
+ * (K = K^T); the two coarse solves of the preconditioner are merged into one,
+ * delta = E^{-1} (Z^T r - (K Z)^T y), z = y + Z delta (linearity of E^{-1}); and
+ * E^{-1} is formed explicitly from the Cholesky factor (E^{-1} = L^{-T} L^{-1}), so
+ * a coarse solve is one dense matrix-vector product.  The start vector is
+ * u_0 = u_{-1} + Z E^{-1} (Z^T f - (K Z)^T u_{-1}).  The literal mode remains the
+ * reference; the fast mode is pinned to it by the tests.
  *
  * Readings where the paper is silent: the iteration count is the number of K p
  * products; a breakdown is p^T K p <= 0 or a non-finite alpha or r^T z; f = 0
@@ -57,6 +69,11 @@ typedef struct {
     double *lb;                              /* dense lower Cholesky factors of K_BB */
     double *le;                              /* dense lower Cholesky factor of E (k x k) */
     double *ework;                           /* E itself (k x k), kept for inspection */
+    /* fast mode, built on its first use (oracle_prepare_fast) */
+    int fast_ready;
+    int64_t *ztp; int32_t *ztc; double *ztv; /* Z^T, CSR k x n */
+    int64_t *kztp; int32_t *kztc; double *kztv; /* (K Z)^T, CSR k x n */
+    double *einv;                            /* E^{-1}, dense k x k */
 } oracle_t;
 
 /* ---------------------------------------------------------------- basic ops */
@@ -79,14 +96,14 @@ static void zt_times(const oracle_t *o, const double *x, double *b) {
         for (int64_t e = o->zp[i]; e < o->zp[i + 1]; e++) b[o->zc[e]] += o->zv[e] * x[i];
 }
 
-/* y = x + Z c. */
+/* y = x + Z c (x nullable: 0). */
 static void x_plus_z_times(const oracle_t *o, const double *x, const double *c, double *y) {
     int64_t i;
 #pragma omp parallel for schedule(static)
     for (i = 0; i < o->n; i++) {
         double s = 0.0;
         for (int64_t e = o->zp[i]; e < o->zp[i + 1]; e++) s += o->zv[e] * c[o->zc[e]];
-        y[i] = x[i] + s;
+        y[i] = x ? x[i] + s : s;
     }
 }
 
@@ -165,6 +182,8 @@ void oracle_destroy(oracle_t *o) {
     free(o->kp); free(o->kc); free(o->kv);
     free(o->zp); free(o->zc); free(o->zv);
     free(o->bp); free(o->lb_off); free(o->lb); free(o->le); free(o->ework);
+    free(o->ztp); free(o->ztc); free(o->ztv);
+    free(o->kztp); free(o->kztc); free(o->kztv); free(o->einv);
     free(o);
 }
 
@@ -257,49 +276,219 @@ int oracle_setup(oracle_t **out, int64_t n,
 
 /* ---------------------------------------------------------------- algorithms */
 
-/* Algorithm 2: u0 = u_{-1} + Z(mu - lambda) with E lambda = Z^T K u_{-1} and
- * E mu = Z^T f.  u_m1 may be NULL (u_{-1} = 0).  work: 2n + 4k doubles. */
+/* out = Q x = Z E^{-1} Z^T x, the coarse-space correction of Sec. 3.2, applied by a
+ * Cholesky solve with E.  work: 2k doubles. */
+static void apply_Q(const oracle_t *o, const double *x, double *out, double *work) {
+    double *b = work, *c = work + o->k;
+    zt_times(o, x, b);
+    coarse_solve(o, b, c);
+    x_plus_z_times(o, NULL, c, out);
+}
+
+/* Literal start (Sec. 3.2, Algorithm 2): u_0 = Q f + P^T u_{-1}, with
+ * P^T u_{-1} = u_{-1} - Q K u_{-1} (P = I - K Q, K and Q symmetric).
+ * u_m1 may be NULL (u_{-1} = 0).  work: 3n + 2k doubles. */
 static void adef2_start(const oracle_t *o, const double *f, const double *u_m1, double *u0,
                         double *work) {
     int64_t n = o->n;
-    int32_t k = o->k;
-    double *ku = work, *zero = work + n, *b1 = work + 2 * n, *lam = b1 + k, *b2 = lam + k,
-           *mu = b2 + k;
-    if (k == 0) {
+    if (o->k == 0) {
         for (int64_t i = 0; i < n; i++) u0[i] = u_m1 ? u_m1[i] : 0.0;
         return;
     }
+    double *qf = work, *ku = work + n, *qku = work + 2 * n, *cw = work + 3 * n;
+    apply_Q(o, f, qf, cw);
     if (u_m1) {
         spmv(o, u_m1, ku);
-        zt_times(o, ku, b1);
+        apply_Q(o, ku, qku, cw);
+        for (int64_t i = 0; i < n; i++) u0[i] = qf[i] + (u_m1[i] - qku[i]);
     } else {
-        for (int32_t j = 0; j < k; j++) b1[j] = 0.0;
+        for (int64_t i = 0; i < n; i++) u0[i] = qf[i];
     }
-    coarse_solve(o, b1, lam);
-    zt_times(o, f, b2);
-    coarse_solve(o, b2, mu);
-    for (int32_t j = 0; j < k; j++) mu[j] -= lam[j];
-    for (int64_t i = 0; i < n; i++) zero[i] = u_m1 ? u_m1[i] : 0.0;
-    x_plus_z_times(o, zero, mu, u0);
 }
 
-/* Algorithm 3: z = A-DEF2(r).  work: n + 4k doubles. */
+/* Literal preconditioner (Sec. 3.2, Algorithm 3): z = M_A-DEF2 r = P^T M^{-1} r + Q r
+ * = y - Q(K y) + Q r with y = M^{-1} r.  work: 3n + 2k doubles. */
 static void adef2_apply(const oracle_t *o, const double *r, double *z, double *y,
                         double *work) {
-    int32_t k = o->k;
+    int64_t n = o->n;
     bj_apply(o, r, y);
-    if (k == 0) {
+    if (o->k == 0) {
+        memcpy(z, y, sizeof(double) * (size_t)n);
+        return;
+    }
+    double *ky = work, *qky = work + n, *qr = work + 2 * n, *cw = work + 3 * n;
+    spmv(o, y, ky);
+    apply_Q(o, ky, qky, cw);
+    apply_Q(o, r, qr, cw);
+    for (int64_t i = 0; i < n; i++) z[i] = (y[i] - qky[i]) + qr[i];
+}
+
+/* ---------------------------------------------------------------- fast mode */
+
+/* Transpose of a CSR m x c matrix into a CSR c x m matrix (rows of each column in
+ * increasing order). */
+static void csr_transpose(int64_t m, int32_t c, const int64_t *p, const int32_t *ci, const double *v,
+                          int64_t **tp, int32_t **tc, double **tv) {
+    int64_t nnz = p[m];
+    int64_t *q = (int64_t *)calloc((size_t)c + 1, sizeof(int64_t));
+    for (int64_t e = 0; e < nnz; e++) q[ci[e] + 1]++;
+    for (int32_t j = 0; j < c; j++) q[j + 1] += q[j];
+    int64_t *fill = (int64_t *)xdup(q, sizeof(int64_t) * (size_t)c);
+    int32_t *cc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nnz ? nnz : 1));
+    double *vv = (double *)malloc(sizeof(double) * (size_t)(nnz ? nnz : 1));
+    for (int64_t i = 0; i < m; i++)
+        for (int64_t e = p[i]; e < p[i + 1]; e++) {
+            int64_t d = fill[ci[e]]++;
+            cc[d] = (int32_t)i;
+            vv[d] = v[e];
+        }
+    free(fill);
+    *tp = q; *tc = cc; *tv = vv;
+}
+
+/* Builds Z^T, (K Z)^T and E^{-1} for the fast mode (once per oracle). */
+int oracle_prepare_fast(oracle_t *o) {
+    if (o->fast_ready) return OR_OK;
+    int64_t n = o->n;
+    int32_t k = o->k;
+    if (k > 0) {
+        csr_transpose(n, k, o->zp, o->zc, o->zv, &o->ztp, &o->ztc, &o->ztv);
+        /* K Z row by row: (K Z)[r, j] = sum_e K[r, c_e] Z[c_e, j], columns sorted */
+        int64_t *kzp = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+        int64_t r;
+#pragma omp parallel
+        {
+            char *mark = (char *)calloc((size_t)k, 1);
+#pragma omp for schedule(static)
+            for (r = 0; r < n; r++) {
+                int64_t cnt = 0;
+                for (int64_t e = o->kp[r]; e < o->kp[r + 1]; e++)
+                    for (int64_t f = o->zp[o->kc[e]]; f < o->zp[o->kc[e] + 1]; f++)
+                        if (!mark[o->zc[f]]) { mark[o->zc[f]] = 1; cnt++; }
+                for (int64_t e = o->kp[r]; e < o->kp[r + 1]; e++)
+                    for (int64_t f = o->zp[o->kc[e]]; f < o->zp[o->kc[e] + 1]; f++) mark[o->zc[f]] = 0;
+                kzp[r + 1] = cnt;
+            }
+            free(mark);
+        }
+        for (r = 0; r < n; r++) kzp[r + 1] += kzp[r];
+        int32_t *kzc = (int32_t *)malloc(sizeof(int32_t) * (size_t)(kzp[n] ? kzp[n] : 1));
+        double *kzv = (double *)malloc(sizeof(double) * (size_t)(kzp[n] ? kzp[n] : 1));
+#pragma omp parallel
+        {
+            double *acc = (double *)calloc((size_t)k, sizeof(double));
+            char *mark = (char *)calloc((size_t)k, 1);
+#pragma omp for schedule(static)
+            for (r = 0; r < n; r++) {
+                int64_t d = kzp[r];
+                for (int64_t e = o->kp[r]; e < o->kp[r + 1]; e++)
+                    for (int64_t f = o->zp[o->kc[e]]; f < o->zp[o->kc[e] + 1]; f++) {
+                        int32_t j = o->zc[f];
+                        if (!mark[j]) { mark[j] = 1; kzc[d++] = j; }
+                        acc[j] += o->kv[e] * o->zv[f];
+                    }
+                /* sort the row's columns (insertion sort: rows hold a few dozen) */
+                for (int64_t a = kzp[r] + 1; a < kzp[r + 1]; a++) {
+                    int32_t t = kzc[a];
+                    int64_t b = a - 1;
+                    while (b >= kzp[r] && kzc[b] > t) { kzc[b + 1] = kzc[b]; b--; }
+                    kzc[b + 1] = t;
+                }
+                for (int64_t a = kzp[r]; a < kzp[r + 1]; a++) {
+                    kzv[a] = acc[kzc[a]];
+                    acc[kzc[a]] = 0.0;
+                    mark[kzc[a]] = 0;
+                }
+            }
+            free(acc);
+            free(mark);
+        }
+        csr_transpose(n, k, kzp, kzc, kzv, &o->kztp, &o->kztc, &o->kztv);
+        free(kzp); free(kzc); free(kzv);
+        /* E^{-1} = L^{-T} L^{-1}: X row j = column j of L^{-1} (forward substitution
+         * from row j on), then (E^{-1})_{ab} = sum_{c >= max(a, b)} X[a][c] X[b][c] */
+        const double *L = o->le;
+        double *X = (double *)calloc((size_t)k * (size_t)k, sizeof(double));
+        int32_t j;
+#pragma omp parallel for schedule(dynamic, 8)
+        for (j = 0; j < k; j++) {
+            double *x = X + (int64_t)j * k;
+            for (int64_t i = j; i < k; i++) {
+                double s = (i == j) ? 1.0 : 0.0;
+                for (int64_t p = j; p < i; p++) s -= L[i * k + p] * x[p];
+                x[i] = s / L[i * k + i];
+            }
+        }
+        o->einv = (double *)malloc(sizeof(double) * (size_t)k * (size_t)k);
+        int32_t a;
+#pragma omp parallel for schedule(dynamic, 8)
+        for (a = 0; a < k; a++) {
+            const double *xa = X + (int64_t)a * k;
+            for (int32_t b = 0; b <= a; b++) {
+                const double *xb = X + (int64_t)b * k;
+                double s = 0.0;
+                for (int64_t c = a; c < k; c++) s += xa[c] * xb[c];
+                o->einv[(int64_t)a * k + b] = s;
+            }
+        }
+        for (a = 0; a < k; a++)
+            for (int32_t b = a + 1; b < k; b++) o->einv[(int64_t)a * k + b] = o->einv[(int64_t)b * k + a];
+        free(X);
+    }
+    o->fast_ready = 1;
+    return OR_OK;
+}
+
+/* g = Z^T a - (K Z)^T b (b nullable: 0); one k-row of each transpose per entry, summed
+ * in increasing row order. */
+static void fast_restrict(const oracle_t *o, const double *a, const double *b, double *g) {
+    int32_t j;
+#pragma omp parallel for schedule(static)
+    for (j = 0; j < o->k; j++) {
+        double s = 0.0, t = 0.0;
+        for (int64_t e = o->ztp[j]; e < o->ztp[j + 1]; e++) s += o->ztv[e] * a[o->ztc[e]];
+        if (b)
+            for (int64_t e = o->kztp[j]; e < o->kztp[j + 1]; e++) t += o->kztv[e] * b[o->kztc[e]];
+        g[j] = s - t;
+    }
+}
+
+/* delta = E^{-1} g (dense product, each row summed in column order). */
+static void fast_coarse(const oracle_t *o, const double *g, double *delta) {
+    int32_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < o->k; i++) {
+        const double *row = o->einv + (int64_t)i * o->k;
+        double s = 0.0;
+        for (int32_t j = 0; j < o->k; j++) s += row[j] * g[j];
+        delta[i] = s;
+    }
+}
+
+/* Fast start: u_0 = u_{-1} + Z E^{-1} (Z^T f - (K Z)^T u_{-1}).  work: 2k doubles. */
+static void fast_start(const oracle_t *o, const double *f, const double *u_m1, double *u0, double *work) {
+    int64_t n = o->n;
+    if (o->k == 0) {
+        for (int64_t i = 0; i < n; i++) u0[i] = u_m1 ? u_m1[i] : 0.0;
+        return;
+    }
+    double *g = work, *d = work + o->k;
+    fast_restrict(o, f, u_m1, g);
+    fast_coarse(o, g, d);
+    x_plus_z_times(o, u_m1, d, u0);
+}
+
+/* Fast preconditioner: z = y + Z E^{-1} (Z^T r - (K Z)^T y), y = M^{-1} r.  work: 2k. */
+static void fast_apply(const oracle_t *o, const double *r, double *z, double *y, double *work) {
+    bj_apply(o, r, y);
+    if (o->k == 0) {
         memcpy(z, y, sizeof(double) * (size_t)o->n);
         return;
     }
-    double *ky = work, *b1 = work + o->n, *mu = b1 + k, *b2 = mu + k, *lam = b2 + k;
-    spmv(o, y, ky);
-    zt_times(o, ky, b1);
-    coarse_solve(o, b1, mu);
-    zt_times(o, r, b2);
-    coarse_solve(o, b2, lam);
-    for (int32_t j = 0; j < k; j++) lam[j] -= mu[j];
-    x_plus_z_times(o, y, lam, z);
+    double *g = work, *d = work + o->k;
+    fast_restrict(o, r, y, g);
+    fast_coarse(o, g, d);
+    x_plus_z_times(o, y, d, z);
 }
 
 static int all_finite(int64_t n, const double *v) {
@@ -310,9 +499,10 @@ static int all_finite(int64_t n, const double *v) {
 
 /* Algorithm 1 preconditioned by Algorithm 3, started from Algorithm 2.
  * u: in (u_{-1} when use_initial_guess) / out (solution).  history (nullable)
- * receives ||r_i||/||f|| for i = 0..iterations.  Returns a status code. */
-int oracle_solve(const oracle_t *o, const double *f, double *u, double tol, int32_t max_iter,
-                 int32_t use_initial_guess, int32_t *iterations, double *rel_res,
+ * receives ||r_i||/||f|| for i = 0..iterations.  fast = 0: the literal operators;
+ * fast = 1: the fast mode (oracle_prepare_fast first).  Returns a status code. */
+int oracle_solve(oracle_t *o, const double *f, double *u, double tol, int32_t max_iter,
+                 int32_t use_initial_guess, int32_t fast, int32_t *iterations, double *rel_res,
                  double *rel_res_true, double *history, int64_t *bad) {
     int64_t n = o->n;
     int32_t k = o->k;
@@ -327,14 +517,18 @@ int oracle_solve(const oracle_t *o, const double *f, double *u, double tol, int3
         if (history) history[0] = 0.0;
         return OR_OK;
     }
-    size_t wn = (size_t)(7 * n + 8 * (int64_t)k + 8);
+    if (fast) oracle_prepare_fast(o);
+    size_t wn = (size_t)(8 * n + 8 * (int64_t)k + 8);
     double *w = (double *)malloc(sizeof(double) * wn);
     double *r = w, *z = r + n, *p = z + n, *q = p + n, *y = q + n, *tmp = y + n;
     double *u_m1 = NULL;
     if (use_initial_guess) {
         u_m1 = (double *)xdup(u, sizeof(double) * (size_t)n);
     }
-    adef2_start(o, f, u_m1, u, tmp);
+    if (fast)
+        fast_start(o, f, u_m1, u, tmp);
+    else
+        adef2_start(o, f, u_m1, u, tmp);
     free(u_m1);
     spmv(o, u, q);
     for (int64_t i = 0; i < n; i++) r[i] = f[i] - q[i];
@@ -345,7 +539,10 @@ int oracle_solve(const oracle_t *o, const double *f, double *u, double tol, int3
     if (rnorm <= tol * fnorm) {
         status = OR_OK;
     } else {
-        adef2_apply(o, r, z, y, tmp);
+        if (fast)
+            fast_apply(o, r, z, y, tmp);
+        else
+            adef2_apply(o, r, z, y, tmp);
         memcpy(p, z, sizeof(double) * (size_t)n);
         double rho = dot(n, r, z);
         for (int32_t i = 0; i < max_iter; i++) {
@@ -366,7 +563,10 @@ int oracle_solve(const oracle_t *o, const double *f, double *u, double tol, int3
                 status = OR_OK;
                 break;
             }
-            adef2_apply(o, r, z, y, tmp);
+            if (fast)
+                fast_apply(o, r, z, y, tmp);
+            else
+                adef2_apply(o, r, z, y, tmp);
             double rho_new = dot(n, r, z);
             if (!isfinite(rho_new)) {
                 status = OR_EBREAKDOWN;
@@ -393,20 +593,36 @@ void oracle_spmv(const oracle_t *o, const double *x, double *y) { spmv(o, x, y);
 
 void oracle_bj_apply(const oracle_t *o, const double *r, double *y) { bj_apply(o, r, y); }
 
-/* z = A-DEF2(r) (Algorithm 3); y receives M^{-1} r. */
-void oracle_adef2_apply(const oracle_t *o, const double *r, double *z, double *y) {
-    double *w = (double *)malloc(sizeof(double) * (size_t)(o->n + 4 * (int64_t)o->k + 4));
-    adef2_apply(o, r, z, y, w);
+/* z = A-DEF2(r) (Algorithm 3); y receives M^{-1} r.  fast selects the mode. */
+void oracle_adef2_apply(oracle_t *o, const double *r, double *z, double *y, int32_t fast) {
+    double *w = (double *)malloc(sizeof(double) * (size_t)(3 * o->n + 4 * (int64_t)o->k + 4));
+    if (fast) {
+        oracle_prepare_fast(o);
+        fast_apply(o, r, z, y, w);
+    } else {
+        adef2_apply(o, r, z, y, w);
+    }
     free(w);
 }
 
-/* u0 from Algorithm 2 (u_m1 nullable) and r0 = f - K u0. */
-void oracle_start(const oracle_t *o, const double *f, const double *u_m1, double *u0, double *r0) {
-    double *w = (double *)malloc(sizeof(double) * (size_t)(2 * o->n + 4 * (int64_t)o->k + 4));
-    adef2_start(o, f, u_m1, u0, w);
+/* u0 from Algorithm 2 (u_m1 nullable) and r0 = f - K u0.  fast selects the mode. */
+void oracle_start(oracle_t *o, const double *f, const double *u_m1, double *u0, double *r0, int32_t fast) {
+    double *w = (double *)malloc(sizeof(double) * (size_t)(3 * o->n + 4 * (int64_t)o->k + 4));
+    if (fast) {
+        oracle_prepare_fast(o);
+        fast_start(o, f, u_m1, u0, w);
+    } else {
+        adef2_start(o, f, u_m1, u0, w);
+    }
     spmv(o, u0, r0);
     for (int64_t i = 0; i < o->n; i++) r0[i] = f[i] - r0[i];
     free(w);
+}
+
+/* Copies the fast mode's explicit E^{-1} (k x k) into out. */
+void oracle_coarse_inverse(oracle_t *o, double *out) {
+    oracle_prepare_fast(o);
+    if (o->k > 0) memcpy(out, o->einv, sizeof(double) * (size_t)o->k * (size_t)o->k);
 }
 
 /* x = E^{-1} b. */
@@ -435,11 +651,5 @@ void oracle_zt_times(const oracle_t *o, const double *x, double *b) { zt_times(o
 
 /* y = x + Z c (x nullable: 0). */
 void oracle_x_plus_z_times(const oracle_t *o, const double *x, const double *c, double *y) {
-    if (x) {
-        x_plus_z_times(o, x, c, y);
-    } else {
-        double *zero = (double *)calloc((size_t)o->n, sizeof(double));
-        x_plus_z_times(o, zero, c, y);
-        free(zero);
-    }
+    x_plus_z_times(o, x, c, y);
 }

@@ -69,34 +69,37 @@ def test_solution_matches_dense_lapack(problems, name):
 
 
 # ------------------------------------------------------------------ Sec. 3.2 operators
+@pytest.mark.parametrize("fast", [False, True])
 @pytest.mark.parametrize("name", ["edge4", "penny12"])
-def test_adef2_apply_is_the_operator(problems, name):
-    """Algorithm 3 applies M_A-DEF2 = P^T M^{-1} + Q with P = I - K Q, Q = Z E^{-1} Z^T."""
+def test_adef2_apply_is_the_operator(problems, name, fast):
+    """Algorithm 3 applies M_A-DEF2 = P^T M^{-1} + Q with P = I - K Q, Q = Z E^{-1} Z^T
+    (the literal mode and the fast mode's merged coarse solve alike)."""
     p = problems(name)
     K, Z, Q, P, Minv = _dense_operators(p)
     o = O.Oracle.from_problem(p)
     rng = np.random.default_rng(11)
     for _ in range(3):
         r = rng.standard_normal(p.n)
-        z, y = o.adef2_apply(r)
+        z, y = o.adef2_apply(r, fast=fast)
         ref = P.T @ (Minv @ r) + Q @ r
         assert np.linalg.norm(z - ref) <= 1e-8 * np.linalg.norm(ref)
         assert np.linalg.norm(y - Minv @ r) <= 1e-12 * np.linalg.norm(y)
 
 
+@pytest.mark.parametrize("fast", [False, True])
 @pytest.mark.parametrize("name", ["edge4", "penny12"])
-def test_adef2_start_is_the_operator(problems, name):
-    """Algorithm 2 gives u_0 = Q f + P^T u_{-1}."""
+def test_adef2_start_is_the_operator(problems, name, fast):
+    """Algorithm 2 gives u_0 = Q f + P^T u_{-1} (both modes)."""
     p = problems(name)
     K, Z, Q, P, _ = _dense_operators(p)
     o = O.Oracle.from_problem(p)
     rng = np.random.default_rng(5)
     um1 = rng.standard_normal(p.n)
-    u0, r0 = o.start(p.f, um1)
+    u0, r0 = o.start(p.f, um1, fast=fast)
     ref = Q @ p.f + P.T @ um1
     assert np.linalg.norm(u0 - ref) <= 1e-8 * np.linalg.norm(ref)
     assert np.allclose(r0, p.f - K @ u0, rtol=0, atol=1e-12 * np.abs(p.f).max())
-    u0z, _ = o.start(p.f, None)
+    u0z, _ = o.start(p.f, None, fast=fast)
     assert np.linalg.norm(u0z - Q @ p.f) <= 1e-8 * np.linalg.norm(Q @ p.f)
 
 
@@ -107,6 +110,42 @@ def test_PK_symmetric_PtK_not(problems):
     PK, PtK = P @ K, P.T @ K
     assert np.abs(PK - PK.T).max() <= 1e-9 * np.abs(PK).max()
     assert np.abs(PtK - PtK.T).max() >= 1e-3 * np.abs(PtK).max()
+
+
+@pytest.mark.parametrize("name", ["plain6", "edge4", "penny12", "edge10"])
+def test_fast_mode_takes_the_literal_iterates(problems, name):
+    """The fast mode (K Z precomputed, one merged coarse solve by the explicit E^-1,
+    Sec. 3.2 identities Z^T K y = (K Z)^T y and lambda - mu = E^-1 (Z^T r - Z^T K y))
+    reproduces the literal mode's iteration count and iterates up to rounding."""
+    p = problems(name)
+    o = O.Oracle.from_problem(p)
+    a = o.solve(p.f, tol=1e-8, history=True)
+    b = o.solve(p.f, tol=1e-8, history=True, fast=True)
+    assert a["status"] == b["status"] == O.OK
+    assert a["iterations"] == b["iterations"]
+    assert np.linalg.norm(a["u"] - b["u"]) <= 1e-10 * np.linalg.norm(a["u"])
+    # residual histories agree to the last digits that rounding leaves intact (the
+    # recurrences amplify rounding as ||r_i|| falls: 1e-5 relative at edge4's end)
+    assert np.all(np.abs(a["history"] - b["history"]) <= 1e-4 * a["history"])
+    # warm start and a few iterations: same recurrences
+    um1 = np.random.default_rng(9).standard_normal(p.n)
+    a = o.solve(p.f, tol=1e-8, max_iter=5, u0=um1)
+    b = o.solve(p.f, tol=1e-8, max_iter=5, u0=um1, fast=True)
+    assert a["iterations"] == b["iterations"]
+    assert np.linalg.norm(a["u"] - b["u"]) <= 1e-9 * np.linalg.norm(a["u"])
+
+
+def test_fast_coarse_inverse(problems):
+    """The fast mode's explicit E^-1 = L^-T L^-1 against LAPACK's inverse of E."""
+    p = problems("penny12")
+    o = O.Oracle.from_problem(p)
+    E = o.coarse_matrix()
+    Ei = o.coarse_inverse()
+    ref = np.linalg.inv(E)
+    kappa = np.linalg.cond(E)
+    assert np.abs(Ei - Ei.T).max() == 0.0
+    assert np.linalg.norm(Ei - ref) <= 1e-15 * kappa * np.linalg.norm(ref)
+    assert np.abs(Ei @ E - np.eye(p.k)).max() <= 1e-15 * kappa
 
 
 def test_coarse_matrix(problems):
