@@ -6,9 +6,14 @@ setup (block-Jacobi inverses, K Z, E = Z^T K Z and E^-1, device layout) followed
 one solve of K u = f to relative residual 1e-8 and the release of the handle.  The
 inputs (K, Z, blocks, f as device arrays) are resident in HBM before timing starts.
 
+The headline workload is the 80^3 configuration (1.66M DoFs), the largest that the
+method's configurations put on one GPU; its matrix (1.38 GB of block values) is far
+larger than the 256 MB last-level cache, so the SpMV roofline there is an HBM figure.
 Prints one JSON line with the throughput, the SpMV kernel's HBM roofline fraction
 (algorithmic bytes / average launch duration measured with HIP events on the
-library's stream during the timed steps) and the CPU oracle timed on this host.
+library's stream during the timed steps), the mixed-precision comparison and both
+paths' errors against the CPU oracle, the oracle itself timed on this host, and the
+40^3 lines (FP64, 32 right-hand sides, uneven systems, subdomain blocks) as extras.
 """
 from __future__ import annotations
 
@@ -22,27 +27,41 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-
-# HBM bytes moved by one k_spmv_p launch on penny40, from two rocprofv3 --pmc passes
-# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the launches of iterations
-# that did work), each scaled by what the same counter reads for a 512 MiB device copy
-# (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources with these
-# digests: after any change to them the figure is reported as null until re-measured.
-SPMV_TRAFFIC = {
-    "workload": "penny40",
-    "sources": {
-        "paper_2111_09294_amd/csrc/kernels.hip": "60fe0a48b57125dca7338279e4cbb335fc9bc8626137cc3e6124bb84713b9bc3",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "c0ba109d4262e5c5c843b0b0f6bd48ea92e9f470dca8de0f2b5f3d72bdf9d8c6"
-    },
-    "fetch_bytes": 171350110,
-    "write_bytes": 2029550,
+METRIC = "DoF-solves/sec to rel. residual 1e-8 + SpMV HBM GB/s fraction; FP64 vs mixed/batched"
+WORKLOADS = {
+    "penny80": "80^3 hex8 unit cube (1.66M DoFs), curved penny crack (R=0.25, z=0.5+0.3 rho^2), Heaviside + "
+               "branch enrichment within r_e=0.05, 8^3 subdomains, clamped bottom, unit top traction, FP64, "
+               "tol 1e-8",
+    "penny40": "40^3 hex8 unit cube, curved penny crack (R=0.25, z=0.5+0.3 rho^2), Heaviside + branch "
+               "enrichment within r_e=0.05, 4^3 subdomains, clamped bottom, unit top traction, FP64, tol 1e-8",
+    "edge10": "10^3 hex8 unit cube, planar edge crack x=0.5 z<0.45, Heaviside + branch enrichment within "
+              "r_e=0.15, 2^3 subdomains, clamped bottom, unit top traction, FP64, tol 1e-8",
 }
+
+# HBM bytes moved by one k_spmv_p launch on the headline workload, from two rocprofv3
+# --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the launches of
+# iterations that did work), each scaled by what the same counter reads for a 512 MiB
+# device copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  Valid only for the kernel sources
+# with these digests: after any change to them the figure is reported as null until
+# re-measured.
+SPMV_TRAFFIC = {
+    "workload": "penny80",
+    "sources": {},
+    "fetch_bytes": None,
+    "write_bytes": None,
+}
+SPMV_SOURCES = ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h")
+
+# The roofline's kernel duration comes from start/stop events recorded by every
+# TIMING_EVERY-th SpMV launch of the timed steps: events on each launch add about 8 us to
+# every iteration, sampling keeps the timed run close to an untimed one.
+TIMING_EVERY = 8
 
 
 def _source_digests():
     import hashlib
     out = {}
-    for rel in ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h"):
+    for rel in SPMV_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             out[rel] = hashlib.sha256(fh.read()).hexdigest()
     return out
@@ -55,20 +74,6 @@ def spmv_traffic(workload):
     if workload != t["workload"] or t["fetch_bytes"] is None or _source_digests() != t["sources"]:
         return None
     return t["fetch_bytes"] + t["write_bytes"]
-METRIC = "DoF-solves/sec to rel. residual 1e-8 + SpMV HBM GB/s fraction; FP64 vs mixed/batched"
-WORKLOADS = {
-    "penny40": "40^3 hex8 unit cube, curved penny crack (R=0.25, z=0.5+0.3 rho^2), Heaviside + branch "
-               "enrichment within r_e=0.05, 4^3 subdomains, clamped bottom, unit top traction, FP64, tol 1e-8",
-    "edge10": "10^3 hex8 unit cube, planar edge crack x=0.5 z<0.45, Heaviside + branch enrichment within "
-              "r_e=0.15, 2^3 subdomains, clamped bottom, unit top traction, FP64, tol 1e-8",
-    "penny80": "80^3 hex8 unit cube, curved penny crack, r_e=0.05, 8^3 subdomains, FP64, tol 1e-8",
-}
-
-
-# The roofline's kernel duration comes from start/stop events recorded by every
-# TIMING_EVERY-th SpMV launch of the timed steps: events on each launch add about 8 us to
-# every iteration (0.8 ms per solve), sampling keeps the timed run close to an untimed one.
-TIMING_EVERY = 8
 
 
 def spmv_bytes(nnzb, n, value_bytes=8):
@@ -77,60 +82,114 @@ def spmv_bytes(nnzb, n, value_bytes=8):
     return nnzb * (9 * value_bytes + 4) + 4 * (n // 3 + 1) + 2 * 8 * n
 
 
-def cpu_baseline(p, budget_s=12.0):
-    """The oracle (plain C FP64, OpenMP row loops) on the same workload, full steps."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(p, literal_iters=20):
+    """The oracle (plain C FP64, OpenMP over rows and blocks, sequential dot products)
+    on the same workload: one full step of its fast mode (setup, then K Z, E^-1 and a
+    solve to 1e-8), the rewrites the GPU uses (one merged coarse solve, precomputed
+    K Z), which takes the literal mode's iterates (pinned by the CPU tests).  The literal
+    mode (two coarse Cholesky solves and an explicit K y per iteration) is timed on its
+    first literal_iters iterations and scaled to the fast mode's iteration count.
+    Returns (line, oracle solution)."""
     import oracle
 
     t0 = time.perf_counter()
-    reps = 0
-    its = None
-    while True:
-        o = oracle.Oracle.from_problem(p)
-        r = o.solve(p.f, tol=1e-8)
-        del o
-        its = r["iterations"]
-        reps += 1
-        if time.perf_counter() - t0 >= budget_s or reps >= 20:
-            break
-    dt = time.perf_counter() - t0
-    return {"value": p.n * reps / dt, "unit": "DoF-solves/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{reps} full steps (setup + solve to 1e-8, {its} iterations) of the same workload, "
-                      f"{dt:.1f} s"}
+    o = oracle.Oracle.from_problem(p)
+    t1 = time.perf_counter()
+    o.prepare_fast()
+    t2 = time.perf_counter()
+    r = o.solve(p.f, tol=1e-8, fast=True)
+    t3 = time.perf_counter()
+    lit = o.solve(p.f, tol=1e-8, max_iter=literal_iters)
+    t4 = time.perf_counter()
+    del o
+    setup_s, prep_s, solve_s = t1 - t0, t2 - t1, t3 - t2
+    step_s = setup_s + prep_s + solve_s
+    lit_iter_s = (t4 - t3) / max(1, lit["iterations"])
+    lit_step_s = setup_s + lit_iter_s * r["iterations"]
+    line = {"value": p.n / step_s, "unit": "DoF-solves/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"one full step of the workload with the oracle's fast mode: setup {setup_s:.1f} s, K Z and "
+                      f"E^-1 {prep_s:.1f} s, solve to 1e-8 {solve_s:.1f} s ({r['iterations']} iterations)",
+            "cpu_model": cpu_model(), "iterations": r["iterations"], "status": r["status"],
+            "solve_only_dof_solves_per_s": p.n / solve_s,
+            "literal_mode": {"value": p.n / lit_step_s, "unit": "DoF-solves/s",
+                             "sample": f"setup plus {lit['iterations']} literal iterations ({t4 - t3:.1f} s), "
+                                       f"scaled to {r['iterations']} iterations"}}
+    return line, r["u"]
 
 
-def run_mixed(step, p, args, stats):
-    """The same steps with precision "mixed" (FP64 refinement around inner solves on
-    binary32 copies of K and of the block inverses), to the same true FP64 residual."""
+def upload(p, dev):
+    import numpy as np
+    import torch
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
+    K = (t(p.k_rowptr, torch.int64), t(p.k_col, torch.int32), t(p.k_val, torch.float64))
+    Z = (t(p.z_rowptr, torch.int64), t(p.z_col, torch.int32), t(p.z_val, torch.float64))
+    return K, Z, t(p.block_ptr, torch.int32), t(p.f, torch.float64)
+
+
+def run_steps(p, tensors, steps, warmup, stream, precision="fp64"):
+    """warmup untimed then `steps` timed full steps (setup, solve to 1e-8, release),
+    SpMV events on every TIMING_EVERY-th launch.  Returns a dict of the results and the
+    last solution (device tensor)."""
     import numpy as np
     import torch
 
-    for _ in range(args.warmup):
-        step(False, "mixed")
+    import paper_2111_09294_amd as dpcg
+    K, Z, bp, f = tensors
+    u = torch.empty_like(f)
+
+    def step(timing):
+        s = dpcg.Solver(p.n, *K, p.k, *Z, bp, stream=stream)
+        if timing:
+            s.set_timing(True, every=TIMING_EVERY)
+        _, info = s.solve(f, u, tol=1e-8, precision=precision)
+        tm = s.timing() if timing else None
+        st = s.stats()
+        s.close()
+        return info, tm, st
+
+    for _ in range(warmup):
+        step(False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos, spmv_ms, spmv_n = [], 0.0, 0
-    for _ in range(args.steps):
-        info, tm, _ = step(True, "mixed")
+    infos, spmv_ms, spmv_n, st = [], 0.0, 0, None
+    for _ in range(steps):
+        info, tm, st = step(True)
         infos.append(info)
         spmv_ms += tm["spmv_ms"]
         spmv_n += tm["spmv_launches"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    bad = [i for i in infos if i["status"] != 0 or i["rel_res_true"] > 1e-8]
     per_launch_s = spmv_ms / 1e3 / max(spmv_n, 1)
-    nbytes = spmv_bytes(stats["nnzb"], p.n, value_bytes=4)
+    nbytes = spmv_bytes(st["nnzb"], p.n, value_bytes=8 if precision == "fp64" else 4)
     achieved = nbytes / per_launch_s / 1e9
-    return {"value": p.n * args.steps / dt, "unit": "DoF-solves/s", "ms_per_step": dt * 1e3 / args.steps,
-            "ok": not bad, "iterations": infos[-1]["iterations"], "refinements": infos[-1]["refinements"],
-            "rel_res_true": infos[-1]["rel_res_true"],
-            "setup_ms": float(np.mean([i["setup_ms"] for i in infos])),
-            "solve_ms": float(np.mean([i["solve_ms"] for i in infos])),
-            "spmv_fp32_values": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                 "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": nbytes,
-                                 "launches": spmv_n, "avg_launch_us": per_launch_s * 1e6}}
+    out = {"value": p.n * steps / dt, "unit": "DoF-solves/s", "ms_per_step": dt * 1e3 / steps,
+           "ok": all(i["status"] == 0 and i["rel_res_true"] <= 1.5e-8 for i in infos),
+           "iterations": infos[-1]["iterations"], "rel_res_true": infos[-1]["rel_res_true"],
+           "setup_ms": float(np.mean([i["setup_ms"] for i in infos])),
+           "solve_ms": float(np.mean([i["solve_ms"] for i in infos])),
+           "spmv": {"kernel": "k_spmv_p<32, double>" if precision == "fp64" else "k_spmv_p<32, float>",
+                    "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                    "bytes_per_launch": nbytes, "launches": spmv_n, "avg_launch_us": per_launch_s * 1e6},
+           "stats": st}
+    if precision != "fp64":
+        out["refinements"] = infos[-1]["refinements"]
+        out["iterations_fp64"] = infos[-1]["iterations_fp64"]
+    out["solve_only_dof_solves_per_s"] = p.n / (out["solve_ms"] / 1e3)
+    return out, u
 
 
-def run_batched(p, args, K, Z, bp, f, stream, nrhs=32):
+def run_batched(name, p, args, K, Z, bp, f, stream, nrhs=32):
     """The same steps with nrhs right-hand sides solved together (Case A of the batching
     workload: seeded random top-face tractions, N(0, 1) components per face node),
     every column to 1e-8."""
@@ -140,7 +199,7 @@ def run_batched(p, args, K, Z, bp, f, stream, nrhs=32):
     import paper_2111_09294_amd as dpcg
 
     from fixtures import box
-    F = box(args.workload).random_top_tractions(nrhs, seed=2024)
+    F = box(name).random_top_tractions(nrhs, seed=2024)
     Fd = torch.as_tensor(F, device=f.device)
     U = torch.empty_like(Fd)
 
@@ -231,67 +290,7 @@ def run_many(args, count=16):
             "iterations_max": max(i["iterations"] for i in infos), "generation_s": t_gen}
 
 
-def run_large(name="penny80", steps=2):
-    """The FP64 path on the 80^3 configuration (1.66M DoFs): its matrix (1.38 GB of block
-    values) is far larger than the 256 MB last-level cache, so the SpMV figure there is
-    an HBM figure; at 40^3 an iteration's data (about 250 MB) can partly stay in that
-    cache.  Full steps (setup + solve to 1e-8), SpMV events on every 8th launch."""
-    import numpy as np
-    import torch
-
-    import paper_2111_09294_amd as dpcg
-    from fixtures import load
-
-    t_gen = time.perf_counter()
-    q = load(name)
-    t_gen = time.perf_counter() - t_gen
-    dev = torch.device("cuda:0")
-    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
-    K = (t(q.k_rowptr, torch.int64), t(q.k_col, torch.int32), t(q.k_val, torch.float64))
-    Z = (t(q.z_rowptr, torch.int64), t(q.z_col, torch.int32), t(q.z_val, torch.float64))
-    bp = t(q.block_ptr, torch.int32)
-    f = t(q.f, torch.float64)
-    u = torch.empty_like(f)
-
-    def step(timing):
-        s = dpcg.Solver(q.n, *K, q.k, *Z, bp)
-        if timing:
-            s.set_timing(True, every=TIMING_EVERY)
-        _, info = s.solve(f, u, tol=1e-8)
-        tm = s.timing() if timing else None
-        st = s.stats()
-        s.close()
-        return info, tm, st
-
-    step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos, spmv_ms, spmv_n = [], 0.0, 0
-    for _ in range(steps):
-        info, tm, st = step(True)
-        infos.append(info)
-        spmv_ms += tm["spmv_ms"]
-        spmv_n += tm["spmv_launches"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    per_launch_s = spmv_ms / 1e3 / max(spmv_n, 1)
-    nbytes = spmv_bytes(st["nnzb"], q.n)
-    achieved = nbytes / per_launch_s / 1e9
-    out = {"value": q.n * steps / dt, "unit": "DoF-solves/s", "workload": name, "n_dofs": q.n, "k": q.k,
-           "nnzb": st["nnzb"], "steps": steps, "ms_per_step": dt * 1e3 / steps,
-           "ok": all(i["status"] == 0 and i["rel_res_true"] <= 1.5e-8 for i in infos),
-           "iterations": infos[-1]["iterations"],
-           "setup_ms": float(np.mean([i["setup_ms"] for i in infos])),
-           "solve_ms": float(np.mean([i["solve_ms"] for i in infos])),
-           "spmv": {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                    "bytes_per_launch": nbytes, "launches": spmv_n, "avg_launch_us": per_launch_s * 1e6},
-           "generation_s": t_gen}
-    del K, Z, bp, f, u, q
-    torch.cuda.empty_cache()
-    return out
-
-
-def run_subdomain(args, p, nsds=(8, 4)):
+def run_subdomain(name, args, p, nsds=(8, 4)):
     """The paper's subdomain-sized block-Jacobi blocks (Sec. 3.4): the same system
     renumbered subdomain by subdomain with one block per subdomain of an nsd^3 box
     partition (explicit inverses from batched Gauss-Jordan sweeps at setup, a dense
@@ -306,7 +305,7 @@ def run_subdomain(args, p, nsds=(8, 4)):
     out = {}
     dev = torch.device("cuda:0")
     for nsd in nsds:
-        q, _ = with_subdomain_blocks(args.workload, nsd, p)
+        q, _ = with_subdomain_blocks(name, nsd, p)
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
         K = (t(q.k_rowptr, torch.int64), t(q.k_col, torch.int32), t(q.k_val, torch.float64))
         Z = (t(q.z_rowptr, torch.int64), t(q.z_col, torch.int32), t(q.z_val, torch.float64))
@@ -352,12 +351,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="penny40", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="penny80", choices=sorted(WORKLOADS))
+    ap.add_argument("--extra-workload", default="penny40", choices=sorted(WORKLOADS),
+                    help="workload of the 32-RHS, uneven-systems and subdomain-block lines")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison line")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 32-right-hand-side comparison line")
+    ap.add_argument("--no-extra", action="store_true", help="skip every line on the extra workload")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 32-right-hand-side and uneven-systems lines")
     ap.add_argument("--no-subdomain", action="store_true", help="skip the subdomain-block comparison lines")
-    ap.add_argument("--no-large", action="store_true", help="skip the 80^3 FP64 line")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also run N plain 512 MiB device copies (counter calibration)")
     args = ap.parse_args()
@@ -369,29 +370,14 @@ def main():
     import numpy as np
     import torch
 
-    import paper_2111_09294_amd as dpcg
     from fixtures import load
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    p = load(args.workload)
-    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a)).to(dev, dt)  # noqa: E731
-    K = (t(p.k_rowptr, torch.int64), t(p.k_col, torch.int32), t(p.k_val, torch.float64))
-    Z = (t(p.z_rowptr, torch.int64), t(p.z_col, torch.int32), t(p.z_val, torch.float64))
-    bp = t(p.block_ptr, torch.int32)
-    f = t(p.f, torch.float64)
-    u = torch.empty_like(f)
     stream = torch.cuda.current_stream()
-
-    def step(timing, precision="fp64"):
-        s = dpcg.Solver(p.n, *K, p.k, *Z, bp, stream=stream)
-        if timing:
-            s.set_timing(True, every=TIMING_EVERY)
-        _, info = s.solve(f, u, tol=1e-8, precision=precision)
-        tm = s.timing() if timing else None
-        st = s.stats()
-        s.close()
-        return info, tm, st
+    print(f"[bench] {args.workload}: generating the system", file=sys.stderr, flush=True)
+    p = load(args.workload)
+    tensors = upload(p, dev)
 
     if args.calibrate_copy:
         a = torch.empty(64 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -401,37 +387,21 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos, spmv_ms, spmv_n = [], 0.0, 0
-    stats = None
-    for _ in range(args.steps):
-        info, tm, stats = step(True)
-        infos.append(info)
-        spmv_ms += tm["spmv_ms"]
-        spmv_n += tm["spmv_launches"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    for info in infos:
-        if info["status"] != 0 or info["rel_res_true"] > 1.5e-8:
-            print(f"solve failed: {info}", file=sys.stderr)
-            return 1
-    ms_step = dt * 1e3 / args.steps
-    solve_ms = float(np.mean([i["solve_ms"] for i in infos]))
-    setup_ms = float(np.mean([i["setup_ms"] for i in infos]))
-    per_launch_s = spmv_ms / 1e3 / max(spmv_n, 1)
-    nbytes = spmv_bytes(stats["nnzb"], p.n)
-    achieved = nbytes / per_launch_s / 1e9
+    print(f"[bench] {args.workload}: FP64 steps", file=sys.stderr, flush=True)
+    fp64, u64 = run_steps(p, tensors, args.steps, args.warmup, stream)
+    if not fp64["ok"]:
+        print(f"solve failed: {fp64}", file=sys.stderr)
+        return 1
+    stats = fp64.pop("stats")
+    rf = fp64["spmv"]
     out = {
         "metric": METRIC,
-        "value": p.n * args.steps / dt,
+        "value": fp64["value"],
         "unit": "DoF-solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": fp64["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -440,27 +410,52 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "n_dofs": p.n,
                    "n_std": p.meta["n_std"], "n_enr": p.meta["n_enr"], "k": p.k, "nnzb": stats["nnzb"],
                    "nblocks": p.nblocks, "parallelism": "single GPU"},
-        "iterations": infos[-1]["iterations"],
-        "setup_ms": setup_ms,
-        "solve_ms": solve_ms,
-        "solve_only_dof_solves_per_s": p.n / (solve_ms / 1e3),
-        "rel_res_true": infos[-1]["rel_res_true"],
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": spmv_traffic(args.workload),
-                     "kernel": "k_spmv_p", "bytes_per_launch": nbytes, "launches": spmv_n,
-                     "avg_launch_us": per_launch_s * 1e6},
+        "iterations": fp64["iterations"],
+        "setup_ms": fp64["setup_ms"],
+        "solve_ms": fp64["solve_ms"],
+        "solve_only_dof_solves_per_s": fp64["solve_only_dof_solves_per_s"],
+        "rel_res_true": fp64["rel_res_true"],
+        "roofline": {"bound": "hbm", "achieved": rf["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": rf["frac"], "traffic": spmv_traffic(args.workload), "kernel": rf["kernel"],
+                     "bytes_per_launch": rf["bytes_per_launch"], "launches": rf["launches"],
+                     "avg_launch_us": rf["avg_launch_us"]},
     }
+    um = None
     if not args.no_mixed:
-        out["mixed"] = run_mixed(step, p, args, stats)
-    if not args.no_batched:
-        out["batched"] = run_batched(p, args, K, Z, bp, f, stream)
-        out["many_systems"] = run_many(args)
-    if not args.no_subdomain:
-        out["subdomain_blocks"] = run_subdomain(args, p)
-    if not args.no_large:
-        out["large_80"] = run_large()
+        print(f"[bench] {args.workload}: mixed-precision steps", file=sys.stderr, flush=True)
+        mixed, um = run_steps(p, tensors, args.steps, args.warmup, stream, precision="mixed")
+        mixed.pop("stats")
+        mixed["spmv_fp32_values"] = mixed.pop("spmv")
+        mixed["speedup_vs_fp64"] = mixed["value"] / fp64["value"]
+        out["mixed"] = mixed
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p)
+        print(f"[bench] {args.workload}: CPU oracle", file=sys.stderr, flush=True)
+        line, uo = cpu_baseline(p)
+        out["cpu_baseline"] = line
+        nref = np.linalg.norm(uo)
+        out["error_vs_oracle"] = {"fp64": float(np.linalg.norm(u64.cpu().numpy() - uo) / nref)}
+        if um is not None:
+            out["error_vs_oracle"]["mixed"] = float(np.linalg.norm(um.cpu().numpy() - uo) / nref)
+    del tensors, u64, um
+    torch.cuda.empty_cache()
+
+    if not args.no_extra:
+        name = args.extra_workload
+        print(f"[bench] {name}: extra lines", file=sys.stderr, flush=True)
+        q = load(name)
+        tq = upload(q, dev)
+        line, _ = run_steps(q, tq, args.steps, args.warmup, stream)
+        line.pop("stats")
+        line["workload"] = name
+        line["n_dofs"] = q.n
+        out["fp64_" + name] = line
+        if not args.no_batched:
+            out["batched"] = run_batched(name, q, args, tq[0], tq[1], tq[2], tq[3], stream)
+            out["many_systems"] = run_many(args)
+        if not args.no_subdomain:
+            out["subdomain_blocks"] = run_subdomain(name, args, q)
+        del tq
+        torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
     return 0
 

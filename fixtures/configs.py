@@ -120,16 +120,28 @@ def log_normal_moduli(name: str, seed: int = 7, sigma: float = 0.5):
     return np.exp(sigma * np.random.default_rng(seed).standard_normal(nel))
 
 
-def uneven_systems(count: int = 16, seed: int = 16, ne_range=(20, 48), r_e: float = 0.05):
+def uneven_specs(count: int = 16, seed: int = 16, ne_range=(20, 48)):
+    """(ne, crack centre) of each system of the multi-system workload, in draw order."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        ne = int(rng.integers(ne_range[0], ne_range[1] + 1))
+        centre = tuple(float(v) for v in rng.uniform(0.3, 0.7, 3))
+        out.append((ne, centre))
+    return out
+
+
+def uneven_systems(count: int = 16, seed: int = 16, ne_range=(20, 48), r_e: float = 0.05, which=None):
     """Independent systems of the multi-system workload: meshes of ne^3 elements with ne
     uniform in ne_range, each with a curved penny crack (radius 0.25, curvature 0.3)
     whose centre is uniform in [0.3, 0.7]^3, 1 + ne // 12 subdomains per axis.
-    Returns a list of Problems (not cached)."""
-    rng = np.random.default_rng(seed)
+    which: indices of the systems to build (default all; the draws of the others are
+    still taken, so system i is the same either way).  Returns a list of Problems (not
+    cached)."""
+    specs = uneven_specs(count, seed, ne_range)
     out = []
-    for i in range(count):
-        ne = int(rng.integers(ne_range[0], ne_range[1] + 1))
-        centre = tuple(float(v) for v in rng.uniform(0.3, 0.7, 3))
+    for i in (range(count) if which is None else which):
+        ne, centre = specs[i]
         crack = CurvedPennyCrack(center=centre, R=0.25, curv=0.3)
         out.append(build_problem(f"uneven{i}", ne, 1 + ne // 12, crack=crack, r_e=r_e))
     return out

@@ -57,6 +57,11 @@ typedef struct {
     int32_t max_refinements;   /* mixed: cap on refinement cycles; default 50            */
     double inner_tol;          /* mixed: each inner solve reduces its residual by this
                                   factor (0 < inner_tol < 1); default 1e-4               */
+    double switch_tol;         /* mixed: the binary32 refinement stops once the true
+                                  residual is <= switch_tol ||f||, and FP64 CG started
+                                  from that iterate (Algorithm 2's u_{-1}) finishes the
+                                  solve to tol; switch_tol <= tol: refinement only.
+                                  Default 1e-6                                           */
 } dpcg_options;
 
 typedef struct {
@@ -68,7 +73,8 @@ typedef struct {
     double solve_ms;           /* wall time of the last solve                           */
     int64_t bad_index;         /* offending block / row / iteration, or -1              */
     int32_t refinements;       /* mixed: refinement cycles (inner solves); FP64: 0      */
-    int32_t pad_;
+    int32_t iterations_fp64;   /* mixed: K p products of the final FP64 phase (included
+                                  in iterations); FP64: equal to iterations              */
 } dpcg_info;
 
 typedef struct {
@@ -118,6 +124,7 @@ void dpcg_default_options(dpcg_options *opt);
  *   stream: hipStream_t (may be NULL for the default stream) on which all of the
  *       handle's work is ordered.
  *
+ * K, Z and block_ptr are device arrays here (dpcg_setup_host takes host arrays).
  * The library deep-copies what it needs; the caller may free K, Z and block_ptr
  * on return.  Setup factorises every block and the coarse matrix E = Z^T K Z
  * (Sec. 3.2; both applied at every iteration) and allocates all device memory
@@ -131,6 +138,20 @@ int dpcg_setup(dpcg_handle *h, int64_t n,
                void *stream, dpcg_info *info);
 
 /*
+ * dpcg_setup with K, Z and block_ptr in HOST memory (the same arrays, sizes and
+ * checks; k_rowptr[n] and z_rowptr[n] give the entry counts).  The arrays are
+ * uploaded on `stream` into library-owned device memory, set up as by dpcg_setup
+ * and released once the setup has finished; the caller may free them on return.
+ * info->setup_ms includes the upload.  Errors as dpcg_setup (DPCG_EINVAL also for a
+ * row pointer that does not start at 0 or a negative entry count).
+ */
+int dpcg_setup_host(dpcg_handle *h, int64_t n,
+                    const int64_t *k_rowptr, const int32_t *k_col, const double *k_val,
+                    int32_t k, const int64_t *z_rowptr, const int32_t *z_col, const double *z_val,
+                    int32_t nblocks, const int32_t *block_ptr,
+                    void *stream, dpcg_info *info);
+
+/*
  * Solves K u = f to ||r_i||_2 <= tol ||f||_2 (Sec. 4: relative tolerance) with
  * Algorithm 1, started from Algorithm 2 and preconditioned by Algorithm 3.
  * f[n] and u[n] are caller-owned device buffers; u is output, and also input
@@ -140,17 +161,26 @@ int dpcg_setup(dpcg_handle *h, int64_t n,
  * DPCG_EINVAL (tol <= 0, max_iter < 0, inner_tol outside (0, 1) or an unknown
  * precision) or DPCG_EHIP.
  *
- * precision = DPCG_PREC_MIXED (an extension beyond the paper's FP64 method):
- * iterative refinement in FP64 around the same method run on binary32 copies of
- * K's values and of the block-Jacobi inverses (vectors, E^-1 and all arithmetic
- * stay binary64).  Each cycle solves K d = r_j for the current FP64 residual
- * r_j = f - K u_j (FP64 K) to ||r_j - K32 d|| <= inner_tol ||r_j||, then sets
- * u_{j+1} = u_j + d.  The solve stops when ||f - K u_j||_2 <= tol ||f||_2 (a true
- * residual, so rel_res_recursive = rel_res_true), or with DPCG_NOT_CONVERGED
- * after max_iter inner iterations in total or max_refinements cycles.
- * iterations counts the inner K p products; the history (record_history) holds
- * ||f - K u_j|| / ||f|| per cycle, j = 0..refinements.  The FP32 copies are made
- * on the first mixed solve of a handle (9 nnzb + sum b^2 floats).
+ * precision = DPCG_PREC_MIXED (an extension beyond the paper's FP64 method), two
+ * phases.  (1) Iterative refinement in FP64 around the same method run on binary32
+ * copies of K's values and of the block-Jacobi inverses (vectors, E^-1 and all
+ * arithmetic stay binary64): each cycle solves K d = r_j for the current FP64
+ * residual r_j = f - K u_j (FP64 K) to ||r_j - K32 d|| <= max(inner_tol ||r_j||,
+ * switch_tol ||f||), then sets u_{j+1} = u_j + d, until ||f - K u_j|| <=
+ * max(tol, switch_tol) ||f||.  (2) When that residual is still above tol ||f||, the
+ * FP64 method itself, started from that iterate (Algorithm 2 with u_{-1} = u_j),
+ * finishes to tol: each
+ * refinement cycle multiplies the error by the inner solve's own error-to-residual
+ * ratio, so refinement alone ends with a larger error than the FP64 method at the
+ * same residual; the FP64 phase removes it.  The solve stops with the FP64 phase's
+ * recursive residual <= tol ||f|| (rel_res_true is recomputed; without an FP64 phase
+ * both are the refinement's true residual), or with
+ * DPCG_NOT_CONVERGED after max_iter iterations in total or max_refinements cycles.
+ * iterations counts all K p products (binary32 inner ones and FP64 ones;
+ * iterations_fp64 the latter); the history (record_history) holds
+ * ||f - K u_j|| / ||f|| per cycle, j = 0..refinements, then the true residual after
+ * the FP64 phase when it ran.  The FP32 copies are made on the first mixed solve of a handle
+ * (9 nnzb + sum b^2 floats).
  */
 int dpcg_solve(dpcg_handle h, const double *f, double *u, double tol,
                const dpcg_options *opt, dpcg_info *info);

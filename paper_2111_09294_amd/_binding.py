@@ -23,16 +23,16 @@ PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED}
 class Options(C.Structure):
     _fields_ = [("max_iter", C.c_int32), ("check_every", C.c_int32), ("use_initial_guess", C.c_int32),
                 ("record_history", C.c_int32), ("precision", C.c_int32), ("max_refinements", C.c_int32),
-                ("inner_tol", C.c_double)]
+                ("inner_tol", C.c_double), ("switch_tol", C.c_double)]
 
 
 class Info(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("rel_res_recursive", C.c_double),
                 ("rel_res_true", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
-                ("bad_index", C.c_int64), ("refinements", C.c_int32), ("pad_", C.c_int32)]
+                ("bad_index", C.c_int64), ("refinements", C.c_int32), ("iterations_fp64", C.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad_"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Stats(C.Structure):
@@ -58,6 +58,8 @@ SIGNATURES = {
     "dpcg_default_options": (None, [C.POINTER(Options)]),
     "dpcg_setup": (C.c_int, [C.POINTER(P), C.c_int64, P, P, P, C.c_int32, P, P, P, C.c_int32, P, P,
                              C.POINTER(Info)]),
+    "dpcg_setup_host": (C.c_int, [C.POINTER(P), C.c_int64, P, P, P, C.c_int32, P, P, P, C.c_int32, P, P,
+                                  C.POINTER(Info)]),
     "dpcg_solve": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
     "dpcg_solve_adjoint": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
     "dpcg_solve_batch": (C.c_int, [P, C.c_int32, P, P, C.c_double, C.POINTER(Options), P]),
@@ -170,6 +172,32 @@ class Solver:
                    zr, t(p.z_col, torch.int32) if p.k else None, t(p.z_val, torch.float64) if p.k else None,
                    t(p.block_ptr, torch.int32), stream=stream)
 
+    @classmethod
+    def from_host_arrays(cls, n, k_rowptr, k_col, k_val, k, z_rowptr, z_col, z_val, block_ptr, stream=None):
+        """Builds the solver from host (numpy) CSR arrays through dpcg_setup_host."""
+        import numpy as np
+        import torch
+        arr = lambda a, dt: np.ascontiguousarray(a, dtype=dt)  # noqa: E731
+        keep = [arr(k_rowptr, np.int64), arr(k_col, np.int32), arr(k_val, np.float64),
+                arr(z_rowptr, np.int64) if k else None, arr(z_col, np.int32) if k else None,
+                arr(z_val, np.float64) if k else None, arr(block_ptr, np.int32)]
+        hp = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)  # noqa: E731
+        self = cls.__new__(cls)
+        self.n, self.k = int(n), int(k)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.device = self.stream.device
+        h = C.c_void_p()
+        info = Info()
+        st = lib().dpcg_setup_host(C.byref(h), self.n, hp(keep[0]), hp(keep[1]), hp(keep[2]), self.k, hp(keep[3]),
+                                   hp(keep[4]), hp(keep[5]), len(keep[6]) - 1, hp(keep[6]),
+                                   C.c_void_p(self.stream.cuda_stream), C.byref(info))
+        if st != OK:
+            self._h = None
+            raise DpcgError(st, "dpcg_setup_host", info)
+        self._h = h
+        self.setup_info = info.as_dict()
+        return self
+
     # ------------------------------------------------------------------ lifecycle
     def close(self):
         h = getattr(self, "_h", None)
@@ -196,7 +224,7 @@ class Solver:
         return self._h
 
     # ------------------------------------------------------------------ solves
-    def _opts(self, max_iter, check_every, guess, record, precision="fp64", inner_tol=None, max_refinements=None):
+    def _opts(self, max_iter, check_every, guess, record, precision="fp64", inner_tol=None, max_refinements=None, switch_tol=None):
         o = Options()
         lib().dpcg_default_options(C.byref(o))
         if max_iter is not None:
@@ -212,10 +240,12 @@ class Solver:
             o.inner_tol = float(inner_tol)
         if max_refinements is not None:
             o.max_refinements = int(max_refinements)
+        if switch_tol is not None:
+            o.switch_tol = float(switch_tol)
         return o
 
     def _run(self, fn, where, f, u, tol, max_iter, check_every, initial_guess, record_history, raise_on_error,
-             precision="fp64", inner_tol=None, max_refinements=None):
+             precision="fp64", inner_tol=None, max_refinements=None, switch_tol=None):
         import torch
         _check_dev(f, torch.float64, "rhs", self.n)
         if u is None:
@@ -226,7 +256,7 @@ class Solver:
             if initial_guess.data_ptr() != u.data_ptr():
                 u.copy_(initial_guess)
         o = self._opts(max_iter, check_every, initial_guess is not None, record_history, precision, inner_tol,
-                       max_refinements)
+                       max_refinements, switch_tol)
         info = Info()
         st = fn(self.handle, _ptr(f), _ptr(u), float(tol), C.byref(o), C.byref(info))
         if st < 0 and raise_on_error:
@@ -234,18 +264,19 @@ class Solver:
         return u, info.as_dict()
 
     def solve(self, f, u=None, tol=1e-8, max_iter=None, check_every=None, initial_guess=None,
-              record_history=False, raise_on_error=True, precision="fp64", inner_tol=None, max_refinements=None):
+              record_history=False, raise_on_error=True, precision="fp64", inner_tol=None, max_refinements=None, switch_tol=None):
         """u = K^{-1} f to ||r||/||f|| <= tol.  precision "mixed" runs FP64 iterative
-        refinement around inner solves on binary32 copies of K and the block inverses.
+        refinement around inner solves on binary32 copies of K and the block inverses
+        down to switch_tol, then the FP64 method from that iterate to tol.
         Returns (u, info dict)."""
         return self._run(lib().dpcg_solve, "dpcg_solve", f, u, tol, max_iter, check_every, initial_guess,
-                         record_history, raise_on_error, precision, inner_tol, max_refinements)
+                         record_history, raise_on_error, precision, inner_tol, max_refinements, switch_tol)
 
     def solve_adjoint(self, g, lam=None, tol=1e-8, max_iter=None, check_every=None, initial_guess=None,
-                      raise_on_error=True, precision="fp64", inner_tol=None, max_refinements=None):
+                      raise_on_error=True, precision="fp64", inner_tol=None, max_refinements=None, switch_tol=None):
         """lambda = K^{-1} g in the adjoint workspace.  Returns (lambda, info dict)."""
         return self._run(lib().dpcg_solve_adjoint, "dpcg_solve_adjoint", g, lam, tol, max_iter, check_every,
-                         initial_guess, False, raise_on_error, precision, inner_tol, max_refinements)
+                         initial_guess, False, raise_on_error, precision, inner_tol, max_refinements, switch_tol)
 
     def solve_batch(self, F, U=None, tol=1e-8, max_iter=None, check_every=None, initial_guess=None,
                     raise_on_error=True):

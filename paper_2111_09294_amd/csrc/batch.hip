@@ -1118,7 +1118,7 @@ int solve_batch(dpcg_ctx *c, int32_t nrhs, const double *F, double *U, double to
             in.solve_ms = ms;
             in.bad_index = bad;
             in.refinements = 0;
-            in.pad_ = 0;
+            in.iterations_fp64 = in.iterations;
         }
     }
     return worst;

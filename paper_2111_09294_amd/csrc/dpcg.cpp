@@ -187,7 +187,7 @@ void fill_info(dpcg_info *info, int status, int32_t iters, double rr, double rt,
     info->solve_ms = solve_ms;
     info->bad_index = bad;
     info->refinements = 0;
-    info->pad_ = 0;
+    info->iterations_fp64 = iters;
 }
 
 int ensure_history(dpcg_ctx *c, Workspace &w, int64_t need) {
@@ -337,8 +337,13 @@ int ensure_fp32(dpcg_ctx *c) {
     return DPCG_OK;
 }
 
-// Iterative refinement: FP64 residuals r_j = f - K u_j, inner solves K32 d = r_j by the
-// same method on the binary32 copies, u_{j+1} = u_j + d.
+// Mixed precision in two phases.  (1) Iterative refinement: FP64 residuals
+// r_j = f - K u_j, inner solves K32 d = r_j by the same method on the binary32 copies,
+// u_{j+1} = u_j + d, down to max(tol, switch_tol) ||f||.  (2) When switch_tol > tol, the
+// FP64 method started from that iterate (Algorithm 2 with u_{-1} = u_j) to tol: each
+// refinement cycle multiplies the error by its inner solve's error-to-residual ratio, so
+// refinement alone stops at the residual tolerance with a larger error than the FP64
+// method reaches there; the FP64 phase takes the error down to the FP64 method's own.
 int solve_mixed(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol, const dpcg_options &opt,
                 double fnorm, double t0, dpcg_info *info) {
     TRY(ensure_fp32(c));
@@ -347,10 +352,11 @@ int solve_mixed(dpcg_ctx *c, Workspace &w, const double *f, double *u, double to
         TRY(alloc(c, &w.dcor, (size_t)c->n));
     }
     if (!opt.use_initial_guess) HIP_TRY(hipMemsetAsync(u, 0, sizeof(double) * c->n, c->stream));
+    const double stop = std::max(tol, opt.switch_tol);
     double rn = 0.0;
     TRY(true_residual(c, w, f, u, w.rout, &rn));
     std::vector<double> hist(1, rn / fnorm);
-    int32_t total = 0, cycles = 0;
+    int32_t total = 0, cycles = 0, fp64_its = 0;
     int status = DPCG_NOT_CONVERGED;
     int64_t bad = -1;
     while (true) {
@@ -359,15 +365,17 @@ int solve_mixed(dpcg_ctx *c, Workspace &w, const double *f, double *u, double to
             bad = total;
             break;
         }
-        if (rn <= tol * fnorm) {
+        if (rn <= stop * fnorm) {
             status = DPCG_OK;
             break;
         }
         if (total >= opt.max_iter || cycles >= opt.max_refinements) break;
         State st;
+        // the last cycle aims below the switch point (half of it) so that rounding in
+        // K32 - K does not leave the true residual just above it
+        const double thr = std::max(opt.inner_tol * rn, 0.5 * opt.switch_tol * fnorm);
         c->inner32 = true;
-        const int e = run_cg(c, w, w.rout, w.dcor, opt.inner_tol * rn, false, opt.max_iter - total,
-                             opt.check_every, 0, st);
+        const int e = run_cg(c, w, w.rout, w.dcor, thr, false, opt.max_iter - total, opt.check_every, 0, st);
         c->inner32 = false;
         TRY(e);
         total += st.iters_done;
@@ -381,12 +389,31 @@ int solve_mixed(dpcg_ctx *c, Workspace &w, const double *f, double *u, double to
         TRY(true_residual(c, w, f, u, w.rout, &rn));
         hist.push_back(rn / fnorm);
     }
+    double rr = rn / fnorm;
+    if (status == DPCG_OK && opt.switch_tol > tol && rn > tol * fnorm) {
+        State st;
+        c->inner32 = false;
+        TRY(run_cg(c, w, f, u, tol * fnorm, true, opt.max_iter - total, opt.check_every, 0, st));
+        fp64_its = st.iters_done;
+        total += st.iters_done;
+        switch (st.flag) {
+            case kConverged: status = DPCG_OK; break;
+            case kBreakdown: status = DPCG_EBREAKDOWN; bad = total; break;
+            default: status = DPCG_NOT_CONVERGED; break;
+        }
+        rr = std::sqrt(st.rr) / fnorm;
+        TRY(true_residual(c, w, f, u, w.tmp, &rn));
+        hist.push_back(rn / fnorm);
+    }
     if (opt.record_history) {
         w.host_hist = hist;
         w.hist_len = (int32_t)hist.size();
     }
-    fill_info(info, status, total, rn / fnorm, rn / fnorm, c->setup_ms, now_ms() - t0, bad);
-    if (info) info->refinements = cycles;
+    fill_info(info, status, total, rr, rn / fnorm, c->setup_ms, now_ms() - t0, bad);
+    if (info) {
+        info->refinements = cycles;
+        info->iterations_fp64 = fp64_its;
+    }
     return status;
 }
 
@@ -399,7 +426,9 @@ int solve_impl(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol
     if (!c || !f || !u || !(tol > 0.0) || opt.max_iter < 0) return DPCG_EINVAL;
     const bool mixed = opt.precision == DPCG_PREC_MIXED;
     if (!mixed && opt.precision != DPCG_PREC_FP64) return DPCG_EINVAL;
-    if (mixed && (!(opt.inner_tol > 0.0 && opt.inner_tol < 1.0) || opt.max_refinements < 0)) return DPCG_EINVAL;
+    if (mixed && (!(opt.inner_tol > 0.0 && opt.inner_tol < 1.0) || opt.max_refinements < 0 ||
+                  !(opt.switch_tol >= 0.0 && opt.switch_tol < 1.0)))
+        return DPCG_EINVAL;
     if (opt.check_every <= 0) opt.check_every = 16;
     const bool guess = opt.use_initial_guess != 0;
     const int record = opt.record_history != 0;
@@ -701,6 +730,7 @@ void dpcg_default_options(dpcg_options *opt) {
     opt->precision = DPCG_PREC_FP64;
     opt->max_refinements = 50;
     opt->inner_tol = 1e-4;
+    opt->switch_tol = 1e-6;
 }
 
 int dpcg_setup(dpcg_handle *h, int64_t n, const int64_t *k_rowptr, const int32_t *k_col, const double *k_val,
@@ -726,6 +756,52 @@ int dpcg_setup(dpcg_handle *h, int64_t n, const int64_t *k_rowptr, const int32_t
     }
     *h = c;
     return DPCG_OK;
+}
+
+int dpcg_setup_host(dpcg_handle *h, int64_t n, const int64_t *k_rowptr, const int32_t *k_col, const double *k_val,
+                    int32_t k, const int64_t *z_rowptr, const int32_t *z_col, const double *z_val, int32_t nblocks,
+                    const int32_t *block_ptr, void *stream, dpcg_info *info) {
+    const double t0 = now_ms();
+    if (!h) return DPCG_EINVAL;
+    *h = nullptr;
+    if (n <= 0 || k < 0 || nblocks <= 0 || !k_rowptr || !k_col || !k_val || !block_ptr ||
+        (k > 0 && (!z_rowptr || !z_col || !z_val))) {
+        fill_info(info, DPCG_EINVAL, 0, 0, 0, 0, 0, -1);
+        return DPCG_EINVAL;
+    }
+    const int64_t nnz = k_rowptr[n], nnz_z = k > 0 ? z_rowptr[n] : 0;
+    if (nnz < 0 || nnz_z < 0 || k_rowptr[0] != 0 || (k > 0 && z_rowptr[0] != 0)) {
+        fill_info(info, DPCG_EINVAL, 0, 0, 0, 0, 0, -1);
+        return DPCG_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // device copies of the inputs (the setup copies what it keeps, so they go back to
+    // the allocation cache once it has finished)
+    struct Up {
+        void *p = nullptr;
+        ~Up() { if (p) dev_release(p); }
+    } kp, kc, kv, zp, zc, zv, bp;
+    auto up = [&](Up &d, const void *src, size_t bytes) -> bool {
+        if (dev_alloc(&d.p, std::max<size_t>(bytes, 1)) != hipSuccess) return false;
+        return bytes == 0 || hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    bool ok = up(kp, k_rowptr, sizeof(int64_t) * (n + 1)) && up(kc, k_col, sizeof(int32_t) * nnz) &&
+              up(kv, k_val, sizeof(double) * nnz) && up(bp, block_ptr, sizeof(int32_t) * (nblocks + 1));
+    if (ok && k > 0)
+        ok = up(zp, z_rowptr, sizeof(int64_t) * (n + 1)) && up(zc, z_col, sizeof(int32_t) * nnz_z) &&
+             up(zv, z_val, sizeof(double) * nnz_z);
+    if (!ok) {
+        (void)hipStreamSynchronize(s);
+        fill_info(info, DPCG_EHIP, 0, 0, 0, 0, 0, -1);
+        return DPCG_EHIP;
+    }
+    const int st = dpcg_setup(h, n, (const int64_t *)kp.p, (const int32_t *)kc.p, (const double *)kv.p, k,
+                              (const int64_t *)zp.p, (const int32_t *)zc.p, (const double *)zv.p, nblocks,
+                              (const int32_t *)bp.p, stream, info);
+    (void)hipStreamSynchronize(s);  // the uploads are released only once the stream is past them
+    if (st == DPCG_OK) (*h)->setup_ms = now_ms() - t0;
+    if (info) info->setup_ms = now_ms() - t0;
+    return st;
 }
 
 int dpcg_solve(dpcg_handle h, const double *f, double *u, double tol, const dpcg_options *opt, dpcg_info *info) {

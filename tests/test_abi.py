@@ -54,3 +54,33 @@ def test_binding_has_no_oracle_import():
             if f.endswith((".py", ".cpp", ".hip", ".h")):
                 src = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in src.lower(), f
+
+
+def test_setup_host_contract_checks_arguments_on_the_host():
+    """dpcg_setup takes device arrays, dpcg_setup_host host arrays (both documented in
+    include/dpcg.h); the host variant reads k_rowptr[n] and z_rowptr[n] on the host and
+    rejects malformed row pointers before any device work."""
+    import ctypes as C
+
+    import numpy as np
+
+    from paper_2111_09294_amd import _binding as B
+    text = open(HEADER).read()
+    assert "dpcg_setup_host" in text and "HOST memory" in text
+    assert "device arrays here (dpcg_setup_host takes host arrays)" in text
+    L = B.lib()
+    h = C.c_void_p()
+    info = B.Info()
+    kp = np.array([1, 2, 3, 4], np.int64)            # does not start at 0
+    kc = np.zeros(4, np.int32)
+    kv = np.ones(4)
+    bp = np.array([0, 3], np.int32)
+    ptr = lambda a: a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    st = L.dpcg_setup_host(C.byref(h), 3, ptr(kp), ptr(kc), ptr(kv), 0, None, None, None, 1, ptr(bp), None,
+                           C.byref(info))
+    assert st == B.EINVAL and not h.value and info.status == B.EINVAL
+    st = L.dpcg_setup_host(C.byref(h), 0, ptr(kp), ptr(kc), ptr(kv), 0, None, None, None, 1, ptr(bp), None, None)
+    assert st == B.EINVAL
+    kp0 = np.array([0, 1, 2, 3], np.int64)
+    st = L.dpcg_setup_host(C.byref(h), 3, ptr(kp0), ptr(kc), ptr(kv), 2, None, None, None, 1, ptr(bp), None, None)
+    assert st == B.EINVAL                             # k > 0 without Z
