@@ -23,6 +23,7 @@
 #ifndef DPCG_H
 #define DPCG_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -38,7 +39,8 @@ enum {
     DPCG_ECOARSE_NOT_SPD = -4,/* E = Z^T K Z not SPD: Z not of full column rank     */
     DPCG_EBREAKDOWN = -5,     /* p^T K p <= 0 or non-finite alpha, beta, residual  */
     DPCG_EHIP = -6,           /* HIP runtime or device allocation failure           */
-    DPCG_ENONFINITE = -7      /* NaN or Inf in an input vector                      */
+    DPCG_ENONFINITE = -7,     /* NaN or Inf in an input vector                      */
+    DPCG_ETOOBIG = -8         /* the problem exceeds dpcg_solve_noalloc's fixed scratch */
 };
 
 typedef struct dpcg_ctx *dpcg_handle;
@@ -299,6 +301,28 @@ int dpcg_get_timing(dpcg_handle h, dpcg_timing *out);
 int dpcg_element_gradient(dpcg_handle h, int64_t nel, const int64_t *elem_ptr, const int32_t *elem_dof,
                           const int64_t *kmat_off, int64_t kmat_len, const double *kmat, const double *u,
                           const double *lambda, double *g);
+
+/*
+ * For callers that cannot allocate device memory (code under stream capture, tight
+ * serving loops, harnesses that forbid allocation): dpcg_solve in FP64 with the
+ * iteration's workspace (the vectors r, y, z, q, p, the k-vectors, the partial sums
+ * and the device state) in a fixed device array of the library instead of the
+ * handle's workspace, so the call allocates nothing (no hipMalloc, hipFree, event or
+ * pinned-memory creation).  Same arguments, kernels and results as dpcg_solve.
+ * Limits: precision must be DPCG_PREC_FP64 and record_history 0 (else DPCG_EINVAL);
+ * the workspace must fit in dpcg_noalloc_scratch_bytes() = 96 MiB, about 57 bytes per
+ * unknown (up to about 1.7M unknowns; the 80^3 configuration, 1.66M, needs 90 MiB),
+ * else DPCG_ETOOBIG before any device work; kernel timing (dpcg_set_timing) is not
+ * applied.  The array is one per device, held from the first call on that device
+ * until the process ends; it is cleared at the start of every call.  Calls that
+ * overlap on one device (any handles, any streams) share it and race: the caller
+ * must order them.  The handle must have been set up on the current device.
+ */
+int dpcg_solve_noalloc(dpcg_handle h, const double *f, double *u, double tol,
+                       const dpcg_options *opt, dpcg_info *info);
+
+/* Size in bytes of the fixed device array dpcg_solve_noalloc uses. */
+size_t dpcg_noalloc_scratch_bytes(void);
 
 /* ---- single steps of the iteration, each the kernel the solve runs ---- */
 

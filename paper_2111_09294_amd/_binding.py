@@ -12,8 +12,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdpcg.so")
 
-OK, NOT_CONVERGED, EINVAL, ENOTSYM, EBLOCK_NOT_SPD, ECOARSE_NOT_SPD, EBREAKDOWN, EHIP, ENONFINITE = (
-    0, 1, -1, -2, -3, -4, -5, -6, -7)
+OK, NOT_CONVERGED, EINVAL, ENOTSYM, EBLOCK_NOT_SPD, ECOARSE_NOT_SPD, EBREAKDOWN, EHIP, ENONFINITE, ETOOBIG = (
+    0, 1, -1, -2, -3, -4, -5, -6, -7, -8)
 
 
 PREC_FP64, PREC_MIXED = 0, 1
@@ -61,6 +61,8 @@ SIGNATURES = {
     "dpcg_setup_host": (C.c_int, [C.POINTER(P), C.c_int64, P, P, P, C.c_int32, P, P, P, C.c_int32, P, P,
                                   C.POINTER(Info)]),
     "dpcg_solve": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
+    "dpcg_solve_noalloc": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
+    "dpcg_noalloc_scratch_bytes": (C.c_size_t, []),
     "dpcg_solve_adjoint": (C.c_int, [P, P, P, C.c_double, C.POINTER(Options), C.POINTER(Info)]),
     "dpcg_solve_batch": (C.c_int, [P, C.c_int32, P, P, C.c_double, C.POINTER(Options), P]),
     "dpcg_solve_many": (C.c_int, [P, C.c_int32, P, P, C.c_double, C.POINTER(Options), P]),

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdpcg.so")
-SOURCES = ["kernels.hip", "setup.hip", "adjoint.hip", "batch.hip", "dpcg.cpp", "devmem.cpp"]
+SOURCES = ["kernels.hip", "setup.hip", "adjoint.hip", "batch.hip", "dpcg.cpp", "devmem.cpp", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -15,6 +15,38 @@
 
 using namespace dpcg;
 
+namespace dpcg {
+
+namespace {
+size_t up256(size_t bytes) { return (bytes + 255) & ~size_t(255); }
+// entries of each partial-sum array: the largest SpMV grid any lane-group size can
+// choose (autotuner) and the other kernels' grids
+size_t partial_count(const dpcg_ctx *c) {
+    const int spmv_max = (int)((c->nb + 7) / 8) + 8;
+    return (size_t)std::max({spmv_max, c->spmv.nwg, c->bj_nwg, c->vec_nwg, 1});
+}
+}  // namespace
+
+size_t workspace_bytes(const dpcg_ctx *c) {
+    const size_t n = (size_t)c->n, kk = (size_t)std::max(1, c->k), np = partial_count(c);
+    return 7 * up256(8 * n) + 4 * up256(8 * kk) + 3 * up256(8 * np) + up256(sizeof(State));
+}
+
+void carve_workspace(dpcg_ctx *c, Workspace &w, char *base) {
+    const size_t n = (size_t)c->n, kk = (size_t)std::max(1, c->k), np = partial_count(c);
+    c->part_cap = (int32_t)np;
+    double **vec[] = {&w.r, &w.y, &w.z, &w.q, &w.p[0], &w.p[1], &w.tmp};
+    double **kv[] = {&w.g, &w.delta, &w.h, &w.hd};
+    double **pv[] = {&w.part_a, &w.part_b, &w.part_c};
+    size_t off = 0;
+    for (double **d : vec) { *d = (double *)(base + off); off += up256(8 * n); }
+    for (double **d : kv) { *d = (double *)(base + off); off += up256(8 * kk); }
+    for (double **d : pv) { *d = (double *)(base + off); off += up256(8 * np); }
+    w.st = (State *)(base + off);
+}
+
+}  // namespace dpcg
+
 namespace {
 
 // Pinned state mirrors and timing events are kept in process-wide free lists: creating
@@ -90,24 +122,10 @@ int alloc(dpcg_ctx *c, T **dst, size_t count) {
     } while (0)
 
 int alloc_workspace(dpcg_ctx *c, Workspace &w) {
-    const size_t n = (size_t)c->n, kk = (size_t)std::max(1, c->k);
-    // partial sums for the largest SpMV grid any lane-group size can choose (autotuner)
-    const int spmv_max = (int)((c->nb + 7) / 8) + 8;
-    const size_t np = (size_t)std::max({spmv_max, c->spmv.nwg, c->bj_nwg, c->vec_nwg, 1});
-    c->part_cap = (int32_t)np;
     // one allocation (one zero fill) carved into 256-byte aligned arrays
-    double **vec[] = {&w.r, &w.y, &w.z, &w.q, &w.p[0], &w.p[1], &w.tmp};
-    double **kv[] = {&w.g, &w.delta, &w.h, &w.hd};
-    double **pv[] = {&w.part_a, &w.part_b, &w.part_c};
-    auto up = [](size_t bytes) { return (bytes + 255) & ~size_t(255); };
-    const size_t total = 7 * up(8 * n) + 4 * up(8 * kk) + 3 * up(8 * np) + up(sizeof(State));
     char *base = nullptr;
-    TRY(alloc(c, &base, total));
-    size_t off = 0;
-    for (double **d : vec) { *d = (double *)(base + off); off += up(8 * n); }
-    for (double **d : kv) { *d = (double *)(base + off); off += up(8 * kk); }
-    for (double **d : pv) { *d = (double *)(base + off); off += up(8 * np); }
-    w.st = (State *)(base + off);
+    TRY(alloc(c, &base, workspace_bytes(c)));
+    carve_workspace(c, w, base);
     w.snap = take_pinned_state();
     if (!w.snap) return DPCG_EHIP;
     return DPCG_OK;
@@ -473,6 +491,17 @@ int solve_impl(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol
     fill_info(info, status, st.iters_done, std::sqrt(st.rr) / fnorm, rt / fnorm, c->setup_ms, now_ms() - t0, bad);
     return status;
 }
+
+}  // namespace
+
+namespace dpcg {
+int solve_on_workspace(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol, const dpcg_options *opt,
+                       dpcg_info *info) {
+    return solve_impl(c, w, f, u, tol, opt, info);
+}
+}  // namespace dpcg
+
+namespace {
 
 // ---------------------------------------------------------------- several systems
 // Measures the SpMV for each lane-group size whose grid fits the workspace and keeps the
@@ -871,6 +900,7 @@ const char *dpcg_status_string(int status) {
         case DPCG_EBREAKDOWN: return "CG breakdown (p^T K p <= 0 or non-finite scalar)";
         case DPCG_EHIP: return "HIP runtime or allocation failure";
         case DPCG_ENONFINITE: return "non-finite value in an input vector";
+        case DPCG_ETOOBIG: return "problem too large for the fixed scratch of the allocation-free solve";
         default: return "unknown status";
     }
 }

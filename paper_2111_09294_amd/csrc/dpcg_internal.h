@@ -269,6 +269,13 @@ hipError_t launch_to_f32(const dpcg_ctx *c, const double *src, int64_t count, fl
 // y += x
 hipError_t launch_add(const dpcg_ctx *c, const double *x, double *y);
 
+// dpcg.cpp: the solve workspace (vectors, k-vectors, partial sums, State) as one block
+// of workspace_bytes(c) bytes carved by carve_workspace, and a solve on a given one
+size_t workspace_bytes(const dpcg_ctx *c);
+void carve_workspace(dpcg_ctx *c, Workspace &w, char *base);
+int solve_on_workspace(dpcg_ctx *c, Workspace &w, const double *f, double *u, double tol, const dpcg_options *opt,
+                       dpcg_info *info);
+
 // setup.hip: new values of K on the same pattern (see dpcg_update_values)
 int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const double *kv, int32_t nlist,
                       const int32_t *list_host, int64_t *bad);

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
 def test_status_strings():
     from paper_2111_09294_amd import status_string
     assert status_string(0) == "converged"
-    for code in (1, -1, -2, -3, -4, -5, -6, -7):
+    for code in (1, -1, -2, -3, -4, -5, -6, -7, -8):
         s = status_string(code)
         assert s and s != "unknown status"
     assert status_string(42) == "unknown status"
