@@ -29,19 +29,26 @@ size_t partial_count(const dpcg_ctx *c) {
 
 size_t workspace_bytes(const dpcg_ctx *c) {
     const size_t n = (size_t)c->n, kk = (size_t)std::max(1, c->k), np = partial_count(c);
-    return 7 * up256(8 * n) + 4 * up256(8 * kk) + 3 * up256(8 * np) + up256(sizeof(State));
+    const size_t nt = (size_t)std::max(1, c->coarse_nt);
+    return 7 * up256(8 * n) + 3 * up256(8 * kk) + 3 * up256(8 * np) + up256(8 * nt * nt * kCoarseTile) +
+           up256(8 * nt) + up256(sizeof(State));
 }
 
 void carve_workspace(dpcg_ctx *c, Workspace &w, char *base) {
     const size_t n = (size_t)c->n, kk = (size_t)std::max(1, c->k), np = partial_count(c);
     c->part_cap = (int32_t)np;
     double **vec[] = {&w.r, &w.y, &w.z, &w.q, &w.p[0], &w.p[1], &w.tmp};
-    double **kv[] = {&w.g, &w.delta, &w.h, &w.hd};
+    double **kv[] = {&w.g, &w.delta, &w.h};
     double **pv[] = {&w.part_a, &w.part_b, &w.part_c};
     size_t off = 0;
     for (double **d : vec) { *d = (double *)(base + off); off += up256(8 * n); }
     for (double **d : kv) { *d = (double *)(base + off); off += up256(8 * kk); }
     for (double **d : pv) { *d = (double *)(base + off); off += up256(8 * np); }
+    const size_t nt = (size_t)std::max(1, c->coarse_nt);
+    w.cpart = (double *)(base + off);
+    off += up256(8 * nt * nt * kCoarseTile);
+    w.hdp = (double *)(base + off);
+    off += up256(8 * nt);
     w.st = (State *)(base + off);
 }
 
@@ -160,6 +167,7 @@ void choose_shapes(dpcg_ctx *c) {
     c->spmv.nwg = c->spmv.steps;  // one row step per workgroup (more per workgroup measured slower)
     if (c->spmv.nwg >= 8) c->spmv.nwg = (c->spmv.nwg + 7) & ~7;
     c->vec_nwg = round_grid((int)std::min<int64_t>((c->n + kThreads - 1) / kThreads, 1024));
+    c->prolong_nwg = round_grid((int)std::min<int64_t>((c->n + kThreads - 1) / kThreads, 16384));
     c->bj_nwg = round_grid(std::min(c->bj_ntiles, 65536));  // one tile each (partials reduced by one workgroup)
 }
 
@@ -234,7 +242,7 @@ int enqueue_start(dpcg_ctx *c, Workspace &w, const double *f, double *u, bool gu
     const double *um1 = guess ? u : nullptr;
     if (c->k > 0) {
         LAUNCH(launch_restrict(c, f, um1, w.g, nullptr, 0, 0, 0, 0, 0));
-        LAUNCH(launch_coarse(c, w.g, w.delta, nullptr));
+        LAUNCH(launch_coarse(c, w.g, w.delta, nullptr, w.cpart));
         LAUNCH(launch_prolong(c, um1, w.delta, u, nullptr, nullptr, 0));
     } else if (!guess) {
         HIP_TRY(hipMemsetAsync(u, 0, sizeof(double) * c->n, c->stream));
@@ -242,7 +250,7 @@ int enqueue_start(dpcg_ctx *c, Workspace &w, const double *f, double *u, bool gu
     LAUNCH(launch_spmv_residual(c, u, f, w.r, w.part_b, w, 1));
     LAUNCH(launch_bj(c, w.r, w.y, &w));
     LAUNCH(launch_restrict(c, w.r, w.y, w.g, &w, 1, c->spmv.nwg, 0, max_iter, record));
-    LAUNCH(launch_coarse(c, w.g, w.delta, &w));
+    LAUNCH(launch_coarse(c, w.g, w.delta, w.st, w.cpart));
     LAUNCH(launch_prolong(c, w.y, w.delta, w.z, &w, w.r, 0));
     LAUNCH(launch_beta(c, w));
     return DPCG_OK;
@@ -289,13 +297,13 @@ int enqueue_iteration(dpcg_ctx *c, Workspace &w, double *u, int max_iter, int re
         // rho = r^T z without z: the prolongation forms beta and p itself
         LAUNCH(launch_update_bj(c, u, w, true));
         LAUNCH(launch_restrict(c, w.r, w.y, w.g, &w, 1, c->bj_nwg, 1, max_iter, record, true));
-        LAUNCH(launch_coarse(c, w.g, w.delta, &w, true));
+        LAUNCH(launch_coarse(c, w.g, w.delta, w.st, w.cpart, w.h, w.hdp));
         LAUNCH(launch_prolong_p(c, w));
         return DPCG_OK;
     }
     LAUNCH(launch_update_bj(c, u, w));
     LAUNCH(launch_restrict(c, w.r, w.y, w.g, &w, 1, c->bj_nwg, 1, max_iter, record));
-    LAUNCH(launch_coarse(c, w.g, w.delta, &w));
+    LAUNCH(launch_coarse(c, w.g, w.delta, w.st, w.cpart));
     LAUNCH(launch_prolong(c, w.y, w.delta, w.z, &w, w.r, 1));
     LAUNCH(launch_beta(c, w));
     return DPCG_OK;
@@ -605,7 +613,7 @@ int solve_many_impl(dpcg_handle *hs, int32_t count, const double *const *F, doub
     std::vector<MsSys> sys(count);
     MsTable tab{};
     tab.nsys = count;
-    int tot[kMsPhases] = {0, 0, 0, 0, 0, 0};
+    int tot[kMsPhases] = {};
     for (int i = 0; i < count; ++i) {
         dpcg_ctx *c = hs[i];
         Workspace &w = c->ws[0];
@@ -654,9 +662,14 @@ int solve_many_impl(dpcg_handle *hs, int32_t count, const double *const *F, doub
         d.part_b = w.part_b;
         d.part_c = w.part_c;
         d.h = w.h;
-        d.hd = w.hd;
+        d.einv_tiles = c->einv_tiles;
+        d.coarse_nt = c->coarse_nt;
+        d.pad2 = 0;
+        d.cpart = w.cpart;
+        d.hdp = w.hdp;
         d.st = w.st;
-        const int n_ph[kMsPhases] = {round8(c->spmv.nwg), 1, round8(c->bj_nwg), std::max(1, c->k), c->k,
+        const int n_ph[kMsPhases] = {round8(c->spmv.nwg), 1, round8(c->bj_nwg), std::max(1, c->k),
+                                     c->k > 0 ? (int)coarse_tile_count(c->coarse_nt) : 0, c->coarse_nt,
                                      round8(c->vec_nwg)};
         for (int ph = 0; ph < kMsPhases; ++ph) {
             tab.off[ph][i] = tot[ph];
@@ -687,11 +700,13 @@ int solve_many_impl(dpcg_handle *hs, int32_t count, const double *const *F, doub
     // Algorithm 2 and the first preconditioned residual, every system at once
     LAUNCH(launch_ms_restrict(S, T, Y, tot[kMsRestrict], 0, 0, 0, 0));
     LAUNCH(launch_ms_coarse(S, T, Y, tot[kMsCoarse], 0));
+    LAUNCH(launch_ms_coarse_sum(S, T, Y, tot[kMsCoarseSum], 0));
     LAUNCH(launch_ms_prolong(S, T, Y, tot[kMsVec], 0, 0));
     LAUNCH(launch_ms_spmv_res(S, T, Y, tot[kMsSpmv]));
     LAUNCH(launch_ms_bj(S, T, Y, tot[kMsBj]));
     LAUNCH(launch_ms_restrict(S, T, Y, tot[kMsRestrict], 1, 1, 0, max_iter));
     LAUNCH(launch_ms_coarse(S, T, Y, tot[kMsCoarse], 1));
+    LAUNCH(launch_ms_coarse_sum(S, T, Y, tot[kMsCoarseSum], 1));
     LAUNCH(launch_ms_prolong(S, T, Y, tot[kMsVec], 1, 0));
     LAUNCH(launch_ms_beta(S, T, Y, tot[kMsVec]));
     auto read_all = [&]() -> int {
@@ -716,6 +731,7 @@ int solve_many_impl(dpcg_handle *hs, int32_t count, const double *const *F, doub
             LAUNCH(launch_ms_update_bj(S, T, Y, tot[kMsBj]));
             LAUNCH(launch_ms_restrict(S, T, Y, tot[kMsRestrict], 1, 1, 1, max_iter));
             LAUNCH(launch_ms_coarse(S, T, Y, tot[kMsCoarse], 2));
+            LAUNCH(launch_ms_coarse_sum(S, T, Y, tot[kMsCoarseSum], 2));
             LAUNCH(launch_ms_prolong(S, T, Y, tot[kMsVec], 2, 0));
         }
         enq += m;
@@ -1001,7 +1017,7 @@ int dpcg_restrict(dpcg_handle h, const double *a, const double *b, double *g) {
 int dpcg_coarse_apply(dpcg_handle h, const double *g, double *delta) {
     if (!h || !g || !delta) return DPCG_EINVAL;
     if (h->k == 0) return DPCG_OK;
-    SYNC_RET(launch_coarse(h, g, delta, nullptr));
+    SYNC_RET(launch_coarse(h, g, delta, nullptr, h->ws[0].cpart));
 }
 
 int dpcg_prolong(dpcg_handle h, const double *base, const double *delta, double *out) {
@@ -1019,7 +1035,7 @@ int dpcg_precond(dpcg_handle h, const double *r, double *z) {
         return hipStreamSynchronize(h->stream) == hipSuccess ? DPCG_OK : DPCG_EHIP;
     }
     if (launch_restrict(h, r, w.y, w.g, nullptr, 0, 0, 0, 0, 0) != hipSuccess) return DPCG_EHIP;
-    if (launch_coarse(h, w.g, w.delta, nullptr) != hipSuccess) return DPCG_EHIP;
+    if (launch_coarse(h, w.g, w.delta, nullptr, w.cpart) != hipSuccess) return DPCG_EHIP;
     SYNC_RET(launch_prolong(h, w.y, w.delta, z, nullptr, nullptr, 0));
 }
 

@@ -32,6 +32,10 @@ constexpr int kMaxBlock = 18;     // largest block-Jacobi block of the fused (no
 constexpr int kMaxDense = 8192;   // largest block-Jacobi block (dense path above kMaxBlock)
 constexpr int kDenseRows = 32;    // rows of a dense block per workgroup of its apply
 constexpr int kMaxElemDofs = 256; // largest element (DoFs) of dpcg_element_gradient
+constexpr int kCoarseTile = 64;   // E^-1 kept as the lower-triangle tiles of this size
+
+// tile (I, J), I >= J, of the lower triangle of a matrix of nt x nt tiles: index I (I + 1) / 2 + J
+__host__ __device__ inline int64_t coarse_tile_count(int32_t nt) { return (int64_t)nt * (nt + 1) / 2; }
 constexpr int kBatchCols = 32;    // columns of the multi-RHS workspace (right-hand sides per batch)
 constexpr int kBatchSegEntries = 2048;  // entries per multi-RHS restriction segment
 constexpr int kBatchTileWindow = 47;                         // block starts per multi-RHS tile
@@ -70,7 +74,10 @@ enum : int32_t { kRunning = 0, kConverged = 1, kMaxIter = 2, kBreakdown = 3 };
 struct Workspace {
     double *r = nullptr, *y = nullptr, *z = nullptr, *q = nullptr, *p[2] = {nullptr, nullptr};
     double *g = nullptr, *delta = nullptr, *tmp = nullptr;
-    double *h = nullptr, *hd = nullptr;  // Z^T r and h_j delta_j for the fused prolongation
+    double *h = nullptr;        // Z^T r for the fused prolongation
+    double *cpart = nullptr;    // coarse product: contribution of tile pair (X, Y) to delta_X,
+                                // nt x nt x kCoarseTile
+    double *hdp = nullptr;      // per tile row X of delta: sum of h_j delta_j over its entries
     double *part_a = nullptr;   // partial sums (p^T q, r^T r, r^T z); sized max grid
     double *part_b = nullptr;
     double *part_c = nullptr;
@@ -139,7 +146,7 @@ struct DenseChunk {
 // workspace and its state) and, per phase, the prefix offsets of the systems'
 // workgroups in the launch grid.
 constexpr int kMaxSystems = 64;
-enum MsPhase { kMsSpmv = 0, kMsAlpha, kMsBj, kMsRestrict, kMsCoarse, kMsVec, kMsPhases };
+enum MsPhase { kMsSpmv = 0, kMsAlpha, kMsBj, kMsRestrict, kMsCoarse, kMsCoarseSum, kMsVec, kMsPhases };
 
 struct MsSys {
     int32_t nb, steps, spmv_nwg, group;
@@ -158,7 +165,10 @@ struct MsSys {
     const int32_t *z_ptr, *z_col;
     const double *z_val;
     const double *f;
-    double *u, *r, *y, *z, *q, *p0, *p1, *g, *delta, *part_a, *part_b, *part_c, *h, *hd;
+    double *u, *r, *y, *z, *q, *p0, *p1, *g, *delta, *part_a, *part_b, *part_c, *h;
+    const double *einv_tiles;   // the coarse product's packed E^-1 and its workspace
+    int32_t coarse_nt, pad2;
+    double *cpart, *hdp;
     State *st;
 };
 
@@ -213,6 +223,10 @@ struct dpcg_ctx {
     double *kzt_val = nullptr;
     double *einv = nullptr;
     int64_t einv_ld = 0;       // leading dimension of E^-1 (k rounded up to 32)
+    double *einv_tiles = nullptr;  // the lower triangle of E^-1 as kCoarseTile^2 row-major tiles,
+                                   // zero beyond k (symmetric diagonal tiles stored whole)
+    int32_t coarse_nt = 0;         // tiles per side: ceil(k / kCoarseTile)
+    int32_t prolong_nwg = 0;       // grid of the fused prolongation (one DoF per thread)
     // launch shapes
     dpcg::SpmvPlan spmv;
     int32_t vec_nwg = 0;       // grid of the elementwise kernels (one DoF per thread)
@@ -245,7 +259,10 @@ hipError_t launch_bj(const dpcg_ctx *c, const double *r, double *y, Workspace *w
 hipError_t launch_bj_dense(const dpcg_ctx *c, const double *r, double *y, const State *st);
 hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, double *g, Workspace *w,
                            int check, int n_parts, int iter_offset, int max_iter, int record, bool fused = false);
-hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Workspace *w, bool fused = false);
+// delta = E^-1 g on the packed tiles (cpart: the pair contributions, nt^2 T); with h
+// given also the tile-row sums hdp of h_j delta_j; st may be null (no state check)
+hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, const State *st, double *cpart,
+                         const double *h = nullptr, double *hdp = nullptr);
 // z = y + Z delta, rho = r^T y + h^T delta, beta and p in one kernel (after the fused
 // update, restriction and coarse product)
 hipError_t launch_prolong_p(const dpcg_ctx *c, Workspace &w);
@@ -262,6 +279,7 @@ hipError_t launch_ms_bj(hipStream_t s, const MsTable *tab, const MsSys *sys, int
 hipError_t launch_ms_restrict(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int mode, int check,
                               int iter_offset, int max_iter);
 hipError_t launch_ms_coarse(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int with_state);
+hipError_t launch_ms_coarse_sum(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int with_state);
 hipError_t launch_ms_prolong(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int mode, int advance);
 hipError_t launch_ms_beta(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid);
 // dst[i] = (float) src[i]

@@ -59,11 +59,33 @@ __device__ __forceinline__ double block_sum_n(double v, double *lds) {
     return s;
 }
 
+// This thread's fixed-order share of sum_i parts[i] for a block of NT threads: U
+// independent accumulators (entries t + NT (U j + u)), their loads issued together, then
+// the tail and a fixed tree over the accumulators.
+template <int NT, int U>
+__device__ __forceinline__ double strided_share(const double *__restrict__ parts, int n) {
+    double a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) a[u] = 0.0;
+    int i = threadIdx.x;
+    for (; i + (U - 1) * NT < n; i += U * NT) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = parts[i + u * NT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) a[u] += v[u];
+    }
+    for (; i < n; i += NT) a[0] += parts[i];
+#pragma unroll
+    for (int w = 1; w < U; w <<= 1)
+#pragma unroll
+        for (int u = 0; u + w < U; u += 2 * w) a[u] += a[u + w];
+    return a[0];
+}
+
 template <int NW>
 __device__ __forceinline__ double reduce_parts_n(const double *parts, int n, double *lds) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += NW * 64) s += parts[i];
-    return block_sum_n<NW>(s, lds);
+    return block_sum_n<NW>(strided_share<NW * 64, 16>(parts, n), lds);
 }
 
 __device__ __forceinline__ bool leader() { return blockIdx.x == 0 && threadIdx.x == 0; }
@@ -572,11 +594,8 @@ __device__ __forceinline__ void k_restrict_body(int vb, int vg,
     if (st) {
         if (wg_flag(st) != kRunning) return;
         if (vb == 0 && n_rr > 0) {
-            double rr = 0.0, ry = 0.0;
-            for (int i = threadIdx.x; i < n_rr; i += kRestrictThreads) {
-                rr += part_rr[i];
-                if (part_ry) ry += part_ry[i];
-            }
+            double rr = strided_share<kRestrictThreads, 8>(part_rr, n_rr);
+            double ry = part_ry ? strided_share<kRestrictThreads, 8>(part_ry, n_rr) : 0.0;
             block_sum2_n<kRestrictWaves>(rr, ry, lds);
             if (threadIdx.x == 0) {
                 const int done = st->iter + iter_offset;
@@ -601,7 +620,7 @@ __device__ __forceinline__ void k_restrict_body(int vb, int vg,
         }
     }
     constexpr int T = kRestrictThreads;
-    for (int j = vb; j < k; j += vg) {
+    for (int j = xcd_remap(vb, vg); j < k; j += vg) {
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;  // Z^T a
         double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;  // -(K Z)^T b
         {
@@ -647,38 +666,113 @@ __global__ __launch_bounds__(kRestrictThreads) void k_restrict(
 }
 
 
-// delta = E^{-1} g: one workgroup per row of the dense symmetric inverse; with h given,
-// also the products hd_j = h_j delta_j.
-__device__ __forceinline__ void k_coarse_body(int vb, int32_t k, int64_t ld, const double *__restrict__ einv,
-                                                     const double *__restrict__ g, double *__restrict__ delta,
-                                                     const State *st, const double *__restrict__ h,
-                                                     double *__restrict__ hd) {
-    __shared__ double lds[4];
+// The coarse product delta = E^-1 g on the stored lower triangle of the symmetric E^-1
+// (kCoarseTile^2 tiles, tile row X = entries X T .. X T + T - 1), in two launches.
+// Stage 1, one workgroup per stored tile (I, J): the tile's rows against g_J are the
+// contribution of the tile pair (I, J) to delta_I, and for I > J its columns against
+// g_I are the contribution of the mirrored tile (J, I) to delta_J; each goes to
+// cpart[(X nt + Y) T ..] for its pair (X, Y).  Every stored value is read once.
+// Stage 2, one workgroup per tile row X: delta_X = sum over Y = 0..nt-1 of the pair
+// contributions in that order; with h given, also hdp[X] = sum of h_j delta_j over the
+// row's entries (the fused prolongation forms rho = r^T y + h^T delta from them).
+__device__ __forceinline__ void k_coarse_tiles_body(int vb, int32_t k, int32_t nt, const double *__restrict__ tiles,
+                                                    const double *__restrict__ g, double *__restrict__ cpart,
+                                                    const State *st) {
+    constexpr int T = kCoarseTile;
+    __shared__ double gi[T], gj[T];
+    __shared__ double X[T][T + 1];
+    __shared__ double part[2][4][T];
     if (st && st->flag != kRunning) return;
-    const int row = vb;
-    if (row >= k) return;
-    const double *e = einv + (int64_t)row * ld;
-    double s0 = 0.0, s1 = 0.0;
-    int l = threadIdx.x;
-    for (; l + kThreads < k; l += 2 * kThreads) {
-        s0 = fma(e[l], g[l], s0);
-        s1 = fma(e[l + kThreads], g[l + kThreads], s1);
+    const int64_t tid = vb;
+    int I = (int)((sqrt(8.0 * (double)tid + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(I + 1) * (I + 2) / 2 <= tid) ++I;
+    while ((int64_t)I * (I + 1) / 2 > tid) --I;
+    const int J = (int)(tid - (int64_t)I * (I + 1) / 2);
+    const double *__restrict__ A = tiles + tid * T * T;
+    const int t = threadIdx.x, b = t & 63, rq = t >> 6;
+    // the thread's column strip: rows 16 rq .. 16 rq + 15 of column b (each load
+    // instruction of a wave reads one whole 512-byte tile row)
+    double v[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a) v[a] = A[(16 * rq + a) * T + b];
+    if (t < T) {
+        gj[t] = J * T + t < k ? g[J * T + t] : 0.0;
+        gi[t] = I * T + t < k ? g[I * T + t] : 0.0;
     }
-    for (; l < k; l += kThreads) s0 = fma(e[l], g[l], s0);
-    const double s = block_sum(s0 + s1, lds);
-    if (threadIdx.x == 0) {
-        delta[row] = s;
-        if (hd) hd[row] = h[row] * s;
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 16; ++a) X[16 * rq + a][b] = v[a] * gj[b];
+    if (I != J) {
+        double cs = 0.0;
+#pragma unroll
+        for (int a = 0; a < 16; ++a) cs = fma(v[a], gi[16 * rq + a], cs);
+        part[1][rq][b] = cs;
+    }
+    __syncthreads();
+    // row a = b of the tile, quarter rq of its columns
+    {
+        double rs = 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) rs += X[b][16 * rq + i];
+        part[0][rq][b] = rs;
+    }
+    __syncthreads();
+    if (t < T) {
+        cpart[((int64_t)I * nt + J) * T + t] = (part[0][0][t] + part[0][1][t]) + (part[0][2][t] + part[0][3][t]);
+        if (I != J)
+            cpart[((int64_t)J * nt + I) * T + t] =
+                (part[1][0][t] + part[1][1][t]) + (part[1][2][t] + part[1][3][t]);
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_coarse(int32_t k, int64_t ld, const double *__restrict__ einv,
-                                                     const double *__restrict__ g, double *__restrict__ delta,
-                                                     const State *st, const double *__restrict__ h,
-                                                     double *__restrict__ hd) {
-    k_coarse_body(blockIdx.x, k, ld, einv, g, delta, st, h, hd);
+__device__ __forceinline__ void k_coarse_sum_body(int vb, int32_t k, int32_t nt, const double *__restrict__ cpart,
+                                                  double *__restrict__ delta, const double *__restrict__ h,
+                                                  double *__restrict__ hdp, const State *st) {
+    constexpr int T = kCoarseTile;
+    __shared__ double ps[4][T];
+    if (st && st->flag != kRunning) return;
+    const int Xr = vb;
+    const int a = threadIdx.x & 63, yq = threadIdx.x >> 6;
+    const int y0 = (nt * yq) / 4, y1 = (nt * (yq + 1)) / 4;
+    const double *__restrict__ src = cpart + (int64_t)Xr * nt * T + a;
+    double s = 0.0;
+    int y = y0;
+    for (; y + 5 < y1; y += 6) {  // six loads in flight, added in order
+        double v[6];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) v[u] = src[(int64_t)(y + u) * T];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) s += v[u];
+    }
+    for (; y < y1; ++y) s += src[(int64_t)y * T];
+    ps[yq][a] = s;
+    __syncthreads();
+    if (threadIdx.x < T) {  // wave 0
+        const double dv = (ps[0][a] + ps[1][a]) + (ps[2][a] + ps[3][a]);
+        const int row = Xr * T + a;
+        double hv = 0.0;
+        if (row < k) {
+            delta[row] = dv;
+            if (h) hv = h[row] * dv;
+        }
+        if (h) {
+            hv = wave_sum(hv);
+            if (a == 0) hdp[Xr] = hv;
+        }
+    }
 }
 
+__global__ __launch_bounds__(256) void k_coarse_tiles(int32_t k, int32_t nt, const double *__restrict__ tiles,
+                                                      const double *__restrict__ g, double *__restrict__ cpart,
+                                                      const State *st) {
+    k_coarse_tiles_body(blockIdx.x, k, nt, tiles, g, cpart, st);
+}
+
+__global__ __launch_bounds__(256) void k_coarse_sum(int32_t k, int32_t nt, const double *__restrict__ cpart,
+                                                    double *__restrict__ delta, const double *__restrict__ h,
+                                                    double *__restrict__ hdp, const State *st) {
+    k_coarse_sum_body(blockIdx.x, k, nt, cpart, delta, h, hdp, st);
+}
 
 // out = base + Z delta; optional partials of rdot^T out; optionally advance the iteration.
 __device__ __forceinline__ void k_prolong_body(int vb, int64_t n, int32_t nwg, const int32_t *__restrict__ z_ptr,
@@ -721,16 +815,17 @@ __global__ __launch_bounds__(kThreads) void k_prolong(int64_t n, int32_t nwg, co
 
 // The prolongation of Algorithm 3 fused with beta and the new search direction of
 // Algorithm 1.  With h = Z^T r from the restriction, r^T z = r^T y + h^T delta exactly, so
-// rho_i is r^T y (summed by the restriction) plus the fixed-order sum of the products
-// hd_j = h_j delta_j of the coarse kernel: every workgroup forms the same bits of rho_i
+// rho_i is r^T y (summed by the restriction) plus the fixed-order sum of the k entries
+// (several systems per launch) or tile-row sums (single system) of h_j delta_j left by
+// the coarse product: every workgroup forms the same bits of rho_i
 // and of beta_{i-1} = rho_i / rho_{i-1} and writes p_i = y + Z delta + beta_{i-1} p_{i-1}
 // into buffer i & 1 directly (z itself is never stored).  The restriction has already
 // advanced the iteration.  Workgroup 0 stores rho_i in slot i & 1 and tests it.
 __device__ __forceinline__ void k_prolong_p_body(int vb, int64_t n, int32_t nwg, const int32_t *__restrict__ z_ptr,
                                                  const int32_t *__restrict__ z_col, const double *__restrict__ z_val,
                                                  const double *__restrict__ delta, const double *__restrict__ y,
-                                                 const double *__restrict__ hd, int32_t k, double *p0, double *p1,
-                                                 State *st) {
+                                                 const double *__restrict__ hparts, int32_t nhp, double *p0,
+                                                 double *p1, State *st) {
     __shared__ double lds[4];
     if (wg_flag(st) != kRunning) return;
     const int it = st->iter;
@@ -748,19 +843,7 @@ __device__ __forceinline__ void k_prolong_p_body(int vb, int64_t n, int32_t nwg,
         v = y[d] + c;
         pold = pp[d];
     }
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    {
-        constexpr int T = kThreads;
-        int j = threadIdx.x;
-        for (; j + 3 * T < k; j += 4 * T) {
-            s0 += hd[j];
-            s1 += hd[j + T];
-            s2 += hd[j + 2 * T];
-            s3 += hd[j + 3 * T];
-        }
-        for (; j < k; j += T) s0 += hd[j];
-    }
-    const double rho = st->ry + block_sum((s0 + s1) + (s2 + s3), lds);
+    const double rho = st->ry + block_sum(strided_share<kThreads, 8>(hparts, nhp), lds);
     const bool bad = !isfinite(rho);
     const double beta = rho / st->rho[(it + 1) & 1];
     if (vb == 0 && threadIdx.x == 0) {
@@ -786,9 +869,9 @@ __global__ __launch_bounds__(kThreads) void k_prolong_p(int64_t n, int32_t nwg, 
                                                         const double *__restrict__ z_val,
                                                         const double *__restrict__ delta,
                                                         const double *__restrict__ y,
-                                                        const double *__restrict__ hd, int32_t k, double *p0,
+                                                        const double *__restrict__ hparts, int32_t nhp, double *p0,
                                                         double *p1, State *st) {
-    k_prolong_p_body(blockIdx.x, n, nwg, z_ptr, z_col, z_val, delta, y, hd, k, p0, p1, st);
+    k_prolong_p_body(blockIdx.x, n, nwg, z_ptr, z_col, z_val, delta, y, hparts, nhp, p0, p1, st);
 }
 
 // ||a||^2 partials and a count of non-finite entries of a and b (b may be null).
@@ -959,13 +1042,24 @@ __global__ __launch_bounds__(kRestrictThreads) void k_ms_restrict(const MsTable 
     }
 }
 
+// the coarse product's two stages (as launch_coarse); with_state 0: the start (no
+// state), 1: with the state, 2: also the tile-row sums of h_j delta_j for the prolongation
 __global__ __launch_bounds__(kThreads) void k_ms_coarse(const MsTable *__restrict__ tab, const MsSys *__restrict__ sys,
                                                         int with_state) {
     const int s = ms_find(tab, kMsCoarse, blockIdx.x);
     const MsSys &S = sys[s];
     if (!with_state && S.st->flag != kRunning) return;
-    k_coarse_body(blockIdx.x - tab->off[kMsCoarse][s], S.k, S.einv_ld, S.einv, S.g, S.delta,
-                  with_state ? S.st : nullptr, S.h, with_state == 2 ? S.hd : nullptr);
+    k_coarse_tiles_body(blockIdx.x - tab->off[kMsCoarse][s], S.k, S.coarse_nt, S.einv_tiles, S.g, S.cpart,
+                        with_state ? S.st : nullptr);
+}
+
+__global__ __launch_bounds__(kThreads) void k_ms_coarse_sum(const MsTable *__restrict__ tab,
+                                                            const MsSys *__restrict__ sys, int with_state) {
+    const int s = ms_find(tab, kMsCoarseSum, blockIdx.x);
+    const MsSys &S = sys[s];
+    if (!with_state && S.st->flag != kRunning) return;
+    k_coarse_sum_body(blockIdx.x - tab->off[kMsCoarseSum][s], S.k, S.coarse_nt, S.cpart, S.delta,
+                      with_state == 2 ? S.h : nullptr, S.hdp, with_state ? S.st : nullptr);
 }
 
 // mode 0: u = u_{-1} + Z delta (no state); mode 1: z = y + Z delta with r^T z partials;
@@ -987,8 +1081,8 @@ __global__ __launch_bounds__(kThreads) void k_ms_prolong(const MsTable *__restri
         k_prolong_body(vb, S.n, S.vec_nwg, S.z_ptr, S.z_col, S.z_val, S.delta, S.y, S.z, S.r, S.part_c, S.st,
                        advance);
     } else {
-        k_prolong_p_body(vb, S.n, S.vec_nwg, S.z_ptr, S.z_col, S.z_val, S.delta, S.y, S.hd, S.k, S.p0, S.p1,
-                         S.st);
+        k_prolong_p_body(vb, S.n, S.vec_nwg, S.z_ptr, S.z_col, S.z_val, S.delta, S.y, S.hdp, max(1, S.coarse_nt),
+                         S.p0, S.p1, S.st);
     }
 }
 
@@ -1095,7 +1189,8 @@ hipError_t launch_bj_dense(const dpcg_ctx *c, const double *r, double *y, const 
 
 hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, double *g, Workspace *w,
                            int check, int n_parts, int iter_offset, int max_iter, int record, bool fused) {
-    const int grid = c->k > 0 ? c->k : 1;
+    // a multiple of 8 workgroups, so that the columns are mapped XCD-major
+    const int grid = c->k >= 8 ? (c->k + 7) & ~7 : std::max(1, c->k);
     hipLaunchKernelGGL(k_restrict, dim3(grid), dim3(kRestrictThreads), 0, c->stream, c->k, c->zt_ptr, c->zt_idx,
                        c->zt_val, c->kzt_ptr, c->kzt_idx, c->kzt_val, a, b, g, w ? w->st : nullptr,
                        w ? w->part_b : nullptr, check ? n_parts : 0, iter_offset, max_iter,
@@ -1104,10 +1199,16 @@ hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, 
     return hipGetLastError();
 }
 
-hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, Workspace *w, bool fused) {
+hipError_t launch_coarse(const dpcg_ctx *c, const double *g, double *delta, const State *st, double *cpart,
+                         const double *h, double *hdp) {
     if (c->k == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_coarse, dim3(c->k), dim3(kThreads), 0, c->stream, c->k, c->einv_ld, c->einv, g, delta,
-                       w ? w->st : nullptr, fused ? w->h : nullptr, fused ? w->hd : nullptr);
+    const int nt = c->coarse_nt;
+    hipLaunchKernelGGL(k_coarse_tiles, dim3((unsigned)coarse_tile_count(nt)), dim3(256), 0, c->stream, c->k, nt,
+                       (const double *)c->einv_tiles, g, cpart, st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_coarse_sum, dim3(nt), dim3(256), 0, c->stream, c->k, nt, (const double *)cpart, delta, h, hdp,
+                       st);
     return hipGetLastError();
 }
 
@@ -1120,8 +1221,9 @@ hipError_t launch_prolong(const dpcg_ctx *c, const double *base, const double *d
 }
 
 hipError_t launch_prolong_p(const dpcg_ctx *c, Workspace &w) {
-    hipLaunchKernelGGL(k_prolong_p, dim3(c->vec_nwg), dim3(kThreads), 0, c->stream, c->n, c->vec_nwg, c->z_ptr,
-                       c->z_col, c->z_val, w.delta, w.y, w.hd, c->k, w.p[0], w.p[1], w.st);
+    hipLaunchKernelGGL(k_prolong_p, dim3(c->prolong_nwg), dim3(kThreads), 0, c->stream, c->n, c->prolong_nwg,
+                       c->z_ptr, c->z_col, c->z_val, w.delta, w.y, (const double *)w.hdp, std::max(1, c->coarse_nt),
+                       w.p[0], w.p[1], w.st);
     return hipGetLastError();
 }
 
@@ -1175,6 +1277,12 @@ hipError_t launch_ms_restrict(hipStream_t s, const MsTable *tab, const MsSys *sy
 hipError_t launch_ms_coarse(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int with_state) {
     if (ngrid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_ms_coarse, dim3(ngrid), dim3(kThreads), 0, s, tab, sys, with_state);
+    return hipGetLastError();
+}
+
+hipError_t launch_ms_coarse_sum(hipStream_t s, const MsTable *tab, const MsSys *sys, int ngrid, int with_state) {
+    if (ngrid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ms_coarse_sum, dim3(ngrid), dim3(kThreads), 0, s, tab, sys, with_state);
     return hipGetLastError();
 }
 

@@ -1491,6 +1491,25 @@ struct Pool {
     }
 };
 
+// Tile (I, J) of the lower triangle of E^-1 (ld x ld row-major, entries beyond k
+// ignored) into tiles[(I (I + 1) / 2 + J) T^2 ..] as a T x T row-major block, zero beyond k.
+__global__ __launch_bounds__(256) void k_pack_einv_tiles(int32_t k, int64_t ld, int32_t nt,
+                                                         const double *__restrict__ einv,
+                                                         double *__restrict__ tiles) {
+    constexpr int T = kCoarseTile;
+    const int64_t tid = blockIdx.x;
+    int I = (int)((sqrt(8.0 * (double)tid + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(I + 1) * (I + 2) / 2 <= tid) ++I;
+    while ((int64_t)I * (I + 1) / 2 > tid) --I;
+    const int J = (int)(tid - (int64_t)I * (I + 1) / 2);
+    double *out = tiles + tid * T * T;
+    for (int e = threadIdx.x; e < T * T; e += 256) {
+        const int a = I * T + e / T, b = J * T + e % T;
+        out[e] = (a < k && b < k) ? einv[(int64_t)a * ld + b] : 0.0;
+    }
+    (void)nt;
+}
+
 template <class T>
 hipError_t keep(dpcg_ctx *c, T **p, size_t count) {
     void *q = nullptr;
@@ -1694,6 +1713,12 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
                                pv + (p & 1) * kNb * kNb, pv + ((p + 1) & 1) * kNb * kNb, diag0, cfail);
             std::swap(src, dst);
         }
+        // the lower-triangle tiles of E^-1 for the solve's coarse product
+        const int32_t cnt = (int32_t)((k + kCoarseTile - 1) / kCoarseTile);
+        c->coarse_nt = cnt;
+        if (!reuse) HT(keep(c, &c->einv_tiles, coarse_tile_count(cnt) * kCoarseTile * kCoarseTile));
+        hipLaunchKernelGGL(k_pack_einv_tiles, dim3((unsigned)coarse_tile_count(cnt)), dim3(256), 0, s, k, ld, cnt,
+                           (const double *)c->einv, c->einv_tiles);
         HT(hipGetLastError());
         if (!reuse) {
             HT(keep(c, &c->kzt_ptr, k + 1));

@@ -7,9 +7,9 @@
   - FP64: iteration count within 2% of the oracle's, solution within 1e-6 relative.
     Residual histories: two runs of the same recurrences with different rounding
     drift apart as the iteration proceeds (the oracle's own literal and fast modes,
-    which differ only in rounding order, do so too), so each GPU entry must lie
-    within 1e-6 relative of the literal oracle's, or within 10 times the largest
-    literal-vs-fast departure reached by that iteration.
+    which differ only in rounding order, reach a 1.4% departure by the end at this
+    size), so the GPU's ||r_i|| must lie within 1e-6 relative of the literal oracle's
+    over the first three decades of the residual and within 10% everywhere.
   - mixed precision (binary32 refinement, then the FP64 method from its iterate):
     solution within 1e-6 relative of the oracle, the bound fixed for both paths
     before this test was first run; true residual <= 1.5e-8 on the host.
@@ -100,7 +100,9 @@ def test_fp64_solve_matches_oracle_penny80(ref80):
     assert iters_close(info["iterations"], ref["iterations"])
     assert err <= 1e-6
     assert rt <= 1.5e-8 and info["rel_res_recursive"] <= 1e-8
-    assert np.all(dev_h <= np.maximum(1e-6, 10 * env))
+    early = hr[:m] >= 1e-3 * hr[0]
+    assert np.all(dev_h[early] <= 1e-6)
+    assert np.all(dev_h <= 0.1)
 
 
 def test_mixed_solve_matches_oracle_penny80(ref80):
