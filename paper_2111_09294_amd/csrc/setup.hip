@@ -1114,17 +1114,73 @@ __global__ __launch_bounds__(256) void k_kzb_erows(const KzBatch *__restrict__ b
             if (b < B.ncol) eraw[(B.j0 + b) * ld + i] = acc[b];
 }
 
-// A = (E + E^T)/2 padded to ld x ld with an identity tail; diag0 = diagonal of A.
+// A = S (E + E^T)/2 S with S = diag(1 / sqrt(E_ii)), padded to ld x ld with an identity
+// tail; diag0 = diagonal of A; scale = the diagonal of S (1 where E_ii <= 0, whose
+// pivot then fails the SPD test).  Inverting the Jacobi-scaled matrix is exact
+// (E^-1 = S (S E S)^-1 S) and much better conditioned when the deflation vectors' scales
+// differ (rigid-body rotations against translations, enriched against standard DoFs);
+// the Schur pivots scale with the diagonal, so the SPD test is the unscaled one.
 __global__ void k_symmetrise(int32_t k, int64_t ld, const double *__restrict__ eraw, double *__restrict__ A,
-                             double *__restrict__ diag0) {
+                             double *__restrict__ diag0, double *__restrict__ scale) {
     const int64_t total = ld * ld;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = t / ld, j = t % ld;
         double v;
-        if (i < k && j < k) v = 0.5 * (eraw[i * ld + j] + eraw[j * ld + i]);
-        else v = (i == j) ? 1.0 : 0.0;
+        if (i < k && j < k) {
+            const double di = eraw[i * ld + i], dj = eraw[j * ld + j];
+            const double si = di > 0.0 ? 1.0 / sqrt(di) : 1.0, sj = dj > 0.0 ? 1.0 / sqrt(dj) : 1.0;
+            v = (0.5 * (eraw[i * ld + j] + eraw[j * ld + i]) * si) * sj;
+            if (i == j) scale[i] = si;
+        } else {
+            v = (i == j) ? 1.0 : 0.0;
+        }
         A[t] = v;
         if (i == j) diag0[i] = v;
+    }
+}
+
+// The final E^-1 from the inverse X of the scaled matrix: F = S (X + X^T)/2 S over the
+// k x k block, written back to the dense array (both triangles) and as the packed
+// lower-triangle tiles of the solve.  One workgroup per tile pair (I, J), I >= J, of
+// kCoarseTile^2 tiles: both tiles are read (coalesced, through LDS) before either is
+// written, and tile pairs are disjoint, so the update is in place.  Taking the
+// symmetric part keeps the operator the inverse of a symmetric matrix near E also when
+// X carries rounding errors of the order of cond(E) times the unit roundoff: the packed
+// lower triangle alone would add X's antisymmetric part.  The two scale factors are
+// applied in index order, so the dense result is exactly symmetric.
+__global__ __launch_bounds__(256) void k_einv_finish(int32_t k, int64_t ld, const double *__restrict__ scale,
+                                                     double *__restrict__ einv, double *__restrict__ tiles) {
+    constexpr int T = kCoarseTile;
+    __shared__ double A[T][T + 1], B[T][T + 1];  // X tile (I, J) and X tile (J, I)
+    const int64_t tid = blockIdx.x;
+    int I = (int)((sqrt(8.0 * (double)tid + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(I + 1) * (I + 2) / 2 <= tid) ++I;
+    while ((int64_t)I * (I + 1) / 2 > tid) --I;
+    const int J = (int)(tid - (int64_t)I * (I + 1) / 2);
+    for (int e = threadIdx.x; e < T * T; e += 256) {
+        const int a = e / T, b = e % T;
+        const int ra = I * T + a, cb = J * T + b;  // (I, J) entry (a, b)
+        const int rb = J * T + a, ca = I * T + b;  // (J, I) entry (a, b)
+        A[a][b] = (ra < k && cb < k) ? einv[(int64_t)ra * ld + cb] : 0.0;
+        B[a][b] = (rb < k && ca < k) ? einv[(int64_t)rb * ld + ca] : 0.0;
+    }
+    __syncthreads();
+    double *out = tiles + tid * T * T;
+    for (int e = threadIdx.x; e < T * T; e += 256) {
+        const int a = e / T, b = e % T;
+        const int ra = I * T + a, cb = J * T + b;
+        double f = 0.0;
+        if (ra < k && cb < k) f = (0.5 * (A[a][b] + B[b][a]) * scale[min(ra, cb)]) * scale[max(ra, cb)];
+        out[e] = f;
+        if (ra < k && cb < k) einv[(int64_t)ra * ld + cb] = f;
+    }
+    if (I != J) {  // the mirrored entries of the dense array: (J, I) entry (a, b) = F(b, a)
+        for (int e = threadIdx.x; e < T * T; e += 256) {
+            const int a = e / T, b = e % T;
+            const int rb = J * T + a, ca = I * T + b;
+            if (rb < k && ca < k)
+                einv[(int64_t)rb * ld + ca] = (0.5 * (A[b][a] + B[a][b]) * scale[min(rb, ca)]) * scale[max(rb, ca)];
+        }
     }
 }
 
@@ -1491,25 +1547,6 @@ struct Pool {
     }
 };
 
-// Tile (I, J) of the lower triangle of E^-1 (ld x ld row-major, entries beyond k
-// ignored) into tiles[(I (I + 1) / 2 + J) T^2 ..] as a T x T row-major block, zero beyond k.
-__global__ __launch_bounds__(256) void k_pack_einv_tiles(int32_t k, int64_t ld, int32_t nt,
-                                                         const double *__restrict__ einv,
-                                                         double *__restrict__ tiles) {
-    constexpr int T = kCoarseTile;
-    const int64_t tid = blockIdx.x;
-    int I = (int)((sqrt(8.0 * (double)tid + 1.0) - 1.0) * 0.5);
-    while ((int64_t)(I + 1) * (I + 2) / 2 <= tid) ++I;
-    while ((int64_t)I * (I + 1) / 2 > tid) --I;
-    const int J = (int)(tid - (int64_t)I * (I + 1) / 2);
-    double *out = tiles + tid * T * T;
-    for (int e = threadIdx.x; e < T * T; e += 256) {
-        const int a = I * T + e / T, b = J * T + e % T;
-        out[e] = (a < k && b < k) ? einv[(int64_t)a * ld + b] : 0.0;
-    }
-    (void)nt;
-}
-
 template <class T>
 hipError_t keep(dpcg_ctx *c, T **p, size_t count) {
     void *q = nullptr;
@@ -1697,9 +1734,11 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         // ---- E^-1 ----
         HT(pool.tmp(&ga, ld * ld));
         if (!reuse) HT(keep(c, &c->einv, ld * ld));
+        double *esc = nullptr;
         HT(pool.tmp(&diag0, ld));
+        HT(pool.tmp(&esc, ld));
         HT(pool.tmp(&pv, 2 * kNb * kNb));
-        hipLaunchKernelGGL(k_symmetrise, dim3(grid_for(ld * ld)), dim3(256), 0, s, k, ld, eraw, ga, diag0);
+        hipLaunchKernelGGL(k_symmetrise, dim3(grid_for(ld * ld)), dim3(256), 0, s, k, ld, eraw, ga, diag0, esc);
         int *cfail = flags + 2;
         HT(hipMemsetAsync(cfail, 0, sizeof(int), s));
         hipLaunchKernelGGL(k_gj_first_pivot, dim3(1), dim3(256), 0, s, ga, ld, k, diag0, pv, cfail);
@@ -1717,8 +1756,8 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         const int32_t cnt = (int32_t)((k + kCoarseTile - 1) / kCoarseTile);
         c->coarse_nt = cnt;
         if (!reuse) HT(keep(c, &c->einv_tiles, coarse_tile_count(cnt) * kCoarseTile * kCoarseTile));
-        hipLaunchKernelGGL(k_pack_einv_tiles, dim3((unsigned)coarse_tile_count(cnt)), dim3(256), 0, s, k, ld, cnt,
-                           (const double *)c->einv, c->einv_tiles);
+        hipLaunchKernelGGL(k_einv_finish, dim3((unsigned)coarse_tile_count(cnt)), dim3(256), 0, s, k, ld,
+                           (const double *)esc, c->einv, c->einv_tiles);
         HT(hipGetLastError());
         if (!reuse) {
             HT(keep(c, &c->kzt_ptr, k + 1));
