@@ -46,9 +46,12 @@ WORKLOADS = {
 # re-measured.
 SPMV_TRAFFIC = {
     "workload": "penny80",
-    "sources": {},
-    "fetch_bytes": None,
-    "write_bytes": None,
+    "sources": {
+        "paper_2111_09294_amd/csrc/kernels.hip": "8f4518e043e4bb37d25871bbe3fea7b51a763023babb8d7a738e930ba0cb56c2",
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "f58a7239a853dd1c5a1fa01034fce2e23bde45d474307c68c667b1e4bfb78a8c"
+    },
+    "fetch_bytes": 1436903854,
+    "write_bytes": 15886168,
 }
 SPMV_SOURCES = ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h")
 
