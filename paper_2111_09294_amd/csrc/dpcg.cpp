@@ -30,8 +30,8 @@ size_t partial_count(const dpcg_ctx *c) {
 size_t workspace_bytes(const dpcg_ctx *c) {
     const size_t n = (size_t)c->n, kk = (size_t)std::max(1, c->k), np = partial_count(c);
     const size_t nt = (size_t)std::max(1, c->coarse_nt);
-    return 7 * up256(8 * n) + 3 * up256(8 * kk) + 3 * up256(8 * np) + up256(8 * nt * nt * kCoarseTile) +
-           up256(8 * nt) + up256(sizeof(State));
+    return 7 * up256(8 * n) + 3 * up256(8 * kk) + 3 * up256(8 * np) + up256(8 * kAlphaParts) +
+           up256(8 * nt * nt * kCoarseTile) + up256(8 * nt) + up256(sizeof(State));
 }
 
 void carve_workspace(dpcg_ctx *c, Workspace &w, char *base) {
@@ -44,6 +44,8 @@ void carve_workspace(dpcg_ctx *c, Workspace &w, char *base) {
     for (double **d : vec) { *d = (double *)(base + off); off += up256(8 * n); }
     for (double **d : kv) { *d = (double *)(base + off); off += up256(8 * kk); }
     for (double **d : pv) { *d = (double *)(base + off); off += up256(8 * np); }
+    w.part_d = (double *)(base + off);
+    off += up256(8 * kAlphaParts);
     const size_t nt = (size_t)std::max(1, c->coarse_nt);
     w.cpart = (double *)(base + off);
     off += up256(8 * nt * nt * kCoarseTile);
@@ -661,6 +663,7 @@ int solve_many_impl(dpcg_handle *hs, int32_t count, const double *const *F, doub
         d.part_a = w.part_a;
         d.part_b = w.part_b;
         d.part_c = w.part_c;
+        d.part_d = w.part_d;
         d.h = w.h;
         d.einv_tiles = c->einv_tiles;
         d.coarse_nt = c->coarse_nt;

@@ -33,6 +33,7 @@ constexpr int kMaxDense = 8192;   // largest block-Jacobi block (dense path abov
 constexpr int kDenseRows = 32;    // rows of a dense block per workgroup of its apply
 constexpr int kMaxElemDofs = 256; // largest element (DoFs) of dpcg_element_gradient
 constexpr int kCoarseTile = 64;   // E^-1 kept as the lower-triangle tiles of this size
+constexpr int kAlphaParts = 64;   // workgroups of the first stage of p^T q
 
 // tile (I, J), I >= J, of the lower triangle of a matrix of nt x nt tiles: index I (I + 1) / 2 + J
 __host__ __device__ inline int64_t coarse_tile_count(int32_t nt) { return (int64_t)nt * (nt + 1) / 2; }
@@ -81,6 +82,7 @@ struct Workspace {
     double *part_a = nullptr;   // partial sums (p^T q, r^T r, r^T z); sized max grid
     double *part_b = nullptr;
     double *part_c = nullptr;
+    double *part_d = nullptr;   // kAlphaParts first-stage sums of p^T q
     double *rout = nullptr;     // mixed precision: FP64 residual f - K u of the refinement
     double *dcor = nullptr;     // mixed precision: correction of one inner solve
     State *st = nullptr;        // device
@@ -165,7 +167,7 @@ struct MsSys {
     const int32_t *z_ptr, *z_col;
     const double *z_val;
     const double *f;
-    double *u, *r, *y, *z, *q, *p0, *p1, *g, *delta, *part_a, *part_b, *part_c, *h;
+    double *u, *r, *y, *z, *q, *p0, *p1, *g, *delta, *part_a, *part_b, *part_c, *part_d, *h;
     const double *einv_tiles;   // the coarse product's packed E^-1 and its workspace
     int32_t coarse_nt, pad2;
     double *cpart, *hdp;

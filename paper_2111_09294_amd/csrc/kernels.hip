@@ -316,21 +316,22 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv_p(SpmvShape sh, const int
 }
 
 
-// alpha_i = rho_i / p_i^T q_i from the SpMV partials (one workgroup, fixed order).
-__global__ __launch_bounds__(1024) void k_alpha(const double *__restrict__ part_pq, int n, State *st) {
+// First stage of p_i^T q_i: workgroup a of kAlphaParts sums its contiguous share of the
+// SpMV's per-workgroup partials (one load per thread, fixed order) into part2[a]; the
+// update kernel adds the kAlphaParts sums and forms alpha_i itself.
+__device__ __forceinline__ void k_alpha_body(int a, const double *__restrict__ part_pq, int n,
+                                             double *__restrict__ part2, const State *st) {
     __shared__ double lds[16];
     if (st->flag != kRunning) return;
-    const double pq = reduce_parts_n<16>(part_pq, n, lds);
-    if (threadIdx.x == 0) {
-        const double alpha = st->rho[st->iter & 1] / pq;
-        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(alpha)) {
-            st->flag = kBreakdown;
-            st->bad = st->iter;
-            st->iters_done = st->iter;
-        } else {
-            st->alpha = alpha;
-        }
-    }
+    const int per = (n + kAlphaParts - 1) / kAlphaParts;
+    const int i0 = min(n, a * per), i1 = min(n, i0 + per);
+    const double s = block_sum_n<16>(strided_share<1024, 4>(part_pq + i0, i1 - i0), lds);
+    if (threadIdx.x == 0) part2[a] = s;
+}
+
+__global__ __launch_bounds__(1024) void k_alpha(const double *__restrict__ part_pq, int n, double *__restrict__ part2,
+                                                const State *st) {
+    k_alpha_body(blockIdx.x, part_pq, n, part2, st);
 }
 
 // rho_i = r_i^T z_i from the prolongation partials (every workgroup reduces them in
@@ -380,7 +381,14 @@ __device__ __forceinline__ double bj_row_at(int t, const double *tile, const M *
     const int size = meta >> 8, loc = meta & 255;
     const double *rt = tile + (t - loc);
     double s = 0.0;
-    for (int j = 0; j < size; ++j) s = fma(m[j], rt[j], s);
+    for (int j0 = 0; j0 < size; j0 += 6) {  // six entries' loads issued together, added in order
+        double v[6];
+#pragma unroll
+        for (int u = 0; u < 6; ++u) v[u] = j0 + u < size ? (double)m[j0 + u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+            if (j0 + u < size) s = fma(v[u], rt[j0 + u], s);
+    }
     return s;
 }
 
@@ -417,7 +425,7 @@ __device__ __forceinline__ void k_update_bj_body(int vb,
     double *__restrict__ r, double *__restrict__ y, const double *__restrict__ q, const double *p0,
     const double *p1, const M *__restrict__ minv, const int32_t *__restrict__ bj_rowoff,
     const int32_t *__restrict__ bj_meta, double *__restrict__ part_rr, double *__restrict__ part_ry,
-    const State *st) {
+    const double *__restrict__ part_pq2, State *st) {
     __shared__ double lds[4];
     __shared__ double tile[kThreads];
     const int t = threadIdx.x;
@@ -437,7 +445,18 @@ __device__ __forceinline__ void k_update_bj_body(int vb,
         b1 = tile_start[t0 + 1];
     }
     if (st->flag != kRunning) return;
-    const double alpha = st->alpha;
+    // alpha_i = rho_i / p_i^T q_i: every wave adds the kAlphaParts first-stage sums with the
+    // same butterfly, so all workgroups hold the same bits; a breakdown is seen by all
+    const double pq = wave_sum((threadIdx.x & 63) < kAlphaParts ? part_pq2[threadIdx.x & 63] : 0.0);
+    const double alpha = st->rho[st->iter & 1] / pq;
+    if (!(pq > 0.0) || !isfinite(pq) || !isfinite(alpha)) {
+        if (vb == 0 && threadIdx.x == 0) {
+            st->flag = kBreakdown;
+            st->bad = st->iter;
+            st->iters_done = st->iter;
+        }
+        return;
+    }
     const double *p = (st->iter & 1) ? p1 : p0;
     double acc = 0.0, accy = 0.0;
     for (int tt = t0; tt < t1; ++tt) {
@@ -480,9 +499,9 @@ __global__ __launch_bounds__(kThreads) void k_update_bj(
     double *__restrict__ r, double *__restrict__ y, const double *__restrict__ q, const double *p0,
     const double *p1, const M *__restrict__ minv, const int32_t *__restrict__ bj_rowoff,
     const int32_t *__restrict__ bj_meta, double *__restrict__ part_rr, double *__restrict__ part_ry,
-    const State *st) {
+    const double *__restrict__ part_pq2, State *st) {
     k_update_bj_body<M>(blockIdx.x, ntiles, nwg, tile_start, u, r, y, q, p0, p1, minv, bj_rowoff, bj_meta, part_rr,
-                        part_ry, st);
+                        part_ry, part_pq2, st);
 }
 
 
@@ -986,23 +1005,10 @@ __global__ __launch_bounds__(kSpmvThreads) void k_ms_spmv(const MsTable *__restr
     }
 }
 
-// alpha for system blockIdx.x (as k_alpha)
+// first stage of p^T q for system blockIdx.x / kAlphaParts (as k_alpha)
 __global__ __launch_bounds__(1024) void k_ms_alpha(const MsSys *__restrict__ sys) {
-    __shared__ double lds[16];
-    const MsSys &S = sys[blockIdx.x];
-    State *st = S.st;
-    if (st->flag != kRunning) return;
-    const double pq = reduce_parts_n<16>(S.part_a, S.spmv_nwg, lds);
-    if (threadIdx.x == 0) {
-        const double alpha = st->rho[st->iter & 1] / pq;
-        if (!(pq > 0.0) || !isfinite(pq) || !isfinite(alpha)) {
-            st->flag = kBreakdown;
-            st->bad = st->iter;
-            st->iters_done = st->iter;
-        } else {
-            st->alpha = alpha;
-        }
-    }
+    const MsSys &S = sys[blockIdx.x / kAlphaParts];
+    k_alpha_body(blockIdx.x % kAlphaParts, S.part_a, S.spmv_nwg, S.part_d, S.st);
 }
 
 __global__ __launch_bounds__(kThreads) void k_ms_update_bj(const MsTable *__restrict__ tab,
@@ -1010,7 +1016,7 @@ __global__ __launch_bounds__(kThreads) void k_ms_update_bj(const MsTable *__rest
     const int s = ms_find(tab, kMsBj, blockIdx.x);
     const MsSys &S = sys[s];
     k_update_bj_body<double>(blockIdx.x - tab->off[kMsBj][s], S.bj_ntiles, S.bj_nwg, S.bj_wg_start, S.u, S.r, S.y,
-                             S.q, S.p0, S.p1, S.minv, S.bj_rowoff, S.bj_meta, S.part_b, S.part_c, S.st);
+                             S.q, S.p0, S.p1, S.minv, S.bj_rowoff, S.bj_meta, S.part_b, S.part_c, S.part_d, S.st);
 }
 
 __global__ __launch_bounds__(kThreads) void k_ms_bj(const MsTable *__restrict__ tab, const MsSys *__restrict__ sys) {
@@ -1137,19 +1143,20 @@ hipError_t launch_spmv_residual(const dpcg_ctx *c, const double *x, const double
 }
 
 hipError_t launch_update_bj(const dpcg_ctx *c, double *u, Workspace &w, bool fused) {
-    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(1024), 0, c->stream, w.part_a, c->spmv.nwg, w.st);
+    hipLaunchKernelGGL(k_alpha, dim3(kAlphaParts), dim3(1024), 0, c->stream, (const double *)w.part_a, c->spmv.nwg,
+                       w.part_d, (const State *)w.st);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (c->inner32)
         hipLaunchKernelGGL(k_update_bj<float>, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles,
                            c->bj_nwg, c->bj_wg_start, u, w.r, w.y, (const double *)w.q, (const double *)w.p[0],
                            (const double *)w.p[1], (const float *)c->minv32, c->bj_rowoff, c->bj_meta, w.part_b,
-                           fused ? w.part_c : nullptr, (const State *)w.st);
+                           fused ? w.part_c : nullptr, (const double *)w.part_d, w.st);
     else
         hipLaunchKernelGGL(k_update_bj<double>, dim3(c->bj_nwg), dim3(kThreads), 0, c->stream, c->bj_ntiles,
                            c->bj_nwg, c->bj_wg_start, u, w.r, w.y, (const double *)w.q, (const double *)w.p[0],
                            (const double *)w.p[1], (const double *)c->minv, c->bj_rowoff, c->bj_meta, w.part_b,
-                           fused ? w.part_c : nullptr, (const State *)w.st);
+                           fused ? w.part_c : nullptr, (const double *)w.part_d, w.st);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_bj_dense(c, w.r, w.y, w.st);
@@ -1250,7 +1257,7 @@ hipError_t launch_ms_spmv_res(hipStream_t s, const MsTable *tab, const MsSys *sy
 }
 
 hipError_t launch_ms_alpha(hipStream_t s, const MsSys *sys, int nsys) {
-    hipLaunchKernelGGL(k_ms_alpha, dim3(nsys), dim3(1024), 0, s, sys);
+    hipLaunchKernelGGL(k_ms_alpha, dim3(nsys * kAlphaParts), dim3(1024), 0, s, sys);
     return hipGetLastError();
 }
 
