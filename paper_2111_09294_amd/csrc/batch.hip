@@ -68,10 +68,19 @@ __device__ __forceinline__ double group_sum_8(double v, double (*lds)[W]) {
 
 // MODE 0: y = K x and partials of x_j^T y_j (column-major: part[j * gridDim.x + wg]).
 // MODE 1: y = f - K x and partials of ||y_j||^2 (row-major: part[wg * W + j]).
-// One wave per block row: lane (bg, cq) = (lane >> 3, lane & 7) takes every eighth
-// block of the row starting at bg (two blocks per step) and the four columns
-// 4 cq .. 4 cq + 3, so a block's nine values are read once for all columns and each x
-// row is read as 16-byte pairs; the eight block groups are added by a fixed shuffle tree.
+// One wave per block row.  The row's values are contiguous (nine planes of m values),
+// so they are staged through wave-private LDS in chunks of 64 blocks with coalesced
+// loads (lane l loads block l of every plane) together with the column indices; the
+// products then read them back as LDS broadcasts.  Lane (bg, cq) = (lane >> 3, lane & 7)
+// takes every eighth block of the chunk starting at bg (kSpmmSteps blocks at a time) and the
+// four columns col4(cq, t): each 16-byte load of an x row by the eight lanes cq covers
+// one whole 128-byte half of the 256-byte row.  The eight block groups are added by a
+// fixed shuffle tree, so each column's sum has the same order for every lane mapping.
+__device__ __forceinline__ int col4(int cq, int t) { return (t >> 1) * 16 + 2 * cq + (t & 1); }
+
+constexpr int kSpmmChunk = 64;
+constexpr int kSpmmSteps = 2;  // blocks per lane whose x rows are loaded together
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_bspmm(int32_t nb, const int32_t *__restrict__ brow_ptr,
                                                const int32_t *__restrict__ bcol, const double *__restrict__ bval,
@@ -79,6 +88,8 @@ __global__ __launch_bounds__(256) void k_bspmm(int32_t nb, const int32_t *__rest
                                                double *__restrict__ y, double *__restrict__ part,
                                                const BatchState *st) {
     __shared__ double lds[4][W];
+    __shared__ double sv[4][9][kSpmmChunk];
+    __shared__ int32_t sc[4][kSpmmChunk];
     if (st && !st->any) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, bg = lane >> 3, cq = lane & 7;
     const int w = xcd_remap(blockIdx.x, gridDim.x);
@@ -87,42 +98,60 @@ __global__ __launch_bounds__(256) void k_bspmm(int32_t nb, const int32_t *__rest
     if (row < nb) {
         const int beg = brow_ptr[row], end = brow_ptr[row + 1];
         const int64_t m = end - beg;
-        const double *rv = bval + 9 * (int64_t)beg - beg;  // plane e of block b: rv[e * m + b]
+        const double *rv = bval + 9 * (int64_t)beg;  // plane e of block beg + i: rv[e * m + i]
         double a[3][4];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
             for (int t = 0; t < 4; ++t) a[i][t] = 0.0;
-        for (int b0 = beg + bg; b0 < end; b0 += 16) {
-            double v[2][9], xv[2][3][4];
+        for (int c0 = 0; c0 < m; c0 += kSpmmChunk) {
+            const int cnt = m - c0 < kSpmmChunk ? (int)(m - c0) : kSpmmChunk;
+            if (lane < cnt) {
+                double v[9];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int b = b0 + 8 * h;
-                const bool ok = b < end;
-                const int bb = ok ? b : b0;
+                for (int e = 0; e < 9; ++e) v[e] = rv[e * m + c0 + lane];
+                sc[wv][lane] = bcol[beg + c0 + lane];
 #pragma unroll
-                for (int e = 0; e < 9; ++e) v[h][e] = ok ? rv[e * m + bb] : 0.0;
-                const int64_t c = 3 * (int64_t)bcol[bb];
-#pragma unroll
-                for (int jj = 0; jj < 3; ++jj) {
-                    const double2 *xr = (const double2 *)(x + (c + jj) * W + 4 * cq);
-                    const double2 x01 = xr[0], x23 = xr[1];
-                    xv[h][jj][0] = x01.x;
-                    xv[h][jj][1] = x01.y;
-                    xv[h][jj][2] = x23.x;
-                    xv[h][jj][3] = x23.y;
-                }
+                for (int e = 0; e < 9; ++e) sv[wv][e][lane] = v[e];
             }
-            const bool ok1 = b0 + 8 < end;
+            // the wave's own LDS writes complete before its reads below
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int k0 = bg; k0 < cnt; k0 += 8 * kSpmmSteps) {
+                double xv[kSpmmSteps][3][4];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                if (h == 0 || ok1)
+                for (int h = 0; h < kSpmmSteps; ++h) {
+                    const int k = k0 + 8 * h < cnt ? k0 + 8 * h : k0;
+                    const int64_t c = 3 * (int64_t)sc[wv][k];
 #pragma unroll
-                    for (int jj = 0; jj < 3; ++jj)
+                    for (int jj = 0; jj < 3; ++jj) {
+                        const double *xr = x + (c + jj) * W + 2 * cq;
+                        const double2 lo = *(const double2 *)xr, hi = *(const double2 *)(xr + 16);
+                        xv[h][jj][0] = lo.x;
+                        xv[h][jj][1] = lo.y;
+                        xv[h][jj][2] = hi.x;
+                        xv[h][jj][3] = hi.y;
+                    }
+                }
 #pragma unroll
-                        for (int i = 0; i < 3; ++i)
+                for (int h = 0; h < kSpmmSteps; ++h)
+                    if (k0 + 8 * h < cnt) {
+                        const int k = k0 + 8 * h;
 #pragma unroll
-                            for (int t = 0; t < 4; ++t) a[i][t] = fma(v[h][3 * i + jj], xv[h][jj][t], a[i][t]);
+                        for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+                            for (int i = 0; i < 3; ++i) {
+                                const double v = sv[wv][3 * i + jj][k];
+#pragma unroll
+                                for (int t = 0; t < 4; ++t) a[i][t] = fma(v, xv[h][jj][t], a[i][t]);
+                            }
+                    }
+            }
+            // every lane is done reading this chunk before the next one is written
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
 #pragma unroll
         for (int off = 8; off < 64; off <<= 1)
@@ -133,27 +162,27 @@ __global__ __launch_bounds__(256) void k_bspmm(int32_t nb, const int32_t *__rest
         if (bg == 0) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
-                const int64_t o = (3 * (int64_t)row + i) * W + 4 * cq;
+                const int64_t o = (3 * (int64_t)row + i) * W;
                 double out[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
+                    const int64_t oj = o + col4(cq, t);
                     if (MODE == 0) {
                         out[t] = a[i][t];
-                        acc[t] = fma(x[o + t], out[t], acc[t]);
+                        acc[t] = fma(x[oj], out[t], acc[t]);
                     } else {
-                        out[t] = f[o + t] - a[i][t];
+                        out[t] = f[oj] - a[i][t];
                         acc[t] = fma(out[t], out[t], acc[t]);
                     }
                 }
-                double2 *yo = (double2 *)(y + o);
-                yo[0] = make_double2(out[0], out[1]);
-                yo[1] = make_double2(out[2], out[3]);
+                *(double2 *)(y + o + 2 * cq) = make_double2(out[0], out[1]);
+                *(double2 *)(y + o + 16 + 2 * cq) = make_double2(out[2], out[3]);
             }
         }
     }
     if (bg == 0)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) lds[wv][4 * cq + t] = acc[t];
+        for (int t = 0; t < 4; ++t) lds[wv][col4(cq, t)] = acc[t];
     __syncthreads();
     if (threadIdx.x < W) {
         const double v = (lds[0][threadIdx.x] + lds[1][threadIdx.x]) + (lds[2][threadIdx.x] + lds[3][threadIdx.x]);
@@ -922,7 +951,7 @@ int enqueue_restrict(dpcg_ctx *c, const double *a, const double *bvec, BatchStat
                      int iter_offset, int max_iter) {
     BatchWorkspace *b = c->bws;
     if (b->grouped) {
-        const int grid = ((b->ngseg + kGroupWaves - 1) / kGroupWaves + 7) & ~7;  // a multiple of 8: XCD-major
+        const int grid = ((b->ngseg + kGroupWaves - 1) / kGroupWaves + 7) & ~7;  // a multiple of 8: XCD-aware mapping
         BLAUNCH(k_brestrict_mfma, dim3(grid), dim3(64 * kGroupWaves), 0, c->stream, (const int32_t *)b->gseg, b->ngseg,
                 (const int32_t *)b->zr, (const double *)b->zv, c->kzt_idx, (const double *)c->kzt_val, a, bvec,
                 b->seg_part, st, part_rr, n_rr, iter_offset, max_iter);
