@@ -47,11 +47,11 @@ WORKLOADS = {
 SPMV_TRAFFIC = {
     "workload": "penny80",
     "sources": {
-        "paper_2111_09294_amd/csrc/kernels.hip": "8f4518e043e4bb37d25871bbe3fea7b51a763023babb8d7a738e930ba0cb56c2",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "f58a7239a853dd1c5a1fa01034fce2e23bde45d474307c68c667b1e4bfb78a8c"
+        "paper_2111_09294_amd/csrc/kernels.hip": "dc2ae2e14214258d29f769016406806cbe8bbb06c4240bf4d921317530390352",
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "191409ded8ffbb25eb66c56190de9ee7f3f66541fb7450a2b1e4643e3da26391"
     },
-    "fetch_bytes": 1436903854,
-    "write_bytes": 15886168,
+    "fetch_bytes": 1482832100,
+    "write_bytes": 15991136,
 }
 SPMV_SOURCES = ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h")
 

@@ -42,11 +42,20 @@ constexpr int kBatchSegEntries = 2048;  // entries per multi-RHS restriction seg
 constexpr int kBatchTileWindow = 47;                         // block starts per multi-RHS tile
 constexpr int kBatchTileDofs = kBatchTileWindow + kMaxBlock - 1;  // <= 64 DoFs per tile
 
-// The hardware spreads consecutive workgroups round-robin over the 8 XCDs; give each
-// XCD a contiguous range of work so neighbouring rows share its L2.
+// The hardware spreads consecutive workgroups round-robin over the 8 XCDs.  The remap
+// gives each XCD runs of kXcdChunk consecutive logical workgroups (neighbouring rows,
+// whose gathers share that XCD's L2) and deals the runs round-robin over the XCDs, so
+// that every XCD gets an even share of any region of the matrix: the crack's enriched
+// rows are several times longer than the others and sit in one band of the numbering,
+// which one contiguous eighth of the rows per XCD would hand to a single XCD.  The
+// last partial group of 8 kXcdChunk workgroups keeps launch order.
+constexpr int kXcdChunk = 16;
+
 __device__ __forceinline__ int xcd_remap(int w, int nwg) {
-    if ((nwg & 7) != 0) return w;
-    return (w & 7) * (nwg >> 3) + (w >> 3);
+    const int full = nwg / (8 * kXcdChunk) * (8 * kXcdChunk);
+    if (w >= full) return w;
+    const int i = w >> 3;  // position of w among its XCD's workgroups
+    return (i / kXcdChunk) * (8 * kXcdChunk) + (w & 7) * kXcdChunk + (i % kXcdChunk);
 }
 
 // Solver state shared by the kernels of one solve; lives in device memory.  Every

@@ -968,7 +968,7 @@ __global__ void k_add(int64_t n, const double *__restrict__ x, double *__restric
 // Each phase of an iteration of several independent systems runs as one launch whose
 // workgroups are the systems' own, concatenated: a workgroup finds its system and its
 // index within that system in the phase's offset table (each system's count is a
-// multiple of 8 where the kernel maps workgroups XCD-major, so the mapping holds), and
+// multiple of 8 where the kernel remaps workgroups over the XCDs, so the mapping holds), and
 // then runs the single-system body on that system's operator, vectors and state.
 __device__ __forceinline__ int ms_find(const MsTable *__restrict__ tab, int phase, int bid) {
     int lo = 0, hi = tab->nsys;  // last s with off[phase][s] <= bid
@@ -1196,7 +1196,7 @@ hipError_t launch_bj_dense(const dpcg_ctx *c, const double *r, double *y, const 
 
 hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, double *g, Workspace *w,
                            int check, int n_parts, int iter_offset, int max_iter, int record, bool fused) {
-    // a multiple of 8 workgroups, so that the columns are mapped XCD-major
+    // a multiple of 8 workgroups, so that the XCD-aware column mapping applies
     const int grid = c->k >= 8 ? (c->k + 7) & ~7 : std::max(1, c->k);
     hipLaunchKernelGGL(k_restrict, dim3(grid), dim3(kRestrictThreads), 0, c->stream, c->k, c->zt_ptr, c->zt_idx,
                        c->zt_val, c->kzt_ptr, c->kzt_idx, c->kzt_val, a, b, g, w ? w->st : nullptr,

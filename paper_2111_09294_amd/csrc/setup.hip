@@ -219,8 +219,9 @@ __global__ __launch_bounds__(256) void k_check_sym(const int32_t *__restrict__ b
     for (int i = 0; i < nmax; ++i) mx = fmax(mx, maxpart[i]);
     const double tol = 1e-12 * mx;
     int64_t lower = 0, found_n = 0;
-    // a contiguous range of blocks per workgroup and per XCD: the mirrors of neighbouring
-    // rows sit side by side in the same block rows, so they share the XCD's L2 lines
+    // a contiguous range of blocks per workgroup, runs of neighbouring ranges per XCD:
+    // the mirrors of neighbouring rows sit side by side in the same block rows, so they
+    // share the XCD's L2 lines
     const int64_t per = ((nnzb + gridDim.x - 1) / gridDim.x + 255) / 256 * 256;
     const int64_t b0 = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * per, b1 = min(nnzb, b0 + per);
     for (int64_t b = b0 + threadIdx.x; b < b1; b += 256) {
