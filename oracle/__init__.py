@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-from .build import LIB, build
+from .build import LIB, LIB_SAN, build
 
 OK, NOT_CONVERGED, EINVAL, EBLOCK_NOT_SPD, ECOARSE_NOT_SPD, EBREAKDOWN, ENONFINITE = 0, 1, -1, -3, -4, -5, -7
 
@@ -22,9 +22,11 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build()
-        L = C.CDLL(LIB)
+        san = os.environ.get("ORACLE_SANITIZED") == "1"
+        path = LIB_SAN if san else LIB
+        if not os.path.exists(path):
+            build(sanitize=san)
+        L = C.CDLL(path)
         P = C.c_void_p
         L.oracle_setup.argtypes = [C.POINTER(C.c_void_p), C.c_int64, P, P, P, C.c_int32, P, P, P,
                                    C.c_int32, P, C.POINTER(C.c_int64)]
