@@ -382,6 +382,7 @@ def main():
     import numpy as np
     import torch
 
+    import paper_2111_09294_amd as dpcg
     from fixtures import load
 
     dev = torch.device("cuda:0")
@@ -448,6 +449,18 @@ def main():
         out["error_vs_oracle"] = {"fp64": float(np.linalg.norm(u64.cpu().numpy() - uo) / nref)}
         if um is not None:
             out["error_vs_oracle"]["mixed"] = float(np.linalg.norm(um.cpu().numpy() - uo) / nref)
+    # distance of both answers from the solution of K u = f, taken as the FP64 solve to a
+    # residual of 1e-12 (four decades below the stopping test): the two paths stop at
+    # different iterates of residual <= 1e-8, so their distance to each other is not
+    # their accuracy
+    with dpcg.Solver(p.n, *tensors[0], p.k, *tensors[1], tensors[2], stream=stream) as s:
+        ut, it = s.solve(tensors[3], tol=1e-12)
+    ut = ut.cpu().numpy()
+    nt = np.linalg.norm(ut)
+    out["error_vs_tight_solve"] = {"tol": 1e-12, "iterations": it["iterations"],
+                                   "fp64": float(np.linalg.norm(u64.cpu().numpy() - ut) / nt)}
+    if um is not None:
+        out["error_vs_tight_solve"]["mixed"] = float(np.linalg.norm(um.cpu().numpy() - ut) / nt)
     del tensors, u64, um
     torch.cuda.empty_cache()
 
