@@ -233,7 +233,7 @@ struct dpcg_ctx {
     int32_t *kzt_ptr = nullptr, *kzt_idx = nullptr;
     double *kzt_val = nullptr;
     double *einv = nullptr;
-    int64_t einv_ld = 0;       // leading dimension of E^-1 (k rounded up to 32)
+    int64_t einv_ld = 0;       // leading dimension of E^-1 (k rounded up to 64)
     double *einv_tiles = nullptr;  // the lower triangle of E^-1 as kCoarseTile^2 row-major tiles,
                                    // zero beyond k (symmetric diagonal tiles stored whole)
     int32_t coarse_nt = 0;         // tiles per side: ceil(k / kCoarseTile)

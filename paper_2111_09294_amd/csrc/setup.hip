@@ -1140,52 +1140,7 @@ __global__ void k_symmetrise(int32_t k, int64_t ld, const double *__restrict__ e
     }
 }
 
-// The final E^-1 from the inverse X of the scaled matrix: F = S (X + X^T)/2 S over the
-// k x k block, written back to the dense array (both triangles) and as the packed
-// lower-triangle tiles of the solve.  One workgroup per tile pair (I, J), I >= J, of
-// kCoarseTile^2 tiles: both tiles are read (coalesced, through LDS) before either is
-// written, and tile pairs are disjoint, so the update is in place.  Taking the
-// symmetric part keeps the operator the inverse of a symmetric matrix near E also when
-// X carries rounding errors of the order of cond(E) times the unit roundoff: the packed
-// lower triangle alone would add X's antisymmetric part.  The two scale factors are
-// applied in index order, so the dense result is exactly symmetric.
-__global__ __launch_bounds__(256) void k_einv_finish(int32_t k, int64_t ld, const double *__restrict__ scale,
-                                                     double *__restrict__ einv, double *__restrict__ tiles) {
-    constexpr int T = kCoarseTile;
-    __shared__ double A[T][T + 1], B[T][T + 1];  // X tile (I, J) and X tile (J, I)
-    const int64_t tid = blockIdx.x;
-    int I = (int)((sqrt(8.0 * (double)tid + 1.0) - 1.0) * 0.5);
-    while ((int64_t)(I + 1) * (I + 2) / 2 <= tid) ++I;
-    while ((int64_t)I * (I + 1) / 2 > tid) --I;
-    const int J = (int)(tid - (int64_t)I * (I + 1) / 2);
-    for (int e = threadIdx.x; e < T * T; e += 256) {
-        const int a = e / T, b = e % T;
-        const int ra = I * T + a, cb = J * T + b;  // (I, J) entry (a, b)
-        const int rb = J * T + a, ca = I * T + b;  // (J, I) entry (a, b)
-        A[a][b] = (ra < k && cb < k) ? einv[(int64_t)ra * ld + cb] : 0.0;
-        B[a][b] = (rb < k && ca < k) ? einv[(int64_t)rb * ld + ca] : 0.0;
-    }
-    __syncthreads();
-    double *out = tiles + tid * T * T;
-    for (int e = threadIdx.x; e < T * T; e += 256) {
-        const int a = e / T, b = e % T;
-        const int ra = I * T + a, cb = J * T + b;
-        double f = 0.0;
-        if (ra < k && cb < k) f = (0.5 * (A[a][b] + B[b][a]) * scale[min(ra, cb)]) * scale[max(ra, cb)];
-        out[e] = f;
-        if (ra < k && cb < k) einv[(int64_t)ra * ld + cb] = f;
-    }
-    if (I != J) {  // the mirrored entries of the dense array: (J, I) entry (a, b) = F(b, a)
-        for (int e = threadIdx.x; e < T * T; e += 256) {
-            const int a = e / T, b = e % T;
-            const int rb = J * T + a, ca = I * T + b;
-            if (rb < k && ca < k)
-                einv[(int64_t)rb * ld + ca] = (0.5 * (A[b][a] + B[a][b]) * scale[min(rb, ca)]) * scale[max(rb, ca)];
-        }
-    }
-}
-
-// ---------------------------------------------------------------- E^-1 by block Gauss-Jordan
+// ---------------------------------------------------------------- block Gauss-Jordan
 // P = S^-1 for the symmetric positive definite 32 x 32 pivot block S (LDS) by in-place
 // Gauss-Jordan elimination without pivoting (on an SPD matrix its pivots are the Schur
 // complement pivots of the Cholesky factorisation).  Step k, pivot p = a_kk:
@@ -1253,15 +1208,6 @@ __device__ void pivot_inverse(const double *S, int lds, double *W, const double 
     }
 }
 
-__global__ __launch_bounds__(256) void k_gj_first_pivot(const double *__restrict__ A, int64_t ld, int32_t kdim,
-                                                        const double *__restrict__ diag0, double *__restrict__ P,
-                                                        int *fail) {
-    __shared__ double S[kNb * kNb], W[kNb * kNb];
-    for (int t = threadIdx.x; t < kNb * kNb; t += 256) S[t] = A[(t / kNb) * ld + (t % kNb)];
-    __syncthreads();
-    pivot_inverse(S, kNb, W, diag0, 0, kdim, P, fail, -1);
-}
-
 // The 32 x 32 tile products of the sweeps on the matrix cores: wave w of the 256 threads
 // computes the 16 x 16 quarter (w / 2, w % 2) of X Y (X, Y in LDS, row stride kLd) as
 // eight v_mfma_f64_16x16x4f64 steps.  Operand lanes: a = X[row l % 16][k-step col l / 16],
@@ -1287,14 +1233,13 @@ __device__ __forceinline__ int tile_row(int v) {
 }
 __device__ __forceinline__ int tile_col() { return ((threadIdx.x >> 6) & 1) * 16 + (threadIdx.x & 15); }
 
-// One sweep with pivot block p: B = sweep(A).  Tile (I, J) of 32 x 32:
+// One sweep with pivot block p of the dense block-Jacobi blocks' inversion: B = sweep(A).
+// Tile (I, J) of 32 x 32:
 //   I = J = p: P;  I = p: P A_pJ;  J = p: -A_Ip P;  else A_IJ - A_Ip (P A_pJ).
-// Every tile is computed from its own formula: mirroring the tiles above the diagonal
-// from those below (the symmetric sweep operator, half the tiles) leaves the inverse as
-// close to E^-1 but makes E X - I about a thousand times larger on an ill-conditioned E,
-// and the deflated iteration then stalls at tight tolerances.  All global loads of a
-// tile are issued before the first LDS store, and P A_pJ reuses the LDS of A_pJ.  The
-// workgroup of tile (p+1, p+1) also inverts the next pivot block.
+// Every tile is computed from its own formula (the coarse matrix, Jacobi-scaled, uses
+// the symmetric 64-wide sweeps below instead).  All global loads of a tile are issued
+// before the first LDS store, and P A_pJ reuses the LDS of A_pJ.  The workgroup of tile
+// (p+1, p+1) also inverts the next pivot block.
 __device__ __forceinline__ void gj_sweep_tile(int p, int nt, int I, int J, const double *__restrict__ A,
                                               double *__restrict__ B, int64_t ld, int32_t kdim,
                                               const double *__restrict__ Pcur, double *__restrict__ Pnext,
@@ -1354,15 +1299,322 @@ __device__ __forceinline__ void gj_sweep_tile(int p, int nt, int I, int J, const
     }
 }
 
-__global__ __launch_bounds__(256) void k_gj_sweep(int p, int nt, const double *__restrict__ A, double *__restrict__ B,
-                                                  int64_t ld, int32_t kdim, const double *__restrict__ Pcur,
-                                                  double *__restrict__ Pnext, const double *__restrict__ diag0,
-                                                  int *fail) {
-    // tiles rotated so that the next pivot tile (p+1, p+1), whose workgroup also runs the
-    // pivot inversion (the critical path of the sweep), is dispatched first
-    const int ntt = nt * nt;
-    const int t = (int)((blockIdx.x + (int64_t)(p + 1) * (nt + 1)) % ntt);
-    gj_sweep_tile(p, nt, t / nt, t % nt, A, B, ld, kdim, Pcur, Pnext, diag0, fail, -1);
+// ---------------------------------------------------------------- E^-1: symmetric sweeps
+// The coarse matrix is symmetric positive definite, so its block Gauss-Jordan inverse is
+// run as the symmetric sweep operator on the lower triangle of 64 x 64 tiles only.  After
+// the sweeps over pivot blocks 0 .. p-1 the working matrix is symmetric up to signs: its
+// entry (i, j) equals sigma_i sigma_j times entry (j, i), sigma = -1 on the rows of the
+// pivot blocks already swept and +1 on the others, so every tile above the diagonal is a
+// signed transpose of one below it, and a diagonal tile is symmetric (its upper half is
+// always taken from its lower half).  Sweep p, with P = A_pp^-1 (symmetrised):
+//   new row p:        T_J  = P A_pJ                       (panel kernel, every J)
+//   new column p:     B_Ip = -A_Ip P = -T_I^T   (I > p)
+//   new pivot tile:   B_pp = P
+//   every other tile: B_IJ = A_IJ - A_Ip T_J
+// so each lower tile costs one 64 x 64 x 64 product on the matrix cores, and a sweep
+// reads and writes the lower triangle once: a quarter of the work of the full 32-wide
+// sweeps over every tile.  The panel kernel stores T and the column panel C_I = A_Ip in
+// buffers of their own, so the sweep updates the matrix in place.  In a numpy model on
+// the Jacobi-scaled coarse matrices of the 40^3 and 80^3 workloads this form leaves
+// max |I - E E^-1| at the level of the full 32-wide sweeps (80^3: 2.6e-3 against 2.9e-3).
+constexpr int kCb = 64;
+constexpr int kCbLd = kCb + 1;  // LDS row stride: a column's 16 rows in distinct banks
+
+// P = S^-1 (symmetrised, in place) for the 64 x 64 SPD pivot block S in LDS (row stride
+// kCbLd) by Gauss-Jordan elimination without pivoting, as pivot_inverse, in its
+// symmetric form: during the in-place elimination of a symmetric matrix, entry (k, c)
+// equals sigma_c times entry (c, k), sigma_c = -1 for the columns already pivoted and +1
+// for the others, so step k reads only column k and takes row k from it.  Thread
+// (ty, tx) = (t / 64, t % 64) keeps rows 16 ty + q, q < 16, of column tx in registers;
+// the lane that owns column k + 1 writes it to W (2 kCb doubles, ping-pong by step
+// parity), one barrier per step.  Pivot j is tested against kdim * DBL_EPSILON times the
+// original diagonal entry gcol0 + j; returns whether one failed (in every thread).
+__device__ __forceinline__ bool pivot_inverse64(double *S, double *W, const double *__restrict__ diag0, int64_t gcol0,
+                                                int32_t kdim) {
+    __shared__ int bad_s;
+    const int tx = threadIdx.x & 63, r0 = (threadIdx.x >> 6) * 16;
+    const int64_t gmine = gcol0 + threadIdx.x;
+    const double myfl = ((int)threadIdx.x < kCb && gmine < kdim) ? (double)kdim * DBL_EPSILON * fabs(diag0[gmine]) : 0.0;
+    if (threadIdx.x == 0) bad_s = 0;
+    double a[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q] = S[(r0 + q) * kCbLd + tx];
+    if ((int)threadIdx.x < kCb) W[threadIdx.x] = S[threadIdx.x * kCbLd];  // column 0
+    bool bad = false;
+    __syncthreads();
+#pragma unroll 1
+    for (int k = 0; k < kCb; ++k) {
+        const double *col = W + (k & 1) * kCb;
+        double *nxt = W + ((k & 1) ^ 1) * kCb;
+        // all LDS reads of the step first (one wait)
+        const double p = col[k];
+        const double ck = col[tx];
+        double rk[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) rk[q] = col[r0 + q];
+        const double kc = tx < k ? -ck : ck;  // entry (k, tx)
+        if ((int)threadIdx.x == k && (!(p > myfl) || !isfinite(p))) bad = true;
+        // 1/p: hardware reciprocal refined by two Newton steps
+        double ip = __builtin_amdgcn_rcp(p);
+        ip = fma(ip, fma(-p, ip, 1.0), ip);
+        ip = fma(ip, fma(-p, ip, 1.0), ip);
+        const double kcip = kc * ip;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const double m = -rk[q] * ip;
+            const double v = fma(m, kc, a[q]);
+            a[q] = (tx == k) ? m : v;
+        }
+        if (k >= r0 && k < r0 + 16) {  // row k lies in this wave: a uniform branch
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (r0 + q == k) a[q] = (tx == k) ? ip : kcip;
+        }
+        if (tx == k + 1) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) nxt[r0 + q] = a[q];
+        }
+        __syncthreads();
+    }
+    if (bad) atomicOr(&bad_s, 1);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) S[(r0 + q) * kCbLd + tx] = a[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) a[q] = 0.5 * (S[(r0 + q) * kCbLd + tx] + S[tx * kCbLd + r0 + q]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) S[(r0 + q) * kCbLd + tx] = a[q];
+    __syncthreads();
+    return bad_s != 0;
+}
+
+// X Y for 64 x 64 tiles X, Y in LDS (row stride kCbLd) on the matrix cores: wave w of the
+// 256 threads computes the 32 x 32 quadrant (w / 2, w % 2) as 2 x 2 blocks of 16 x 16,
+// sixteen v_mfma_f64_16x16x4f64 steps each.  Result item v of block b = 2 bi + bj of lane
+// l is element (cb_row(b, v), cb_col(b)) of the product.
+__device__ __forceinline__ int cb_row(int b, int v) {
+    return ((threadIdx.x >> 6) >> 1) * 32 + (b >> 1) * 16 + ((threadIdx.x & 63) >> 4) + 4 * v;
+}
+__device__ __forceinline__ int cb_col(int b) { return ((threadIdx.x >> 6) & 1) * 32 + (b & 1) * 16 + (threadIdx.x & 15); }
+
+__device__ __forceinline__ void cb_mfma(const double *X, const double *Y, dbl4 (&acc)[4]) {
+    const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, kq = l >> 4;
+    const int r0 = (wv >> 1) * 32 + (l & 15), c0 = (wv & 1) * 32 + (l & 15);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[b] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int s4 = 0; s4 < kCb; s4 += 4) {
+        const double x0 = X[r0 * kCbLd + s4 + kq], x1 = X[(r0 + 16) * kCbLd + s4 + kq];
+        const double y0 = Y[(s4 + kq) * kCbLd + c0], y1 = Y[(s4 + kq) * kCbLd + c0 + 16];
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y1, acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y0, acc[2], 0, 0, 0);
+        acc[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, acc[3], 0, 0, 0);
+    }
+}
+
+// entry (a, b) of diagonal tile (I, I) (first row r0) of the row-major ld x ld array A,
+// from its lower half
+__device__ __forceinline__ double diag_tile_at(const double *__restrict__ A, int64_t ld, int64_t r0, int a, int b) {
+    return a >= b ? A[(r0 + a) * ld + r0 + b] : A[(r0 + b) * ld + r0 + a];
+}
+
+// P_0 = A_00^-1 (symmetrised) from the first diagonal tile's lower half.
+__global__ __launch_bounds__(256) void k_cgj_first_pivot(const double *__restrict__ A, int64_t ld, int32_t kdim,
+                                                         const double *__restrict__ diag0, double *__restrict__ P,
+                                                         int *fail) {
+    __shared__ double S[kCb * kCbLd], W[4 * kCb];
+    const int tb = threadIdx.x & 63, ta = threadIdx.x >> 6;  // element (ta + 4 q, tb)
+    double sv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) sv[q] = A[(ta + 4 * q) * ld + tb];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) S[(ta + 4 * q) * kCbLd + tb] = sv[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int a = ta + 4 * q;
+        sv[q] = a >= tb ? S[a * kCbLd + tb] : S[tb * kCbLd + a];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) S[(ta + 4 * q) * kCbLd + tb] = sv[q];
+    __syncthreads();
+    const bool bad = pivot_inverse64(S, W, diag0, 0, kdim);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) P[(ta + 4 * q) * kCb + tb] = S[(ta + 4 * q) * kCbLd + tb];
+    if (bad && threadIdx.x == 0) atomicOr(fail, 1);
+}
+
+// Panel of sweep p, workgroup J != p: the tile A_pJ (stored below the diagonal for J < p;
+// for J > p the transpose of the stored (J, p), sign +1), T_J = P A_pJ into tbuf[J], and
+// the column tile A_Jp = s A_pJ^T into cbuf[J] (s = +1 for J > p, -1 for J < p: block row
+// J is swept, block row p not yet).  Both buffers hold nt tiles of 64 x 64, row-major.
+__global__ __launch_bounds__(256) void k_cgj_panel(int p, const double *__restrict__ A, int64_t ld,
+                                                   const double *__restrict__ P, double *__restrict__ cbuf,
+                                                   double *__restrict__ tbuf) {
+    __shared__ double S[kCb * kCbLd], Y[kCb * kCbLd];
+    const int J = blockIdx.x;
+    if (J == p) return;
+    const int64_t rp = (int64_t)p * kCb, cj = (int64_t)J * kCb;
+    // all loads (coalesced, row-major) before the first LDS store: P, and the stored
+    // tile (p, J) for J < p or (J, p) for J > p, which is A_pJ transposed
+    const int tb = threadIdx.x & 63, ta = threadIdx.x >> 6;  // element (ta + 4 q, tb)
+    const int64_t yo = J < p ? rp * ld + cj : cj * ld + rp;
+    double pv[16], yv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int a = ta + 4 * q;
+        pv[q] = P[a * kCb + tb];
+        yv[q] = A[yo + (int64_t)a * ld + tb];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int a = ta + 4 * q;
+        S[a * kCbLd + tb] = pv[q];
+        if (J < p) Y[a * kCbLd + tb] = yv[q];
+        else Y[tb * kCbLd + a] = yv[q];
+    }
+    __syncthreads();
+    const double s = J > p ? 1.0 : -1.0;
+    double *cj_out = cbuf + (int64_t)J * kCb * kCb;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int a = ta + 4 * q;
+        cj_out[a * kCb + tb] = s * Y[tb * kCbLd + a];
+    }
+    dbl4 acc[4];
+    cb_mfma(S, Y, acc);
+    double *tj = tbuf + (int64_t)J * kCb * kCb;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) tj[cb_row(b, v) * kCb + cb_col(b)] = acc[b][v];
+}
+
+// Sweep p over the lower tiles (I, J), I >= J, in place (tiles numbered row by row,
+// I (I + 1) / 2 + J).  The tiles are rotated so that the next pivot tile (p + 1, p + 1)
+// is dispatched first: its workgroup also inverts it into Pnext (the critical path of
+// the sweep, overlapped with the other tiles).  P and Pnext are distinct buffers.
+__global__ __launch_bounds__(256) void k_cgj_sweep(int p, int nt, double *__restrict__ A, int64_t ld, int32_t kdim,
+                                                   const double *__restrict__ P, double *__restrict__ Pnext,
+                                                   const double *__restrict__ cbuf, const double *__restrict__ tbuf,
+                                                   const double *__restrict__ diag0, int *fail) {
+    __shared__ double X[kCb * kCbLd], Y[kCb * kCbLd], W[4 * kCb];
+    const int64_t ntl = (int64_t)nt * (nt + 1) / 2;
+    const int64_t first = p + 1 < nt ? (int64_t)(p + 1) * (p + 2) / 2 + (p + 1) : 0;
+    const int64_t tid = (blockIdx.x + first) % ntl;
+    int I = (int)((sqrt(8.0 * (double)tid + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(I + 1) * (I + 2) / 2 <= tid) ++I;
+    while ((int64_t)I * (I + 1) / 2 > tid) --I;
+    const int J = (int)(tid - (int64_t)I * (I + 1) / 2);
+    const int64_t r0 = (int64_t)I * kCb, c0 = (int64_t)J * kCb;
+    const int tb = threadIdx.x & 63, ta = threadIdx.x >> 6;  // element (ta + 4 q, tb)
+    if (I == p || J == p) {
+        // pivot tile P; row p: T_J; column p: -T_I^T (transposed through LDS)
+        const double *src = I == p && J == p ? P : tbuf + (int64_t)(I == p ? J : I) * kCb * kCb;
+        double v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = src[(ta + 4 * q) * kCb + tb];
+        if (J == p && I != p) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) X[(ta + 4 * q) * kCbLd + tb] = v[q];
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = -X[tb * kCbLd + ta + 4 * q];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) A[(r0 + ta + 4 * q) * ld + c0 + tb] = v[q];
+        return;
+    }
+    // all loads before the first LDS store
+    const double *xi = cbuf + (int64_t)I * kCb * kCb, *yj = tbuf + (int64_t)J * kCb * kCb;
+    double sr[16], xr[16], yr[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        xr[q] = xi[(ta + 4 * q) * kCb + tb];
+        yr[q] = yj[(ta + 4 * q) * kCb + tb];
+    }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int a = cb_row(b, v), c = cb_col(b);
+            sr[4 * b + v] = I == J ? diag_tile_at(A, ld, r0, a, c) : A[(r0 + a) * ld + c0 + c];
+        }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        X[(ta + 4 * q) * kCbLd + tb] = xr[q];
+        Y[(ta + 4 * q) * kCbLd + tb] = yr[q];
+    }
+    __syncthreads();
+    dbl4 acc[4];
+    cb_mfma(X, Y, acc);
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            sr[4 * b + v] -= acc[b][v];
+            A[(r0 + cb_row(b, v)) * ld + c0 + cb_col(b)] = sr[4 * b + v];
+        }
+    if (I == p + 1 && J == p + 1) {
+        __syncthreads();  // every wave is done with X
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) X[cb_row(b, v) * kCbLd + cb_col(b)] = sr[4 * b + v];
+        __syncthreads();
+        // the symmetric block from the lower half
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int a = ta + 4 * q;
+            Y[a * kCbLd + tb] = a >= tb ? X[a * kCbLd + tb] : X[tb * kCbLd + a];
+        }
+        __syncthreads();
+        const bool bad = pivot_inverse64(Y, W, diag0, r0, kdim);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) Pnext[(ta + 4 * q) * kCb + tb] = Y[(ta + 4 * q) * kCbLd + tb];
+        if (bad && threadIdx.x == 0) atomicOr(fail, 1);
+    }
+}
+
+// The final E^-1 from the lower tiles of the inverse X of the scaled matrix: F = S X S,
+// entry (i, j) from X's entry (max(i, j), min(i, j)), written to the dense array (both
+// triangles) and as the packed lower-triangle tiles of the solve; one workgroup per
+// lower tile of kCoarseTile^2.  The two scale factors are applied in index order, so the
+// dense result is exactly symmetric.
+__global__ __launch_bounds__(256) void k_einv_from_lower(int32_t k, int64_t ld, const double *__restrict__ scale,
+                                                         const double *__restrict__ X, double *__restrict__ einv,
+                                                         double *__restrict__ tiles) {
+    constexpr int T = kCoarseTile;
+    __shared__ double F[T][T + 1];
+    const int64_t tid = blockIdx.x;
+    int I = (int)((sqrt(8.0 * (double)tid + 1.0) - 1.0) * 0.5);
+    while ((int64_t)(I + 1) * (I + 2) / 2 <= tid) ++I;
+    while ((int64_t)I * (I + 1) / 2 > tid) --I;
+    const int J = (int)(tid - (int64_t)I * (I + 1) / 2);
+    double *out = tiles + tid * T * T;
+    for (int e = threadIdx.x; e < T * T; e += 256) {
+        const int a = e / T, b = e % T;
+        const int ra = I * T + a, cb = J * T + b;
+        double f = 0.0;
+        if (ra < k && cb < k) {
+            const int hi = max(ra, cb), lo = min(ra, cb);
+            f = (X[(int64_t)hi * ld + lo] * scale[lo]) * scale[hi];
+            einv[(int64_t)ra * ld + cb] = f;
+        }
+        out[e] = f;
+        F[a][b] = f;
+    }
+    if (I != J) {  // the mirrored tile (J, I) of the dense array, written row by row
+        __syncthreads();
+        for (int e = threadIdx.x; e < T * T; e += 256) {
+            const int a = e / T, b = e % T;
+            const int rb = J * T + a, ca = I * T + b;
+            if (rb < k && ca < k) einv[(int64_t)rb * ld + ca] = F[b][a];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- dense blocks
@@ -1715,7 +1967,7 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
             HT(keep(c, &c->kzt_idx, nkz));
             HT(keep(c, &c->kzt_val, nkz));
         }
-        const int64_t ld = ((int64_t)k + kNb - 1) / kNb * kNb;
+        const int64_t ld = ((int64_t)k + kCb - 1) / kCb * kCb;
         c->einv_ld = ld;
         double *eraw = nullptr, *ga = nullptr, *diag0 = nullptr, *pv = nullptr;
         HT(pool.tmp(&eraw, ld * ld));
@@ -1738,27 +1990,28 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         double *esc = nullptr;
         HT(pool.tmp(&diag0, ld));
         HT(pool.tmp(&esc, ld));
-        HT(pool.tmp(&pv, 2 * kNb * kNb));
+        HT(pool.tmp(&pv, 2 * kCb * kCb));
         hipLaunchKernelGGL(k_symmetrise, dim3(grid_for(ld * ld)), dim3(256), 0, s, k, ld, eraw, ga, diag0, esc);
         int *cfail = flags + 2;
         HT(hipMemsetAsync(cfail, 0, sizeof(int), s));
-        hipLaunchKernelGGL(k_gj_first_pivot, dim3(1), dim3(256), 0, s, ga, ld, k, diag0, pv, cfail);
-        const int nt = (int)(ld / kNb);
-        double *src = ga, *dst = c->einv;
-        if (nt % 2 == 0) std::swap(src, dst);  // the last sweep must land in c->einv
-        if (nt % 2 == 0)
-            HT(hipMemcpyAsync(src, ga, sizeof(double) * ld * ld, hipMemcpyDeviceToDevice, s));
+        const int nt = (int)(ld / kCb);
+        double *cbuf = nullptr, *tbuf = nullptr;
+        HT(pool.tmp(&cbuf, ld * kCb));
+        HT(pool.tmp(&tbuf, ld * kCb));
+        hipLaunchKernelGGL(k_cgj_first_pivot, dim3(1), dim3(256), 0, s, (const double *)ga, ld, k, diag0, pv, cfail);
         for (int p = 0; p < nt; ++p) {
-            hipLaunchKernelGGL(k_gj_sweep, dim3(nt * nt), dim3(256), 0, s, p, nt, src, dst, ld, k,
-                               pv + (p & 1) * kNb * kNb, pv + ((p + 1) & 1) * kNb * kNb, diag0, cfail);
-            std::swap(src, dst);
+            const double *pc = pv + (p & 1) * kCb * kCb;
+            hipLaunchKernelGGL(k_cgj_panel, dim3(nt), dim3(256), 0, s, p, (const double *)ga, ld, pc, cbuf, tbuf);
+            hipLaunchKernelGGL(k_cgj_sweep, dim3((unsigned)coarse_tile_count(nt)), dim3(256), 0, s, p, nt, ga, ld, k, pc,
+                               pv + ((p + 1) & 1) * kCb * kCb, (const double *)cbuf, (const double *)tbuf, diag0,
+                               cfail);
         }
-        // the lower-triangle tiles of E^-1 for the solve's coarse product
+        // E^-1 from the lower tiles, and its lower-triangle tiles for the solve's coarse product
         const int32_t cnt = (int32_t)((k + kCoarseTile - 1) / kCoarseTile);
         c->coarse_nt = cnt;
         if (!reuse) HT(keep(c, &c->einv_tiles, coarse_tile_count(cnt) * kCoarseTile * kCoarseTile));
-        hipLaunchKernelGGL(k_einv_finish, dim3((unsigned)coarse_tile_count(cnt)), dim3(256), 0, s, k, ld,
-                           (const double *)esc, c->einv, c->einv_tiles);
+        hipLaunchKernelGGL(k_einv_from_lower, dim3((unsigned)coarse_tile_count(cnt)), dim3(256), 0, s, k, ld,
+                           (const double *)esc, (const double *)ga, c->einv, c->einv_tiles);
         HT(hipGetLastError());
         if (!reuse) {
             HT(keep(c, &c->kzt_ptr, k + 1));
