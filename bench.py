@@ -48,10 +48,10 @@ SPMV_TRAFFIC = {
     "workload": "penny80",
     "sources": {
         "paper_2111_09294_amd/csrc/kernels.hip": "dc2ae2e14214258d29f769016406806cbe8bbb06c4240bf4d921317530390352",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "191409ded8ffbb25eb66c56190de9ee7f3f66541fb7450a2b1e4643e3da26391"
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "0ffa9fdd2e38941fa00f9df5b975557cacd493c80a43440d93447827a9babc47"
     },
-    "fetch_bytes": 1482832100,
-    "write_bytes": 15991136,
+    "fetch_bytes": 1482744798,
+    "write_bytes": 15988739,
 }
 SPMV_SOURCES = ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h")
 
