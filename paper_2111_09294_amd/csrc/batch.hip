@@ -68,127 +68,291 @@ __device__ __forceinline__ double group_sum_8(double v, double (*lds)[W]) {
 
 // MODE 0: y = K x and partials of x_j^T y_j (column-major: part[j * gridDim.x + wg]).
 // MODE 1: y = f - K x and partials of ||y_j||^2 (row-major: part[wg * W + j]).
-// One wave per block row.  The row's values are contiguous (nine planes of m values),
-// so they are staged through wave-private LDS in chunks of 64 blocks with coalesced
-// loads (lane l loads block l of every plane) together with the column indices; the
-// products then read them back as LDS broadcasts.  Lane (bg, cq) = (lane >> 3, lane & 7)
-// takes every eighth block of the chunk starting at bg (kSpmmSteps blocks at a time) and the
-// four columns col4(cq, t): each 16-byte load of an x row by the eight lanes cq covers
-// one whole 128-byte half of the 256-byte row.  The eight block groups are added by a
-// fixed shuffle tree, so each column's sum has the same order for every lane mapping.
+// One wave per slot of two consecutive block rows (2 s, 2 s + 1).  A row's values are
+// contiguous (nine planes of m values), so they are staged through wave-private LDS with
+// coalesced loads (lane l loads block l of every plane) together with the column
+// indices, and read back as LDS broadcasts.  Lane (bg, cq) = (lane >> 3, lane & 7) takes
+// every eighth entry starting at bg (kSpmmSteps at a time) and the four columns
+// col4(cq, t): each 16-byte load of an x row by the eight lanes cq covers one whole
+// 128-byte half of the 256-byte row.  When both rows of a slot have at most kPairMax
+// blocks (a "pair", most of the matrix), the wave walks the merged list of their block
+// columns (built once per workspace by k_pair_merge) and applies every gathered x row to
+// each row that has a block there: consecutive rows share about two thirds of their
+// columns, so a pair gathers about a third fewer x rows than its two rows one by one,
+// and the gathers bound this kernel.  Other slots run their rows one after the other in
+// chunks of 64 blocks.  The eight block groups of a row are added by a fixed shuffle
+// tree, so every result is deterministic.
 __device__ __forceinline__ int col4(int cq, int t) { return (t >> 1) * 16 + 2 * cq + (t & 1); }
 
 constexpr int kSpmmChunk = 64;
-constexpr int kSpmmSteps = 2;  // blocks per lane whose x rows are loaded together
+constexpr int kSpmmSteps = 2;  // entries per lane whose x rows are loaded together
+constexpr int kPairMax = 64;   // blocks per row of a pair
+constexpr int kPairCap = 128;  // merged columns of a pair (stride of the merged lists)
+constexpr int kNoBlock = 255;  // "no block of this row at this column" in a merged entry
+constexpr int kSpmmWaves = 4;  // waves (slots) per workgroup
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// the lane's four columns of the three x rows of block column c
+__device__ __forceinline__ void load_x3(const double *__restrict__ x, int32_t c, int cq, double (&xv)[3][4]) {
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+        const double *xr = x + (3 * (int64_t)c + jj) * W + 2 * cq;
+        const double2 lo = *(const double2 *)xr, hi = *(const double2 *)(xr + 16);
+        xv[jj][0] = lo.x;
+        xv[jj][1] = lo.y;
+        xv[jj][2] = hi.x;
+        xv[jj][3] = hi.y;
+    }
+}
+
+// a += block k of the staged planes sv times xv
+__device__ __forceinline__ void block_fma(const double (*sv)[kSpmmChunk], int k, const double (&xv)[3][4],
+                                          double (&a)[3][4]) {
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double v = sv[3 * i + jj][k];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a[i][t] = fma(v, xv[jj][t], a[i][t]);
+        }
+}
+
+// the row's result from the lane groups' sums: y rows (MODE), and the dot partials
+template <int MODE>
+__device__ __forceinline__ void finish_row(double (&a)[3][4], int row, int bg, int cq, const double *__restrict__ x,
+                                           const double *__restrict__ f, double *__restrict__ y, double (&acc)[4]) {
+#pragma unroll
+    for (int off = 8; off < 64; off <<= 1)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a[i][t] += __shfl_xor(a[i][t], off);
+    if (bg == 0) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const int64_t o = (3 * (int64_t)row + i) * W;
+            double out[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int64_t oj = o + col4(cq, t);
+                if (MODE == 0) {
+                    out[t] = a[i][t];
+                    acc[t] = fma(x[oj], out[t], acc[t]);
+                } else {
+                    out[t] = f[oj] - a[i][t];
+                    acc[t] = fma(out[t], out[t], acc[t]);
+                }
+            }
+            *(double2 *)(y + o + 2 * cq) = make_double2(out[0], out[1]);
+            *(double2 *)(y + o + 16 + 2 * cq) = make_double2(out[2], out[3]);
+        }
+    }
+}
+
+// one row in chunks of 64 blocks (sv, sc: the wave's LDS)
+template <int MODE>
+__device__ __forceinline__ void single_row(int row, const int32_t *__restrict__ brow_ptr,
+                                           const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+                                           const double *__restrict__ x, const double *__restrict__ f,
+                                           double *__restrict__ y, double (*sv)[kSpmmChunk], int32_t *sc, int lane,
+                                           double (&acc)[4]) {
+    const int bg = lane >> 3, cq = lane & 7;
+    const int beg = brow_ptr[row], end = brow_ptr[row + 1];
+    const int64_t m = end - beg;
+    const double *rv = bval + 9 * (int64_t)beg;  // plane e of block beg + i: rv[e * m + i]
+    double a[3][4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[i][t] = 0.0;
+    for (int c0 = 0; c0 < m; c0 += kSpmmChunk) {
+        const int cnt = m - c0 < kSpmmChunk ? (int)(m - c0) : kSpmmChunk;
+        if (lane < cnt) {
+            double v[9];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) v[e] = rv[e * m + c0 + lane];
+            sc[lane] = bcol[beg + c0 + lane];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) sv[e][lane] = v[e];
+        }
+        wave_lds_sync();  // the wave's own LDS writes complete before its reads below
+        for (int k0 = bg; k0 < cnt; k0 += 8 * kSpmmSteps) {
+            double xv[kSpmmSteps][3][4];
+#pragma unroll
+            for (int h = 0; h < kSpmmSteps; ++h) {
+                const int k = k0 + 8 * h;
+                if (k < cnt) load_x3(x, sc[k], cq, xv[h]);
+            }
+#pragma unroll
+            for (int h = 0; h < kSpmmSteps; ++h)
+                if (k0 + 8 * h < cnt) block_fma(sv, k0 + 8 * h, xv[h], a);
+        }
+        wave_lds_sync();  // every lane is done reading this chunk before the next one is written
+    }
+    finish_row<MODE>(a, row, bg, cq, x, f, y, acc);
+}
 
 template <int MODE>
-__global__ __launch_bounds__(256) void k_bspmm(int32_t nb, const int32_t *__restrict__ brow_ptr,
+__global__ __launch_bounds__(64 * kSpmmWaves) void k_bspmm(int32_t nb, const int32_t *__restrict__ brow_ptr,
                                                const int32_t *__restrict__ bcol, const double *__restrict__ bval,
-                                               const double *__restrict__ x, const double *__restrict__ f,
-                                               double *__restrict__ y, double *__restrict__ part,
-                                               const BatchState *st) {
-    __shared__ double lds[4][W];
-    __shared__ double sv[4][9][kSpmmChunk];
-    __shared__ int32_t sc[4][kSpmmChunk];
+                                               const int32_t *__restrict__ pair_len,
+                                               const int32_t *__restrict__ pair_col,
+                                               const uint16_t *__restrict__ pair_ab, const double *__restrict__ x,
+                                               const double *__restrict__ f, double *__restrict__ y,
+                                               double *__restrict__ part, const BatchState *st) {
+    __shared__ double lds[kSpmmWaves][W];
+    __shared__ double sv[kSpmmWaves][2][9][kSpmmChunk];
+    __shared__ int32_t sc[kSpmmWaves][kPairCap];
+    __shared__ uint16_t sab[kSpmmWaves][kPairCap];
     if (st && !st->any) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, bg = lane >> 3, cq = lane & 7;
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int row = w * 4 + wv;
-    if (row < nb) {
-        const int beg = brow_ptr[row], end = brow_ptr[row + 1];
-        const int64_t m = end - beg;
-        const double *rv = bval + 9 * (int64_t)beg;  // plane e of block beg + i: rv[e * m + i]
-        double a[3][4];
+    const int slot = w * kSpmmWaves + wv, ra = 2 * slot, rb = ra + 1;
+    const int u = ra < nb ? pair_len[slot] : 0;  // merged columns of a pair, 0 otherwise
+    if (u > 0) {
+        const int ba = brow_ptr[ra], bb = brow_ptr[rb], eb = brow_ptr[rb + 1];
+        const int ma = bb - ba, mb = eb - bb;
+        const double *rva = bval + 9 * (int64_t)ba, *rvb = bval + 9 * (int64_t)bb;
+        {
+            double va[9], vb[9];
+            int32_t c0 = 0, c1 = 0;
+            uint16_t a0 = 0, a1 = 0;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) {
+                va[e] = lane < ma ? rva[e * ma + lane] : 0.0;
+                vb[e] = lane < mb ? rvb[e * mb + lane] : 0.0;
+            }
+            const int64_t mo = (int64_t)slot * kPairCap;
+            if (lane < u) {
+                c0 = pair_col[mo + lane];
+                a0 = pair_ab[mo + lane];
+            }
+            if (lane + 64 < u) {
+                c1 = pair_col[mo + 64 + lane];
+                a1 = pair_ab[mo + 64 + lane];
+            }
+#pragma unroll
+            for (int e = 0; e < 9; ++e) {
+                sv[wv][0][e][lane] = va[e];
+                sv[wv][1][e][lane] = vb[e];
+            }
+            sc[wv][lane] = c0;
+            sab[wv][lane] = a0;
+            sc[wv][64 + lane] = c1;
+            sab[wv][64 + lane] = a1;
+        }
+        wave_lds_sync();
+        double aa[3][4], ab[3][4];
 #pragma unroll
         for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int t = 0; t < 4; ++t) a[i][t] = 0.0;
-        for (int c0 = 0; c0 < m; c0 += kSpmmChunk) {
-            const int cnt = m - c0 < kSpmmChunk ? (int)(m - c0) : kSpmmChunk;
-            if (lane < cnt) {
-                double v[9];
+            for (int t = 0; t < 4; ++t) aa[i][t] = ab[i][t] = 0.0;
+        for (int k0 = bg; k0 < u; k0 += 8 * kSpmmSteps) {
+            double xv[kSpmmSteps][3][4];
 #pragma unroll
-                for (int e = 0; e < 9; ++e) v[e] = rv[e * m + c0 + lane];
-                sc[wv][lane] = bcol[beg + c0 + lane];
-#pragma unroll
-                for (int e = 0; e < 9; ++e) sv[wv][e][lane] = v[e];
+            for (int h = 0; h < kSpmmSteps; ++h) {
+                const int k = k0 + 8 * h;
+                if (k < u) load_x3(x, sc[wv][k], cq, xv[h]);
             }
-            // the wave's own LDS writes complete before its reads below
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            for (int k0 = bg; k0 < cnt; k0 += 8 * kSpmmSteps) {
-                double xv[kSpmmSteps][3][4];
 #pragma unroll
-                for (int h = 0; h < kSpmmSteps; ++h) {
-                    const int k = k0 + 8 * h < cnt ? k0 + 8 * h : k0;
-                    const int64_t c = 3 * (int64_t)sc[wv][k];
-#pragma unroll
-                    for (int jj = 0; jj < 3; ++jj) {
-                        const double *xr = x + (c + jj) * W + 2 * cq;
-                        const double2 lo = *(const double2 *)xr, hi = *(const double2 *)(xr + 16);
-                        xv[h][jj][0] = lo.x;
-                        xv[h][jj][1] = lo.y;
-                        xv[h][jj][2] = hi.x;
-                        xv[h][jj][3] = hi.y;
-                    }
+            for (int h = 0; h < kSpmmSteps; ++h) {
+                const int k = k0 + 8 * h;
+                if (k < u) {
+                    const int e = sab[wv][k], ia = e & 255, ib = e >> 8;
+                    if (ia != kNoBlock) block_fma(sv[wv][0], ia, xv[h], aa);
+                    if (ib != kNoBlock) block_fma(sv[wv][1], ib, xv[h], ab);
                 }
-#pragma unroll
-                for (int h = 0; h < kSpmmSteps; ++h)
-                    if (k0 + 8 * h < cnt) {
-                        const int k = k0 + 8 * h;
-#pragma unroll
-                        for (int jj = 0; jj < 3; ++jj)
-#pragma unroll
-                            for (int i = 0; i < 3; ++i) {
-                                const double v = sv[wv][3 * i + jj][k];
-#pragma unroll
-                                for (int t = 0; t < 4; ++t) a[i][t] = fma(v, xv[h][jj][t], a[i][t]);
-                            }
-                    }
-            }
-            // every lane is done reading this chunk before the next one is written
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        }
-#pragma unroll
-        for (int off = 8; off < 64; off <<= 1)
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) a[i][t] += __shfl_xor(a[i][t], off);
-        if (bg == 0) {
-#pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const int64_t o = (3 * (int64_t)row + i) * W;
-                double out[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int64_t oj = o + col4(cq, t);
-                    if (MODE == 0) {
-                        out[t] = a[i][t];
-                        acc[t] = fma(x[oj], out[t], acc[t]);
-                    } else {
-                        out[t] = f[oj] - a[i][t];
-                        acc[t] = fma(out[t], out[t], acc[t]);
-                    }
-                }
-                *(double2 *)(y + o + 2 * cq) = make_double2(out[0], out[1]);
-                *(double2 *)(y + o + 16 + 2 * cq) = make_double2(out[2], out[3]);
             }
         }
+        finish_row<MODE>(aa, ra, bg, cq, x, f, y, acc);
+        finish_row<MODE>(ab, rb, bg, cq, x, f, y, acc);
+    } else {
+        if (ra < nb) single_row<MODE>(ra, brow_ptr, bcol, bval, x, f, y, sv[wv][0], sc[wv], lane, acc);
+        if (rb < nb) single_row<MODE>(rb, brow_ptr, bcol, bval, x, f, y, sv[wv][0], sc[wv], lane, acc);
     }
     if (bg == 0)
 #pragma unroll
         for (int t = 0; t < 4; ++t) lds[wv][col4(cq, t)] = acc[t];
     __syncthreads();
     if (threadIdx.x < W) {
-        const double v = (lds[0][threadIdx.x] + lds[1][threadIdx.x]) + (lds[2][threadIdx.x] + lds[3][threadIdx.x]);
+        double v = lds[0][threadIdx.x];
+#pragma unroll
+        for (int h = 1; h < kSpmmWaves; ++h) v += lds[h][threadIdx.x];
         if (MODE == 0) part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = v;
         else part[(int64_t)blockIdx.x * W + threadIdx.x] = v;
     }
+}
+
+// The merged block-column list of slot s = (rows 2 s, 2 s + 1), one wave per slot, when
+// both rows have at most kPairMax blocks: the columns of either row in increasing order,
+// each once, with the block's index in row 2 s (low byte) and in row 2 s + 1 (high byte),
+// kNoBlock where the row has none; pair_len[s] = their number (0: not a pair).  A row's
+// columns are strictly increasing (a checked input property), so the position of a
+// column in the merged list is the number of distinct columns of both rows below it.
+__global__ __launch_bounds__(256) void k_pair_merge(int32_t nb, const int32_t *__restrict__ brow_ptr,
+                                                    const int32_t *__restrict__ bcol, int32_t nslots,
+                                                    int32_t *__restrict__ pair_len, int32_t *__restrict__ pair_col,
+                                                    uint16_t *__restrict__ pair_ab) {
+    __shared__ int32_t ca[4][64], cb[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int s = blockIdx.x * 4 + wv;
+    if (s >= nslots) return;  // no barrier below: waves leave independently
+    const int ra = 2 * s, rb = ra + 1;
+    int ma = 0, mb = 0, ba = 0, bb = 0;
+    if (rb < nb) {
+        ba = brow_ptr[ra];
+        bb = brow_ptr[rb];
+        ma = bb - ba;
+        mb = brow_ptr[rb + 1] - bb;
+    }
+    if (rb >= nb || ma > kPairMax || mb > kPairMax) {
+        if (lane == 0) pair_len[s] = 0;
+        return;
+    }
+    const int32_t a = lane < ma ? bcol[ba + lane] : INT32_MAX;
+    const int32_t b = lane < mb ? bcol[bb + lane] : INT32_MAX;
+    ca[wv][lane] = a;
+    cb[wv][lane] = b;
+    wave_lds_sync();
+    // lower bounds: lt_b = #{b_j < a}, lt_a = #{a_i < b}
+    int lo = 0, hi = mb;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cb[wv][mid] < a) lo = mid + 1;
+        else hi = mid;
+    }
+    const int lt_b = lo;
+    lo = 0;
+    hi = ma;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ca[wv][mid] < b) lo = mid + 1;
+        else hi = mid;
+    }
+    const int lt_a = lo;
+    const bool a_in_b = lane < ma && lt_b < mb && cb[wv][lt_b] == a;
+    const bool b_in_a = lane < mb && lt_a < ma && ca[wv][lt_a] == b;
+    const uint64_t dup = __ballot(b_in_a);
+    auto below = [&](int n) { return n >= 64 ? __popcll(dup) : __popcll(dup & ((1ull << n) - 1)); };
+    const int64_t mo = (int64_t)s * kPairCap;
+    if (lane < ma) {
+        const int pos = lane + lt_b - below(lt_b);
+        pair_col[mo + pos] = a;
+        pair_ab[mo + pos] = (uint16_t)(lane | ((a_in_b ? lt_b : kNoBlock) << 8));
+    }
+    if (lane < mb && !b_in_a) {
+        const int pos = lt_a + lane - below(lane);
+        pair_col[mo + pos] = b;
+        pair_ab[mo + pos] = (uint16_t)(kNoBlock | (lane << 8));
+    }
+    if (lane == 0) pair_len[s] = ma + mb - __popcll(dup);
 }
 
 // Fixed-order sum of column j of column-major partials (nparts per column) by one
@@ -814,7 +978,13 @@ int ensure_ws(dpcg_ctx *c) {
     BTRY(balloc(c, &b->p, nw));
     BTRY(balloc(c, &b->g, kw));
     BTRY(balloc(c, &b->delta, kw));
-    b->spmm_nwg = grid_rows(c->nb, 4, 1 << 30);
+    const int64_t nslots = (c->nb + 1) / 2;
+    b->spmm_nwg = grid_rows(nslots, kSpmmWaves, 1 << 30);
+    BTRY(balloc(c, &b->pair_len, (size_t)nslots));
+    BTRY(balloc(c, &b->pair_col, (size_t)nslots * kPairCap));
+    BTRY(balloc(c, &b->pair_ab, (size_t)nslots * kPairCap));
+    BLAUNCH(k_pair_merge, dim3((unsigned)((nslots + 3) / 4)), dim3(256), 0, c->stream, c->nb, c->brow_ptr, c->bcol,
+            (int32_t)nslots, b->pair_len, b->pair_col, b->pair_ab);
     b->upd_nwg = grid_rows(c->bjb_ntiles, 1, 2048);
     b->vec_nwg = grid_rows(c->n, 32, 4096);
     const size_t np = (size_t)std::max({b->spmm_nwg, b->upd_nwg, b->vec_nwg}) * W;
@@ -993,7 +1163,8 @@ int enqueue_bstart(dpcg_ctx *c, bool guess, int max_iter) {
         BTRY(enqueue_coarse(c, nullptr));
         BTRY(enqueue_prolong(c, guess ? b->u : nullptr, b->u, nullptr, nullptr, 0));
     }
-    BLAUNCH(k_bspmm<1>, dim3(b->spmm_nwg), dim3(256), 0, c->stream, c->nb, c->brow_ptr, c->bcol, c->bval,
+    BLAUNCH(k_bspmm<1>, dim3(b->spmm_nwg), dim3(64 * kSpmmWaves), 0, c->stream, c->nb, c->brow_ptr, c->bcol, c->bval,
+            (const int32_t *)b->pair_len, (const int32_t *)b->pair_col, (const uint16_t *)b->pair_ab,
             (const double *)b->u, (const double *)b->f, b->r, b->part2, (const BatchState *)st);
     BLAUNCH(k_bupdate_bj, dim3(b->upd_nwg), dim3(256), 0, c->stream, c->bjb_ntiles, b->upd_nwg, c->bjb_start, b->u,
             b->r, b->y, (const double *)b->q, (const double *)b->p, (const double *)c->minv, c->bj_rowoff, c->bj_meta,
@@ -1022,9 +1193,10 @@ int enqueue_biteration(dpcg_ctx *c, int max_iter, std::vector<hipEvent_t> &ev, s
         e1 = ev[ev_used + 1];
         ev_used += 2;
     }
-    hipExtLaunchKernelGGL(k_bspmm<0>, dim3(b->spmm_nwg), dim3(256), 0, c->stream, e0, e1, 0, c->nb, c->brow_ptr,
-                          c->bcol, (const double *)c->bval, (const double *)b->p, (const double *)nullptr, b->q,
-                          b->part, (const BatchState *)st);
+    hipExtLaunchKernelGGL(k_bspmm<0>, dim3(b->spmm_nwg), dim3(64 * kSpmmWaves), 0, c->stream, e0, e1, 0, c->nb, c->brow_ptr,
+                          c->bcol, (const double *)c->bval, (const int32_t *)b->pair_len,
+                          (const int32_t *)b->pair_col, (const uint16_t *)b->pair_ab, (const double *)b->p,
+                          (const double *)nullptr, b->q, b->part, (const BatchState *)st);
     BHIP(hipGetLastError());
     BLAUNCH(k_balpha, dim3(W), dim3(1024), 0, c->stream, (const double *)b->part, b->spmm_nwg, st);
     BLAUNCH(k_bupdate_bj, dim3(b->upd_nwg), dim3(256), 0, c->stream, c->bjb_ntiles, b->upd_nwg, c->bjb_start, b->u,
@@ -1117,7 +1289,8 @@ int solve_batch(dpcg_ctx *c, int32_t nrhs, const double *F, double *U, double to
     }
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     // true residuals f_j - K u_j
-    BLAUNCH(k_bspmm<1>, dim3(b->spmm_nwg), dim3(256), 0, s, c->nb, c->brow_ptr, c->bcol, c->bval,
+    BLAUNCH(k_bspmm<1>, dim3(b->spmm_nwg), dim3(64 * kSpmmWaves), 0, s, c->nb, c->brow_ptr, c->bcol, c->bval,
+            (const int32_t *)b->pair_len, (const int32_t *)b->pair_col, (const uint16_t *)b->pair_ab,
             (const double *)b->u, (const double *)b->f, b->q, b->part2, (const BatchState *)nullptr);
     BLAUNCH(k_baux, dim3(1), dim3(1024), 0, s, (const double *)b->part2, (const double *)nullptr, b->spmm_nwg, b->st);
     BatchState fin;

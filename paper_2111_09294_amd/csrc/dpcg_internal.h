@@ -128,6 +128,11 @@ struct BatchWorkspace {
     BatchState *st = nullptr;                     // device
     BatchState *snap = nullptr;                   // pinned host mirror
     int32_t spmm_nwg = 0, upd_nwg = 0, vec_nwg = 0;
+    // the SpMM's slots of two consecutive block rows: pair_len[s] merged block columns
+    // when both rows of slot s are short (0 otherwise), the merged columns and each
+    // one's block indices in the two rows at pair_col / pair_ab[s * 128 ..]
+    int32_t *pair_len = nullptr, *pair_col = nullptr;
+    uint16_t *pair_ab = nullptr;
     // restriction segments: seg[4 s .. 4 s + 3] = (column, list 0 = Z^T / 1 = (KZ)^T, begin,
     // end), at most kBatchSegEntries entries each; column c owns segments
     // seg_ptr[c] .. seg_ptr[c + 1] - 1, whose partial sums are added in that order
