@@ -778,16 +778,21 @@ constexpr int kTouchLds = 2048;  // LDS words of the touched-vector bitmap (k <=
 
 struct KzBatch {
     int64_t j0, ncol, lo3, w3, off3, slice0, nslice, bit0;
+    int64_t moff;  // first triplet of the batch's window in the structure masks mk and rb
 };
 
+// clears the batch's touched bits and, when masks, its structure masks
 __global__ __launch_bounds__(256) void k_kzb_init(const KzBatch *__restrict__ bt, int words, uint32_t *__restrict__ mk,
-                                                  uint32_t *__restrict__ rb, uint32_t *__restrict__ touched) {
+                                                  uint32_t *__restrict__ rb, uint32_t *__restrict__ touched,
+                                                  int masks) {
     const KzBatch B = bt[blockIdx.y];
     if (blockIdx.x >= B.nslice) return;
     const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
     for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
-        mk[B.off3 + t] = 0u;
-        rb[B.off3 + t] = 0u;
+        if (masks) {
+            mk[B.moff + t] = 0u;
+            rb[B.moff + t] = 0u;
+        }
     }
     if (blockIdx.x == 0)
         for (int t = threadIdx.x; t < words; t += 256) touched[B.bit0 + t] = 0u;
@@ -814,7 +819,7 @@ __global__ __launch_bounds__(256) void k_kzb_scatter(const KzBatch *__restrict__
         const int64_t t = (int64_t)zti[e] - 3 * B.lo3;
         if (t < 0 || t >= 3 * B.w3) continue;
         zd[(3 * B.off3 + t) * kBatch + b] = ztv[e];
-        atomicOr(&rb[B.off3 + t / 3], 1u << b);
+        atomicOr(&rb[B.moff + t / 3], 1u << b);
     }
 }
 
@@ -834,13 +839,13 @@ __global__ __launch_bounds__(256) void k_kzb_mark(const KzBatch *__restrict__ bt
     if (blockIdx.x >= B.nslice) return;
     const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
     bool any = false;
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) any = any || rb[B.off3 + t] != 0u;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) any = any || rb[B.moff + t] != 0u;
     if (!__syncthreads_or(any)) return;
     for (int i = threadIdx.x; i < kMarkWindow; i += 256) win[i] = 0u;
     __syncthreads();
     const int64_t w0 = t0 - kMarkHalo;  // window column of win[0] (may be negative)
     for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
-        const uint32_t bits = rb[B.off3 + t];
+        const uint32_t bits = rb[B.moff + t];
         if (!bits) continue;
         const int64_t R = B.lo3 + t;
         for (int64_t q = bptr[R]; q < bptr[R + 1]; ++q) {
@@ -848,14 +853,14 @@ __global__ __launch_bounds__(256) void k_kzb_mark(const KzBatch *__restrict__ bt
             if (c < 0 || c >= B.w3) continue;
             const int64_t l = c - w0;
             if (l >= 0 && l < kMarkWindow) atomicOr(&win[l], bits);
-            else atomicOr(&mk[B.off3 + c], bits);
+            else atomicOr(&mk[B.moff + c], bits);
         }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kMarkWindow; i += 256) {
         const uint32_t v = win[i];
         const int64_t c = w0 + i;
-        if (v && c >= 0 && c < B.w3) atomicOr(&mk[B.off3 + c], v);
+        if (v && c >= 0 && c < B.w3) atomicOr(&mk[B.moff + c], v);
     }
 }
 
@@ -872,7 +877,7 @@ __global__ __launch_bounds__(256) void k_kzb_count(const KzBatch *__restrict__ b
     int32_t mine[kBatch + 1];
     for (int b = 0; b <= kBatch; ++b) mine[b] = 0;
     for (int64_t t = t0 + threadIdx.x; t < t1; t += 256) {
-        const uint32_t m = mk[B.off3 + t];
+        const uint32_t m = mk[B.moff + t];
         for (int b = 0; b < kBatch; ++b) mine[b] += 3 * ((m >> b) & 1u);
         mine[kBatch] += m != 0u;
     }
@@ -933,7 +938,7 @@ __global__ __launch_bounds__(256) void k_kzb_rank(const KzBatch *__restrict__ bt
     const int64_t t0 = (int64_t)blockIdx.x * kSlice, t1 = min<int64_t>(B.w3, t0 + kSlice);
     for (int64_t c0 = t0; c0 < t1; c0 += 256) {
         const int64_t t = c0 + threadIdx.x;
-        const uint32_t m = t < t1 ? mk[B.off3 + t] : 0u;
+        const uint32_t m = t < t1 ? mk[B.moff + t] : 0u;
         int32_t rank[kBatch + 1];
         for (int b = 0; b <= kBatch; ++b) {
             const bool f = b < kBatch ? ((m >> b) & 1u) : (m != 0u);
@@ -1006,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_kzb_values(const KzBatch *__restrict__ 
             for (int64_t q = beg + part; q < beg + mR; q += 4) {
                 const int64_t c = (int64_t)bcol[q] - B.lo3;
                 if (c < 0 || c >= B.w3) continue;
-                const uint32_t zb = rb[B.off3 + c] >> (4 * sub);
+                const uint32_t zb = rb[B.moff + c] >> (4 * sub);
                 if (!(zb & 15u)) continue;  // none of this lane's vectors has support on triplet c
                 double v[9];
                 for (int e = 0; e < 9; ++e) v[e] = rv[e * mR + (q - beg)];
@@ -1099,7 +1104,7 @@ __global__ __launch_bounds__(256) void k_kzb_erows(const KzBatch *__restrict__ b
     for (int b = 0; b < kBatch; ++b) acc[b] = 0.0;
     for (int64_t q = a + lane; q < e; q += 64) {
         const int64_t t = (int64_t)zti[q] - lo;
-        if (!mk[B.off3 + t / 3]) continue;  // (K z_j)_t is structurally zero for every vector of the batch
+        if (!mk[B.moff + t / 3]) continue;  // (K z_j)_t is structurally zero for every vector of the batch
         const double z = ztv[q];
         const double *kdr = kd + (3 * B.off3 + t) * kBatch;
         for (int b = 0; b < kBatch; ++b) acc[b] = fma(z, kdr[b], acc[b]);
@@ -1893,7 +1898,7 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         const int64_t per_triplet = 2 * 3 * kBatch * sizeof(double) + 2 * sizeof(uint32_t);
         const int64_t budget = int64_t(1) << 30;
         std::vector<int> gcut{0};
-        int64_t acc_w = 0, max_group_w = 0;
+        int64_t acc_w = 0, max_group_w = 0, total_w = 0;
         int max_group_nb = 0;
         for (int bi = 0; bi < nbat; ++bi) {
             if (acc_w > 0 && (acc_w + bt[bi].w3) * per_triplet > budget) {
@@ -1901,6 +1906,8 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
                 acc_w = 0;
             }
             bt[bi].off3 = acc_w;
+            bt[bi].moff = total_w;
+            total_w += bt[bi].w3;
             bt[bi].bit0 = (int64_t)(bi - gcut.back()) * words;
             acc_w += bt[bi].w3;
             max_group_w = std::max(max_group_w, acc_w);
@@ -1921,8 +1928,10 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         HT(pool.tmp(&kzp, k + 1));
         HT(pool.tmp(&zd, 3 * max_group_w * kBatch));
         HT(pool.tmp(&kd, 3 * max_group_w * kBatch));
-        HT(pool.tmp(&mk, max_group_w));
-        HT(pool.tmp(&rbits, max_group_w));
+        // the structure masks of every batch at once (4 bytes per window triplet each):
+        // the values pass of a call with several groups then needs no second marking
+        HT(pool.tmp(&mk, std::max<int64_t>(1, total_w)));
+        HT(pool.tmp(&rbits, std::max<int64_t>(1, total_w)));
         HT(pool.tmp(&touched, (int64_t)max_group_nb * words));
         int32_t *icnt = nullptr;
         int64_t *nitems = nullptr;
@@ -1935,15 +1944,18 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
             for (int bi = g0; bi < g1; ++bi) m = std::max(m, bt[bi].nslice);
             return (int)m;
         };
-        auto prepare = [&](int g0, int g1) {
+        // full: the count pass (masks cleared, z scattered, structure marked); otherwise the
+        // values pass of a later group, which only needs its z rows again (the scatter's
+        // bits are already in rbits) and clear touched bits
+        auto prepare = [&](int g0, int g1, bool full) {
             const dim3 gs(max_slices(g0, g1), g1 - g0);
-            hipLaunchKernelGGL(k_kzb_init, gs, dim3(256), 0, s, bt_d + g0, words, mk, rbits, touched);
+            hipLaunchKernelGGL(k_kzb_init, gs, dim3(256), 0, s, bt_d + g0, words, mk, rbits, touched, full ? 1 : 0);
             hipLaunchKernelGGL(k_kzb_scatter, dim3(kBatch, g1 - g0), dim3(256), 0, s, bt_d + g0, ztp, zti, ztv, zd,
                                rbits);
-            hipLaunchKernelGGL(k_kzb_mark, gs, dim3(256), 0, s, bt_d + g0, c->brow_ptr, c->bcol, rbits, mk);
+            if (full) hipLaunchKernelGGL(k_kzb_mark, gs, dim3(256), 0, s, bt_d + g0, c->brow_ptr, c->bcol, rbits, mk);
         };
         for (size_t g = 0; g + 1 < gcut.size(); ++g) {
-            prepare(gcut[g], gcut[g + 1]);
+            prepare(gcut[g], gcut[g + 1], true);
             hipLaunchKernelGGL(k_kzb_count, dim3(max_slices(gcut[g], gcut[g + 1]), gcut[g + 1] - gcut[g]), dim3(256),
                                0, s, bt_d + gcut[g], mk, scnt, tcnt);
         }
@@ -1974,7 +1986,7 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         HT(hipMemsetAsync(eraw, 0, sizeof(double) * ld * ld, s));
         for (size_t g = 0; g + 1 < gcut.size(); ++g) {
             const int g0 = gcut[g], g1 = gcut[g + 1];
-            if (gcut.size() > 2) prepare(g0, g1);  // one group: the count pass left it ready
+            if (gcut.size() > 2) prepare(g0, g1, false);  // one group: the count pass left it ready
             hipLaunchKernelGGL(k_kzb_rank, dim3(max_slices(g0, g1), g1 - g0), dim3(256), 0, s, bt_d + g0, mk, soff,
                                icnt, kzp, items);
             hipLaunchKernelGGL(k_kzb_values, dim3(512, g1 - g0), dim3(256),
