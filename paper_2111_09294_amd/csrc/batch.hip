@@ -402,7 +402,13 @@ __global__ __launch_bounds__(1024) void k_balpha(const double *__restrict__ part
 
 // update = 1: u_j += alpha_j p_j and r_j -= alpha_j q_j for the running columns, with
 // partials of ||r_j||^2; then (both modes) y = M^{-1} r over the tile's whole blocks
-// from an LDS copy of r.  One workgroup per contiguous range of tiles.
+// from an LDS copy of r.  One workgroup per contiguous range of tiles.  A tile's block
+// inverses are one contiguous range of minv (whole blocks), staged in LDS with coalesced
+// loads when it fits in kBjStage entries (3 x 3 blocks: 3 per DoF), so the product reads
+// broadcast LDS words instead of broadcast global loads; each DoF's row offset, block size
+// and position go packed into one LDS word.
+constexpr int kBjStage = 480;
+
 __global__ __launch_bounds__(256) void k_bupdate_bj(int32_t ntiles, int32_t nwg, const int32_t *__restrict__ tile_start,
                                                     double *__restrict__ u, double *__restrict__ r,
                                                     double *__restrict__ y, const double *__restrict__ q,
@@ -411,7 +417,9 @@ __global__ __launch_bounds__(256) void k_bupdate_bj(int32_t ntiles, int32_t nwg,
                                                     const int32_t *__restrict__ bj_meta, double *__restrict__ part,
                                                     const BatchState *st, int update) {
     __shared__ double tile[kBatchTileDofs][W];
-    __shared__ double lds[8][W];
+    __shared__ double mv[kBjStage];  // also the 8 x W doubles of the final group sum
+    __shared__ int32_t md[kBatchTileDofs];
+    static_assert(kBjStage >= 8 * W && kBatchTileDofs * kMaxBlock < (1 << 21) && kMaxBlock < 32, "packing");
     if (!st->any) return;
     const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
     const bool run = update && st->flag[j] == kRunning;
@@ -421,7 +429,16 @@ __global__ __launch_bounds__(256) void k_bupdate_bj(int32_t ntiles, int32_t nwg,
     double acc = 0.0;
     for (int t = t0; t < t1; ++t) {
         const int64_t d0 = tile_start[t], d1 = tile_start[t + 1];
+        if (d1 <= d0) continue;  // uniform: the last tile can be empty
+        const int32_t m0 = bj_rowoff[d0], m1 = bj_rowoff[d1 - 1] + (bj_meta[d1 - 1] >> 8);
+        const bool staged = m1 - m0 <= kBjStage;
         __syncthreads();
+        if (staged)
+            for (int e = threadIdx.x; e < m1 - m0; e += blockDim.x) mv[e] = minv[m0 + e];
+        if (threadIdx.x < d1 - d0) {
+            const int mt = bj_meta[d0 + threadIdx.x];
+            md[threadIdx.x] = ((bj_rowoff[d0 + threadIdx.x] - m0) << 10) | ((mt >> 8) << 5) | (mt & 255);
+        }
         // four DoFs of the group at a time: all loads first, then the updates
         for (int64_t db = d0 + g; db < d1; db += 32) {
             double rv[4], pv[4], qv[4], uv[4];
@@ -454,27 +471,23 @@ __global__ __launch_bounds__(256) void k_bupdate_bj(int32_t ntiles, int32_t nwg,
         }
         __syncthreads();
         for (int64_t db = d0 + g; db < d1; db += 32) {
-            int meta[4], ro[4];
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                const int64_t d = db + 8 * h;
-                meta[h] = d < d1 ? bj_meta[d] : 0;
-                ro[h] = d < d1 ? bj_rowoff[d] : 0;
-            }
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
                 const int64_t d = db + 8 * h;
                 if (d >= d1) continue;
-                const int size = meta[h] >> 8, loc = meta[h] & 255;
-                const double *mrow = minv + ro[h];
-                const int base = (int)(d - d0) - loc;
+                const int mt = md[d - d0], size = (mt >> 5) & 31, ro = mt >> 10;
+                const int base = (int)(d - d0) - (mt & 31);
                 double s = 0.0;
-                for (int kk = 0; kk < size; ++kk) s = fma(mrow[kk], tile[base + kk][j], s);
+                if (staged)
+                    for (int kk = 0; kk < size; ++kk) s = fma(mv[ro + kk], tile[base + kk][j], s);
+                else
+                    for (int kk = 0; kk < size; ++kk) s = fma(minv[m0 + ro + kk], tile[base + kk][j], s);
                 y[d * W + j] = s;
             }
         }
     }
-    const double tot = group_sum_8(acc, lds);
+    __syncthreads();  // the last tile's reads of mv precede its reuse
+    const double tot = group_sum_8(acc, reinterpret_cast<double(*)[W]>(mv));
     if (update && threadIdx.x < W) part[(int64_t)blockIdx.x * W + threadIdx.x] = tot;
 }
 
