@@ -79,8 +79,10 @@ __device__ __forceinline__ double group_sum_8(double v, double (*lds)[W]) {
 // columns (built once per workspace by k_pair_merge) and applies every gathered x row to
 // each row that has a block there: consecutive rows share about two thirds of their
 // columns, so a pair gathers about a third fewer x rows than its two rows one by one,
-// and the gathers bound this kernel.  Other slots run their rows one after the other in
-// chunks of 64 blocks.  The eight block groups of a row are added by a fixed shuffle
+// and the gathers bound this kernel.  Longer rows with the same block columns ("twins":
+// the block rows of one enriched node, about a fifth of the blocks) walk their common
+// list in chunks of 64 blocks, each gathered x row serving both.  Other slots run their
+// rows one after the other in chunks of 64 blocks.  The eight block groups of a row are added by a fixed shuffle
 // tree, so every result is deterministic.
 __device__ __forceinline__ int col4(int cq, int t) { return (t >> 1) * 16 + 2 * cq + (t & 1); }
 
@@ -198,8 +200,52 @@ __device__ __forceinline__ void single_row(int row, const int32_t *__restrict__ 
     finish_row<MODE>(a, row, bg, cq, x, f, y, acc);
 }
 
+// rows ra and ra + 1 with the same block columns, in chunks of 64 blocks: each gathered
+// x row serves both rows, and each row sums its blocks in single_row's order
 template <int MODE>
-__global__ __launch_bounds__(64 * kSpmmWaves) void k_bspmm(int32_t nb, const int32_t *__restrict__ brow_ptr,
+__device__ __forceinline__ void twin_rows(int ra, const int32_t *__restrict__ brow_ptr,
+                                          const int32_t *__restrict__ bcol, const double *__restrict__ bval,
+                                          const double *__restrict__ x, const double *__restrict__ f,
+                                          double *__restrict__ y, double (*sv)[9][kSpmmChunk], int32_t *sc, int lane,
+                                          double (&acc)[4]) {
+    const int bg = lane >> 3, cq = lane & 7;
+    const int ba = brow_ptr[ra], bb = brow_ptr[ra + 1];
+    const int64_t m = bb - ba;  // the length of both rows
+    const double *rva = bval + 9 * (int64_t)ba, *rvb = bval + 9 * (int64_t)bb;
+    double aa[3][4], ab[3][4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) aa[i][t] = ab[i][t] = 0.0;
+    for (int c0 = 0; c0 < m; c0 += kSpmmChunk) {
+        const int cnt = m - c0 < kSpmmChunk ? (int)(m - c0) : kSpmmChunk;
+        if (lane < cnt) {
+            double v[9];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) v[e] = rva[e * m + c0 + lane];
+            sc[lane] = bcol[ba + c0 + lane];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) sv[0][e][lane] = v[e];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) v[e] = rvb[e * m + c0 + lane];
+#pragma unroll
+            for (int e = 0; e < 9; ++e) sv[1][e][lane] = v[e];
+        }
+        wave_lds_sync();
+        for (int k = bg; k < cnt; k += 8) {
+            double xv[3][4];
+            load_x3(x, sc[k], cq, xv);
+            block_fma(sv[0], k, xv, aa);
+            block_fma(sv[1], k, xv, ab);
+        }
+        wave_lds_sync();  // every lane is done reading this chunk before the next one is written
+    }
+    finish_row<MODE>(aa, ra, bg, cq, x, f, y, acc);
+    finish_row<MODE>(ab, ra + 1, bg, cq, x, f, y, acc);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(64 * kSpmmWaves) __attribute__((amdgpu_waves_per_eu(4))) void k_bspmm(int32_t nb, const int32_t *__restrict__ brow_ptr,
                                                const int32_t *__restrict__ bcol, const double *__restrict__ bval,
                                                const int32_t *__restrict__ pair_len,
                                                const int32_t *__restrict__ pair_col,
@@ -215,7 +261,7 @@ __global__ __launch_bounds__(64 * kSpmmWaves) void k_bspmm(int32_t nb, const int
     const int w = xcd_remap(blockIdx.x, gridDim.x);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const int slot = w * kSpmmWaves + wv, ra = 2 * slot, rb = ra + 1;
-    const int u = ra < nb ? pair_len[slot] : 0;  // merged columns of a pair, 0 otherwise
+    const int u = ra < nb ? pair_len[slot] : 0;  // merged columns of a pair, -1 twins, 0 otherwise
     if (u > 0) {
         const int ba = brow_ptr[ra], bb = brow_ptr[rb], eb = brow_ptr[rb + 1];
         const int ma = bb - ba, mb = eb - bb;
@@ -273,6 +319,8 @@ __global__ __launch_bounds__(64 * kSpmmWaves) void k_bspmm(int32_t nb, const int
         }
         finish_row<MODE>(aa, ra, bg, cq, x, f, y, acc);
         finish_row<MODE>(ab, rb, bg, cq, x, f, y, acc);
+    } else if (u < 0) {
+        twin_rows<MODE>(ra, brow_ptr, bcol, bval, x, f, y, sv[wv], sc[wv], lane, acc);
     } else {
         if (ra < nb) single_row<MODE>(ra, brow_ptr, bcol, bval, x, f, y, sv[wv][0], sc[wv], lane, acc);
         if (rb < nb) single_row<MODE>(rb, brow_ptr, bcol, bval, x, f, y, sv[wv][0], sc[wv], lane, acc);
@@ -312,8 +360,16 @@ __global__ __launch_bounds__(256) void k_pair_merge(int32_t nb, const int32_t *_
         ma = bb - ba;
         mb = brow_ptr[rb + 1] - bb;
     }
-    if (rb >= nb || ma > kPairMax || mb > kPairMax) {
+    if (rb >= nb) {
         if (lane == 0) pair_len[s] = 0;
+        return;
+    }
+    if (ma > kPairMax || mb > kPairMax) {
+        // twins: the same block columns (the block rows of one enriched node), -1
+        bool same = ma == mb;
+        for (int i0 = 0; same && i0 < ma; i0 += 64)
+            same = __ballot(lane + i0 < ma && bcol[ba + i0 + lane] != bcol[bb + i0 + lane]) == 0;
+        if (lane == 0) pair_len[s] = same ? -1 : 0;
         return;
     }
     const int32_t a = lane < ma ? bcol[ba + lane] : INT32_MAX;
