@@ -595,14 +595,17 @@ __global__ __launch_bounds__(kThreads) void k_bj_dense(const DenseBlk *__restric
 }
 
 // Convergence test (workgroup 0 only) and g_j = Z^T a - (K Z)^T b, one column per
-// workgroup of kRestrictThreads threads, four independent chains per thread for each of
-// the two products.  h (when given) receives Z^T a and workgroup 0 also sums the r^T y
-// partials into st->ry; advance (iteration launches whose iterate continues) moves the
-// state to the next iteration after the test.
+// workgroup of kRestrictThreads threads; each thread takes every T-th entry of the
+// column's two lists, kRestrictDepth entries (index, value, then the gathered vector
+// entry) at a time, so that one or two rounds of dependent loads cover a column.  h (when
+// given) receives Z^T a and workgroup 0 also sums the r^T y partials into st->ry; advance
+// (iteration launches whose iterate continues) moves the state to the next iteration
+// after the test.
 constexpr int kRestrictWaves = 8;
 constexpr int kRestrictThreads = 64 * kRestrictWaves;
+constexpr int kRestrictDepth = 8;  // entries per thread whose loads are in flight together
 
-__device__ __forceinline__ void k_restrict_body(int vb, int vg, 
+__device__ __forceinline__ void k_restrict_body(int vb, int vg,
     int32_t k, const int32_t *__restrict__ zt_ptr, const int32_t *__restrict__ zt_idx,
     const double *__restrict__ zt_val, const int32_t *__restrict__ kzt_ptr, const int32_t *__restrict__ kzt_idx,
     const double *__restrict__ kzt_val, const double *__restrict__ a, const double *__restrict__ b,
@@ -640,31 +643,42 @@ __device__ __forceinline__ void k_restrict_body(int vb, int vg,
     }
     constexpr int T = kRestrictThreads;
     for (int j = xcd_remap(vb, vg); j < k; j += vg) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;  // Z^T a
-        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;  // -(K Z)^T b
-        {
-            const int e1 = zt_ptr[j + 1];
-            int e = zt_ptr[j] + threadIdx.x;
-            for (; e + 3 * T < e1; e += 4 * T) {
-                s0 = fma(zt_val[e], a[zt_idx[e]], s0);
-                s1 = fma(zt_val[e + T], a[zt_idx[e + T]], s1);
-                s2 = fma(zt_val[e + 2 * T], a[zt_idx[e + 2 * T]], s2);
-                s3 = fma(zt_val[e + 3 * T], a[zt_idx[e + 3 * T]], s3);
+        // the column's Z^T entries, then its (K Z)^T entries (when b is given), as one list:
+        // each thread loads kRestrictDepth entries and their gathers at a time
+        const int zb = zt_ptr[j], nz = zt_ptr[j + 1] - zb;
+        const int kb0 = b ? kzt_ptr[j] : 0, nt = nz + (b ? kzt_ptr[j + 1] - kb0 : 0);
+        double za = 0.0, kb = 0.0;  // Z^T a and -(K Z)^T b
+        for (int e0 = threadIdx.x; e0 < nt; e0 += kRestrictDepth * T) {
+            int32_t idx[kRestrictDepth];
+            double v[kRestrictDepth], x[kRestrictDepth];
+            // one load of each kind per entry: the lane picks the list (and vector) by address
+#pragma unroll
+            for (int u = 0; u < kRestrictDepth; ++u) {
+                const int e = e0 + u * T;
+                const bool inz = e < nz;
+                const int o = inz ? zb + e : kb0 + e - nz;
+                const int32_t *ip = inz ? zt_idx : kzt_idx;
+                const double *vp = inz ? zt_val : kzt_val;
+                idx[u] = 0;
+                v[u] = 0.0;
+                if (e < nt) {
+                    idx[u] = ip[o];
+                    v[u] = vp[o];
+                }
             }
-            for (; e < e1; e += T) s0 = fma(zt_val[e], a[zt_idx[e]], s0);
-        }
-        if (b) {
-            const int e1 = kzt_ptr[j + 1];
-            int e = kzt_ptr[j] + threadIdx.x;
-            for (; e + 3 * T < e1; e += 4 * T) {
-                t0 = fma(-kzt_val[e], b[kzt_idx[e]], t0);
-                t1 = fma(-kzt_val[e + T], b[kzt_idx[e + T]], t1);
-                t2 = fma(-kzt_val[e + 2 * T], b[kzt_idx[e + 2 * T]], t2);
-                t3 = fma(-kzt_val[e + 3 * T], b[kzt_idx[e + 3 * T]], t3);
+#pragma unroll
+            for (int u = 0; u < kRestrictDepth; ++u) {
+                const int e = e0 + u * T;
+                const double *xp = e < nz ? a : b;
+                x[u] = e < nt ? xp[idx[u]] : 0.0;
             }
-            for (; e < e1; e += T) t0 = fma(-kzt_val[e], b[kzt_idx[e]], t0);
+#pragma unroll
+            for (int u = 0; u < kRestrictDepth; ++u) {
+                const bool inz = e0 + u * T < nz;
+                za = fma(inz ? v[u] : 0.0, x[u], za);
+                kb = fma(inz ? 0.0 : -v[u], x[u], kb);
+            }
         }
-        double za = (s0 + s1) + (s2 + s3), kb = (t0 + t1) + (t2 + t3);
         block_sum2_n<kRestrictWaves>(za, kb, lds);
         if (threadIdx.x == 0) {
             g[j] = za + kb;
