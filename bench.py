@@ -47,11 +47,11 @@ WORKLOADS = {
 SPMV_TRAFFIC = {
     "workload": "penny80",
     "sources": {
-        "paper_2111_09294_amd/csrc/kernels.hip": "dc2ae2e14214258d29f769016406806cbe8bbb06c4240bf4d921317530390352",
+        "paper_2111_09294_amd/csrc/kernels.hip": "b57fe1ec57af5b33866977548b705d2b70dc74dcc367cf76d32d7cff505cd1a7",
         "paper_2111_09294_amd/csrc/dpcg_internal.h": "42dcd5dd6eaf15f576166a8f6617bc6eb2a82a017474b6ef79d5edfce7c5183f"
     },
-    "fetch_bytes": 1482790624,
-    "write_bytes": 15987540,
+    "fetch_bytes": 1482824216,
+    "write_bytes": 15994204,
 }
 SPMV_SOURCES = ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h")
 
