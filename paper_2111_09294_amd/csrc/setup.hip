@@ -830,6 +830,7 @@ __global__ __launch_bounds__(256) void k_kzb_scatter(const KzBatch *__restrict__
 // flagged triplet return at once.
 constexpr int kMarkHalo = 7680;
 constexpr int kMarkWindow = kSlice + 2 * kMarkHalo;  // 16384 words, 64 KB of LDS
+constexpr int kMarkRun = 16;  // block columns of a row loaded together
 
 __global__ __launch_bounds__(256) void k_kzb_mark(const KzBatch *__restrict__ bt, const int32_t *__restrict__ bptr,
                                                   const int32_t *__restrict__ bcol, const uint32_t *__restrict__ rb,
@@ -848,12 +849,21 @@ __global__ __launch_bounds__(256) void k_kzb_mark(const KzBatch *__restrict__ bt
         const uint32_t bits = rb[B.moff + t];
         if (!bits) continue;
         const int64_t R = B.lo3 + t;
-        for (int64_t q = bptr[R]; q < bptr[R + 1]; ++q) {
-            const int64_t c = (int64_t)bcol[q] - B.lo3;
-            if (c < 0 || c >= B.w3) continue;
-            const int64_t l = c - w0;
-            if (l >= 0 && l < kMarkWindow) atomicOr(&win[l], bits);
-            else atomicOr(&mk[B.moff + c], bits);
+        const int64_t q0 = bptr[R], q1 = bptr[R + 1];
+        for (int64_t q = q0; q < q1; q += kMarkRun) {
+            // a run of block columns loaded together, then their marks
+            int32_t cr[kMarkRun];
+#pragma unroll
+            for (int u = 0; u < kMarkRun; ++u) cr[u] = q + u < q1 ? bcol[q + u] : -1;
+#pragma unroll
+            for (int u = 0; u < kMarkRun; ++u) {
+                if (cr[u] < 0) continue;
+                const int64_t c = (int64_t)cr[u] - B.lo3;
+                if (c < 0 || c >= B.w3) continue;
+                const int64_t l = c - w0;
+                if (l >= 0 && l < kMarkWindow) atomicOr(&win[l], bits);
+                else atomicOr(&mk[B.moff + c], bits);
+            }
         }
     }
     __syncthreads();
@@ -1084,6 +1094,8 @@ __device__ __forceinline__ int64_t wave_lower_bound(const int32_t *__restrict__ 
     return lo;
 }
 
+constexpr int kErowRun = 4;  // entries per lane whose rows and masks are loaded together
+
 __global__ __launch_bounds__(256) void k_kzb_erows(const KzBatch *__restrict__ bt, int32_t k,
                                                    const int64_t *__restrict__ ztp, const int32_t *__restrict__ zti,
                                                    const double *__restrict__ ztv, const double *__restrict__ kd,
@@ -1102,12 +1114,20 @@ __global__ __launch_bounds__(256) void k_kzb_erows(const KzBatch *__restrict__ b
     a = wave_lower_bound(zti, a, e, lo);
     double acc[kBatch];
     for (int b = 0; b < kBatch; ++b) acc[b] = 0.0;
-    for (int64_t q = a + lane; q < e; q += 64) {
-        const int64_t t = (int64_t)zti[q] - lo;
-        if (!mk[B.moff + t / 3]) continue;  // (K z_j)_t is structurally zero for every vector of the batch
-        const double z = ztv[q];
-        const double *kdr = kd + (3 * B.off3 + t) * kBatch;
-        for (int b = 0; b < kBatch; ++b) acc[b] = fma(z, kdr[b], acc[b]);
+    for (int64_t q0 = a + lane; q0 < e; q0 += 64 * kErowRun) {
+        // a run of the lane's entries: rows, then their structure masks, loaded together
+        int64_t tr[kErowRun];
+        bool on[kErowRun];
+#pragma unroll
+        for (int u = 0; u < kErowRun; ++u) tr[u] = q0 + 64 * u < e ? (int64_t)zti[q0 + 64 * u] - lo : -1;
+#pragma unroll
+        for (int u = 0; u < kErowRun; ++u) on[u] = tr[u] >= 0 && mk[B.moff + tr[u] / 3] != 0u;
+        for (int u = 0; u < kErowRun; ++u) {
+            if (!on[u]) continue;  // (K z_j)_t is structurally zero for every vector of the batch
+            const double z = ztv[q0 + 64 * u];
+            const double *kdr = kd + (3 * B.off3 + tr[u]) * kBatch;
+            for (int b = 0; b < kBatch; ++b) acc[b] = fma(z, kdr[b], acc[b]);
+        }
     }
     for (int b = 0; b < kBatch; ++b) {
         double v = acc[b];
