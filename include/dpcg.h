@@ -329,6 +329,14 @@ size_t dpcg_noalloc_scratch_bytes(void);
 /* y = K x (Algorithm 1's K p_i) with the block-CSR kernel.  x, y: device, n. */
 int dpcg_spmv(dpcg_handle h, const double *x, double *y);
 
+/* Y = K X for nrhs columns at once, 1 <= nrhs <= 32 (Algorithm 1's K p for every column
+ * of dpcg_solve_batch), with that solve's multi-RHS product kernel.  X, Y: n x nrhs
+ * row-major device arrays (column j of row d at X[d * nrhs + j]), caller-owned.  The
+ * first call makes the handle's multi-RHS workspace.  Returns after the product has
+ * completed.  DPCG_EINVAL for nrhs outside [1, 32], null arrays or a handle with blocks
+ * of more than 18 DoFs; DPCG_EHIP. */
+int dpcg_spmv_batch(dpcg_handle h, int32_t nrhs, const double *X, double *Y);
+
 /* y = K32 x, the product the inner solves of DPCG_PREC_MIXED use: K's values
  * rounded to binary32, products and sums in binary64. */
 int dpcg_spmv_fp32(dpcg_handle h, const double *x, double *y);

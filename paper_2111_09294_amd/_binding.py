@@ -77,6 +77,7 @@ SIGNATURES = {
     "dpcg_get_timing": (C.c_int, [P, C.POINTER(Timing)]),
     "dpcg_spmv": (C.c_int, [P, P, P]),
     "dpcg_spmv_fp32": (C.c_int, [P, P, P]),
+    "dpcg_spmv_batch": (C.c_int, [P, C.c_int32, P, P]),
     "dpcg_bj_apply": (C.c_int, [P, P, P]),
     "dpcg_bj_apply_fp32": (C.c_int, [P, P, P]),
     "dpcg_restrict": (C.c_int, [P, P, P, P]),
@@ -345,6 +346,19 @@ class Solver:
         y = torch.empty_like(x) if y is None else y
         self._call("dpcg_spmv", x, y)
         return y
+
+    def spmv_batch(self, X):
+        """Y = K X for an n x nrhs float64 device tensor X (1 <= nrhs <= 32) with the
+        multi-RHS product of solve_batch."""
+        import torch
+        if X.dim() != 2 or X.shape[0] != self.n:
+            raise ValueError(f"X must be {self.n} x nrhs")
+        _check_dev(X, torch.float64, "X")
+        Y = torch.empty_like(X)
+        st = lib().dpcg_spmv_batch(self.handle, int(X.shape[1]), _ptr(X), _ptr(Y))
+        if st != OK:
+            raise DpcgError(st, "dpcg_spmv_batch")
+        return Y
 
     def bj_apply(self, r):
         import torch

@@ -1291,6 +1291,24 @@ int column_norms(dpcg_ctx *c, const double *a, const double *bvec, bool check, B
 
 }  // namespace
 
+// Y = K X for nrhs <= 32 columns (n x nrhs row-major, as in solve_batch): the columns
+// packed into the batch layout, the multi-RHS product of the batched iteration
+// (k_bspmm, mode 0: pairs, twin rows and single rows as there), and unpacked.
+int spmv_batch(dpcg_ctx *c, int32_t nrhs, const double *X, double *Y) {
+    if (!c || nrhs < 1 || nrhs > W || !X || !Y || c->ndense > 0) return DPCG_EINVAL;
+    BTRY(ensure_ws(c));
+    BatchWorkspace *b = c->bws;
+    hipStream_t s = c->stream;
+    const int pgrid = (int)std::min<int64_t>(8192, (c->n * W + 255) / 256);
+    BLAUNCH(k_bpack, dim3(pgrid), dim3(256), 0, s, c->n, nrhs, X, b->p);
+    BLAUNCH(k_bspmm<0>, dim3(b->spmm_nwg), dim3(64 * kSpmmWaves), 0, s, c->nb, c->brow_ptr, c->bcol, c->bval,
+            (const int32_t *)b->pair_len, (const int32_t *)b->pair_col, (const uint16_t *)b->pair_ab,
+            (const double *)b->p, (const double *)nullptr, b->q, b->part, (const BatchState *)nullptr);
+    BLAUNCH(k_bunpack, dim3(pgrid), dim3(256), 0, s, c->n, nrhs, (const double *)b->q, Y, 0u);
+    BHIP(hipStreamSynchronize(s));
+    return DPCG_OK;
+}
+
 int solve_batch(dpcg_ctx *c, int32_t nrhs, const double *F, double *U, double tol, const dpcg_options *opt_in,
                 dpcg_info *infos) {
     const double t0 = now_ms();

@@ -978,6 +978,11 @@ int dpcg_spmv(dpcg_handle h, const double *x, double *y) {
     SYNC_RET(launch_spmv_plain(h, x, y));
 }
 
+int dpcg_spmv_batch(dpcg_handle h, int32_t nrhs, const double *X, double *Y) {
+    if (!h) return DPCG_EINVAL;
+    return spmv_batch(h, nrhs, X, Y);
+}
+
 int dpcg_spmv_fp32(dpcg_handle h, const double *x, double *y) {
     if (!h || !x || !y) return DPCG_EINVAL;
     const int e = ensure_fp32(h);

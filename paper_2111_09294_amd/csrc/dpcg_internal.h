@@ -318,6 +318,8 @@ int gpu_update_values(dpcg_ctx *c, const int64_t *kp, const int32_t *kc, const d
 // row-major); returns a DPCG_* status and fills infos[nrhs] when given.
 int solve_batch(dpcg_ctx *c, int32_t nrhs, const double *F, double *U, double tol, const dpcg_options *opt,
                 dpcg_info *infos);
+// Y = K X for nrhs <= kBatchCols columns (n x nrhs row-major) with the multi-RHS product.
+int spmv_batch(dpcg_ctx *c, int32_t nrhs, const double *X, double *Y);
 void release_batch(dpcg_ctx *c);
 
 // adjoint.hip: g[e] = -lam_e^T K_e u_e after a device-side check of the element data;

@@ -91,6 +91,33 @@ def test_batch_matches_single_solves(solver, name, nrhs):
         assert iters_close(infos[0]["iterations"], ref["iterations"])
 
 
+@pytest.mark.parametrize("name,nrhs", [("penny12", 7), ("penny40", 32)])
+def test_spmv_batch_matches_oracle(solver, name, nrhs):
+    """The multi-RHS product of the batched iteration (rows in pairs over their merged
+    block columns, twin rows of enriched nodes together, long rows one at a time) against
+    the oracle's K x for every column, entry by entry: each side sums at most m products
+    (m = the longest row of K), so the two differ by at most 2 m eps (|K| |x|) per entry."""
+    p, s = solver(name)
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal((p.n, nrhs))
+    Y = host(s.spmv_batch(dev(X)))
+    o = O.Oracle.from_problem(p)
+    K = p.K_scipy().tocsr()
+    Ka = abs(K)
+    m = int(np.diff(K.indptr).max())
+    eps = np.finfo(np.float64).eps
+    worst = 0.0
+    for j in range(nrhs):
+        yo = o.spmv(X[:, j])
+        bound = 2 * m * eps * (Ka @ np.abs(X[:, j]))
+        err = np.abs(Y[:, j] - yo)
+        assert np.all(err <= bound), (j, int(np.argmax(err - bound)))
+        worst = max(worst, float((err / np.maximum(bound, 1e-300)).max()))
+    say(f"[batch] {name} spmv_batch nrhs={nrhs}: max |Y - Kx| / bound = {worst:.3f} (m = {m})")
+    with pytest.raises(D.DpcgError):
+        s.spmv_batch(dev(np.zeros((p.n, 33))))
+
+
 @pytest.mark.parametrize("order", ["mod7", "tail10"])
 def test_batch_restriction_column_orders(problems, order):
     """The batched restriction takes runs of deflation vectors that cover the same
