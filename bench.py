@@ -48,10 +48,10 @@ SPMV_TRAFFIC = {
     "workload": "penny80",
     "sources": {
         "paper_2111_09294_amd/csrc/kernels.hip": "b57fe1ec57af5b33866977548b705d2b70dc74dcc367cf76d32d7cff505cd1a7",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "42dcd5dd6eaf15f576166a8f6617bc6eb2a82a017474b6ef79d5edfce7c5183f"
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "5ddd0dce7d529b1d0143f8ec0e688ef4d6b85d8d9812666f4ca12817aaeef022"
     },
-    "fetch_bytes": 1482824216,
-    "write_bytes": 15994204,
+    "fetch_bytes": 1482849898,
+    "write_bytes": 15995424,
 }
 SPMV_SOURCES = ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h")
 
