@@ -79,10 +79,11 @@ def spmv_traffic(workload):
     return t["fetch_bytes"] + t["write_bytes"]
 
 
-def spmv_bytes(nnzb, n, value_bytes=8):
-    """Algorithmic bytes of one q = K p launch: each 3x3 block (9 values + a 4 B column
-    index) once, the block-row pointers, p read once and q written once."""
-    return nnzb * (9 * value_bytes + 4) + 4 * (n // 3 + 1) + 2 * 8 * n
+def spmv_bytes(nnzb, n, value_bytes=8, col_bytes=4):
+    """Algorithmic bytes of one q = K p launch: each 3x3 block (9 values and its block
+    column: a 2 B offset from its row, or a 4 B index) once, the block-row pointers, p
+    read once and q written once."""
+    return nnzb * (9 * value_bytes + col_bytes) + 4 * (n // 3 + 1) + 2 * 8 * n
 
 
 def cpu_model():
@@ -183,14 +184,16 @@ def run_steps(p, tensors, steps, warmup, stream, precision="fp64"):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     per_launch_s = spmv_ms / 1e3 / max(spmv_n, 1)
-    nbytes = spmv_bytes(st["nnzb"], p.n, value_bytes=8 if precision == "fp64" else 4)
+    nbytes = spmv_bytes(st["nnzb"], p.n, value_bytes=8 if precision == "fp64" else 4,
+                        col_bytes=st["spmv_col_bytes"])
     achieved = nbytes / per_launch_s / 1e9
     out = {"value": p.n * steps / dt, "unit": "DoF-solves/s", "ms_per_step": dt * 1e3 / steps,
            "ok": all(i["status"] == 0 and i["rel_res_true"] <= 1.5e-8 for i in infos),
            "iterations": infos[-1]["iterations"], "rel_res_true": infos[-1]["rel_res_true"],
            "setup_ms": float(np.mean([i["setup_ms"] for i in infos])),
            "solve_ms": float(np.mean([i["solve_ms"] for i in infos])),
-           "spmv": {"kernel": "k_spmv_p<32, double>" if precision == "fp64" else "k_spmv_p<32, float>",
+           "spmv": {"kernel": "k_spmv_p<32, %s%s>" % ("double" if precision == "fp64" else "float",
+                                                      ", short" if st["spmv_col_bytes"] == 2 else ""),
                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                     "bytes_per_launch": nbytes, "launches": spmv_n, "avg_launch_us": per_launch_s * 1e6},
            "stats": st}

@@ -91,6 +91,9 @@ typedef struct {
     int64_t device_bytes;      /* device memory held by the handle                      */
     int64_t dense_blocks;      /* blocks of more than 18 unknowns                       */
     int64_t dense_values;      /* entries of their stored inverses (sum of ld^2)        */
+    int64_t spmv_col_bytes;    /* bytes per block column the iteration SpMV reads: 2 when
+                                  every column fits as a 16-bit offset from its block
+                                  row, else 4                                           */
 } dpcg_stats;
 
 typedef struct {

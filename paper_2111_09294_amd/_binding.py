@@ -37,7 +37,7 @@ class Info(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [(f, C.c_int64) for f in ("n", "nnz", "nnzb", "k", "nnz_z", "nnz_kz", "nblocks", "bj_values",
-                                         "device_bytes", "dense_blocks", "dense_values")]
+                                         "device_bytes", "dense_blocks", "dense_values", "spmv_col_bytes")]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

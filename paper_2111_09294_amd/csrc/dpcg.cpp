@@ -937,6 +937,7 @@ int dpcg_get_stats(dpcg_handle h, dpcg_stats *out) {
     out->device_bytes = h->device_bytes;
     out->dense_blocks = h->ndense;
     out->dense_values = h->dinv_len;
+    out->spmv_col_bytes = h->bcol16 ? 2 : 4;
     return DPCG_OK;
 }
 

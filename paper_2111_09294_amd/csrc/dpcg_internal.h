@@ -208,6 +208,7 @@ struct dpcg_ctx {
     int32_t nb = 0, k = 0, nblocks = 0;
     // K
     int32_t *brow_ptr = nullptr, *bcol = nullptr;
+    int16_t *bcol16 = nullptr;  // block columns as offsets from their row (null: an offset exceeds 16 bits)
     double *bval = nullptr;
     // FP32 copies (same layouts) for the inner solves of mixed precision; made on the
     // first mixed solve.  inner32 selects them in the launchers while an inner solve runs.

@@ -135,8 +135,15 @@ struct XPlain {
 // row = -1 and take part in the shuffles with zeros.
 // V is the storage type of the block values (double, or float for the inner solves of
 // mixed precision); the arithmetic is FP64 either way.
-template <int G, class XL, class V>
-__device__ __forceinline__ void block_row_span(int row, int beg, int end, int lg, const int32_t *__restrict__ bcol,
+// block column of entry b of block row `row`: stored as is (int32) or as its offset from
+// the row (int16, when every offset fits)
+__device__ __forceinline__ int64_t col_at(const int32_t *__restrict__ bc, int b, int row) { return bc[b]; }
+__device__ __forceinline__ int64_t col_at(const int16_t *__restrict__ bc, int b, int row) {
+    return (int64_t)row + bc[b];
+}
+
+template <int G, class XL, class V, class CI>
+__device__ __forceinline__ void block_row_span(int row, int beg, int end, int lg, const CI *__restrict__ bcol,
                                                const V *__restrict__ bval, const XL &xl, double &a0, double &a1,
                                                double &a2) {
     a0 = a1 = a2 = 0.0;
@@ -147,7 +154,7 @@ __device__ __forceinline__ void block_row_span(int row, int beg, int end, int lg
             const double v0 = rv[b], v1 = rv[m + b], v2 = rv[2 * m + b];
             const double v3 = rv[3 * m + b], v4 = rv[4 * m + b], v5 = rv[5 * m + b];
             const double v6 = rv[6 * m + b], v7 = rv[7 * m + b], v8 = rv[8 * m + b];
-            const int64_t c = 3 * (int64_t)bcol[b];
+            const int64_t c = 3 * col_at(bcol, b, row);
             const double x0 = xl(c), x1 = xl(c + 1), x2 = xl(c + 2);
             a0 = fma(v0, x0, fma(v1, x1, fma(v2, x2, a0)));
             a1 = fma(v3, x0, fma(v4, x1, fma(v5, x2, a1)));
@@ -262,9 +269,9 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvShape sh, const int32
 // single-workgroup kernels and workgroup 0 of later kernels change the flag, so it is
 // stable while this kernel runs.  The first step's row pointers are loaded before the
 // state, so that the two round trips overlap.
-template <int G, class V>
+template <int G, class V, class CI = int32_t>
 __device__ __forceinline__ void k_spmv_p_body(int vb, SpmvShape sh, const int32_t *__restrict__ brow_ptr,
-                                                         const int32_t *__restrict__ bcol,
+                                                         const CI *__restrict__ bcol,
                                                          const V *__restrict__ bval, int64_t nnzb,
                                                          const double *p0, const double *p1,
                                                          double *__restrict__ q, double *__restrict__ part_pq,
@@ -305,14 +312,14 @@ __device__ __forceinline__ void k_spmv_p_body(int vb, SpmvShape sh, const int32_
     if (threadIdx.x == 0) part_pq[vb] = t;
 }
 
-template <int G, class V>
+template <int G, class V, class CI>
 __global__ __launch_bounds__(kSpmvThreads) void k_spmv_p(SpmvShape sh, const int32_t *__restrict__ brow_ptr,
-                                                         const int32_t *__restrict__ bcol,
+                                                         const CI *__restrict__ bcol,
                                                          const V *__restrict__ bval, int64_t nnzb,
                                                          const double *p0, const double *p1,
                                                          double *__restrict__ q, double *__restrict__ part_pq,
                                                          const State *st) {
-    k_spmv_p_body<G, V>(blockIdx.x, sh, brow_ptr, bcol, bval, nnzb, p0, p1, q, part_pq, st);
+    k_spmv_p_body<G, V, CI>(blockIdx.x, sh, brow_ptr, bcol, bval, nnzb, p0, p1, q, part_pq, st);
 }
 
 
@@ -944,15 +951,26 @@ __global__ __launch_bounds__(kThreads) void k_reduce_aux(const double *__restric
 template <int G>
 hipError_t spmv_p_g(const dpcg_ctx *c, Workspace &w, hipEvent_t ev0, hipEvent_t ev1) {
     SpmvShape sh{c->nb, c->spmv.steps, c->spmv.nwg};
-    // the events (when given) take the kernel's own start and end timestamps
-    if (c->inner32)
-        hipExtLaunchKernelGGL(k_spmv_p<G, float>, dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, ev0, ev1, 0,
-                              sh, c->brow_ptr, c->bcol, (const float *)c->bval32, c->nnzb,
+    // the events (when given) take the kernel's own start and end timestamps; block
+    // columns as 16-bit row offsets when the handle has them
+    const int16_t *b16 = c->bcol16;
+    if (c->inner32 && b16)
+        hipExtLaunchKernelGGL((k_spmv_p<G, float, int16_t>), dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, ev0,
+                              ev1, 0, sh, c->brow_ptr, b16, (const float *)c->bval32, c->nnzb,
+                              (const double *)w.p[0], (const double *)w.p[1], w.q, w.part_a, (const State *)w.st);
+    else if (c->inner32)
+        hipExtLaunchKernelGGL((k_spmv_p<G, float, int32_t>), dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, ev0,
+                              ev1, 0, sh, c->brow_ptr, (const int32_t *)c->bcol, (const float *)c->bval32, c->nnzb,
+                              (const double *)w.p[0], (const double *)w.p[1], w.q, w.part_a, (const State *)w.st);
+    else if (b16)
+        hipExtLaunchKernelGGL((k_spmv_p<G, double, int16_t>), dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream,
+                              ev0, ev1, 0, sh, c->brow_ptr, b16, (const double *)c->bval, c->nnzb,
                               (const double *)w.p[0], (const double *)w.p[1], w.q, w.part_a, (const State *)w.st);
     else
-        hipExtLaunchKernelGGL(k_spmv_p<G, double>, dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream, ev0, ev1,
-                              0, sh, c->brow_ptr, c->bcol, (const double *)c->bval, c->nnzb,
-                              (const double *)w.p[0], (const double *)w.p[1], w.q, w.part_a, (const State *)w.st);
+        hipExtLaunchKernelGGL((k_spmv_p<G, double, int32_t>), dim3(c->spmv.nwg), dim3(kSpmvThreads), 0, c->stream,
+                              ev0, ev1, 0, sh, c->brow_ptr, (const int32_t *)c->bcol, (const double *)c->bval,
+                              c->nnzb, (const double *)w.p[0], (const double *)w.p[1], w.q, w.part_a,
+                              (const State *)w.st);
     return hipGetLastError();
 }
 

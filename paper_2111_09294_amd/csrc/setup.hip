@@ -661,6 +661,18 @@ __global__ void k_tiles(int32_t ntiles, int32_t nblocks, const int32_t *__restri
     }
 }
 
+// Block columns as offsets from their block row in 16 bits (the iteration SpMV reads 2
+// bytes per block instead of 4); *bad becomes 1 when an offset does not fit.
+__global__ void k_bcol16(int64_t nnzb, const int32_t *__restrict__ brow, const int32_t *__restrict__ bcol,
+                         int16_t *__restrict__ out, int *bad) {
+    for (int64_t b = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; b < nnzb; b += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t d = bcol[b] - brow[b];
+        const bool fits = d >= INT16_MIN && d <= INT16_MAX;
+        out[b] = fits ? (int16_t)d : (int16_t)0;
+        if (!fits) *bad = 1;
+    }
+}
+
 // ---------------------------------------------------------------- Z^T
 // Z^T by a stable counting sort over chunks of Z's entries in row-major order.  Pass 1
 // counts each chunk's entries per column into cnt[c * nch + w]; an exclusive scan in
@@ -2265,6 +2277,14 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
     HT(pool.tmp(&brow, nnzb));
     hipLaunchKernelGGL((k_bsr<true>), dim3(grid_for(nb, 4)), dim3(256), 0, s, nb, kp, kc, kv, nullptr, c->brow_ptr,
                        c->bcol, c->bval, brow);
+    // block columns as 16-bit offsets from their row for the iteration SpMV (kept when
+    // every offset fits: read back at the end of setup)
+    int *b16bad = nullptr;
+    HT(pool.tmp(&b16bad, 1));
+    HT(keep(c, &c->bcol16, nnzb));
+    HT(hipMemsetAsync(b16bad, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_bcol16, dim3(grid_for(nnzb)), dim3(256), 0, s, nnzb, (const int32_t *)brow,
+                       (const int32_t *)c->bcol, c->bcol16, b16bad);
     // The symmetry test and the small block-Jacobi inverses do not feed K Z, E or E^-1:
     // they run on the side stream beside that chain (whose kernels are latency bound and
     // leave most of the chip idle), joined before their flags are read.  Dense blocks
@@ -2343,6 +2363,9 @@ int gpu_setup(dpcg_ctx *c, int64_t n, const int64_t *kp, const int32_t *kc, cons
             return DPCG_EBLOCK_NOT_SPD;
         }
     }
+    int b16 = 0;
+    HT(hipMemcpy(&b16, b16bad, sizeof(int), hipMemcpyDeviceToHost));
+    if (b16) c->bcol16 = nullptr;  // an offset does not fit: the SpMV reads the int32 columns
     return DPCG_OK;
 }
 
