@@ -165,6 +165,36 @@ def test_solve_matches_oracle(pair, name):
     assert np.allclose(h[:m], ref["history"][:m], rtol=1e-6, atol=1e-12)
 
 
+def test_block_columns_beyond_16_bits(pair):
+    """The iteration SpMV reads its block columns as 16-bit offsets from their row when
+    every offset fits (node-major numbering) and the 4-byte columns otherwise.  The 40^3
+    system with its nodal blocks in a random order (70,857 block rows, so offsets far
+    beyond 16 bits) takes the 4-byte path; both solve to the oracle's solution with its
+    iteration count."""
+    from fixtures import permuted
+    p, o, s = pair("penny40")
+    assert s.stats()["spmv_col_bytes"] == 2
+    bp = np.asarray(p.block_ptr, np.int64)
+    order = np.random.default_rng(5).permutation(len(bp) - 1)
+    lens = np.diff(bp)[order]
+    starts = bp[:-1][order]
+    offs = np.zeros(len(order) + 1, np.int64)
+    np.cumsum(lens, out=offs[1:])
+    perm = np.repeat(starts - offs[:-1], lens) + np.arange(offs[-1])
+    q = permuted(p, perm, offs.astype(np.int32), name="penny40-shuffled")
+    ref = o.solve(p.f, tol=1e-8)
+    with D.Solver.from_problem(q, DEV) as sq:
+        assert sq.stats()["spmv_col_bytes"] == 4
+        u, info = sq.solve(dev(q.f), tol=1e-8)
+    u0, info0 = s.solve(dev(p.f), tol=1e-8)
+    for uu, inf, pp in ((host(u), info, perm), (host(u0), info0, np.arange(p.n))):
+        assert inf["status"] == D.abi.OK
+        assert np.linalg.norm(uu - ref["u"][pp]) <= 1e-6 * np.linalg.norm(ref["u"])
+        assert iters_close(inf["iterations"], ref["iterations"])
+    say(f"[columns] penny40 shuffled: {info['iterations']} iterations (node-major {info0['iterations']}, "
+        f"oracle {ref['iterations']})")
+
+
 @pytest.mark.parametrize("name", ["penny12", "penny40"])
 def test_deterministic_and_adjoint(pair, name):
     """Two solves are bitwise identical; the adjoint solve runs the same operator."""
