@@ -47,11 +47,11 @@ WORKLOADS = {
 SPMV_TRAFFIC = {
     "workload": "penny80",
     "sources": {
-        "paper_2111_09294_amd/csrc/kernels.hip": "b57fe1ec57af5b33866977548b705d2b70dc74dcc367cf76d32d7cff505cd1a7",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "5ddd0dce7d529b1d0143f8ec0e688ef4d6b85d8d9812666f4ca12817aaeef022"
+        "paper_2111_09294_amd/csrc/kernels.hip": "eda0e13f7eb90f129f9f47ac7d68cf7bea55718a8216a01bf1327caea512030d",
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "5cee45c8ba4eacdd1184d5ce8dd1d319281971db60f7eb8c77def9ab518a39a8"
     },
-    "fetch_bytes": 1482849898,
-    "write_bytes": 15995424,
+    "fetch_bytes": 1444607815,
+    "write_bytes": 15970603,
 }
 SPMV_SOURCES = ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h")
 
