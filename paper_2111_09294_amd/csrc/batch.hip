@@ -157,6 +157,59 @@ __device__ __forceinline__ void finish_row(double (&a)[3][4], int row, int bg, i
     }
 }
 
+// rows r0 and r0 + 1 finished together from their lane-group sums aa and ab: three
+// exchanges between lane groups 8, 16 and 32 lanes apart (finish_row's pairings, so every
+// element is the same sum) each halve what a lane carries, leaving lane group bg with row
+// r0 + (bg & 1) at position t = bg >> 1 of its column quad (21 doubles exchanged per lane
+// against 72 for two finish_row calls).  The dot partials keep finish_row's order: the
+// row-r0 lane passes its three-term chain to the row-(r0 + 1) lane of the same column,
+// which continues it; the odd lane groups return column col4(cq, bg >> 1)'s partial in
+// accs (the wave's first and only rows: the chains start from zero)
+template <int MODE>
+__device__ __forceinline__ void finish_pair(const double (&aa)[3][4], const double (&ab)[3][4], int r0, int bg, int cq,
+                                            const double *__restrict__ x, const double *__restrict__ f,
+                                            double *__restrict__ y, double &accs) {
+    const bool b0 = bg & 1, b1 = (bg >> 1) & 1, b2 = (bg >> 2) & 1;
+    double k1[3][4];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const double keep = b0 ? ab[i][t] : aa[i][t], give = b0 ? aa[i][t] : ab[i][t];
+            k1[i][t] = keep + __shfl_xor(give, 8);
+        }
+    double k2[3][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double lo = k1[i][2 * h], hi = k1[i][2 * h + 1];
+            k2[i][h] = (b1 ? hi : lo) + __shfl_xor(b1 ? lo : hi, 16);
+        }
+    const int row = r0 + b0, t = bg >> 1;
+    double out[3], other[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double sum = (b2 ? k2[i][1] : k2[i][0]) + __shfl_xor(b2 ? k2[i][0] : k2[i][1], 32);
+        const int64_t oj = (3 * (int64_t)row + i) * W + col4(cq, t);
+        if (MODE == 0) {
+            out[i] = sum;
+            other[i] = x[oj];
+        } else {
+            out[i] = f[oj] - sum;
+            other[i] = out[i];
+        }
+        y[oj] = out[i];
+    }
+    double pa = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pa = fma(other[i], out[i], pa);
+    double pb = __shfl_xor(pa, 8);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) pb = fma(other[i], out[i], pb);
+    accs = pb;
+}
+
 // one row in chunks of 64 blocks (sv, sc: the wave's LDS)
 template <int MODE>
 __device__ __forceinline__ void single_row(int row, const int32_t *__restrict__ brow_ptr,
@@ -207,7 +260,7 @@ __device__ __forceinline__ void twin_rows(int ra, const int32_t *__restrict__ br
                                           const int32_t *__restrict__ bcol, const double *__restrict__ bval,
                                           const double *__restrict__ x, const double *__restrict__ f,
                                           double *__restrict__ y, double (*sv)[9][kSpmmChunk], int32_t *sc, int lane,
-                                          double (&acc)[4]) {
+                                          double &accs) {
     const int bg = lane >> 3, cq = lane & 7;
     const int ba = brow_ptr[ra], bb = brow_ptr[ra + 1];
     const int64_t m = bb - ba;  // the length of both rows
@@ -240,8 +293,7 @@ __device__ __forceinline__ void twin_rows(int ra, const int32_t *__restrict__ br
         }
         wave_lds_sync();  // every lane is done reading this chunk before the next one is written
     }
-    finish_row<MODE>(aa, ra, bg, cq, x, f, y, acc);
-    finish_row<MODE>(ab, ra + 1, bg, cq, x, f, y, acc);
+    finish_pair<MODE>(aa, ab, ra, bg, cq, x, f, y, accs);
 }
 
 template <int MODE>
@@ -259,7 +311,8 @@ __global__ __launch_bounds__(64 * kSpmmWaves) __attribute__((amdgpu_waves_per_eu
     if (st && !st->any) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, bg = lane >> 3, cq = lane & 7;
     const int w = xcd_remap(blockIdx.x, gridDim.x);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // single rows: the bg == 0 lanes' four columns
+    double accs = 0.0;                      // two rows finished together: see finish_pair
     const int slot = w * kSpmmWaves + wv, ra = 2 * slot, rb = ra + 1;
     const int u = ra < nb ? pair_len[slot] : 0;  // merged columns of a pair, -1 twins, 0 otherwise
     if (u > 0) {
@@ -317,17 +370,19 @@ __global__ __launch_bounds__(64 * kSpmmWaves) __attribute__((amdgpu_waves_per_eu
                 }
             }
         }
-        finish_row<MODE>(aa, ra, bg, cq, x, f, y, acc);
-        finish_row<MODE>(ab, rb, bg, cq, x, f, y, acc);
+        finish_pair<MODE>(aa, ab, ra, bg, cq, x, f, y, accs);
     } else if (u < 0) {
-        twin_rows<MODE>(ra, brow_ptr, bcol, bval, x, f, y, sv[wv], sc[wv], lane, acc);
+        twin_rows<MODE>(ra, brow_ptr, bcol, bval, x, f, y, sv[wv], sc[wv], lane, accs);
     } else {
         if (ra < nb) single_row<MODE>(ra, brow_ptr, bcol, bval, x, f, y, sv[wv][0], sc[wv], lane, acc);
         if (rb < nb) single_row<MODE>(rb, brow_ptr, bcol, bval, x, f, y, sv[wv][0], sc[wv], lane, acc);
     }
-    if (bg == 0)
+    if (u != 0) {
+        if (bg & 1) lds[wv][col4(cq, bg >> 1)] = accs;
+    } else if (bg == 0) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) lds[wv][col4(cq, t)] = acc[t];
+    }
     __syncthreads();
     if (threadIdx.x < W) {
         double v = lds[0][threadIdx.x];
