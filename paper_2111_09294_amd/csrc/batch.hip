@@ -130,11 +130,13 @@ template <int MODE>
 __device__ __forceinline__ void finish_row(double (&a)[3][4], int row, int bg, int cq, const double *__restrict__ x,
                                            const double *__restrict__ f, double *__restrict__ y, double (&acc)[4]) {
 #pragma unroll
-    for (int off = 8; off < 64; off <<= 1)
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int t = 0; t < 4; ++t) a[i][t] += __shfl_xor(a[i][t], off);
+        for (int t = 0; t < 4; ++t) {
+            a[i][t] += lane_xor<8>(a[i][t]);
+            a[i][t] += lane_xor<16>(a[i][t]);
+            a[i][t] += lane_xor<32>(a[i][t]);
+        }
     if (bg == 0) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -176,7 +178,7 @@ __device__ __forceinline__ void finish_pair(const double (&aa)[3][4], const doub
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const double keep = b0 ? ab[i][t] : aa[i][t], give = b0 ? aa[i][t] : ab[i][t];
-            k1[i][t] = keep + __shfl_xor(give, 8);
+            k1[i][t] = keep + lane_xor<8>(give);
         }
     double k2[3][2];
 #pragma unroll
@@ -184,13 +186,13 @@ __device__ __forceinline__ void finish_pair(const double (&aa)[3][4], const doub
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const double lo = k1[i][2 * h], hi = k1[i][2 * h + 1];
-            k2[i][h] = (b1 ? hi : lo) + __shfl_xor(b1 ? lo : hi, 16);
+            k2[i][h] = (b1 ? hi : lo) + lane_xor<16>(b1 ? lo : hi);
         }
     const int row = r0 + b0, t = bg >> 1;
     double out[3], other[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const double sum = (b2 ? k2[i][1] : k2[i][0]) + __shfl_xor(b2 ? k2[i][0] : k2[i][1], 32);
+        const double sum = (b2 ? k2[i][1] : k2[i][0]) + lane_xor<32>(b2 ? k2[i][0] : k2[i][1]);
         const int64_t oj = (3 * (int64_t)row + i) * W + col4(cq, t);
         if (MODE == 0) {
             out[i] = sum;
@@ -204,7 +206,7 @@ __device__ __forceinline__ void finish_pair(const double (&aa)[3][4], const doub
     double pa = 0.0;
 #pragma unroll
     for (int i = 0; i < 3; ++i) pa = fma(other[i], out[i], pa);
-    double pb = __shfl_xor(pa, 8);
+    double pb = lane_xor<8>(pa);
 #pragma unroll
     for (int i = 0; i < 3; ++i) pb = fma(other[i], out[i], pb);
     accs = pb;

@@ -58,6 +58,28 @@ __device__ __forceinline__ int xcd_remap(int w, int nwg) {
     return (i / kXcdChunk) * (8 * kXcdChunk) + (w & 7) * kXcdChunk + (i % kXcdChunk);
 }
 
+// v from lane (lane ^ OFF) of the wave, every lane active: OFF 1, 2, 8 as one DPP move per
+// 32-bit half (quad permutations, rotation by 8 within a row of 16 lanes), 4 as two (the
+// half-row mirror, lane ^ 7, then the quad reversal, ^ 3), 16 as a bit-mode swizzle
+// within 32-lane halves, 32 as a permute through the LDS crossbar
+template <int OFF>
+__device__ __forceinline__ int lane_xor_b32(int v) {
+    static_assert(OFF == 1 || OFF == 2 || OFF == 4 || OFF == 8 || OFF == 16 || OFF == 32, "lane offset");
+    if constexpr (OFF == 1) return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+    else if constexpr (OFF == 2) return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+    else if constexpr (OFF == 4)
+        return __builtin_amdgcn_mov_dpp(__builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false), 0x1B, 0xF, 0xF, false);
+    else if constexpr (OFF == 8) return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false);
+    else if constexpr (OFF == 16) return __builtin_amdgcn_ds_swizzle(v, 0x401F);
+    else return __shfl_xor(v, 32);
+}
+
+template <int OFF>
+__device__ __forceinline__ double lane_xor(double v) {
+    const int lo = lane_xor_b32<OFF>(__double2loint(v)), hi = lane_xor_b32<OFF>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
 // Solver state shared by the kernels of one solve; lives in device memory.  Every
 // field is written by exactly one thread of one kernel, and read only by kernels
 // that run after that one in stream order.

@@ -142,11 +142,39 @@ __device__ __forceinline__ int64_t col_at(const int16_t *__restrict__ bc, int b,
     return (int64_t)row + bc[b];
 }
 
+// The sums over the row's G lanes, scattered: the exchanges with the lanes G/2 and then
+// G/4 apart (the butterfly's first two) each halve what a lane carries, a zero fourth
+// value padding the three, so that lane lg keeps element e = 2 [lg & G/2] + [lg & G/4];
+// the exchanges 8 .. 1 lanes apart complete it.  Every element is summed in the
+// butterfly's pairing (the same bits); lane e G/4 of the group returns element e < 3.
+template <int G, int OFF>
+__device__ __forceinline__ void lanes_add(double &v) {
+    if constexpr (OFF >= 1) {
+        v += lane_xor<OFF>(v);
+        lanes_add<G, OFF / 2>(v);
+    }
+}
+
+template <int G>
+__device__ __forceinline__ double row_scatter(int lg, double a0, double a1, double a2) {
+    const bool hi = lg & (G / 2), lo = lg & (G / 4);
+    const double k0 = (hi ? a2 : a0) + lane_xor<G / 2>(hi ? a0 : a2);
+    const double k1 = (hi ? 0.0 : a1) + lane_xor<G / 2>(hi ? a1 : 0.0);
+    double v = (lo ? k1 : k0) + lane_xor<G / 4>(lo ? k0 : k1);
+    lanes_add<G, G / 8>(v);
+    return v;
+}
+
+// lane lg of a row's group holds element row_elem(lg) of the row's product (3: none)
+template <int G>
+__device__ __forceinline__ int row_elem(int lg) {
+    return lg % (G / 4) == 0 ? lg / (G / 4) : 3;
+}
+
 template <int G, class XL, class V, class CI>
-__device__ __forceinline__ void block_row_span(int row, int beg, int end, int lg, const CI *__restrict__ bcol,
-                                               const V *__restrict__ bval, const XL &xl, double &a0, double &a1,
-                                               double &a2) {
-    a0 = a1 = a2 = 0.0;
+__device__ __forceinline__ double block_row_span(int row, int beg, int end, int lg, const CI *__restrict__ bcol,
+                                                 const V *__restrict__ bval, const XL &xl) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     if (row >= 0) {
         const int64_t m = end - beg;
         const V *rv = bval + 9 * (int64_t)beg - beg;  // plane e of block b: rv[e * m + b]
@@ -161,24 +189,19 @@ __device__ __forceinline__ void block_row_span(int row, int beg, int end, int lg
             a2 = fma(v6, x0, fma(v7, x1, fma(v8, x2, a2)));
         }
     }
-#pragma unroll
-    for (int off = G / 2; off > 0; off >>= 1) {
-        a0 += __shfl_xor(a0, off);
-        a1 += __shfl_xor(a1, off);
-        a2 += __shfl_xor(a2, off);
-    }
+    return row_scatter<G>(lg, a0, a1, a2);
 }
 
 template <int G, class XL, class V>
-__device__ __forceinline__ void block_row(int row, int lg, const int32_t *__restrict__ brow_ptr,
-                                          const int32_t *__restrict__ bcol, const V *__restrict__ bval,
-                                          int64_t nnzb, const XL &xl, double &a0, double &a1, double &a2) {
+__device__ __forceinline__ double block_row(int row, int lg, const int32_t *__restrict__ brow_ptr,
+                                            const int32_t *__restrict__ bcol, const V *__restrict__ bval,
+                                            int64_t nnzb, const XL &xl) {
     int beg = 0, end = 0;
     if (row >= 0) {
         beg = brow_ptr[row];
         end = brow_ptr[row + 1];
     }
-    block_row_span<G>(row, beg, end, lg, bcol, bval, xl, a0, a1, a2);
+    return block_row_span<G>(row, beg, end, lg, bcol, bval, xl);
 }
 
 struct SpmvShape {
@@ -214,10 +237,6 @@ __device__ __forceinline__ int step_row(int s, int nb) {
     return row < nb ? row : -1;
 }
 
-__device__ __forceinline__ double pick3(int lg, double a0, double a1, double a2) {
-    return lg == 0 ? a0 : (lg == 1 ? a1 : a2);
-}
-
 // MODE 0: y = K x.   MODE 1: r = f - K x and ||r||^2 partials.
 template <int G, int MODE, class V>
 __device__ __forceinline__ void k_spmv_body(int vb, SpmvShape sh, const int32_t *__restrict__ brow_ptr,
@@ -234,11 +253,10 @@ __device__ __forceinline__ void k_spmv_body(int vb, SpmvShape sh, const int32_t 
     double acc = 0.0;
     for (int s = s0; s < s1; ++s) {
         const int row = step_row<G>(s, sh.nb);
-        double a0, a1, a2;
-        block_row<G>(row, lg, brow_ptr, bcol, bval, nnzb, xl, a0, a1, a2);
-        if (row >= 0 && lg < 3) {
-            const int64_t i = 3 * (int64_t)row + lg;
-            const double v = pick3(lg, a0, a1, a2);
+        const double v = block_row<G>(row, lg, brow_ptr, bcol, bval, nnzb, xl);
+        const int e = row_elem<G>(lg);
+        if (row >= 0 && e < 3) {
+            const int64_t i = 3 * (int64_t)row + e;
             if (MODE == 0) {
                 y[i] = v;
             } else {
@@ -299,11 +317,10 @@ __device__ __forceinline__ void k_spmv_p_body(int vb, SpmvShape sh, const int32_
                 end = brow_ptr[row + 1];
             }
         }
-        double a0, a1, a2;
-        block_row_span<G>(row, beg, end, lg, bcol, bval, xl, a0, a1, a2);
-        if (row >= 0 && lg < 3) {
-            const int64_t i = 3 * (int64_t)row + lg;
-            const double v = pick3(lg, a0, a1, a2);
+        const double v = block_row_span<G>(row, beg, end, lg, bcol, bval, xl);
+        const int e = row_elem<G>(lg);
+        if (row >= 0 && e < 3) {
+            const int64_t i = 3 * (int64_t)row + e;
             q[i] = v;
             acc = fma(p[i], v, acc);
         }
