@@ -474,8 +474,7 @@ __device__ __forceinline__ double col_sum_cm(const double *__restrict__ part, in
     const double *pc = part + (int64_t)j * nparts;
     double s = 0.0;
     for (int w = threadIdx.x; w < nparts; w += 256) s += pc[w];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = s;
     __syncthreads();
     return (lds4[0] + lds4[1]) + (lds4[2] + lds4[3]);
@@ -492,8 +491,7 @@ __global__ __launch_bounds__(1024) void k_balpha(const double *__restrict__ part
         const double *pc = part + (int64_t)j * nparts;
         double s = 0.0;
         for (int w = threadIdx.x; w < nparts; w += 1024) s += pc[w];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        s = wave_sum(s);
         if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
         __syncthreads();
         pq = 0.0;

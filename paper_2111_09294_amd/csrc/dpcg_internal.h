@@ -80,6 +80,17 @@ __device__ __forceinline__ double lane_xor(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// Sum over the wave (every lane active), valid in every lane: exchanges 32, 16, .. 1 lanes apart
+__device__ __forceinline__ double wave_sum(double v) {
+    v += lane_xor<32>(v);
+    v += lane_xor<16>(v);
+    v += lane_xor<8>(v);
+    v += lane_xor<4>(v);
+    v += lane_xor<2>(v);
+    v += lane_xor<1>(v);
+    return v;
+}
+
 // Solver state shared by the kernels of one solve; lives in device memory.  Every
 // field is written by exactly one thread of one kernel, and read only by kernels
 // that run after that one in stream order.

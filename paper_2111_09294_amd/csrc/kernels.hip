@@ -22,12 +22,6 @@ namespace dpcg {
 
 namespace {
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
 // Sum over the workgroup; every thread receives the same value.
 __device__ __forceinline__ double block_sum(double v, double *lds) {
     v = wave_sum(v);
@@ -450,7 +444,7 @@ __device__ __forceinline__ void k_update_bj_body(int vb,
     const double *p1, const M *__restrict__ minv, const int32_t *__restrict__ bj_rowoff,
     const int32_t *__restrict__ bj_meta, double *__restrict__ part_rr, double *__restrict__ part_ry,
     const double *__restrict__ part_pq2, State *st) {
-    __shared__ double lds[4];
+    __shared__ double lds[2 * (kThreads / 64)];
     __shared__ double tile[kThreads];
     const int t = threadIdx.x;
     const int w = xcd_remap(vb, nwg);
@@ -509,11 +503,15 @@ __device__ __forceinline__ void k_update_bj_body(int vb,
             accy = fma(rn, yd, accy);
         }
     }
-    const double s = block_sum(acc, lds);
-    if (threadIdx.x == 0) part_rr[vb] = s;
     if (part_ry) {  // r^T y partials: rho = r^T z is formed from them in the prolongation
-        const double sy = block_sum(accy, lds);
-        if (threadIdx.x == 0) part_ry[vb] = sy;
+        block_sum2_n<kThreads / 64>(acc, accy, lds);
+        if (threadIdx.x == 0) {
+            part_rr[vb] = acc;
+            part_ry[vb] = accy;
+        }
+    } else {
+        const double s = block_sum(acc, lds);
+        if (threadIdx.x == 0) part_rr[vb] = s;
     }
 }
 
