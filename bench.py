@@ -47,11 +47,11 @@ WORKLOADS = {
 SPMV_TRAFFIC = {
     "workload": "penny80",
     "sources": {
-        "paper_2111_09294_amd/csrc/kernels.hip": "eda0e13f7eb90f129f9f47ac7d68cf7bea55718a8216a01bf1327caea512030d",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "5cee45c8ba4eacdd1184d5ce8dd1d319281971db60f7eb8c77def9ab518a39a8"
+        "paper_2111_09294_amd/csrc/kernels.hip": "a107d84149c7bf221cea81691c36e27acac01685caf79030c36f3a48fe95f87a",
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "8fb09e803349ebc8ea15cd91a171e9e1d5fb6ddb21cd8543d1ae39b89ee7ccdc"
     },
-    "fetch_bytes": 1444607815,
-    "write_bytes": 15970603,
+    "fetch_bytes": 1444790721,
+    "write_bytes": 16008235,
 }
 SPMV_SOURCES = ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h")
 
