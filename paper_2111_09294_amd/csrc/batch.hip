@@ -36,14 +36,26 @@ __device__ __forceinline__ int32_t wg_any(const BatchState *st) {
 // (h < 32) adds rows h, h + 32, ..., and the 32 partial sums are then added in order.  A
 // workgroup of 32 NG threads computes partial sums h = g, g + NG, ... in lane group g,
 // so the result does not depend on NG.  Valid in threads j < W.
+// sum of x[i stride] over i in [i0, n) with step di, added in index order, eight loads
+// issued before their additions
+__device__ __forceinline__ double seq_sum(const double *__restrict__ x, int64_t stride, int i0, int n, int di) {
+    double s = 0.0;
+    int i = i0;
+    for (; i + 7 * di < n; i += 8 * di) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = x[(int64_t)(i + u * di) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; i < n; i += di) s += x[(int64_t)i * stride];
+    return s;
+}
+
 template <int NG>
 __device__ __forceinline__ double col_reduce(const double *__restrict__ part, int nparts, double (*lds)[W + 1]) {
     const int j = threadIdx.x & 31, g = threadIdx.x >> 5;
-    for (int h = g; h < 32; h += NG) {
-        double s = 0.0;
-        for (int w = h; w < nparts; w += 32) s += part[(int64_t)w * W + j];
-        lds[h][j] = s;
-    }
+    for (int h = g; h < 32; h += NG) lds[h][j] = seq_sum(part + j, W, h, nparts, 32);
     __syncthreads();
     double t = 0.0;
     if (threadIdx.x < W)
@@ -472,8 +484,7 @@ __global__ __launch_bounds__(256) void k_pair_merge(int32_t nb, const int32_t *_
 // 256-thread workgroup; valid in thread 0.
 __device__ __forceinline__ double col_sum_cm(const double *__restrict__ part, int nparts, int j, double *lds4) {
     const double *pc = part + (int64_t)j * nparts;
-    double s = 0.0;
-    for (int w = threadIdx.x; w < nparts; w += 256) s += pc[w];
+    double s = seq_sum(pc, 1, threadIdx.x, nparts, 256);
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) lds4[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -489,8 +500,7 @@ __global__ __launch_bounds__(1024) void k_balpha(const double *__restrict__ part
     double pq;
     {  // fixed-order sum of column j over 1024 threads
         const double *pc = part + (int64_t)j * nparts;
-        double s = 0.0;
-        for (int w = threadIdx.x; w < nparts; w += 1024) s += pc[w];
+        double s = seq_sum(pc, 1, threadIdx.x, nparts, 1024);
         s = wave_sum(s);
         if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
         __syncthreads();
@@ -896,6 +906,36 @@ __global__ __launch_bounds__(64 * kCoarseWaves) void k_bcoarse(int32_t k, int64_
     }
 }
 
+// sum_e z_val[e] delta[z_col[e]][j] over the cnt entries of a row from e0, in index order:
+// lane j loads entry j of each chunk of 32 (one coalesced load), the column indices are
+// passed round by shuffles and up to eight delta rows are gathered at a time
+__device__ __forceinline__ double zrow_dot_long(int e0, int cnt, int j, const int32_t *__restrict__ z_col,
+                                                const double *__restrict__ z_val, const double *__restrict__ delta) {
+    double c = 0.0;
+    for (int b0 = 0; b0 < cnt; b0 += 32) {
+        int col = 0;
+        double v = 0.0;
+        if (b0 + j < cnt) {
+            col = z_col[e0 + b0 + j];
+            v = z_val[e0 + b0 + j];
+        }
+        const int m = min(32, cnt - b0);  // the same for the whole group
+        for (int q0 = 0; q0 < m; q0 += 8) {
+            double x[8], vq[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int cq = __shfl(col, q0 + q, 32);
+                vq[q] = __shfl(v, q0 + q, 32);
+                x[q] = q0 + q < m ? delta[(int64_t)cq * W + j] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q0 + q < m) c = fma(vq[q], x[q], c);
+        }
+    }
+    return c;
+}
+
 // out = base + Z delta (base may be null); optional partials of rdot_j^T out_j;
 // optionally advance the iteration.
 __global__ __launch_bounds__(256) void k_bprolong(int64_t n, int32_t nwg, const int32_t *__restrict__ z_ptr,
@@ -910,39 +950,60 @@ __global__ __launch_bounds__(256) void k_bprolong(int64_t n, int32_t nwg, const 
     const int64_t per = (n + nwg - 1) / nwg;
     const int64_t d1 = std::min<int64_t>(n, (int64_t)(w + 1) * per);
     double acc = 0.0;
-    for (int64_t d = (int64_t)w * per + g; d < d1; d += 8) {
-        const int64_t o = d * W + j;
-        double s = base ? base[o] : 0.0;
-        double c = 0.0;
+    // rows d and d + 8 of the group per pass, their loads issued together; each row's
+    // entries are added in index order (c from zero), then s = base + c
+    for (int64_t d = (int64_t)w * per + g; d < d1; d += 16) {
+        const int64_t db = d + 8;
+        const bool hb = db < d1;
+        const int64_t oa = d * W + j, ob = db * W + j;
+        double sa = base ? base[oa] : 0.0, sb = base && hb ? base[ob] : 0.0;
+        double ca = 0.0, cb = 0.0;
         if (delta) {
-            // lane j loads entry j of the row (one coalesced load); the column indices are
-            // passed round by shuffles and up to eight delta rows are gathered at a time
-            const int e0 = z_ptr[d], cnt = z_ptr[d + 1] - e0;
-            for (int b0 = 0; b0 < cnt; b0 += 32) {
-                int col = 0;
-                double v = 0.0;
-                if (b0 + j < cnt) {
-                    col = z_col[e0 + b0 + j];
-                    v = z_val[e0 + b0 + j];
+            const int ea = z_ptr[d], na = z_ptr[d + 1] - ea;
+            const int eb = hb ? z_ptr[db] : 0, nb = hb ? z_ptr[db + 1] - eb : 0;
+            if (na <= 32 && nb <= 32) {
+                // lane j loads entry j of each row; the entries are passed round by shuffles,
+                // four per row and step, and their delta rows gathered together
+                int cola = 0, colb = 0;
+                double va = 0.0, vb = 0.0;
+                if (j < na) {
+                    cola = z_col[ea + j];
+                    va = z_val[ea + j];
                 }
-                const int m = min(32, cnt - b0);  // the same for the whole group
-                for (int q0 = 0; q0 < m; q0 += 8) {
-                    double x[8], vq[8];
+                if (j < nb) {
+                    colb = z_col[eb + j];
+                    vb = z_val[eb + j];
+                }
+                const int m = max(na, nb);  // the same for the whole group
+                for (int q0 = 0; q0 < m; q0 += 4) {
+                    double xa[4], xb[4], wa[4], wb[4];
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) {
-                        const int cq = __shfl(col, q0 + q, 32);
-                        vq[q] = __shfl(v, q0 + q, 32);
-                        x[q] = q0 + q < m ? delta[(int64_t)cq * W + j] : 0.0;
+                    for (int q = 0; q < 4; ++q) {
+                        const int ka = __shfl(cola, q0 + q, 32), kb = __shfl(colb, q0 + q, 32);
+                        wa[q] = __shfl(va, q0 + q, 32);
+                        wb[q] = __shfl(vb, q0 + q, 32);
+                        xa[q] = q0 + q < na ? delta[(int64_t)ka * W + j] : 0.0;
+                        xb[q] = q0 + q < nb ? delta[(int64_t)kb * W + j] : 0.0;
                     }
 #pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        if (q0 + q < m) c = fma(vq[q], x[q], c);
+                    for (int q = 0; q < 4; ++q) {
+                        if (q0 + q < na) ca = fma(wa[q], xa[q], ca);
+                        if (q0 + q < nb) cb = fma(wb[q], xb[q], cb);
+                    }
                 }
+            } else {
+                ca = zrow_dot_long(ea, na, j, z_col, z_val, delta);
+                if (hb) cb = zrow_dot_long(eb, nb, j, z_col, z_val, delta);
             }
         }
-        s += c;
-        out[o] = s;
-        if (rdot) acc = fma(rdot[o], s, acc);
+        sa += ca;
+        out[oa] = sa;
+        if (rdot) acc = fma(rdot[oa], sa, acc);
+        if (hb) {
+            sb += cb;
+            out[ob] = sb;
+            if (rdot) acc = fma(rdot[ob], sb, acc);
+        }
     }
     if (rdot) {
         const double t = group_sum_8(acc, lds);
@@ -1109,7 +1170,7 @@ int ensure_ws(dpcg_ctx *c) {
     BTRY(balloc(c, &b->pair_ab, (size_t)nslots * kPairCap));
     BLAUNCH(k_pair_merge, dim3((unsigned)((nslots + 3) / 4)), dim3(256), 0, c->stream, c->nb, c->brow_ptr, c->bcol,
             (int32_t)nslots, b->pair_len, b->pair_col, b->pair_ab);
-    b->upd_nwg = grid_rows(c->bjb_ntiles, 1, 2048);
+    b->upd_nwg = grid_rows(c->bjb_ntiles, 1, 4096);  // about one tile per workgroup at 40^3
     b->vec_nwg = grid_rows(c->n, 32, 4096);
     const size_t np = (size_t)std::max({b->spmm_nwg, b->upd_nwg, b->vec_nwg}) * W;
     BTRY(balloc(c, &b->part, np));
