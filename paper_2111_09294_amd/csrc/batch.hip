@@ -560,11 +560,11 @@ __global__ __launch_bounds__(256) void k_bupdate_bj(int32_t ntiles, int32_t nwg,
             const int mt = bj_meta[d0 + threadIdx.x];
             md[threadIdx.x] = ((bj_rowoff[d0 + threadIdx.x] - m0) << 10) | ((mt >> 8) << 5) | (mt & 255);
         }
-        // four DoFs of the group at a time: all loads first, then the updates
-        for (int64_t db = d0 + g; db < d1; db += 32) {
-            double rv[4], pv[4], qv[4], uv[4];
+        // eight DoFs of the group at a time (a whole tile): all loads first, then the updates
+        for (int64_t db = d0 + g; db < d1; db += 64) {
+            double rv[8], pv[8], qv[8], uv[8];
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
+            for (int h = 0; h < 8; ++h) {
                 const int64_t d = db + 8 * h, o = d * W + j;
                 rv[h] = pv[h] = qv[h] = uv[h] = 0.0;
                 if (d < d1) {
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(256) void k_bupdate_bj(int32_t ntiles, int32_t nwg,
                 }
             }
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
+            for (int h = 0; h < 8; ++h) {
                 const int64_t d = db + 8 * h, o = d * W + j;
                 if (d >= d1) continue;
                 double rn = rv[h];
