@@ -50,8 +50,8 @@ SPMV_TRAFFIC = {
         "paper_2111_09294_amd/csrc/kernels.hip": "a107d84149c7bf221cea81691c36e27acac01685caf79030c36f3a48fe95f87a",
         "paper_2111_09294_amd/csrc/dpcg_internal.h": "8fb09e803349ebc8ea15cd91a171e9e1d5fb6ddb21cd8543d1ae39b89ee7ccdc"
     },
-    "fetch_bytes": 1444790721,
-    "write_bytes": 16008235,
+    "fetch_bytes": 1444784949,
+    "write_bytes": 16008458,
 }
 SPMV_SOURCES = ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h")
 
