@@ -280,7 +280,9 @@ int64_t dpcg_get_history(dpcg_handle h, double *out, int64_t cap);
  * stream, and accumulates the durations of the launches that did work; on = 0 stops
  * timing, on < 0 is DPCG_EINVAL.  Turning it on resets the counters.  A timed launch
  * adds about 8 us to its iteration (measured: 0.8 ms per 105-iteration solve with
- * m = 1), so sampling every 8th launch keeps the measured run close to an untimed one. */
+ * m = 1), so sampling every 8th launch keeps the measured run close to an untimed one.
+ * In a mixed-precision solve only the SpMV of the binary32 inner iterations is timed
+ * (the FP64 phase that ends it runs the FP64 kernel, which the counters leave out). */
 int dpcg_set_timing(dpcg_handle h, int32_t on);
 int dpcg_get_timing(dpcg_handle h, dpcg_timing *out);
 

@@ -421,7 +421,12 @@ int solve_mixed(dpcg_ctx *c, Workspace &w, const double *f, double *u, double to
     if (status == DPCG_OK && opt.switch_tol > tol && rn > tol * fnorm) {
         State st;
         c->inner32 = false;
-        TRY(run_cg(c, w, f, u, tol * fnorm, true, opt.max_iter - total, opt.check_every, 0, st));
+        // the SpMV timing counts the binary32 kernel only: none for the FP64 phase
+        const int32_t timing = c->timing;
+        c->timing = 0;
+        const int e = run_cg(c, w, f, u, tol * fnorm, true, opt.max_iter - total, opt.check_every, 0, st);
+        c->timing = timing;
+        TRY(e);
         fp64_its = st.iters_done;
         total += st.iters_done;
         switch (st.flag) {

@@ -144,6 +144,20 @@ def test_mixed_deterministic_adjoint_and_warm_start(solver):
     assert torch.equal(u3, u64)
 
 
+def test_mixed_timing_counts_binary32_spmv_only(solver):
+    """In a mixed solve the SpMV timing samples the binary32 inner iterations only: with
+    every launch timed, one sample per binary32 iteration and none for the FP64 phase."""
+    p, s = solver("penny12")
+    f = dev(p.f)
+    s.set_timing(True, every=1)
+    _, info = s.solve(f, precision="mixed")
+    t = s.timing()
+    s.set_timing(False)
+    assert info["status"] == D.abi.OK and info["iterations_fp64"] > 0
+    assert t["spmv_launches"] == info["iterations"] - info["iterations_fp64"]
+    assert t["spmv_ms"] > 0.0
+
+
 def test_mixed_caps_and_options(solver):
     p, s = solver("edge10")
     f = dev(p.f)
