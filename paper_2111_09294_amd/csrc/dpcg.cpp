@@ -169,7 +169,8 @@ void choose_shapes(dpcg_ctx *c) {
     c->spmv.nwg = c->spmv.steps;  // one row step per workgroup (more per workgroup measured slower)
     if (c->spmv.nwg >= 8) c->spmv.nwg = (c->spmv.nwg + 7) & ~7;
     c->vec_nwg = round_grid((int)std::min<int64_t>((c->n + kThreads - 1) / kThreads, 1024));
-    c->prolong_nwg = round_grid((int)std::min<int64_t>((c->n + kThreads - 1) / kThreads, 16384));
+    // two rows per thread: half the workgroups, each forming rho once (four measured slower)
+    c->prolong_nwg = round_grid((int)std::min<int64_t>((c->n + 2 * kThreads - 1) / (2 * kThreads), 16384));
     c->bj_nwg = round_grid(std::min(c->bj_ntiles, 65536));  // one tile each (partials reduced by one workgroup)
 }
 

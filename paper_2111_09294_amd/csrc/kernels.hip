@@ -889,14 +889,20 @@ __device__ __forceinline__ void k_prolong_p_body(int vb, int64_t n, int32_t nwg,
     const int w = xcd_remap(vb, nwg);
     const int64_t per = (n + nwg - 1) / nwg;
     const int64_t d1 = min(n, (int64_t)(w + 1) * per);
-    // the thread's first row, y + Z delta and the old p, before beta is known: these
-    // loads overlap the reduction below
+    // the thread's first two rows (the grid gives each thread two or more), y + Z delta and the
+    // old p, before beta is known: these loads overlap the reduction below
     int64_t d = (int64_t)w * per + threadIdx.x;
-    double v = 0.0, pold = 0.0;
+    const int64_t d2 = d + kThreads;
+    double v = 0.0, pold = 0.0, v2 = 0.0, pold2 = 0.0;
     if (d < d1) {
         const double c = z_row_dot(z_ptr[d], z_ptr[d + 1], z_col, z_val, delta);
         v = y[d] + c;
         pold = pp[d];
+    }
+    if (d2 < d1) {
+        const double c = z_row_dot(z_ptr[d2], z_ptr[d2 + 1], z_col, z_val, delta);
+        v2 = y[d2] + c;
+        pold2 = pp[d2];
     }
     const double rho = st->ry + block_sum(strided_share<kThreads, 8>(hparts, nhp), lds);
     const bool bad = !isfinite(rho);
@@ -913,7 +919,8 @@ __device__ __forceinline__ void k_prolong_p_body(int vb, int64_t n, int32_t nwg,
     }
     if (bad) return;
     if (d < d1) pc[d] = fma(beta, pold, v);
-    for (d += kThreads; d < d1; d += kThreads) {
+    if (d2 < d1) pc[d2] = fma(beta, pold2, v2);
+    for (d += 2 * kThreads; d < d1; d += kThreads) {
         const double c = z_row_dot(z_ptr[d], z_ptr[d + 1], z_col, z_val, delta);
         pc[d] = fma(beta, pp[d], y[d] + c);
     }
