@@ -47,11 +47,11 @@ WORKLOADS = {
 SPMV_TRAFFIC = {
     "workload": "penny80",
     "sources": {
-        "paper_2111_09294_amd/csrc/kernels.hip": "a107d84149c7bf221cea81691c36e27acac01685caf79030c36f3a48fe95f87a",
+        "paper_2111_09294_amd/csrc/kernels.hip": "a2420904c1b9adde20df25e809abddaa8342c18965d1f8ebb8a8b8a36d6a6e98",
         "paper_2111_09294_amd/csrc/dpcg_internal.h": "8fb09e803349ebc8ea15cd91a171e9e1d5fb6ddb21cd8543d1ae39b89ee7ccdc"
     },
-    "fetch_bytes": 1444784949,
-    "write_bytes": 16008458,
+    "fetch_bytes": 1444796371,
+    "write_bytes": 16006473,
 }
 SPMV_SOURCES = ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h")
 
