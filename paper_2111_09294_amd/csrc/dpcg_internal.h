@@ -34,6 +34,7 @@ constexpr int kDenseRows = 32;    // rows of a dense block per workgroup of its 
 constexpr int kMaxElemDofs = 256; // largest element (DoFs) of dpcg_element_gradient
 constexpr int kCoarseTile = 64;   // E^-1 kept as the lower-triangle tiles of this size
 constexpr int kAlphaParts = 64;   // workgroups of the first stage of p^T q
+constexpr int kRestrictRound = 4096;  // list entries per round of the restriction's loads (threads x depth)
 
 // tile (I, J), I >= J, of the lower triangle of a matrix of nt x nt tiles: index I (I + 1) / 2 + J
 __host__ __device__ inline int64_t coarse_tile_count(int32_t nt) { return (int64_t)nt * (nt + 1) / 2; }
@@ -271,6 +272,7 @@ struct dpcg_ctx {
     double *zt_val = nullptr;
     int32_t *kzt_ptr = nullptr, *kzt_idx = nullptr;
     double *kzt_val = nullptr;
+    int32_t *rs_order = nullptr;  // the restriction's column order (longer columns first), k entries
     double *einv = nullptr;
     int64_t einv_ld = 0;       // leading dimension of E^-1 (k rounded up to 64)
     double *einv_tiles = nullptr;  // the lower triangle of E^-1 as kCoarseTile^2 row-major tiles,

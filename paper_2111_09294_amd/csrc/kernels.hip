@@ -626,6 +626,7 @@ __global__ __launch_bounds__(kThreads) void k_bj_dense(const DenseBlk *__restric
 constexpr int kRestrictWaves = 8;
 constexpr int kRestrictThreads = 64 * kRestrictWaves;
 constexpr int kRestrictDepth = 8;  // entries per thread whose loads are in flight together
+static_assert(kRestrictThreads * kRestrictDepth == kRestrictRound, "restriction round");
 
 __device__ __forceinline__ void k_restrict_body(int vb, int vg,
     int32_t k, const int32_t *__restrict__ zt_ptr, const int32_t *__restrict__ zt_idx,
@@ -633,7 +634,7 @@ __device__ __forceinline__ void k_restrict_body(int vb, int vg,
     const double *__restrict__ kzt_val, const double *__restrict__ a, const double *__restrict__ b,
     double *__restrict__ g, double *__restrict__ h, State *st, const double *__restrict__ part_rr,
     const double *__restrict__ part_ry, int n_rr, int iter_offset, int max_iter, double *__restrict__ hist,
-    int advance) {
+    int advance, const int32_t *__restrict__ order = nullptr) {
     __shared__ double lds[2 * kRestrictWaves];
     if (st) {
         if (wg_flag(st) != kRunning) return;
@@ -664,7 +665,9 @@ __device__ __forceinline__ void k_restrict_body(int vb, int vg,
         }
     }
     constexpr int T = kRestrictThreads;
-    for (int j = xcd_remap(vb, vg); j < k; j += vg) {
+    for (int jj = xcd_remap(vb, vg); jj < k; jj += vg) {
+        const int j = order ? order[jj] : jj;  // columns with more rounds of loads first (a
+                                               // shorter tail); each column's sum is unchanged
         // the column's Z^T entries, then its (K Z)^T entries (when b is given), as one list:
         // each thread loads kRestrictDepth entries and their gathers at a time
         const int zb = zt_ptr[j], nz = zt_ptr[j + 1] - zb;
@@ -715,9 +718,9 @@ __global__ __launch_bounds__(kRestrictThreads) void k_restrict(
     const double *__restrict__ kzt_val, const double *__restrict__ a, const double *__restrict__ b,
     double *__restrict__ g, State *st, const double *__restrict__ part_rr, int n_rr, int iter_offset,
     int max_iter, double *__restrict__ hist, double *__restrict__ h, const double *__restrict__ part_ry,
-    int advance) {
+    int advance, const int32_t *__restrict__ order) {
     k_restrict_body(blockIdx.x, gridDim.x, k, zt_ptr, zt_idx, zt_val, kzt_ptr, kzt_idx, kzt_val, a, b, g, h, st,
-                    part_rr, part_ry, n_rr, iter_offset, max_iter, hist, advance);
+                    part_rr, part_ry, n_rr, iter_offset, max_iter, hist, advance, order);
 }
 
 
@@ -1256,7 +1259,7 @@ hipError_t launch_restrict(const dpcg_ctx *c, const double *a, const double *b, 
                        c->zt_val, c->kzt_ptr, c->kzt_idx, c->kzt_val, a, b, g, w ? w->st : nullptr,
                        w ? w->part_b : nullptr, check ? n_parts : 0, iter_offset, max_iter,
                        (w && record) ? w->hist : nullptr, fused ? w->h : nullptr, fused ? w->part_c : nullptr,
-                       fused ? 1 : 0);
+                       fused ? 1 : 0, (const int32_t *)c->rs_order);
     return hipGetLastError();
 }
 

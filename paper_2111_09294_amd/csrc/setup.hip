@@ -2067,6 +2067,25 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         HT(hipMemcpyAsync(fl + 4, cfail, sizeof(int), hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
         if (fl[4]) return DPCG_ECOARSE_NOT_SPD;
+        if (!reuse) {
+            // the restriction's column order: columns needing more rounds of its loads first,
+            // launch order kept within each class (neighbouring columns share their gathers)
+            // (from the 64-bit list pointers of this step: the 32-bit Z^T ones come later)
+            std::vector<int64_t> zp(k + 1), kp(k + 1);
+            std::vector<int32_t> ord(k);
+            HT(hipMemcpyAsync(zp.data(), ztp, sizeof(int64_t) * (k + 1), hipMemcpyDeviceToHost, s));
+            HT(hipMemcpyAsync(kp.data(), kzp, sizeof(int64_t) * (k + 1), hipMemcpyDeviceToHost, s));
+            HT(hipStreamSynchronize(s));
+            auto rounds = [&](int32_t j) {
+                const int64_t len = zp[j + 1] - zp[j] + kp[j + 1] - kp[j];
+                return (len + kRestrictRound - 1) / kRestrictRound;
+            };
+            for (int32_t j = 0; j < k; ++j) ord[j] = j;
+            std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return rounds(a) > rounds(b); });
+            HT(keep(c, &c->rs_order, k));
+            HT(hipMemcpyAsync(c->rs_order, ord.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
+            HT(hipStreamSynchronize(s));  // ord is released on return
+        }
         return DPCG_OK;
     }
 }
