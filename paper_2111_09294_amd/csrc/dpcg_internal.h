@@ -273,6 +273,7 @@ struct dpcg_ctx {
     int32_t *kzt_ptr = nullptr, *kzt_idx = nullptr;
     double *kzt_val = nullptr;
     int32_t *rs_order = nullptr;  // the restriction's column order (longer columns first), k entries
+    std::vector<int32_t> rs_order_h;  // its host copy (the source of the upload)
     double *einv = nullptr;
     int64_t einv_ld = 0;       // leading dimension of E^-1 (k rounded up to 64)
     double *einv_tiles = nullptr;  // the lower triangle of E^-1 as kCoarseTile^2 row-major tiles,

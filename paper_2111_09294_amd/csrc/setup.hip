@@ -1998,6 +1998,13 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
                            icnt, nitems);
         HT(scan(s, kzcnt, k, kzp, part));
         HT(hipMemcpyAsync(nkzp, kzp + k, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        int64_t *zp_h = nullptr, *kp_h = nullptr;  // list lengths for the restriction's column order
+        if (!reuse) {
+            HT(pool.host(&zp_h, k + 1));
+            HT(pool.host(&kp_h, k + 1));
+            HT(hipMemcpyAsync(zp_h, ztp, sizeof(int64_t) * (k + 1), hipMemcpyDeviceToHost, s));
+            HT(hipMemcpyAsync(kp_h, kzp, sizeof(int64_t) * (k + 1), hipMemcpyDeviceToHost, s));
+        }
         HT(pool.join());  // the symmetry and block flags are read here
         HT(hipMemcpyAsync(fl, flags, sizeof(int) * 4, hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
@@ -2010,6 +2017,22 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         if (nkz > (int64_t)INT32_MAX) return DPCG_EINVAL;
         if (reuse && nkz != c->nnz_kz) return DPCG_EINVAL;  // the structure of K Z must not change
         c->nnz_kz = nkz;
+        if (!reuse) {
+            // the restriction's column order: columns needing more rounds of its loads first,
+            // launch order kept within each class (neighbouring columns share their gathers)
+            // (a counting sort: classes of 0 .. 63 rounds and one of 64 or more)
+            constexpr int kCls = 64;
+            std::vector<int32_t> cls(k), start(kCls + 2, 0);
+            for (int32_t j = 0; j < k; ++j) {
+                const int64_t len = zp_h[j + 1] - zp_h[j] + kp_h[j + 1] - kp_h[j];
+                const int64_t r = std::min<int64_t>((len + kRestrictRound - 1) / kRestrictRound, kCls);
+                cls[j] = kCls - (int32_t)r;  // more rounds, earlier class
+                ++start[cls[j] + 1];
+            }
+            for (int q = 0; q <= kCls; ++q) start[q + 1] += start[q];
+            c->rs_order_h.resize(k);
+            for (int32_t j = 0; j < k; ++j) c->rs_order_h[start[cls[j]]++] = j;
+        }
         if (!reuse) {
             HT(keep(c, &c->kzt_idx, nkz));
             HT(keep(c, &c->kzt_val, nkz));
@@ -2063,29 +2086,12 @@ int coarse_operator(dpcg_ctx *c, Pool &pool, int32_t k, const int64_t *zp, const
         if (!reuse) {
             HT(keep(c, &c->kzt_ptr, k + 1));
             hipLaunchKernelGGL(k_to_i32, dim3(grid_for(k + 1)), dim3(256), 0, s, kzp, (int64_t)k + 1, c->kzt_ptr);
+            HT(keep(c, &c->rs_order, k));
+            HT(hipMemcpyAsync(c->rs_order, c->rs_order_h.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
         }
         HT(hipMemcpyAsync(fl + 4, cfail, sizeof(int), hipMemcpyDeviceToHost, s));
         HT(hipStreamSynchronize(s));
         if (fl[4]) return DPCG_ECOARSE_NOT_SPD;
-        if (!reuse) {
-            // the restriction's column order: columns needing more rounds of its loads first,
-            // launch order kept within each class (neighbouring columns share their gathers)
-            // (from the 64-bit list pointers of this step: the 32-bit Z^T ones come later)
-            std::vector<int64_t> zp(k + 1), kp(k + 1);
-            std::vector<int32_t> ord(k);
-            HT(hipMemcpyAsync(zp.data(), ztp, sizeof(int64_t) * (k + 1), hipMemcpyDeviceToHost, s));
-            HT(hipMemcpyAsync(kp.data(), kzp, sizeof(int64_t) * (k + 1), hipMemcpyDeviceToHost, s));
-            HT(hipStreamSynchronize(s));
-            auto rounds = [&](int32_t j) {
-                const int64_t len = zp[j + 1] - zp[j] + kp[j + 1] - kp[j];
-                return (len + kRestrictRound - 1) / kRestrictRound;
-            };
-            for (int32_t j = 0; j < k; ++j) ord[j] = j;
-            std::stable_sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) { return rounds(a) > rounds(b); });
-            HT(keep(c, &c->rs_order, k));
-            HT(hipMemcpyAsync(c->rs_order, ord.data(), sizeof(int32_t) * k, hipMemcpyHostToDevice, s));
-            HT(hipStreamSynchronize(s));  // ord is released on return
-        }
         return DPCG_OK;
     }
 }
