@@ -47,11 +47,11 @@ WORKLOADS = {
 SPMV_TRAFFIC = {
     "workload": "penny80",
     "sources": {
-        "paper_2111_09294_amd/csrc/kernels.hip": "a2420904c1b9adde20df25e809abddaa8342c18965d1f8ebb8a8b8a36d6a6e98",
-        "paper_2111_09294_amd/csrc/dpcg_internal.h": "8fb09e803349ebc8ea15cd91a171e9e1d5fb6ddb21cd8543d1ae39b89ee7ccdc"
+        "paper_2111_09294_amd/csrc/kernels.hip": "9184e2300ba6de0e7e9657e77a8c4bb8355af437fa3be6de05a3e341df1b7577",
+        "paper_2111_09294_amd/csrc/dpcg_internal.h": "09b37faadb31f46c783ea09d232a204d9f7c117366662471a83d34623f83b69c"
     },
-    "fetch_bytes": 1444796371,
-    "write_bytes": 16006473,
+    "fetch_bytes": 1444818874,
+    "write_bytes": 16007888,
 }
 SPMV_SOURCES = ("paper_2111_09294_amd/csrc/kernels.hip", "paper_2111_09294_amd/csrc/dpcg_internal.h")
 
